@@ -1,0 +1,212 @@
+/*
+ * nsf.h - C ABI of the MI355X (gfx950) latent-space time step for reduced-order MPM with
+ * neural deformation, stress and affine fields (Zong et al., "Neural Stress Fields for
+ * Reduced-order Elastoplasticity and Fracture", SIGGRAPH Asia 2023).
+ *
+ * The problem, as the paper states it: given trained fields g (deformation, Sec. 4.2),
+ * h (Kirchhoff stress, Sec. 4.3) and l (affine momentum, Sec. 4.4), reference positions
+ * X_p (Sec. 3.2), a latent z_0, MPM constants (dt, dx, gravity, boundaries; Sec. 3.3) and
+ * sample / integration particle sets (Sec. 5.4):
+ *   - advance the latent z_n -> z_{n+1} by inference, one MPM step on the integration
+ *     particles, and Gauss-Newton network inversion (Sec. 5.1-5.3);
+ *   - decode positions x = X + u(X, z_n) at any reference point (Sec. 5.1; Sec. 6
+ *     resolution boost).
+ *
+ * Conventions
+ *   - Every call returns nsf_status (0 = NSF_OK). No exception crosses the ABI; the
+ *     message of the last failure on the calling thread is nsf_last_error().
+ *   - "host" pointers are read during the call only and may be freed afterwards.
+ *     "device" pointers are HIP device addresses on the current device.
+ *   - Stream arguments are hipStream_t passed as void* (NULL = the legacy default
+ *     stream). Calls marked async only enqueue work on that stream.
+ *   - Points are structure-of-arrays float32: X[3][n] means X[c * n + p].
+ *   - A sim is not thread-safe. Distinct sims may be stepped on distinct streams.
+ */
+#ifndef NSF_H
+#define NSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NSF_OK = 0,
+  NSF_EINVAL = -1,       /* invalid argument or descriptor                                */
+  NSF_ENOMEM = -2,       /* arena too small / workspace too small                         */
+  NSF_EHIP = -3,         /* a HIP runtime call failed                                     */
+  NSF_ENODEV = -4,       /* no gfx950 device is visible                                   */
+  NSF_EDOMAIN = -5,      /* sticky: a particle stencil left the grid                      */
+  NSF_ESINGULAR = -6,    /* sticky: Gauss-Newton normal matrix had a pivot <= 0           */
+  NSF_ENONFINITE = -7    /* sticky: the latent or the residual became non-finite          */
+} nsf_status;
+
+typedef enum { NSF_FP32 = 0, NSF_BF16 = 1 } nsf_precision;
+
+/* sticky device status bits, see nsf_status_flags */
+enum { NSF_FLAG_DOMAIN = 1u, NSF_FLAG_NONFINITE = 2u, NSF_FLAG_SINGULAR = 4u };
+
+/* Fields and their output widths (supplementary "Network architecture"): g -> 3
+ * (displacement u, x = X + u), h -> 6 (Kirchhoff stress, Voigt xx yy zz yz xz xy),
+ * l -> 9 (affine matrix C, row-major). */
+enum { NSF_FIELD_G = 0, NSF_FIELD_H = 1, NSF_FIELD_L = 2 };
+
+/* A moving blade imposed as a grid velocity boundary condition: after gravity and the
+ * sticky walls, every node i with |normal . x_i - offset| <= half_thickness and
+ * x_i.z >= edge_z0 - edge_speed * t_{n+1} takes `velocity`. */
+typedef struct {
+  int32_t enabled;
+  double normal[3];
+  double offset;
+  double half_thickness;
+  double edge_z0;
+  double edge_speed;
+  double velocity[3];
+} nsf_knife;
+
+/* Everything a reduced simulation needs. Read once by nsf_create_sim.
+ *
+ * weights[f] (host, float32) holds field f's six affine layers back to back, each as
+ * W (row-major, out x in) followed by b (out):
+ *   W1 [width x (3 + r)], b1 [width], W2..W5 [width x width] + b, W6 [d x width], b6 [d]
+ * with d = 3, 6, 9 for g, h, l. The network input is [X; z] and ELU (alpha = 1) follows
+ * layers 1-5. The physical value is out_scale[f][c] * y_c + out_shift[f][c]
+ * (de-normalisation of data normalised to mean 0, variance 1; supplementary
+ * "Training Details"). */
+typedef struct {
+  int32_t r;                   /* latent dimension, 1 <= r <= 32                          */
+  int32_t width;               /* hidden width: 64 or 128                                 */
+  int32_t n_hidden;            /* must be 5                                               */
+  nsf_precision precision;     /* FP32, or BF16 hidden layers with FP32 accumulation      */
+  const float *weights[3];     /* host, see above                                         */
+  double out_scale[3][9];
+  double out_shift[3][9];
+  int64_t n_particles;         /* |P|                                                     */
+  const float *X;              /* host, [3][n_particles] reference positions              */
+  double rho;                  /* density; m_p = rho V_p                                  */
+  double body_volume;          /* V_p = body_volume / n_integration                       */
+  int32_t grid_n;              /* nodes per axis, x_i = i dx, 8 <= grid_n <= 512          */
+  double dx, dt;
+  double gravity[3];
+  int32_t wall_nodes;          /* sticky band: nodes with any index < b or >= n - b       */
+  nsf_knife knife;
+  int32_t n_integration;       /* |N| per step                                            */
+  int32_t n_sample;            /* |S| <= |N|; S = first n_sample entries of the step list */
+  int32_t plan_steps;          /* rows in sample_plan; step n uses row n mod plan_steps   */
+  const int32_t *sample_plan;  /* host, [plan_steps][n_integration] indices into P        */
+  int32_t gn_iters;            /* Gauss-Newton iterations per step, 1..4 (paper: 2-3)     */
+  int32_t decode_every_step;   /* 1: each step ends by decoding all P into the sim's
+                                  decoded-position buffer (nsf_sim_buffer NSF_BUF_XDEC)  */
+  const double *z0;            /* host [r]                                                */
+  const double *z_prev;        /* host [r] or NULL (then z_{-1} = z_0, zero velocity)     */
+} nsf_sim_desc;
+
+typedef struct nsf_sim nsf_sim;  /* opaque, owned by the library */
+
+/* Bytes of device memory nsf_create_sim needs for this descriptor (0 if invalid). This
+ * is the unit of HBM-budget admission. */
+size_t nsf_sim_bytes(const nsf_sim_desc *d);
+
+/* Validate d, carve `arena` (device, >= nsf_sim_bytes(d) bytes, 256-byte aligned, owned
+ * by the caller and kept alive until nsf_destroy_sim), copy every input into it and
+ * pack the weights for the MFMA kernels. Work is enqueued on `stream`; the call returns
+ * after that work completes. Validation: r in 1..32, width in {64, 128}, n_hidden == 5,
+ * n_sample >= ceil(r / 3) (well-posedness of the inversion, Sec. 5.4),
+ * 1 <= n_sample <= n_integration <= n_particles, plan indices in range.
+ * NSF_ENODEV without a gfx950 device. */
+nsf_status nsf_create_sim(const nsf_sim_desc *d, void *arena, size_t arena_bytes,
+                          void *stream, nsf_sim **out);
+
+/* Advance n_steps latent steps (Sec. 5.1-5.3), async. The first call on a stream captures
+ * one step into a HIP graph; later calls replay it. No device-to-host transfer occurs. */
+nsf_status nsf_step(nsf_sim *s, int32_t n_steps, void *stream);
+
+/* Advance several sims together, async: each kernel of the step runs once over the
+ * union of the sims' work (fields of every sim in one launch, P2G of every sim in one
+ * launch, ...). Sims keep private grids and latents, so each sim's result is the same as
+ * stepping it alone (up to the order of float atomics). All sims must share width and
+ * precision. The launch shape is planned for this set of sims on first use and reused
+ * while the same set is passed. */
+nsf_status nsf_step_batch(nsf_sim *const *sims, int32_t n, int32_t n_steps, void *stream);
+
+/* Decode x = X + u(X, z_n) (Sec. 5.1), async. X: device [3][n] or NULL for the sim's own
+ * reference positions (then n must equal n_particles). x_out: device [3][n]. */
+nsf_status nsf_decode(nsf_sim *s, const float *X, int64_t n, float *x_out, void *stream);
+
+/* Copy the latent state to host (synchronises the stream). z, z_prev: host [r] or NULL;
+ * step: host or NULL. This is the whole dynamic state (checkpoint). */
+nsf_status nsf_get_latent(nsf_sim *s, double *z, double *z_prev, int64_t *step, void *stream);
+
+/* Restore a latent state (host arrays, z_prev NULL -> z), async. Clears sticky flags. */
+nsf_status nsf_set_latent(nsf_sim *s, const double *z, const double *z_prev, int64_t step,
+                          void *stream);
+
+/* Read the sticky device flags (synchronises). Returns NSF_OK with *flags = 0, or, with
+ * *flags set, the status of the first set condition in the order NONFINITE, SINGULAR,
+ * DOMAIN (a non-finite latent also throws particles off the grid). */
+nsf_status nsf_status_flags(nsf_sim *s, uint32_t *flags, void *stream);
+
+/* Inspect a per-step device buffer of the sim (read-only views for tests and callers
+ * that consume the step's intermediates). *ptr receives the device address and *count
+ * the number of elements (float unless noted).
+ *   NSF_BUF_U       u(X_N, z_n)          [3][n_integration]
+ *   NSF_BUF_UPREV   u(X_N, z_{n-1})      [3][n_integration]
+ *   NSF_BUF_TAU     h(X_N, z_n)          [6][n_integration]
+ *   NSF_BUF_C       l(X_N, z_n)          [9][n_integration]
+ *   NSF_BUF_JAC     du/dz at z_n on S    [3 r][n_sample], row c*r + j = du_c/dz_j
+ *   NSF_BUF_VNEW    G2P velocity on S    [3][n_sample]
+ *   NSF_BUF_XDEC    decoded positions    [3][n_particles]
+ *   NSF_BUF_GRID    grid (m, p_x, p_y, p_z) per node [4][grid_n^3] interleaved as float4;
+ *                   zero between steps (cleaned after use)
+ *   NSF_BUF_Z       double [3][r]: z_{n-1}, z_n, last Gauss-Newton iterate
+ * Buffers hold the values of the last completed step. */
+enum { NSF_BUF_U = 0, NSF_BUF_UPREV, NSF_BUF_TAU, NSF_BUF_C, NSF_BUF_JAC, NSF_BUF_VNEW,
+       NSF_BUF_XDEC, NSF_BUF_GRID, NSF_BUF_Z };
+nsf_status nsf_sim_buffer(nsf_sim *s, int32_t which, void **ptr, int64_t *count);
+
+/* Release host-side state and any captured graphs. The arena stays the caller's. */
+nsf_status nsf_destroy_sim(nsf_sim *s);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *nsf_last_error(void);
+
+/* Number of visible gfx950 devices (0 without a GPU). Does not create a context on
+ * machines without HIP devices. */
+int32_t nsf_device_count(void);
+
+/* ---- Field fitting (differentiation form) ------------------------------------------
+ * One MLP as above (in = 3 + r, width, out = d, 6 layers), weights in the same layout
+ * as nsf_sim_desc.weights but on the device. Per-point latents: the input of point p is
+ * [X_p ; z_rows[p]] with z_rows device float32 [n][r] row-major. Training data for the
+ * fields is fitted by minimising squared error (Sec. 4.5).
+ *
+ * nsf_mlp_forward: out device [d][n] (SoA); saved device float32 of nsf_mlp_saved_floats
+ *   (width, n) elements, receiving the five hidden pre-activations for the backward
+ *   (NULL = inference only).
+ * nsf_mlp_backward: given dout [d][n] = dLoss/dout, accumulate (+=) dW (device, same
+ *   layout and size as the weights) and write dz device [n][r] = dLoss/dz_rows (NULL to
+ *   skip). Requires `saved` from the forward of the same weights and inputs.
+ * Precision: NSF_FP32 (also used by the finite-difference check) or NSF_BF16 (hidden
+ * layers on BF16 MFMA, FP32 accumulation). */
+typedef struct {
+  int32_t r, width, d;
+  nsf_precision precision;
+  const float *weights;        /* device, layout as nsf_sim_desc.weights                  */
+} nsf_mlp;
+
+size_t nsf_mlp_param_count(int32_t r, int32_t width, int32_t d);
+size_t nsf_mlp_saved_floats(int32_t width, int64_t n);
+size_t nsf_mlp_workspace_bytes(const nsf_mlp *m, int64_t n);
+nsf_status nsf_mlp_forward(const nsf_mlp *m, const float *X, const float *z_rows, int64_t n,
+                           float *out, float *saved, void *workspace, size_t workspace_bytes,
+                           void *stream);
+nsf_status nsf_mlp_backward(const nsf_mlp *m, const float *X, const float *z_rows, int64_t n,
+                            const float *saved, const float *dout, float *dW, float *dz,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSF_H */

@@ -1,0 +1,664 @@
+// C ABI of the latent-step library: descriptor validation, arena layout, weight packing,
+// work tables and step orchestration (one HIP graph per stepped set of simulations).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nsf.h"
+#include "nsf_dev.h"
+#include "pack.h"
+
+using namespace nsf;
+
+namespace {
+
+thread_local std::string g_err;
+
+nsf_status fail(nsf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define NSF_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) return fail(NSF_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+const int kFieldOut[3] = {3, 6, 9};
+
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  }
+};
+
+// Byte offsets of every buffer of a sim inside its arena.
+struct Layout {
+  size_t simdev;
+  size_t w1p[3], whp[3], whb[3], bhp[3], w6p[3], b6[3];
+  size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, step, flags, gn_part;
+  size_t total;
+};
+
+int gn_entries(int r) { return r * (r + 1) / 2 + r; }
+
+Layout make_layout(const nsf_sim_desc* d) {
+  Layout L{};
+  Carver c;
+  const int r = d->r, W = d->width;
+  const int64_t P = d->n_particles, N = d->n_integration, S = d->n_sample;
+  L.simdev = c.take(sizeof(SimDev));
+  for (int f = 0; f < 3; ++f) {
+    const PackSizes ps = pack_sizes(r, W, kFieldOut[f]);
+    L.w1p[f] = c.take(ps.w1p * 4);
+    L.whp[f] = c.take(ps.whp * 4);
+    L.whb[f] = c.take(ps.whb * 2);
+    L.bhp[f] = c.take(ps.bhp * 4);
+    L.w6p[f] = c.take(ps.w6p * 4);
+    L.b6[f] = c.take(ps.b6 * 4);
+  }
+  L.X = c.take((size_t)3 * P * 4);
+  L.plan = c.take((size_t)d->plan_steps * N * 4);
+  L.u_n = c.take((size_t)3 * N * 4);
+  L.u_prev = c.take((size_t)3 * N * 4);
+  L.tau = c.take((size_t)6 * N * 4);
+  L.C = c.take((size_t)9 * N * 4);
+  L.J = c.take((size_t)3 * r * S * 4);
+  L.vnew = c.take((size_t)3 * S * 4);
+  L.u_gn = c.take((size_t)3 * S * 4);
+  L.J2 = c.take((size_t)3 * r * S * 4);
+  L.xdec = c.take((size_t)3 * P * 4);
+  const size_t n3 = (size_t)d->grid_n * d->grid_n * d->grid_n;
+  L.grid = c.take(n3 * 16);
+  L.z = c.take((size_t)3 * r * 8);
+  L.step = c.take(8);
+  L.flags = c.take(4);
+  L.gn_part = c.take((size_t)ceil_div(S, kGnChunk) * gn_entries(r) * 8);
+  L.total = c.off;
+  return L;
+}
+
+nsf_status validate(const nsf_sim_desc* d) {
+  if (!d) return fail(NSF_EINVAL, "descriptor is NULL");
+  if (d->r < 1 || d->r > kMaxR) return fail(NSF_EINVAL, "r = %d outside 1..%d", d->r, kMaxR);
+  if (d->width != 64 && d->width != 128) return fail(NSF_EINVAL, "width = %d (64 or 128)", d->width);
+  if (d->n_hidden != 5) return fail(NSF_EINVAL, "n_hidden = %d (the fields have 5 hidden layers)", d->n_hidden);
+  if (d->precision != NSF_FP32 && d->precision != NSF_BF16) return fail(NSF_EINVAL, "unknown precision");
+  for (int f = 0; f < 3; ++f)
+    if (!d->weights[f]) return fail(NSF_EINVAL, "weights[%d] is NULL", f);
+  if (d->n_particles < 1 || d->n_particles > (int64_t)INT32_MAX / 4)
+    return fail(NSF_EINVAL, "n_particles = %lld", (long long)d->n_particles);
+  if (!d->X) return fail(NSF_EINVAL, "X is NULL");
+  if (d->n_integration < 1 || d->n_integration > d->n_particles)
+    return fail(NSF_EINVAL, "n_integration = %d must be in 1..n_particles", d->n_integration);
+  if (d->n_sample < 1 || d->n_sample > d->n_integration)
+    return fail(NSF_EINVAL, "n_sample = %d must be in 1..n_integration", d->n_sample);
+  if (3 * (int64_t)d->n_sample < d->r)
+    return fail(NSF_EINVAL, "n_sample = %d < r / 3: the inversion is under-determined", d->n_sample);
+  if (d->plan_steps < 1 || !d->sample_plan) return fail(NSF_EINVAL, "sample_plan missing");
+  if (d->grid_n < 8 || d->grid_n > 512) return fail(NSF_EINVAL, "grid_n = %d outside 8..512", d->grid_n);
+  if (!(d->dx > 0) || !(d->dt > 0)) return fail(NSF_EINVAL, "dx and dt must be positive");
+  if (!(d->rho > 0) || !(d->body_volume > 0)) return fail(NSF_EINVAL, "rho and body_volume must be positive");
+  if (d->wall_nodes < 0 || 2 * d->wall_nodes >= d->grid_n) return fail(NSF_EINVAL, "wall_nodes = %d", d->wall_nodes);
+  if (d->gn_iters < 1 || d->gn_iters > 4) return fail(NSF_EINVAL, "gn_iters = %d outside 1..4", d->gn_iters);
+  if (!d->z0) return fail(NSF_EINVAL, "z0 is NULL");
+  for (int j = 0; j < d->r; ++j)
+    if (!std::isfinite(d->z0[j]) || (d->z_prev && !std::isfinite(d->z_prev[j])))
+      return fail(NSF_EINVAL, "initial latent is not finite");
+  const int64_t cnt = (int64_t)d->plan_steps * d->n_integration;
+  for (int64_t i = 0; i < cnt; ++i)
+    if (d->sample_plan[i] < 0 || d->sample_plan[i] >= d->n_particles)
+      return fail(NSF_EINVAL, "sample_plan[%lld] = %d out of range", (long long)i, d->sample_plan[i]);
+  return NSF_OK;
+}
+
+bool device_ok(std::string* why) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+    if (why) *why = "no HIP device visible";
+    return false;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    if (why) *why = "cannot query the current HIP device";
+    return false;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    if (why) *why = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+struct Plan;
+
+struct nsf_sim {
+  int device = 0;
+  int r = 0, width = 0;
+  bool bf16 = false;
+  int64_t n_part = 0;
+  int n_int = 0, n_samp = 0, gn_iters = 2;
+  bool decode_every_step = false;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  Layout L{};
+  SimDev hd{};            // host copy of the device constants
+  SimDev* dd = nullptr;   // device copy in the arena
+  FieldPack pack[3]{};
+  float scale[3][9]{}, shift[3][9]{};
+  std::unique_ptr<Plan> solo;
+};
+
+// Work tables and the captured step graph for one ordered set of sims.
+struct Plan {
+  std::vector<nsf_sim*> members;
+  int width = 0, gn_iters = 0, tc = 0;
+  bool bf16 = false, decode = false;
+  void* dbuf = nullptr;
+  int32_t* d_counts = nullptr;
+  SimDev* d_sims = nullptr;
+  FieldJob* d_jobs = nullptr;
+  FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tD = nullptr;
+  BlockWork *d_bP = nullptr, *d_bS = nullptr, *d_bGN = nullptr;
+  int nA = 0, nG = 0, nD = 0, nP = 0, nS = 0, nGN = 0, nsims = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~Plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (dbuf) (void)hipFree(dbuf);
+  }
+};
+
+namespace {
+
+std::mutex g_plans_mu;
+std::map<std::vector<nsf_sim*>, std::unique_ptr<Plan>> g_batch_plans;
+
+FieldJob base_job(const nsf_sim* s, int field, const double* z) {
+  FieldJob j{};
+  j.w = s->pack[field];
+  j.z = z;
+  j.X = s->hd.X;
+  j.ldx = s->n_part;
+  j.idx = s->hd.plan;
+  j.step = s->hd.step;
+  j.plan_steps = s->hd.plan_steps;
+  j.plan_ld = s->n_int;
+  j.r = s->r;
+  j.d = kFieldOut[field];
+  for (int c = 0; c < 9; ++c) {
+    j.scale[c] = s->scale[field][c];
+    j.shift[c] = s->shift[field][c];
+  }
+  return j;
+}
+
+void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc) {
+  for (int p0 = 0; p0 < n; p0 += kTile) {
+    if (ntan == 0) {
+      out.push_back({job, p0, 0, 0});
+    } else {
+      for (int t0 = 0; t0 < ntan; t0 += tc) out.push_back({job, p0, t0, std::min(tc, ntan - t0)});
+    }
+  }
+}
+
+template <class T>
+size_t put(std::vector<char>& blob, const std::vector<T>& v) {
+  const size_t off = align_up(blob.size());
+  blob.resize(off + std::max<size_t>(v.size() * sizeof(T), 1));
+  if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+  blob.resize(align_up(blob.size()));
+  return off;
+}
+
+nsf_status build_plan(Plan& P, hipStream_t stream) {
+  nsf_sim* s0 = P.members[0];
+  P.width = s0->width;
+  P.bf16 = s0->bf16;
+  P.gn_iters = s0->gn_iters;
+  P.decode = s0->decode_every_step;
+  P.tc = fields_max_tangents(P.width, P.bf16);
+  std::vector<SimDev> sims;
+  std::vector<FieldJob> jobs;
+  std::vector<FieldTile> tA_jac, tA_prim, tG, tD;
+  std::vector<BlockWork> bP, bS, bGN;
+  for (size_t si = 0; si < P.members.size(); ++si) {
+    nsf_sim* s = P.members[si];
+    const SimDev& H = s->hd;
+    sims.push_back(H);
+    const double* zp = H.z;
+    const double* zc = H.z + s->r;
+    const double* zi = H.z + 2 * s->r;
+    const int N = s->n_int, S = s->n_samp, r = s->r;
+    const int j0 = (int)jobs.size();
+    // pass A: g with its Jacobian on S, g on N \ S, g at z_{n-1}, h, l
+    FieldJob a = base_job(s, NSF_FIELD_G, zc);
+    a.n = S; a.out = H.u_n; a.ldo = N; a.jac = H.J; a.ldj = S;
+    jobs.push_back(a);
+    add_tiles(tA_jac, j0, S, r, P.tc);
+    if (N > S) {
+      FieldJob b = base_job(s, NSF_FIELD_G, zc);
+      b.n = N - S; b.p_off = S; b.out = H.u_n + S; b.ldo = N;
+      add_tiles(tA_prim, (int)jobs.size(), N - S, 0, P.tc);
+      jobs.push_back(b);
+    }
+    FieldJob c = base_job(s, NSF_FIELD_G, zp);
+    c.n = N; c.out = H.u_prev; c.ldo = N;
+    add_tiles(tA_prim, (int)jobs.size(), N, 0, P.tc);
+    jobs.push_back(c);
+    FieldJob h = base_job(s, NSF_FIELD_H, zc);
+    h.n = N; h.out = H.tau; h.ldo = N;
+    add_tiles(tA_prim, (int)jobs.size(), N, 0, P.tc);
+    jobs.push_back(h);
+    FieldJob l = base_job(s, NSF_FIELD_L, zc);
+    l.n = N; l.out = H.C; l.ldo = N;
+    add_tiles(tA_prim, (int)jobs.size(), N, 0, P.tc);
+    jobs.push_back(l);
+    // Gauss-Newton iterate: g and its Jacobian on S
+    FieldJob g = base_job(s, NSF_FIELD_G, zi);
+    g.n = S; g.out = H.u_gn; g.ldo = S; g.jac = H.J2; g.ldj = S;
+    add_tiles(tG, (int)jobs.size(), S, r, P.tc);
+    jobs.push_back(g);
+    // decode all particles at the new latent
+    FieldJob dj = base_job(s, NSF_FIELD_G, zc);
+    dj.idx = nullptr; dj.step = nullptr; dj.n = (int)s->n_part; dj.mode = 1;
+    dj.out = H.xdec; dj.ldo = s->n_part;
+    add_tiles(tD, (int)jobs.size(), (int)s->n_part, 0, 0);
+    jobs.push_back(dj);
+    for (int p0 = 0; p0 < N; p0 += kMpmBlock) bP.push_back({(int)si, p0});
+    for (int p0 = 0; p0 < S; p0 += kMpmBlock) bS.push_back({(int)si, p0});
+    for (int p0 = 0; p0 < S; p0 += kGnChunk) bGN.push_back({(int)si, p0});
+  }
+  std::vector<FieldTile> tA(tA_jac);
+  tA.insert(tA.end(), tA_prim.begin(), tA_prim.end());
+  P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nD = (int)tD.size();
+  P.nP = (int)bP.size(); P.nS = (int)bS.size(); P.nGN = (int)bGN.size();
+  P.nsims = (int)sims.size();
+  std::vector<int32_t> counts = {P.nA, P.nG, P.nD, P.nP, P.nS, P.nGN, P.nsims, 0};
+  std::vector<char> blob;
+  const size_t o_counts = put(blob, counts);
+  const size_t o_sims = put(blob, sims);
+  const size_t o_jobs = put(blob, jobs);
+  const size_t o_tA = put(blob, tA);
+  const size_t o_tG = put(blob, tG);
+  const size_t o_tD = put(blob, tD);
+  const size_t o_bP = put(blob, bP);
+  const size_t o_bS = put(blob, bS);
+  const size_t o_bGN = put(blob, bGN);
+  NSF_HIP(hipMalloc(&P.dbuf, blob.size()));
+  char* b = static_cast<char*>(P.dbuf);
+  P.d_counts = reinterpret_cast<int32_t*>(b + o_counts);
+  P.d_sims = reinterpret_cast<SimDev*>(b + o_sims);
+  P.d_jobs = reinterpret_cast<FieldJob*>(b + o_jobs);
+  P.d_tA = reinterpret_cast<FieldTile*>(b + o_tA);
+  P.d_tG = reinterpret_cast<FieldTile*>(b + o_tG);
+  P.d_tD = reinterpret_cast<FieldTile*>(b + o_tD);
+  P.d_bP = reinterpret_cast<BlockWork*>(b + o_bP);
+  P.d_bS = reinterpret_cast<BlockWork*>(b + o_bS);
+  P.d_bGN = reinterpret_cast<BlockWork*>(b + o_bGN);
+  NSF_HIP(hipMemcpyAsync(P.dbuf, blob.data(), blob.size(), hipMemcpyHostToDevice, stream));
+  NSF_HIP(hipStreamSynchronize(stream));
+  return NSF_OK;
+}
+
+nsf_status enqueue_step(Plan& P, hipStream_t s) {
+  const int waves_per_block = 4;
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
+                              ceil_div(P.nA, waves_per_block), s));
+  NSF_HIP(launch_p2g(P.d_sims, P.d_bP, P.d_counts + 3, P.nP, s));
+  NSF_HIP(launch_g2p(P.d_sims, P.d_bS, P.d_counts + 4, P.nS, s));
+  NSF_HIP(launch_grid_clean(P.d_sims, P.d_bP, P.d_counts + 3, P.nP, s));
+  NSF_HIP(launch_gn_reduce(P.d_sims, P.d_bGN, P.d_counts + 5, 0, P.nGN, s));
+  NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.nsims, s));
+  for (int k = 1; k < P.gn_iters; ++k) {
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1,
+                                ceil_div(P.nG, waves_per_block), s));
+    NSF_HIP(launch_gn_reduce(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.nGN, s));
+    NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, k, P.nsims, s));
+  }
+  if (P.decode)
+    NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 2,
+                                ceil_div(P.nD, waves_per_block), s));
+  return NSF_OK;
+}
+
+nsf_status run_plan(Plan& P, int32_t n_steps, hipStream_t s) {
+  if (s == nullptr) {
+    for (int i = 0; i < n_steps; ++i) {
+      const nsf_status st = enqueue_step(P, s);
+      if (st != NSF_OK) return st;
+    }
+    return NSF_OK;
+  }
+  if (!P.exec) {
+    NSF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const nsf_status st = enqueue_step(P, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != NSF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(NSF_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    P.graph = g;
+    NSF_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+  }
+  for (int i = 0; i < n_steps; ++i) NSF_HIP(hipGraphLaunch(P.exec, s));
+  return NSF_OK;
+}
+
+void drop_batch_plans_with(nsf_sim* s) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  for (auto it = g_batch_plans.begin(); it != g_batch_plans.end();) {
+    if (std::find(it->first.begin(), it->first.end(), s) != it->first.end()) it = g_batch_plans.erase(it);
+    else ++it;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+const char* nsf_last_error(void) { return g_err.c_str(); }
+
+int32_t nsf_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  return n;
+}
+
+size_t nsf_sim_bytes(const nsf_sim_desc* d) {
+  if (validate(d) != NSF_OK) return 0;
+  return make_layout(d).total;
+}
+
+nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes, void* stream,
+                          nsf_sim** out) {
+  if (!out) return fail(NSF_EINVAL, "out is NULL");
+  *out = nullptr;
+  nsf_status st = validate(d);
+  if (st != NSF_OK) return st;
+  std::string why;
+  if (!device_ok(&why)) return fail(NSF_ENODEV, "%s", why.c_str());
+  const Layout L = make_layout(d);
+  if (!arena) return fail(NSF_EINVAL, "arena is NULL");
+  if ((reinterpret_cast<uintptr_t>(arena) & (kAlign - 1)) != 0) return fail(NSF_EINVAL, "arena must be 256-byte aligned");
+  if (arena_bytes < L.total) return fail(NSF_ENOMEM, "arena has %zu bytes, needs %zu", arena_bytes, L.total);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::unique_ptr<nsf_sim> sim(new nsf_sim());
+  NSF_HIP(hipGetDevice(&sim->device));
+  sim->r = d->r;
+  sim->width = d->width;
+  sim->bf16 = d->precision == NSF_BF16;
+  sim->n_part = d->n_particles;
+  sim->n_int = d->n_integration;
+  sim->n_samp = d->n_sample;
+  sim->gn_iters = d->gn_iters;
+  sim->decode_every_step = d->decode_every_step != 0;
+  sim->arena = static_cast<char*>(arena);
+  sim->arena_bytes = arena_bytes;
+  sim->L = L;
+  char* A = sim->arena;
+  const int r = d->r, W = d->width;
+  for (int f = 0; f < 3; ++f)
+    for (int c = 0; c < 9; ++c) {
+      sim->scale[f][c] = c < kFieldOut[f] ? (float)d->out_scale[f][c] : 0.f;
+      sim->shift[f][c] = c < kFieldOut[f] ? (float)d->out_shift[f][c] : 0.f;
+    }
+  // pack weights on the host, one upload per field
+  std::vector<char> staging;
+  for (int f = 0; f < 3; ++f) {
+    const int dd = kFieldOut[f];
+    const PackSizes ps = pack_sizes(r, W, dd);
+    std::vector<float> w1p(ps.w1p), whp(ps.whp), bhp(ps.bhp), w6p(ps.w6p), b6(ps.b6);
+    std::vector<uint16_t> whb(ps.whb);
+    pack_field(d->weights[f], r, W, dd, w1p.data(), whp.data(), whb.data(), bhp.data(), w6p.data(), b6.data());
+    NSF_HIP(hipMemcpyAsync(A + L.w1p[f], w1p.data(), w1p.size() * 4, hipMemcpyHostToDevice, s));
+    NSF_HIP(hipMemcpyAsync(A + L.whp[f], whp.data(), whp.size() * 4, hipMemcpyHostToDevice, s));
+    NSF_HIP(hipMemcpyAsync(A + L.whb[f], whb.data(), whb.size() * 2, hipMemcpyHostToDevice, s));
+    NSF_HIP(hipMemcpyAsync(A + L.bhp[f], bhp.data(), bhp.size() * 4, hipMemcpyHostToDevice, s));
+    NSF_HIP(hipMemcpyAsync(A + L.w6p[f], w6p.data(), w6p.size() * 4, hipMemcpyHostToDevice, s));
+    NSF_HIP(hipMemcpyAsync(A + L.b6[f], b6.data(), b6.size() * 4, hipMemcpyHostToDevice, s));
+    NSF_HIP(hipStreamSynchronize(s));  // host staging vectors die at the end of this scope
+    FieldPack& fp = sim->pack[f];
+    fp.w1p = reinterpret_cast<const float*>(A + L.w1p[f]);
+    fp.whp = reinterpret_cast<const float*>(A + L.whp[f]);
+    fp.whb = reinterpret_cast<const bf16x8*>(A + L.whb[f]);
+    fp.bhp = reinterpret_cast<const float*>(A + L.bhp[f]);
+    fp.w6p = reinterpret_cast<const float*>(A + L.w6p[f]);
+    fp.b6 = reinterpret_cast<const float*>(A + L.b6[f]);
+  }
+  const int64_t P = d->n_particles;
+  NSF_HIP(hipMemcpyAsync(A + L.X, d->X, (size_t)3 * P * 4, hipMemcpyHostToDevice, s));
+  NSF_HIP(hipMemcpyAsync(A + L.plan, d->sample_plan, (size_t)d->plan_steps * d->n_integration * 4,
+                         hipMemcpyHostToDevice, s));
+  std::vector<double> z(3 * r);
+  for (int j = 0; j < r; ++j) {
+    z[j] = d->z_prev ? d->z_prev[j] : d->z0[j];
+    z[r + j] = d->z0[j];
+    z[2 * r + j] = d->z0[j];
+  }
+  NSF_HIP(hipMemcpyAsync(A + L.z, z.data(), z.size() * 8, hipMemcpyHostToDevice, s));
+  const size_t n3 = (size_t)d->grid_n * d->grid_n * d->grid_n;
+  NSF_HIP(hipMemsetAsync(A + L.grid, 0, n3 * 16, s));
+  NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
+  NSF_HIP(hipMemsetAsync(A + L.flags, 0, 4, s));
+  NSF_HIP(hipMemsetAsync(A + L.xdec, 0, (size_t)3 * P * 4, s));
+
+  SimDev& H = sim->hd;
+  H.r = r;
+  H.n_part = (int32_t)P;
+  H.n_int = d->n_integration;
+  H.n_samp = d->n_sample;
+  H.plan_steps = d->plan_steps;
+  H.grid_n = d->grid_n;
+  H.wall = d->wall_nodes;
+  H.gn_iters = d->gn_iters;
+  H.knife_on = d->knife.enabled ? 1 : 0;
+  H.n_gn_chunks = ceil_div(d->n_sample, kGnChunk);
+  H.width = W;
+  const double Vp = d->body_volume / d->n_integration;
+  H.dx = (float)d->dx;
+  H.inv_dx = (float)(1.0 / d->dx);
+  H.dt = (float)d->dt;
+  H.mp = (float)(d->rho * Vp);
+  H.stress_k = (float)(d->dt * Vp * 4.0 / (d->dx * d->dx));
+  for (int c = 0; c < 3; ++c) {
+    H.grav[c] = (float)d->gravity[c];
+    H.grav_d[c] = d->gravity[c];
+    H.kn[c] = d->knife.normal[c];
+    H.kv[c] = d->knife.velocity[c];
+  }
+  H.dt_d = d->dt;
+  H.dx_d = d->dx;
+  H.koff = d->knife.offset;
+  H.khalf = d->knife.half_thickness;
+  H.kz0 = d->knife.edge_z0;
+  H.kspeed = d->knife.edge_speed;
+  H.X = reinterpret_cast<const float*>(A + L.X);
+  H.plan = reinterpret_cast<const int32_t*>(A + L.plan);
+  H.u_n = reinterpret_cast<float*>(A + L.u_n);
+  H.u_prev = reinterpret_cast<float*>(A + L.u_prev);
+  H.tau = reinterpret_cast<float*>(A + L.tau);
+  H.C = reinterpret_cast<float*>(A + L.C);
+  H.J = reinterpret_cast<float*>(A + L.J);
+  H.vnew = reinterpret_cast<float*>(A + L.vnew);
+  H.u_gn = reinterpret_cast<float*>(A + L.u_gn);
+  H.J2 = reinterpret_cast<float*>(A + L.J2);
+  H.xdec = reinterpret_cast<float*>(A + L.xdec);
+  H.grid = reinterpret_cast<float4*>(A + L.grid);
+  H.z = reinterpret_cast<double*>(A + L.z);
+  H.step = reinterpret_cast<int64_t*>(A + L.step);
+  H.flags = reinterpret_cast<uint32_t*>(A + L.flags);
+  H.gn_part = reinterpret_cast<double*>(A + L.gn_part);
+  sim->dd = reinterpret_cast<SimDev*>(A + L.simdev);
+  NSF_HIP(hipMemcpyAsync(sim->dd, &H, sizeof(SimDev), hipMemcpyHostToDevice, s));
+  NSF_HIP(hipStreamSynchronize(s));
+  *out = sim.release();
+  return NSF_OK;
+}
+
+nsf_status nsf_step(nsf_sim* s, int32_t n_steps, void* stream) {
+  if (!s) return fail(NSF_EINVAL, "sim is NULL");
+  if (n_steps < 0) return fail(NSF_EINVAL, "n_steps < 0");
+  if (n_steps == 0) return NSF_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!s->solo) {
+    std::unique_ptr<Plan> p(new Plan());
+    p->members.push_back(s);
+    const nsf_status e = build_plan(*p, st);
+    if (e != NSF_OK) return e;
+    s->solo = std::move(p);
+  }
+  return run_plan(*s->solo, n_steps, st);
+}
+
+nsf_status nsf_step_batch(nsf_sim* const* sims, int32_t n, int32_t n_steps, void* stream) {
+  if (!sims || n < 1) return fail(NSF_EINVAL, "empty batch");
+  if (n_steps < 0) return fail(NSF_EINVAL, "n_steps < 0");
+  if (n == 1) return nsf_step(sims[0], n_steps, stream);
+  std::vector<nsf_sim*> key(sims, sims + n);
+  for (int i = 0; i < n; ++i) {
+    if (!key[i]) return fail(NSF_EINVAL, "sims[%d] is NULL", i);
+    if (key[i]->width != key[0]->width || key[i]->bf16 != key[0]->bf16 ||
+        key[i]->gn_iters != key[0]->gn_iters || key[i]->decode_every_step != key[0]->decode_every_step)
+      return fail(NSF_EINVAL, "sims[%d] differs in width, precision, gn_iters or decode mode", i);
+    for (int j = 0; j < i; ++j)
+      if (key[j] == key[i]) return fail(NSF_EINVAL, "sim listed twice in a batch");
+  }
+  if (n_steps == 0) return NSF_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Plan* plan = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    auto it = g_batch_plans.find(key);
+    if (it != g_batch_plans.end()) plan = it->second.get();
+  }
+  if (!plan) {
+    std::unique_ptr<Plan> p(new Plan());
+    p->members = key;
+    const nsf_status e = build_plan(*p, st);
+    if (e != NSF_OK) return e;
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    if (g_batch_plans.size() >= 16) g_batch_plans.clear();
+    plan = p.get();
+    g_batch_plans[key] = std::move(p);
+  }
+  return run_plan(*plan, n_steps, st);
+}
+
+nsf_status nsf_decode(nsf_sim* s, const float* X, int64_t n, float* x_out, void* stream) {
+  if (!s) return fail(NSF_EINVAL, "sim is NULL");
+  if (!x_out) return fail(NSF_EINVAL, "x_out is NULL");
+  if (n < 0 || n > (int64_t)INT32_MAX / 4) return fail(NSF_EINVAL, "n = %lld", (long long)n);
+  if (!X && n != s->n_part) return fail(NSF_EINVAL, "own X has %lld points, n = %lld", (long long)s->n_part, (long long)n);
+  if (n == 0) return NSF_OK;
+  FieldJob j = base_job(s, NSF_FIELD_G, s->hd.z + s->r);
+  j.idx = nullptr;
+  j.step = nullptr;
+  j.X = X ? X : s->hd.X;
+  j.ldx = n;
+  j.n = (int)n;
+  j.mode = 1;
+  j.out = x_out;
+  j.ldo = n;
+  NSF_HIP(launch_fields_dense(s->width, s->bf16, j, ceil_div(n, kTile), static_cast<hipStream_t>(stream)));
+  return NSF_OK;
+}
+
+nsf_status nsf_get_latent(nsf_sim* s, double* z, double* z_prev, int64_t* step, void* stream) {
+  if (!s) return fail(NSF_EINVAL, "sim is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (z) NSF_HIP(hipMemcpyAsync(z, s->hd.z + s->r, s->r * 8, hipMemcpyDeviceToHost, st));
+  if (z_prev) NSF_HIP(hipMemcpyAsync(z_prev, s->hd.z, s->r * 8, hipMemcpyDeviceToHost, st));
+  if (step) NSF_HIP(hipMemcpyAsync(step, s->hd.step, 8, hipMemcpyDeviceToHost, st));
+  NSF_HIP(hipStreamSynchronize(st));
+  return NSF_OK;
+}
+
+nsf_status nsf_set_latent(nsf_sim* s, const double* z, const double* z_prev, int64_t step, void* stream) {
+  if (!s || !z) return fail(NSF_EINVAL, "sim or z is NULL");
+  if (step < 0) return fail(NSF_EINVAL, "step < 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<double> buf(3 * s->r);
+  for (int j = 0; j < s->r; ++j) {
+    buf[j] = z_prev ? z_prev[j] : z[j];
+    buf[s->r + j] = z[j];
+    buf[2 * s->r + j] = z[j];
+  }
+  const uint32_t zero = 0;
+  NSF_HIP(hipMemcpyAsync(s->hd.z, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, st));
+  NSF_HIP(hipMemcpyAsync(s->hd.step, &step, 8, hipMemcpyHostToDevice, st));
+  NSF_HIP(hipMemcpyAsync(s->hd.flags, &zero, 4, hipMemcpyHostToDevice, st));
+  NSF_HIP(hipStreamSynchronize(st));
+  return NSF_OK;
+}
+
+nsf_status nsf_status_flags(nsf_sim* s, uint32_t* flags, void* stream) {
+  if (!s || !flags) return fail(NSF_EINVAL, "sim or flags is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t f = 0;
+  NSF_HIP(hipMemcpyAsync(&f, s->hd.flags, 4, hipMemcpyDeviceToHost, st));
+  NSF_HIP(hipStreamSynchronize(st));
+  *flags = f;
+  if (f & FLAG_NONFINITE) return fail(NSF_ENONFINITE, "the latent or the residual became non-finite");
+  if (f & FLAG_SINGULAR) return fail(NSF_ESINGULAR, "Gauss-Newton normal matrix is not positive definite");
+  if (f & FLAG_DOMAIN) return fail(NSF_EDOMAIN, "a particle stencil left the grid");
+  return NSF_OK;
+}
+
+nsf_status nsf_sim_buffer(nsf_sim* s, int32_t which, void** ptr, int64_t* count) {
+  if (!s || !ptr || !count) return fail(NSF_EINVAL, "NULL argument");
+  const SimDev& H = s->hd;
+  const int64_t N = s->n_int, S = s->n_samp, P = s->n_part, r = s->r;
+  switch (which) {
+    case NSF_BUF_U: *ptr = H.u_n; *count = 3 * N; break;
+    case NSF_BUF_UPREV: *ptr = H.u_prev; *count = 3 * N; break;
+    case NSF_BUF_TAU: *ptr = H.tau; *count = 6 * N; break;
+    case NSF_BUF_C: *ptr = H.C; *count = 9 * N; break;
+    case NSF_BUF_JAC: *ptr = H.J; *count = 3 * r * S; break;
+    case NSF_BUF_VNEW: *ptr = H.vnew; *count = 3 * S; break;
+    case NSF_BUF_XDEC: *ptr = H.xdec; *count = 3 * P; break;
+    case NSF_BUF_GRID: *ptr = H.grid; *count = (int64_t)4 * H.grid_n * H.grid_n * H.grid_n; break;
+    case NSF_BUF_Z: *ptr = H.z; *count = 3 * r; break;
+    default: return fail(NSF_EINVAL, "unknown buffer %d", which);
+  }
+  return NSF_OK;
+}
+
+nsf_status nsf_destroy_sim(nsf_sim* s) {
+  if (!s) return NSF_OK;
+  drop_batch_plans_with(s);
+  delete s;
+  return NSF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Device-side data structures shared by the library's kernels and host orchestration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nsf {
+
+constexpr int kMaxR = 32;          // largest latent dimension
+constexpr int kTile = 32;          // points per wave tile (MFMA N dimension)
+constexpr int kGnChunk = 128;      // sample points per Gauss-Newton reduction block
+constexpr int kMpmBlock = 256;     // particles per P2G / G2P block
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Hidden neuron held in accumulator register i of M-block mb by lane half h (lanes 0-31:
+// h = 0, lanes 32-63: h = 1) for the 32x32 MFMA output layout: within each group of 8
+// rows, lanes 0-31 hold rows 0-3 and lanes 32-63 rows 4-7.
+__host__ __device__ inline int acc_neuron(int mb, int i, int h) {
+  return 32 * mb + 8 * (i >> 2) + 4 * h + (i & 3);
+}
+
+// Packed parameters of one field (one MLP), all in device memory. See pack.cpp for how
+// the host builds each array from the row-major masters.
+struct FieldPack {
+  const float* w1p;      // layer 1 incl. bias column: [MB][K1s][64] MFMA A operands
+  const float* whp;      // hidden layers 2..5, FP32 A operands: [4][MB][W/8][64][4]
+  const bf16x8* whb;     // hidden layers 2..5, BF16 A operands: [4][MB][W/16][64]
+  const float* bhp;      // hidden biases in accumulator order: [4][2][W/2]
+  const float* w6p;      // output weights in accumulator order: [d][2][W/2]
+  const float* b6;       // output bias [d]
+};
+
+// One batch of MLP evaluations: a field at one latent over a list of points.
+struct FieldJob {
+  FieldPack w;
+  const double* z;           // device latent (r)
+  const float* X;            // reference positions SoA, leading dimension ldx
+  const int32_t* idx;        // gather list (NULL: point index is the row of X)
+  const int64_t* step;       // if non-NULL, idx += (step mod plan_steps) * plan_ld
+  int64_t ldx;
+  int32_t plan_steps, plan_ld;
+  int32_t p_off;             // point p of this job reads list entry p_off + p
+  int32_t n;                 // number of points
+  int32_t r, d;
+  int32_t mode;              // 0: out = field; 1: out = X + field (decode)
+  int32_t pad0;
+  float* out; int64_t ldo;   // SoA [d][ldo], already offset to this job's first point
+  float* jac; int64_t ldj;   // SoA [3 r][ldj] (row c*r + j), only for d = 3
+  float scale[9], shift[9];
+};
+
+// One wave's work: 32 points of a job, the primal plus tangents [t0, t0 + nt).
+// Only the tile with t0 == 0 writes the primal output.
+struct FieldTile {
+  int32_t job, p0, t0, nt;
+};
+
+// Per-simulation constants and device pointers (lives in the sim's arena and is copied
+// into batch tables).
+struct SimDev {
+  int32_t r, n_part, n_int, n_samp;
+  int32_t plan_steps, grid_n, wall, gn_iters;
+  int32_t knife_on, n_gn_chunks, width, pad0;
+  float dx, inv_dx, dt, mp;          // mp = particle mass rho V_p
+  float stress_k;                    // dt V_p 4 / dx^2
+  float grav[3];
+  double dt_d, dx_d;
+  double grav_d[3];
+  double kn[3], koff, khalf, kz0, kspeed, kv[3];
+  const float* X;                    // [3][n_part]
+  const int32_t* plan;               // [plan_steps][n_int]
+  float* u_n;                        // [3][n_int]
+  float* u_prev;                     // [3][n_int]
+  float* tau;                        // [6][n_int]
+  float* C;                          // [9][n_int]
+  float* J;                          // [3r][n_samp]  at z_n
+  float* vnew;                       // [3][n_samp]
+  float* u_gn;                       // [3][n_samp]   at the Gauss-Newton iterate
+  float* J2;                         // [3r][n_samp]  at the Gauss-Newton iterate
+  float* xdec;                       // [3][n_part]
+  float4* grid;                      // [grid_n^3] (m, p_x, p_y, p_z)
+  double* z;                         // [3][r]: z_{n-1}, z_n, iterate
+  int64_t* step;
+  uint32_t* flags;
+  double* gn_part;                   // [n_gn_chunks][E], E = r(r+1)/2 + r
+};
+
+enum : uint32_t { FLAG_DOMAIN = 1u, FLAG_NONFINITE = 2u, FLAG_SINGULAR = 4u };
+
+// Work item of a per-particle MPM kernel or a Gauss-Newton reduction block.
+struct BlockWork {
+  int32_t sim, p0;
+};
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
+                               const FieldTile* tiles, const int32_t* n_tiles, int grid,
+                               hipStream_t s);
+hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_tiles,
+                               hipStream_t s);
+int fields_max_tangents(int width, bool bf16);
+
+hipError_t launch_p2g(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
+                      int grid, hipStream_t s);
+hipError_t launch_g2p(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
+                      int grid, hipStream_t s);
+hipError_t launch_grid_clean(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
+                             int grid, hipStream_t s);
+hipError_t launch_gn_reduce(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
+                            int iter, int grid, hipStream_t s);
+hipError_t launch_gn_solve(const SimDev* sims, const int32_t* n_sims, int iter, int grid,
+                           hipStream_t s);
+
+}  // namespace nsf

@@ -1,0 +1,30 @@
+// Host-side weight packing for the MFMA field kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace nsf {
+
+// Pointers into one field's row-major parameter block (layout of nsf_sim_desc.weights).
+struct MlpView {
+  const float* W1;
+  const float* b1;
+  const float* Wh[4];
+  const float* bh[4];
+  const float* W6;
+  const float* b6;
+};
+
+struct PackSizes {
+  size_t w1p, whp, whb, bhp, w6p, b6;  // element counts (whb in bf16 elements)
+};
+
+size_t mlp_param_count(int r, int width, int d);
+MlpView view_master(const float* p, int r, int width, int d);
+PackSizes pack_sizes(int r, int width, int d);
+uint16_t float_to_bf16(float f);
+void pack_field(const float* master, int r, int width, int d, float* w1p, float* whp,
+                uint16_t* whb, float* bhp, float* w6p, float* b6);
+
+}  // namespace nsf

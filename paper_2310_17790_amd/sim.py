@@ -1,0 +1,157 @@
+"""Python face of one reduced simulation (a thin owner around nsf_create_sim & co).
+
+PyTorch provides the device memory (one uint8 arena tensor per sim) and the streams;
+all computation happens in libnsf.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+FIELD_OUT = (3, 6, 9)
+
+
+def flatten_mlp(layers: Sequence[Tuple[np.ndarray, np.ndarray]]) -> np.ndarray:
+    """Concatenate (W row-major, b) for layers 1..6 into the ABI's weight layout."""
+    parts = []
+    for W, b in layers:
+        parts.append(np.ascontiguousarray(W, np.float32).ravel())
+        parts.append(np.ascontiguousarray(b, np.float32).ravel())
+    return np.concatenate(parts)
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Sim:
+    """One reduced-order simulation resident on the current GPU.
+
+    ``w`` is any object with the attributes of ``synth.Workload`` (fields, X, z0, plan,
+    constants). ``precision`` is "fp32" or "bf16".
+    """
+
+    def __init__(self, w, precision: str = "fp32", decode_every_step: bool = True,
+                 stream: Optional[torch.cuda.Stream] = None, device: Optional[torch.device] = None):
+        self.r = int(w.r)
+        self.width = int(w.width)
+        self.n_particles = int(w.X.shape[1])
+        self.n_integration = int(w.plan.shape[1])
+        self.n_sample = int(w.n_sample)
+        self.grid_n = int(w.grid_n)
+        self.precision = precision
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        keep = []  # host arrays referenced by the descriptor until create returns
+
+        def fptr(a):
+            a = np.ascontiguousarray(a, np.float32)
+            keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_float))
+
+        def dptr(a):
+            a = np.ascontiguousarray(a, np.float64)
+            keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_double))
+
+        d = A.nsf_sim_desc()
+        d.r, d.width, d.n_hidden = self.r, self.width, 5
+        d.precision = A.NSF_BF16 if precision == "bf16" else A.NSF_FP32
+        for f, name in enumerate(("g", "h", "l")):
+            d.weights[f] = fptr(flatten_mlp(w.fields[name]))
+            for c in range(FIELD_OUT[f]):
+                d.out_scale[f][c] = float(w.out_scale[name][c])
+                d.out_shift[f][c] = float(w.out_shift[name][c])
+        d.n_particles = self.n_particles
+        d.X = fptr(w.X)
+        d.rho, d.body_volume = float(w.rho), float(w.body_volume)
+        d.grid_n, d.dx, d.dt = self.grid_n, float(w.dx), float(w.dt)
+        for c in range(3):
+            d.gravity[c] = float(w.gravity[c])
+        d.wall_nodes = int(w.wall_nodes)
+        k = w.knife
+        d.knife.enabled = 1 if k.enabled else 0
+        for c in range(3):
+            d.knife.normal[c] = float(k.normal[c])
+            d.knife.velocity[c] = float(k.velocity[c])
+        d.knife.offset, d.knife.half_thickness = float(k.offset), float(k.half_thickness)
+        d.knife.edge_z0, d.knife.edge_speed = float(k.edge_z0), float(k.edge_speed)
+        d.n_integration, d.n_sample = self.n_integration, self.n_sample
+        plan = np.ascontiguousarray(w.plan, np.int32)
+        keep.append(plan)
+        d.plan_steps = int(plan.shape[0])
+        d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
+        d.gn_iters = int(w.gn_iters)
+        d.decode_every_step = 1 if decode_every_step else 0
+        d.z0 = dptr(w.z0)
+        d.z_prev = dptr(w.z_prev) if w.z_prev is not None else None
+        nbytes = A.nsf_sim_bytes(d)
+        if nbytes == 0:
+            raise A.NsfError(A.NSF_EINVAL, A.nsf_last_error())
+        self.arena_bytes = nbytes
+        self._raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._raw.data_ptr()
+        self._off = (-base) % 256
+        self.arena = self._raw[self._off:self._off + nbytes]
+        self.handle = A.nsf_create_sim(d, self.arena.data_ptr(), nbytes, _stream_handle(stream))
+        del keep
+
+    # ---- stepping ------------------------------------------------------------------
+    def step(self, n: int = 1, stream: Optional[torch.cuda.Stream] = None) -> None:
+        A.nsf_step(self.handle, n, _stream_handle(stream))
+
+    def decode(self, X: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """x = X + u(X, z_n) as a (3, n) float32 tensor; X is a (3, n) float32 device tensor."""
+        if X is None:
+            n = self.n_particles
+            out = torch.empty((3, n), dtype=torch.float32, device=self.device)
+            A.nsf_decode(self.handle, None, n, out.data_ptr(), _stream_handle(stream))
+        else:
+            X = X.contiguous()
+            assert X.dtype == torch.float32 and X.dim() == 2 and X.shape[0] == 3
+            n = int(X.shape[1])
+            out = torch.empty((3, n), dtype=torch.float32, device=self.device)
+            A.nsf_decode(self.handle, X.data_ptr(), n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    # ---- state ---------------------------------------------------------------------
+    def latent(self, stream=None):
+        z, zp, st = A.nsf_get_latent(self.handle, self.r, _stream_handle(stream))
+        return np.array(z), np.array(zp), st
+
+    def set_latent(self, z, z_prev=None, step: int = 0, stream=None) -> None:
+        A.nsf_set_latent(self.handle, list(z), None if z_prev is None else list(z_prev), step,
+                         _stream_handle(stream))
+
+    def flags(self, stream=None) -> Tuple[int, int]:
+        """(status, flag bits) of the sticky device flags."""
+        return A.nsf_status_flags(self.handle, _stream_handle(stream))
+
+    def buffer(self, which: int) -> torch.Tensor:
+        """A view of one of the sim's device buffers (see NSF_BUF_*)."""
+        ptr, count = A.nsf_sim_buffer(self.handle, which)
+        off = ptr - self.arena.data_ptr()
+        esize = 8 if which == A.NSF_BUF_Z else 4
+        dtype = torch.float64 if which == A.NSF_BUF_Z else torch.float32
+        return self.arena[off:off + count * esize].view(dtype)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            A.nsf_destroy_sim(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def step_batch(sims: List[Sim], n: int = 1, stream=None) -> None:
+    A.nsf_step_batch([s.handle for s in sims], n, _stream_handle(stream))

@@ -1,0 +1,116 @@
+"""C-ABI contract tests that run without a GPU: the library loads, exports every symbol
+include/nsf.h declares, validates descriptors and reports NSF_ENODEV when no device is
+visible. No compute call is made here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2310_17790_amd import _abi as A
+from paper_2310_17790_amd.sim import flatten_mlp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "nsf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nsf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = A.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(A.EXPORTED) == declared
+
+
+def _desc(w, keep):
+    d = A.nsf_sim_desc()
+    d.r, d.width, d.n_hidden, d.precision = w.r, w.width, 5, A.NSF_FP32
+    for f, name in enumerate(("g", "h", "l")):
+        a = flatten_mlp(w.fields[name])
+        keep.append(a)
+        d.weights[f] = a.ctypes.data_as(C.POINTER(C.c_float))
+    X = np.ascontiguousarray(w.X)
+    keep.append(X)
+    d.n_particles = X.shape[1]
+    d.X = X.ctypes.data_as(C.POINTER(C.c_float))
+    d.rho, d.body_volume = 1.0, 0.008
+    d.grid_n, d.dx, d.dt = w.grid_n, w.dx, w.dt
+    d.gravity[2] = -9.8
+    d.wall_nodes = 3
+    plan = np.ascontiguousarray(w.plan, np.int32)
+    keep.append(plan)
+    d.n_integration, d.n_sample, d.plan_steps = plan.shape[1], w.n_sample, plan.shape[0]
+    d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
+    d.gn_iters = 2
+    z = np.ascontiguousarray(w.z0)
+    keep.append(z)
+    d.z0 = z.ctypes.data_as(C.POINTER(C.c_double))
+    return d
+
+
+def test_sim_bytes_and_validation():
+    keep = []
+    w = synth.small_cube(r=6, width=64, n=256)
+    d = _desc(w, keep)
+    nbytes = A.nsf_sim_bytes(d)
+    # the dense grid alone is 32^3 float4
+    assert nbytes > 32 ** 3 * 16
+    assert nbytes % 256 == 0
+    bad = []
+    for field, val in [("r", 0), ("r", 33), ("width", 96), ("n_hidden", 4), ("gn_iters", 0),
+                       ("grid_n", 4), ("n_sample", 0), ("wall_nodes", 16)]:
+        old = getattr(d, field)
+        setattr(d, field, val)
+        if A.nsf_sim_bytes(d) != 0:
+            bad.append(field)
+        assert A.nsf_last_error() != ""
+        setattr(d, field, old)
+    assert bad == []
+    # well-posedness of the inversion: 3 |S| >= r
+    d.n_sample = 1
+    d.r = 6
+    assert A.nsf_sim_bytes(d) == 0
+    assert "under-determined" in A.nsf_last_error()
+    d.n_sample = 256
+    # out-of-range plan index
+    plan = np.array(w.plan, np.int32)
+    plan[0, 7] = 10 ** 6
+    keep.append(plan)
+    d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
+    assert A.nsf_sim_bytes(d) == 0
+    assert "out of range" in A.nsf_last_error()
+
+
+def test_sim_bytes_scales_with_grid_and_particles():
+    keep = []
+    a = A.nsf_sim_bytes(_desc(synth.small_cube(r=6, width=64, n=256), keep))
+    b = A.nsf_sim_bytes(_desc(synth.small_cube(r=6, width=64, n=512), keep))
+    assert b > a
+
+
+@pytest.mark.skipif(A.nsf_device_count() > 0, reason="a GPU is visible")
+def test_create_without_device_reports_enodev():
+    keep = []
+    d = _desc(synth.small_cube(r=6, width=64, n=256), keep)
+    h = C.c_void_p()
+    st = A.lib().nsf_create_sim(C.byref(d), C.c_void_p(256), A.nsf_sim_bytes(d), None, C.byref(h))
+    assert st == A.NSF_ENODEV
+    assert "device" in A.nsf_last_error()
+    assert h.value is None
+
+
+def test_null_arguments_are_rejected():
+    L = A.lib()
+    assert L.nsf_step(None, 1, None) == A.NSF_EINVAL
+    assert L.nsf_decode(None, None, 0, None, None) == A.NSF_EINVAL
+    assert L.nsf_destroy_sim(None) == A.NSF_OK
+    arr = (C.c_void_p * 1)(None)
+    assert L.nsf_step_batch(arr, 0, 1, None) == A.NSF_EINVAL
