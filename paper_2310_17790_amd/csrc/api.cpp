@@ -186,6 +186,7 @@ struct Plan {
   FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tD = nullptr;
   BlockWork *d_bP = nullptr, *d_bS = nullptr, *d_bGN = nullptr;
   int nA = 0, nG = 0, nD = 0, nP = 0, nS = 0, nGN = 0, nsims = 0;
+  FieldJob decode_job{};   // single-sim plans decode with the dense kernel (job by value)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~Plan() {
@@ -292,6 +293,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     dj.out = H.xdec; dj.ldo = s->n_part;
     add_tiles(tD, (int)jobs.size(), (int)s->n_part, 0, 0);
     jobs.push_back(dj);
+    P.decode_job = dj;
     for (int p0 = 0; p0 < N; p0 += kMpmBlock) bP.push_back({(int)si, p0});
     for (int p0 = 0; p0 < S; p0 += kMpmBlock) bS.push_back({(int)si, p0});
     for (int p0 = 0; p0 < S; p0 += kGnChunk) bGN.push_back({(int)si, p0});
@@ -343,9 +345,13 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
     NSF_HIP(launch_gn_reduce(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.nGN, s));
     NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, k, P.nsims, s));
   }
-  if (P.decode)
-    NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 2,
-                                ceil_div(P.nD, waves_per_block), s));
+  if (P.decode) {
+    if (P.nsims == 1)  // same kernel and launch shape as nsf_decode
+      NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.nD, s));
+    else
+      NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 2,
+                                  ceil_div(P.nD, waves_per_block), s));
+  }
   return NSF_OK;
 }
 
