@@ -57,7 +57,7 @@ struct Carver {
 struct Layout {
   size_t simdev;
   size_t w1p[3], whp[3], whb[3], bhp[3], w6p[3], b6[3];
-  size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, step, flags, gn_part;
+  size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, step, flags, gn_part, gn_count;
   size_t total;
 };
 
@@ -95,6 +95,7 @@ Layout make_layout(const nsf_sim_desc* d) {
   L.step = c.take(8);
   L.flags = c.take(4);
   L.gn_part = c.take((size_t)ceil_div(S, kGnChunk) * gn_entries(r) * 8);
+  L.gn_count = c.take(4);
   L.total = c.off;
   return L;
 }
@@ -221,13 +222,21 @@ FieldJob base_job(const nsf_sim* s, int field, const double* z) {
 }
 
 void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc) {
-  for (int p0 = 0; p0 < n; p0 += kTile) {
+  const int span = kTile * fields_group_waves(ntan > 0 ? tc : 0);
+  for (int p0 = 0; p0 < n; p0 += span) {
     if (ntan == 0) {
       out.push_back({job, p0, 0, 0});
     } else {
       for (int t0 = 0; t0 < ntan; t0 += tc) out.push_back({job, p0, t0, std::min(tc, ntan - t0)});
     }
   }
+}
+
+// Primal-only groups that run in the tangent kernel (same workgroup shape as its
+// Jacobian groups).
+void add_prim_tiles(std::vector<FieldTile>& out, int job, int n, int tc) {
+  const int span = kTile * fields_group_waves(tc);
+  for (int p0 = 0; p0 < n; p0 += span) out.push_back({job, p0, 0, 0});
 }
 
 template <class T>
@@ -267,20 +276,20 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     if (N > S) {
       FieldJob b = base_job(s, NSF_FIELD_G, zc);
       b.n = N - S; b.p_off = S; b.out = H.u_n + S; b.ldo = N;
-      add_tiles(tA_prim, (int)jobs.size(), N - S, 0, P.tc);
+      add_prim_tiles(tA_prim, (int)jobs.size(), N - S, P.tc);
       jobs.push_back(b);
     }
     FieldJob c = base_job(s, NSF_FIELD_G, zp);
     c.n = N; c.out = H.u_prev; c.ldo = N;
-    add_tiles(tA_prim, (int)jobs.size(), N, 0, P.tc);
+    add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
     jobs.push_back(c);
     FieldJob h = base_job(s, NSF_FIELD_H, zc);
     h.n = N; h.out = H.tau; h.ldo = N;
-    add_tiles(tA_prim, (int)jobs.size(), N, 0, P.tc);
+    add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
     jobs.push_back(h);
     FieldJob l = base_job(s, NSF_FIELD_L, zc);
     l.n = N; l.out = H.C; l.ldo = N;
-    add_tiles(tA_prim, (int)jobs.size(), N, 0, P.tc);
+    add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
     jobs.push_back(l);
     // Gauss-Newton iterate: g and its Jacobian on S
     FieldJob g = base_job(s, NSF_FIELD_G, zi);
@@ -331,26 +340,20 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
 }
 
 nsf_status enqueue_step(Plan& P, hipStream_t s) {
-  const int waves_per_block = 4;
-  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
-                              ceil_div(P.nA, waves_per_block), s));
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0, P.nA, s));
   NSF_HIP(launch_p2g(P.d_sims, P.d_bP, P.d_counts + 3, P.nP, s));
   NSF_HIP(launch_g2p(P.d_sims, P.d_bS, P.d_counts + 4, P.nS, s));
   NSF_HIP(launch_grid_clean(P.d_sims, P.d_bP, P.d_counts + 3, P.nP, s));
-  NSF_HIP(launch_gn_reduce(P.d_sims, P.d_bGN, P.d_counts + 5, 0, P.nGN, s));
-  NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.nsims, s));
+  NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, 0, P.nGN, s));
   for (int k = 1; k < P.gn_iters; ++k) {
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1,
-                                ceil_div(P.nG, waves_per_block), s));
-    NSF_HIP(launch_gn_reduce(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.nGN, s));
-    NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, k, P.nsims, s));
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1, P.nG, s));
+    NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.nGN, s));
   }
   if (P.decode) {
     if (P.nsims == 1)  // same kernel and launch shape as nsf_decode
-      NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.nD, s));
+      NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, s));
     else
-      NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 2,
-                                  ceil_div(P.nD, waves_per_block), s));
+      NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 2, P.nD, s));
   }
   return NSF_OK;
 }
@@ -477,6 +480,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   NSF_HIP(hipMemsetAsync(A + L.grid, 0, n3 * 16, s));
   NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
   NSF_HIP(hipMemsetAsync(A + L.flags, 0, 4, s));
+  NSF_HIP(hipMemsetAsync(A + L.gn_count, 0, 4, s));
   NSF_HIP(hipMemsetAsync(A + L.xdec, 0, (size_t)3 * P * 4, s));
 
   SimDev& H = sim->hd;
@@ -525,6 +529,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.step = reinterpret_cast<int64_t*>(A + L.step);
   H.flags = reinterpret_cast<uint32_t*>(A + L.flags);
   H.gn_part = reinterpret_cast<double*>(A + L.gn_part);
+  H.gn_count = reinterpret_cast<uint32_t*>(A + L.gn_count);
   sim->dd = reinterpret_cast<SimDev*>(A + L.simdev);
   NSF_HIP(hipMemcpyAsync(sim->dd, &H, sizeof(SimDev), hipMemcpyHostToDevice, s));
   NSF_HIP(hipStreamSynchronize(s));
@@ -596,7 +601,7 @@ nsf_status nsf_decode(nsf_sim* s, const float* X, int64_t n, float* x_out, void*
   j.mode = 1;
   j.out = x_out;
   j.ldo = n;
-  NSF_HIP(launch_fields_dense(s->width, s->bf16, j, ceil_div(n, kTile), static_cast<hipStream_t>(stream)));
+  NSF_HIP(launch_fields_dense(s->width, s->bf16, j, (int)n, static_cast<hipStream_t>(stream)));
   return NSF_OK;
 }
 

@@ -107,11 +107,10 @@ __device__ __forceinline__ void init_hidden(f32x16 (&acc)[T][W / 32], const floa
   }
 }
 
-template <int W, int T>
+template <int W, int T, class APtr>
 __device__ __forceinline__ void hidden_f32(f32x16 (&acc)[T][W / 32], const float (&H)[T][W / 2],
-                                           const float* whp_layer, int lane, int nt) {
+                                           APtr A, int lane, int nt) {
   constexpr int MB = W / 32;
-  const f32x4* A = reinterpret_cast<const f32x4*>(whp_layer);
 #pragma unroll
   for (int sg = 0; sg < W / 8; ++sg) {
     f32x4 a4[MB];
@@ -129,10 +128,10 @@ __device__ __forceinline__ void hidden_f32(f32x16 (&acc)[T][W / 32], const float
   }
 }
 
-template <int W, int T>
+template <int W, int T, class APtr>
 __device__ __forceinline__ void hidden_bf16(f32x16 (&acc)[T][W / 32],
                                             const bf16x8 (&Hb)[T][W / 16],
-                                            const bf16x8* whb_layer, int lane, int nt) {
+                                            APtr whb_layer, int lane, int nt) {
   constexpr int MB = W / 32;
 #pragma unroll
   for (int s = 0; s < W / 16; ++s) {
@@ -165,13 +164,50 @@ __device__ __forceinline__ float output_dot(const float* w6p, int o, int h, cons
   return s + __shfl_xor(s, 32);
 }
 
-template <int W, int TC, bool BF>
-__device__ __forceinline__ void run_tile(const FieldJob& jb, int p0, int t0, int nt, int lane) {
+// Bytes of one packed hidden layer and of one LDS DMA instruction per wave (64 lanes x 16 B).
+template <int W, bool BF>
+struct HiddenLayer {
+  static constexpr int kBytes = BF ? W * W * 2 : W * W * 4;
+  static constexpr int kChunks = kBytes / 1024;
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Copy hidden layer k of `w` into LDS buffer dst with direct global->LDS loads; every
+// wave of the workgroup moves its share of the 1 KB chunks.
+template <int W, bool BF, int WPG>
+__device__ __forceinline__ void dma_layer(const FieldPack& w, int k, char* dst, int wave, int lane) {
+  constexpr int kPer = HiddenLayer<W, BF>::kChunks / WPG;
+  static_assert(HiddenLayer<W, BF>::kChunks % WPG == 0, "layer must split evenly over waves");
+  const char* src = (BF ? reinterpret_cast<const char*>(w.whb) : reinterpret_cast<const char*>(w.whp)) +
+                    (size_t)k * HiddenLayer<W, BF>::kBytes;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int chunk = wave * kPer + i;
+    __builtin_amdgcn_global_load_lds(src + chunk * 1024 + lane * 16,
+                                      (lds_void*)(dst + chunk * 1024), 16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void wait_dma_and_sync() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+// One workgroup evaluates WPG tiles of 32 points of the same job (wave w takes points
+// p0 + 32 w): the primal plus tangents [t0, t0 + nt). Hidden-layer weights stream
+// through two LDS buffers: layer k + 1 (or the next group's layer 2) is fetched while
+// layer k computes. Returns after the output layer.
+template <int W, int NT, bool BF, int WPG>
+__device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0,
+                                          const FieldPack* next_w, char* lds, int wave, int lane) {
   constexpr int MB = W / 32;
-  constexpr int T = 1 + TC;
+  constexpr int T = 1 + NT;
+  constexpr int nt = NT;  // compile-time: no per-MFMA guards
   constexpr int KH = W / 2;
+  constexpr int LB = HiddenLayer<W, BF>::kBytes;
   const int h = lane >> 5;
-  const int p = p0 + (lane & 31);
+  const int p = p0g + 32 * wave + (lane & 31);
   const bool valid = p < jb.n;
   int gi = jb.p_off + (valid ? p : jb.n - 1);
   if (jb.idx != nullptr) {
@@ -213,23 +249,31 @@ __device__ __forceinline__ void run_tile(const FieldJob& jb, int p0, int t0, int
   float H[T][KH];
   if constexpr (!BF) {
     activate_f32<W, T>(acc, H, nt);
-    for (int k = 0; k < 4; ++k) {
-      init_hidden<W, T>(acc, jb.w.bhp + k * W, h);
-      hidden_f32<W, T>(acc, H, jb.w.whp + (size_t)k * W * W, lane, nt);
+  }
+  bf16x8 Hb[T][BF ? W / 16 : 1];
+  if constexpr (BF) activate_bf16<W, T>(acc, Hb, nt);
+  // Hidden layers 2..5 (k = 0..3): wait for layer k in LDS, start fetching layer k + 1
+  // (after the last layer: the next group's first layer), multiply, activate.
+#pragma unroll 1
+  for (int k = 0; k < 3; ++k) {
+    wait_dma_and_sync();
+    char* cur = lds + (k & 1) * LB;
+    dma_layer<W, BF, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
+    init_hidden<W, T>(acc, jb.w.bhp + k * W, h);
+    if constexpr (!BF) {
+      hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(cur), lane, nt);
       activate_f32<W, T>(acc, H, nt);
-    }
-  } else {
-    bf16x8 Hb[T][W / 16];
-    activate_bf16<W, T>(acc, Hb, nt);
-    for (int k = 0; k < 3; ++k) {
-      init_hidden<W, T>(acc, jb.w.bhp + k * W, h);
-      hidden_bf16<W, T>(acc, Hb, jb.w.whb + (size_t)k * MB * (W / 16) * 64, lane, nt);
+    } else {
+      hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(cur), lane, nt);
       activate_bf16<W, T>(acc, Hb, nt);
     }
-    init_hidden<W, T>(acc, jb.w.bhp + 3 * W, h);
-    hidden_bf16<W, T>(acc, Hb, jb.w.whb + (size_t)3 * MB * (W / 16) * 64, lane, nt);
-    activate_f32<W, T>(acc, H, nt);
   }
+  wait_dma_and_sync();
+  if (next_w) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
+  init_hidden<W, T>(acc, jb.w.bhp + 3 * W, h);
+  if constexpr (!BF) hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(lds + LB), lane, nt);
+  else hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(lds + LB), lane, nt);
+  activate_f32<W, T>(acc, H, nt);
 
   // Output layer, primal.
   const int d = jb.d;
@@ -258,30 +302,90 @@ __device__ __forceinline__ void run_tile(const FieldJob& jb, int p0, int t0, int
   }
 }
 
-template <int W, int TC, bool BF>
-__global__ __launch_bounds__(256) void fields_table_kernel(const FieldJob* __restrict__ jobs,
-                                                           const FieldTile* __restrict__ tiles,
-                                                           const int32_t* __restrict__ n_tiles) {
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  const int nw = (gridDim.x * blockDim.x) >> 6;
-  const int total = *n_tiles;
-  for (int t = wave; t < total; t += nw) {
-    const FieldTile tl = tiles[t];
-    run_tile<W, TC, BF>(jobs[tl.job], tl.p0, tl.t0, tl.nt, lane);
+// Run a group with its tangent count as a template argument (0 .. TC).
+template <int W, int TC, bool BF, int WPG>
+__device__ __forceinline__ void dispatch_nt(const FieldJob& jb, int p0, int t0, int nt,
+                                            const FieldPack* next_w, char* lds, int wave, int lane) {
+  if constexpr (TC > 0) {
+    if (nt == TC) { run_group<W, TC, BF, WPG>(jb, p0, t0, next_w, lds, wave, lane); return; }
+    dispatch_nt<W, TC - 1, BF, WPG>(jb, p0, t0, nt, next_w, lds, wave, lane);
+  } else {
+    run_group<W, 0, BF, WPG>(jb, p0, t0, next_w, lds, wave, lane);
   }
 }
 
-template <int W, bool BF>
-__global__ __launch_bounds__(256) void fields_dense_kernel(FieldJob job, int n_tiles) {
+// Work groups from a table (several jobs; a group is WPG tiles of one job).
+template <int W, int TC, bool BF, int WPG>
+__global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* __restrict__ jobs,
+                                                                const FieldTile* __restrict__ groups,
+                                                                const int32_t* __restrict__ n_groups) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  const int nw = (gridDim.x * blockDim.x) >> 6;
-  for (int t = wave; t < n_tiles; t += nw) run_tile<W, 0, BF>(job, t * kTile, 0, 0, lane);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int total = *n_groups;
+  int g = blockIdx.x;
+  if (g >= total) return;
+  dma_layer<W, BF, WPG>(jobs[groups[g].job].w, 0, lds, wave, lane);
+  for (; g < total; g += gridDim.x) {
+    const FieldTile tl = groups[g];
+    const int gn = g + gridDim.x;
+    const FieldPack* next_w = gn < total ? &jobs[groups[gn].job].w : nullptr;
+    dispatch_nt<W, TC, BF, WPG>(jobs[tl.job], tl.p0, tl.t0, tl.nt, next_w, lds, wave, lane);
+  }
+}
+
+// One job over n points (decode): group g covers points [32 WPG g, 32 WPG (g + 1)).
+template <int W, bool BF, int WPG>
+__global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, int n_groups) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int g = blockIdx.x;
+  if (g >= n_groups) return;
+  dma_layer<W, BF, WPG>(job.w, 0, lds, wave, lane);
+  for (; g < n_groups; g += gridDim.x) {
+    const FieldPack* next_w = g + (int)gridDim.x < n_groups ? &job.w : nullptr;
+    run_group<W, 0, BF, WPG>(job, g * kTile * WPG, 0, next_w, lds, wave, lane);
+  }
 }
 
 // Tangents one wave carries next to the primal, by register budget (512 per lane).
 constexpr int kTcF32W64 = 3, kTcF32W128 = 2, kTcBf16W64 = 4, kTcBf16W128 = 2;
+
+// Waves per workgroup: kernels with tangents hold ~500 registers (one wave per SIMD),
+// primal-only kernels fit two waves per SIMD.
+template <int TC> struct Wpg { static constexpr int value = TC > 0 ? 4 : 8; };
+
+template <int W, int TC, bool BF>
+hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int32_t* n_groups,
+                        int grid, hipStream_t s) {
+  constexpr int WPG = Wpg<TC>::value;
+  constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes;
+  auto k = fields_table_kernel<W, TC, BF, WPG>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, jobs, groups, n_groups);
+  return hipGetLastError();
+}
+
+template <int W, bool BF>
+hipError_t launch_dense(const FieldJob& job, int n_groups, hipStream_t s) {
+  constexpr int WPG = Wpg<0>::value;
+  constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes;
+  auto k = fields_dense_kernel<W, BF, WPG>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k, dim3(n_groups), dim3(64 * WPG), lds, s, job, n_groups);
+  return hipGetLastError();
+}
 
 }  // namespace
 
@@ -290,42 +394,35 @@ int fields_max_tangents(int width, bool bf16) {
   return bf16 ? kTcBf16W128 : kTcF32W128;
 }
 
+int fields_group_waves(int tc) { return tc > 0 ? Wpg<1>::value : Wpg<0>::value; }
+
 hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
-                               const FieldTile* tiles, const int32_t* n_tiles, int grid,
+                               const FieldTile* groups, const int32_t* n_groups, int grid,
                                hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  dim3 g(grid), b(256);
   const bool full = tc > 0;
-#define NSF_LAUNCH(WW, TT, BB) \
-  hipLaunchKernelGGL((fields_table_kernel<WW, TT, BB>), g, b, 0, s, jobs, tiles, n_tiles)
   if (width == 64) {
-    if (!bf16) { if (full) NSF_LAUNCH(64, kTcF32W64, false); else NSF_LAUNCH(64, 0, false); }
-    else { if (full) NSF_LAUNCH(64, kTcBf16W64, true); else NSF_LAUNCH(64, 0, true); }
-  } else if (width == 128) {
-    if (!bf16) { if (full) NSF_LAUNCH(128, kTcF32W128, false); else NSF_LAUNCH(128, 0, false); }
-    else { if (full) NSF_LAUNCH(128, kTcBf16W128, true); else NSF_LAUNCH(128, 0, true); }
-  } else {
-    return hipErrorInvalidValue;
+    if (!bf16) return full ? launch_table<64, kTcF32W64, false>(jobs, groups, n_groups, grid, s)
+                           : launch_table<64, 0, false>(jobs, groups, n_groups, grid, s);
+    return full ? launch_table<64, kTcBf16W64, true>(jobs, groups, n_groups, grid, s)
+                : launch_table<64, 0, true>(jobs, groups, n_groups, grid, s);
   }
-#undef NSF_LAUNCH
-  return hipGetLastError();
+  if (width == 128) {
+    if (!bf16) return full ? launch_table<128, kTcF32W128, false>(jobs, groups, n_groups, grid, s)
+                           : launch_table<128, 0, false>(jobs, groups, n_groups, grid, s);
+    return full ? launch_table<128, kTcBf16W128, true>(jobs, groups, n_groups, grid, s)
+                : launch_table<128, 0, true>(jobs, groups, n_groups, grid, s);
+  }
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_tiles,
+hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
                                hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
-  const int grid = (n_tiles + 3) / 4;
-  dim3 g(grid), b(256);
-  if (width == 64) {
-    if (bf16) hipLaunchKernelGGL((fields_dense_kernel<64, true>), g, b, 0, s, job, n_tiles);
-    else hipLaunchKernelGGL((fields_dense_kernel<64, false>), g, b, 0, s, job, n_tiles);
-  } else if (width == 128) {
-    if (bf16) hipLaunchKernelGGL((fields_dense_kernel<128, true>), g, b, 0, s, job, n_tiles);
-    else hipLaunchKernelGGL((fields_dense_kernel<128, false>), g, b, 0, s, job, n_tiles);
-  } else {
-    return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  const int groups = (n_points + kTile * Wpg<0>::value - 1) / (kTile * Wpg<0>::value);
+  if (groups <= 0) return hipSuccess;
+  if (width == 64) return bf16 ? launch_dense<64, true>(job, groups, s) : launch_dense<64, false>(job, groups, s);
+  if (width == 128) return bf16 ? launch_dense<128, true>(job, groups, s) : launch_dense<128, false>(job, groups, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace nsf

@@ -5,19 +5,24 @@
 // k = 0 the first two terms are the same value, so r = -dt v) and Jacobian J (3|S| x r)
 // from the field kernel. The step solves (J^T J) delta = -J^T r by Cholesky and sets
 // z^(k+1) = z^(k) + delta. Everything from the residual on is FP64: J and u enter as the
-// FP32 values the field kernel stored, widened.
+// FP32 values the field kernel stored, widened (a product of two FP32 values is exact in
+// FP64).
 //
-// gn_reduce: one block per 128 sample points stages J and r in LDS and writes its
-//   partial H (upper triangle, r(r+1)/2 entries) and b (r entries) in FP64.
-// gn_solve: one 64-thread block per simulation sums the partials in a fixed order
-//   (deterministic), factors H with a column-parallel Cholesky in LDS, solves, and
-//   updates the latent; the last iteration also shifts z_{n-1} <- z_n <- z_{n+1} and
-//   advances the step counter. A pivot <= 0 raises the SINGULAR flag and a non-finite
-//   system or latent the NONFINITE flag; the latent is then left unchanged.
+// One launch per iteration. Each block stages 128 sample points of J and r in LDS and
+// reduces its partial H (upper triangle, r(r+1)/2 entries) and b (r entries) with all
+// threads: thread (e, g) sums entry e over the columns g, g + G, ... and the G column
+// groups are then added in a fixed order. The block stores its partial, and the last
+// block of the simulation to finish (release fence + counter) adds the partials in chunk
+// order (deterministic), factors H with a column-parallel Cholesky in LDS, solves, and
+// updates the latent; the last iteration also shifts z_{n-1} <- z_n <- z_{n+1} and
+// advances the step counter. A pivot <= 0 raises the SINGULAR flag and a non-finite
+// system or latent the NONFINITE flag; the latent is then left unchanged.
 #include "nsf_dev.h"
 
 namespace nsf {
 namespace {
+
+constexpr int kThreads = 256;
 
 // Entry e of the packed system: e < r(r+1)/2 -> H[j][k], j <= k (row-major upper
 // triangle); else b[e - r(r+1)/2].
@@ -31,12 +36,72 @@ __device__ __forceinline__ void decode_entry(int e, int r, int& j, int& k, bool&
   k = row + (e - start);
 }
 
-__global__ __launch_bounds__(256) void gn_reduce_kernel(const SimDev* __restrict__ sims,
-                                                        const BlockWork* __restrict__ work,
-                                                        const int32_t* __restrict__ n_work,
-                                                        int iter) {
+// Factor and solve in the last block of a simulation. H and y live in LDS.
+__device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 1], double* y,
+                                 int* bad) {
+  const int r = S.r, tid = threadIdx.x;
+  for (int j = 0; j < r && *bad == 0; ++j) {
+    if (tid == 0) {
+      const double dj = H[j][j];
+      if (!(dj > 0.0)) *bad = 1;
+      else H[j][j] = sqrt(dj);
+    }
+    __syncthreads();
+    if (*bad) break;
+    const double ljj = H[j][j];
+    for (int i = j + 1 + tid; i < r; i += blockDim.x) H[i][j] /= ljj;
+    __syncthreads();
+    const int m = r - j - 1;
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) H[i][k] -= H[i][j] * H[k][j];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (*bad == 0) {
+    for (int j = 0; j < r; ++j) {            // L w = -b
+      if (tid == 0) y[j] /= H[j][j];
+      __syncthreads();
+      for (int i = j + 1 + tid; i < r; i += blockDim.x) y[i] -= H[i][j] * y[j];
+      __syncthreads();
+    }
+    for (int j = r - 1; j >= 0; --j) {       // L^T delta = w
+      if (tid == 0) y[j] /= H[j][j];
+      __syncthreads();
+      for (int i = tid; i < j; i += blockDim.x) y[i] -= H[j][i] * y[j];
+      __syncthreads();
+    }
+  }
+  const bool final_iter = (iter == S.gn_iters - 1);
+  double* zp = S.z;
+  double* zc = S.z + r;
+  double* zi = S.z + 2 * r;
+  if (tid == 0 && *bad) atomicOr(S.flags, (*bad & 2) ? FLAG_NONFINITE : FLAG_SINGULAR);
+  for (int j = tid; j < r; j += blockDim.x) {
+    const double base = (iter == 0) ? zc[j] : zi[j];
+    const double zn = *bad ? base : base + y[j];
+    if (!isfinite(zn)) atomicOr(S.flags, FLAG_NONFINITE);
+    if (final_iter) {
+      zp[j] = zc[j];
+      zc[j] = zn;
+    } else {
+      zi[j] = zn;
+    }
+  }
+  if (final_iter && tid == 0) *S.step += 1;
+}
+
+__global__ __launch_bounds__(kThreads) void gn_kernel(const SimDev* __restrict__ sims,
+                                                      const BlockWork* __restrict__ work,
+                                                      const int32_t* __restrict__ n_work, int iter) {
   __shared__ float Jl[3 * kMaxR][kGnChunk + 1];
   __shared__ double R[3][kGnChunk];
+  __shared__ double part[kThreads];
+  __shared__ double H[kMaxR][kMaxR + 1];
+  __shared__ double y[kMaxR];
+  __shared__ int last, bad;
+  const int tid = threadIdx.x;
   const int total = *n_work;
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
     const BlockWork wk = work[b];
@@ -45,11 +110,11 @@ __global__ __launch_bounds__(256) void gn_reduce_kernel(const SimDev* __restrict
     const int r = S.r, ns = S.n_samp, p0 = wk.p0;
     const int cnt = min(kGnChunk, ns - p0);
     const float* J = iter == 0 ? S.J : S.J2;
-    for (int e = threadIdx.x; e < 3 * r * kGnChunk; e += blockDim.x) {
+    for (int e = tid; e < 3 * r * kGnChunk; e += kThreads) {
       const int row = e / kGnChunk, col = e % kGnChunk;
       Jl[row][col] = col < cnt ? J[(int64_t)row * ns + p0 + col] : 0.f;
     }
-    for (int e = threadIdx.x; e < 3 * kGnChunk; e += blockDim.x) {
+    for (int e = tid; e < 3 * kGnChunk; e += kThreads) {
       const int c = e / kGnChunk, col = e % kGnChunk;
       double rv = 0.0;
       if (col < cnt) {
@@ -61,125 +126,95 @@ __global__ __launch_bounds__(256) void gn_reduce_kernel(const SimDev* __restrict
     }
     __syncthreads();
     const int E = r * (r + 1) / 2 + r;
-    for (int e = threadIdx.x; e < E; e += blockDim.x) {
-      int j, k;
-      bool is_b;
-      decode_entry(e, r, j, k, is_b);
+    const int G = E >= kThreads ? 1 : kThreads / E;   // column groups per entry
+    double* out = S.gn_part + (int64_t)(p0 / kGnChunk) * E;
+    for (int e0 = 0; e0 < E; e0 += kThreads / G) {
+      const int e = e0 + tid % (kThreads / G);
+      const int g = tid / (kThreads / G);
       double acc = 0.0;
-      for (int c = 0; c < 3; ++c) {
-        const float* a = Jl[c * r + j];
-        if (is_b) {
-          for (int col = 0; col < cnt; ++col) acc += (double)a[col] * R[c][col];
-        } else {
-          const float* bb = Jl[c * r + k];
-          for (int col = 0; col < cnt; ++col) acc += (double)a[col] * (double)bb[col];
+      if (e < E && g < G) {
+        int j, k;
+        bool is_b;
+        decode_entry(e, r, j, k, is_b);
+        for (int c = 0; c < 3; ++c) {
+          const float* a = Jl[c * r + j];
+          if (is_b) {
+            for (int col = g; col < kGnChunk; col += G) acc += (double)a[col] * R[c][col];
+          } else {
+            const float* bb = Jl[c * r + k];
+            for (int col = g; col < kGnChunk; col += G) acc += (double)a[col] * (double)bb[col];
+          }
         }
       }
-      S.gn_part[(int64_t)(p0 / kGnChunk) * E + e] = acc;
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(64) void gn_solve_kernel(const SimDev* __restrict__ sims,
-                                                      const int32_t* __restrict__ n_sims,
-                                                      int iter) {
-  __shared__ double H[kMaxR][kMaxR + 1];
-  __shared__ double y[kMaxR];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  const int total = *n_sims;
-  for (int s = blockIdx.x; s < total; s += gridDim.x) {
-    const SimDev& S = sims[s];
-    if (iter >= S.gn_iters) continue;
-    const int r = S.r;
-    const int E = r * (r + 1) / 2 + r;
-    if (tid == 0) bad = 0;
-    __syncthreads();
-    for (int e = tid; e < E; e += blockDim.x) {
-      double acc = 0.0;
-      for (int c = 0; c < S.n_gn_chunks; ++c) acc += S.gn_part[(int64_t)c * E + e];
-      int j, k;
-      bool is_b;
-      decode_entry(e, r, j, k, is_b);
-      if (!isfinite(acc)) atomicOr(&bad, 2);
-      if (is_b) {
-        y[j] = -acc;  // right-hand side -J^T r
-      } else {
-        H[j][k] = acc;
-        H[k][j] = acc;
-      }
-    }
-    __syncthreads();
-    // Cholesky H = L L^T, right-looking, L overwrites the lower triangle.
-    for (int j = 0; j < r && bad == 0; ++j) {
-      if (tid == 0) {
-        const double dj = H[j][j];
-        if (!(dj > 0.0)) bad = 1;
-        else H[j][j] = sqrt(dj);
-      }
+      part[tid] = acc;
       __syncthreads();
-      if (bad) break;
-      const double ljj = H[j][j];
-      for (int i = j + 1 + tid; i < r; i += blockDim.x) H[i][j] /= ljj;
-      __syncthreads();
-      const int m = r - j - 1;
-      for (int e = tid; e < m * m; e += blockDim.x) {
-        const int i = j + 1 + e / m, k = j + 1 + e % m;
-        if (k <= i) H[i][k] -= H[i][j] * H[k][j];
+      if (tid < kThreads / G && e0 + tid < E) {
+        double s = 0.0;
+        for (int gg = 0; gg < G; ++gg) s += part[gg * (kThreads / G) + tid];
+        out[e0 + tid] = s;
       }
       __syncthreads();
     }
+    // The last block of this simulation to arrive solves the system.
+    __threadfence();
+    if (tid == 0) {
+      const uint32_t prev = __hip_atomic_fetch_add(S.gn_count, 1u, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+      last = (prev == (uint32_t)S.n_gn_chunks - 1) ? 1 : 0;
+      bad = 0;
+    }
     __syncthreads();
-    if (bad == 0) {
-      // forward substitution L w = -b, then back substitution L^T delta = w (in y)
-      for (int j = 0; j < r; ++j) {
-        if (tid == 0) y[j] /= H[j][j];
+    if (last) {
+      __threadfence();
+      // Sum the chunk partials: thread (e, g) adds chunks g, g + G, ... with independent
+      // loads, then the G groups are added in a fixed order.
+      const int nch = S.n_gn_chunks;
+      for (int e0 = 0; e0 < E; e0 += kThreads / G) {
+        const int e = e0 + tid % (kThreads / G);
+        const int g = tid / (kThreads / G);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (e < E && g < G) {
+          const double* src = S.gn_part + e;
+          int c = g;
+          for (; c + 3 * G < nch; c += 4 * G) {
+            a0 += src[(int64_t)c * E];
+            a1 += src[(int64_t)(c + G) * E];
+            a2 += src[(int64_t)(c + 2 * G) * E];
+            a3 += src[(int64_t)(c + 3 * G) * E];
+          }
+          for (; c < nch; c += G) a0 += src[(int64_t)c * E];
+        }
+        part[tid] = (a0 + a1) + (a2 + a3);
         __syncthreads();
-        for (int i = j + 1 + tid; i < r; i += blockDim.x) y[i] -= H[i][j] * y[j];
+        if (tid < kThreads / G && e0 + tid < E) {
+          double acc = 0.0;
+          for (int gg = 0; gg < G; ++gg) acc += part[gg * (kThreads / G) + tid];
+          int j, k;
+          bool is_b;
+          decode_entry(e0 + tid, r, j, k, is_b);
+          if (!isfinite(acc)) atomicOr(&bad, 2);
+          if (is_b) {
+            y[j] = -acc;  // right-hand side -J^T r
+          } else {
+            H[j][k] = acc;
+            H[k][j] = acc;
+          }
+        }
         __syncthreads();
       }
-      for (int j = r - 1; j >= 0; --j) {
-        if (tid == 0) y[j] /= H[j][j];
-        __syncthreads();
-        for (int i = tid; i < j; i += blockDim.x) y[i] -= H[j][i] * y[j];
-        __syncthreads();
-      }
+      solve_and_update(S, iter, H, y, &bad);
+      if (tid == 0) __hip_atomic_store(S.gn_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const bool final_iter = (iter == S.gn_iters - 1);
-    double* zp = S.z;
-    double* zc = S.z + r;
-    double* zi = S.z + 2 * r;
-    if (tid == 0 && bad) atomicOr(S.flags, (bad & 2) ? FLAG_NONFINITE : FLAG_SINGULAR);
-    for (int j = tid; j < r; j += blockDim.x) {
-      const double base = (iter == 0) ? zc[j] : zi[j];
-      double zn = bad ? base : base + y[j];
-      if (!isfinite(zn)) atomicOr(S.flags, FLAG_NONFINITE);
-      if (final_iter) {
-        zp[j] = zc[j];
-        zc[j] = zn;
-      } else {
-        zi[j] = zn;
-      }
-    }
-    if (final_iter && tid == 0) *S.step += 1;
     __syncthreads();
   }
 }
 
 }  // namespace
 
-hipError_t launch_gn_reduce(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                            int iter, int grid, hipStream_t s) {
+hipError_t launch_gn(const SimDev* sims, const BlockWork* work, const int32_t* n_work, int iter,
+                     int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gn_reduce_kernel, dim3(grid), dim3(256), 0, s, sims, work, n_work, iter);
-  return hipGetLastError();
-}
-
-hipError_t launch_gn_solve(const SimDev* sims, const int32_t* n_sims, int iter, int grid,
-                           hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gn_solve_kernel, dim3(grid), dim3(64), 0, s, sims, n_sims, iter);
+  hipLaunchKernelGGL(gn_kernel, dim3(grid), dim3(kThreads), 0, s, sims, work, n_work, iter);
   return hipGetLastError();
 }
 

@@ -52,8 +52,9 @@ struct FieldJob {
   float scale[9], shift[9];
 };
 
-// One wave's work: 32 points of a job, the primal plus tangents [t0, t0 + nt).
-// Only the tile with t0 == 0 writes the primal output.
+// One workgroup's work: WPG consecutive 32-point tiles of a job starting at point p0
+// (wave w takes p0 + 32 w), the primal plus tangents [t0, t0 + nt). Only groups with
+// t0 == 0 write the primal output.
 struct FieldTile {
   int32_t job, p0, t0, nt;
 };
@@ -86,6 +87,7 @@ struct SimDev {
   int64_t* step;
   uint32_t* flags;
   double* gn_part;                   // [n_gn_chunks][E], E = r(r+1)/2 + r
+  uint32_t* gn_count;                // chunks of the current iteration done (zero between launches)
 };
 
 enum : uint32_t { FLAG_DOMAIN = 1u, FLAG_NONFINITE = 2u, FLAG_SINGULAR = 4u };
@@ -99,9 +101,10 @@ struct BlockWork {
 hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
                                const FieldTile* tiles, const int32_t* n_tiles, int grid,
                                hipStream_t s);
-hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_tiles,
+hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
                                hipStream_t s);
 int fields_max_tangents(int width, bool bf16);
+int fields_group_waves(int tc);   // waves (32-point tiles) per workgroup
 
 hipError_t launch_p2g(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
                       int grid, hipStream_t s);
@@ -109,9 +112,7 @@ hipError_t launch_g2p(const SimDev* sims, const BlockWork* work, const int32_t* 
                       int grid, hipStream_t s);
 hipError_t launch_grid_clean(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
                              int grid, hipStream_t s);
-hipError_t launch_gn_reduce(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                            int iter, int grid, hipStream_t s);
-hipError_t launch_gn_solve(const SimDev* sims, const int32_t* n_sims, int iter, int grid,
-                           hipStream_t s);
+hipError_t launch_gn(const SimDev* sims, const BlockWork* work, const int32_t* n_work, int iter,
+                     int grid, hipStream_t s);
 
 }  // namespace nsf
