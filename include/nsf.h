@@ -131,6 +131,12 @@ nsf_status nsf_step(nsf_sim *s, int32_t n_steps, void *stream);
  * while the same set is passed. */
 nsf_status nsf_step_batch(nsf_sim *const *sims, int32_t n, int32_t n_steps, void *stream);
 
+/* Evaluate the fields at the current latent in one launch, async: decode all particles
+ * into the decoded-position buffer (when decode_every_step) and the field inference the
+ * next step starts from (Sec. 5.1). nsf_step ends every step with this launch; call it
+ * directly to refresh the decoded positions after nsf_set_latent, or to time it. */
+nsf_status nsf_refresh(nsf_sim *s, void *stream);
+
 /* Decode x = X + u(X, z_n) (Sec. 5.1), async. X: device [3][n] or NULL for the sim's own
  * reference positions (then n must equal n_particles). x_out: device [3][n]. */
 nsf_status nsf_decode(nsf_sim *s, const float *X, int64_t n, float *x_out, void *stream);

@@ -23,7 +23,7 @@ NSF_FIELD_G, NSF_FIELD_H, NSF_FIELD_L = 0, 1, 2
 STATUS_NAMES = {0: "NSF_OK", -1: "NSF_EINVAL", -2: "NSF_ENOMEM", -3: "NSF_EHIP", -4: "NSF_ENODEV",
                 -5: "NSF_EDOMAIN", -6: "NSF_ESINGULAR", -7: "NSF_ENONFINITE"}
 
-EXPORTED = ["nsf_sim_bytes", "nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_decode",
+EXPORTED = ["nsf_sim_bytes", "nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_refresh", "nsf_decode",
             "nsf_get_latent", "nsf_set_latent", "nsf_status_flags", "nsf_sim_buffer",
             "nsf_destroy_sim", "nsf_last_error", "nsf_device_count", "nsf_mlp_param_count",
             "nsf_mlp_saved_floats", "nsf_mlp_workspace_bytes", "nsf_mlp_forward",
@@ -77,6 +77,7 @@ def lib() -> C.CDLL:
         L.nsf_create_sim.argtypes = [C.POINTER(nsf_sim_desc), vp, sz, vp, C.POINTER(vp)]
         L.nsf_step.argtypes = [vp, i32, vp]
         L.nsf_step_batch.argtypes = [C.POINTER(vp), i32, i32, vp]
+        L.nsf_refresh.argtypes = [vp, vp]
         L.nsf_decode.argtypes = [vp, vp, i64, vp, vp]
         L.nsf_get_latent.argtypes = [vp, vp, vp, vp, vp]
         L.nsf_set_latent.argtypes = [vp, vp, vp, i64, vp]
@@ -95,7 +96,7 @@ def lib() -> C.CDLL:
         L.nsf_mlp_workspace_bytes.restype = sz
         L.nsf_mlp_forward.argtypes = [C.POINTER(nsf_mlp), vp, vp, i64, vp, vp, vp, sz, vp]
         L.nsf_mlp_backward.argtypes = [C.POINTER(nsf_mlp), vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
-        for name in ("nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_decode", "nsf_get_latent",
+        for name in ("nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_refresh", "nsf_decode", "nsf_get_latent",
                      "nsf_set_latent", "nsf_status_flags", "nsf_sim_buffer", "nsf_destroy_sim",
                      "nsf_mlp_forward", "nsf_mlp_backward"):
             getattr(L, name).restype = C.c_int
@@ -126,6 +127,10 @@ def nsf_step(sim: int, n_steps: int, stream: int) -> None:
 def nsf_step_batch(sims, n_steps: int, stream: int) -> None:
     arr = (C.c_void_p * len(sims))(*sims)
     check(lib().nsf_step_batch(arr, len(sims), n_steps, stream or None))
+
+
+def nsf_refresh(sim: int, stream: int) -> None:
+    check(lib().nsf_refresh(sim, stream or None))
 
 
 def nsf_decode(sim: int, X_ptr: int | None, n: int, out_ptr: int, stream: int) -> None:

@@ -173,6 +173,9 @@ struct nsf_sim {
   FieldPack pack[3]{};
   float scale[3][9]{}, shift[3][9]{};
   std::unique_ptr<Plan> solo;
+  // The step's field inference for the current latent is in the sim's buffers (the
+  // previous step computed it at its end); false after create and set_latent.
+  bool inference_ready = false;
 };
 
 // Work tables and the captured step graph for one ordered set of sims.
@@ -184,13 +187,19 @@ struct Plan {
   int32_t* d_counts = nullptr;
   SimDev* d_sims = nullptr;
   FieldJob* d_jobs = nullptr;
-  FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tD = nullptr;
+  FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tAD = nullptr, *d_tD = nullptr;
   BlockWork *d_bP = nullptr, *d_bS = nullptr, *d_bGN = nullptr;
-  int nA = 0, nG = 0, nD = 0, nP = 0, nS = 0, nGN = 0, nsims = 0;
-  FieldJob decode_job{};   // single-sim plans decode with the dense kernel (job by value)
+  int nA = 0, nG = 0, nAD = 0, nD = 0, nP = 0, nS = 0, nGN = 0, nsims = 0;
+  FieldJob decode_job{};          // single-sim plans decode with the dense kernel
+  // Decode runs on a side stream, concurrently with the next step's inference.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~Plan() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (dbuf) (void)hipFree(dbuf);
@@ -257,7 +266,8 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.tc = fields_max_tangents(P.width, P.bf16);
   std::vector<SimDev> sims;
   std::vector<FieldJob> jobs;
-  std::vector<FieldTile> tA_jac, tA_prim, tG, tD;
+  std::vector<FieldTile> tA_jac, tA_prim, tG, tD, tD0;  // tD: decode groups for the tangent
+                                                         // kernel, tD0: for the primal kernel
   std::vector<BlockWork> bP, bS, bGN;
   for (size_t si = 0; si < P.members.size(); ++si) {
     nsf_sim* s = P.members[si];
@@ -300,26 +310,31 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     FieldJob dj = base_job(s, NSF_FIELD_G, zc);
     dj.idx = nullptr; dj.step = nullptr; dj.n = (int)s->n_part; dj.mode = 1;
     dj.out = H.xdec; dj.ldo = s->n_part;
-    add_tiles(tD, (int)jobs.size(), (int)s->n_part, 0, 0);
+    add_prim_tiles(tD, (int)jobs.size(), (int)s->n_part, P.tc);
+    add_tiles(tD0, (int)jobs.size(), (int)s->n_part, 0, 0);
     jobs.push_back(dj);
     P.decode_job = dj;
     for (int p0 = 0; p0 < N; p0 += kMpmBlock) bP.push_back({(int)si, p0});
     for (int p0 = 0; p0 < S; p0 += kMpmBlock) bS.push_back({(int)si, p0});
     for (int p0 = 0; p0 < S; p0 += kGnChunk) bGN.push_back({(int)si, p0});
   }
-  std::vector<FieldTile> tA(tA_jac);
+  // Longest groups first: Jacobian groups, then decode, then the primal-only groups.
+  std::vector<FieldTile> tA(tA_jac), tAD(tA_jac);
   tA.insert(tA.end(), tA_prim.begin(), tA_prim.end());
-  P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nD = (int)tD.size();
+  if (P.decode) tAD.insert(tAD.end(), tD.begin(), tD.end());
+  tAD.insert(tAD.end(), tA_prim.begin(), tA_prim.end());
+  P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nAD = (int)tAD.size(); P.nD = (int)tD0.size();
   P.nP = (int)bP.size(); P.nS = (int)bS.size(); P.nGN = (int)bGN.size();
   P.nsims = (int)sims.size();
-  std::vector<int32_t> counts = {P.nA, P.nG, P.nD, P.nP, P.nS, P.nGN, P.nsims, 0};
+  std::vector<int32_t> counts = {P.nA, P.nG, P.nAD, P.nP, P.nS, P.nGN, P.nsims, P.nD};
   std::vector<char> blob;
   const size_t o_counts = put(blob, counts);
   const size_t o_sims = put(blob, sims);
   const size_t o_jobs = put(blob, jobs);
   const size_t o_tA = put(blob, tA);
   const size_t o_tG = put(blob, tG);
-  const size_t o_tD = put(blob, tD);
+  const size_t o_tAD = put(blob, tAD);
+  const size_t o_tD = put(blob, tD0);
   const size_t o_bP = put(blob, bP);
   const size_t o_bS = put(blob, bS);
   const size_t o_bGN = put(blob, bGN);
@@ -330,7 +345,13 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.d_jobs = reinterpret_cast<FieldJob*>(b + o_jobs);
   P.d_tA = reinterpret_cast<FieldTile*>(b + o_tA);
   P.d_tG = reinterpret_cast<FieldTile*>(b + o_tG);
+  P.d_tAD = reinterpret_cast<FieldTile*>(b + o_tAD);
   P.d_tD = reinterpret_cast<FieldTile*>(b + o_tD);
+  if (P.decode) {
+    NSF_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+    NSF_HIP(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
+    NSF_HIP(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
+  }
   P.d_bP = reinterpret_cast<BlockWork*>(b + o_bP);
   P.d_bS = reinterpret_cast<BlockWork*>(b + o_bS);
   P.d_bGN = reinterpret_cast<BlockWork*>(b + o_bGN);
@@ -339,8 +360,37 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   return NSF_OK;
 }
 
-nsf_status enqueue_step(Plan& P, hipStream_t s) {
+// Field inference of the step for the current latent, alone (prologue after create or
+// set_latent).
+nsf_status enqueue_inference(Plan& P, hipStream_t s) {
   NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0, P.nA, s));
+  return NSF_OK;
+}
+
+// Decode of the current latent and the next step's field inference, in one launch (both
+// evaluate the fields at the same latent).
+nsf_status enqueue_refresh(Plan& P, hipStream_t s) {
+  if (!P.decode || s == nullptr || !P.side) {
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tAD, P.d_counts + 2, P.nAD, s));
+    return NSF_OK;
+  }
+  // fork: decode (primal kernel, two waves per SIMD) on the side stream, the next step's
+  // inference (tangent kernel) on the main stream; join before the step continues
+  NSF_HIP(hipEventRecord(P.ev_fork, s));
+  NSF_HIP(hipStreamWaitEvent(P.side, P.ev_fork, 0));
+  if (P.nsims == 1)
+    NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, P.side));
+  else
+    NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7, P.nD, P.side));
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0, P.nA, s));
+  NSF_HIP(hipEventRecord(P.ev_join, P.side));
+  NSF_HIP(hipStreamWaitEvent(s, P.ev_join, 0));
+  return NSF_OK;
+}
+
+// One latent step, given its field inference in the buffers: MPM step, Gauss-Newton
+// iterations, then decode at z_{n+1} together with the inference of step n + 1.
+nsf_status enqueue_step(Plan& P, hipStream_t s) {
   NSF_HIP(launch_p2g(P.d_sims, P.d_bP, P.d_counts + 3, P.nP, s));
   NSF_HIP(launch_g2p(P.d_sims, P.d_bS, P.d_counts + 4, P.nS, s));
   NSF_HIP(launch_grid_clean(P.d_sims, P.d_bP, P.d_counts + 3, P.nP, s));
@@ -349,37 +399,38 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
     NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1, P.nG, s));
     NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.nGN, s));
   }
-  if (P.decode) {
-    if (P.nsims == 1)  // same kernel and launch shape as nsf_decode
-      NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, s));
-    else
-      NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 2, P.nD, s));
-  }
-  return NSF_OK;
+  return enqueue_refresh(P, s);
 }
 
 nsf_status run_plan(Plan& P, int32_t n_steps, hipStream_t s) {
+  bool ready = true;
+  for (nsf_sim* m : P.members) ready = ready && m->inference_ready;
+  if (!ready) {
+    const nsf_status st = enqueue_inference(P, s);
+    if (st != NSF_OK) return st;
+  }
   if (s == nullptr) {
     for (int i = 0; i < n_steps; ++i) {
       const nsf_status st = enqueue_step(P, s);
       if (st != NSF_OK) return st;
     }
-    return NSF_OK;
-  }
-  if (!P.exec) {
-    NSF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    const nsf_status st = enqueue_step(P, s);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(s, &g);
-    if (st != NSF_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
+  } else {
+    if (!P.exec) {
+      NSF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const nsf_status st = enqueue_step(P, s);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(s, &g);
+      if (st != NSF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(NSF_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+      P.graph = g;
+      NSF_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
     }
-    if (e != hipSuccess) return fail(NSF_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-    P.graph = g;
-    NSF_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+    for (int i = 0; i < n_steps; ++i) NSF_HIP(hipGraphLaunch(P.exec, s));
   }
-  for (int i = 0; i < n_steps; ++i) NSF_HIP(hipGraphLaunch(P.exec, s));
+  for (nsf_sim* m : P.members) m->inference_ready = true;
   return NSF_OK;
 }
 
@@ -630,7 +681,23 @@ nsf_status nsf_set_latent(nsf_sim* s, const double* z, const double* z_prev, int
   NSF_HIP(hipMemcpyAsync(s->hd.step, &step, 8, hipMemcpyHostToDevice, st));
   NSF_HIP(hipMemcpyAsync(s->hd.flags, &zero, 4, hipMemcpyHostToDevice, st));
   NSF_HIP(hipStreamSynchronize(st));
+  s->inference_ready = false;
   return NSF_OK;
+}
+
+nsf_status nsf_refresh(nsf_sim* s, void* stream) {
+  if (!s) return fail(NSF_EINVAL, "sim is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!s->solo) {
+    std::unique_ptr<Plan> p(new Plan());
+    p->members.push_back(s);
+    const nsf_status e = build_plan(*p, st);
+    if (e != NSF_OK) return e;
+    s->solo = std::move(p);
+  }
+  const nsf_status e = enqueue_refresh(*s->solo, st);
+  if (e == NSF_OK) s->inference_ready = true;
+  return e;
 }
 
 nsf_status nsf_status_flags(nsf_sim* s, uint32_t* flags, void* stream) {

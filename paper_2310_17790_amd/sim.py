@@ -106,6 +106,11 @@ class Sim:
     def step(self, n: int = 1, stream: Optional[torch.cuda.Stream] = None) -> None:
         A.nsf_step(self.handle, n, _stream_handle(stream))
 
+    def refresh(self, stream: Optional[torch.cuda.Stream] = None) -> None:
+        """Evaluate the fields at the current latent (decoded positions and the next step's
+        field inference) in one launch."""
+        A.nsf_refresh(self.handle, _stream_handle(stream))
+
     def decode(self, X: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         """x = X + u(X, z_n) as a (3, n) float32 tensor; X is a (3, n) float32 device tensor."""
         if X is None:

@@ -47,9 +47,12 @@ def test_stage_parity_one_step(r, width, n):
     print(f"\n[case] stage parity r={r} width={width} n={n}", flush=True)
     s = _stream()
     sim = Sim(w, stream=s)
-    sim.step(1, stream=s)
+    # the field inference of step 0 (and the decode at z0), as the step will consume it
+    sim.refresh(stream=s)
     s.synchronize()
     o = OracleSim(w)
+    x0 = _soa(sim.buffer(A.NSF_BUF_XDEC)).reshape(3, -1).T
+    errs0 = _rel_max(x0 - o.X, o.decode() - o.X)
     idx = o.indices(0)
     x, v, tau, C, u_n = o.inference(idx)
     XN = o.X[idx]
@@ -65,6 +68,10 @@ def test_stage_parity_one_step(r, width, n):
     J = o.jac(XN[:S], o.z)                              # (S, 3, r)
     Jg = _soa(sim.buffer(A.NSF_BUF_JAC)).reshape(3, r, S).transpose(2, 0, 1)
     errs["J"] = _rel_max(Jg, J)
+    errs["decode_u"] = errs0
+    u_gpu = _soa(sim.buffer(A.NSF_BUF_U)).reshape(3, N).T
+    sim.step(1, stream=s)
+    s.synchronize()
     v_new = o.mpm_step(x, v, tau, C, S)
     errs["v_new"] = _rel_max(_soa(sim.buffer(A.NSF_BUF_VNEW)).reshape(3, S).T, v_new)
     z_ref = o.inversion(XN[:S], u_n[:S] + w.dt * v_new)
@@ -83,11 +90,10 @@ def test_stage_parity_one_step(r, width, n):
     print("errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     assert st == 1
     np.testing.assert_array_equal(zp_gpu, w.z0)
-    for k in ("u", "u_prev", "tau", "C", "J"):
+    for k in ("u", "u_prev", "tau", "C", "J", "decode_u"):
         assert errs[k] < 2e-5, (k, errs[k])
     # velocities are (u(z_n) - u(z_{n-1})) / dt of FP32 field values: absolute error ~ 2 eps_u / dt
     v_gpu = _soa(sim.buffer(A.NSF_BUF_VNEW)).reshape(3, S).T
-    u_gpu = _soa(sim.buffer(A.NSF_BUF_U)).reshape(3, N).T
     eps_u = float(np.abs(u_gpu - u_n).max())
     tol_v = 1e-4 + 10 * eps_u / (w.dt * np.abs(v_new).max())
     assert errs["v_new"] < tol_v, (errs["v_new"], tol_v)
