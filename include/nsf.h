@@ -87,7 +87,7 @@ typedef struct {
   const float *X;              /* host, [3][n_particles] reference positions              */
   double rho;                  /* density; m_p = rho V_p                                  */
   double body_volume;          /* V_p = body_volume / n_integration                       */
-  int32_t grid_n;              /* nodes per axis, x_i = i dx, 8 <= grid_n <= 512          */
+  int32_t grid_n;              /* nodes per axis, x_i = i dx, 8 <= grid_n <= 256          */
   double dx, dt;
   double gravity[3];
   int32_t wall_nodes;          /* sticky band: nodes with any index < b or >= n - b       */
@@ -158,14 +158,16 @@ nsf_status nsf_status_flags(nsf_sim *s, uint32_t *flags, void *stream);
  * that consume the step's intermediates). *ptr receives the device address and *count
  * the number of elements (float unless noted).
  *   NSF_BUF_U       u(X_N, z_n)          [3][n_integration]
- *   NSF_BUF_UPREV   u(X_N, z_{n-1})      [3][n_integration]
+ *   NSF_BUF_UPREV   u(X_N, z_{n-1})      [3][n_integration]; with BF16 precision the
+ *                   velocity itself, J((z_n + z_{n-1})/2) (z_n - z_{n-1}) / dt
  *   NSF_BUF_TAU     h(X_N, z_n)          [6][n_integration]
  *   NSF_BUF_C       l(X_N, z_n)          [9][n_integration]
  *   NSF_BUF_JAC     du/dz at z_n on S    [3 r][n_sample], row c*r + j = du_c/dz_j
  *   NSF_BUF_VNEW    G2P velocity on S    [3][n_sample]
  *   NSF_BUF_XDEC    decoded positions    [3][n_particles]
- *   NSF_BUF_GRID    grid (m, p_x, p_y, p_z) per node [4][grid_n^3] interleaved as float4;
- *                   zero between steps (cleaned after use)
+ *   NSF_BUF_GRID    grid after the grid update, float4 (v_x, v_y, v_z, m) per node,
+ *                   node (i, j, k) at (i grid_n + j) grid_n + k; valid on the node blocks
+ *                   the step's particles reach (others hold older values)
  *   NSF_BUF_Z       double [3][r]: z_{n-1}, z_n, last Gauss-Newton iterate
  * Buffers hold the values of the last completed step. */
 enum { NSF_BUF_U = 0, NSF_BUF_UPREV, NSF_BUF_TAU, NSF_BUF_C, NSF_BUF_JAC, NSF_BUF_VNEW,

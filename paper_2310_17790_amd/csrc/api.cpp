@@ -58,10 +58,14 @@ struct Layout {
   size_t simdev;
   size_t w1p[3], whp[3], whb[3], bhp[3], w6p[3], b6[3];
   size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, step, flags, gn_part, gn_count;
+  size_t bin_cnt, bin_start, pbin, prank, rec, sorted, active, nonempty, n_active;
   size_t total;
 };
 
 int gn_entries(int r) { return r * (r + 1) / 2 + r; }
+// P2G bins: cubes of bin_edge^3 cells, at most 32 per axis
+int bin_edge(int grid_n) { return grid_n <= 128 ? 4 : 8; }
+int bins_per_axis(int grid_n) { return (grid_n + bin_edge(grid_n) - 1) / bin_edge(grid_n); }
 
 Layout make_layout(const nsf_sim_desc* d) {
   Layout L{};
@@ -96,6 +100,17 @@ Layout make_layout(const nsf_sim_desc* d) {
   L.flags = c.take(4);
   L.gn_part = c.take((size_t)ceil_div(S, kGnChunk) * gn_entries(r) * 8);
   L.gn_count = c.take(4);
+  const int nbs = bins_per_axis(d->grid_n);
+  const size_t nb = (size_t)nbs * nbs * nbs;
+  L.bin_cnt = c.take(nb * 4);
+  L.bin_start = c.take((nb + 1) * 4);
+  L.pbin = c.take((size_t)N * 4);
+  L.prank = c.take((size_t)N * 4);
+  L.rec = c.take((size_t)N * 64);
+  L.sorted = c.take((size_t)N * 4);
+  L.active = c.take(nb * 4);
+  L.nonempty = c.take(nb * 4);
+  L.n_active = c.take(8);
   L.total = c.off;
   return L;
 }
@@ -118,7 +133,7 @@ nsf_status validate(const nsf_sim_desc* d) {
   if (3 * (int64_t)d->n_sample < d->r)
     return fail(NSF_EINVAL, "n_sample = %d < r / 3: the inversion is under-determined", d->n_sample);
   if (d->plan_steps < 1 || !d->sample_plan) return fail(NSF_EINVAL, "sample_plan missing");
-  if (d->grid_n < 8 || d->grid_n > 512) return fail(NSF_EINVAL, "grid_n = %d outside 8..512", d->grid_n);
+  if (d->grid_n < 8 || d->grid_n > 256) return fail(NSF_EINVAL, "grid_n = %d outside 8..256", d->grid_n);
   if (!(d->dx > 0) || !(d->dt > 0)) return fail(NSF_EINVAL, "dx and dt must be positive");
   if (!(d->rho > 0) || !(d->body_volume > 0)) return fail(NSF_EINVAL, "rho and body_volume must be positive");
   if (d->wall_nodes < 0 || 2 * d->wall_nodes >= d->grid_n) return fail(NSF_EINVAL, "wall_nodes = %d", d->wall_nodes);
@@ -178,18 +193,26 @@ struct nsf_sim {
   bool inference_ready = false;
 };
 
-// Work tables and the captured step graph for one ordered set of sims.
+// Work tables and the captured step graph for one ordered set of sims. A batch plan
+// (persistent=true) launches every kernel with a fixed grid that loops over device-side
+// work counts, so when the set of sims changes only the tables are rewritten in place
+// and the captured graph is replayed unchanged.
 struct Plan {
   std::vector<nsf_sim*> members;
   int width = 0, gn_iters = 0, tc = 0;
-  bool bf16 = false, decode = false;
+  bool bf16 = false, decode = false, persistent = false;
   void* dbuf = nullptr;
-  int32_t* d_counts = nullptr;
+  size_t dcap = 0;
+  void* staging = nullptr;        // pinned host copy of the tables (persistent plans)
+  std::vector<size_t> caps;       // byte capacity of each table region
+  int32_t* d_counts = nullptr;    // [0..7] work counts, [8..15] claim counters
   SimDev* d_sims = nullptr;
   FieldJob* d_jobs = nullptr;
   FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tAD = nullptr, *d_tD = nullptr;
   BlockWork *d_bP = nullptr, *d_bS = nullptr, *d_bGN = nullptr;
   int nA = 0, nG = 0, nAD = 0, nD = 0, nP = 0, nS = 0, nGN = 0, nsims = 0;
+  // launch grids (fixed for persistent plans)
+  int gF = 0, gF0 = 0, gP = 0, gS = 0, gGN = 0, gSims = 0, gBlk = 0;
   FieldJob decode_job{};          // single-sim plans decode with the dense kernel
   // Decode runs on a side stream, concurrently with the next step's inference.
   hipStream_t side = nullptr;
@@ -203,13 +226,20 @@ struct Plan {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (dbuf) (void)hipFree(dbuf);
+    if (staging) (void)hipHostFree(staging);
   }
 };
 
 namespace {
 
 std::mutex g_plans_mu;
-std::map<std::vector<nsf_sim*>, std::unique_ptr<Plan>> g_batch_plans;
+// One persistent batch plan per (width, precision, Gauss-Newton iterations, decode mode);
+// its tables are rewritten when the set of stepped sims changes.
+std::map<int, std::unique_ptr<Plan>> g_batch_plans;
+
+int batch_signature(const nsf_sim* s) {
+  return s->width * 64 + (s->bf16 ? 32 : 0) + s->gn_iters * 2 + (s->decode_every_step ? 1 : 0);
+}
 
 FieldJob base_job(const nsf_sim* s, int field, const double* z) {
   FieldJob j{};
@@ -248,15 +278,19 @@ void add_prim_tiles(std::vector<FieldTile>& out, int job, int n, int tc) {
   for (int p0 = 0; p0 < n; p0 += span) out.push_back({job, p0, 0, 0});
 }
 
-template <class T>
-size_t put(std::vector<char>& blob, const std::vector<T>& v) {
-  const size_t off = align_up(blob.size());
-  blob.resize(off + std::max<size_t>(v.size() * sizeof(T), 1));
-  if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
-  blob.resize(align_up(blob.size()));
-  return off;
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
 }
 
+// Build the work tables of P.members into one blob and install it in P's device buffer.
 nsf_status build_plan(Plan& P, hipStream_t stream) {
   nsf_sim* s0 = P.members[0];
   P.width = s0->width;
@@ -278,7 +312,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     const double* zi = H.z + 2 * s->r;
     const int N = s->n_int, S = s->n_samp, r = s->r;
     const int j0 = (int)jobs.size();
-    // pass A: g with its Jacobian on S, g on N \ S, g at z_{n-1}, h, l
+    // inference: g with its Jacobian on S, g on N \ S, velocity, h, l
     FieldJob a = base_job(s, NSF_FIELD_G, zc);
     a.n = S; a.out = H.u_n; a.ldo = N; a.jac = H.J; a.ldj = S;
     jobs.push_back(a);
@@ -291,7 +325,15 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     }
     FieldJob c = base_job(s, NSF_FIELD_G, zp);
     c.n = N; c.out = H.u_prev; c.ldo = N;
-    add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
+    if (H.tangent_forms) {
+      // velocity as the directional derivative at the midpoint:
+      // v = J((z_n + z_{n-1}) / 2) (z_n - z_{n-1}) / dt
+      c.z = zc; c.z2 = zp; c.jvp = 1; c.jvp_scale = (float)(1.0 / H.dt_d);
+      for (int p0 = 0; p0 < N; p0 += kTile * fields_group_waves(P.tc))
+        tA_jac.push_back({(int)jobs.size(), p0, 0, 1});
+    } else {
+      add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
+    }
     jobs.push_back(c);
     FieldJob h = base_job(s, NSF_FIELD_H, zc);
     h.n = N; h.out = H.tau; h.ldo = N;
@@ -326,80 +368,140 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nAD = (int)tAD.size(); P.nD = (int)tD0.size();
   P.nP = (int)bP.size(); P.nS = (int)bS.size(); P.nGN = (int)bGN.size();
   P.nsims = (int)sims.size();
-  std::vector<int32_t> counts = {P.nA, P.nG, P.nAD, P.nP, P.nS, P.nGN, P.nsims, P.nD};
-  std::vector<char> blob;
-  const size_t o_counts = put(blob, counts);
-  const size_t o_sims = put(blob, sims);
-  const size_t o_jobs = put(blob, jobs);
-  const size_t o_tA = put(blob, tA);
-  const size_t o_tG = put(blob, tG);
-  const size_t o_tAD = put(blob, tAD);
-  const size_t o_tD = put(blob, tD0);
-  const size_t o_bP = put(blob, bP);
-  const size_t o_bS = put(blob, bS);
-  const size_t o_bGN = put(blob, bGN);
-  NSF_HIP(hipMalloc(&P.dbuf, blob.size()));
+  std::vector<int32_t> counts = {P.nA, P.nG, P.nAD, P.nP, P.nS, P.nGN, P.nsims, P.nD,
+                                 0, 0, 0, 0, 0, 0, 0, 0};
+  // Regions of the device buffer. A persistent plan keeps fixed region capacities (grown
+  // by half when exceeded), so its captured graph stays valid while tables are rewritten.
+  struct Region { const void* data; size_t bytes; };
+  const Region reg[10] = {
+      {counts.data(), counts.size() * 4}, {sims.data(), sims.size() * sizeof(SimDev)},
+      {jobs.data(), jobs.size() * sizeof(FieldJob)}, {tA.data(), tA.size() * sizeof(FieldTile)},
+      {tG.data(), tG.size() * sizeof(FieldTile)}, {tAD.data(), tAD.size() * sizeof(FieldTile)},
+      {tD0.data(), tD0.size() * sizeof(FieldTile)}, {bP.data(), bP.size() * sizeof(BlockWork)},
+      {bS.data(), bS.size() * sizeof(BlockWork)}, {bGN.data(), bGN.size() * sizeof(BlockWork)}};
+  bool relayout = P.caps.empty();
+  for (int i = 0; i < 10 && !relayout; ++i) relayout = reg[i].bytes > P.caps[i];
+  if (relayout) {
+    P.caps.assign(10, 0);
+    for (int i = 0; i < 10; ++i)
+      P.caps[i] = align_up(P.persistent ? reg[i].bytes + reg[i].bytes / 2 + 4096 : std::max<size_t>(reg[i].bytes, 1));
+  }
+  size_t off[10], total = 0;
+  for (int i = 0; i < 10; ++i) { off[i] = total; total += P.caps[i]; }
+  if (relayout || total > P.dcap) {
+    if (P.exec) { (void)hipGraphExecDestroy(P.exec); P.exec = nullptr; }
+    if (P.graph) { (void)hipGraphDestroy(P.graph); P.graph = nullptr; }
+    if (P.dbuf) { NSF_HIP(hipStreamSynchronize(stream)); NSF_HIP(hipFree(P.dbuf)); P.dbuf = nullptr; }
+    P.dcap = total;
+    NSF_HIP(hipMalloc(&P.dbuf, P.dcap));
+    if (P.persistent) {
+      if (P.staging) NSF_HIP(hipHostFree(P.staging));
+      P.staging = nullptr;
+      NSF_HIP(hipHostMalloc(&P.staging, P.dcap, hipHostMallocDefault));
+    }
+  }
   char* b = static_cast<char*>(P.dbuf);
-  P.d_counts = reinterpret_cast<int32_t*>(b + o_counts);
-  P.d_sims = reinterpret_cast<SimDev*>(b + o_sims);
-  P.d_jobs = reinterpret_cast<FieldJob*>(b + o_jobs);
-  P.d_tA = reinterpret_cast<FieldTile*>(b + o_tA);
-  P.d_tG = reinterpret_cast<FieldTile*>(b + o_tG);
-  P.d_tAD = reinterpret_cast<FieldTile*>(b + o_tAD);
-  P.d_tD = reinterpret_cast<FieldTile*>(b + o_tD);
-  if (P.decode) {
+  P.d_counts = reinterpret_cast<int32_t*>(b + off[0]);
+  P.d_sims = reinterpret_cast<SimDev*>(b + off[1]);
+  P.d_jobs = reinterpret_cast<FieldJob*>(b + off[2]);
+  P.d_tA = reinterpret_cast<FieldTile*>(b + off[3]);
+  P.d_tG = reinterpret_cast<FieldTile*>(b + off[4]);
+  P.d_tAD = reinterpret_cast<FieldTile*>(b + off[5]);
+  P.d_tD = reinterpret_cast<FieldTile*>(b + off[6]);
+  P.d_bP = reinterpret_cast<BlockWork*>(b + off[7]);
+  P.d_bS = reinterpret_cast<BlockWork*>(b + off[8]);
+  P.d_bGN = reinterpret_cast<BlockWork*>(b + off[9]);
+  if (P.persistent) {
+    NSF_HIP(hipStreamSynchronize(stream));  // the previous upload has been consumed
+    char* st = static_cast<char*>(P.staging);
+    for (int i = 0; i < 10; ++i)
+      if (reg[i].bytes) std::memcpy(st + off[i], reg[i].data, reg[i].bytes);
+    // only the used part of each region is copied (regions are independent)
+    for (int i = 0; i < 10; ++i)
+      if (reg[i].bytes)
+        NSF_HIP(hipMemcpyAsync(b + off[i], st + off[i], reg[i].bytes, hipMemcpyHostToDevice, stream));
+  } else {
+    std::vector<char> blob(total, 0);
+    for (int i = 0; i < 10; ++i)
+      if (reg[i].bytes) std::memcpy(blob.data() + off[i], reg[i].data, reg[i].bytes);
+    NSF_HIP(hipMemcpyAsync(P.dbuf, blob.data(), total, hipMemcpyHostToDevice, stream));
+    NSF_HIP(hipStreamSynchronize(stream));
+  }
+  // grids
+  const int cus = device_cus();
+  const int fcap = cus * fields_table_blocks_per_cu(P.width, P.bf16, P.tc);
+  const int fcap0 = cus * fields_table_blocks_per_cu(P.width, P.bf16, 0);
+  auto mn = [](int a, int b) { return a < b ? a : b; };
+  P.gF = P.persistent ? fcap : mn(fcap, std::max(P.nA, std::max(P.nAD, P.nG)));
+  P.gF0 = P.persistent ? fcap0 : mn(fcap0, P.nD);
+  P.gP = P.persistent ? 4 * cus : P.nP;
+  P.gS = P.persistent ? 4 * cus : P.nS;
+  P.gGN = P.persistent ? 4 * cus : P.nGN;
+  P.gSims = P.persistent ? cus : P.nsims;
+  P.gBlk = 2 * cus;   // gather workgroups loop over each sim's active node blocks
+  if (P.decode && !P.side) {
     NSF_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
     NSF_HIP(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
     NSF_HIP(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
   }
-  P.d_bP = reinterpret_cast<BlockWork*>(b + o_bP);
-  P.d_bS = reinterpret_cast<BlockWork*>(b + o_bS);
-  P.d_bGN = reinterpret_cast<BlockWork*>(b + o_bGN);
-  NSF_HIP(hipMemcpyAsync(P.dbuf, blob.data(), blob.size(), hipMemcpyHostToDevice, stream));
-  NSF_HIP(hipStreamSynchronize(stream));
   return NSF_OK;
 }
+
+// Claim counters (zeroed at the start of every launch sequence): 8 inference, 9 + k the
+// Gauss-Newton iterate pass k, 13 refresh (inference + decode), 14 decode alone.
+constexpr int kClaimA = 8, kClaimG = 9, kClaimAD = 13, kClaimD = 14;
 
 // Field inference of the step for the current latent, alone (prologue after create or
 // set_latent).
 nsf_status enqueue_inference(Plan& P, hipStream_t s) {
-  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0, P.nA, s));
+  NSF_HIP(launch_reset_counters(P.d_counts + 8, 8, s));
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
+                              P.d_counts + kClaimA, std::min(P.gF, std::max(P.nA, 1)), s));
   return NSF_OK;
 }
 
-// Decode of the current latent and the next step's field inference, in one launch (both
-// evaluate the fields at the same latent).
-nsf_status enqueue_refresh(Plan& P, hipStream_t s) {
+// Decode of the current latent and the next step's field inference (both evaluate the
+// fields at the same latent). Counters must have been reset in this sequence.
+nsf_status enqueue_refresh_body(Plan& P, hipStream_t s) {
   if (!P.decode || s == nullptr || !P.side) {
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tAD, P.d_counts + 2, P.nAD, s));
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tAD, P.d_counts + 2,
+                                P.d_counts + kClaimAD, P.gF, s));
     return NSF_OK;
   }
   // fork: decode (primal kernel, two waves per SIMD) on the side stream, the next step's
   // inference (tangent kernel) on the main stream; join before the step continues
   NSF_HIP(hipEventRecord(P.ev_fork, s));
   NSF_HIP(hipStreamWaitEvent(P.side, P.ev_fork, 0));
-  if (P.nsims == 1)
+  if (P.nsims == 1 && !P.persistent)
     NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, P.side));
   else
-    NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7, P.nD, P.side));
-  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0, P.nA, s));
+    NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
+                                P.d_counts + kClaimD, P.gF0, P.side));
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
+                              P.d_counts + kClaimA, P.gF, s));
   NSF_HIP(hipEventRecord(P.ev_join, P.side));
   NSF_HIP(hipStreamWaitEvent(s, P.ev_join, 0));
   return NSF_OK;
 }
 
+nsf_status enqueue_refresh(Plan& P, hipStream_t s) {
+  NSF_HIP(launch_reset_counters(P.d_counts + 8, 8, s));
+  return enqueue_refresh_body(P, s);
+}
+
 // One latent step, given its field inference in the buffers: MPM step, Gauss-Newton
 // iterations, then decode at z_{n+1} together with the inference of step n + 1.
 nsf_status enqueue_step(Plan& P, hipStream_t s) {
-  NSF_HIP(launch_p2g(P.d_sims, P.d_bP, P.d_counts + 3, P.nP, s));
-  NSF_HIP(launch_g2p(P.d_sims, P.d_bS, P.d_counts + 4, P.nS, s));
-  NSF_HIP(launch_grid_clean(P.d_sims, P.d_bP, P.d_counts + 3, P.nP, s));
-  NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, 0, P.nGN, s));
+  NSF_HIP(launch_reset_counters(P.d_counts + 8, 8, s));
+  NSF_HIP(launch_p2g(P.d_sims, P.d_bP, P.d_counts + 3, P.d_counts + 6, P.gP, P.gSims, P.gBlk, s));
+  NSF_HIP(launch_g2p(P.d_sims, P.d_bS, P.d_counts + 4, P.gS, s));
+  NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, 0, P.gGN, s));
   for (int k = 1; k < P.gn_iters; ++k) {
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1, P.nG, s));
-    NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.nGN, s));
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1,
+                                P.d_counts + kClaimG + (k - 1), P.gF, s));
+    NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.gGN, s));
   }
-  return enqueue_refresh(P, s);
+  return enqueue_refresh_body(P, s);
 }
 
 nsf_status run_plan(Plan& P, int32_t n_steps, hipStream_t s) {
@@ -436,9 +538,10 @@ nsf_status run_plan(Plan& P, int32_t n_steps, hipStream_t s) {
 
 void drop_batch_plans_with(nsf_sim* s) {
   std::lock_guard<std::mutex> lk(g_plans_mu);
-  for (auto it = g_batch_plans.begin(); it != g_batch_plans.end();) {
-    if (std::find(it->first.begin(), it->first.end(), s) != it->first.end()) it = g_batch_plans.erase(it);
-    else ++it;
+  for (auto& kv : g_batch_plans) {
+    Plan& P = *kv.second;
+    if (std::find(P.members.begin(), P.members.end(), s) != P.members.end())
+      P.members.clear();  // tables reference the sim: rebuild before the next replay
   }
 }
 
@@ -532,6 +635,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
   NSF_HIP(hipMemsetAsync(A + L.flags, 0, 4, s));
   NSF_HIP(hipMemsetAsync(A + L.gn_count, 0, 4, s));
+  NSF_HIP(hipMemsetAsync(A + L.bin_cnt, 0, L.bin_start - L.bin_cnt, s));
   NSF_HIP(hipMemsetAsync(A + L.xdec, 0, (size_t)3 * P * 4, s));
 
   SimDev& H = sim->hd;
@@ -546,6 +650,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.knife_on = d->knife.enabled ? 1 : 0;
   H.n_gn_chunks = ceil_div(d->n_sample, kGnChunk);
   H.width = W;
+  H.tangent_forms = sim->bf16 ? 1 : 0;
   const double Vp = d->body_volume / d->n_integration;
   H.dx = (float)d->dx;
   H.inv_dx = (float)(1.0 / d->dx);
@@ -581,6 +686,18 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.flags = reinterpret_cast<uint32_t*>(A + L.flags);
   H.gn_part = reinterpret_cast<double*>(A + L.gn_part);
   H.gn_count = reinterpret_cast<uint32_t*>(A + L.gn_count);
+  H.bin_edge = bin_edge(d->grid_n);
+  H.nbs = bins_per_axis(d->grid_n);
+  H.n_bins = H.nbs * H.nbs * H.nbs;
+  H.bin_cnt = reinterpret_cast<int32_t*>(A + L.bin_cnt);
+  H.bin_start = reinterpret_cast<int32_t*>(A + L.bin_start);
+  H.pbin = reinterpret_cast<int32_t*>(A + L.pbin);
+  H.prank = reinterpret_cast<int32_t*>(A + L.prank);
+  H.rec = reinterpret_cast<float*>(A + L.rec);
+  H.sorted = reinterpret_cast<int32_t*>(A + L.sorted);
+  H.active = reinterpret_cast<int32_t*>(A + L.active);
+  H.nonempty = reinterpret_cast<int32_t*>(A + L.nonempty);
+  H.n_active = reinterpret_cast<int32_t*>(A + L.n_active);
   sim->dd = reinterpret_cast<SimDev*>(A + L.simdev);
   NSF_HIP(hipMemcpyAsync(sim->dd, &H, sizeof(SimDev), hipMemcpyHostToDevice, s));
   NSF_HIP(hipStreamSynchronize(s));
@@ -618,23 +735,22 @@ nsf_status nsf_step_batch(nsf_sim* const* sims, int32_t n, int32_t n_steps, void
   }
   if (n_steps == 0) return NSF_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  Plan* plan = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_plans_mu);
-    auto it = g_batch_plans.find(key);
-    if (it != g_batch_plans.end()) plan = it->second.get();
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  std::unique_ptr<Plan>& slot = g_batch_plans[batch_signature(key[0])];
+  if (!slot) {
+    slot.reset(new Plan());
+    slot->persistent = true;
   }
-  if (!plan) {
-    std::unique_ptr<Plan> p(new Plan());
-    p->members = key;
-    const nsf_status e = build_plan(*p, st);
-    if (e != NSF_OK) return e;
-    std::lock_guard<std::mutex> lk(g_plans_mu);
-    if (g_batch_plans.size() >= 16) g_batch_plans.clear();
-    plan = p.get();
-    g_batch_plans[key] = std::move(p);
+  Plan& P = *slot;
+  if (P.members != key) {
+    P.members = key;
+    const nsf_status e = build_plan(P, st);
+    if (e != NSF_OK) {
+      P.members.clear();
+      return e;
+    }
   }
-  return run_plan(*plan, n_steps, st);
+  return run_plan(P, n_steps, st);
 }
 
 nsf_status nsf_decode(nsf_sim* s, const float* X, int64_t n, float* x_out, void* stream) {

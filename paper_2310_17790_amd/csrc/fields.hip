@@ -198,9 +198,9 @@ __device__ __forceinline__ void wait_dma_and_sync() {
 // p0 + 32 w): the primal plus tangents [t0, t0 + nt). Hidden-layer weights stream
 // through two LDS buffers: layer k + 1 (or the next group's layer 2) is fetched while
 // layer k computes. Returns after the output layer.
-template <int W, int NT, bool BF, int WPG>
-__device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0,
-                                          const FieldPack* next_w, char* lds, int wave, int lane) {
+template <int W, int NT, bool BF, int WPG, class NextFn>
+__device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0, NextFn&& next,
+                                          char* lds, int wave, int lane) {
   constexpr int MB = W / 32;
   constexpr int T = 1 + NT;
   constexpr int nt = NT;  // compile-time: no per-MFMA guards
@@ -227,22 +227,32 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0,
     for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f32x16{};
 
   // Layer 1: input rows 0..2 = X, 3..2+r = z, 3+r = 1 (bias column of the packed W1).
+  // Tangent columns are one-hot in z (Jacobian) or the direction z - z2 (JVP job).
   const int K1s = (r + 5) >> 1;
+  const bool jvp = jb.jvp != 0;
   for (int s2 = 0; s2 < K1s; ++s2) {
     const int k = 2 * s2 + h;
-    float b0 = 0.f;
+    float b0 = 0.f, bt = 0.f;
     if (k == 0) b0 = X0;
     else if (k == 1) b0 = X1;
     else if (k == 2) b0 = X2;
-    else if (k < 3 + r) b0 = (float)jb.z[k - 3];
-    else if (k == 3 + r) b0 = 1.f;
+    else if (k < 3 + r) {
+      const double zk = jb.z[k - 3];
+      if (jvp) {
+        const double z2k = jb.z2[k - 3];
+        b0 = (float)(0.5 * (zk + z2k));
+        bt = (float)(zk - z2k);
+      } else {
+        b0 = (float)zk;
+      }
+    } else if (k == 3 + r) b0 = 1.f;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
       const float a = jb.w.w1p[(mb * K1s + s2) * 64 + lane];
       acc[0][mb] = mfma_f32(a, b0, acc[0][mb]);
 #pragma unroll
       for (int t = 1; t < T; ++t)
-        if (t <= nt) acc[t][mb] = mfma_f32(a, (k == 3 + t0 + t - 1) ? 1.f : 0.f, acc[t][mb]);
+        if (t <= nt) acc[t][mb] = mfma_f32(a, jvp ? bt : ((k == 3 + t0 + t - 1) ? 1.f : 0.f), acc[t][mb]);
     }
   }
 
@@ -269,14 +279,25 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0,
     }
   }
   wait_dma_and_sync();
-  if (next_w) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
+  // decide the workgroup's next group now and start fetching its first hidden layer
+  if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
   init_hidden<W, T>(acc, jb.w.bhp + 3 * W, h);
   if constexpr (!BF) hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(lds + LB), lane, nt);
   else hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(lds + LB), lane, nt);
   activate_f32<W, T>(acc, H, nt);
 
-  // Output layer, primal.
   const int d = jb.d;
+  if constexpr (NT >= 1) {
+    if (jvp) {  // directional derivative only: out = scale * (W6 T) * jvp_scale
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float y = output_dot<W>(jb.w.w6p, c, h, H[1]);
+        if (valid && h == (c & 1)) jb.out[c * jb.ldo + p] = jb.scale[c] * y * jb.jvp_scale;
+      }
+      return;
+    }
+  }
+  // Output layer, primal.
   if (t0 == 0) {
 #pragma unroll
     for (int o = 0; o < 9; ++o) {
@@ -303,34 +324,49 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0,
 }
 
 // Run a group with its tangent count as a template argument (0 .. TC).
-template <int W, int TC, bool BF, int WPG>
+template <int W, int TC, bool BF, int WPG, class NextFn>
 __device__ __forceinline__ void dispatch_nt(const FieldJob& jb, int p0, int t0, int nt,
-                                            const FieldPack* next_w, char* lds, int wave, int lane) {
+                                            NextFn&& next, char* lds, int wave, int lane) {
   if constexpr (TC > 0) {
-    if (nt == TC) { run_group<W, TC, BF, WPG>(jb, p0, t0, next_w, lds, wave, lane); return; }
-    dispatch_nt<W, TC - 1, BF, WPG>(jb, p0, t0, nt, next_w, lds, wave, lane);
+    if (nt == TC) { run_group<W, TC, BF, WPG>(jb, p0, t0, next, lds, wave, lane); return; }
+    dispatch_nt<W, TC - 1, BF, WPG>(jb, p0, t0, nt, next, lds, wave, lane);
   } else {
-    run_group<W, 0, BF, WPG>(jb, p0, t0, next_w, lds, wave, lane);
+    run_group<W, 0, BF, WPG>(jb, p0, t0, next, lds, wave, lane);
   }
 }
 
-// Work groups from a table (several jobs; a group is WPG tiles of one job).
+// Work groups from a table (several jobs; a group is WPG tiles of one job). Workgroups
+// claim groups dynamically from a counter (zero at launch), one group ahead so the next
+// group's first hidden layer can be fetched while the current group finishes; groups
+// are ordered longest first, so the claims balance the load.
 template <int W, int TC, bool BF, int WPG>
 __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* __restrict__ jobs,
                                                                 const FieldTile* __restrict__ groups,
-                                                                const int32_t* __restrict__ n_groups) {
+                                                                const int32_t* __restrict__ n_groups,
+                                                                int32_t* __restrict__ claim) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
+  __shared__ int s_claim;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int total = *n_groups;
-  int g = blockIdx.x;
+  if (threadIdx.x == 0) s_claim = atomicAdd(claim, 1);
+  __syncthreads();
+  int g = s_claim;
   if (g >= total) return;
   dma_layer<W, BF, WPG>(jobs[groups[g].job].w, 0, lds, wave, lane);
-  for (; g < total; g += gridDim.x) {
+  int gn = total;
+  // called by every thread at the same point of run_group (after a barrier)
+  auto next = [&]() -> const FieldPack* {
+    if (threadIdx.x == 0) s_claim = atomicAdd(claim, 1);
+    __syncthreads();
+    gn = s_claim;
+    return gn < total ? &jobs[groups[gn].job].w : nullptr;
+  };
+  while (true) {
     const FieldTile tl = groups[g];
-    const int gn = g + gridDim.x;
-    const FieldPack* next_w = gn < total ? &jobs[groups[gn].job].w : nullptr;
-    dispatch_nt<W, TC, BF, WPG>(jobs[tl.job], tl.p0, tl.t0, tl.nt, next_w, lds, wave, lane);
+    dispatch_nt<W, TC, BF, WPG>(jobs[tl.job], tl.p0, tl.t0, tl.nt, next, lds, wave, lane);
+    if (gn >= total) break;
+    g = gn;
   }
 }
 
@@ -344,8 +380,9 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, in
   if (g >= n_groups) return;
   dma_layer<W, BF, WPG>(job.w, 0, lds, wave, lane);
   for (; g < n_groups; g += gridDim.x) {
-    const FieldPack* next_w = g + (int)gridDim.x < n_groups ? &job.w : nullptr;
-    run_group<W, 0, BF, WPG>(job, g * kTile * WPG, 0, next_w, lds, wave, lane);
+    const bool more = g + (int)gridDim.x < n_groups;
+    auto next = [&]() -> const FieldPack* { return more ? &job.w : nullptr; };
+    run_group<W, 0, BF, WPG>(job, g * kTile * WPG, 0, next, lds, wave, lane);
   }
 }
 
@@ -358,7 +395,7 @@ template <int TC> struct Wpg { static constexpr int value = TC > 0 ? 4 : 8; };
 
 template <int W, int TC, bool BF>
 hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int32_t* n_groups,
-                        int grid, hipStream_t s) {
+                        int32_t* claim, int grid, hipStream_t s) {
   constexpr int WPG = Wpg<TC>::value;
   constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes;
   auto k = fields_table_kernel<W, TC, BF, WPG>;
@@ -368,7 +405,7 @@ hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, jobs, groups, n_groups);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, jobs, groups, n_groups, claim);
   return hipGetLastError();
 }
 
@@ -397,23 +434,40 @@ int fields_max_tangents(int width, bool bf16) {
 int fields_group_waves(int tc) { return tc > 0 ? Wpg<1>::value : Wpg<0>::value; }
 
 hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
-                               const FieldTile* groups, const int32_t* n_groups, int grid,
-                               hipStream_t s) {
+                               const FieldTile* groups, const int32_t* n_groups, int32_t* claim,
+                               int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   const bool full = tc > 0;
+#define NSF_TABLE(WW, TT, BB) launch_table<WW, TT, BB>(jobs, groups, n_groups, claim, grid, s)
   if (width == 64) {
-    if (!bf16) return full ? launch_table<64, kTcF32W64, false>(jobs, groups, n_groups, grid, s)
-                           : launch_table<64, 0, false>(jobs, groups, n_groups, grid, s);
-    return full ? launch_table<64, kTcBf16W64, true>(jobs, groups, n_groups, grid, s)
-                : launch_table<64, 0, true>(jobs, groups, n_groups, grid, s);
+    if (!bf16) return full ? NSF_TABLE(64, kTcF32W64, false) : NSF_TABLE(64, 0, false);
+    return full ? NSF_TABLE(64, kTcBf16W64, true) : NSF_TABLE(64, 0, true);
   }
   if (width == 128) {
-    if (!bf16) return full ? launch_table<128, kTcF32W128, false>(jobs, groups, n_groups, grid, s)
-                           : launch_table<128, 0, false>(jobs, groups, n_groups, grid, s);
-    return full ? launch_table<128, kTcBf16W128, true>(jobs, groups, n_groups, grid, s)
-                : launch_table<128, 0, true>(jobs, groups, n_groups, grid, s);
+    if (!bf16) return full ? NSF_TABLE(128, kTcF32W128, false) : NSF_TABLE(128, 0, false);
+    return full ? NSF_TABLE(128, kTcBf16W128, true) : NSF_TABLE(128, 0, true);
   }
+#undef NSF_TABLE
   return hipErrorInvalidValue;
+}
+
+int fields_table_blocks_per_cu(int width, bool bf16, int tc) {
+  // dynamic LDS (two hidden layers) bounds residency: 160 KB per CU
+  const int lds = 2 * (bf16 ? width * width * 2 : width * width * 4);
+  int by_lds = (160 * 1024) / (lds + 1024);
+  if (by_lds < 1) by_lds = 1;
+  // registers: the tangent kernels run one wave per SIMD, the primal ones two
+  const int by_regs = tc > 0 ? 1 : 1;
+  return by_lds < by_regs ? by_lds : by_regs;
+}
+
+__global__ void reset_counters_kernel(int32_t* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, c, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,

@@ -120,7 +120,22 @@ __global__ __launch_bounds__(kThreads) void gn_kernel(const SimDev* __restrict__
       if (col < cnt) {
         const int p = p0 + col;
         rv = -S.dt_d * (double)S.vnew[c * ns + p];
-        if (iter > 0) rv += (double)S.u_gn[c * ns + p] - (double)S.u_n[c * S.n_int + p];
+        if (iter > 0) {
+          if (S.tangent_forms) {
+            // u(z^(k)) - u(z_n) by the trapezoid rule along z^(k) - z_n from the two
+            // Jacobians (error O(|dz|^3)), avoiding the difference of two BF16 values
+            const double* zc = S.z + r;
+            const double* zi = S.z + 2 * r;
+            double du = 0.0;
+            for (int j = 0; j < r; ++j) {
+              const int64_t o = (int64_t)(c * r + j) * ns + p;
+              du += 0.5 * ((double)S.J[o] + (double)S.J2[o]) * (zi[j] - zc[j]);
+            }
+            rv += du;
+          } else {
+            rv += (double)S.u_gn[c * ns + p] - (double)S.u_n[c * S.n_int + p];
+          }
+        }
       }
       R[c][col] = rv;
     }

@@ -1,21 +1,27 @@
 // MLS-MPM transfers of the reduced step (paper Sec. 3.3 on the integration particles,
-// Sec. 5.2).
+// Sec. 5.2), written as a gather so that no float atomics are needed.
 //
 // P2G (Sec. 3.3 step 1 with APIC, plus the node force balance of Sec. 3.2 in MLS form):
-// for every integration particle, x = X + u(z_n), v = (u(z_n) - u(z_{n-1})) / dt and
+// every integration particle has x = X + u(z_n), a velocity v and
 //   A = m_p C - dt V_p (4 / dx^2) tau      (D^-1 = 4 / dx^2 for quadratic B-splines)
-// scatter m_i += w m_p and p_i += w (m_p v + A (x_i - x_p)) over the 27 stencil nodes.
+// and node i receives m_i = sum_p w_ip m_p and p_i = sum_p w_ip (m_p v + A (x_i - x_p)).
+// The grid update (Sec. 3.3 step 2: v_i = p_i / m_i + dt g, sticky walls, moving knife)
+// runs once per node right after its sums, and G2P (Sec. 3.3 step 3) gathers the new node
+// velocities for the sample particles.
 //
-// Grid update (Sec. 3.3 step 2) is fused into the gather: G2P evaluates each stencil
-// node's new velocity v_i = p_i / m_i + dt g, applies the sticky walls and the moving
-// knife, and accumulates w v_i (Sec. 3.3 step 3) for the sample particles. The node
-// value is a pure function of (m_i, p_i, node index, time), so every reader computes
-// the same v_i the separate grid pass would have stored, and no dense grid sweep is
-// needed.
-//
-// The grid is a dense array of float4 (m, p) per node that is zero between steps: after
-// G2P the clean kernel zeroes the stencils the integration particles wrote, so a step
-// touches only the nodes it uses.
+// Kernels of one step:
+//   bin      each integration particle finds its stencil base cell and its bin (a cube
+//            of bin_edge^3 cells), counts itself in the bin and remembers its rank;
+//   scan     one workgroup per simulation: prefix sum of the bin counts, the list of node
+//            blocks (same tiling as the bins) that receive mass, counts reset to zero;
+//   scatter  each particle writes its P2G record (x, m v, A, index) into bin order;
+//   gather   one workgroup per active node block stages the records of the 2 x 2 x 2 bins
+//            whose particles reach it in LDS, sorted by particle index, sums every node's
+//            mass and momentum in that order (deterministic), applies the grid update and
+//            stores the node's new velocity;
+//   g2p      each sample particle sums w_ip v_i over its 27 stencil nodes.
+// A node block only holds values written this step; nodes outside active blocks are never
+// read because every particle's stencil lies in active blocks.
 #include "nsf_dev.h"
 
 namespace nsf {
@@ -52,7 +58,13 @@ __device__ __forceinline__ const int32_t* plan_row(const SimDev& S) {
 
 __device__ __forceinline__ void flag(const SimDev& S, uint32_t bit) { atomicOr(S.flags, bit); }
 
-__global__ __launch_bounds__(kMpmBlock) void p2g_kernel(const SimDev* __restrict__ sims,
+__device__ __forceinline__ void particle_x(const SimDev& S, int p, int gi, float x[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x[c] = S.X[(int64_t)c * S.n_part + gi] + S.u_n[c * S.n_int + p];
+}
+
+// ---- bin ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kMpmBlock) void bin_kernel(const SimDev* __restrict__ sims,
                                                         const BlockWork* __restrict__ work,
                                                         const int32_t* __restrict__ n_work) {
   const int total = *n_work;
@@ -61,67 +73,236 @@ __global__ __launch_bounds__(kMpmBlock) void p2g_kernel(const SimDev* __restrict
     const SimDev& S = sims[wk.sim];
     const int p = wk.p0 + threadIdx.x;
     if (p >= S.n_int) continue;
-    const int n_int = S.n_int;
-    const int gi = plan_row(S)[p];
-    float x[3], v[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float u = S.u_n[c * n_int + p];
-      const float up = S.u_prev[c * n_int + p];
-      x[c] = S.X[(int64_t)c * S.n_part + gi] + u;
-      v[c] = (u - up) / S.dt;
-    }
-    float t6[6], C[9];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) t6[c] = S.tau[c * n_int + p];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) C[c] = S.C[c * n_int + p];
-    // Voigt (xx, yy, zz, yz, xz, xy) -> symmetric tau
-    const float tau[9] = {t6[0], t6[5], t6[4], t6[5], t6[1], t6[3], t6[4], t6[3], t6[2]};
-    float A[9];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) A[e] = S.mp * C[e] - S.stress_k * tau[e];
+    float x[3];
+    particle_x(S, p, plan_row(S)[p], x);
     const Stencil st = make_stencil(x, S.inv_dx, S.grid_n);
-    if (!st.ok) { flag(S, FLAG_DOMAIN); continue; }
-    const float mv[3] = {S.mp * v[0], S.mp * v[1], S.mp * v[2]};
-    const int n = S.grid_n;
+    if (!st.ok) {
+      flag(S, FLAG_DOMAIN);
+      S.pbin[p] = -1;
+      continue;
+    }
+    const int B = S.bin_edge, nbs = S.nbs;
+    const int bin = ((st.base[0] / B) * nbs + st.base[1] / B) * nbs + st.base[2] / B;
+    S.pbin[p] = bin;
+    S.prank[p] = atomicAdd(&S.bin_cnt[bin], 1);
+  }
+}
+
+// ---- scan --------------------------------------------------------------------------
+constexpr int kScanThreads = 1024;
+
+// Exclusive scan of one value per thread over the workgroup; returns the prefix and the
+// workgroup total in *total.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* wave_sums, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const float dx0 = ((float)i - st.f[0]) * S.dx;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const float dx1 = ((float)j - st.f[1]) * S.dx;
-        const float wij = st.w[0][i] * st.w[1][j];
-        const int64_t row = ((int64_t)(st.base[0] + i) * n + (st.base[1] + j)) * n + st.base[2];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const float dx2 = ((float)k - st.f[2]) * S.dx;
-          const float w = wij * st.w[2][k];
-          float* node = reinterpret_cast<float*>(S.grid + row + k);
-          const float px = w * (mv[0] + A[0] * dx0 + A[1] * dx1 + A[2] * dx2);
-          const float py = w * (mv[1] + A[3] * dx0 + A[4] * dx1 + A[5] * dx2);
-          const float pz = w * (mv[2] + A[6] * dx0 + A[7] * dx1 + A[8] * dx2);
-          unsafeAtomicAdd(node + 0, w * S.mp);
-          unsafeAtomicAdd(node + 1, px);
-          unsafeAtomicAdd(node + 2, py);
-          unsafeAtomicAdd(node + 3, pz);
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wave_sums[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+      const int t = wave_sums[w];
+      wave_sums[w] = run;
+      run += t;
+    }
+    wave_sums[kScanThreads / 64] = run;
+  }
+  __syncthreads();
+  const int excl = wave_sums[wave] + incl - v;
+  *total = wave_sums[kScanThreads / 64];
+  __syncthreads();
+  return excl;
+}
+
+__device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
+
+// Counts are staged in (dynamic) LDS with one pad word per 32 so that each thread can walk
+// its contiguous range without bank conflicts; global reads and writes stay coalesced.
+__global__ __launch_bounds__(kScanThreads) void bin_scan_kernel(const SimDev* __restrict__ sims,
+                                                                const int32_t* __restrict__ n_sims) {
+  extern __shared__ int s_cnt[];
+  __shared__ int wave_sums[kScanThreads / 64 + 1];
+  __shared__ uint32_t mark[32768 / 32];
+  const int tid = threadIdx.x;
+  const int total_sims = *n_sims;
+  for (int s = blockIdx.x; s < total_sims; s += gridDim.x) {
+    const SimDev& S = sims[s];
+    int32_t* __restrict__ cnt_g = S.bin_cnt;
+    int32_t* __restrict__ start_g = S.bin_start;
+    int32_t* __restrict__ nonempty = S.nonempty;
+    const int nb = S.n_bins, nbs = S.nbs;
+    for (int i = tid; i < nb; i += kScanThreads) s_cnt[pad32(i)] = cnt_g[i];
+    for (int wd = tid; wd < (nb + 31) / 32; wd += kScanThreads) mark[wd] = 0u;
+    __syncthreads();
+    const int per = (nb + kScanThreads - 1) / kScanThreads;
+    const int lo = min(nb, tid * per), hi = min(nb, lo + per);
+    int local = 0, ne = 0;
+    for (int i = lo; i < hi; ++i) {
+      const int c = s_cnt[pad32(i)];
+      local += c;
+      ne += c > 0;
+    }
+    int all, n_ne;
+    int run = block_exclusive_scan(local, wave_sums, &all);
+    int ne_pos = block_exclusive_scan(ne, wave_sums, &n_ne);
+    for (int i = lo; i < hi; ++i) {
+      const int c = s_cnt[pad32(i)];
+      s_cnt[pad32(i)] = run;
+      run += c;
+      if (c == 0) continue;
+      nonempty[ne_pos++] = i;
+      // node blocks reached by bin i: i + {0, 1}^3
+      const int bx = i / (nbs * nbs), by = (i / nbs) % nbs, bz = i % nbs;
+      for (int d = 0; d < 8; ++d) {
+        const int x = bx + (d >> 2), y = by + ((d >> 1) & 1), z = bz + (d & 1);
+        if (x < nbs && y < nbs && z < nbs) {
+          const int k = (x * nbs + y) * nbs + z;
+          atomicOr(&mark[k >> 5], 1u << (k & 31));
         }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nb; i += kScanThreads) {
+      start_g[i] = s_cnt[pad32(i)];
+      cnt_g[i] = 0;   // counts start from zero next step
+    }
+    if (tid == 0) start_g[nb] = all;
+    // compact the marked node blocks in index order
+    const int nwords = (nb + 31) / 32;
+    const int wper = (nwords + kScanThreads - 1) / kScanThreads;
+    const int wlo = min(nwords, tid * wper), whi = min(nwords, wlo + wper);
+    int cnt = 0;
+    for (int wd = wlo; wd < whi; ++wd) cnt += __popc(mark[wd]);
+    int n_act;
+    int pos = block_exclusive_scan(cnt, wave_sums, &n_act);
+    for (int wd = wlo; wd < whi; ++wd) {
+      uint32_t m = mark[wd];
+      while (m) {
+        const int bit = __ffs(m) - 1;
+        m &= m - 1;
+        S.active[pos++] = wd * 32 + bit;
+      }
+    }
+    if (tid == 0) {
+      S.n_active[0] = n_act;
+      S.n_active[1] = n_ne;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- place -------------------------------------------------------------------------
+__global__ __launch_bounds__(kMpmBlock) void place_kernel(const SimDev* __restrict__ sims,
+                                                          const BlockWork* __restrict__ work,
+                                                          const int32_t* __restrict__ n_work) {
+  const int total = *n_work;
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    const BlockWork wk = work[b];
+    const SimDev& S = sims[wk.sim];
+    const int p = wk.p0 + threadIdx.x;
+    if (p >= S.n_int) continue;
+    const int bin = S.pbin[p];
+    if (bin >= 0) S.sorted[S.bin_start[bin] + S.prank[p]] = p;
+  }
+}
+
+// ---- sort each bin, write records ---------------------------------------------------
+// P2G record of particle p: x, m_p v, A = m_p C - dt V_p (4/dx^2) tau, and p itself.
+__device__ __forceinline__ void write_record(const SimDev& S, int p, float* r) {
+  const int n_int = S.n_int;
+  const int gi = plan_row(S)[p];
+  float x[3], v[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float u = S.u_n[c * n_int + p];
+    const float up = S.u_prev[c * n_int + p];
+    x[c] = S.X[(int64_t)c * S.n_part + gi] + u;
+    v[c] = S.tangent_forms ? up : (u - up) / S.dt;  // u_prev holds v itself in tangent form
+  }
+  float t6[6], C[9];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) t6[c] = S.tau[c * n_int + p];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) C[c] = S.C[c * n_int + p];
+  // Voigt (xx, yy, zz, yz, xz, xy) -> symmetric tau
+  const float tau[9] = {t6[0], t6[5], t6[4], t6[5], t6[1], t6[3], t6[4], t6[3], t6[2]};
+  float A[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) A[e] = S.mp * C[e] - S.stress_k * tau[e];
+  float4* r4 = reinterpret_cast<float4*>(r);
+  r4[0] = make_float4(x[0], x[1], x[2], S.mp * v[0]);
+  r4[1] = make_float4(S.mp * v[1], S.mp * v[2], A[0], A[1]);
+  r4[2] = make_float4(A[2], A[3], A[4], A[5]);
+  r4[3] = make_float4(A[6], A[7], A[8], __int_as_float(p));
+}
+
+// One 64-thread workgroup per non-empty bin: sort the bin's particle indices (in
+// registers up to 64, in LDS up to kSegMax; a larger bin keeps its arrival order) and
+// write the records in that order.
+__global__ __launch_bounds__(64) void bin_sort_kernel(const SimDev* __restrict__ sims,
+                                                      const int32_t* __restrict__ n_sims) {
+  __shared__ int s_buf[kSegMax];
+  const int lane = threadIdx.x;
+  const int total_sims = *n_sims;
+  for (int s = 0; s < total_sims; ++s) {
+    const SimDev& S = sims[s];
+    const int ne = S.n_active[1];
+    for (int k = blockIdx.x; k < ne; k += gridDim.x) {
+      const int b = S.nonempty[k];
+      const int start = S.bin_start[b];
+      const int cnt = S.bin_start[b + 1] - start;
+      int32_t* seg = S.sorted + start;
+      if (cnt <= 64) {
+        int v = lane < cnt ? seg[lane] : 0x7fffffff;
+        for (int kk = 2; kk <= 64; kk <<= 1)
+          for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            const int o = __shfl_xor(v, jj);
+            const bool lower = (lane & jj) == 0, up = (lane & kk) == 0;
+            v = (lower == up) ? min(v, o) : max(v, o);
+          }
+        if (lane < cnt) write_record(S, v, S.rec + (int64_t)(start + lane) * 16);
+      } else if (cnt <= kSegMax) {
+        int p2 = 64;
+        while (p2 < cnt) p2 <<= 1;
+        for (int i = lane; i < p2; i += 64) s_buf[i] = i < cnt ? seg[i] : 0x7fffffff;
+        __syncthreads();
+        for (int kk = 2; kk <= p2; kk <<= 1)
+          for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int i = lane; i < p2; i += 64) {
+              const int l = i ^ jj;
+              if (l > i) {
+                const int a = s_buf[i], c = s_buf[l];
+                if ((a > c) == ((i & kk) == 0)) { s_buf[i] = c; s_buf[l] = a; }
+              }
+            }
+            __syncthreads();
+          }
+        for (int i = lane; i < cnt; i += 64) write_record(S, s_buf[i], S.rec + (int64_t)(start + i) * 16);
+        __syncthreads();
+      } else {
+        for (int i = lane; i < cnt; i += 64) write_record(S, seg[i], S.rec + (int64_t)(start + i) * 16);
       }
     }
   }
 }
 
+// ---- gather + grid update ----------------------------------------------------------
+constexpr int kGatherThreads = 256;   // 4 groups of 64 lanes
+constexpr int kMaxNodesPerLane = 8;   // bin_edge <= 8
+
 // New velocity of node (i, j, k) from its mass and momentum (grid update + boundaries).
-__device__ __forceinline__ void node_velocity(const SimDev& S, float4 g, int i, int j, int k,
-                                              double t_new, float out[3]) {
-  if (!(g.x > 0.f)) { out[0] = out[1] = out[2] = 0.f; return; }
-  out[0] = g.y / g.x + S.dt * S.grav[0];
-  out[1] = g.z / g.x + S.dt * S.grav[1];
-  out[2] = g.w / g.x + S.dt * S.grav[2];
+__device__ __forceinline__ void node_velocity(const SimDev& S, float m, const float pm[3], int i,
+                                              int j, int k, double t_new, float out[3]) {
+  if (!(m > 0.f)) { out[0] = out[1] = out[2] = 0.f; return; }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c] = pm[c] / m + S.dt * S.grav[c];
   const int n = S.grid_n, b = S.wall;
-  if (i < b || j < b || k < b || i >= n - b || j >= n - b || k >= n - b) {
-    out[0] = out[1] = out[2] = 0.f;
-  }
+  if (i < b || j < b || k < b || i >= n - b || j >= n - b || k >= n - b) out[0] = out[1] = out[2] = 0.f;
   if (S.knife_on) {
     const double xi = i * S.dx_d, yi = j * S.dx_d, zi = k * S.dx_d;
     const double dist = S.kn[0] * xi + S.kn[1] * yi + S.kn[2] * zi - S.koff;
@@ -133,6 +314,131 @@ __device__ __forceinline__ void node_velocity(const SimDev& S, float4 g, int i, 
   }
 }
 
+__global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __restrict__ sims,
+                                                                const int32_t* __restrict__ n_sims) {
+  // staged records, structure of arrays
+  __shared__ float s_mv[3][kSegMax];
+  __shared__ float s_A[9][kSegMax];
+  __shared__ float s_w[9][kSegMax];
+  __shared__ float s_f[3][kSegMax];
+  __shared__ int s_base[kSegMax];     // packed base cell (10 bits per axis)
+  __shared__ float s_red[4][64][4];
+  __shared__ int s_seg[9];            // the source bins' record ranges, concatenated
+  __shared__ int s_from[8];
+  const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+  const int total_sims = *n_sims;
+  for (int s = 0; s < total_sims; ++s) {
+    const SimDev& S = sims[s];
+    const int nact = S.n_active[0];
+    const int B = S.bin_edge, nbs = S.nbs, n = S.grid_n;
+    const int nodes = B * B * B;
+    const int npl = (nodes + 63) / 64;   // nodes per lane
+    const double t_new = (double)(*S.step + 1) * S.dt_d;
+    for (int k = blockIdx.x; k < nact; k += gridDim.x) {
+      const int blk = S.active[k];
+      const int bx = blk / (nbs * nbs), by = (blk / nbs) % nbs, bz = blk % nbs;
+      // source bins in a fixed order: the block itself and its lower neighbours
+      if (tid == 0) {
+        int run = 0;
+        for (int d = 0; d < 8; ++d) {
+          const int sx = bx - (d >> 2), sy = by - ((d >> 1) & 1), sz = bz - (d & 1);
+          int c = 0, from = 0;
+          if (sx >= 0 && sy >= 0 && sz >= 0) {
+            const int sb = (sx * nbs + sy) * nbs + sz;
+            from = S.bin_start[sb];
+            c = S.bin_start[sb + 1] - from;
+          }
+          s_seg[d] = run;
+          s_from[d] = from;
+          run += c;
+        }
+        s_seg[8] = run;
+      }
+      __syncthreads();
+      const int total = s_seg[8];
+      float acc[kMaxNodesPerLane][4];
+#pragma unroll
+      for (int q = 0; q < kMaxNodesPerLane; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
+      // records in concatenated order (bin order, each bin sorted by particle index),
+      // staged kSegMax at a time
+      for (int c0 = 0; c0 < total; c0 += kSegMax) {
+        const int cnt = min(kSegMax, total - c0);
+        for (int i = tid; i < cnt; i += kGatherThreads) {
+          const int g = c0 + i;
+          int d = 0;
+          while (g >= s_seg[d + 1]) ++d;
+          const float4* r4 = reinterpret_cast<const float4*>(S.rec + (int64_t)(s_from[d] + g - s_seg[d]) * 16);
+          const float4 a = r4[0], b4 = r4[1], c4 = r4[2], e4 = r4[3];
+          const float x[3] = {a.x, a.y, a.z};
+          const Stencil st = make_stencil(x, S.inv_dx, n);
+          s_mv[0][i] = a.w; s_mv[1][i] = b4.x; s_mv[2][i] = b4.y;
+          s_A[0][i] = b4.z; s_A[1][i] = b4.w; s_A[2][i] = c4.x; s_A[3][i] = c4.y;
+          s_A[4][i] = c4.z; s_A[5][i] = c4.w; s_A[6][i] = e4.x; s_A[7][i] = e4.y;
+          s_A[8][i] = e4.z;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            s_f[c][i] = st.f[c];
+            s_w[3 * c + 0][i] = st.w[c][0];
+            s_w[3 * c + 1][i] = st.w[c][1];
+            s_w[3 * c + 2][i] = st.w[c][2];
+          }
+          s_base[i] = (st.base[0] << 20) | (st.base[1] << 10) | st.base[2];
+        }
+        __syncthreads();
+        // group g adds records g, g + 4, ... of this stage
+#pragma unroll
+        for (int q = 0; q < kMaxNodesPerLane; ++q) {
+          const int node = lane + 64 * q;
+          if (q >= npl || node >= nodes) continue;
+          const int ni = bx * B + node / (B * B), nj = by * B + (node / B) % B, nk = bz * B + node % B;
+          for (int i = grp; i < cnt; i += 4) {
+            const int pb = s_base[i];
+            const int di = ni - (pb >> 20), dj = nj - ((pb >> 10) & 1023), dk = nk - (pb & 1023);
+            if ((unsigned)di > 2u || (unsigned)dj > 2u || (unsigned)dk > 2u) continue;
+            const float w = s_w[di][i] * s_w[3 + dj][i] * s_w[6 + dk][i];
+            const float d0 = ((float)di - s_f[0][i]) * S.dx;
+            const float d1 = ((float)dj - s_f[1][i]) * S.dx;
+            const float d2 = ((float)dk - s_f[2][i]) * S.dx;
+            acc[q][0] += w * S.mp;
+            acc[q][1] += w * (s_mv[0][i] + s_A[0][i] * d0 + s_A[1][i] * d1 + s_A[2][i] * d2);
+            acc[q][2] += w * (s_mv[1][i] + s_A[3][i] * d0 + s_A[4][i] * d1 + s_A[5][i] * d2);
+            acc[q][3] += w * (s_mv[2][i] + s_A[6][i] * d0 + s_A[7][i] * d1 + s_A[8][i] * d2);
+          }
+        }
+        __syncthreads();
+      }
+      // add the four groups in order, grid update, store
+#pragma unroll
+      for (int q = 0; q < kMaxNodesPerLane; ++q) {
+        if (q >= npl) break;
+        const int node = lane + 64 * q;
+        s_red[grp][lane][0] = acc[q][0];
+        s_red[grp][lane][1] = acc[q][1];
+        s_red[grp][lane][2] = acc[q][2];
+        s_red[grp][lane][3] = acc[q][3];
+        __syncthreads();
+        if (grp == 0 && node < nodes) {
+          float m = 0.f, pm[3] = {0.f, 0.f, 0.f};
+          for (int g = 0; g < 4; ++g) {
+            m += s_red[g][lane][0];
+            pm[0] += s_red[g][lane][1];
+            pm[1] += s_red[g][lane][2];
+            pm[2] += s_red[g][lane][3];
+          }
+          const int ni = bx * B + node / (B * B), nj = by * B + (node / B) % B, nk = bz * B + node % B;
+          if (ni < n && nj < n && nk < n) {
+            float v[3];
+            node_velocity(S, m, pm, ni, nj, nk, t_new, v);
+            S.grid[((int64_t)ni * n + nj) * n + nk] = make_float4(v[0], v[1], v[2], m);
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// ---- G2P ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kMpmBlock) void g2p_kernel(const SimDev* __restrict__ sims,
                                                         const BlockWork* __restrict__ work,
                                                         const int32_t* __restrict__ n_work) {
@@ -142,15 +448,11 @@ __global__ __launch_bounds__(kMpmBlock) void g2p_kernel(const SimDev* __restrict
     const SimDev& S = sims[wk.sim];
     const int p = wk.p0 + threadIdx.x;
     if (p >= S.n_samp) continue;
-    const int n_int = S.n_int;
-    const int gi = plan_row(S)[p];
     float x[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) x[c] = S.X[(int64_t)c * S.n_part + gi] + S.u_n[c * n_int + p];
+    particle_x(S, p, plan_row(S)[p], x);
     const Stencil st = make_stencil(x, S.inv_dx, S.grid_n);
     float v[3] = {0.f, 0.f, 0.f};
     if (st.ok) {
-      const double t_new = (double)(*S.step + 1) * S.dt_d;
       const int n = S.grid_n;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -161,57 +463,37 @@ __global__ __launch_bounds__(kMpmBlock) void g2p_kernel(const SimDev* __restrict
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
             const float w = wij * st.w[2][k];
-            float vi[3];
-            node_velocity(S, S.grid[row + k], st.base[0] + i, st.base[1] + j, st.base[2] + k,
-                          t_new, vi);
-            v[0] += w * vi[0];
-            v[1] += w * vi[1];
-            v[2] += w * vi[2];
+            const float4 g = S.grid[row + k];
+            v[0] += w * g.x;
+            v[1] += w * g.y;
+            v[2] += w * g.z;
           }
         }
-    } else {
-      flag(S, FLAG_DOMAIN);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) S.vnew[c * S.n_samp + p] = v[c];
   }
 }
 
-__global__ __launch_bounds__(kMpmBlock) void grid_clean_kernel(const SimDev* __restrict__ sims,
-                                                               const BlockWork* __restrict__ work,
-                                                               const int32_t* __restrict__ n_work) {
-  const int total = *n_work;
-  for (int b = blockIdx.x; b < total; b += gridDim.x) {
-    const BlockWork wk = work[b];
-    const SimDev& S = sims[wk.sim];
-    const int p = wk.p0 + threadIdx.x;
-    if (p >= S.n_int) continue;
-    const int gi = plan_row(S)[p];
-    float x[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      x[c] = S.X[(int64_t)c * S.n_part + gi] + S.u_n[c * S.n_int + p];
-    const Stencil st = make_stencil(x, S.inv_dx, S.grid_n);
-    if (!st.ok) continue;
-    const int n = S.grid_n;
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int64_t row = ((int64_t)(st.base[0] + i) * n + (st.base[1] + j)) * n + st.base[2];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) S.grid[row + k] = z;
-      }
-  }
-}
-
 }  // namespace
 
-hipError_t launch_p2g(const SimDev* sims, const BlockWork* work, const int32_t* n_work, int grid,
+hipError_t launch_p2g(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
+                      const int32_t* n_sims, int grid_particles, int grid_sims, int grid_blocks,
                       hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(p2g_kernel, dim3(grid), dim3(kMpmBlock), 0, s, sims, work, n_work);
+  if (grid_particles <= 0) return hipSuccess;
+  constexpr int scan_lds = (32768 + 32768 / 32) * 4;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)bin_scan_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, scan_lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(bin_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int);
+  hipLaunchKernelGGL(bin_scan_kernel, dim3(grid_sims), dim3(kScanThreads), scan_lds, s, sims, n_sims);
+  hipLaunchKernelGGL(place_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int);
+  hipLaunchKernelGGL(bin_sort_kernel, dim3(grid_blocks), dim3(64), 0, s, sims, n_sims);
+  hipLaunchKernelGGL(gather_kernel, dim3(grid_blocks), dim3(kGatherThreads), 0, s, sims, n_sims);
   return hipGetLastError();
 }
 
@@ -219,13 +501,6 @@ hipError_t launch_g2p(const SimDev* sims, const BlockWork* work, const int32_t* 
                       hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(g2p_kernel, dim3(grid), dim3(kMpmBlock), 0, s, sims, work, n_work);
-  return hipGetLastError();
-}
-
-hipError_t launch_grid_clean(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                             int grid, hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(grid_clean_kernel, dim3(grid), dim3(kMpmBlock), 0, s, sims, work, n_work);
   return hipGetLastError();
 }
 

@@ -46,7 +46,11 @@ struct FieldJob {
   int32_t n;                 // number of points
   int32_t r, d;
   int32_t mode;              // 0: out = field; 1: out = X + field (decode)
-  int32_t pad0;
+  int32_t jvp;               // 1: directional derivative job (see z2)
+  const double* z2;          // jvp: evaluate at (z + z2) / 2 with the one tangent along
+                             // z - z2, and write scale * (tangent output) * jvp_scale
+  float jvp_scale;
+  int32_t pad1;
   float* out; int64_t ldo;   // SoA [d][ldo], already offset to this job's first point
   float* jac; int64_t ldj;   // SoA [3 r][ldj] (row c*r + j), only for d = 3
   float scale[9], shift[9];
@@ -64,7 +68,9 @@ struct FieldTile {
 struct SimDev {
   int32_t r, n_part, n_int, n_samp;
   int32_t plan_steps, grid_n, wall, gn_iters;
-  int32_t knife_on, n_gn_chunks, width, pad0;
+  int32_t knife_on, n_gn_chunks, width;
+  int32_t tangent_forms;             // 1 (BF16): velocity stored directly in u_prev (a JVP)
+                                     // and trapezoid Gauss-Newton residuals from Jacobians
   float dx, inv_dx, dt, mp;          // mp = particle mass rho V_p
   float stress_k;                    // dt V_p 4 / dx^2
   float grav[3];
@@ -88,6 +94,17 @@ struct SimDev {
   uint32_t* flags;
   double* gn_part;                   // [n_gn_chunks][E], E = r(r+1)/2 + r
   uint32_t* gn_count;                // chunks of the current iteration done (zero between launches)
+  // particle binning for the gather-form P2G: bins of bin_edge^3 cells, nbs per axis
+  int32_t bin_edge, nbs, n_bins, pad2;
+  int32_t* bin_cnt;                  // [n_bins] particles per bin (zero between steps)
+  int32_t* bin_start;                // [n_bins + 1] exclusive prefix of bin_cnt
+  int32_t* pbin;                     // [n_int] bin of each integration particle, -1 if off-grid
+  int32_t* prank;                    // [n_int] slot of the particle inside its bin
+  float* rec;                        // [n_int][16] P2G records in bin order
+  int32_t* sorted;                   // [n_int] particle indices grouped by bin
+  int32_t* active;                   // [n_bins] node blocks that receive mass this step
+  int32_t* nonempty;                 // [n_bins] bins holding particles this step
+  int32_t* n_active;                 // [2]: active node blocks, non-empty bins
 };
 
 enum : uint32_t { FLAG_DOMAIN = 1u, FLAG_NONFINITE = 2u, FLAG_SINGULAR = 4u };
@@ -99,19 +116,23 @@ struct BlockWork {
 
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
-                               const FieldTile* tiles, const int32_t* n_tiles, int grid,
-                               hipStream_t s);
+                               const FieldTile* groups, const int32_t* n_groups, int32_t* claim,
+                               int grid, hipStream_t s);
+int fields_table_blocks_per_cu(int width, bool bf16, int tc);
+hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s);   // n <= 64
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
                                hipStream_t s);
 int fields_max_tangents(int width, bool bf16);
 int fields_group_waves(int tc);   // waves (32-point tiles) per workgroup
 
-hipError_t launch_p2g(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                      int grid, hipStream_t s);
+// MPM transfers: bin (per integration particle), scan (per sim), scatter (per integration
+// particle), gather + grid update (per active node block), G2P (per sample particle).
+hipError_t launch_p2g(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
+                      const int32_t* n_sims, int grid_particles, int grid_sims, int grid_blocks,
+                      hipStream_t s);
 hipError_t launch_g2p(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
                       int grid, hipStream_t s);
-hipError_t launch_grid_clean(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                             int grid, hipStream_t s);
+constexpr int kSegMax = 512;   // bin segments up to this size are summed in index order
 hipError_t launch_gn(const SimDev* sims, const BlockWork* work, const int32_t* n_work, int iter,
                      int grid, hipStream_t s);
 

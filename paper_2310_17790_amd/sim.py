@@ -25,6 +25,54 @@ def flatten_mlp(layers: Sequence[Tuple[np.ndarray, np.ndarray]]) -> np.ndarray:
     return np.concatenate(parts)
 
 
+def build_desc(w, precision: str, decode_every_step: bool):
+    """nsf_sim_desc for a workload; returns (desc, host arrays the desc points into)."""
+    keep = []
+
+    def fptr(a):
+        a = np.ascontiguousarray(a, np.float32)
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_float))
+
+    def dptr(a):
+        a = np.ascontiguousarray(a, np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+
+    d = A.nsf_sim_desc()
+    d.r, d.width, d.n_hidden = int(w.r), int(w.width), 5
+    d.precision = A.NSF_BF16 if precision == "bf16" else A.NSF_FP32
+    for f, name in enumerate(("g", "h", "l")):
+        d.weights[f] = fptr(flatten_mlp(w.fields[name]))
+        for c in range(FIELD_OUT[f]):
+            d.out_scale[f][c] = float(w.out_scale[name][c])
+            d.out_shift[f][c] = float(w.out_shift[name][c])
+    d.n_particles = int(w.X.shape[1])
+    d.X = fptr(w.X)
+    d.rho, d.body_volume = float(w.rho), float(w.body_volume)
+    d.grid_n, d.dx, d.dt = int(w.grid_n), float(w.dx), float(w.dt)
+    for c in range(3):
+        d.gravity[c] = float(w.gravity[c])
+    d.wall_nodes = int(w.wall_nodes)
+    k = w.knife
+    d.knife.enabled = 1 if k.enabled else 0
+    for c in range(3):
+        d.knife.normal[c] = float(k.normal[c])
+        d.knife.velocity[c] = float(k.velocity[c])
+    d.knife.offset, d.knife.half_thickness = float(k.offset), float(k.half_thickness)
+    d.knife.edge_z0, d.knife.edge_speed = float(k.edge_z0), float(k.edge_speed)
+    plan = np.ascontiguousarray(w.plan, np.int32)
+    keep.append(plan)
+    d.n_integration, d.n_sample = int(plan.shape[1]), int(w.n_sample)
+    d.plan_steps = int(plan.shape[0])
+    d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
+    d.gn_iters = int(w.gn_iters)
+    d.decode_every_step = 1 if decode_every_step else 0
+    d.z0 = dptr(w.z0)
+    d.z_prev = dptr(w.z_prev) if w.z_prev is not None else None
+    return d, keep
+
+
 def _stream_handle(stream) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -48,49 +96,7 @@ class Sim:
         self.grid_n = int(w.grid_n)
         self.precision = precision
         self.device = device or torch.device("cuda", torch.cuda.current_device())
-        keep = []  # host arrays referenced by the descriptor until create returns
-
-        def fptr(a):
-            a = np.ascontiguousarray(a, np.float32)
-            keep.append(a)
-            return a.ctypes.data_as(C.POINTER(C.c_float))
-
-        def dptr(a):
-            a = np.ascontiguousarray(a, np.float64)
-            keep.append(a)
-            return a.ctypes.data_as(C.POINTER(C.c_double))
-
-        d = A.nsf_sim_desc()
-        d.r, d.width, d.n_hidden = self.r, self.width, 5
-        d.precision = A.NSF_BF16 if precision == "bf16" else A.NSF_FP32
-        for f, name in enumerate(("g", "h", "l")):
-            d.weights[f] = fptr(flatten_mlp(w.fields[name]))
-            for c in range(FIELD_OUT[f]):
-                d.out_scale[f][c] = float(w.out_scale[name][c])
-                d.out_shift[f][c] = float(w.out_shift[name][c])
-        d.n_particles = self.n_particles
-        d.X = fptr(w.X)
-        d.rho, d.body_volume = float(w.rho), float(w.body_volume)
-        d.grid_n, d.dx, d.dt = self.grid_n, float(w.dx), float(w.dt)
-        for c in range(3):
-            d.gravity[c] = float(w.gravity[c])
-        d.wall_nodes = int(w.wall_nodes)
-        k = w.knife
-        d.knife.enabled = 1 if k.enabled else 0
-        for c in range(3):
-            d.knife.normal[c] = float(k.normal[c])
-            d.knife.velocity[c] = float(k.velocity[c])
-        d.knife.offset, d.knife.half_thickness = float(k.offset), float(k.half_thickness)
-        d.knife.edge_z0, d.knife.edge_speed = float(k.edge_z0), float(k.edge_speed)
-        d.n_integration, d.n_sample = self.n_integration, self.n_sample
-        plan = np.ascontiguousarray(w.plan, np.int32)
-        keep.append(plan)
-        d.plan_steps = int(plan.shape[0])
-        d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
-        d.gn_iters = int(w.gn_iters)
-        d.decode_every_step = 1 if decode_every_step else 0
-        d.z0 = dptr(w.z0)
-        d.z_prev = dptr(w.z_prev) if w.z_prev is not None else None
+        d, keep = build_desc(w, precision, decode_every_step)
         nbytes = A.nsf_sim_bytes(d)
         if nbytes == 0:
             raise A.NsfError(A.NSF_EINVAL, A.nsf_last_error())
@@ -101,6 +107,16 @@ class Sim:
         self.arena = self._raw[self._off:self._off + nbytes]
         self.handle = A.nsf_create_sim(d, self.arena.data_ptr(), nbytes, _stream_handle(stream))
         del keep
+
+    @staticmethod
+    def bytes_for(w, precision: str = "fp32", decode_every_step: bool = True) -> int:
+        """Device bytes a sim of this workload needs (nsf_sim_bytes), without creating it."""
+        d, keep = build_desc(w, precision, decode_every_step)
+        n = A.nsf_sim_bytes(d)
+        del keep
+        if n == 0:
+            raise A.NsfError(A.NSF_EINVAL, A.nsf_last_error())
+        return n + 256
 
     # ---- stepping ------------------------------------------------------------------
     def step(self, n: int = 1, stream: Optional[torch.cuda.Stream] = None) -> None:
