@@ -164,6 +164,21 @@ __device__ __forceinline__ float output_dot(const float* w6p, int o, int h, cons
   return s + __shfl_xor(s, 32);
 }
 
+// Training: store the pre-activations of one layer, point-major saved[layer][p][W]. The
+// 16 registers of M-block mb hold neurons 32 mb + 8 q + 4 h + (0..3), q = 0..3.
+template <int W, int T>
+__device__ __forceinline__ void save_preact(const FieldJob& jb, const f32x16 (&acc)[T][W / 32],
+                                            int layer, int p, bool valid, int h) {
+  if (jb.saved == nullptr || !valid) return;
+  float* row = jb.saved + ((int64_t)layer * jb.n + p) * W;
+#pragma unroll
+  for (int mb = 0; mb < W / 32; ++mb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<f32x4*>(row + 32 * mb + 8 * q + 4 * h) =
+          f32x4{acc[0][mb][4 * q], acc[0][mb][4 * q + 1], acc[0][mb][4 * q + 2], acc[0][mb][4 * q + 3]};
+}
+
 // Bytes of one packed hidden layer and of one LDS DMA instruction per wave (64 lanes x 16 B).
 template <int W, bool BF>
 struct HiddenLayer {
@@ -236,7 +251,9 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0, N
     if (k == 0) b0 = X0;
     else if (k == 1) b0 = X1;
     else if (k == 2) b0 = X2;
-    else if (k < 3 + r) {
+    else if (k < 3 + r && jb.zrows != nullptr) {
+      b0 = jb.zrows[(int64_t)(valid ? p : jb.n - 1) * r + (k - 3)];
+    } else if (k < 3 + r) {
       const double zk = jb.z[k - 3];
       if (jvp) {
         const double z2k = jb.z2[k - 3];
@@ -256,6 +273,7 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0, N
     }
   }
 
+  if constexpr (NT == 0) save_preact<W, T>(jb, acc, 0, p, valid, h);
   float H[T][KH];
   if constexpr (!BF) {
     activate_f32<W, T>(acc, H, nt);
@@ -272,9 +290,11 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0, N
     init_hidden<W, T>(acc, jb.w.bhp + k * W, h);
     if constexpr (!BF) {
       hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(cur), lane, nt);
+      if constexpr (NT == 0) save_preact<W, T>(jb, acc, k + 1, p, valid, h);
       activate_f32<W, T>(acc, H, nt);
     } else {
       hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(cur), lane, nt);
+      if constexpr (NT == 0) save_preact<W, T>(jb, acc, k + 1, p, valid, h);
       activate_bf16<W, T>(acc, Hb, nt);
     }
   }
@@ -284,6 +304,7 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0, N
   init_hidden<W, T>(acc, jb.w.bhp + 3 * W, h);
   if constexpr (!BF) hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(lds + LB), lane, nt);
   else hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(lds + LB), lane, nt);
+  if constexpr (NT == 0) save_preact<W, T>(jb, acc, 4, p, valid, h);
   activate_f32<W, T>(acc, H, nt);
 
   const int d = jb.d;

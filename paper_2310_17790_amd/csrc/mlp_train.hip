@@ -1,28 +1,421 @@
-// Field fitting entry points (forward with saved activations, hand-written backward).
+// Field fitting: forward with saved pre-activations and a hand-written backward of one
+// field MLP (weights and per-point latents), for minimising squared error against
+// snapshots (paper Sec. 4.5; supplementary "Training Details").
+//
+// Network: a_1 = W_1 [X; z] + b_1, h_k = ELU(a_k), a_{k+1} = W_{k+1} h_k + b_{k+1}
+// (k = 1..4), out = W_6 h_5 + b_6. Given dout = dLoss/dout per point:
+//   delta_6 = dout,  delta_k = (W_{k+1}^T delta_{k+1}) * ELU'(a_k)   (k = 5 .. 1)
+//   dW_k += sum_p delta_k h_{k-1}^T, db_k += sum_p delta_k          (h_0 = [X; z])
+//   dz = W_1[:, 3:]^T delta_1.
+//
+// Kernels. The forward is the field kernel of the latent step (per-point latents, raw
+// output, pre-activations stored point-major). The backward-data kernel carries 32 points
+// per wave through the five W^T products on MFMA (the same accumulator-layout chaining as
+// the forward, with the transposed weights packed on the device) and computes dz on the
+// VALU. The weight gradients are reductions over points: each workgroup sums a chunk of
+// points for one layer into a partial, and the partials are added in chunk order
+// (deterministic) into dW.
 #include <hip/hip_runtime.h>
 
 #include "nsf.h"
 #include "nsf_dev.h"
 #include "pack.h"
 
+namespace nsf {
+namespace {
+
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int acc_n(int mb, int i, int h) { return 32 * mb + 8 * (i >> 2) + 4 * h + (i & 3); }
+
+// ---- device packing (same orders as pack.cpp, plus transposed hidden layers) --------
+struct Packed {
+  float* w1p; float* whp; uint16_t* whb; float* bhp; float* w6p; float* b6; float* whtp;
+};
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ void pack_kernel(const float* __restrict__ master, int r, int W, int d, Packed P) {
+  const int in1 = 3 + r, MB = W / 32, K1s = (r + 5) / 2;
+  const float* W1 = master;
+  const float* b1 = W1 + (size_t)W * in1;
+  const float* hid = b1 + W;   // W2 b2 W3 b3 W4 b4 W5 b5
+  const float* W6 = hid + 4 * ((size_t)W * W + W);
+  const float* b6 = W6 + (size_t)d * W;
+  const int64_t n1 = (int64_t)MB * K1s * 64, nh = (int64_t)4 * W * W, nb = 4 * W, n6 = (int64_t)d * W;
+  const int64_t total = n1 + 3 * nh + nb + n6 + d;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t t = e;
+    if (t < n1) {
+      const int l = t % 64, s2 = (t / 64) % K1s, mb = t / (64 * K1s);
+      const int m = 32 * mb + (l & 31), k = 2 * s2 + (l >> 5);
+      P.w1p[t] = k < in1 ? W1[(size_t)m * in1 + k] : (k == in1 ? b1[m] : 0.f);
+      continue;
+    }
+    t -= n1;
+    if (t < nh) {   // FP32 forward: [4][MB][W/8][64][4]
+      const int j = t % 4, l = (t / 4) % 64, sg = (t / 256) % (W / 8), mb = (t / (256 * (W / 8))) % MB;
+      const int kk = t / ((int64_t)W * W);
+      const int s = 4 * sg + j, m = 32 * mb + (l & 31), nn = acc_n(s / 16, s % 16, l >> 5);
+      P.whp[t] = hid[kk * ((size_t)W * W + W) + (size_t)m * W + nn];
+      continue;
+    }
+    t -= nh;
+    if (t < nh) {   // BF16 forward: [4][MB][W/16][64][8]
+      const int j = t % 8, l = (t / 8) % 64, s = (t / 512) % (W / 16), mb = (t / (512 * (W / 16))) % MB;
+      const int kk = t / ((int64_t)W * W);
+      const int m = 32 * mb + (l & 31), nn = acc_n(s / 2, 8 * (s % 2) + j, l >> 5);
+      P.whb[t] = to_bf16(hid[kk * ((size_t)W * W + W) + (size_t)m * W + nn]);
+      continue;
+    }
+    t -= nh;
+    if (t < nh) {   // FP32 transposed (backward): A[m][s] = W[nn(s)][m]
+      const int j = t % 4, l = (t / 4) % 64, sg = (t / 256) % (W / 8), mb = (t / (256 * (W / 8))) % MB;
+      const int kk = t / ((int64_t)W * W);
+      const int s = 4 * sg + j, m = 32 * mb + (l & 31), nn = acc_n(s / 16, s % 16, l >> 5);
+      P.whtp[t] = hid[kk * ((size_t)W * W + W) + (size_t)nn * W + m];
+      continue;
+    }
+    t -= nh;
+    if (t < nb) {
+      const int s = t % (W / 2), h = (t / (W / 2)) % 2, kk = t / W;
+      P.bhp[t] = hid[kk * ((size_t)W * W + W) + (size_t)W * W + acc_n(s / 16, s % 16, h)];
+      continue;
+    }
+    t -= nb;
+    if (t < n6) {
+      const int s = t % (W / 2), h = (t / (W / 2)) % 2, o = t / W;
+      P.w6p[t] = W6[(size_t)o * W + acc_n(s / 16, s % 16, h)];
+      continue;
+    }
+    t -= n6;
+    P.b6[t] = b6[t];
+  }
+}
+
+__device__ __forceinline__ float elu_prime(float a) { return a > 0.f ? 1.f : __expf(a); }
+__device__ __forceinline__ float elu(float a) { return a > 0.f ? a : __expf(a) - 1.f; }
+
+// ---- backward through the network, 32 points per wave --------------------------------
+template <int W>
+__global__ __launch_bounds__(256) void backward_data_kernel(const float* __restrict__ master,
+                                                            const float* __restrict__ whtp,
+                                                            const float* __restrict__ w6p,
+                                                            const float* __restrict__ saved,
+                                                            const float* __restrict__ dout,
+                                                            float* __restrict__ delta,
+                                                            float* __restrict__ dz,
+                                                            int n, int r, int d) {
+  constexpr int MB = W / 32, KH = W / 2;
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  const int in1 = 3 + r;
+  for (int t = wave; t * 32 < n; t += nw) {
+    const int p = t * 32 + (lane & 31);
+    const bool valid = p < n;
+    const int pc = valid ? p : n - 1;
+    float d6[9];
+#pragma unroll
+    for (int o = 0; o < 9; ++o) d6[o] = (o < d && valid) ? dout[(int64_t)o * n + p] : 0.f;
+    // delta_5 = (W6^T delta_6) * ELU'(a_5), in accumulator order
+    float D[KH];
+    const float* a5 = saved + ((int64_t)4 * n + pc) * W;
+#pragma unroll
+    for (int s = 0; s < KH; ++s) {
+      float g = 0.f;
+#pragma unroll
+      for (int o = 0; o < 9; ++o)
+        if (o < d) g += w6p[(o * 2 + h) * KH + s] * d6[o];
+      D[s] = g * elu_prime(a5[acc_n(s / 16, s % 16, h)]);
+    }
+    for (int L = 4; L >= 0; --L) {
+      // store delta_{L+1} point-major
+      if (valid) {
+        float* row = delta + ((int64_t)L * n + p) * W;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<f32x4*>(row + 32 * mb + 8 * q + 4 * h) =
+                f32x4{D[16 * mb + 4 * q], D[16 * mb + 4 * q + 1], D[16 * mb + 4 * q + 2], D[16 * mb + 4 * q + 3]};
+      }
+      if (L == 0) break;
+      // g_L = W_{L+1}^T delta_{L+1} on MFMA (hidden pack L - 1 maps h_L -> a_{L+1})
+      f32x16_t acc[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x16_t{};
+      const f32x4* A = reinterpret_cast<const f32x4*>(whtp + (size_t)(L - 1) * W * W);
+#pragma unroll
+      for (int sg = 0; sg < W / 8; ++sg) {
+        f32x4 a4[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) a4[mb] = A[(mb * (W / 8) + sg) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+            acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[mb][j], D[4 * sg + j], acc[mb], 0, 0, 0);
+      }
+      const float* aL = saved + ((int64_t)(L - 1) * n + pc) * W;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) D[16 * mb + i] = acc[mb][i] * elu_prime(aL[acc_n(mb, i, h)]);
+    }
+    // dz_j = sum_n W1[n][3 + j] delta_1[n]
+    for (int j = 0; j < r; ++j) {
+      float s = 0.f;
+#pragma unroll
+      for (int s_ = 0; s_ < KH; ++s_) s += master[(size_t)acc_n(s_ / 16, s_ % 16, h) * in1 + 3 + j] * D[s_];
+      s += __shfl_xor(s, 32);
+      if (valid && h == (j & 1) && dz != nullptr) dz[(int64_t)p * r + j] = s;
+    }
+  }
+}
+
+// ---- weight gradients: C[m][j] = sum_p A(p, m) B(p, j) over a chunk of points ---------
+// A(p, m): delta rows (point-major [n][W]) or dout (SoA [d][n]) for the output layer.
+// B(p, j): ELU of saved pre-activations (point-major), or the layer-1 input [X; z], with
+// a last column equal to 1 (bias gradient).
+constexpr int kChunk = 1024;   // points per workgroup
+constexpr int kSub = 32;       // points staged per pass
+
+struct GradLayer {
+  const float* A; int a_soa;       // a_soa: A is [M][n] (dout), else [n][lda]
+  int lda;
+  const float* Bsaved;             // point-major pre-activations [n][W] -> ELU
+  const float* X; const float* zrows; int r;   // layer-1 input when Bsaved == NULL
+  int M, N;                        // N includes the bias column
+  float* partial;                  // [n_chunks][M][N]
+};
+
+__global__ __launch_bounds__(256) void grad_partial_kernel(GradLayer g, int n, int W) {
+  __shared__ float sA[kSub][129];
+  __shared__ float sB[kSub][130];
+  const int chunk = blockIdx.x;
+  const int p0 = chunk * kChunk, p1 = min(n, p0 + kChunk);
+  const int tid = threadIdx.x;
+  const int tiles_n = (g.N + 7) / 8, tiles = ((g.M + 7) / 8) * tiles_n;
+  float acc[2][8][8];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc[u][a][b] = 0.f;
+  for (int ps = p0; ps < p1; ps += kSub) {
+    const int cnt = min(kSub, p1 - ps);
+    for (int e = tid; e < kSub * g.M; e += 256) {
+      const int pt = e / g.M, m = e % g.M;
+      float v = 0.f;
+      if (pt < cnt) v = g.a_soa ? g.A[(int64_t)m * n + ps + pt] : g.A[(int64_t)(ps + pt) * g.lda + m];
+      sA[pt][m] = v;
+    }
+    for (int e = tid; e < kSub * g.N; e += 256) {
+      const int pt = e / g.N, j = e % g.N;
+      float v = 0.f;
+      if (pt < cnt) {
+        const int p = ps + pt;
+        if (j == g.N - 1) v = 1.f;
+        else if (g.Bsaved) v = elu(g.Bsaved[(int64_t)p * W + j]);
+        else if (j < 3) v = g.X[(int64_t)j * n + p];
+        else v = g.zrows[(int64_t)p * g.r + (j - 3)];
+      }
+      sB[pt][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int tile = tid + 256 * u;
+      if (tile >= tiles) continue;
+      const int m0 = (tile / tiles_n) * 8, j0 = (tile % tiles_n) * 8;
+      for (int pt = 0; pt < cnt; ++pt) {
+        float a[8], b[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a[q] = m0 + q < g.M ? sA[pt][m0 + q] : 0.f;
+          b[q] = j0 + q < g.N ? sB[pt][j0 + q] : 0.f;
+        }
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+#pragma unroll
+          for (int y = 0; y < 8; ++y) acc[u][x][y] += a[x] * b[y];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int tile = tid + 256 * u;
+    if (tile >= tiles) continue;
+    const int m0 = (tile / tiles_n) * 8, j0 = (tile % tiles_n) * 8;
+    float* out = g.partial + (int64_t)chunk * g.M * g.N;
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+      for (int y = 0; y < 8; ++y)
+        if (m0 + x < g.M && j0 + y < g.N) out[(m0 + x) * g.N + j0 + y] = acc[u][x][y];
+  }
+}
+
+// dW[m][j] += sum over chunks (in order); column N-1 goes to the bias db[m].
+__global__ void grad_reduce_kernel(const float* __restrict__ partial, int n_chunks, int M, int N,
+                                   float* __restrict__ dW, float* __restrict__ db) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  float s = 0.f;
+  for (int c = 0; c < n_chunks; ++c) s += partial[(int64_t)c * M * N + e];
+  const int m = e / N, j = e % N;
+  if (j == N - 1) db[m] += s;
+  else dW[(int64_t)m * (N - 1) + j] += s;
+}
+
+struct TrainWs {
+  Packed pk;
+  float* delta;     // [5][n][W]
+  float* partial;   // [n_chunks][max M][max N]
+  size_t bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+TrainWs carve(char* base, int r, int W, int d, int64_t n, bool backward) {
+  TrainWs w{};
+  const PackSizes ps = pack_sizes(r, W, d);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { char* p = base ? base + off : nullptr; off += align256(bytes); return p; };
+  w.pk.w1p = (float*)take(ps.w1p * 4);
+  w.pk.whp = (float*)take(ps.whp * 4);
+  w.pk.whb = (uint16_t*)take(ps.whb * 2);
+  w.pk.bhp = (float*)take(ps.bhp * 4);
+  w.pk.w6p = (float*)take(ps.w6p * 4);
+  w.pk.b6 = (float*)take(ps.b6 * 4);
+  w.pk.whtp = (float*)take(ps.whp * 4);
+  if (backward) {
+    w.delta = (float*)take((size_t)5 * n * W * 4);
+    const int64_t chunks = (n + kChunk - 1) / kChunk;
+    w.partial = (float*)take((size_t)chunks * W * (W + 1) * 4);
+  }
+  w.bytes = off;
+  return w;
+}
+
+thread_local char g_train_err[256];
+
+nsf_status check_mlp(const nsf_mlp* m, int64_t n) {
+  if (!m || !m->weights) return NSF_EINVAL;
+  if (m->width != 64 && m->width != 128) return NSF_EINVAL;
+  if (m->r < 1 || m->r > kMaxR || m->d < 1 || m->d > 9) return NSF_EINVAL;
+  if (n < 1 || n > (int64_t)INT32_MAX / 8) return NSF_EINVAL;
+  return NSF_OK;
+}
+
+}  // namespace
+}  // namespace nsf
+
+using namespace nsf;
+
 extern "C" {
 
-size_t nsf_mlp_param_count(int32_t r, int32_t width, int32_t d) {
-  return nsf::mlp_param_count(r, width, d);
-}
+size_t nsf_mlp_param_count(int32_t r, int32_t width, int32_t d) { return mlp_param_count(r, width, d); }
 
 size_t nsf_mlp_saved_floats(int32_t width, int64_t n) { return (size_t)5 * width * n; }
 
-size_t nsf_mlp_workspace_bytes(const nsf_mlp*, int64_t) { return 0; }
-
-nsf_status nsf_mlp_forward(const nsf_mlp*, const float*, const float*, int64_t, float*, float*,
-                           void*, size_t, void*) {
-  return NSF_EINVAL;
+size_t nsf_mlp_workspace_bytes(const nsf_mlp* m, int64_t n) {
+  if (check_mlp(m, n) != NSF_OK) return 0;
+  return carve(nullptr, m->r, m->width, m->d, n, true).bytes;
 }
 
-nsf_status nsf_mlp_backward(const nsf_mlp*, const float*, const float*, int64_t, const float*,
-                            const float*, float*, float*, void*, size_t, void*) {
-  return NSF_EINVAL;
+nsf_status nsf_mlp_forward(const nsf_mlp* m, const float* X, const float* z_rows, int64_t n,
+                           float* out, float* saved, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  if (check_mlp(m, n) != NSF_OK || !X || !z_rows || !out || !workspace) return NSF_EINVAL;
+  const TrainWs ws = carve(static_cast<char*>(workspace), m->r, m->width, m->d, n, false);
+  if (workspace_bytes < ws.bytes) return NSF_ENOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s, m->weights, m->r, m->width, m->d, ws.pk);
+  if (hipGetLastError() != hipSuccess) return NSF_EHIP;
+  FieldJob j{};
+  j.w.w1p = ws.pk.w1p;
+  j.w.whp = ws.pk.whp;
+  j.w.whb = reinterpret_cast<const bf16x8*>(ws.pk.whb);
+  j.w.bhp = ws.pk.bhp;
+  j.w.w6p = ws.pk.w6p;
+  j.w.b6 = ws.pk.b6;
+  j.X = X;
+  j.ldx = n;
+  j.zrows = z_rows;
+  j.saved = saved;
+  j.n = (int)n;
+  j.r = m->r;
+  j.d = m->d;
+  j.out = out;
+  j.ldo = n;
+  for (int c = 0; c < 9; ++c) { j.scale[c] = 1.f; j.shift[c] = 0.f; }
+  if (launch_fields_dense(m->width, m->precision == NSF_BF16, j, (int)n, s) != hipSuccess) return NSF_EHIP;
+  return NSF_OK;
+}
+
+nsf_status nsf_mlp_backward(const nsf_mlp* m, const float* X, const float* z_rows, int64_t n,
+                            const float* saved, const float* dout, float* dW, float* dz,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  if (check_mlp(m, n) != NSF_OK || !X || !z_rows || !saved || !dout || !dW || !workspace)
+    return NSF_EINVAL;
+  const int r = m->r, W = m->width, d = m->d;
+  const TrainWs ws = carve(static_cast<char*>(workspace), r, W, d, n, true);
+  if (workspace_bytes < ws.bytes) return NSF_ENOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s, m->weights, r, W, d, ws.pk);
+  const int waves = (int)((n + 31) / 32);
+  const int grid = (waves + 3) / 4;
+  if (W == 64)
+    hipLaunchKernelGGL(backward_data_kernel<64>, dim3(grid), dim3(256), 0, s, m->weights, ws.pk.whtp,
+                       ws.pk.w6p, saved, dout, ws.delta, dz, (int)n, r, d);
+  else
+    hipLaunchKernelGGL(backward_data_kernel<128>, dim3(grid), dim3(256), 0, s, m->weights, ws.pk.whtp,
+                       ws.pk.w6p, saved, dout, ws.delta, dz, (int)n, r, d);
+  if (hipGetLastError() != hipSuccess) return NSF_EHIP;
+  // parameter offsets in the master layout
+  const size_t in1 = 3 + r;
+  float* gW1 = dW;
+  float* gb1 = gW1 + (size_t)W * in1;
+  float* gh = gb1 + W;
+  float* gW6 = gh + 4 * ((size_t)W * W + W);
+  float* gb6 = gW6 + (size_t)d * W;
+  const int chunks = (int)((n + kChunk - 1) / kChunk);
+  for (int layer = 1; layer <= 6; ++layer) {
+    GradLayer g{};
+    g.partial = ws.partial;
+    g.r = r;
+    float *tW, *tb;
+    if (layer == 6) {
+      g.A = dout; g.a_soa = 1; g.lda = 0; g.M = d;
+      g.Bsaved = saved + (size_t)4 * n * W; g.N = W + 1;
+      tW = gW6; tb = gb6;
+    } else {
+      g.A = ws.delta + (size_t)(layer - 1) * n * W; g.a_soa = 0; g.lda = W; g.M = W;
+      if (layer == 1) {
+        g.Bsaved = nullptr; g.X = X; g.zrows = z_rows; g.N = (int)in1 + 1;
+        tW = gW1; tb = gb1;
+      } else {
+        g.Bsaved = saved + (size_t)(layer - 2) * n * W; g.N = W + 1;
+        tW = gh + (size_t)(layer - 2) * ((size_t)W * W + W);
+        tb = tW + (size_t)W * W;
+      }
+    }
+    hipLaunchKernelGGL(grad_partial_kernel, dim3(chunks), dim3(256), 0, s, g, (int)n, W);
+    const int e = g.M * g.N;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((e + 255) / 256), dim3(256), 0, s, ws.partial, chunks,
+                       g.M, g.N, tW, tb);
+    if (hipGetLastError() != hipSuccess) return NSF_EHIP;
+  }
+  return NSF_OK;
 }
 
 }  // extern "C"

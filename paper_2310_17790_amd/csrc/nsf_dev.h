@@ -51,6 +51,8 @@ struct FieldJob {
                              // z - z2, and write scale * (tangent output) * jvp_scale
   float jvp_scale;
   int32_t pad1;
+  const float* zrows;        // training: per-point latents [n][r] instead of z (NULL in the step)
+  float* saved;              // training: pre-activations of layers 1..5, [5][n][W] (or NULL)
   float* out; int64_t ldo;   // SoA [d][ldo], already offset to this job's first point
   float* jac; int64_t ldj;   // SoA [3 r][ldj] (row c*r + j), only for d = 3
   float scale[9], shift[9];

@@ -1,0 +1,65 @@
+"""Field fitting with the hand-written HIP backward (torch.autograd.Function).
+
+FieldFn.apply(X, z_rows, weights, width, d, precision) evaluates one field MLP at the
+points X (n, 3) with per-point latents z_rows (n, r) and flat weights (layout of
+nsf_sim_desc.weights) and returns (n, d). Its backward calls nsf_mlp_backward, which
+returns dLoss/dweights (same flat layout) and dLoss/dz_rows; X gets no gradient.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _abi as A
+
+
+def _mlp(weights: torch.Tensor, r: int, width: int, d: int, precision: str) -> A.nsf_mlp:
+    m = A.nsf_mlp()
+    m.r, m.width, m.d = r, width, d
+    m.precision = A.NSF_BF16 if precision == "bf16" else A.NSF_FP32
+    m.weights = weights.data_ptr()
+    return m
+
+
+def _stream() -> int:
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+class FieldFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, X, z_rows, weights, width: int, d: int, precision: str = "fp32"):
+        n, r = z_rows.shape
+        assert X.shape == (n, 3) and X.dtype == torch.float32 and z_rows.dtype == torch.float32
+        assert weights.numel() == A.lib().nsf_mlp_param_count(r, width, d)
+        L = A.lib()
+        Xs = X.t().contiguous()
+        zr = z_rows.contiguous()
+        w = weights.contiguous()
+        m = _mlp(w, r, width, d, precision)
+        out = torch.empty((d, n), dtype=torch.float32, device=X.device)
+        saved = torch.empty(L.nsf_mlp_saved_floats(width, n), dtype=torch.float32, device=X.device)
+        ws_bytes = L.nsf_mlp_workspace_bytes(C.byref(m), n)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=X.device)
+        A.check(L.nsf_mlp_forward(C.byref(m), Xs.data_ptr(), zr.data_ptr(), n, out.data_ptr(),
+                                  saved.data_ptr(), ws.data_ptr(), ws_bytes, _stream()))
+        ctx.save_for_backward(Xs, zr, w, saved)
+        ctx.cfg = (width, d, precision)
+        return out.t()
+
+    @staticmethod
+    def backward(ctx, gout):
+        Xs, zr, w, saved = ctx.saved_tensors
+        width, d, precision = ctx.cfg
+        n, r = zr.shape
+        L = A.lib()
+        m = _mlp(w, r, width, d, precision)
+        dout = gout.t().contiguous().float()
+        dW = torch.zeros_like(w)
+        dz = torch.empty_like(zr)
+        ws_bytes = L.nsf_mlp_workspace_bytes(C.byref(m), n)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=w.device)
+        A.check(L.nsf_mlp_backward(C.byref(m), Xs.data_ptr(), zr.data_ptr(), n, saved.data_ptr(),
+                                   dout.data_ptr(), dW.data_ptr(), dz.data_ptr(), ws.data_ptr(),
+                                   ws_bytes, _stream()))
+        return None, dz, dW, None, None, None

@@ -1,0 +1,133 @@
+"""The hand-written field-MLP backward (nsf_mlp_forward / nsf_mlp_backward through
+FieldFn) against finite differences of the FP64 oracle and against torch autograd in FP64.
+
+Loss L = sum_{p, o} c_{p,o} f_o(X_p, z_p) with fixed random c, on 64 points (the
+finite-difference check of the fitting configuration). FP32 kernels: gradients agree with
+central differences of the FP64 oracle (step 1e-6 relative) to 1e-4 of each parameter
+block's largest gradient, and with FP64 autograd to 2e-5. BF16 hidden layers: 5e-2.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import fields as F
+from paper_2310_17790_amd.sim import flatten_mlp
+from paper_2310_17790_amd.train import FieldFn
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(r=12, width=128, d=3, n=64, seed=0):
+    fl = synth.make_fields(seed, r, width, bias_scale=0.1)
+    layers = fl[{3: "g", 6: "h", 9: "l"}[d]]
+    X = synth.box_points(seed + 1, n, (0.3, 0.3, 0.3), (0.7, 0.7, 0.7)).T.copy()   # (n, 3)
+    Z = np.random.default_rng(seed + 2).normal(0, 0.3, size=(n, r)).astype(np.float32)
+    c = np.random.default_rng(seed + 3).normal(size=(n, d))
+    return layers, X, Z, c
+
+
+def _oracle_loss(layers, X, Z, c):
+    out = np.stack([F.mlp(layers, F.network_input(X[p:p + 1], Z[p]))[0] for p in range(X.shape[0])])
+    return float((out * c).sum())
+
+
+def _gpu_grads(layers, X, Z, c, width, d, precision):
+    w = torch.from_numpy(flatten_mlp(layers)).cuda().requires_grad_(True)
+    Xt = torch.from_numpy(X.astype(np.float32)).cuda()
+    Zt = torch.from_numpy(Z).cuda().requires_grad_(True)
+    out = FieldFn.apply(Xt, Zt, w, width, d, precision)
+    loss = (out.double() * torch.from_numpy(c).cuda()).sum()
+    loss.backward()
+    return out.detach().cpu().numpy(), w.grad.cpu().numpy(), Zt.grad.cpu().numpy()
+
+
+def _blocks(r, width, d):
+    """(name, start, size) of each parameter block in the flat layout."""
+    sizes = [("W1", width * (3 + r)), ("b1", width)]
+    for k in range(2, 6):
+        sizes += [(f"W{k}", width * width), (f"b{k}", width)]
+    sizes += [("W6", d * width), ("b6", d)]
+    out, o = [], 0
+    for name, s in sizes:
+        out.append((name, o, s))
+        o += s
+    return out
+
+
+def _torch_grads(layers, X, Z, c):
+    Ws = [torch.tensor(W, dtype=torch.float64, requires_grad=True) for W, _ in layers]
+    bs = [torch.tensor(b, dtype=torch.float64, requires_grad=True) for _, b in layers]
+    Zt = torch.tensor(Z, dtype=torch.float64, requires_grad=True)
+    h = torch.cat([torch.tensor(X, dtype=torch.float64), Zt], 1)
+    for k in range(6):
+        h = torch.nn.functional.linear(h, Ws[k], bs[k])
+        if k < 5:
+            h = torch.nn.functional.elu(h)
+    (h * torch.tensor(c)).sum().backward()
+    flat = np.concatenate([np.concatenate([W.grad.numpy().ravel(), b.grad.numpy().ravel()])
+                           for W, b in zip(Ws, bs)])
+    return h.detach().numpy(), flat, Zt.grad.numpy()
+
+
+@pytest.mark.parametrize("d", [3, 9])
+def test_backward_matches_fp64_autograd(d):
+    r, width = 12, 128
+    layers, X, Z, c = _problem(r, width, d, n=200)
+    out, gW, gZ = _gpu_grads(layers, X, Z, c, width, d, "fp32")
+    ref_out, rW, rZ = _torch_grads(layers, X, Z, c)
+    assert np.abs(out - ref_out).max() <= 2e-5 * np.abs(ref_out).max()
+    for name, o, s in _blocks(r, width, d):
+        err = np.abs(gW[o:o + s] - rW[o:o + s]).max() / np.abs(rW[o:o + s]).max()
+        assert err < 2e-5, (name, err)
+    assert np.abs(gZ - rZ).max() <= 2e-5 * np.abs(rZ).max()
+
+
+def test_backward_matches_fp64_finite_differences():
+    """Central differences of the oracle's FP64 loss on 64 points, for 8 entries of every
+    parameter block and every latent of 4 points."""
+    r, width, d = 12, 128, 3
+    layers, X, Z, c = _problem(r, width, d, n=64)
+    _, gW, gZ = _gpu_grads(layers, X, Z, c, width, d, "fp32")
+    flat = np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers]).astype(np.float64)
+    shapes = [(W.shape, b.shape) for W, b in layers]
+
+    def unflat(v):
+        out, o = [], 0
+        for (ws, bs) in shapes:
+            nw, nb = int(np.prod(ws)), int(np.prod(bs))
+            out.append((v[o:o + nw].reshape(ws), v[o + nw:o + nw + nb]))
+            o += nw + nb
+        return out
+
+    rng = np.random.default_rng(7)
+    for name, o, s in _blocks(r, width, d):
+        scale = np.abs(gW[o:o + s]).max()
+        for i in rng.choice(s, size=min(8, s), replace=False):
+            e = 1e-6 * (1 + abs(flat[o + i]))
+            vp, vm = flat.copy(), flat.copy()
+            vp[o + i] += e
+            vm[o + i] -= e
+            fd = (_oracle_loss(unflat(vp), X, Z, c) - _oracle_loss(unflat(vm), X, Z, c)) / (2 * e)
+            assert abs(gW[o + i] - fd) <= 1e-4 * scale, (name, i, gW[o + i], fd)
+    Z64 = Z.astype(np.float64)
+    for p in range(4):
+        for j in range(r):
+            e = 1e-6 * (1 + abs(Z64[p, j]))
+            Zp, Zm = Z64.copy(), Z64.copy()
+            Zp[p, j] += e
+            Zm[p, j] -= e
+            fd = (_oracle_loss(layers, X, Zp, c) - _oracle_loss(layers, X, Zm, c)) / (2 * e)
+            assert abs(gZ[p, j] - fd) <= 1e-4 * np.abs(gZ).max(), (p, j)
+
+
+def test_bf16_backward_close_to_fp64():
+    r, width, d = 12, 128, 6
+    layers, X, Z, c = _problem(r, width, d, n=256)
+    out, gW, gZ = _gpu_grads(layers, X, Z, c, width, d, "bf16")
+    ref_out, rW, rZ = _torch_grads(layers, X, Z, c)
+    assert np.abs(out - ref_out).max() <= 5e-2 * np.abs(ref_out).max()
+    # hidden layers of the backward run in FP32 on the BF16 forward's pre-activations
+    for name, o, s in _blocks(r, width, d):
+        err = np.abs(gW[o:o + s] - rW[o:o + s]).max() / np.abs(rW[o:o + s]).max()
+        assert err < 5e-2, (name, err)
