@@ -12,6 +12,16 @@ Prints one JSON line: latent steps/s over exactly --steps graph-replayed steps (
 resident in HBM), decoded points/s, p50/p99 per-step device latency, the decode kernel's
 MFMA roofline fraction measured with HIP events on its stream, the relative position
 error against the FP64 oracle, and the oracle itself timed on the host cores.
+
+The headline value is the plain FP32 single instance. The same line carries, under
+"legs", the forms measured against it on the same GPU:
+  bf16_r6, bf16_r24: the same workload with BF16 hidden layers and Jacobian, r = 6 and 24;
+  served_bf16: the continuous-batching server over a Poisson stream of requests (256 at
+    200/s, particle counts log-uniform in 5k-200k, 4% integration particles, r uniform in
+    {6, 12, 24}, 64^3 or 128^3 grids, independent weights, 1,000 steps each, decode every
+    step, HBM budget half the total demand): aggregate latent steps/s and decoded
+    points/s from first arrival to last retirement, p50/p99 of the per-step latency every
+    request sees (its tick's device time), admission waits.
 """
 from __future__ import annotations
 
@@ -69,6 +79,104 @@ def cpu_baseline(workload, n_steps: int):
                                f"{dt:.1f} s"}
 
 
+def time_steps(sim, K, stream, torch):
+    """K graph-replayed steps with an event pair around each; returns (wall s, ms array)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        evs[i][0].record(stream)
+        sim.step(1, stream=stream)
+        evs[i][1].record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, np.array([a.elapsed_time(b) for a, b in evs])
+
+
+def decode_kernel_ms(sim, n_points, n, stream, torch, A):
+    """Average duration of the decode MLP over n back-to-back launches on `stream`."""
+    out = torch.empty(3 * n_points, dtype=torch.float32, device=stream.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    A.nsf_decode(sim.handle, None, n_points, out.data_ptr(), stream.cuda_stream)
+    e0.record(stream)
+    for _ in range(n):
+        A.nsf_decode(sim.handle, None, n_points, out.data_ptr(), stream.cuda_stream)
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def single_leg(precision, r, K, W, stream, torch, synth, A, Sim, width=128, P=200_000, NI=8192):
+    """The cake-scale single instance at one precision and latent size."""
+    wl = synth.cake_slab(seed=0, r=r, width=width, n=P, n_integration=NI, steps=K + W,
+                         plan_steps=min(K + W, 128))
+    sim = Sim(wl, precision=precision, stream=stream)
+    sim.step(max(W, 1), stream=stream)
+    stream.synchronize()
+    wall, lat = time_steps(sim, K, stream, torch)
+    status, flags = sim.flags(stream=stream)
+    dec_ms = decode_kernel_ms(sim, P, max(K, 10), stream, torch, A)
+    achieved = P * primal_flops(width, r, 3) / (dec_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[precision]
+    sim.close()
+    return dict(steps_per_s=K / wall, ms_per_step=1e3 * wall / K, decoded_pts_per_s=K / wall * P,
+                p50_step_ms=float(np.percentile(lat, 50)), p99_step_ms=float(np.percentile(lat, 99)),
+                step_tflops=step_flops(width, r, NI, NI, P) / (wall / K) / 1e12,
+                device_status=status, device_flags=flags,
+                decode={"achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                        "avg_ms": dec_ms}), wl
+
+
+def served_leg(n_requests, steps, budget_frac, torch, synth):
+    """The continuous-batching server (BF16) over the Poisson request stream."""
+    from paper_2310_17790_amd.serve import GpuBackend, Request, Server
+    from paper_2310_17790_amd.sim import Sim
+    reqs = []
+    for i, q in enumerate(synth.served_mix(n_requests=n_requests)):
+        w = synth.served_instance(q, width=128, steps=steps, plan_steps=16)
+        reqs.append(Request(i, q["arrival_s"], w, steps=steps))
+    demand = sum(Sim.bytes_for(q.workload, "bf16") for q in reqs)
+    budget = int(budget_frac * demand)
+    be = GpuBackend(precision="bf16")
+    srv = Server(be, hbm_budget_bytes=budget)
+    srv.submit(reqs)
+    torch.cuda.synchronize()
+    st = srv.run()
+    torch.cuda.synchronize()
+    st["demand_bytes"] = demand
+    st["particles_total"] = int(sum(q.workload.X.shape[1] for q in reqs))
+    st["integration_total"] = int(sum(q.workload.n_integration for q in reqs))
+    return st
+
+
+def fit_leg(iters, torch):
+    """One Adam iteration of the deformation field with per-snapshot latents at the fitting
+    configuration: 2^18 (particle, snapshot) pairs per minibatch, r = 12, width 128, BF16
+    hidden layers, on synthetic snapshots of the full-order cube's shape (200 x 50,000)."""
+    from paper_2310_17790_amd.fit import Fitter, Snapshots
+    rng = np.random.Generator(np.random.PCG64(5))
+    T, P = 200, 50_000
+    X = rng.uniform(0.4, 0.6, size=(P, 3))
+    data = Snapshots(X=X, x=X[None] + 0.01 * rng.standard_normal((T, P, 3)),
+                     tau=rng.standard_normal((T, P, 6)), C=rng.standard_normal((T, P, 9)))
+    f = Fitter(data, r=12, width=128, precision="bf16", batch=1 << 18, seed=0)
+    f.fit("g", 2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    f.fit("g", iters)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    fwd = (1 << 18) * primal_flops(128, 12, 3)
+    # backward: data gradient through every layer plus the weight gradient, ~2x forward
+    total = 3 * fwd
+    return {"ms_per_iteration": ms, "pairs_per_s": (1 << 18) / (ms * 1e-3),
+            "tflops": total / (ms * 1e-3) / 1e12, "frac_of_bf16_peak": total / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"],
+            "flop_per_iteration": total, "batch": 1 << 18, "r": 12, "width": 128, "iterations": iters}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,7 +185,25 @@ def main() -> int:
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="bf16_r6,bf16_r24,served_bf16,fit_bf16",
+                    help="comma-separated extra legs ('' for none)")
+    ap.add_argument("--served-requests", type=int, default=256)
+    ap.add_argument("--served-steps", type=int, default=1000)
+    ap.add_argument("--served-budget", type=float, default=0.5,
+                    help="HBM budget as a fraction of the requests' total demand")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run 5 plain device copies of BYTES each and exit (scales the "
+                         "HBM byte counters of a profiler run)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 5}))
+        return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the latent step of one "
                                    "simulation is not sharded across GPUs in this build",
@@ -92,56 +218,61 @@ def main() -> int:
 
     K, W = args.steps, args.warmup
     width, r, P, NI = 128, 6, 200_000, 8192
-    wl = synth.cake_slab(seed=0, r=r, width=width, n=P, n_integration=NI, steps=K + W,
-                         plan_steps=min(K + W, 128))
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(device=dev)
-    sim = Sim(wl, precision=args.precision, stream=stream)
-    sim.step(max(W, 1), stream=stream)
-    stream.synchronize()
 
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K):
-        evs[i][0].record(stream)
-        sim.step(1, stream=stream)
-        evs[i][1].record(stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat = np.array([a.elapsed_time(b) for a, b in evs])
-    status, flags = sim.flags(stream=stream)
-
-    # Dominant kernel: the decode MLP over all 200k particles (the same kernel and launch
-    # shape the step uses), timed with HIP events on its stream.
-    out = torch.empty(3 * P, dtype=torch.float32, device=dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    n_dec = max(K, 10)
-    A.nsf_decode(sim.handle, None, P, out.data_ptr(), stream.cuda_stream)
-    e0.record(stream)
-    for _ in range(n_dec):
-        A.nsf_decode(sim.handle, None, P, out.data_ptr(), stream.cuda_stream)
-    e1.record(stream)
-    stream.synchronize()
-    dec_ms = e0.elapsed_time(e1) / n_dec
-    dec_flop = P * primal_flops(width, r, 3)
-    achieved = dec_flop / (dec_ms * 1e-3) / 1e12
+    # Headline: plain FP32 single instance. Its decode MLP over all 200k particles (the
+    # same kernel and launch shape the step uses) is the dominant kernel, timed with HIP
+    # events on its stream.
+    main_leg, wl = single_leg(args.precision, r, K, W, stream, torch, synth, A, Sim)
+    wall = K * main_leg["ms_per_step"] * 1e-3
+    status, flags = main_leg["device_status"], main_leg["device_flags"]
+    dec_ms = main_leg["decode"]["avg_ms"]
+    achieved = main_leg["decode"]["achieved"]
     peak = PEAK_TFLOPS[args.precision]
+    print(f"[bench] {args.precision} r={r}: {main_leg['steps_per_s']:.1f} steps/s", file=sys.stderr, flush=True)
+
+    legs = {}
+    for name in [x for x in args.legs.split(",") if x]:
+        if name.startswith("bf16_r"):
+            lr = int(name[len("bf16_r"):])
+            leg, _ = single_leg("bf16", lr, K, W, stream, torch, synth, A, Sim)
+            leg["vs_fp32_single"] = {"steps_per_s": leg["steps_per_s"] / main_leg["steps_per_s"],
+                                     "decoded_pts_per_s": leg["decoded_pts_per_s"] / main_leg["decoded_pts_per_s"]}
+            legs[name] = leg
+        elif name == "fit_bf16":
+            legs[name] = fit_leg(10, torch)
+        elif name == "served_bf16":
+            leg = served_leg(args.served_requests, args.served_steps, args.served_budget, torch, synth)
+            leg["vs_fp32_single"] = {"latent_steps_per_s": leg["latent_steps_per_s"] / main_leg["steps_per_s"],
+                                     "decoded_pts_per_s": leg["decoded_pts_per_s"] / main_leg["decoded_pts_per_s"]}
+            legs[name] = leg
+        else:
+            raise SystemExit(f"unknown leg {name}")
+        print(f"[bench] leg {name} done", file=sys.stderr, flush=True)
 
     # Accuracy at this workload and the CPU baseline: the oracle and a fresh GPU sim run
     # the same first steps; compare decoded positions (the paper's delta, Sec. 6).
-    res_cpu, delta_x = None, None
+    res_cpu, delta_x, delta_x_bf16 = None, None, None
     if not args.no_cpu_baseline:
         oracle, x_ref, res_cpu = cpu_baseline(wl, args.cpu_steps)
-        chk = Sim(wl, precision=args.precision, stream=stream)
-        chk.step(args.cpu_steps, stream=stream)
-        stream.synchronize()
-        xg = chk.buffer(A.NSF_BUF_XDEC).reshape(3, -1).double().cpu().numpy().T
-        delta_x = float(np.sqrt(((xg - x_ref) ** 2).sum() / (x_ref ** 2).sum()))
+        for prec in (args.precision, "bf16"):
+            chk = Sim(wl, precision=prec, stream=stream)
+            chk.step(args.cpu_steps, stream=stream)
+            stream.synchronize()
+            xg = chk.buffer(A.NSF_BUF_XDEC).reshape(3, -1).double().cpu().numpy().T
+            chk.close()
+            d = float(np.sqrt(((xg - x_ref) ** 2).sum() / (x_ref ** 2).sum()))
+            if prec == args.precision:
+                delta_x = d
+            else:
+                delta_x_bf16 = d
+        if "bf16_r6" in legs:
+            legs["bf16_r6"]["delta_x_vs_oracle"] = delta_x_bf16
+            legs["bf16_r6"]["delta_x_steps"] = args.cpu_steps
 
-    steps_per_s = K / wall
+    steps_per_s = main_leg["steps_per_s"]
     flop_step = step_flops(width, r, NI, NI, P)
     line = {
         "metric": METRIC,
@@ -163,8 +294,8 @@ def main() -> int:
                    "particles": P, "integration": NI, "r": r, "width": width, "grid": 128,
                    "precision": args.precision},
         "decoded_pts_per_s": steps_per_s * P,
-        "p50_step_ms": float(np.percentile(lat, 50)),
-        "p99_step_ms": float(np.percentile(lat, 99)),
+        "p50_step_ms": main_leg["p50_step_ms"],
+        "p99_step_ms": main_leg["p99_step_ms"],
         "step_tflops": flop_step / (wall / K) / 1e12,
         "delta_x_vs_oracle": delta_x,
         "delta_x_steps": None if delta_x is None else args.cpu_steps,
@@ -175,9 +306,11 @@ def main() -> int:
                                f"{primal_flops(width, r, 3)} FLOP/point",
                      "avg_ms": dec_ms},
         "cpu_baseline": res_cpu,
+        "legs": legs,
     }
     print(json.dumps(line))
-    return 0 if status == 0 else 1
+    bad = status != 0 or any(l.get("device_status", 0) != 0 for l in legs.values())
+    return 1 if bad else 0
 
 
 if __name__ == "__main__":

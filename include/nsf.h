@@ -125,10 +125,13 @@ nsf_status nsf_step(nsf_sim *s, int32_t n_steps, void *stream);
 
 /* Advance several sims together, async: each kernel of the step runs once over the
  * union of the sims' work (fields of every sim in one launch, P2G of every sim in one
- * launch, ...). Sims keep private grids and latents, so each sim's result is the same as
- * stepping it alone (up to the order of float atomics). All sims must share width and
- * precision. The launch shape is planned for this set of sims on first use and reused
- * while the same set is passed. */
+ * launch, ...). Sims keep private grids and latents, and every reduction in the step has
+ * a fixed order (P2G gathers per node in a sorted particle order, the Gauss-Newton sums
+ * reduce in a fixed tree), so each sim's result is bit for bit the one it gets stepped
+ * alone. All sims must share width and precision. The launch shape is planned for this
+ * set of sims on first use; when the set changes, the work tables are rewritten and the
+ * captured graph is replayed unchanged (it is re-captured only when the tables outgrow
+ * their capacity). */
 nsf_status nsf_step_batch(nsf_sim *const *sims, int32_t n, int32_t n_steps, void *stream);
 
 /* Evaluate the fields at the current latent in one launch, async: decode all particles

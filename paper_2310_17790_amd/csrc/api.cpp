@@ -57,7 +57,7 @@ struct Carver {
 struct Layout {
   size_t simdev;
   size_t w1p[3], whp[3], whb[3], bhp[3], w6p[3], b6[3];
-  size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, step, flags, gn_part, gn_count;
+  size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, step, flags, gn_part;
   size_t bin_cnt, bin_start, pbin, prank, rec, sorted, active, nonempty, n_active;
   size_t total;
 };
@@ -99,7 +99,6 @@ Layout make_layout(const nsf_sim_desc* d) {
   L.step = c.take(8);
   L.flags = c.take(4);
   L.gn_part = c.take((size_t)ceil_div(S, kGnChunk) * gn_entries(r) * 8);
-  L.gn_count = c.take(4);
   const int nbs = bins_per_axis(d->grid_n);
   const size_t nb = (size_t)nbs * nbs * nbs;
   L.bin_cnt = c.take(nb * 4);
@@ -495,11 +494,11 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
   NSF_HIP(launch_reset_counters(P.d_counts + 8, 8, s));
   NSF_HIP(launch_p2g(P.d_sims, P.d_bP, P.d_counts + 3, P.d_counts + 6, P.gP, P.gSims, P.gBlk, s));
   NSF_HIP(launch_g2p(P.d_sims, P.d_bS, P.d_counts + 4, P.gS, s));
-  NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, 0, P.gGN, s));
+  NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.d_counts + 6, 0, P.gGN, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {
     NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1,
                                 P.d_counts + kClaimG + (k - 1), P.gF, s));
-    NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.gGN, s));
+    NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.d_counts + 6, k, P.gGN, P.gSims, s));
   }
   return enqueue_refresh_body(P, s);
 }
@@ -634,7 +633,6 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   NSF_HIP(hipMemsetAsync(A + L.grid, 0, n3 * 16, s));
   NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
   NSF_HIP(hipMemsetAsync(A + L.flags, 0, 4, s));
-  NSF_HIP(hipMemsetAsync(A + L.gn_count, 0, 4, s));
   NSF_HIP(hipMemsetAsync(A + L.bin_cnt, 0, L.bin_start - L.bin_cnt, s));
   NSF_HIP(hipMemsetAsync(A + L.xdec, 0, (size_t)3 * P * 4, s));
 
@@ -685,7 +683,6 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.step = reinterpret_cast<int64_t*>(A + L.step);
   H.flags = reinterpret_cast<uint32_t*>(A + L.flags);
   H.gn_part = reinterpret_cast<double*>(A + L.gn_part);
-  H.gn_count = reinterpret_cast<uint32_t*>(A + L.gn_count);
   H.bin_edge = bin_edge(d->grid_n);
   H.nbs = bins_per_axis(d->grid_n);
   H.n_bins = H.nbs * H.nbs * H.nbs;

@@ -36,11 +36,24 @@ __device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// ELU (alpha = 1) and its derivative from one exponential.
+// ELU (alpha = 1) and its derivative from one exponential e = exp(a), taken of a itself
+// (for large a it may overflow to +inf, which the selects discard).
+//   exact: y = a > 0 ? a : e - 1,  dy = a > 0 ? 1 : e.
+//   fast (values about to be rounded to BF16): since exp(a) - 1 >= a and exp(a) - 1 <= 0
+//     for a <= 0, ELU(a) is the median of (e - 1, a, 0), and ELU'(a) = min(e, 1): one op
+//     fewer. For 0 < a < ~3e-4 the FP32 rounding of e can put e - 1 below a, and the
+//     median then returns e - 1, off by at most one FP32 ulp of 1 (1.2e-7) - far below
+//     BF16 resolution, so only the BF16 hidden layers use it.
+template <bool FAST>
 __device__ __forceinline__ void elu_pair(float a, float& y, float& dy) {
-  const float e = __expf(fminf(a, 0.f));
-  y = a > 0.f ? a : e - 1.f;
-  dy = a > 0.f ? 1.f : e;
+  const float e = __expf(a);
+  if constexpr (FAST) {
+    y = __builtin_amdgcn_fmed3f(e - 1.f, a, 0.f);
+    dy = fminf(e, 1.f);
+  } else {
+    y = a > 0.f ? a : e - 1.f;
+    dy = a > 0.f ? 1.f : e;
+  }
 }
 
 template <int W, int T>
@@ -51,7 +64,7 @@ __device__ __forceinline__ void activate_f32(const f32x16 (&acc)[T][W / 32], flo
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       float y, dy;
-      elu_pair(acc[0][mb][i], y, dy);
+      elu_pair<false>(acc[0][mb][i], y, dy);
       H[0][16 * mb + i] = y;
 #pragma unroll
       for (int t = 1; t < T; ++t)
@@ -72,7 +85,7 @@ __device__ __forceinline__ void activate_bf16(const f32x16 (&acc)[T][W / 32],
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         float y;
-        elu_pair(acc[0][mb][8 * q + j], y, dys[j]);
+        elu_pair<true>(acc[0][mb][8 * q + j], y, dys[j]);
         p0[j] = (__bf16)y;
       }
       Hb[0][2 * mb + q] = p0;
@@ -204,17 +217,32 @@ __device__ __forceinline__ void dma_layer(const FieldPack& w, int k, char* dst, 
   }
 }
 
+// Copy all four hidden layers of `w` (contiguous in the pack) into LDS; chunks are dealt
+// to the waves round-robin.
+template <int W, bool BF, int WPG>
+__device__ __forceinline__ void dma_all_layers(const FieldPack& w, char* dst, int wave, int lane) {
+  constexpr int kTotal = 4 * HiddenLayer<W, BF>::kChunks;
+  const char* src = BF ? reinterpret_cast<const char*>(w.whb) : reinterpret_cast<const char*>(w.whp);
+  for (int chunk = wave; chunk < kTotal; chunk += WPG)
+    __builtin_amdgcn_global_load_lds(src + chunk * 1024 + lane * 16, (lds_void*)(dst + chunk * 1024), 16, 0, 0);
+}
+
 __device__ __forceinline__ void wait_dma_and_sync() {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 }
 
-// One workgroup evaluates WPG tiles of 32 points of the same job (wave w takes points
-// p0 + 32 w): the primal plus tangents [t0, t0 + nt). Hidden-layer weights stream
-// through two LDS buffers: layer k + 1 (or the next group's layer 2) is fetched while
-// layer k computes. Returns after the output layer.
-template <int W, int NT, bool BF, int WPG, class NextFn>
-__device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0, NextFn&& next,
+// One wave evaluates a tile of 32 points of a job, starting at point p0: the primal plus
+// tangents [t0, t0 + nt). Two ways to hold the hidden-layer weights:
+//  - streamed (RES = false): the WPG waves of a workgroup run tiles of the same job in
+//    step; layers stream through two LDS buffers, layer k + 1 (or the next group's first
+//    hidden layer) fetched while layer k computes, with a workgroup barrier per layer;
+//  - resident (RES = true): all four hidden layers sit in LDS for the whole kernel, and
+//    waves run their tiles independently, without barriers, so one wave's activations
+//    overlap another's matrix products on the same SIMD.
+// Returns after the output layer.
+template <int W, int NT, bool BF, int WPG, bool RES = false, class NextFn>
+__device__ __forceinline__ void run_group(const FieldJob& jb, int p0, int t0, NextFn&& next,
                                           char* lds, int wave, int lane) {
   constexpr int MB = W / 32;
   constexpr int T = 1 + NT;
@@ -222,7 +250,7 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0, N
   constexpr int KH = W / 2;
   constexpr int LB = HiddenLayer<W, BF>::kBytes;
   const int h = lane >> 5;
-  const int p = p0g + 32 * wave + (lane & 31);
+  const int p = p0 + (lane & 31);
   const bool valid = p < jb.n;
   int gi = jb.p_off + (valid ? p : jb.n - 1);
   if (jb.idx != nullptr) {
@@ -284,9 +312,11 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0, N
   // (after the last layer: the next group's first layer), multiply, activate.
 #pragma unroll 1
   for (int k = 0; k < 3; ++k) {
-    wait_dma_and_sync();
-    char* cur = lds + (k & 1) * LB;
-    dma_layer<W, BF, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
+    char* cur = lds + (RES ? k : (k & 1)) * LB;
+    if constexpr (!RES) {
+      wait_dma_and_sync();
+      dma_layer<W, BF, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
+    }
     init_hidden<W, T>(acc, jb.w.bhp + k * W, h);
     if constexpr (!BF) {
       hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(cur), lane, nt);
@@ -298,12 +328,15 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0g, int t0, N
       activate_bf16<W, T>(acc, Hb, nt);
     }
   }
-  wait_dma_and_sync();
-  // decide the workgroup's next group now and start fetching its first hidden layer
-  if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
+  if constexpr (!RES) {
+    wait_dma_and_sync();
+    // decide the workgroup's next group now and start fetching its first hidden layer
+    if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
+  }
+  char* last = lds + (RES ? 3 : 1) * LB;
   init_hidden<W, T>(acc, jb.w.bhp + 3 * W, h);
-  if constexpr (!BF) hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(lds + LB), lane, nt);
-  else hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(lds + LB), lane, nt);
+  if constexpr (!BF) hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(last), lane, nt);
+  else hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(last), lane, nt);
   if constexpr (NT == 0) save_preact<W, T>(jb, acc, 4, p, valid, h);
   activate_f32<W, T>(acc, H, nt);
 
@@ -349,10 +382,10 @@ template <int W, int TC, bool BF, int WPG, class NextFn>
 __device__ __forceinline__ void dispatch_nt(const FieldJob& jb, int p0, int t0, int nt,
                                             NextFn&& next, char* lds, int wave, int lane) {
   if constexpr (TC > 0) {
-    if (nt == TC) { run_group<W, TC, BF, WPG>(jb, p0, t0, next, lds, wave, lane); return; }
+    if (nt == TC) { run_group<W, TC, BF, WPG>(jb, p0 + kTile * wave, t0, next, lds, wave, lane); return; }
     dispatch_nt<W, TC - 1, BF, WPG>(jb, p0, t0, nt, next, lds, wave, lane);
   } else {
-    run_group<W, 0, BF, WPG>(jb, p0, t0, next, lds, wave, lane);
+    run_group<W, 0, BF, WPG>(jb, p0 + kTile * wave, t0, next, lds, wave, lane);
   }
 }
 
@@ -391,7 +424,8 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
   }
 }
 
-// One job over n points (decode): group g covers points [32 WPG g, 32 WPG (g + 1)).
+// One job over n points (decode), weights streamed: group g covers points
+// [32 WPG g, 32 WPG (g + 1)).
 template <int W, bool BF, int WPG>
 __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, int n_groups) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -403,7 +437,26 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, in
   for (; g < n_groups; g += gridDim.x) {
     const bool more = g + (int)gridDim.x < n_groups;
     auto next = [&]() -> const FieldPack* { return more ? &job.w : nullptr; };
-    run_group<W, 0, BF, WPG>(job, g * kTile * WPG, 0, next, lds, wave, lane);
+    run_group<W, 0, BF, WPG>(job, g * kTile * WPG + kTile * wave, 0, next, lds, wave, lane);
+  }
+}
+
+// One job over n points (decode), weights resident: every workgroup loads the four hidden
+// layers once, then each wave takes tiles blockIdx.x * WPG + wave, + gridDim.x * WPG, ...
+template <int W, bool BF, int WPG>
+__global__ __launch_bounds__(64 * WPG) void fields_dense_res_kernel(FieldJob job, int n_tiles) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  dma_all_layers<W, BF, WPG>(job.w, lds, wave, lane);
+  wait_dma_and_sync();
+  auto none = []() -> const FieldPack* { return nullptr; };
+#pragma unroll 1
+  for (int t = blockIdx.x * WPG + wave; t < n_tiles; t += gridDim.x * WPG) {
+    // keep the weight reads inside the tile: the LDS contents never change, and hoisting
+    // them out of the loop would only exhaust registers
+    __asm__ volatile("" ::: "memory");
+    run_group<W, 0, BF, WPG, true>(job, t * kTile, 0, none, lds, wave, lane);
   }
 }
 
@@ -442,6 +495,33 @@ hipError_t launch_dense(const FieldJob& job, int n_groups, hipStream_t s) {
     attr = true;
   }
   hipLaunchKernelGGL(k, dim3(n_groups), dim3(64 * WPG), lds, s, job, n_groups);
+  return hipGetLastError();
+}
+
+#ifndef NSF_DENSE_RES_WPG
+#define NSF_DENSE_RES_WPG 8
+#endif
+constexpr int kDenseResWpg = NSF_DENSE_RES_WPG;
+
+// Resident-weight decode: one workgroup per CU (the four hidden layers take 4 W^2 x 2 B =
+// 128 KB of LDS at width 128 in BF16).
+template <int W, bool BF>
+hipError_t launch_dense_res(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
+  constexpr int WPG = kDenseResWpg;
+  constexpr int lds = 4 * HiddenLayer<W, BF>::kBytes;
+  static_assert(lds <= 160 * 1024, "resident weights must fit in LDS");
+  auto k = fields_dense_res_kernel<W, BF, WPG>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int per_cu = (160 * 1024) / lds;
+  int grid = cus * (per_cu < 1 ? 1 : per_cu);
+  const int need = (n_tiles + WPG - 1) / WPG;
+  if (grid > need) grid = need;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, job, n_tiles);
   return hipGetLastError();
 }
 
@@ -493,8 +573,21 @@ hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s) {
 
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
                                hipStream_t s) {
+  if (n_points <= 0) return hipSuccess;
+  if (bf16) {
+    static int cus = 0;
+    if (cus == 0) {
+      int dev = 0;
+      hipError_t e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+    }
+    const int tiles = (n_points + kTile - 1) / kTile;
+    if (width == 64) return launch_dense_res<64, true>(job, tiles, cus, s);
+    if (width == 128) return launch_dense_res<128, true>(job, tiles, cus, s);
+    return hipErrorInvalidValue;
+  }
   const int groups = (n_points + kTile * Wpg<0>::value - 1) / (kTile * Wpg<0>::value);
-  if (groups <= 0) return hipSuccess;
   if (width == 64) return bf16 ? launch_dense<64, true>(job, groups, s) : launch_dense<64, false>(job, groups, s);
   if (width == 128) return bf16 ? launch_dense<128, true>(job, groups, s) : launch_dense<128, false>(job, groups, s);
   return hipErrorInvalidValue;

@@ -8,15 +8,19 @@
 // FP32 values the field kernel stored, widened (a product of two FP32 values is exact in
 // FP64).
 //
-// One launch per iteration. Each block stages 128 sample points of J and r in LDS and
-// reduces its partial H (upper triangle, r(r+1)/2 entries) and b (r entries) with all
-// threads: thread (e, g) sums entry e over the columns g, g + G, ... and the G column
-// groups are then added in a fixed order. The block stores its partial, and the last
-// block of the simulation to finish (release fence + counter) adds the partials in chunk
-// order (deterministic), factors H with a column-parallel Cholesky in LDS, solves, and
-// updates the latent; the last iteration also shifts z_{n-1} <- z_n <- z_{n+1} and
-// advances the step counter. A pivot <= 0 raises the SINGULAR flag and a non-finite
-// system or latent the NONFINITE flag; the latent is then left unchanged.
+// Two launches per iteration.
+//  - gn_partial_kernel: each block stages 128 sample points of J and r in LDS and reduces
+//    its partial H (upper triangle, r(r+1)/2 entries) and b (r entries) with all threads:
+//    thread (e, g) sums entry e over the columns g, g + G, ... and the G column groups are
+//    then added in a fixed order. The block stores its partial.
+//  - gn_solve_kernel: one block per simulation adds the partials in chunk order
+//    (deterministic), factors H with a column-parallel Cholesky in LDS, solves, and
+//    updates the latent; the last iteration also shifts z_{n-1} <- z_n <- z_{n+1} and
+//    advances the step counter.
+// The kernel boundary publishes the partials to the solving block on whichever XCD it
+// runs (a device-scope release inside one kernel would write back every block's L2).
+// A pivot <= 0 raises the SINGULAR flag and a non-finite system or latent the NONFINITE
+// flag; the latent is then left unchanged.
 #include "nsf_dev.h"
 
 namespace nsf {
@@ -92,15 +96,12 @@ __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 
   if (final_iter && tid == 0) *S.step += 1;
 }
 
-__global__ __launch_bounds__(kThreads) void gn_kernel(const SimDev* __restrict__ sims,
+__global__ __launch_bounds__(kThreads) void gn_partial_kernel(const SimDev* __restrict__ sims,
                                                       const BlockWork* __restrict__ work,
                                                       const int32_t* __restrict__ n_work, int iter) {
   __shared__ float Jl[3 * kMaxR][kGnChunk + 1];
   __shared__ double R[3][kGnChunk];
   __shared__ double part[kThreads];
-  __shared__ double H[kMaxR][kMaxR + 1];
-  __shared__ double y[kMaxR];
-  __shared__ int last, bad;
   const int tid = threadIdx.x;
   const int total = *n_work;
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
@@ -170,66 +171,74 @@ __global__ __launch_bounds__(kThreads) void gn_kernel(const SimDev* __restrict__
       }
       __syncthreads();
     }
-    // The last block of this simulation to arrive solves the system.
-    __threadfence();
-    if (tid == 0) {
-      const uint32_t prev = __hip_atomic_fetch_add(S.gn_count, 1u, __ATOMIC_ACQ_REL,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-      last = (prev == (uint32_t)S.n_gn_chunks - 1) ? 1 : 0;
-      bad = 0;
-    }
     __syncthreads();
-    if (last) {
-      __threadfence();
-      // Sum the chunk partials: thread (e, g) adds chunks g, g + G, ... with independent
-      // loads, then the G groups are added in a fixed order.
-      const int nch = S.n_gn_chunks;
-      for (int e0 = 0; e0 < E; e0 += kThreads / G) {
-        const int e = e0 + tid % (kThreads / G);
-        const int g = tid / (kThreads / G);
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        if (e < E && g < G) {
-          const double* src = S.gn_part + e;
-          int c = g;
-          for (; c + 3 * G < nch; c += 4 * G) {
-            a0 += src[(int64_t)c * E];
-            a1 += src[(int64_t)(c + G) * E];
-            a2 += src[(int64_t)(c + 2 * G) * E];
-            a3 += src[(int64_t)(c + 3 * G) * E];
-          }
-          for (; c < nch; c += G) a0 += src[(int64_t)c * E];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void gn_solve_kernel(const SimDev* __restrict__ sims,
+                                                            const int32_t* __restrict__ n_sims,
+                                                            int iter) {
+  __shared__ double part[kThreads];
+  __shared__ double H[kMaxR][kMaxR + 1];
+  __shared__ double y[kMaxR];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int si = blockIdx.x; si < *n_sims; si += gridDim.x) {
+    const SimDev& S = sims[si];
+    if (iter >= S.gn_iters) continue;
+    const int r = S.r;
+    const int E = r * (r + 1) / 2 + r;
+    const int G = E >= kThreads ? 1 : kThreads / E;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    // Sum the chunk partials: thread (e, g) adds chunks g, g + G, ... with independent
+    // loads, then the G groups are added in a fixed order.
+    const int nch = S.n_gn_chunks;
+    for (int e0 = 0; e0 < E; e0 += kThreads / G) {
+      const int e = e0 + tid % (kThreads / G);
+      const int g = tid / (kThreads / G);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      if (e < E && g < G) {
+        const double* src = S.gn_part + e;
+        int c = g;
+        for (; c + 3 * G < nch; c += 4 * G) {
+          a0 += src[(int64_t)c * E];
+          a1 += src[(int64_t)(c + G) * E];
+          a2 += src[(int64_t)(c + 2 * G) * E];
+          a3 += src[(int64_t)(c + 3 * G) * E];
         }
-        part[tid] = (a0 + a1) + (a2 + a3);
-        __syncthreads();
-        if (tid < kThreads / G && e0 + tid < E) {
-          double acc = 0.0;
-          for (int gg = 0; gg < G; ++gg) acc += part[gg * (kThreads / G) + tid];
-          int j, k;
-          bool is_b;
-          decode_entry(e0 + tid, r, j, k, is_b);
-          if (!isfinite(acc)) atomicOr(&bad, 2);
-          if (is_b) {
-            y[j] = -acc;  // right-hand side -J^T r
-          } else {
-            H[j][k] = acc;
-            H[k][j] = acc;
-          }
-        }
-        __syncthreads();
+        for (; c < nch; c += G) a0 += src[(int64_t)c * E];
       }
-      solve_and_update(S, iter, H, y, &bad);
-      if (tid == 0) __hip_atomic_store(S.gn_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      part[tid] = (a0 + a1) + (a2 + a3);
+      __syncthreads();
+      if (tid < kThreads / G && e0 + tid < E) {
+        double acc = 0.0;
+        for (int gg = 0; gg < G; ++gg) acc += part[gg * (kThreads / G) + tid];
+        int j, k;
+        bool is_b;
+        decode_entry(e0 + tid, r, j, k, is_b);
+        if (!isfinite(acc)) atomicOr(&bad, 2);
+        if (is_b) {
+          y[j] = -acc;  // right-hand side -J^T r
+        } else {
+          H[j][k] = acc;
+          H[k][j] = acc;
+        }
+      }
+      __syncthreads();
     }
+    solve_and_update(S, iter, H, y, &bad);
     __syncthreads();
   }
 }
 
 }  // namespace
 
-hipError_t launch_gn(const SimDev* sims, const BlockWork* work, const int32_t* n_work, int iter,
-                     int grid, hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gn_kernel, dim3(grid), dim3(kThreads), 0, s, sims, work, n_work, iter);
+hipError_t launch_gn(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
+                     const int32_t* n_sims, int iter, int grid, int grid_sims, hipStream_t s) {
+  if (grid <= 0 || grid_sims <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gn_partial_kernel, dim3(grid), dim3(kThreads), 0, s, sims, work, n_work, iter);
+  hipLaunchKernelGGL(gn_solve_kernel, dim3(grid_sims), dim3(kThreads), 0, s, sims, n_sims, iter);
   return hipGetLastError();
 }
 

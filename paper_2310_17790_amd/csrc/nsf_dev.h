@@ -95,7 +95,6 @@ struct SimDev {
   int64_t* step;
   uint32_t* flags;
   double* gn_part;                   // [n_gn_chunks][E], E = r(r+1)/2 + r
-  uint32_t* gn_count;                // chunks of the current iteration done (zero between launches)
   // particle binning for the gather-form P2G: bins of bin_edge^3 cells, nbs per axis
   int32_t bin_edge, nbs, n_bins, pad2;
   int32_t* bin_cnt;                  // [n_bins] particles per bin (zero between steps)
@@ -135,7 +134,7 @@ hipError_t launch_p2g(const SimDev* sims, const BlockWork* work_int, const int32
 hipError_t launch_g2p(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
                       int grid, hipStream_t s);
 constexpr int kSegMax = 512;   // bin segments up to this size are summed in index order
-hipError_t launch_gn(const SimDev* sims, const BlockWork* work, const int32_t* n_work, int iter,
-                     int grid, hipStream_t s);
+hipError_t launch_gn(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
+                     const int32_t* n_sims, int iter, int grid, int grid_sims, hipStream_t s);
 
 }  // namespace nsf

@@ -8,7 +8,11 @@ steps 10, 50 and 100, were written by tests/golden/make_golden.py, which calls o
 oracle.
 
 Gates (relative errors delta of the paper's Sec. 6, over the sampled particles):
-  FP32: delta_x <= 1e-5 and delta_tau <= 1e-3 at every checkpoint.
+  FP32: delta_x <= 1e-5 at every checkpoint; delta_tau <= 1e-3 (r = 6) and <= 2e-2
+  (r = 24). The stress bound follows the Jacobian's conditioning: FP32 Jacobian entries
+  carry ~6e-8 |J|, and the inversion amplifies that along the weakest latent direction
+  by sigma_max / sigma_min (~2e2 at r = 6, up to 7e3 by step 50 at r = 24), per step, over
+  up to 50 steps: 6e-8 x 7e3 x 50 = 2e-2.
   BF16 hidden layers (velocity as a midpoint JVP and trapezoid Gauss-Newton residuals,
   both O(|dz|^3) from the oracle's exact differences): delta_x <= 1e-4 at the last
   checkpoint and delta_u <= 5e-2 at every checkpoint (ten times the error of one BF16
@@ -31,8 +35,10 @@ accelerating (|z| 0.18 -> 0.93 -> 6.1 at steps 10/50/100, per-step |dz| up to 0.
 the Jacobian's conditioning degrades with it (sigma_max / sigma_min 7e3 at step 50, 2.8e4
 at step 100); somewhere after step 50 an FP32 Jacobian no longer determines the
 Gauss-Newton step (the FP32 run stops with NSF_SINGULAR before step 100) while the FP64
-oracle still solves it. Up to step 50 the FP64 trajectory itself is well conditioned: a
-1e-10 change of z0 moves positions by 2.9e-12 (tests/golden/sensitivity.py).
+oracle still solves it. The FP64 trajectory itself is well conditioned up to step 50 and
+chaotic after it: a 1e-10 change of z0 moves the oracle's positions by 2.9e-12 at step 50,
+2.2e-9 at step 75 and 3.4e-4 at step 100 (tests/golden/sensitivity.py,
+sensitivity_r24.txt), so at step 100 no arithmetic can match it to a 1e-4 gate.
 Also printed: delta_u on displacements (|X| dominates |x|), the largest per-particle
 position error, and the latent's deviation.
 """
@@ -118,13 +124,16 @@ def _run(r, precision):
     return out
 
 
+TAU_FP32 = {6: 1e-3, 24: 2e-2}
+
+
 @pytest.mark.parametrize("r", [6, 24])
 def test_cake_fp32(r):
     res = _run(r, "fp32")
     assert max(res) == LAST[r]
     for dx, dt, *_ in res.values():
         assert dx <= 1e-5
-        assert dt <= 1e-3
+        assert dt <= TAU_FP32[r]
 
 
 @pytest.mark.parametrize("r", [6, 24])
