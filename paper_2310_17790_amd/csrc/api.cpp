@@ -58,7 +58,8 @@ struct Layout {
   size_t simdev;
   size_t w1p[3], whp[3], whb[3], bhp[3], w6p[3], b6[3];
   size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, step, flags, gn_part;
-  size_t bin_cnt, bin_start, pbin, prank, rec, sorted, active, nonempty, n_active;
+  size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active,
+      nonempty, n_active;
   size_t total;
 };
 
@@ -102,7 +103,10 @@ Layout make_layout(const nsf_sim_desc* d) {
   const int nbs = bins_per_axis(d->grid_n);
   const size_t nb = (size_t)nbs * nbs * nbs;
   L.bin_cnt = c.take(nb * 4);
-  L.bin_start = c.take((nb + 1) * 4);
+  L.bin_start = c.take(nb * 4);
+  L.seg_cnt = c.take(nb * 4);
+  L.bin_epoch = c.take(nb * 4);
+  L.epoch = c.take(4);
   L.pbin = c.take((size_t)N * 4);
   L.prank = c.take((size_t)N * 4);
   L.rec = c.take((size_t)N * 64);
@@ -208,10 +212,10 @@ struct Plan {
   SimDev* d_sims = nullptr;
   FieldJob* d_jobs = nullptr;
   FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tAD = nullptr, *d_tD = nullptr;
-  BlockWork *d_bP = nullptr, *d_bS = nullptr, *d_bGN = nullptr;
-  int nA = 0, nG = 0, nAD = 0, nD = 0, nP = 0, nS = 0, nGN = 0, nsims = 0;
+  BlockWork *d_bP = nullptr, *d_bGN = nullptr;
+  int nA = 0, nG = 0, nAD = 0, nD = 0, nP = 0, nGN = 0, nsims = 0;
   // launch grids (fixed for persistent plans)
-  int gF = 0, gF0 = 0, gP = 0, gS = 0, gGN = 0, gSims = 0, gBlk = 0;
+  int gF = 0, gF0 = 0, gP = 0, gGN = 0, gSims = 0, gBlk = 0;
   FieldJob decode_job{};          // single-sim plans decode with the dense kernel
   // Decode runs on a side stream, concurrently with the next step's inference.
   hipStream_t side = nullptr;
@@ -301,7 +305,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   std::vector<FieldJob> jobs;
   std::vector<FieldTile> tA_jac, tA_prim, tG, tD, tD0;  // tD: decode groups for the tangent
                                                          // kernel, tD0: for the primal kernel
-  std::vector<BlockWork> bP, bS, bGN;
+  std::vector<BlockWork> bP, bGN;
   for (size_t si = 0; si < P.members.size(); ++si) {
     nsf_sim* s = P.members[si];
     const SimDev& H = s->hd;
@@ -356,7 +360,6 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     jobs.push_back(dj);
     P.decode_job = dj;
     for (int p0 = 0; p0 < N; p0 += kMpmBlock) bP.push_back({(int)si, p0});
-    for (int p0 = 0; p0 < S; p0 += kMpmBlock) bS.push_back({(int)si, p0});
     for (int p0 = 0; p0 < S; p0 += kGnChunk) bGN.push_back({(int)si, p0});
   }
   // Longest groups first: Jacobian groups, then decode, then the primal-only groups.
@@ -365,28 +368,29 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   if (P.decode) tAD.insert(tAD.end(), tD.begin(), tD.end());
   tAD.insert(tAD.end(), tA_prim.begin(), tA_prim.end());
   P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nAD = (int)tAD.size(); P.nD = (int)tD0.size();
-  P.nP = (int)bP.size(); P.nS = (int)bS.size(); P.nGN = (int)bGN.size();
+  P.nP = (int)bP.size(); P.nGN = (int)bGN.size();
   P.nsims = (int)sims.size();
-  std::vector<int32_t> counts = {P.nA, P.nG, P.nAD, P.nP, P.nS, P.nGN, P.nsims, P.nD,
+  std::vector<int32_t> counts = {P.nA, P.nG, P.nAD, P.nP, 0 /* unused */, P.nGN, P.nsims, P.nD,
                                  0, 0, 0, 0, 0, 0, 0, 0};
   // Regions of the device buffer. A persistent plan keeps fixed region capacities (grown
   // by half when exceeded), so its captured graph stays valid while tables are rewritten.
   struct Region { const void* data; size_t bytes; };
-  const Region reg[10] = {
+  constexpr int kRegions = 9;
+  const Region reg[kRegions] = {
       {counts.data(), counts.size() * 4}, {sims.data(), sims.size() * sizeof(SimDev)},
       {jobs.data(), jobs.size() * sizeof(FieldJob)}, {tA.data(), tA.size() * sizeof(FieldTile)},
       {tG.data(), tG.size() * sizeof(FieldTile)}, {tAD.data(), tAD.size() * sizeof(FieldTile)},
       {tD0.data(), tD0.size() * sizeof(FieldTile)}, {bP.data(), bP.size() * sizeof(BlockWork)},
-      {bS.data(), bS.size() * sizeof(BlockWork)}, {bGN.data(), bGN.size() * sizeof(BlockWork)}};
+      {bGN.data(), bGN.size() * sizeof(BlockWork)}};
   bool relayout = P.caps.empty();
-  for (int i = 0; i < 10 && !relayout; ++i) relayout = reg[i].bytes > P.caps[i];
+  for (int i = 0; i < kRegions && !relayout; ++i) relayout = reg[i].bytes > P.caps[i];
   if (relayout) {
-    P.caps.assign(10, 0);
-    for (int i = 0; i < 10; ++i)
+    P.caps.assign(kRegions, 0);
+    for (int i = 0; i < kRegions; ++i)
       P.caps[i] = align_up(P.persistent ? reg[i].bytes + reg[i].bytes / 2 + 4096 : std::max<size_t>(reg[i].bytes, 1));
   }
-  size_t off[10], total = 0;
-  for (int i = 0; i < 10; ++i) { off[i] = total; total += P.caps[i]; }
+  size_t off[kRegions], total = 0;
+  for (int i = 0; i < kRegions; ++i) { off[i] = total; total += P.caps[i]; }
   if (relayout || total > P.dcap) {
     if (P.exec) { (void)hipGraphExecDestroy(P.exec); P.exec = nullptr; }
     if (P.graph) { (void)hipGraphDestroy(P.graph); P.graph = nullptr; }
@@ -408,20 +412,19 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.d_tAD = reinterpret_cast<FieldTile*>(b + off[5]);
   P.d_tD = reinterpret_cast<FieldTile*>(b + off[6]);
   P.d_bP = reinterpret_cast<BlockWork*>(b + off[7]);
-  P.d_bS = reinterpret_cast<BlockWork*>(b + off[8]);
-  P.d_bGN = reinterpret_cast<BlockWork*>(b + off[9]);
+  P.d_bGN = reinterpret_cast<BlockWork*>(b + off[8]);
   if (P.persistent) {
     NSF_HIP(hipStreamSynchronize(stream));  // the previous upload has been consumed
     char* st = static_cast<char*>(P.staging);
-    for (int i = 0; i < 10; ++i)
+    for (int i = 0; i < kRegions; ++i)
       if (reg[i].bytes) std::memcpy(st + off[i], reg[i].data, reg[i].bytes);
     // only the used part of each region is copied (regions are independent)
-    for (int i = 0; i < 10; ++i)
+    for (int i = 0; i < kRegions; ++i)
       if (reg[i].bytes)
         NSF_HIP(hipMemcpyAsync(b + off[i], st + off[i], reg[i].bytes, hipMemcpyHostToDevice, stream));
   } else {
     std::vector<char> blob(total, 0);
-    for (int i = 0; i < 10; ++i)
+    for (int i = 0; i < kRegions; ++i)
       if (reg[i].bytes) std::memcpy(blob.data() + off[i], reg[i].data, reg[i].bytes);
     NSF_HIP(hipMemcpyAsync(P.dbuf, blob.data(), total, hipMemcpyHostToDevice, stream));
     NSF_HIP(hipStreamSynchronize(stream));
@@ -434,7 +437,6 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.gF = P.persistent ? fcap : mn(fcap, std::max(P.nA, std::max(P.nAD, P.nG)));
   P.gF0 = P.persistent ? fcap0 : mn(fcap0, P.nD);
   P.gP = P.persistent ? 4 * cus : P.nP;
-  P.gS = P.persistent ? 4 * cus : P.nS;
   P.gGN = P.persistent ? 4 * cus : P.nGN;
   P.gSims = P.persistent ? cus : P.nsims;
   P.gBlk = 2 * cus;   // gather workgroups loop over each sim's active node blocks
@@ -491,14 +493,15 @@ nsf_status enqueue_refresh(Plan& P, hipStream_t s) {
 // One latent step, given its field inference in the buffers: MPM step, Gauss-Newton
 // iterations, then decode at z_{n+1} together with the inference of step n + 1.
 nsf_status enqueue_step(Plan& P, hipStream_t s) {
-  NSF_HIP(launch_reset_counters(P.d_counts + 8, 8, s));
-  NSF_HIP(launch_p2g(P.d_sims, P.d_bP, P.d_counts + 3, P.d_counts + 6, P.gP, P.gSims, P.gBlk, s));
-  NSF_HIP(launch_g2p(P.d_sims, P.d_bS, P.d_counts + 4, P.gS, s));
-  NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.d_counts + 6, 0, P.gGN, P.gSims, s));
+  NSF_HIP(launch_p2g(P.d_sims, P.d_bP, P.d_counts + 3, P.d_counts + 6, P.d_counts + 8, P.gP,
+                     P.gSims, P.gBlk, s));
+  NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.gGN, s));
+  NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {
     NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1,
                                 P.d_counts + kClaimG + (k - 1), P.gF, s));
-    NSF_HIP(launch_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.d_counts + 6, k, P.gGN, P.gSims, s));
+    NSF_HIP(launch_gn_partial(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.gGN, s));
+    NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, k, P.gSims, s));
   }
   return enqueue_refresh_body(P, s);
 }
@@ -634,6 +637,8 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
   NSF_HIP(hipMemsetAsync(A + L.flags, 0, 4, s));
   NSF_HIP(hipMemsetAsync(A + L.bin_cnt, 0, L.bin_start - L.bin_cnt, s));
+  NSF_HIP(hipMemsetAsync(A + L.bin_epoch, 0xff, L.epoch - L.bin_epoch, s));   // epoch -1: never set
+  NSF_HIP(hipMemsetAsync(A + L.epoch, 0, 4, s));
   NSF_HIP(hipMemsetAsync(A + L.xdec, 0, (size_t)3 * P * 4, s));
 
   SimDev& H = sim->hd;
@@ -688,6 +693,9 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.n_bins = H.nbs * H.nbs * H.nbs;
   H.bin_cnt = reinterpret_cast<int32_t*>(A + L.bin_cnt);
   H.bin_start = reinterpret_cast<int32_t*>(A + L.bin_start);
+  H.seg_cnt = reinterpret_cast<int32_t*>(A + L.seg_cnt);
+  H.bin_epoch = reinterpret_cast<int32_t*>(A + L.bin_epoch);
+  H.epoch = reinterpret_cast<int32_t*>(A + L.epoch);
   H.pbin = reinterpret_cast<int32_t*>(A + L.pbin);
   H.prank = reinterpret_cast<int32_t*>(A + L.prank);
   H.rec = reinterpret_cast<float*>(A + L.rec);

@@ -9,11 +9,11 @@
 // FP64).
 //
 // Two launches per iteration.
-//  - gn_partial_kernel: each block stages 128 sample points of J and r in LDS and reduces
-//    its partial H (upper triangle, r(r+1)/2 entries) and b (r entries) with all threads:
-//    thread (e, g) sums entry e over the columns g, g + G, ... and the G column groups are
-//    then added in a fixed order. The block stores its partial.
-//  - gn_solve_kernel: one block per simulation adds the partials in chunk order
+//  - the chunk reduction (gn_reduce.h): each block stages 128 sample points of J and r in
+//    LDS and stores its partial H (upper triangle) and b. Iteration 0 runs it inside the
+//    G2P kernel (mpm.hip), where r = -dt v is at hand; later iterations in
+//    gn_partial_kernel, after the field kernel evaluated u and J at the iterate.
+//  - gn_solve_kernel: one wave per simulation adds the partials in chunk order
 //    (deterministic), factors H with a column-parallel Cholesky in LDS, solves, and
 //    updates the latent; the last iteration also shifts z_{n-1} <- z_n <- z_{n+1} and
 //    advances the step counter.
@@ -21,26 +21,14 @@
 // runs (a device-scope release inside one kernel would write back every block's L2).
 // A pivot <= 0 raises the SINGULAR flag and a non-finite system or latent the NONFINITE
 // flag; the latent is then left unchanged.
-#include "nsf_dev.h"
+#include "gn_reduce.h"
 
 namespace nsf {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kSolveThreads = 64;   // one wave: the solve's barriers cost nothing
 
-// Entry e of the packed system: e < r(r+1)/2 -> H[j][k], j <= k (row-major upper
-// triangle); else b[e - r(r+1)/2].
-__device__ __forceinline__ void decode_entry(int e, int r, int& j, int& k, bool& is_b) {
-  const int nh = r * (r + 1) / 2;
-  if (e >= nh) { is_b = true; j = e - nh; k = 0; return; }
-  is_b = false;
-  int row = 0, start = 0;
-  while (e >= start + (r - row)) { start += r - row; ++row; }
-  j = row;
-  k = row + (e - start);
-}
-
-// Factor and solve in the last block of a simulation. H and y live in LDS.
+// Factor and solve in one wave. H and y live in LDS.
 __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 1], double* y,
                                  int* bad) {
   const int r = S.r, tid = threadIdx.x;
@@ -96,12 +84,13 @@ __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 
   if (final_iter && tid == 0) *S.step += 1;
 }
 
-__global__ __launch_bounds__(kThreads) void gn_partial_kernel(const SimDev* __restrict__ sims,
-                                                      const BlockWork* __restrict__ work,
-                                                      const int32_t* __restrict__ n_work, int iter) {
-  __shared__ float Jl[3 * kMaxR][kGnChunk + 1];
-  __shared__ double R[3][kGnChunk];
-  __shared__ double part[kThreads];
+// Iterations k >= 1: residual r = u(z^(k)) - u^n - dt v^{n+1}, from the field kernel's
+// values at the iterate (or, with tangent forms, the trapezoid rule along z^(k) - z_n).
+__global__ __launch_bounds__(kGnThreads) void gn_partial_kernel(const SimDev* __restrict__ sims,
+                                                                const BlockWork* __restrict__ work,
+                                                                const int32_t* __restrict__ n_work,
+                                                                int iter) {
+  __shared__ GnChunkLds<kGnThreads> sh;
   const int tid = threadIdx.x;
   const int total = *n_work;
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
@@ -110,75 +99,39 @@ __global__ __launch_bounds__(kThreads) void gn_partial_kernel(const SimDev* __re
     if (iter >= S.gn_iters) continue;
     const int r = S.r, ns = S.n_samp, p0 = wk.p0;
     const int cnt = min(kGnChunk, ns - p0);
-    const float* J = iter == 0 ? S.J : S.J2;
-    for (int e = tid; e < 3 * r * kGnChunk; e += kThreads) {
-      const int row = e / kGnChunk, col = e % kGnChunk;
-      Jl[row][col] = col < cnt ? J[(int64_t)row * ns + p0 + col] : 0.f;
-    }
-    for (int e = tid; e < 3 * kGnChunk; e += kThreads) {
-      const int c = e / kGnChunk, col = e % kGnChunk;
+    gn_stage_jacobian(S, S.J2, p0, cnt, sh);
+    const int p = p0 + tid;
+#pragma unroll
+    for (int c = 0; c < 3 && tid < kGnChunk; ++c) {
       double rv = 0.0;
-      if (col < cnt) {
-        const int p = p0 + col;
+      if (tid < cnt) {
         rv = -S.dt_d * (double)S.vnew[c * ns + p];
-        if (iter > 0) {
-          if (S.tangent_forms) {
-            // u(z^(k)) - u(z_n) by the trapezoid rule along z^(k) - z_n from the two
-            // Jacobians (error O(|dz|^3)), avoiding the difference of two BF16 values
-            const double* zc = S.z + r;
-            const double* zi = S.z + 2 * r;
-            double du = 0.0;
-            for (int j = 0; j < r; ++j) {
-              const int64_t o = (int64_t)(c * r + j) * ns + p;
-              du += 0.5 * ((double)S.J[o] + (double)S.J2[o]) * (zi[j] - zc[j]);
-            }
-            rv += du;
-          } else {
-            rv += (double)S.u_gn[c * ns + p] - (double)S.u_n[c * S.n_int + p];
+        if (S.tangent_forms) {
+          // u(z^(k)) - u(z_n) by the trapezoid rule along z^(k) - z_n from the two
+          // Jacobians (error O(|dz|^3)), avoiding the difference of two BF16 values
+          const double* zc = S.z + r;
+          const double* zi = S.z + 2 * r;
+          double du = 0.0;
+          for (int j = 0; j < r; ++j) {
+            const int64_t o = (int64_t)(c * r + j) * ns + p;
+            du += 0.5 * ((double)S.J[o] + (double)S.J2[o]) * (zi[j] - zc[j]);
           }
+          rv += du;
+        } else {
+          rv += (double)S.u_gn[c * ns + p] - (double)S.u_n[c * S.n_int + p];
         }
       }
-      R[c][col] = rv;
+      sh.R[c][tid] = rv;
     }
     __syncthreads();
-    const int E = r * (r + 1) / 2 + r;
-    const int G = E >= kThreads ? 1 : kThreads / E;   // column groups per entry
-    double* out = S.gn_part + (int64_t)(p0 / kGnChunk) * E;
-    for (int e0 = 0; e0 < E; e0 += kThreads / G) {
-      const int e = e0 + tid % (kThreads / G);
-      const int g = tid / (kThreads / G);
-      double acc = 0.0;
-      if (e < E && g < G) {
-        int j, k;
-        bool is_b;
-        decode_entry(e, r, j, k, is_b);
-        for (int c = 0; c < 3; ++c) {
-          const float* a = Jl[c * r + j];
-          if (is_b) {
-            for (int col = g; col < kGnChunk; col += G) acc += (double)a[col] * R[c][col];
-          } else {
-            const float* bb = Jl[c * r + k];
-            for (int col = g; col < kGnChunk; col += G) acc += (double)a[col] * (double)bb[col];
-          }
-        }
-      }
-      part[tid] = acc;
-      __syncthreads();
-      if (tid < kThreads / G && e0 + tid < E) {
-        double s = 0.0;
-        for (int gg = 0; gg < G; ++gg) s += part[gg * (kThreads / G) + tid];
-        out[e0 + tid] = s;
-      }
-      __syncthreads();
-    }
-    __syncthreads();
+    gn_reduce_chunk(S, p0, sh);
   }
 }
 
-__global__ __launch_bounds__(kThreads) void gn_solve_kernel(const SimDev* __restrict__ sims,
-                                                            const int32_t* __restrict__ n_sims,
-                                                            int iter) {
-  __shared__ double part[kThreads];
+__global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* __restrict__ sims,
+                                                                 const int32_t* __restrict__ n_sims,
+                                                                 int iter) {
+  __shared__ double part[kSolveThreads];
   __shared__ double H[kMaxR][kMaxR + 1];
   __shared__ double y[kMaxR];
   __shared__ int bad;
@@ -187,16 +140,16 @@ __global__ __launch_bounds__(kThreads) void gn_solve_kernel(const SimDev* __rest
     const SimDev& S = sims[si];
     if (iter >= S.gn_iters) continue;
     const int r = S.r;
-    const int E = r * (r + 1) / 2 + r;
-    const int G = E >= kThreads ? 1 : kThreads / E;
+    const int E = gn_entries_dev(r);
+    const int G = E >= kSolveThreads ? 1 : kSolveThreads / E;
     if (tid == 0) bad = 0;
     __syncthreads();
     // Sum the chunk partials: thread (e, g) adds chunks g, g + G, ... with independent
     // loads, then the G groups are added in a fixed order.
     const int nch = S.n_gn_chunks;
-    for (int e0 = 0; e0 < E; e0 += kThreads / G) {
-      const int e = e0 + tid % (kThreads / G);
-      const int g = tid / (kThreads / G);
+    for (int e0 = 0; e0 < E; e0 += kSolveThreads / G) {
+      const int e = e0 + tid % (kSolveThreads / G);
+      const int g = tid / (kSolveThreads / G);
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       if (e < E && g < G) {
         const double* src = S.gn_part + e;
@@ -211,12 +164,12 @@ __global__ __launch_bounds__(kThreads) void gn_solve_kernel(const SimDev* __rest
       }
       part[tid] = (a0 + a1) + (a2 + a3);
       __syncthreads();
-      if (tid < kThreads / G && e0 + tid < E) {
+      if (tid < kSolveThreads / G && e0 + tid < E) {
         double acc = 0.0;
-        for (int gg = 0; gg < G; ++gg) acc += part[gg * (kThreads / G) + tid];
+        for (int gg = 0; gg < G; ++gg) acc += part[gg * (kSolveThreads / G) + tid];
         int j, k;
         bool is_b;
-        decode_entry(e0 + tid, r, j, k, is_b);
+        gn_decode_entry(e0 + tid, r, j, k, is_b);
         if (!isfinite(acc)) atomicOr(&bad, 2);
         if (is_b) {
           y[j] = -acc;  // right-hand side -J^T r
@@ -234,11 +187,17 @@ __global__ __launch_bounds__(kThreads) void gn_solve_kernel(const SimDev* __rest
 
 }  // namespace
 
-hipError_t launch_gn(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                     const int32_t* n_sims, int iter, int grid, int grid_sims, hipStream_t s) {
-  if (grid <= 0 || grid_sims <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gn_partial_kernel, dim3(grid), dim3(kThreads), 0, s, sims, work, n_work, iter);
-  hipLaunchKernelGGL(gn_solve_kernel, dim3(grid_sims), dim3(kThreads), 0, s, sims, n_sims, iter);
+hipError_t launch_gn_partial(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
+                             int iter, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gn_partial_kernel, dim3(grid), dim3(kGnThreads), 0, s, sims, work, n_work, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_gn_solve(const SimDev* sims, const int32_t* n_sims, int iter, int grid_sims,
+                           hipStream_t s) {
+  if (grid_sims <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gn_solve_kernel, dim3(grid_sims), dim3(kSolveThreads), 0, s, sims, n_sims, iter);
   return hipGetLastError();
 }
 

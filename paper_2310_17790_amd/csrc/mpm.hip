@@ -12,16 +12,25 @@
 // Kernels of one step:
 //   bin      each integration particle finds its stencil base cell and its bin (a cube
 //            of bin_edge^3 cells), counts itself in the bin and remembers its rank;
-//   scan     one workgroup per simulation: prefix sum of the bin counts, the list of node
-//            blocks (same tiling as the bins) that receive mass, counts reset to zero;
-//   scatter  each particle writes its P2G record (x, m v, A, index) into bin order;
+//   alloc    one workgroup per simulation: the first particle of each bin (in particle
+//            order) gets the bin's record slots from a block-wide prefix sum, the bin is
+//            listed as non-empty and the node blocks its particles reach are marked in an
+//            LDS bitmap, which is then compacted into the list of active node blocks;
+//            finally every particle writes its index at its bin's slot + rank;
+//   sort     one wave per non-empty bin sorts the bin's indices and writes the P2G
+//            records (x, m v, A, index) in that order;
 //   gather   one workgroup per active node block stages the records of the 2 x 2 x 2 bins
-//            whose particles reach it in LDS, sorted by particle index, sums every node's
-//            mass and momentum in that order (deterministic), applies the grid update and
-//            stores the node's new velocity;
-//   g2p      each sample particle sums w_ip v_i over its 27 stencil nodes.
+//            whose particles reach it in LDS, sums every node's mass and momentum in that
+//            order (deterministic: where each bin's slots lie does not matter, only the
+//            sorted order inside a bin and the fixed order of the bins), applies the grid
+//            update and stores the node's new velocity;
+//   g2p      each sample particle sums w_ip v_i over its 27 stencil nodes, and the block
+//            reduces its chunk of the first Gauss-Newton system (gn_reduce.h).
 // A node block only holds values written this step; nodes outside active blocks are never
-// read because every particle's stencil lies in active blocks.
+// read because every particle's stencil lies in active blocks. A bin's slot range and
+// count are valid only in the epoch that set them, so no per-step clearing of the bin
+// tables is needed.
+#include "gn_reduce.h"
 #include "nsf_dev.h"
 
 namespace nsf {
@@ -66,11 +75,15 @@ __device__ __forceinline__ void particle_x(const SimDev& S, int p, int gi, float
 // ---- bin ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kMpmBlock) void bin_kernel(const SimDev* __restrict__ sims,
                                                         const BlockWork* __restrict__ work,
-                                                        const int32_t* __restrict__ n_work) {
+                                                        const int32_t* __restrict__ n_work,
+                                                        int32_t* __restrict__ claims) {
+  // the field kernels' claim counters of this step start from zero
+  if (blockIdx.x == 0 && threadIdx.x < kClaimCounters) claims[threadIdx.x] = 0;
   const int total = *n_work;
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
     const BlockWork wk = work[b];
     const SimDev& S = sims[wk.sim];
+    if (wk.p0 == 0 && threadIdx.x == 0) *S.epoch += 1;   // this step's binning epoch
     const int p = wk.p0 + threadIdx.x;
     if (p >= S.n_int) continue;
     float x[3];
@@ -88,8 +101,10 @@ __global__ __launch_bounds__(kMpmBlock) void bin_kernel(const SimDev* __restrict
   }
 }
 
-// ---- scan --------------------------------------------------------------------------
-constexpr int kScanThreads = 1024;
+// ---- allocate + place ---------------------------------------------------------------
+constexpr int kAllocThreads = 1024;
+constexpr int kAllocBatch = 8;    // particles per thread per batch of loads
+constexpr int kMaxBins = 32768;   // 32 bins per axis at most
 
 // Exclusive scan of one value per thread over the workgroup; returns the prefix and the
 // workgroup total in *total.
@@ -103,78 +118,98 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wave_sums, int* 
   }
   if (lane == 63) wave_sums[wave] = incl;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) {
-      const int t = wave_sums[w];
-      wave_sums[w] = run;
-      run += t;
+  if (threadIdx.x < 64) {
+    const int w = threadIdx.x;
+    int x = w < kAllocThreads / 64 ? wave_sums[w] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(x, o);
+      if (w >= o) x += t;
     }
-    wave_sums[kScanThreads / 64] = run;
+    if (w < kAllocThreads / 64) wave_sums[w] = x;   // inclusive over waves
   }
   __syncthreads();
-  const int excl = wave_sums[wave] + incl - v;
-  *total = wave_sums[kScanThreads / 64];
+  const int excl = (wave > 0 ? wave_sums[wave - 1] : 0) + incl - v;
+  *total = wave_sums[kAllocThreads / 64 - 1];
   __syncthreads();
   return excl;
 }
 
-__device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
-
-// Counts are staged in (dynamic) LDS with one pad word per 32 so that each thread can walk
-// its contiguous range without bank conflicts; global reads and writes stay coalesced.
-__global__ __launch_bounds__(kScanThreads) void bin_scan_kernel(const SimDev* __restrict__ sims,
-                                                                const int32_t* __restrict__ n_sims) {
-  extern __shared__ int s_cnt[];
-  __shared__ int wave_sums[kScanThreads / 64 + 1];
-  __shared__ uint32_t mark[32768 / 32];
+__global__ __launch_bounds__(kAllocThreads) void alloc_place_kernel(const SimDev* __restrict__ sims,
+                                                                    const int32_t* __restrict__ n_sims) {
+  extern __shared__ int s_start[];              // [n_bins] first slot of each non-empty bin
+  __shared__ uint32_t mark[kMaxBins / 32];      // node blocks reached this step
+  __shared__ int wave_sums[kAllocThreads / 64];
   const int tid = threadIdx.x;
-  const int total_sims = *n_sims;
-  for (int s = blockIdx.x; s < total_sims; s += gridDim.x) {
+  for (int s = blockIdx.x; s < *n_sims; s += gridDim.x) {
     const SimDev& S = sims[s];
-    int32_t* __restrict__ cnt_g = S.bin_cnt;
-    int32_t* __restrict__ start_g = S.bin_start;
-    int32_t* __restrict__ nonempty = S.nonempty;
-    const int nb = S.n_bins, nbs = S.nbs;
-    for (int i = tid; i < nb; i += kScanThreads) s_cnt[pad32(i)] = cnt_g[i];
-    for (int wd = tid; wd < (nb + 31) / 32; wd += kScanThreads) mark[wd] = 0u;
-    __syncthreads();
-    const int per = (nb + kScanThreads - 1) / kScanThreads;
-    const int lo = min(nb, tid * per), hi = min(nb, lo + per);
+    const int n = S.n_int, nb = S.n_bins, nbs = S.nbs;
+    const int nwords = (nb + 31) / 32;
+    for (int wd = tid; wd < nwords; wd += kAllocThreads) mark[wd] = 0u;
+    // Thread t owns particles t, t + T, t + 2T, ... (coalesced); the first particle of each
+    // bin (rank 0) allocates the bin. Loads are issued kAllocBatch at a time.
     int local = 0, ne = 0;
-    for (int i = lo; i < hi; ++i) {
-      const int c = s_cnt[pad32(i)];
-      local += c;
-      ne += c > 0;
+    for (int p0 = 0; p0 < n; p0 += kAllocThreads * kAllocBatch) {
+      int bin[kAllocBatch], cnt[kAllocBatch];
+#pragma unroll
+      for (int u = 0; u < kAllocBatch; ++u) {
+        const int p = p0 + u * kAllocThreads + tid;
+        bin[u] = -1;
+        if (p < n) {
+          const int b = S.pbin[p], rk = S.prank[p];
+          bin[u] = (b >= 0 && rk == 0) ? b : -1;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kAllocBatch; ++u) cnt[u] = bin[u] >= 0 ? S.bin_cnt[bin[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < kAllocBatch; ++u) {
+        local += cnt[u];
+        ne += bin[u] >= 0;
+      }
     }
-    int all, n_ne;
-    int run = block_exclusive_scan(local, wave_sums, &all);
+    int used, n_ne;
+    int run = block_exclusive_scan(local, wave_sums, &used);
     int ne_pos = block_exclusive_scan(ne, wave_sums, &n_ne);
-    for (int i = lo; i < hi; ++i) {
-      const int c = s_cnt[pad32(i)];
-      s_cnt[pad32(i)] = run;
-      run += c;
-      if (c == 0) continue;
-      nonempty[ne_pos++] = i;
-      // node blocks reached by bin i: i + {0, 1}^3
-      const int bx = i / (nbs * nbs), by = (i / nbs) % nbs, bz = i % nbs;
-      for (int d = 0; d < 8; ++d) {
-        const int x = bx + (d >> 2), y = by + ((d >> 1) & 1), z = bz + (d & 1);
-        if (x < nbs && y < nbs && z < nbs) {
-          const int k = (x * nbs + y) * nbs + z;
-          atomicOr(&mark[k >> 5], 1u << (k & 31));
+    const int ep = *S.epoch;
+    for (int p0 = 0; p0 < n; p0 += kAllocThreads * kAllocBatch) {
+      int bin[kAllocBatch], cnt[kAllocBatch];
+#pragma unroll
+      for (int u = 0; u < kAllocBatch; ++u) {
+        const int p = p0 + u * kAllocThreads + tid;
+        bin[u] = -1;
+        if (p < n) {
+          const int b = S.pbin[p], rk = S.prank[p];
+          bin[u] = (b >= 0 && rk == 0) ? b : -1;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kAllocBatch; ++u) cnt[u] = bin[u] >= 0 ? S.bin_cnt[bin[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < kAllocBatch; ++u) {
+        const int b = bin[u];
+        if (b < 0) continue;
+        S.bin_cnt[b] = 0;   // counts start from zero next step
+        S.seg_cnt[b] = cnt[u];
+        S.bin_start[b] = run;
+        S.bin_epoch[b] = ep;
+        s_start[b] = run;
+        run += cnt[u];
+        S.nonempty[ne_pos++] = b;
+        // node blocks reached by the bin's particles: bin + {0, 1}^3
+        const int bx = b / (nbs * nbs), by = (b / nbs) % nbs, bz = b % nbs;
+        for (int d = 0; d < 8; ++d) {
+          const int x = bx + (d >> 2), y = by + ((d >> 1) & 1), z = bz + (d & 1);
+          if (x < nbs && y < nbs && z < nbs) {
+            const int k = (x * nbs + y) * nbs + z;
+            atomicOr(&mark[k >> 5], 1u << (k & 31));
+          }
         }
       }
     }
     __syncthreads();
-    for (int i = tid; i < nb; i += kScanThreads) {
-      start_g[i] = s_cnt[pad32(i)];
-      cnt_g[i] = 0;   // counts start from zero next step
-    }
-    if (tid == 0) start_g[nb] = all;
     // compact the marked node blocks in index order
-    const int nwords = (nb + 31) / 32;
-    const int wper = (nwords + kScanThreads - 1) / kScanThreads;
+    const int wper = (nwords + kAllocThreads - 1) / kAllocThreads;
     const int wlo = min(nwords, tid * wper), whi = min(nwords, wlo + wper);
     int cnt = 0;
     for (int wd = wlo; wd < whi; ++wd) cnt += __popc(mark[wd]);
@@ -188,26 +223,24 @@ __global__ __launch_bounds__(kScanThreads) void bin_scan_kernel(const SimDev* __
         S.active[pos++] = wd * 32 + bit;
       }
     }
+    // place: every particle's index at its bin's slot + rank
+    for (int p0 = 0; p0 < n; p0 += kAllocThreads * kAllocBatch) {
+      int bin[kAllocBatch], rk[kAllocBatch];
+#pragma unroll
+      for (int u = 0; u < kAllocBatch; ++u) {
+        const int p = p0 + u * kAllocThreads + tid;
+        bin[u] = p < n ? S.pbin[p] : -1;
+        rk[u] = p < n ? S.prank[p] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kAllocBatch; ++u)
+        if (bin[u] >= 0) S.sorted[s_start[bin[u]] + rk[u]] = p0 + u * kAllocThreads + tid;
+    }
     if (tid == 0) {
       S.n_active[0] = n_act;
       S.n_active[1] = n_ne;
     }
     __syncthreads();
-  }
-}
-
-// ---- place -------------------------------------------------------------------------
-__global__ __launch_bounds__(kMpmBlock) void place_kernel(const SimDev* __restrict__ sims,
-                                                          const BlockWork* __restrict__ work,
-                                                          const int32_t* __restrict__ n_work) {
-  const int total = *n_work;
-  for (int b = blockIdx.x; b < total; b += gridDim.x) {
-    const BlockWork wk = work[b];
-    const SimDev& S = sims[wk.sim];
-    const int p = wk.p0 + threadIdx.x;
-    if (p >= S.n_int) continue;
-    const int bin = S.pbin[p];
-    if (bin >= 0) S.sorted[S.bin_start[bin] + S.prank[p]] = p;
   }
 }
 
@@ -255,7 +288,7 @@ __global__ __launch_bounds__(64) void bin_sort_kernel(const SimDev* __restrict__
     for (int k = blockIdx.x; k < ne; k += gridDim.x) {
       const int b = S.nonempty[k];
       const int start = S.bin_start[b];
-      const int cnt = S.bin_start[b + 1] - start;
+      const int cnt = S.seg_cnt[b];
       int32_t* seg = S.sorted + start;
       if (cnt <= 64) {
         int v = lane < cnt ? seg[lane] : 0x7fffffff;
@@ -325,6 +358,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
   __shared__ float s_red[4][64][4];
   __shared__ int s_seg[9];            // the source bins' record ranges, concatenated
   __shared__ int s_from[8];
+  __shared__ int s_cnt[8];
   const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
   const int total_sims = *n_sims;
   for (int s = 0; s < total_sims; ++s) {
@@ -334,23 +368,33 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
     const int nodes = B * B * B;
     const int npl = (nodes + 63) / 64;   // nodes per lane
     const double t_new = (double)(*S.step + 1) * S.dt_d;
+    const int ep = *S.epoch;
     for (int k = blockIdx.x; k < nact; k += gridDim.x) {
       const int blk = S.active[k];
       const int bx = blk / (nbs * nbs), by = (blk / nbs) % nbs, bz = blk % nbs;
-      // source bins in a fixed order: the block itself and its lower neighbours
+      // source bins in a fixed order: the block itself and its lower neighbours (looked up
+      // by 8 threads at once, then prefix-summed)
+      if (tid < 8) {
+        const int d = tid;
+        const int sx = bx - (d >> 2), sy = by - ((d >> 1) & 1), sz = bz - (d & 1);
+        int c = 0, from = 0;
+        if (sx >= 0 && sy >= 0 && sz >= 0) {
+          const int sb = (sx * nbs + sy) * nbs + sz;
+          const int e = S.bin_epoch[sb], f = S.bin_start[sb], cc = S.seg_cnt[sb];
+          if (e == ep) {
+            from = f;
+            c = cc;
+          }
+        }
+        s_from[d] = from;
+        s_cnt[d] = c;
+      }
+      __syncthreads();
       if (tid == 0) {
         int run = 0;
         for (int d = 0; d < 8; ++d) {
-          const int sx = bx - (d >> 2), sy = by - ((d >> 1) & 1), sz = bz - (d & 1);
-          int c = 0, from = 0;
-          if (sx >= 0 && sy >= 0 && sz >= 0) {
-            const int sb = (sx * nbs + sy) * nbs + sz;
-            from = S.bin_start[sb];
-            c = S.bin_start[sb + 1] - from;
-          }
           s_seg[d] = run;
-          s_from[d] = from;
-          run += c;
+          run += s_cnt[d];
         }
         s_seg[8] = run;
       }
@@ -438,69 +482,81 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
   }
 }
 
-// ---- G2P ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kMpmBlock) void g2p_kernel(const SimDev* __restrict__ sims,
-                                                        const BlockWork* __restrict__ work,
-                                                        const int32_t* __restrict__ n_work) {
+// ---- G2P + first Gauss-Newton chunk -------------------------------------------------
+__global__ __launch_bounds__(kGnThreads) void g2p_gn_kernel(const SimDev* __restrict__ sims,
+                                                            const BlockWork* __restrict__ work,
+                                                            const int32_t* __restrict__ n_work) {
+  __shared__ GnChunkLds<kGnThreads> sh;
+  const int tid = threadIdx.x;
   const int total = *n_work;
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
     const BlockWork wk = work[b];
     const SimDev& S = sims[wk.sim];
-    const int p = wk.p0 + threadIdx.x;
-    if (p >= S.n_samp) continue;
-    float x[3];
-    particle_x(S, p, plan_row(S)[p], x);
-    const Stencil st = make_stencil(x, S.inv_dx, S.grid_n);
+    const int ns = S.n_samp;
+    const int p = wk.p0 + tid;
+    const int cnt = min(kGnChunk, ns - wk.p0);
+    gn_stage_jacobian(S, S.J, wk.p0, cnt, sh);
     float v[3] = {0.f, 0.f, 0.f};
-    if (st.ok) {
-      const int n = S.grid_n;
+    if (tid < kGnChunk && p < ns) {
+      float x[3];
+      particle_x(S, p, plan_row(S)[p], x);
+      const Stencil st = make_stencil(x, S.inv_dx, S.grid_n);
+      if (st.ok) {
+        const int n = S.grid_n;
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const float wij = st.w[0][i] * st.w[1][j];
-          const int64_t row = ((int64_t)(st.base[0] + i) * n + (st.base[1] + j)) * n + st.base[2];
+          for (int j = 0; j < 3; ++j) {
+            const float wij = st.w[0][i] * st.w[1][j];
+            const int64_t row = ((int64_t)(st.base[0] + i) * n + (st.base[1] + j)) * n + st.base[2];
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const float w = wij * st.w[2][k];
-            const float4 g = S.grid[row + k];
-            v[0] += w * g.x;
-            v[1] += w * g.y;
-            v[2] += w * g.z;
+            for (int k = 0; k < 3; ++k) {
+              const float w = wij * st.w[2][k];
+              const float4 g = S.grid[row + k];
+              v[0] += w * g.x;
+              v[1] += w * g.y;
+              v[2] += w * g.z;
+            }
           }
-        }
-    }
+      }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) S.vnew[c * S.n_samp + p] = v[c];
+      for (int c = 0; c < 3; ++c) S.vnew[c * ns + p] = v[c];
+    }
+    // iteration 0: u(z_n) - u^n vanishes, r = -dt v^{n+1}
+    if (tid < kGnChunk) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sh.R[c][tid] = p < ns ? -S.dt_d * (double)v[c] : 0.0;
+    }
+    __syncthreads();
+    gn_reduce_chunk(S, wk.p0, sh);
   }
 }
 
 }  // namespace
 
 hipError_t launch_p2g(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
-                      const int32_t* n_sims, int grid_particles, int grid_sims, int grid_blocks,
-                      hipStream_t s) {
+                      const int32_t* n_sims, int32_t* claims, int grid_particles, int grid_sims,
+                      int grid_blocks, hipStream_t s) {
   if (grid_particles <= 0) return hipSuccess;
-  constexpr int scan_lds = (32768 + 32768 / 32) * 4;
+  constexpr int alloc_lds = kMaxBins * 4;
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)bin_scan_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, scan_lds);
+    const hipError_t e = hipFuncSetAttribute((const void*)alloc_place_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, alloc_lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(bin_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int);
-  hipLaunchKernelGGL(bin_scan_kernel, dim3(grid_sims), dim3(kScanThreads), scan_lds, s, sims, n_sims);
-  hipLaunchKernelGGL(place_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int);
+  hipLaunchKernelGGL(bin_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int, claims);
+  hipLaunchKernelGGL(alloc_place_kernel, dim3(grid_sims), dim3(kAllocThreads), alloc_lds, s, sims, n_sims);
   hipLaunchKernelGGL(bin_sort_kernel, dim3(grid_blocks), dim3(64), 0, s, sims, n_sims);
   hipLaunchKernelGGL(gather_kernel, dim3(grid_blocks), dim3(kGatherThreads), 0, s, sims, n_sims);
   return hipGetLastError();
 }
 
-hipError_t launch_g2p(const SimDev* sims, const BlockWork* work, const int32_t* n_work, int grid,
-                      hipStream_t s) {
+hipError_t launch_g2p_gn(const SimDev* sims, const BlockWork* work_gn, const int32_t* n_work_gn,
+                         int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(g2p_kernel, dim3(grid), dim3(kMpmBlock), 0, s, sims, work, n_work);
+  hipLaunchKernelGGL(g2p_gn_kernel, dim3(grid), dim3(kGnThreads), 0, s, sims, work_gn, n_work_gn);
   return hipGetLastError();
 }
 

@@ -9,6 +9,8 @@ namespace nsf {
 constexpr int kMaxR = 32;          // largest latent dimension
 constexpr int kTile = 32;          // points per wave tile (MFMA N dimension)
 constexpr int kGnChunk = 128;      // sample points per Gauss-Newton reduction block
+constexpr int kGnThreads = 256;    // threads of a Gauss-Newton reduction block
+constexpr int kClaimCounters = 8;  // work-claim counters of the field kernels, zeroed per step
 constexpr int kMpmBlock = 256;     // particles per P2G / G2P block
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -98,11 +100,14 @@ struct SimDev {
   // particle binning for the gather-form P2G: bins of bin_edge^3 cells, nbs per axis
   int32_t bin_edge, nbs, n_bins, pad2;
   int32_t* bin_cnt;                  // [n_bins] particles per bin (zero between steps)
-  int32_t* bin_start;                // [n_bins + 1] exclusive prefix of bin_cnt
+  int32_t* bin_start;                // [n_bins] first record slot of each bin (this step)
+  int32_t* seg_cnt;                  // [n_bins] records of each bin (this step)
+  int32_t* bin_epoch;                // [n_bins] epoch in which bin_start / seg_cnt were set
+  int32_t* epoch;                    // binning epoch, +1 every step
   int32_t* pbin;                     // [n_int] bin of each integration particle, -1 if off-grid
   int32_t* prank;                    // [n_int] slot of the particle inside its bin
-  float* rec;                        // [n_int][16] P2G records in bin order
-  int32_t* sorted;                   // [n_int] particle indices grouped by bin
+  float* rec;                        // [n_int][16] P2G records, each bin contiguous
+  int32_t* sorted;                   // [n_int] particle indices, each bin contiguous
   int32_t* active;                   // [n_bins] node blocks that receive mass this step
   int32_t* nonempty;                 // [n_bins] bins holding particles this step
   int32_t* n_active;                 // [2]: active node blocks, non-empty bins
@@ -126,15 +131,21 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
 int fields_max_tangents(int width, bool bf16);
 int fields_group_waves(int tc);   // waves (32-point tiles) per workgroup
 
-// MPM transfers: bin (per integration particle), scan (per sim), scatter (per integration
-// particle), gather + grid update (per active node block), G2P (per sample particle).
+// MPM transfers: bin (per integration particle; also zeroes the step's claim counters),
+// allocate and place (per sim), sort and write records (per non-empty bin), gather + grid
+// update (per active node block).
 hipError_t launch_p2g(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
-                      const int32_t* n_sims, int grid_particles, int grid_sims, int grid_blocks,
-                      hipStream_t s);
-hipError_t launch_g2p(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                      int grid, hipStream_t s);
+                      const int32_t* n_sims, int32_t* claims, int grid_particles, int grid_sims,
+                      int grid_blocks, hipStream_t s);
+// G2P at the sample particles fused with the first Gauss-Newton reduction: work items are
+// Gauss-Newton chunks (kGnChunk sample particles).
+hipError_t launch_g2p_gn(const SimDev* sims, const BlockWork* work_gn, const int32_t* n_work_gn,
+                         int grid, hipStream_t s);
 constexpr int kSegMax = 512;   // bin segments up to this size are summed in index order
-hipError_t launch_gn(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                     const int32_t* n_sims, int iter, int grid, int grid_sims, hipStream_t s);
+// Gauss-Newton: chunk reduction of iteration iter >= 1, and the per-sim solve of any iteration.
+hipError_t launch_gn_partial(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
+                             int iter, int grid, hipStream_t s);
+hipError_t launch_gn_solve(const SimDev* sims, const int32_t* n_sims, int iter, int grid_sims,
+                           hipStream_t s);
 
 }  // namespace nsf
