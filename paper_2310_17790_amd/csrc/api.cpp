@@ -439,7 +439,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.gP = P.persistent ? 4 * cus : P.nP;
   P.gGN = P.persistent ? 4 * cus : P.nGN;
   P.gSims = P.persistent ? cus : P.nsims;
-  P.gBlk = 2 * cus;   // gather workgroups loop over each sim's active node blocks
+  P.gBlk = 5 * cus;   // gather workgroups (5 fit per CU) loop over each sim's active node blocks
   if (P.decode && !P.side) {
     NSF_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
     NSF_HIP(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));

@@ -144,25 +144,27 @@ __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* _
     const int G = E >= kSolveThreads ? 1 : kSolveThreads / E;
     if (tid == 0) bad = 0;
     __syncthreads();
-    // Sum the chunk partials: thread (e, g) adds chunks g, g + G, ... with independent
-    // loads, then the G groups are added in a fixed order.
+    // Sum the chunk partials: thread (e, g) adds chunks g, g + G, ... (16 loads in flight
+    // per batch, four running sums), then the G groups are added in a fixed order.
     const int nch = S.n_gn_chunks;
     for (int e0 = 0; e0 < E; e0 += kSolveThreads / G) {
       const int e = e0 + tid % (kSolveThreads / G);
       const int g = tid / (kSolveThreads / G);
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
       if (e < E && g < G) {
         const double* src = S.gn_part + e;
-        int c = g;
-        for (; c + 3 * G < nch; c += 4 * G) {
-          a0 += src[(int64_t)c * E];
-          a1 += src[(int64_t)(c + G) * E];
-          a2 += src[(int64_t)(c + 2 * G) * E];
-          a3 += src[(int64_t)(c + 3 * G) * E];
+        for (int c0 = g; c0 < nch; c0 += 16 * G) {
+          double v[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int c = c0 + u * G;
+            v[u] = c < nch ? src[(int64_t)c * E] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) a[u & 3] += v[u];
         }
-        for (; c < nch; c += G) a0 += src[(int64_t)c * E];
       }
-      part[tid] = (a0 + a1) + (a2 + a3);
+      part[tid] = (a[0] + a[1]) + (a[2] + a[3]);
       __syncthreads();
       if (tid < kSolveThreads / G && e0 + tid < E) {
         double acc = 0.0;

@@ -147,48 +147,40 @@ __global__ __launch_bounds__(kAllocThreads) void alloc_place_kernel(const SimDev
     const int nwords = (nb + 31) / 32;
     for (int wd = tid; wd < nwords; wd += kAllocThreads) mark[wd] = 0u;
     // Thread t owns particles t, t + T, t + 2T, ... (coalesced); the first particle of each
-    // bin (rank 0) allocates the bin. Loads are issued kAllocBatch at a time.
-    int local = 0, ne = 0;
-    for (int p0 = 0; p0 < n; p0 += kAllocThreads * kAllocBatch) {
-      int bin[kAllocBatch], cnt[kAllocBatch];
+    // bin (rank 0) allocates the bin. Loads are issued kAllocBatch at a time; with at most
+    // T kAllocBatch particles (one round) they are loaded once and kept in registers.
+    const int round = kAllocThreads * kAllocBatch;
+    const bool one = n <= round;
+    int pb[kAllocBatch], rk[kAllocBatch], cnt[kAllocBatch];
+    auto load = [&](int p0) {
 #pragma unroll
       for (int u = 0; u < kAllocBatch; ++u) {
         const int p = p0 + u * kAllocThreads + tid;
-        bin[u] = -1;
-        if (p < n) {
-          const int b = S.pbin[p], rk = S.prank[p];
-          bin[u] = (b >= 0 && rk == 0) ? b : -1;
-        }
+        pb[u] = p < n ? S.pbin[p] : -1;
+        rk[u] = p < n ? S.prank[p] : 1;
       }
 #pragma unroll
-      for (int u = 0; u < kAllocBatch; ++u) cnt[u] = bin[u] >= 0 ? S.bin_cnt[bin[u]] : 0;
+      for (int u = 0; u < kAllocBatch; ++u) cnt[u] = (pb[u] >= 0 && rk[u] == 0) ? S.bin_cnt[pb[u]] : 0;
+    };
+    int local = 0, ne = 0;
+    for (int p0 = 0; p0 < n; p0 += round) {
+      load(p0);
 #pragma unroll
       for (int u = 0; u < kAllocBatch; ++u) {
         local += cnt[u];
-        ne += bin[u] >= 0;
+        ne += (pb[u] >= 0 && rk[u] == 0);
       }
     }
     int used, n_ne;
     int run = block_exclusive_scan(local, wave_sums, &used);
     int ne_pos = block_exclusive_scan(ne, wave_sums, &n_ne);
     const int ep = *S.epoch;
-    for (int p0 = 0; p0 < n; p0 += kAllocThreads * kAllocBatch) {
-      int bin[kAllocBatch], cnt[kAllocBatch];
+    for (int p0 = 0; p0 < n; p0 += round) {
+      if (!one) load(p0);
 #pragma unroll
       for (int u = 0; u < kAllocBatch; ++u) {
-        const int p = p0 + u * kAllocThreads + tid;
-        bin[u] = -1;
-        if (p < n) {
-          const int b = S.pbin[p], rk = S.prank[p];
-          bin[u] = (b >= 0 && rk == 0) ? b : -1;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kAllocBatch; ++u) cnt[u] = bin[u] >= 0 ? S.bin_cnt[bin[u]] : 0;
-#pragma unroll
-      for (int u = 0; u < kAllocBatch; ++u) {
-        const int b = bin[u];
-        if (b < 0) continue;
+        const int b = pb[u];
+        if (b < 0 || rk[u] != 0) continue;
         S.bin_cnt[b] = 0;   // counts start from zero next step
         S.seg_cnt[b] = cnt[u];
         S.bin_start[b] = run;
@@ -211,10 +203,10 @@ __global__ __launch_bounds__(kAllocThreads) void alloc_place_kernel(const SimDev
     // compact the marked node blocks in index order
     const int wper = (nwords + kAllocThreads - 1) / kAllocThreads;
     const int wlo = min(nwords, tid * wper), whi = min(nwords, wlo + wper);
-    int cnt = 0;
-    for (int wd = wlo; wd < whi; ++wd) cnt += __popc(mark[wd]);
+    int n_marked = 0;
+    for (int wd = wlo; wd < whi; ++wd) n_marked += __popc(mark[wd]);
     int n_act;
-    int pos = block_exclusive_scan(cnt, wave_sums, &n_act);
+    int pos = block_exclusive_scan(n_marked, wave_sums, &n_act);
     for (int wd = wlo; wd < whi; ++wd) {
       uint32_t m = mark[wd];
       while (m) {
@@ -224,17 +216,11 @@ __global__ __launch_bounds__(kAllocThreads) void alloc_place_kernel(const SimDev
       }
     }
     // place: every particle's index at its bin's slot + rank
-    for (int p0 = 0; p0 < n; p0 += kAllocThreads * kAllocBatch) {
-      int bin[kAllocBatch], rk[kAllocBatch];
-#pragma unroll
-      for (int u = 0; u < kAllocBatch; ++u) {
-        const int p = p0 + u * kAllocThreads + tid;
-        bin[u] = p < n ? S.pbin[p] : -1;
-        rk[u] = p < n ? S.prank[p] : 0;
-      }
+    for (int p0 = 0; p0 < n; p0 += round) {
+      if (!one) load(p0);
 #pragma unroll
       for (int u = 0; u < kAllocBatch; ++u)
-        if (bin[u] >= 0) S.sorted[s_start[bin[u]] + rk[u]] = p0 + u * kAllocThreads + tid;
+        if (pb[u] >= 0) S.sorted[s_start[pb[u]] + rk[u]] = p0 + u * kAllocThreads + tid;
     }
     if (tid == 0) {
       S.n_active[0] = n_act;
@@ -326,6 +312,7 @@ __global__ __launch_bounds__(64) void bin_sort_kernel(const SimDev* __restrict__
 
 // ---- gather + grid update ----------------------------------------------------------
 constexpr int kGatherThreads = 256;   // 4 groups of 64 lanes
+constexpr int kGatherStage = 256;     // records staged in LDS at a time (~30 KB: 5 blocks per CU)
 constexpr int kMaxNodesPerLane = 8;   // bin_edge <= 8
 
 // New velocity of node (i, j, k) from its mass and momentum (grid update + boundaries).
@@ -350,11 +337,11 @@ __device__ __forceinline__ void node_velocity(const SimDev& S, float m, const fl
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __restrict__ sims,
                                                                 const int32_t* __restrict__ n_sims) {
   // staged records, structure of arrays
-  __shared__ float s_mv[3][kSegMax];
-  __shared__ float s_A[9][kSegMax];
-  __shared__ float s_w[9][kSegMax];
-  __shared__ float s_f[3][kSegMax];
-  __shared__ int s_base[kSegMax];     // packed base cell (10 bits per axis)
+  __shared__ float s_mv[3][kGatherStage];
+  __shared__ float s_A[9][kGatherStage];
+  __shared__ float s_w[9][kGatherStage];
+  __shared__ float s_f[3][kGatherStage];
+  __shared__ int s_base[kGatherStage];   // packed base cell (10 bits per axis)
   __shared__ float s_red[4][64][4];
   __shared__ int s_seg[9];            // the source bins' record ranges, concatenated
   __shared__ int s_from[8];
@@ -404,9 +391,9 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
 #pragma unroll
       for (int q = 0; q < kMaxNodesPerLane; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
       // records in concatenated order (bin order, each bin sorted by particle index),
-      // staged kSegMax at a time
-      for (int c0 = 0; c0 < total; c0 += kSegMax) {
-        const int cnt = min(kSegMax, total - c0);
+      // staged kGatherStage at a time
+      for (int c0 = 0; c0 < total; c0 += kGatherStage) {
+        const int cnt = min(kGatherStage, total - c0);
         for (int i = tid; i < cnt; i += kGatherThreads) {
           const int g = c0 + i;
           int d = 0;
