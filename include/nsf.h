@@ -194,8 +194,8 @@ int32_t nsf_device_count(void);
  * fields is fitted by minimising squared error (Sec. 4.5).
  *
  * nsf_mlp_forward: out device [d][n] (SoA); saved device float32 of nsf_mlp_saved_floats
- *   (width, n) elements, receiving the five hidden pre-activations for the backward
- *   (NULL = inference only).
+ *   (width, n) elements, receiving the five hidden pre-activations for the backward in
+ *   the kernels' internal format (scaled by log2 e; NULL = inference only).
  * nsf_mlp_backward: given dout [d][n] = dLoss/dout, accumulate (+=) dW (device, same
  *   layout and size as the weights) and write dz device [n][r] = dLoss/dz_rows (NULL to
  *   skip). Requires `saved` from the forward of the same weights and inputs.

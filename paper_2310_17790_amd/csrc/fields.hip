@@ -18,6 +18,7 @@
 // in-lane. A wave processes the primal plus up to TC tangents; a Jacobian with more
 // tangents is split over several waves, each recomputing the primal.
 //
+// Pre-activations are carried scaled by log2(e) (see elu_pair and pack.cpp).
 // Layer 1 also runs on FP32 MFMA, with the bias folded in as an input row equal to 1
 // and the tangent seeds as one-hot input columns. FP32 precision: hidden layers on
 // v_mfma_f32_32x32x2_f32. BF16 precision: hidden layers on v_mfma_f32_32x32x16_bf16
@@ -36,22 +37,26 @@ __device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// ELU (alpha = 1) and its derivative from one exponential e = exp(a), taken of a itself
-// (for large a it may overflow to +inf, which the selects discard).
-//   exact: y = a > 0 ? a : e - 1,  dy = a > 0 ? 1 : e.
-//   fast (values about to be rounded to BF16): since exp(a) - 1 >= a and exp(a) - 1 <= 0
-//     for a <= 0, ELU(a) is the median of (e - 1, a, 0), and ELU'(a) = min(e, 1): one op
-//     fewer. For 0 < a < ~3e-4 the FP32 rounding of e can put e - 1 below a, and the
-//     median then returns e - 1, off by at most one FP32 ulp of 1 (1.2e-7) - far below
-//     BF16 resolution, so only the BF16 hidden layers use it.
+// ELU (alpha = 1) on scaled pre-activations. The kernels carry a' = log2(e) a and
+// h' = ELU(a) / ln 2 (pack.cpp folds the scales into the weights), so one exp2 of a'
+// itself gives e = exp(a), with no multiply (for large a' it may overflow to +inf, which
+// the selects discard):
+//   exact: h' = a' > 0 ? a' : (e - 1) / ln 2,  dh'/da' = a' > 0 ? 1 : e.
+//   fast (values about to be rounded to BF16): since (e - 1) / ln 2 >= a' everywhere and
+//     <= 0 for a' <= 0, h' is the median of ((e - 1) / ln 2, a', 0), and dh'/da' =
+//     min(e, 1): one op fewer. For 0 < a' < ~3e-4 the FP32 rounding of e can put
+//     (e - 1) / ln 2 below a', and the median then returns it, off by at most 1.7e-7 -
+//     far below BF16 resolution, so only the BF16 hidden layers use it.
+constexpr float kInvLn2 = 1.44269504088896340736f;
 template <bool FAST>
 __device__ __forceinline__ void elu_pair(float a, float& y, float& dy) {
-  const float e = __expf(a);
+  const float e = __builtin_amdgcn_exp2f(a);
+  const float em1 = fmaf(e, kInvLn2, -kInvLn2);
   if constexpr (FAST) {
-    y = __builtin_amdgcn_fmed3f(e - 1.f, a, 0.f);
+    y = __builtin_amdgcn_fmed3f(em1, a, 0.f);
     dy = fminf(e, 1.f);
   } else {
-    y = a > 0.f ? a : e - 1.f;
+    y = a > 0.f ? a : em1;
     dy = a > 0.f ? 1.f : e;
   }
 }
@@ -177,7 +182,7 @@ __device__ __forceinline__ float output_dot(const float* w6p, int o, int h, cons
   return s + __shfl_xor(s, 32);
 }
 
-// Training: store the pre-activations of one layer, point-major saved[layer][p][W]. The
+// Training: store the (scaled) pre-activations of one layer, point-major saved[layer][p][W]. The
 // 16 registers of M-block mb hold neurons 32 mb + 8 q + 4 h + (0..3), q = 0..3.
 template <int W, int T>
 __device__ __forceinline__ void save_preact(const FieldJob& jb, const f32x16 (&acc)[T][W / 32],

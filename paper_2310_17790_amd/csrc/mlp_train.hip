@@ -28,6 +28,12 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ int acc_n(int mb, int i, int h) { return 32 * mb + 8 * (i >> 2) + 4 * h + (i & 3); }
 
+// The forward kernels carry scaled pre-activations a' = log2(e) a (see pack.cpp): layer 1
+// and the hidden biases are packed times log2(e), the output layer times ln 2.
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2 = 0.69314718055994530942;
+__device__ __forceinline__ float scaled(float w, double f) { return (float)((double)w * f); }
+
 // ---- device packing (same orders as pack.cpp, plus transposed hidden layers) --------
 struct Packed {
   float* w1p; float* whp; uint16_t* whb; float* bhp; float* w6p; float* b6; float* whtp;
@@ -54,7 +60,7 @@ __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int 
     if (t < n1) {
       const int l = t % 64, s2 = (t / 64) % K1s, mb = t / (64 * K1s);
       const int m = 32 * mb + (l & 31), k = 2 * s2 + (l >> 5);
-      P.w1p[t] = k < in1 ? W1[(size_t)m * in1 + k] : (k == in1 ? b1[m] : 0.f);
+      P.w1p[t] = k < in1 ? scaled(W1[(size_t)m * in1 + k], kLog2e) : (k == in1 ? scaled(b1[m], kLog2e) : 0.f);
       continue;
     }
     t -= n1;
@@ -84,13 +90,13 @@ __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int 
     t -= nh;
     if (t < nb) {
       const int s = t % (W / 2), h = (t / (W / 2)) % 2, kk = t / W;
-      P.bhp[t] = hid[kk * ((size_t)W * W + W) + (size_t)W * W + acc_n(s / 16, s % 16, h)];
+      P.bhp[t] = scaled(hid[kk * ((size_t)W * W + W) + (size_t)W * W + acc_n(s / 16, s % 16, h)], kLog2e);
       continue;
     }
     t -= nb;
     if (t < n6) {
       const int s = t % (W / 2), h = (t / (W / 2)) % 2, o = t / W;
-      P.w6p[t] = W6[(size_t)o * W + acc_n(s / 16, s % 16, h)];
+      P.w6p[t] = scaled(W6[(size_t)o * W + acc_n(s / 16, s % 16, h)], kLn2);
       continue;
     }
     t -= n6;
@@ -98,8 +104,11 @@ __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int 
   }
 }
 
-__device__ __forceinline__ float elu_prime(float a) { return a > 0.f ? 1.f : __expf(a); }
-__device__ __forceinline__ float elu(float a) { return a > 0.f ? a : __expf(a) - 1.f; }
+// ELU'(a) and ELU(a) from a saved scaled pre-activation a' = log2(e) a.
+__device__ __forceinline__ float elu_prime(float as) { return as > 0.f ? 1.f : __builtin_amdgcn_exp2f(as); }
+__device__ __forceinline__ float elu(float as) {
+  return as > 0.f ? as * (float)kLn2 : __builtin_amdgcn_exp2f(as) - 1.f;
+}
 
 // ---- backward through the network, 32 points per wave --------------------------------
 template <int W>
@@ -132,7 +141,8 @@ __global__ __launch_bounds__(256) void backward_data_kernel(const float* __restr
 #pragma unroll
       for (int o = 0; o < 9; ++o)
         if (o < d) g += w6p[(o * 2 + h) * KH + s] * d6[o];
-      D[s] = g * elu_prime(a5[acc_n(s / 16, s % 16, h)]);
+      // w6p holds ln 2 W6: undo the scale
+      D[s] = g * (float)kLog2e * elu_prime(a5[acc_n(s / 16, s % 16, h)]);
     }
     for (int L = 4; L >= 0; --L) {
       // store delta_{L+1} point-major

@@ -1,10 +1,20 @@
 // Host-side packing of one field's row-major FP32 parameters into the operand orders the
 // MFMA field kernels read (see fields.hip for the register mapping).
+//
+// Scaled pre-activations. The kernels carry a' = log2(e) a instead of a, so that ELU needs
+// exp2 (one hardware instruction) with no multiply: layer 1's weights and bias and the
+// hidden biases are packed times log2(e); the hidden layers then see h' = ELU(a) / ln 2,
+// which their unscaled weights map to log2(e) (W h + b) again, and the output layer's
+// weights are packed times ln 2. Each scaled value is rounded to FP32 once.
 #include "pack.h"
 
 #include <cstring>
 
 namespace nsf {
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2 = 0.69314718055994530942;
+static inline float scaled(float w, double f) { return (float)((double)w * f); }
 
 static inline int acc_neuron_h(int mb, int i, int h) { return 32 * mb + 8 * (i >> 2) + 4 * h + (i & 3); }
 
@@ -60,8 +70,8 @@ void pack_field(const float* master, int r, int width, int d, float* w1p, float*
       for (int l = 0; l < 64; ++l) {
         const int m = 32 * mb + (l & 31), k = 2 * s2 + (l >> 5);
         float val = 0.f;
-        if (k < in1) val = v.W1[(size_t)m * in1 + k];
-        else if (k == in1) val = v.b1[m];
+        if (k < in1) val = scaled(v.W1[(size_t)m * in1 + k], kLog2e);
+        else if (k == in1) val = scaled(v.b1[m], kLog2e);
         w1p[((size_t)mb * K1s + s2) * 64 + l] = val;
       }
   for (int kk = 0; kk < 4; ++kk) {
@@ -91,12 +101,12 @@ void pack_field(const float* master, int r, int width, int d, float* w1p, float*
     // biases in accumulator order [2][W/2]
     for (int h = 0; h < 2; ++h)
       for (int s = 0; s < W / 2; ++s)
-        bhp[(size_t)kk * W + h * (W / 2) + s] = v.bh[kk][acc_neuron_h(s / 16, s % 16, h)];
+        bhp[(size_t)kk * W + h * (W / 2) + s] = scaled(v.bh[kk][acc_neuron_h(s / 16, s % 16, h)], kLog2e);
   }
   for (int o = 0; o < d; ++o) {
     for (int h = 0; h < 2; ++h)
       for (int s = 0; s < W / 2; ++s)
-        w6p[((size_t)o * 2 + h) * (W / 2) + s] = v.W6[(size_t)o * W + acc_neuron_h(s / 16, s % 16, h)];
+        w6p[((size_t)o * 2 + h) * (W / 2) + s] = scaled(v.W6[(size_t)o * W + acc_neuron_h(s / 16, s % 16, h)], kLn2);
     b6[o] = v.b6[o];
   }
 }
