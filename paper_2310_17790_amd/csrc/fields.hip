@@ -128,21 +128,28 @@ __device__ __forceinline__ void init_hidden(f32x16 (&acc)[T][W / 32], const floa
 template <int W, int T, class APtr>
 __device__ __forceinline__ void hidden_f32(f32x16 (&acc)[T][W / 32], const float (&H)[T][W / 2],
                                            APtr A, int lane, int nt) {
-  constexpr int MB = W / 32;
+  constexpr int MB = W / 32, SG = W / 8;
+  // A fragments (four K-steps each) are read one group ahead of their use.
+  f32x4 a4[2][MB];
 #pragma unroll
-  for (int sg = 0; sg < W / 8; ++sg) {
-    f32x4 a4[MB];
+  for (int mb = 0; mb < MB; ++mb) a4[0][mb] = A[(mb * SG) * 64 + lane];
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) a4[mb] = A[(mb * (W / 8) + sg) * 64 + lane];
+  for (int sg = 0; sg < SG; ++sg) {
+    if (sg + 1 < SG) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) a4[(sg + 1) & 1][mb] = A[(mb * SG + sg + 1) * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        acc[0][mb] = mfma_f32(a4[mb][j], H[0][4 * sg + j], acc[0][mb]);
+        acc[0][mb] = mfma_f32(a4[sg & 1][mb][j], H[0][4 * sg + j], acc[0][mb]);
 #pragma unroll
         for (int t = 1; t < T; ++t)
-          if (t <= nt) acc[t][mb] = mfma_f32(a4[mb][j], H[t][4 * sg + j], acc[t][mb]);
+          if (t <= nt) acc[t][mb] = mfma_f32(a4[sg & 1][mb][j], H[t][4 * sg + j], acc[t][mb]);
       }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -150,19 +157,31 @@ template <int W, int T, class APtr>
 __device__ __forceinline__ void hidden_bf16(f32x16 (&acc)[T][W / 32],
                                             const bf16x8 (&Hb)[T][W / 16],
                                             APtr whb_layer, int lane, int nt) {
-  constexpr int MB = W / 32;
+  constexpr int MB = W / 32, S = W / 16;
+  // A fragments come from LDS two K-steps ahead of their use (a ring of three steps), so
+  // each matrix product does not wait on its own LDS read; scheduling barriers keep the
+  // compiler from sinking the reads back next to their uses.
+  constexpr int D = 2;
+  bf16x8 a[D + 1][MB];
 #pragma unroll
-  for (int s = 0; s < W / 16; ++s) {
-    bf16x8 a[MB];
+  for (int s = 0; s < D; ++s)
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) a[mb] = whb_layer[(mb * (W / 16) + s) * 64 + lane];
+    for (int mb = 0; mb < MB; ++mb) a[s][mb] = whb_layer[(mb * S + s) * 64 + lane];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    if (s + D < S) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) a[(s + D) % (D + 1)][mb] = whb_layer[(mb * S + s + D) * 64 + lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-      acc[0][mb] = mfma_bf16(a[mb], Hb[0][s], acc[0][mb]);
+      acc[0][mb] = mfma_bf16(a[s % (D + 1)][mb], Hb[0][s], acc[0][mb]);
 #pragma unroll
       for (int t = 1; t < T; ++t)
-        if (t <= nt) acc[t][mb] = mfma_bf16(a[mb], Hb[t][s], acc[t][mb]);
+        if (t <= nt) acc[t][mb] = mfma_bf16(a[s % (D + 1)][mb], Hb[t][s], acc[t][mb]);
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
