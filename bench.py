@@ -39,6 +39,25 @@ sys.path.insert(0, ROOT)
 METRIC = "latent steps/s & decoded pts/s vs plain FP32; p99 step latency at 1e-4 err"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # dense MFMA peaks of MI355X
 
+# HBM bytes of one FP32 decode launch (fields_dense_kernel, width 128, 200,000 points) from
+# two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled
+# by what the same counter reads for a plain 256 MiB device copy (bench.py --copy-probe:
+# FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them). Valid only for the
+# kernel source they were taken on (SHA-256 of csrc/fields.hip); null otherwise.
+DECODE_COUNTERS = {"fields_hip_sha256": "4455fea83c3160a86c4b18ceb56b2e6ebea82a6556618e5983a3d4a3387ce911",
+                   "fetch_kib": 2389.0, "write_kib": 2343.8, "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def decode_traffic_bytes():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2310_17790_amd", "csrc", "fields.hip")
+    c = DECODE_COUNTERS
+    if c["fields_hip_sha256"] is None or not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != c["fields_hip_sha256"]:
+        return None
+    return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
+
 
 def primal_flops(width: int, r: int, d: int) -> int:
     """Algorithmic FLOP per point of one field MLP: 2 [(3 + r) w + 4 w^2 + w d]."""
@@ -301,7 +320,8 @@ def main() -> int:
         "delta_x_steps": None if delta_x is None else args.cpu_steps,
         "device_flags": flags,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": decode_traffic_bytes() if args.precision == "fp32" else None,
                      "kernel": f"decode MLP (fields_dense_kernel, width {width}), {P} points, "
                                f"{primal_flops(width, r, 3)} FLOP/point",
                      "avg_ms": dec_ms},
