@@ -67,6 +67,18 @@ __device__ __forceinline__ const int32_t* plan_row(const SimDev& S) {
 
 __device__ __forceinline__ void flag(const SimDev& S, uint32_t bit) { atomicOr(S.flags, bit); }
 
+// Workgroups of a per-sim kernel are dealt to the sims in equal shares: `per` workgroups
+// work on each sim (all of them when there is one sim), each taking items q, q + per, ...
+struct SimShare {
+  int per, groups, q, first;
+  __device__ SimShare(int n_sims) {
+    per = max(1, (int)gridDim.x / max(n_sims, 1));
+    groups = gridDim.x / per;
+    q = blockIdx.x % per;
+    first = blockIdx.x < groups * per ? blockIdx.x / per : n_sims;
+  }
+};
+
 __device__ __forceinline__ void particle_x(const SimDev& S, int p, int gi, float x[3]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) x[c] = S.X[(int64_t)c * S.n_part + gi] + S.u_n[c * S.n_int + p];
@@ -268,10 +280,11 @@ __global__ __launch_bounds__(64) void bin_sort_kernel(const SimDev* __restrict__
   __shared__ int s_buf[kSegMax];
   const int lane = threadIdx.x;
   const int total_sims = *n_sims;
-  for (int s = 0; s < total_sims; ++s) {
+  const SimShare sh(total_sims);
+  for (int s = sh.first; s < total_sims; s += sh.groups) {
     const SimDev& S = sims[s];
     const int ne = S.n_active[1];
-    for (int k = blockIdx.x; k < ne; k += gridDim.x) {
+    for (int k = sh.q; k < ne; k += sh.per) {
       const int b = S.nonempty[k];
       const int start = S.bin_start[b];
       const int cnt = S.seg_cnt[b];
@@ -348,7 +361,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
   __shared__ int s_cnt[8];
   const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
   const int total_sims = *n_sims;
-  for (int s = 0; s < total_sims; ++s) {
+  const SimShare share(total_sims);
+  for (int s = share.first; s < total_sims; s += share.groups) {
     const SimDev& S = sims[s];
     const int nact = S.n_active[0];
     const int B = S.bin_edge, nbs = S.nbs, n = S.grid_n;
@@ -356,7 +370,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
     const int npl = (nodes + 63) / 64;   // nodes per lane
     const double t_new = (double)(*S.step + 1) * S.dt_d;
     const int ep = *S.epoch;
-    for (int k = blockIdx.x; k < nact; k += gridDim.x) {
+    for (int k = share.q; k < nact; k += share.per) {
       const int blk = S.active[k];
       const int bx = blk / (nbs * nbs), by = (blk / nbs) % nbs, bz = blk % nbs;
       // source bins in a fixed order: the block itself and its lower neighbours (looked up

@@ -1,0 +1,93 @@
+"""Edge cases of the GPU path against the FP64 oracle: BF16 stage parity at both widths
+(the width-64 kernels carry four tangents per wave, the width-128 ones two), and the ABI's
+empty calls.
+
+BF16 tolerance. Each of the four hidden layers rounds its weights and its input
+activations to BF16 (unit roundoff u = 2^-9), so a layer's output carries up to ~2u of
+the sum of its terms' magnitudes. Over four layers that is ~8u = 1.6e-2 of the field's
+scale, and 3e-2 of each quantity's largest magnitude is used. The first and output
+layers are FP32. The velocity is the directional derivative at the midpoint. Its error is
+the Jacobian's BF16 error, plus an O(|dz|^3) truncation that is negligible at
+|dz| ~ 2e-3.
+"""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle.step import OracleSim
+from paper_2310_17790_amd import _abi as A
+from paper_2310_17790_amd.sim import Sim
+
+pytestmark = pytest.mark.gpu
+
+TOL_BF16 = 3e-2
+
+
+def _soa(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+@pytest.mark.parametrize("width", [64, 128])
+def test_bf16_stage_parity(width):
+    r, n = 6, 1000
+    w = copy.deepcopy(synth.small_cube(seed=5, r=r, width=width, n=n, bias_scale=0.1))
+    w.z_prev = w.z0 - 2e-3 * np.random.default_rng(7).normal(size=r)
+    print(f"\n[case] bf16 stage parity width={width}", flush=True)
+    s = torch.cuda.Stream()
+    sim = Sim(w, precision="bf16", stream=s)
+    sim.refresh(stream=s)
+    s.synchronize()
+    o = OracleSim(w)
+    idx = o.indices(0)
+    x, v, tau, C, u_n = o.inference(idx)
+    N, S = w.n_integration, w.n_sample
+    errs = {
+        "u": _rel_max(_soa(sim.buffer(A.NSF_BUF_U)).reshape(3, N).T, u_n),
+        "v": _rel_max(_soa(sim.buffer(A.NSF_BUF_UPREV)).reshape(3, N).T, v),
+        "tau": _rel_max(_soa(sim.buffer(A.NSF_BUF_TAU)).reshape(6, N).T,
+                        np.stack([tau[:, 0, 0], tau[:, 1, 1], tau[:, 2, 2], tau[:, 1, 2], tau[:, 0, 2],
+                                  tau[:, 0, 1]], 1)),
+        "C": _rel_max(_soa(sim.buffer(A.NSF_BUF_C)).reshape(9, N).T, C.reshape(N, 9)),
+        "J": _rel_max(_soa(sim.buffer(A.NSF_BUF_JAC)).reshape(3, r, S).transpose(2, 0, 1),
+                      o.jac(o.X[idx][:S], o.z)),
+        "decode_u": _rel_max(_soa(sim.buffer(A.NSF_BUF_XDEC)).reshape(3, -1).T - o.X, o.decode() - o.X),
+    }
+    print("errors:", {k: f"{e:.2e}" for k, e in errs.items()}, flush=True)
+    for k, e in errs.items():
+        assert e < TOL_BF16, (k, e)
+    # one step: positions against the oracle's, at the BF16 gate
+    sim.step(1, stream=s)
+    s.synchronize()
+    o.step(1)
+    xg = _soa(sim.buffer(A.NSF_BUF_XDEC)).reshape(3, -1).T
+    xo = o.decode()
+    dx = float(np.sqrt(((xg - xo) ** 2).sum() / (xo ** 2).sum()))
+    print(f"delta_x after one step: {dx:.2e}", flush=True)
+    assert dx <= 1e-4
+    assert sim.flags(stream=s) == (0, 0)
+    sim.close()
+
+
+def test_empty_calls():
+    """Zero steps and an empty decode are no-ops; an empty batch is rejected."""
+    w = synth.small_cube(seed=1, r=3, width=64, n=64)
+    s = torch.cuda.Stream()
+    sim = Sim(w, stream=s)
+    z0, _, st0 = sim.latent(stream=s)
+    A.check(A.lib().nsf_step(sim.handle, 0, s.cuda_stream))
+    out = torch.empty(3, dtype=torch.float32, device="cuda")
+    A.check(A.lib().nsf_decode(sim.handle, out.data_ptr(), 0, out.data_ptr(), s.cuda_stream))
+    z1, _, st1 = sim.latent(stream=s)
+    assert st1 == st0 == 0
+    np.testing.assert_array_equal(z0, z1)
+    import ctypes as C
+    arr = (C.c_void_p * 1)()
+    assert A.lib().nsf_step_batch(arr, 0, 1, s.cuda_stream) == A.NSF_EINVAL
+    sim.close()
