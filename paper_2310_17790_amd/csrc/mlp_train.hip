@@ -12,8 +12,8 @@
 // output, pre-activations stored point-major). The backward-data kernel carries 32 points
 // per wave through the five W^T products on MFMA (the same accumulator-layout chaining as
 // the forward, with the transposed weights packed on the device) and computes dz on the
-// VALU. The weight gradients are reductions over points: each workgroup sums a chunk of
-// points for one layer into a partial, and the partials are added in chunk order
+// VALU. The weight gradients are reductions over points on MFMA: each workgroup sums a
+// chunk of points for one layer into a partial, and the partials are added in chunk order
 // (deterministic) into dW.
 #include <hip/hip_runtime.h>
 
@@ -189,89 +189,154 @@ __global__ __launch_bounds__(256) void backward_data_kernel(const float* __restr
   }
 }
 
-// ---- weight gradients: C[m][j] = sum_p A(p, m) B(p, j) over a chunk of points ---------
-// A(p, m): delta rows (point-major [n][W]) or dout (SoA [d][n]) for the output layer.
-// B(p, j): ELU of saved pre-activations (point-major), or the layer-1 input [X; z], with
-// a last column equal to 1 (bias gradient).
-constexpr int kChunk = 1024;   // points per workgroup
-constexpr int kSub = 32;       // points staged per pass
+constexpr int kChunk = 1024;   // points per weight-gradient workgroup
 
-struct GradLayer {
-  const float* A; int a_soa;       // a_soa: A is [M][n] (dout), else [n][lda]
-  int lda;
-  const float* Bsaved;             // point-major pre-activations [n][W] -> ELU
-  const float* X; const float* zrows; int r;   // layer-1 input when Bsaved == NULL
-  int M, N;                        // N includes the bias column
-  float* partial;                  // [n_chunks][M][N]
+// ---- weight gradients on MFMA -------------------------------------------------------------
+// dW[m][j] = sum_p A(p, m) B(p, j) and db[m] = sum_p A(p, m) over one chunk of kChunk points,
+// for every layer: A is the layer's delta (point-major [n][W], or the SoA dout [d][n] for
+// the output layer), B its input (ELU of the saved pre-activations [n][W], or [X; z] for
+// layer 1). The points are the K dimension. Each stage brings kGStage points of A and B
+// into LDS as FP32, transposed to [neuron][point]; for the point-major operands the next
+// stage's global loads (16 B per lane) are issued before the current stage's products. The
+// four waves accumulate 32 x 32 tiles of the M x N output (M, N <= 128, padded to
+// multiples of 32) on MFMA: FP32 products on v_mfma_f32_32x32x2_f32, or, for BF16
+// training, operands rounded to BF16 on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.
+// db is summed in FP32 from the staged A. The chunk's result goes to
+// partial[chunk][m][N + 1], bias in the last column.
+constexpr int kGStage = 64;        // points per stage
+constexpr int kGLd = kGStage + 4;  // LDS row stride (floats): 16-byte aligned rows
+
+enum GradKind { kGradFirst = 0, kGradHidden = 1, kGradOutput = 2 };
+
+struct GradIn {
+  const float* A;         // delta [n][W] (first, hidden) or dout [M][n] (output)
+  const float* Bsaved;    // pre-activations [n][W] (hidden, output)
+  const float* X;         // [3][n] (first)
+  const float* zrows;     // [n][r] (first)
+  int M, N, r;            // M rows (W, or d), N input columns (W, or 3 + r)
+  float* partial;
 };
 
-__global__ __launch_bounds__(256) void grad_partial_kernel(GradLayer g, int n, int W) {
-  __shared__ float sA[kSub][129];
-  __shared__ float sB[kSub][130];
-  const int chunk = blockIdx.x;
-  const int p0 = chunk * kChunk, p1 = min(n, p0 + kChunk);
-  const int tid = threadIdx.x;
-  const int tiles_n = (g.N + 7) / 8, tiles = ((g.M + 7) / 8) * tiles_n;
-  float acc[2][8][8];
+template <int W, bool BF, int KIND>
+__global__ __launch_bounds__(256) void grad_mfma_kernel(GradIn g, int n) {
+  __shared__ __attribute__((aligned(16))) float sA[128][kGLd];
+  __shared__ __attribute__((aligned(16))) float sB[128][kGLd];
+  constexpr int V4 = kGStage * W / 4 / 256;   // float4 per thread per point-major stage
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+  const int p0 = blockIdx.x * kChunk, p1 = min(n, p0 + kChunk);
+  const int M = g.M, N = g.N;
+  const int MB = (M + 31) / 32, NB = (N + 31) / 32, tiles = MB * NB;
+  for (int e = tid; e < (32 * MB - M) * kGLd; e += 256) sA[M + e / kGLd][e % kGLd] = 0.f;
+  for (int e = tid; e < (32 * NB - N) * kGLd; e += 256) sB[N + e / kGLd][e % kGLd] = 0.f;
+  f32x16_t acc[4];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int t = 0; t < 4; ++t) acc[t] = f32x16_t{};
+  float db = 0.f;   // thread tid < M: bias gradient of row tid
+  f32x4 ra[V4], rb[V4];
+  // point-major [n][W] rows of the stage starting at ps into registers (zero past p1)
+  auto load_pm = [&](const float* src, f32x4 (&r)[V4], int ps) {
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b < 8; ++b) acc[u][a][b] = 0.f;
-  for (int ps = p0; ps < p1; ps += kSub) {
-    const int cnt = min(kSub, p1 - ps);
-    for (int e = tid; e < kSub * g.M; e += 256) {
-      const int pt = e / g.M, m = e % g.M;
-      float v = 0.f;
-      if (pt < cnt) v = g.a_soa ? g.A[(int64_t)m * n + ps + pt] : g.A[(int64_t)(ps + pt) * g.lda + m];
-      sA[pt][m] = v;
+    for (int i = 0; i < V4; ++i) {
+      const int e = tid + 256 * i, pt = e / (W / 4), c4 = (e % (W / 4)) * 4;
+      r[i] = ps + pt < p1 ? *reinterpret_cast<const f32x4*>(src + (int64_t)(ps + pt) * W + c4)
+                          : f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    for (int e = tid; e < kSub * g.N; e += 256) {
-      const int pt = e / g.N, j = e % g.N;
-      float v = 0.f;
-      if (pt < cnt) {
-        const int p = ps + pt;
-        if (j == g.N - 1) v = 1.f;
-        else if (g.Bsaved) v = elu(g.Bsaved[(int64_t)p * W + j]);
-        else if (j < 3) v = g.X[(int64_t)j * n + p];
-        else v = g.zrows[(int64_t)p * g.r + (j - 3)];
+  };
+  auto store_pm = [&](float (*dst)[kGLd], const f32x4 (&r)[V4], bool act) {
+#pragma unroll
+    for (int i = 0; i < V4; ++i) {
+      const int e = tid + 256 * i, pt = e / (W / 4), c4 = (e % (W / 4)) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[c4 + q][pt] = act ? elu(r[i][q]) : r[i][q];
+    }
+  };
+  auto load_next = [&](int ps) {
+    if constexpr (KIND != kGradOutput) load_pm(g.A, ra, ps);
+    if constexpr (KIND != kGradFirst) load_pm(g.Bsaved, rb, ps);
+  };
+  load_next(p0);
+  for (int ps = p0; ps < p1; ps += kGStage) {
+    const int cnt = min(kGStage, p1 - ps);
+    if constexpr (KIND != kGradOutput) {
+      store_pm(sA, ra, false);
+    } else {   // dout [M][n], M <= 9
+      for (int e = tid; e < M * kGStage; e += 256) {
+        const int m = e / kGStage, pt = e % kGStage;
+        sA[m][pt] = pt < cnt ? g.A[(int64_t)m * n + ps + pt] : 0.f;
       }
-      sB[pt][j] = v;
+    }
+    if constexpr (KIND != kGradFirst) {
+      // the saved values are rows of pre-activations; padded points stay exactly zero
+      store_pm(sB, rb, true);
+      if (cnt < kGStage)
+        for (int e = tid; e < W * (kGStage - cnt); e += 256) sB[e / (kGStage - cnt)][cnt + e % (kGStage - cnt)] = 0.f;
+    } else {   // [X; z], N = 3 + r
+      for (int e = tid; e < N * kGStage; e += 256) {
+        const int j = e / kGStage, pt = e % kGStage;
+        float v = 0.f;
+        if (pt < cnt)
+          v = j < 3 ? g.X[(int64_t)j * n + ps + pt] : g.zrows[(int64_t)(ps + pt) * g.r + (j - 3)];
+        sB[j][pt] = v;
+      }
     }
     __syncthreads();
+    if (ps + kGStage < p1) load_next(ps + kGStage);   // in flight during the products below
+    if (tid < M)
+      for (int pt = 0; pt < cnt; ++pt) db += sA[tid][pt];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int tile = tid + 256 * u;
-      if (tile >= tiles) continue;
-      const int m0 = (tile / tiles_n) * 8, j0 = (tile % tiles_n) * 8;
-      for (int pt = 0; pt < cnt; ++pt) {
-        float a[8], b[8];
+    for (int t = 0; t < 4; ++t) {
+      const int tile = wave + 4 * t;
+      if (tile >= tiles) break;
+      const int mb = tile / NB, nb = tile % NB;
+      const float* arow = sA[32 * mb + (lane & 31)];
+      const float* brow = sB[32 * nb + (lane & 31)];
+      if constexpr (BF) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          a[q] = m0 + q < g.M ? sA[pt][m0 + q] : 0.f;
-          b[q] = j0 + q < g.N ? sB[pt][j0 + q] : 0.f;
+        for (int k0 = 0; k0 < kGStage; k0 += 16) {
+          const int kk = k0 + 8 * h;
+          const f32x4 a0 = *reinterpret_cast<const f32x4*>(arow + kk);
+          const f32x4 a1 = *reinterpret_cast<const f32x4*>(arow + kk + 4);
+          const f32x4 b0 = *reinterpret_cast<const f32x4*>(brow + kk);
+          const f32x4 b1 = *reinterpret_cast<const f32x4*>(brow + kk + 4);
+          bf16x8 a, b;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            a[q] = (__bf16)a0[q];
+            a[4 + q] = (__bf16)a1[q];
+            b[q] = (__bf16)b0[q];
+            b[4 + q] = (__bf16)b1[q];
+          }
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
         }
+      } else {
 #pragma unroll
-        for (int x = 0; x < 8; ++x)
-#pragma unroll
-          for (int y = 0; y < 8; ++y) acc[u][x][y] += a[x] * b[y];
+        for (int k0 = 0; k0 < kGStage; k0 += 2)
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[k0 + h], brow[k0 + h], acc[t], 0, 0, 0);
       }
     }
     __syncthreads();
   }
+  float* out = g.partial + (int64_t)blockIdx.x * M * (N + 1);
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int tile = tid + 256 * u;
-    if (tile >= tiles) continue;
-    const int m0 = (tile / tiles_n) * 8, j0 = (tile % tiles_n) * 8;
-    float* out = g.partial + (int64_t)chunk * g.M * g.N;
+  for (int t = 0; t < 4; ++t) {
+    const int tile = wave + 4 * t;
+    if (tile >= tiles) break;
+    const int mb = tile / NB, nb = tile % NB;
 #pragma unroll
-    for (int x = 0; x < 8; ++x)
-#pragma unroll
-      for (int y = 0; y < 8; ++y)
-        if (m0 + x < g.M && j0 + y < g.N) out[(m0 + x) * g.N + j0 + y] = acc[u][x][y];
+    for (int e = 0; e < 16; ++e) {
+      const int m = 32 * mb + 8 * (e >> 2) + 4 * h + (e & 3);
+      const int j = 32 * nb + (lane & 31);
+      if (m < M && j < N) out[m * (N + 1) + j] = acc[t][e];
+    }
   }
+  if (tid < M) out[tid * (N + 1) + N] = db;
+}
+
+template <int W, bool BF>
+void launch_grad(const GradIn& g, int kind, int chunks, int n, hipStream_t s) {
+  if (kind == kGradFirst) hipLaunchKernelGGL((grad_mfma_kernel<W, BF, kGradFirst>), dim3(chunks), dim3(256), 0, s, g, n);
+  else if (kind == kGradHidden) hipLaunchKernelGGL((grad_mfma_kernel<W, BF, kGradHidden>), dim3(chunks), dim3(256), 0, s, g, n);
+  else hipLaunchKernelGGL((grad_mfma_kernel<W, BF, kGradOutput>), dim3(chunks), dim3(256), 0, s, g, n);
 }
 
 // dW[m][j] += sum over chunks (in order); column N-1 goes to the bias db[m].
@@ -279,8 +344,20 @@ __global__ void grad_reduce_kernel(const float* __restrict__ partial, int n_chun
                                    float* __restrict__ dW, float* __restrict__ db) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= M * N) return;
-  float s = 0.f;
-  for (int c = 0; c < n_chunks; ++c) s += partial[(int64_t)c * M * N + e];
+  // eight running sums (chunk c goes to sum c mod 8) keep eight loads in flight; they are
+  // combined in a fixed order, so the result does not depend on timing
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int64_t stride = (int64_t)M * N;
+  int c = 0;
+  for (; c + 8 <= n_chunks; c += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(c + u) * stride + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += v[u];
+  }
+  for (; c < n_chunks; ++c) a[c & 7] += partial[(int64_t)c * stride + e];
+  const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   const int m = e / N, j = e % N;
   if (j == N - 1) db[m] += s;
   else dW[(int64_t)m * (N - 1) + j] += s;
@@ -399,30 +476,36 @@ nsf_status nsf_mlp_backward(const nsf_mlp* m, const float* X, const float* z_row
   float* gW6 = gh + 4 * ((size_t)W * W + W);
   float* gb6 = gW6 + (size_t)d * W;
   const int chunks = (int)((n + kChunk - 1) / kChunk);
+  const bool bf = m->precision == NSF_BF16;
   for (int layer = 1; layer <= 6; ++layer) {
-    GradLayer g{};
+    GradIn g{};
     g.partial = ws.partial;
     g.r = r;
     float *tW, *tb;
+    int kind;
     if (layer == 6) {
-      g.A = dout; g.a_soa = 1; g.lda = 0; g.M = d;
-      g.Bsaved = saved + (size_t)4 * n * W; g.N = W + 1;
+      kind = kGradOutput;
+      g.A = dout; g.M = d;
+      g.Bsaved = saved + (size_t)4 * n * W; g.N = W;
       tW = gW6; tb = gb6;
     } else {
-      g.A = ws.delta + (size_t)(layer - 1) * n * W; g.a_soa = 0; g.lda = W; g.M = W;
+      g.A = ws.delta + (size_t)(layer - 1) * n * W; g.M = W;
       if (layer == 1) {
-        g.Bsaved = nullptr; g.X = X; g.zrows = z_rows; g.N = (int)in1 + 1;
+        kind = kGradFirst;
+        g.X = X; g.zrows = z_rows; g.N = (int)in1;
         tW = gW1; tb = gb1;
       } else {
-        g.Bsaved = saved + (size_t)(layer - 2) * n * W; g.N = W + 1;
+        kind = kGradHidden;
+        g.Bsaved = saved + (size_t)(layer - 2) * n * W; g.N = W;
         tW = gh + (size_t)(layer - 2) * ((size_t)W * W + W);
         tb = tW + (size_t)W * W;
       }
     }
-    hipLaunchKernelGGL(grad_partial_kernel, dim3(chunks), dim3(256), 0, s, g, (int)n, W);
-    const int e = g.M * g.N;
+    if (W == 64) bf ? launch_grad<64, true>(g, kind, chunks, (int)n, s) : launch_grad<64, false>(g, kind, chunks, (int)n, s);
+    else bf ? launch_grad<128, true>(g, kind, chunks, (int)n, s) : launch_grad<128, false>(g, kind, chunks, (int)n, s);
+    const int e = g.M * (g.N + 1);
     hipLaunchKernelGGL(grad_reduce_kernel, dim3((e + 255) / 256), dim3(256), 0, s, ws.partial, chunks,
-                       g.M, g.N, tW, tb);
+                       g.M, g.N + 1, tW, tb);
     if (hipGetLastError() != hipSuccess) return NSF_EHIP;
   }
   return NSF_OK;

@@ -81,7 +81,11 @@ class Fitter:
 
     def loss(self, f: str, t: torch.Tensor, p: torch.Tensor, z: torch.Tensor) -> torch.Tensor:
         """Mean squared error of field f on the normalised targets at pairs (t, p)."""
-        out = FieldFn.apply(self.X[p], z[t], self.w[f], self.width, OUT_DIM[f], self.precision)
+        # index_select: its backward adds the per-pair latent gradients into the table with
+        # one scatter-add (indexing's backward would sort the indices first)
+        zr = torch.index_select(z, 0, t)
+        out = FieldFn.apply(torch.index_select(self.X, 0, p), zr, self.w[f], self.width, OUT_DIM[f],
+                            self.precision)
         return ((out - self.Y[f][t, p]) ** 2).mean()
 
     def fit(self, f: str, iters: int) -> List[float]:
