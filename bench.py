@@ -126,11 +126,13 @@ def decode_kernel_ms(sim, n_points, n, stream, torch, A):
     return e0.elapsed_time(e1) / n
 
 
-def single_leg(precision, r, K, W, stream, torch, synth, A, Sim, width=128, P=200_000, NI=8192):
-    """The cake-scale single instance at one precision and latent size."""
+def single_leg(precision, r, K, W, stream, torch, synth, A, Sim, width=128, P=200_000, NI=8192,
+               decode_mode=1):
+    """The cake-scale single instance at one precision and latent size (decode_mode 2:
+    each step's decode overlaps the step, one step behind the latent)."""
     wl = synth.cake_slab(seed=0, r=r, width=width, n=P, n_integration=NI, steps=K + W,
                          plan_steps=min(K + W, 128))
-    sim = Sim(wl, precision=precision, stream=stream)
+    sim = Sim(wl, precision=precision, decode_every_step=decode_mode, stream=stream)
     sim.step(max(W, 1), stream=stream)
     stream.synchronize()
     wall, lat = time_steps(sim, K, stream, torch)
@@ -204,7 +206,7 @@ def main() -> int:
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="bf16_r6,bf16_r24,served_bf16,fit_bf16",
+    ap.add_argument("--legs", default="bf16_r6,bf16_r24,fp32_pipelined,bf16_pipelined,served_bf16,fit_bf16",
                     help="comma-separated extra legs ('' for none)")
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--served-steps", type=int, default=1000)
@@ -254,7 +256,12 @@ def main() -> int:
 
     legs = {}
     for name in [x for x in args.legs.split(",") if x]:
-        if name.startswith("bf16_r"):
+        if name in ("fp32_pipelined", "bf16_pipelined"):
+            leg, _ = single_leg(name[:4], r, K, W, stream, torch, synth, A, Sim, decode_mode=2)
+            leg["vs_fp32_single"] = {"steps_per_s": leg["steps_per_s"] / main_leg["steps_per_s"],
+                                     "decoded_pts_per_s": leg["decoded_pts_per_s"] / main_leg["decoded_pts_per_s"]}
+            legs[name] = leg
+        elif name.startswith("bf16_r"):
             lr = int(name[len("bf16_r"):])
             leg, _ = single_leg("bf16", lr, K, W, stream, torch, synth, A, Sim)
             leg["vs_fp32_single"] = {"steps_per_s": leg["steps_per_s"] / main_leg["steps_per_s"],

@@ -97,8 +97,13 @@ typedef struct {
   int32_t plan_steps;          /* rows in sample_plan; step n uses row n mod plan_steps   */
   const int32_t *sample_plan;  /* host, [plan_steps][n_integration] indices into P        */
   int32_t gn_iters;            /* Gauss-Newton iterations per step, 1..4 (paper: 2-3)     */
-  int32_t decode_every_step;   /* 1: each step ends by decoding all P into the sim's
-                                  decoded-position buffer (nsf_sim_buffer NSF_BUF_XDEC)  */
+  int32_t decode_every_step;   /* 0: no decode in the step. 1: each step ends by decoding
+                                  all P into the decoded-position buffer (nsf_sim_buffer
+                                  NSF_BUF_XDEC) at the new latent. 2 (pipelined): each step
+                                  decodes the latent it starts from, on a side stream,
+                                  concurrently with its MPM step and inversion, so after a
+                                  step the buffer holds the positions one step behind the
+                                  latent; nsf_refresh decodes the current latent       */
   const double *z0;            /* host [r]                                                */
   const double *z_prev;        /* host [r] or NULL (then z_{-1} = z_0, zero velocity)     */
 } nsf_sim_desc;
@@ -135,7 +140,7 @@ nsf_status nsf_step(nsf_sim *s, int32_t n_steps, void *stream);
 nsf_status nsf_step_batch(nsf_sim *const *sims, int32_t n, int32_t n_steps, void *stream);
 
 /* Evaluate the fields at the current latent in one launch, async: decode all particles
- * into the decoded-position buffer (when decode_every_step) and the field inference the
+ * into the decoded-position buffer (when decode_every_step is 1 or 2) and the field inference the
  * next step starts from (Sec. 5.1). nsf_step ends every step with this launch; call it
  * directly to refresh the decoded positions after nsf_set_latent, or to time it. */
 nsf_status nsf_refresh(nsf_sim *s, void *stream);

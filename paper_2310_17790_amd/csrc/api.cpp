@@ -57,7 +57,7 @@ struct Carver {
 struct Layout {
   size_t simdev;
   size_t w1p[3], whp[3], whb[3], bhp[3], w6p[3], b6[3];
-  size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, step, flags, gn_part;
+  size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, zdec, step, flags, gn_part;
   size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active,
       nonempty, n_active;
   size_t total;
@@ -97,6 +97,7 @@ Layout make_layout(const nsf_sim_desc* d) {
   const size_t n3 = (size_t)d->grid_n * d->grid_n * d->grid_n;
   L.grid = c.take(n3 * 16);
   L.z = c.take((size_t)3 * r * 8);
+  L.zdec = c.take((size_t)r * 8);
   L.step = c.take(8);
   L.flags = c.take(4);
   L.gn_part = c.take((size_t)ceil_div(S, kGnChunk) * gn_entries(r) * 8);
@@ -141,6 +142,8 @@ nsf_status validate(const nsf_sim_desc* d) {
   if (!(d->rho > 0) || !(d->body_volume > 0)) return fail(NSF_EINVAL, "rho and body_volume must be positive");
   if (d->wall_nodes < 0 || 2 * d->wall_nodes >= d->grid_n) return fail(NSF_EINVAL, "wall_nodes = %d", d->wall_nodes);
   if (d->gn_iters < 1 || d->gn_iters > 4) return fail(NSF_EINVAL, "gn_iters = %d outside 1..4", d->gn_iters);
+  if (d->decode_every_step < 0 || d->decode_every_step > 2)
+    return fail(NSF_EINVAL, "decode_every_step = %d (0, 1 or 2)", d->decode_every_step);
   if (!d->z0) return fail(NSF_EINVAL, "z0 is NULL");
   for (int j = 0; j < d->r; ++j)
     if (!std::isfinite(d->z0[j]) || (d->z_prev && !std::isfinite(d->z_prev[j])))
@@ -182,7 +185,7 @@ struct nsf_sim {
   bool bf16 = false;
   int64_t n_part = 0;
   int n_int = 0, n_samp = 0, gn_iters = 2;
-  bool decode_every_step = false;
+  int decode_mode = 0;    // decode_every_step: 0, 1 or 2 (pipelined)
   char* arena = nullptr;
   size_t arena_bytes = 0;
   Layout L{};
@@ -203,7 +206,7 @@ struct nsf_sim {
 struct Plan {
   std::vector<nsf_sim*> members;
   int width = 0, gn_iters = 0, tc = 0;
-  bool bf16 = false, decode = false, persistent = false;
+  bool bf16 = false, decode = false, pipelined = false, persistent = false;
   void* dbuf = nullptr;
   size_t dcap = 0;
   void* staging = nullptr;        // pinned host copy of the tables (persistent plans)
@@ -241,7 +244,7 @@ std::mutex g_plans_mu;
 std::map<int, std::unique_ptr<Plan>> g_batch_plans;
 
 int batch_signature(const nsf_sim* s) {
-  return s->width * 64 + (s->bf16 ? 32 : 0) + s->gn_iters * 2 + (s->decode_every_step ? 1 : 0);
+  return s->width * 64 + (s->bf16 ? 32 : 0) + s->gn_iters * 4 + s->decode_mode;
 }
 
 FieldJob base_job(const nsf_sim* s, int field, const double* z) {
@@ -299,7 +302,8 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.width = s0->width;
   P.bf16 = s0->bf16;
   P.gn_iters = s0->gn_iters;
-  P.decode = s0->decode_every_step;
+  P.decode = s0->decode_mode != 0;
+  P.pipelined = s0->decode_mode == 2;
   P.tc = fields_max_tangents(P.width, P.bf16);
   std::vector<SimDev> sims;
   std::vector<FieldJob> jobs;
@@ -352,7 +356,8 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     add_tiles(tG, (int)jobs.size(), S, r, P.tc);
     jobs.push_back(g);
     // decode all particles at the new latent
-    FieldJob dj = base_job(s, NSF_FIELD_G, zc);
+    // (a pipelined decode reads the snapshot of z_n the step's first kernel takes)
+    FieldJob dj = base_job(s, NSF_FIELD_G, s->decode_mode == 2 ? H.zdec : zc);
     dj.idx = nullptr; dj.step = nullptr; dj.n = (int)s->n_part; dj.mode = 1;
     dj.out = H.xdec; dj.ldo = s->n_part;
     add_prim_tiles(tD, (int)jobs.size(), (int)s->n_part, P.tc);
@@ -461,16 +466,17 @@ nsf_status enqueue_inference(Plan& P, hipStream_t s) {
   return NSF_OK;
 }
 
-// Decode of the current latent and the next step's field inference (both evaluate the
-// fields at the same latent). Counters must have been reset in this sequence.
-nsf_status enqueue_refresh_body(Plan& P, hipStream_t s) {
-  if (!P.decode || s == nullptr || !P.side) {
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tAD, P.d_counts + 2,
-                                P.d_counts + kClaimAD, P.gF, s));
+// Decode of all particles, on the side stream between a fork and a join recorded on s
+// (inline on s when there is no side stream).
+nsf_status fork_decode(Plan& P, hipStream_t s) {
+  if (s == nullptr || !P.side) {
+    if (P.nsims == 1 && !P.persistent)
+      NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, s));
+    else
+      NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
+                                  P.d_counts + kClaimD, P.gF0, s));
     return NSF_OK;
   }
-  // fork: decode (primal kernel, two waves per SIMD) on the side stream, the next step's
-  // inference (tangent kernel) on the main stream; join before the step continues
   NSF_HIP(hipEventRecord(P.ev_fork, s));
   NSF_HIP(hipStreamWaitEvent(P.side, P.ev_fork, 0));
   if (P.nsims == 1 && !P.persistent)
@@ -478,23 +484,59 @@ nsf_status enqueue_refresh_body(Plan& P, hipStream_t s) {
   else
     NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
                                 P.d_counts + kClaimD, P.gF0, P.side));
-  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
-                              P.d_counts + kClaimA, P.gF, s));
   NSF_HIP(hipEventRecord(P.ev_join, P.side));
-  NSF_HIP(hipStreamWaitEvent(s, P.ev_join, 0));
   return NSF_OK;
 }
 
+nsf_status join_decode(Plan& P, hipStream_t s) {
+  if (s != nullptr && P.side) NSF_HIP(hipStreamWaitEvent(s, P.ev_join, 0));
+  return NSF_OK;
+}
+
+// The next step's field inference at the current latent, with (decode = true) the decode
+// of all particles at the same latent, concurrently. Counters must have been reset in
+// this sequence.
+nsf_status enqueue_refresh_body(Plan& P, hipStream_t s, bool decode) {
+  if (!decode) {
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
+                                P.d_counts + kClaimA, P.gF, s));
+    return NSF_OK;
+  }
+  if (s == nullptr || !P.side) {
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tAD, P.d_counts + 2,
+                                P.d_counts + kClaimAD, P.gF, s));
+    return NSF_OK;
+  }
+  // fork: decode on the side stream, the next step's inference (tangent kernel) on the
+  // main stream; join before the step continues
+  nsf_status st = fork_decode(P, s);
+  if (st != NSF_OK) return st;
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
+                              P.d_counts + kClaimA, P.gF, s));
+  return join_decode(P, s);
+}
+
+// Refresh outside a step (nsf_refresh): a pipelined sim first points its decode at the
+// current latent.
 nsf_status enqueue_refresh(Plan& P, hipStream_t s) {
   NSF_HIP(launch_reset_counters(P.d_counts + 8, 8, s));
-  return enqueue_refresh_body(P, s);
+  if (P.pipelined)
+    for (nsf_sim* m : P.members)
+      NSF_HIP(hipMemcpyAsync(m->hd.zdec, m->hd.z + m->r, (size_t)m->r * 8, hipMemcpyDeviceToDevice, s));
+  return enqueue_refresh_body(P, s, P.decode);
 }
 
 // One latent step, given its field inference in the buffers: MPM step, Gauss-Newton
-// iterations, then decode at z_{n+1} together with the inference of step n + 1.
+// iterations, then the inference of step n + 1. The decode of all particles runs at
+// z_{n+1} together with that inference, or (pipelined) at z_n alongside the whole step,
+// forked right after the first kernel has taken its latent snapshot.
 nsf_status enqueue_step(Plan& P, hipStream_t s) {
-  NSF_HIP(launch_p2g(P.d_sims, P.d_bP, P.d_counts + 3, P.d_counts + 6, P.d_counts + 8, P.gP,
-                     P.gSims, P.gBlk, s));
+  NSF_HIP(launch_bin(P.d_sims, P.d_bP, P.d_counts + 3, P.d_counts + 8, P.gP, s));
+  if (P.decode && P.pipelined) {
+    const nsf_status st = fork_decode(P, s);
+    if (st != NSF_OK) return st;
+  }
+  NSF_HIP(launch_p2g_after_bin(P.d_sims, P.d_counts + 6, P.gSims, P.gBlk, s));
   NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.gGN, s));
   NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {
@@ -503,7 +545,12 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
     NSF_HIP(launch_gn_partial(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.gGN, s));
     NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, k, P.gSims, s));
   }
-  return enqueue_refresh_body(P, s);
+  if (P.decode && P.pipelined) {
+    const nsf_status st = enqueue_refresh_body(P, s, false);
+    if (st != NSF_OK) return st;
+    return join_decode(P, s);
+  }
+  return enqueue_refresh_body(P, s, P.decode);
 }
 
 nsf_status run_plan(Plan& P, int32_t n_steps, hipStream_t s) {
@@ -587,7 +634,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   sim->n_int = d->n_integration;
   sim->n_samp = d->n_sample;
   sim->gn_iters = d->gn_iters;
-  sim->decode_every_step = d->decode_every_step != 0;
+  sim->decode_mode = d->decode_every_step;
   sim->arena = static_cast<char*>(arena);
   sim->arena_bytes = arena_bytes;
   sim->L = L;
@@ -632,6 +679,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
     z[2 * r + j] = d->z0[j];
   }
   NSF_HIP(hipMemcpyAsync(A + L.z, z.data(), z.size() * 8, hipMemcpyHostToDevice, s));
+  NSF_HIP(hipMemcpyAsync(A + L.zdec, z.data() + r, (size_t)r * 8, hipMemcpyHostToDevice, s));
   const size_t n3 = (size_t)d->grid_n * d->grid_n * d->grid_n;
   NSF_HIP(hipMemsetAsync(A + L.grid, 0, n3 * 16, s));
   NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
@@ -654,6 +702,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.n_gn_chunks = ceil_div(d->n_sample, kGnChunk);
   H.width = W;
   H.tangent_forms = sim->bf16 ? 1 : 0;
+  H.pipelined_decode = sim->decode_mode == 2 ? 1 : 0;
   const double Vp = d->body_volume / d->n_integration;
   H.dx = (float)d->dx;
   H.inv_dx = (float)(1.0 / d->dx);
@@ -685,6 +734,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.xdec = reinterpret_cast<float*>(A + L.xdec);
   H.grid = reinterpret_cast<float4*>(A + L.grid);
   H.z = reinterpret_cast<double*>(A + L.z);
+  H.zdec = reinterpret_cast<double*>(A + L.zdec);
   H.step = reinterpret_cast<int64_t*>(A + L.step);
   H.flags = reinterpret_cast<uint32_t*>(A + L.flags);
   H.gn_part = reinterpret_cast<double*>(A + L.gn_part);
@@ -733,7 +783,7 @@ nsf_status nsf_step_batch(nsf_sim* const* sims, int32_t n, int32_t n_steps, void
   for (int i = 0; i < n; ++i) {
     if (!key[i]) return fail(NSF_EINVAL, "sims[%d] is NULL", i);
     if (key[i]->width != key[0]->width || key[i]->bf16 != key[0]->bf16 ||
-        key[i]->gn_iters != key[0]->gn_iters || key[i]->decode_every_step != key[0]->decode_every_step)
+        key[i]->gn_iters != key[0]->gn_iters || key[i]->decode_mode != key[0]->decode_mode)
       return fail(NSF_EINVAL, "sims[%d] differs in width, precision, gn_iters or decode mode", i);
     for (int j = 0; j < i; ++j)
       if (key[j] == key[i]) return fail(NSF_EINVAL, "sim listed twice in a batch");

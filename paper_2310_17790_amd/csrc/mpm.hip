@@ -95,7 +95,11 @@ __global__ __launch_bounds__(kMpmBlock) void bin_kernel(const SimDev* __restrict
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
     const BlockWork wk = work[b];
     const SimDev& S = sims[wk.sim];
-    if (wk.p0 == 0 && threadIdx.x == 0) *S.epoch += 1;   // this step's binning epoch
+    if (wk.p0 == 0) {
+      if (threadIdx.x == 0) *S.epoch += 1;   // this step's binning epoch
+      // the latent a pipelined decode of this step reads (z_n; the step overwrites z)
+      if (S.pipelined_decode && (int)threadIdx.x < S.r) S.zdec[threadIdx.x] = S.z[S.r + threadIdx.x];
+    }
     const int p = wk.p0 + threadIdx.x;
     if (p >= S.n_int) continue;
     float x[3];
@@ -535,10 +539,15 @@ __global__ __launch_bounds__(kGnThreads) void g2p_gn_kernel(const SimDev* __rest
 
 }  // namespace
 
-hipError_t launch_p2g(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
-                      const int32_t* n_sims, int32_t* claims, int grid_particles, int grid_sims,
-                      int grid_blocks, hipStream_t s) {
+hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
+                      int32_t* claims, int grid_particles, hipStream_t s) {
   if (grid_particles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bin_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int, claims);
+  return hipGetLastError();
+}
+
+hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int grid_sims,
+                                int grid_blocks, hipStream_t s) {
   constexpr int alloc_lds = kMaxBins * 4;
   static bool attr = false;
   if (!attr) {
@@ -547,7 +556,6 @@ hipError_t launch_p2g(const SimDev* sims, const BlockWork* work_int, const int32
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(bin_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int, claims);
   hipLaunchKernelGGL(alloc_place_kernel, dim3(grid_sims), dim3(kAllocThreads), alloc_lds, s, sims, n_sims);
   hipLaunchKernelGGL(bin_sort_kernel, dim3(grid_blocks), dim3(64), 0, s, sims, n_sims);
   hipLaunchKernelGGL(gather_kernel, dim3(grid_blocks), dim3(kGatherThreads), 0, s, sims, n_sims);

@@ -73,6 +73,7 @@ struct SimDev {
   int32_t r, n_part, n_int, n_samp;
   int32_t plan_steps, grid_n, wall, gn_iters;
   int32_t knife_on, n_gn_chunks, width;
+  int32_t pipelined_decode;          // 1: the step's first kernel snapshots z_n into zdec
   int32_t tangent_forms;             // 1 (BF16): velocity stored directly in u_prev (a JVP)
                                      // and trapezoid Gauss-Newton residuals from Jacobians
   float dx, inv_dx, dt, mp;          // mp = particle mass rho V_p
@@ -94,6 +95,7 @@ struct SimDev {
   float* xdec;                       // [3][n_part]
   float4* grid;                      // [grid_n^3] (m, p_x, p_y, p_z)
   double* z;                         // [3][r]: z_{n-1}, z_n, iterate
+  double* zdec;                      // [r]: the latent a pipelined decode reads
   int64_t* step;
   uint32_t* flags;
   double* gn_part;                   // [n_gn_chunks][E], E = r(r+1)/2 + r
@@ -131,12 +133,13 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
 int fields_max_tangents(int width, bool bf16);
 int fields_group_waves(int tc);   // waves (32-point tiles) per workgroup
 
-// MPM transfers: bin (per integration particle; also zeroes the step's claim counters),
-// allocate and place (per sim), sort and write records (per non-empty bin), gather + grid
-// update (per active node block).
-hipError_t launch_p2g(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
-                      const int32_t* n_sims, int32_t* claims, int grid_particles, int grid_sims,
-                      int grid_blocks, hipStream_t s);
+// MPM transfers: bin (per integration particle; also zeroes the step's claim counters and,
+// for pipelined decodes, snapshots z_n), then allocate and place (per sim), sort and write
+// records (per non-empty bin), gather + grid update (per active node block).
+hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
+                      int32_t* claims, int grid_particles, hipStream_t s);
+hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int grid_sims,
+                                int grid_blocks, hipStream_t s);
 // G2P at the sample particles fused with the first Gauss-Newton reduction: work items are
 // Gauss-Newton chunks (kGnChunk sample particles).
 hipError_t launch_g2p_gn(const SimDev* sims, const BlockWork* work_gn, const int32_t* n_work_gn,

@@ -91,3 +91,36 @@ def test_empty_calls():
     arr = (C.c_void_p * 1)()
     assert A.lib().nsf_step_batch(arr, 0, 1, s.cuda_stream) == A.NSF_EINVAL
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_pipelined_decode_lags_one_step(precision):
+    """decode_every_step = 2 decodes the latent each step starts from, concurrently with
+    the step: the latent trajectory is bit for bit the synchronous one, and after k steps
+    the decoded positions are the synchronous sim's after k - 1 steps; nsf_refresh brings
+    them to the current latent."""
+    w = synth.cake_slab(seed=2, r=6, width=128, n=20_000, n_integration=2048, steps=8, plan_steps=8)
+    s = torch.cuda.Stream()
+    ref = Sim(w, precision=precision, decode_every_step=1, stream=s)
+    pip = Sim(w, precision=precision, decode_every_step=2, stream=s)
+    ref.refresh(stream=s)
+    pip.refresh(stream=s)
+    s.synchronize()
+    prev = _soa(ref.buffer(A.NSF_BUF_XDEC)).copy()
+    np.testing.assert_array_equal(_soa(pip.buffer(A.NSF_BUF_XDEC)), prev)
+    for k in range(1, 6):
+        ref.step(1, stream=s)
+        pip.step(1, stream=s)
+        s.synchronize()
+        zr, _, sr = ref.latent(stream=s)
+        zp, _, sp = pip.latent(stream=s)
+        assert sr == sp == k
+        np.testing.assert_array_equal(zr, zp)
+        np.testing.assert_array_equal(_soa(pip.buffer(A.NSF_BUF_XDEC)), prev)
+        prev = _soa(ref.buffer(A.NSF_BUF_XDEC)).copy()
+    pip.refresh(stream=s)
+    s.synchronize()
+    np.testing.assert_array_equal(_soa(pip.buffer(A.NSF_BUF_XDEC)), prev)
+    assert ref.flags(stream=s) == (0, 0) and pip.flags(stream=s) == (0, 0)
+    ref.close()
+    pip.close()
