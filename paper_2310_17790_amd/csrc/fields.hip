@@ -128,26 +128,29 @@ __device__ __forceinline__ void init_hidden(f32x16 (&acc)[T][W / 32], const floa
 template <int W, int T, class APtr>
 __device__ __forceinline__ void hidden_f32(f32x16 (&acc)[T][W / 32], const float (&H)[T][W / 2],
                                            APtr A, int lane, int nt) {
-  constexpr int MB = W / 32, SG = W / 8;
-  // A fragments (four K-steps each) are read one group ahead of their use.
-  f32x4 a4[2][MB];
+  constexpr int MB = W / 32, SG = W / 4;   // groups of two K-steps
+  const f32x2* A2 = reinterpret_cast<const f32x2*>(A);
+  // fragment of K-steps 2 sg, 2 sg + 1 of M-block mb: half (sg & 1) of the f32x4 at
+  // (mb * (W / 8) + sg / 2) * 64 + lane
+  auto at = [&](int mb, int sg) { return A2[2 * ((mb * (W / 8) + (sg >> 1)) * 64 + lane) + (sg & 1)]; };
+  f32x2 a2[2][MB];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) a4[0][mb] = A[(mb * SG) * 64 + lane];
+  for (int mb = 0; mb < MB; ++mb) a2[0][mb] = at(mb, 0);
 #pragma unroll
   for (int sg = 0; sg < SG; ++sg) {
     if (sg + 1 < SG) {
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) a4[(sg + 1) & 1][mb] = A[(mb * SG + sg + 1) * 64 + lane];
+      for (int mb = 0; mb < MB; ++mb) a2[(sg + 1) & 1][mb] = at(mb, sg + 1);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        acc[0][mb] = mfma_f32(a4[sg & 1][mb][j], H[0][4 * sg + j], acc[0][mb]);
+        acc[0][mb] = mfma_f32(a2[sg & 1][mb][j], H[0][2 * sg + j], acc[0][mb]);
 #pragma unroll
         for (int t = 1; t < T; ++t)
-          if (t <= nt) acc[t][mb] = mfma_f32(a4[sg & 1][mb][j], H[t][4 * sg + j], acc[t][mb]);
+          if (t <= nt) acc[t][mb] = mfma_f32(a2[sg & 1][mb][j], H[t][2 * sg + j], acc[t][mb]);
       }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -448,20 +451,40 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
   }
 }
 
-// One job over n points (decode), weights streamed: group g covers points
-// [32 WPG g, 32 WPG (g + 1)).
+// The barrier and DMA sequence of run_group (streamed weights) for a wave with no tile in
+// this round: it keeps the workgroup's per-layer barriers and weight copies in step.
+template <int W, bool BF, int WPG, class NextFn>
+__device__ __forceinline__ void idle_group(const FieldJob& jb, NextFn&& next, char* lds, int wave,
+                                           int lane) {
+  constexpr int LB = HiddenLayer<W, BF>::kBytes;
+#pragma unroll 1
+  for (int k = 0; k < 3; ++k) {
+    wait_dma_and_sync();
+    dma_layer<W, BF, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
+  }
+  wait_dma_and_sync();
+  if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
+}
+
+// One job over n points (decode), weights streamed, persistent workgroups. Tiles are dealt
+// so that every round but the last fills all waves of all workgroups, and the last round's
+// tiles go to wave 0 of distinct workgroups, which then run alone on their SIMDs:
+// tile t = round * gridDim.x * WPG + wave * gridDim.x + blockIdx.x.
 template <int W, bool BF, int WPG>
-__global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, int n_groups) {
+__global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, int n_tiles) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int g = blockIdx.x;
-  if (g >= n_groups) return;
+  const int G = gridDim.x, b = blockIdx.x, per_round = G * WPG;
+  if (b >= n_tiles) return;
   dma_layer<W, BF, WPG>(job.w, 0, lds, wave, lane);
-  for (; g < n_groups; g += gridDim.x) {
-    const bool more = g + (int)gridDim.x < n_groups;
+#pragma unroll 1
+  for (int base = 0; base + b < n_tiles; base += per_round) {
+    const bool more = base + per_round + b < n_tiles;
     auto next = [&]() -> const FieldPack* { return more ? &job.w : nullptr; };
-    run_group<W, 0, BF, WPG>(job, g * kTile * WPG + kTile * wave, 0, next, lds, wave, lane);
+    const int t = base + wave * G + b;
+    if (t < n_tiles) run_group<W, 0, BF, WPG>(job, t * kTile, 0, next, lds, wave, lane);
+    else idle_group<W, BF, WPG>(job, next, lds, wave, lane);
   }
 }
 
@@ -507,18 +530,22 @@ hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int
   return hipGetLastError();
 }
 
+// Streamed-weight decode: as many persistent workgroups as fit on the device at once.
 template <int W, bool BF>
-hipError_t launch_dense(const FieldJob& job, int n_groups, hipStream_t s) {
+hipError_t launch_dense(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
   constexpr int WPG = Wpg<0>::value;
   constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes;
   auto k = fields_dense_kernel<W, BF, WPG>;
-  static bool attr = false;
-  if (!attr) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * WPG, lds);
     if (e != hipSuccess) return e;
-    attr = true;
+    if (per_cu < 1) per_cu = 1;
   }
-  hipLaunchKernelGGL(k, dim3(n_groups), dim3(64 * WPG), lds, s, job, n_groups);
+  int grid = cus * per_cu;
+  if (grid > n_tiles) grid = n_tiles;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, job, n_tiles);
   return hipGetLastError();
 }
 
@@ -598,22 +625,21 @@ hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s) {
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
                                hipStream_t s) {
   if (n_points <= 0) return hipSuccess;
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  const int tiles = (n_points + kTile - 1) / kTile;
   if (bf16) {
-    static int cus = 0;
-    if (cus == 0) {
-      int dev = 0;
-      hipError_t e = hipGetDevice(&dev);
-      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      if (e != hipSuccess) return e;
-    }
-    const int tiles = (n_points + kTile - 1) / kTile;
     if (width == 64) return launch_dense_res<64, true>(job, tiles, cus, s);
     if (width == 128) return launch_dense_res<128, true>(job, tiles, cus, s);
     return hipErrorInvalidValue;
   }
-  const int groups = (n_points + kTile * Wpg<0>::value - 1) / (kTile * Wpg<0>::value);
-  if (width == 64) return bf16 ? launch_dense<64, true>(job, groups, s) : launch_dense<64, false>(job, groups, s);
-  if (width == 128) return bf16 ? launch_dense<128, true>(job, groups, s) : launch_dense<128, false>(job, groups, s);
+  if (width == 64) return launch_dense<64, false>(job, tiles, cus, s);
+  if (width == 128) return launch_dense<128, false>(job, tiles, cus, s);
   return hipErrorInvalidValue;
 }
 

@@ -15,6 +15,7 @@ constexpr int kMpmBlock = 256;     // particles per P2G / G2P block
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Hidden neuron held in accumulator register i of M-block mb by lane half h (lanes 0-31:
