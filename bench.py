@@ -99,17 +99,21 @@ def cpu_baseline(workload, n_steps: int):
 
 
 def time_steps(sim, K, stream, torch):
-    """K graph-replayed steps with an event pair around each; returns (wall s, ms array)."""
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    """Throughput: K steps in one call (the library replays its step graphs back to back),
+    wall clock between device synchronisations. Latency: K more steps, one call each, with an
+    event pair around each. Returns (wall s of the K-step call, per-step ms array)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    sim.step(K, stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     for i in range(K):
         evs[i][0].record(stream)
         sim.step(1, stream=stream)
         evs[i][1].record(stream)
     stream.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     return wall, np.array([a.elapsed_time(b) for a, b in evs])
 
 

@@ -206,6 +206,7 @@ struct nsf_sim {
 struct Plan {
   std::vector<nsf_sim*> members;
   int width = 0, gn_iters = 0, tc = 0;
+  int r_cap = kMaxR;             // largest latent the Gauss-Newton chunk kernels serve
   bool bf16 = false, decode = false, pipelined = false, persistent = false;
   void* dbuf = nullptr;
   size_t dcap = 0;
@@ -223,14 +224,23 @@ struct Plan {
   // Decode runs on a side stream, concurrently with the next step's inference.
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // graphs of one step and of kGraphSteps steps (long runs launch the latter: each graph
+  // launch costs some microseconds between the last kernel of one and the first of the next)
+  hipGraph_t graph = nullptr, graph_n = nullptr;
+  hipGraphExec_t exec = nullptr, exec_n = nullptr;
+  void drop_graphs() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (exec_n) (void)hipGraphExecDestroy(exec_n);
+    if (graph_n) (void)hipGraphDestroy(graph_n);
+    exec = exec_n = nullptr;
+    graph = graph_n = nullptr;
+  }
   ~Plan() {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    drop_graphs();
     if (dbuf) (void)hipFree(dbuf);
     if (staging) (void)hipHostFree(staging);
   }
@@ -305,6 +315,10 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.decode = s0->decode_mode != 0;
   P.pipelined = s0->decode_mode == 2;
   P.tc = fields_max_tangents(P.width, P.bf16);
+  // a persistent plan's graph outlives its members: its chunk kernels take the largest size
+  P.r_cap = 1;
+  for (nsf_sim* m : P.members) P.r_cap = std::max(P.r_cap, m->r);
+  if (P.persistent) P.r_cap = kMaxR;
   std::vector<SimDev> sims;
   std::vector<FieldJob> jobs;
   std::vector<FieldTile> tA_jac, tA_prim, tG, tD, tD0;  // tD: decode groups for the tangent
@@ -397,8 +411,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   size_t off[kRegions], total = 0;
   for (int i = 0; i < kRegions; ++i) { off[i] = total; total += P.caps[i]; }
   if (relayout || total > P.dcap) {
-    if (P.exec) { (void)hipGraphExecDestroy(P.exec); P.exec = nullptr; }
-    if (P.graph) { (void)hipGraphDestroy(P.graph); P.graph = nullptr; }
+    P.drop_graphs();
     if (P.dbuf) { NSF_HIP(hipStreamSynchronize(stream)); NSF_HIP(hipFree(P.dbuf)); P.dbuf = nullptr; }
     P.dcap = total;
     NSF_HIP(hipMalloc(&P.dbuf, P.dcap));
@@ -466,6 +479,13 @@ nsf_status enqueue_inference(Plan& P, hipStream_t s) {
   return NSF_OK;
 }
 
+// A pipelined decode leaves 1 / kPipelinedFreeCuDiv of the compute units to the MPM and
+// Gauss-Newton kernels that run beside it.
+#ifndef NSF_PIPE_DIV
+#define NSF_PIPE_DIV 4
+#endif
+constexpr int kPipelinedFreeCuDiv = NSF_PIPE_DIV;
+
 // Decode of all particles, on the side stream between a fork and a join recorded on s
 // (inline on s when there is no side stream).
 nsf_status fork_decode(Plan& P, hipStream_t s) {
@@ -480,7 +500,8 @@ nsf_status fork_decode(Plan& P, hipStream_t s) {
   NSF_HIP(hipEventRecord(P.ev_fork, s));
   NSF_HIP(hipStreamWaitEvent(P.side, P.ev_fork, 0));
   if (P.nsims == 1 && !P.persistent)
-    NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, P.side));
+    NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, P.side,
+                                P.pipelined ? device_cus() - device_cus() / kPipelinedFreeCuDiv : 0));
   else
     NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
                                 P.d_counts + kClaimD, P.gF0, P.side));
@@ -537,12 +558,12 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
     if (st != NSF_OK) return st;
   }
   NSF_HIP(launch_p2g_after_bin(P.d_sims, P.d_counts + 6, P.gSims, P.gBlk, s));
-  NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.gGN, s));
+  NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.r_cap, P.gGN, s));
   NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {
     NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1,
                                 P.d_counts + kClaimG + (k - 1), P.gF, s));
-    NSF_HIP(launch_gn_partial(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.gGN, s));
+    NSF_HIP(launch_gn_partial(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.r_cap, P.gGN, s));
     NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, k, P.gSims, s));
   }
   if (P.decode && P.pipelined) {
@@ -551,6 +572,25 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
     return join_decode(P, s);
   }
   return enqueue_refresh_body(P, s, P.decode);
+}
+
+constexpr int kGraphSteps = 8;
+
+// Capture `steps` consecutive steps on s into a graph and instantiate it.
+nsf_status capture_steps(Plan& P, int steps, hipStream_t s, hipGraph_t* graph, hipGraphExec_t* exec) {
+  NSF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  nsf_status st = NSF_OK;
+  for (int i = 0; i < steps && st == NSF_OK; ++i) st = enqueue_step(P, s);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != NSF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(NSF_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  *graph = g;
+  NSF_HIP(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
+  return NSF_OK;
 }
 
 nsf_status run_plan(Plan& P, int32_t n_steps, hipStream_t s) {
@@ -566,20 +606,16 @@ nsf_status run_plan(Plan& P, int32_t n_steps, hipStream_t s) {
       if (st != NSF_OK) return st;
     }
   } else {
-    if (!P.exec) {
-      NSF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      const nsf_status st = enqueue_step(P, s);
-      hipGraph_t g = nullptr;
-      const hipError_t e = hipStreamEndCapture(s, &g);
-      if (st != NSF_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        return st;
-      }
-      if (e != hipSuccess) return fail(NSF_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-      P.graph = g;
-      NSF_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+    if (n_steps >= kGraphSteps && !P.exec_n) {
+      const nsf_status st = capture_steps(P, kGraphSteps, s, &P.graph_n, &P.exec_n);
+      if (st != NSF_OK) return st;
     }
-    for (int i = 0; i < n_steps; ++i) NSF_HIP(hipGraphLaunch(P.exec, s));
+    if (n_steps % kGraphSteps != 0 && !P.exec) {
+      const nsf_status st = capture_steps(P, 1, s, &P.graph, &P.exec);
+      if (st != NSF_OK) return st;
+    }
+    for (int i = 0; i < n_steps / kGraphSteps; ++i) NSF_HIP(hipGraphLaunch(P.exec_n, s));
+    for (int i = 0; i < n_steps % kGraphSteps; ++i) NSF_HIP(hipGraphLaunch(P.exec, s));
   }
   for (nsf_sim* m : P.members) m->inference_ready = true;
   return NSF_OK;

@@ -623,15 +623,16 @@ hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s) {
 }
 
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
-                               hipStream_t s) {
+                               hipStream_t s, int max_cus) {
   if (n_points <= 0) return hipSuccess;
-  static int cus = 0;
-  if (cus == 0) {
+  static int dev_cus = 0;
+  if (dev_cus == 0) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
   }
+  const int cus = max_cus > 0 && max_cus < dev_cus ? max_cus : dev_cus;
   const int tiles = (n_points + kTile - 1) / kTile;
   if (bf16) {
     if (width == 64) return launch_dense_res<64, true>(job, tiles, cus, s);

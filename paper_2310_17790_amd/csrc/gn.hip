@@ -90,7 +90,8 @@ __global__ __launch_bounds__(kGnThreads) void gn_partial_kernel(const SimDev* __
                                                                 const BlockWork* __restrict__ work,
                                                                 const int32_t* __restrict__ n_work,
                                                                 int iter) {
-  __shared__ GnChunkLds<kGnThreads> sh;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const GnChunkLds<kGnThreads> sh(lds);
   const int tid = threadIdx.x;
   const int total = *n_work;
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(kGnThreads) void gn_partial_kernel(const SimDev* __
           rv += (double)S.u_gn[c * ns + p] - (double)S.u_n[c * S.n_int + p];
         }
       }
-      sh.R[c][tid] = rv;
+      sh.res(c, tid) = rv;
     }
     __syncthreads();
     gn_reduce_chunk(S, p0, sh);
@@ -190,9 +191,18 @@ __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* _
 }  // namespace
 
 hipError_t launch_gn_partial(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                             int iter, int grid, hipStream_t s) {
+                             int iter, int r_cap, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gn_partial_kernel, dim3(grid), dim3(kGnThreads), 0, s, sims, work, n_work, iter);
+  if (r_cap < 1 || r_cap > kMaxR) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)gn_partial_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             gn_chunk_lds_bytes(kGnThreads, kMaxR));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(gn_partial_kernel, dim3(grid), dim3(kGnThreads), gn_chunk_lds_bytes(kGnThreads, r_cap), s,
+                     sims, work, n_work, iter);
   return hipGetLastError();
 }
 

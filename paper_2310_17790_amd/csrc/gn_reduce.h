@@ -14,12 +14,26 @@
 
 namespace nsf {
 
+// The chunk's LDS, carved from the kernel's dynamic LDS: R [3][kGnChunk] and the group
+// sums part[NT] (FP64), then the Jacobian rows Jl [3 r_cap][kGnChunk + 1] (FP32), where
+// r_cap bounds the latent size of every sim the launch serves.
 template <int NT>
 struct GnChunkLds {
-  float Jl[3 * kMaxR][kGnChunk + 1];
-  double R[3][kGnChunk];
-  double part[NT];
+  double* R;
+  double* part;
+  float* Jl;
+  __device__ explicit GnChunkLds(char* lds)
+      : R(reinterpret_cast<double*>(lds)),
+        part(reinterpret_cast<double*>(lds) + 3 * kGnChunk),
+        Jl(reinterpret_cast<float*>(lds + (3 * kGnChunk + NT) * sizeof(double))) {}
+  __device__ float* row(int i) const { return Jl + i * (kGnChunk + 1); }
+  __device__ double& res(int c, int col) const { return R[c * kGnChunk + col]; }
 };
+
+// Dynamic LDS bytes of a chunk kernel with NT threads serving latents up to r_cap.
+constexpr int gn_chunk_lds_bytes(int nt, int r_cap) {
+  return (3 * kGnChunk + nt) * (int)sizeof(double) + 3 * r_cap * (kGnChunk + 1) * (int)sizeof(float);
+}
 
 __device__ __forceinline__ int gn_entries_dev(int r) { return r * (r + 1) / 2 + r; }
 
@@ -39,7 +53,7 @@ __device__ __forceinline__ void gn_decode_entry(int e, int r, int& j, int& k, bo
 // in batches of 8 per thread before any is stored, so their latencies overlap.
 template <int NT>
 __device__ __forceinline__ void gn_stage_jacobian(const SimDev& S, const float* J, int p0, int cnt,
-                                                  GnChunkLds<NT>& sh) {
+                                                  const GnChunkLds<NT>& sh) {
   constexpr int U = 8;
   const int r = S.r, ns = S.n_samp;
   const int total = 3 * r * kGnChunk;
@@ -54,14 +68,14 @@ __device__ __forceinline__ void gn_stage_jacobian(const SimDev& S, const float* 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = e0 + u * NT;
-      if (e < total) sh.Jl[e / kGnChunk][e % kGnChunk] = v[u];
+      if (e < total) sh.row(e / kGnChunk)[e % kGnChunk] = v[u];
     }
   }
 }
 
 // Reduce the staged chunk into gn_part (Jl and R must be staged and visible).
 template <int NT>
-__device__ __forceinline__ void gn_reduce_chunk(const SimDev& S, int p0, GnChunkLds<NT>& sh) {
+__device__ __forceinline__ void gn_reduce_chunk(const SimDev& S, int p0, const GnChunkLds<NT>& sh) {
   const int r = S.r, tid = threadIdx.x;
   const int E = gn_entries_dev(r);
   const int G = E >= NT ? 1 : NT / E;   // column groups per entry
@@ -75,11 +89,11 @@ __device__ __forceinline__ void gn_reduce_chunk(const SimDev& S, int p0, GnChunk
       bool is_b;
       gn_decode_entry(e, r, j, k, is_b);
       for (int c = 0; c < 3; ++c) {
-        const float* a = sh.Jl[c * r + j];
+        const float* a = sh.row(c * r + j);
         if (is_b) {
-          for (int col = g; col < kGnChunk; col += G) acc += (double)a[col] * sh.R[c][col];
+          for (int col = g; col < kGnChunk; col += G) acc += (double)a[col] * sh.res(c, col);
         } else {
-          const float* bb = sh.Jl[c * r + k];
+          const float* bb = sh.row(c * r + k);
           for (int col = g; col < kGnChunk; col += G) acc += (double)a[col] * (double)bb[col];
         }
       }

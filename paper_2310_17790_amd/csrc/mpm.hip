@@ -491,7 +491,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
 __global__ __launch_bounds__(kGnThreads) void g2p_gn_kernel(const SimDev* __restrict__ sims,
                                                             const BlockWork* __restrict__ work,
                                                             const int32_t* __restrict__ n_work) {
-  __shared__ GnChunkLds<kGnThreads> sh;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const GnChunkLds<kGnThreads> sh(lds);
   const int tid = threadIdx.x;
   const int total = *n_work;
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(kGnThreads) void g2p_gn_kernel(const SimDev* __rest
     // iteration 0: u(z_n) - u^n vanishes, r = -dt v^{n+1}
     if (tid < kGnChunk) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sh.R[c][tid] = p < ns ? -S.dt_d * (double)v[c] : 0.0;
+      for (int c = 0; c < 3; ++c) sh.res(c, tid) = p < ns ? -S.dt_d * (double)v[c] : 0.0;
     }
     __syncthreads();
     gn_reduce_chunk(S, wk.p0, sh);
@@ -563,9 +564,18 @@ hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int g
 }
 
 hipError_t launch_g2p_gn(const SimDev* sims, const BlockWork* work_gn, const int32_t* n_work_gn,
-                         int grid, hipStream_t s) {
+                         int r_cap, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(g2p_gn_kernel, dim3(grid), dim3(kGnThreads), 0, s, sims, work_gn, n_work_gn);
+  if (r_cap < 1 || r_cap > kMaxR) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)g2p_gn_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             gn_chunk_lds_bytes(kGnThreads, kMaxR));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(g2p_gn_kernel, dim3(grid), dim3(kGnThreads), gn_chunk_lds_bytes(kGnThreads, r_cap), s,
+                     sims, work_gn, n_work_gn);
   return hipGetLastError();
 }
 

@@ -129,8 +129,10 @@ hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* job
                                int grid, hipStream_t s);
 int fields_table_blocks_per_cu(int width, bool bf16, int tc);
 hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s);   // n <= 64
+// One job over n points with persistent workgroups on at most max_cus compute units (0: all;
+// a decode that runs beside latency-bound kernels leaves them the rest).
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
-                               hipStream_t s);
+                               hipStream_t s, int max_cus = 0);
 int fields_max_tangents(int width, bool bf16);
 int fields_group_waves(int tc);   // waves (32-point tiles) per workgroup
 
@@ -142,13 +144,14 @@ hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32
 hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int grid_sims,
                                 int grid_blocks, hipStream_t s);
 // G2P at the sample particles fused with the first Gauss-Newton reduction: work items are
-// Gauss-Newton chunks (kGnChunk sample particles).
+// Gauss-Newton chunks (kGnChunk sample particles). r_cap (<= kMaxR) bounds the latent size
+// of every sim in the launch and sizes the chunk's LDS.
 hipError_t launch_g2p_gn(const SimDev* sims, const BlockWork* work_gn, const int32_t* n_work_gn,
-                         int grid, hipStream_t s);
+                         int r_cap, int grid, hipStream_t s);
 constexpr int kSegMax = 512;   // bin segments up to this size are summed in index order
 // Gauss-Newton: chunk reduction of iteration iter >= 1, and the per-sim solve of any iteration.
 hipError_t launch_gn_partial(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
-                             int iter, int grid, hipStream_t s);
+                             int iter, int r_cap, int grid, hipStream_t s);
 hipError_t launch_gn_solve(const SimDev* sims, const int32_t* n_sims, int iter, int grid_sims,
                            hipStream_t s);
 
