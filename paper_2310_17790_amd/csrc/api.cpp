@@ -56,7 +56,7 @@ struct Carver {
 // Byte offsets of every buffer of a sim inside its arena.
 struct Layout {
   size_t simdev;
-  size_t w1p[3], whp[3], whb[3], bhp[3], w6p[3], b6[3];
+  size_t w1p[3], whp[3], whb[3], bhp[3], w6p[3], b6[3], w1q[3], bhq[3], w6q[3];
   size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, zdec, step, flags, gn_part;
   size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active,
       nonempty, n_active;
@@ -82,6 +82,9 @@ Layout make_layout(const nsf_sim_desc* d) {
     L.bhp[f] = c.take(ps.bhp * 4);
     L.w6p[f] = c.take(ps.w6p * 4);
     L.b6[f] = c.take(ps.b6 * 4);
+    L.w1q[f] = c.take(ps.w1q * 4);
+    L.bhq[f] = c.take(ps.bhq * 4);
+    L.w6q[f] = c.take(ps.w6q * 4);
   }
   L.X = c.take((size_t)3 * P * 4);
   L.plan = c.take((size_t)d->plan_steps * N * 4);
@@ -215,9 +218,9 @@ struct Plan {
   int32_t* d_counts = nullptr;    // [0..7] work counts, [8..15] claim counters
   SimDev* d_sims = nullptr;
   FieldJob* d_jobs = nullptr;
-  FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tAD = nullptr, *d_tD = nullptr;
+  FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tD = nullptr;
   BlockWork *d_bP = nullptr, *d_bGN = nullptr;
-  int nA = 0, nG = 0, nAD = 0, nD = 0, nP = 0, nGN = 0, nsims = 0;
+  int nA = 0, nG = 0, nD = 0, nP = 0, nGN = 0, nsims = 0;
   // launch grids (fixed for persistent plans)
   int gF = 0, gF0 = 0, gP = 0, gGN = 0, gSims = 0, gBlk = 0;
   FieldJob decode_job{};          // single-sim plans decode with the dense kernel
@@ -277,7 +280,7 @@ FieldJob base_job(const nsf_sim* s, int field, const double* z) {
 }
 
 void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc) {
-  const int span = kTile * fields_group_waves(ntan > 0 ? tc : 0);
+  const int span = fields_group_points(ntan > 0 ? tc : 0);
   for (int p0 = 0; p0 < n; p0 += span) {
     if (ntan == 0) {
       out.push_back({job, p0, 0, 0});
@@ -290,7 +293,7 @@ void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc) {
 // Primal-only groups that run in the tangent kernel (same workgroup shape as its
 // Jacobian groups).
 void add_prim_tiles(std::vector<FieldTile>& out, int job, int n, int tc) {
-  const int span = kTile * fields_group_waves(tc);
+  const int span = fields_group_points(tc);
   for (int p0 = 0; p0 < n; p0 += span) out.push_back({job, p0, 0, 0});
 }
 
@@ -321,8 +324,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   if (P.persistent) P.r_cap = kMaxR;
   std::vector<SimDev> sims;
   std::vector<FieldJob> jobs;
-  std::vector<FieldTile> tA_jac, tA_prim, tG, tD, tD0;  // tD: decode groups for the tangent
-                                                         // kernel, tD0: for the primal kernel
+  std::vector<FieldTile> tA_jac, tA_prim, tG, tD;  // tD: decode groups (primal kernel)
   std::vector<BlockWork> bP, bGN;
   for (size_t si = 0; si < P.members.size(); ++si) {
     nsf_sim* s = P.members[si];
@@ -350,7 +352,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
       // velocity as the directional derivative at the midpoint:
       // v = J((z_n + z_{n-1}) / 2) (z_n - z_{n-1}) / dt
       c.z = zc; c.z2 = zp; c.jvp = 1; c.jvp_scale = (float)(1.0 / H.dt_d);
-      for (int p0 = 0; p0 < N; p0 += kTile * fields_group_waves(P.tc))
+      for (int p0 = 0; p0 < N; p0 += fields_group_points(P.tc))
         tA_jac.push_back({(int)jobs.size(), p0, 0, 1});
     } else {
       add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
@@ -374,33 +376,29 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     FieldJob dj = base_job(s, NSF_FIELD_G, s->decode_mode == 2 ? H.zdec : zc);
     dj.idx = nullptr; dj.step = nullptr; dj.n = (int)s->n_part; dj.mode = 1;
     dj.out = H.xdec; dj.ldo = s->n_part;
-    add_prim_tiles(tD, (int)jobs.size(), (int)s->n_part, P.tc);
-    add_tiles(tD0, (int)jobs.size(), (int)s->n_part, 0, 0);
+    add_tiles(tD, (int)jobs.size(), (int)s->n_part, 0, 0);
     jobs.push_back(dj);
     P.decode_job = dj;
     for (int p0 = 0; p0 < N; p0 += kMpmBlock) bP.push_back({(int)si, p0});
     for (int p0 = 0; p0 < S; p0 += kGnChunk) bGN.push_back({(int)si, p0});
   }
-  // Longest groups first: Jacobian groups, then decode, then the primal-only groups.
-  std::vector<FieldTile> tA(tA_jac), tAD(tA_jac);
+  // Longest groups first: Jacobian groups, then the primal-only groups.
+  std::vector<FieldTile> tA(tA_jac);
   tA.insert(tA.end(), tA_prim.begin(), tA_prim.end());
-  if (P.decode) tAD.insert(tAD.end(), tD.begin(), tD.end());
-  tAD.insert(tAD.end(), tA_prim.begin(), tA_prim.end());
-  P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nAD = (int)tAD.size(); P.nD = (int)tD0.size();
+  P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nD = (int)tD.size();
   P.nP = (int)bP.size(); P.nGN = (int)bGN.size();
   P.nsims = (int)sims.size();
-  std::vector<int32_t> counts = {P.nA, P.nG, P.nAD, P.nP, 0 /* unused */, P.nGN, P.nsims, P.nD,
+  std::vector<int32_t> counts = {P.nA, P.nG, 0 /* unused */, P.nP, 0 /* unused */, P.nGN, P.nsims, P.nD,
                                  0, 0, 0, 0, 0, 0, 0, 0};
   // Regions of the device buffer. A persistent plan keeps fixed region capacities (grown
   // by half when exceeded), so its captured graph stays valid while tables are rewritten.
   struct Region { const void* data; size_t bytes; };
-  constexpr int kRegions = 9;
+  constexpr int kRegions = 8;
   const Region reg[kRegions] = {
       {counts.data(), counts.size() * 4}, {sims.data(), sims.size() * sizeof(SimDev)},
       {jobs.data(), jobs.size() * sizeof(FieldJob)}, {tA.data(), tA.size() * sizeof(FieldTile)},
-      {tG.data(), tG.size() * sizeof(FieldTile)}, {tAD.data(), tAD.size() * sizeof(FieldTile)},
-      {tD0.data(), tD0.size() * sizeof(FieldTile)}, {bP.data(), bP.size() * sizeof(BlockWork)},
-      {bGN.data(), bGN.size() * sizeof(BlockWork)}};
+      {tG.data(), tG.size() * sizeof(FieldTile)}, {tD.data(), tD.size() * sizeof(FieldTile)},
+      {bP.data(), bP.size() * sizeof(BlockWork)}, {bGN.data(), bGN.size() * sizeof(BlockWork)}};
   bool relayout = P.caps.empty();
   for (int i = 0; i < kRegions && !relayout; ++i) relayout = reg[i].bytes > P.caps[i];
   if (relayout) {
@@ -427,10 +425,9 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.d_jobs = reinterpret_cast<FieldJob*>(b + off[2]);
   P.d_tA = reinterpret_cast<FieldTile*>(b + off[3]);
   P.d_tG = reinterpret_cast<FieldTile*>(b + off[4]);
-  P.d_tAD = reinterpret_cast<FieldTile*>(b + off[5]);
-  P.d_tD = reinterpret_cast<FieldTile*>(b + off[6]);
-  P.d_bP = reinterpret_cast<BlockWork*>(b + off[7]);
-  P.d_bGN = reinterpret_cast<BlockWork*>(b + off[8]);
+  P.d_tD = reinterpret_cast<FieldTile*>(b + off[5]);
+  P.d_bP = reinterpret_cast<BlockWork*>(b + off[6]);
+  P.d_bGN = reinterpret_cast<BlockWork*>(b + off[7]);
   if (P.persistent) {
     NSF_HIP(hipStreamSynchronize(stream));  // the previous upload has been consumed
     char* st = static_cast<char*>(P.staging);
@@ -452,13 +449,13 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   const int fcap = cus * fields_table_blocks_per_cu(P.width, P.bf16, P.tc);
   const int fcap0 = cus * fields_table_blocks_per_cu(P.width, P.bf16, 0);
   auto mn = [](int a, int b) { return a < b ? a : b; };
-  P.gF = P.persistent ? fcap : mn(fcap, std::max(P.nA, std::max(P.nAD, P.nG)));
+  P.gF = P.persistent ? fcap : mn(fcap, std::max(P.nA, P.nG));
   P.gF0 = P.persistent ? fcap0 : mn(fcap0, P.nD);
   P.gP = P.persistent ? 4 * cus : P.nP;
   P.gGN = P.persistent ? 4 * cus : P.nGN;
   P.gSims = P.persistent ? cus : P.nsims;
   P.gBlk = 5 * cus;   // gather workgroups (5 fit per CU) loop over each sim's active node blocks
-  if (P.decode && !P.side) {
+  if (P.pipelined && !P.side) {
     NSF_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
     NSF_HIP(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
     NSF_HIP(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
@@ -468,7 +465,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
 
 // Claim counters (zeroed at the start of every launch sequence): 8 inference, 9 + k the
 // Gauss-Newton iterate pass k, 13 refresh (inference + decode), 14 decode alone.
-constexpr int kClaimA = 8, kClaimG = 9, kClaimAD = 13, kClaimD = 14;
+constexpr int kClaimA = 8, kClaimG = 9, kClaimD = 14;
 
 // Field inference of the step for the current latent, alone (prologue after create or
 // set_latent).
@@ -488,23 +485,25 @@ constexpr int kPipelinedFreeCuDiv = NSF_PIPE_DIV;
 
 // Decode of all particles, on the side stream between a fork and a join recorded on s
 // (inline on s when there is no side stream).
-nsf_status fork_decode(Plan& P, hipStream_t s) {
-  if (s == nullptr || !P.side) {
-    if (P.nsims == 1 && !P.persistent)
-      NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, s));
-    else
-      NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
-                                  P.d_counts + kClaimD, P.gF0, s));
-    return NSF_OK;
-  }
-  NSF_HIP(hipEventRecord(P.ev_fork, s));
-  NSF_HIP(hipStreamWaitEvent(P.side, P.ev_fork, 0));
+// Decode of all particles on stream s: the dense kernel for one sim, else the primal
+// table kernel over every sim's decode groups.
+nsf_status launch_decode(Plan& P, hipStream_t s, int max_cus) {
   if (P.nsims == 1 && !P.persistent)
-    NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, P.side,
-                                P.pipelined ? device_cus() - device_cus() / kPipelinedFreeCuDiv : 0));
+    NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, s, max_cus));
   else
     NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
-                                P.d_counts + kClaimD, P.gF0, P.side));
+                                P.d_counts + kClaimD, P.gF0, s));
+  return NSF_OK;
+}
+
+// Pipelined decode: on the side stream between a fork and a join recorded on s (inline on
+// s when there is no side stream), on all but 1 / kPipelinedFreeCuDiv of the CUs.
+nsf_status fork_decode(Plan& P, hipStream_t s) {
+  if (s == nullptr || !P.side) return launch_decode(P, s, 0);
+  NSF_HIP(hipEventRecord(P.ev_fork, s));
+  NSF_HIP(hipStreamWaitEvent(P.side, P.ev_fork, 0));
+  const nsf_status st = launch_decode(P, P.side, device_cus() - device_cus() / kPipelinedFreeCuDiv);
+  if (st != NSF_OK) return st;
   NSF_HIP(hipEventRecord(P.ev_join, P.side));
   return NSF_OK;
 }
@@ -514,27 +513,14 @@ nsf_status join_decode(Plan& P, hipStream_t s) {
   return NSF_OK;
 }
 
-// The next step's field inference at the current latent, with (decode = true) the decode
-// of all particles at the same latent, concurrently. Counters must have been reset in
-// this sequence.
+// The next step's field inference at the current latent, then (decode = true) the decode
+// of all particles at the same latent, on the same stream: the two persistent kernels fill
+// the device one after the other (run side by side they only contend for the same CUs).
+// Counters must have been reset in this sequence.
 nsf_status enqueue_refresh_body(Plan& P, hipStream_t s, bool decode) {
-  if (!decode) {
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
-                                P.d_counts + kClaimA, P.gF, s));
-    return NSF_OK;
-  }
-  if (s == nullptr || !P.side) {
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tAD, P.d_counts + 2,
-                                P.d_counts + kClaimAD, P.gF, s));
-    return NSF_OK;
-  }
-  // fork: decode on the side stream, the next step's inference (tangent kernel) on the
-  // main stream; join before the step continues
-  nsf_status st = fork_decode(P, s);
-  if (st != NSF_OK) return st;
   NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
                               P.d_counts + kClaimA, P.gF, s));
-  return join_decode(P, s);
+  return decode ? launch_decode(P, s, 0) : NSF_OK;
 }
 
 // Refresh outside a step (nsf_refresh): a pipelined sim first points its decode at the
@@ -686,15 +672,24 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   for (int f = 0; f < 3; ++f) {
     const int dd = kFieldOut[f];
     const PackSizes ps = pack_sizes(r, W, dd);
-    std::vector<float> w1p(ps.w1p), whp(ps.whp), bhp(ps.bhp), w6p(ps.w6p), b6(ps.b6);
+    std::vector<float> w1p(ps.w1p), whp(ps.whp), bhp(ps.bhp), w6p(ps.w6p), b6(ps.b6), w1q(ps.w1q),
+        bhq(ps.bhq), w6q(ps.w6q);
     std::vector<uint16_t> whb(ps.whb);
-    pack_field(d->weights[f], r, W, dd, w1p.data(), whp.data(), whb.data(), bhp.data(), w6p.data(), b6.data());
-    NSF_HIP(hipMemcpyAsync(A + L.w1p[f], w1p.data(), w1p.size() * 4, hipMemcpyHostToDevice, s));
-    NSF_HIP(hipMemcpyAsync(A + L.whp[f], whp.data(), whp.size() * 4, hipMemcpyHostToDevice, s));
-    NSF_HIP(hipMemcpyAsync(A + L.whb[f], whb.data(), whb.size() * 2, hipMemcpyHostToDevice, s));
-    NSF_HIP(hipMemcpyAsync(A + L.bhp[f], bhp.data(), bhp.size() * 4, hipMemcpyHostToDevice, s));
-    NSF_HIP(hipMemcpyAsync(A + L.w6p[f], w6p.data(), w6p.size() * 4, hipMemcpyHostToDevice, s));
-    NSF_HIP(hipMemcpyAsync(A + L.b6[f], b6.data(), b6.size() * 4, hipMemcpyHostToDevice, s));
+    pack_field(d->weights[f], r, W, dd,
+               PackOut{w1p.data(), whp.data(), whb.data(), bhp.data(), w6p.data(), b6.data(), w1q.data(),
+                       bhq.data(), w6q.data()});
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+      return hipMemcpyAsync(A + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    NSF_HIP(up(L.w1p[f], w1p.data(), w1p.size() * 4));
+    NSF_HIP(up(L.whp[f], whp.data(), whp.size() * 4));
+    NSF_HIP(up(L.whb[f], whb.data(), whb.size() * 2));
+    NSF_HIP(up(L.bhp[f], bhp.data(), bhp.size() * 4));
+    NSF_HIP(up(L.w6p[f], w6p.data(), w6p.size() * 4));
+    NSF_HIP(up(L.b6[f], b6.data(), b6.size() * 4));
+    NSF_HIP(up(L.w1q[f], w1q.data(), w1q.size() * 4));
+    NSF_HIP(up(L.bhq[f], bhq.data(), bhq.size() * 4));
+    NSF_HIP(up(L.w6q[f], w6q.data(), w6q.size() * 4));
     NSF_HIP(hipStreamSynchronize(s));  // host staging vectors die at the end of this scope
     FieldPack& fp = sim->pack[f];
     fp.w1p = reinterpret_cast<const float*>(A + L.w1p[f]);
@@ -702,6 +697,9 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
     fp.whb = reinterpret_cast<const bf16x8*>(A + L.whb[f]);
     fp.bhp = reinterpret_cast<const float*>(A + L.bhp[f]);
     fp.w6p = reinterpret_cast<const float*>(A + L.w6p[f]);
+    fp.w1q = reinterpret_cast<const float*>(A + L.w1q[f]);
+    fp.bhq = reinterpret_cast<const float*>(A + L.bhq[f]);
+    fp.w6q = reinterpret_cast<const float*>(A + L.w6q[f]);
     fp.b6 = reinterpret_cast<const float*>(A + L.b6[f]);
   }
   const int64_t P = d->n_particles;

@@ -126,37 +126,6 @@ __device__ __forceinline__ void init_hidden(f32x16 (&acc)[T][W / 32], const floa
 }
 
 template <int W, int T, class APtr>
-__device__ __forceinline__ void hidden_f32(f32x16 (&acc)[T][W / 32], const float (&H)[T][W / 2],
-                                           APtr A, int lane, int nt) {
-  constexpr int MB = W / 32, SG = W / 4;   // groups of two K-steps
-  const f32x2* A2 = reinterpret_cast<const f32x2*>(A);
-  // fragment of K-steps 2 sg, 2 sg + 1 of M-block mb: half (sg & 1) of the f32x4 at
-  // (mb * (W / 8) + sg / 2) * 64 + lane
-  auto at = [&](int mb, int sg) { return A2[2 * ((mb * (W / 8) + (sg >> 1)) * 64 + lane) + (sg & 1)]; };
-  f32x2 a2[2][MB];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) a2[0][mb] = at(mb, 0);
-#pragma unroll
-  for (int sg = 0; sg < SG; ++sg) {
-    if (sg + 1 < SG) {
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) a2[(sg + 1) & 1][mb] = at(mb, sg + 1);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        acc[0][mb] = mfma_f32(a2[sg & 1][mb][j], H[0][2 * sg + j], acc[0][mb]);
-#pragma unroll
-        for (int t = 1; t < T; ++t)
-          if (t <= nt) acc[t][mb] = mfma_f32(a2[sg & 1][mb][j], H[t][2 * sg + j], acc[t][mb]);
-      }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
-template <int W, int T, class APtr>
 __device__ __forceinline__ void hidden_bf16(f32x16 (&acc)[T][W / 32],
                                             const bf16x8 (&Hb)[T][W / 16],
                                             APtr whb_layer, int lane, int nt) {
@@ -219,6 +188,105 @@ __device__ __forceinline__ void save_preact(const FieldJob& jb, const f32x16 (&a
           f32x4{acc[0][mb][4 * q], acc[0][mb][4 * q + 1], acc[0][mb][4 * q + 2], acc[0][mb][4 * q + 3]};
 }
 
+// ---- FP32 precision: 16-point tiles on v_mfma_f32_16x16x4_f32 ------------------------
+// Lane l holds point l % 16 of the tile and lane group g = l / 16. The 16x16 accumulator
+// gives lane (point, g) neurons 16 mb + 4 g + v (v = 0..3) of M-block mb, and K-step
+// s = 4 mb + v of the next layer consumes exactly those registers: the host stores, for
+// output row m and K-group sg, the inputs 16 sg + 4 g + 0..3 of row m as lane (m % 16 + 16 g)'s
+// four floats. Biases and output weights are then read in plain neuron order. A tile
+// holds a quarter of the registers of a 32-point tile, so twice as many waves fit on a
+// SIMD (two with two tangents, four for the primal), which is what hides the activations
+// of one wave behind the matrix products of another.
+constexpr int kTile16 = 16;
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int W, int T>
+__device__ __forceinline__ void activate16(const f32x4 (&acc)[T][W / 16], float (&H)[T][W / 4], int nt) {
+#pragma unroll
+  for (int mb = 0; mb < W / 16; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float y, dy;
+      elu_pair<false>(acc[0][mb][v], y, dy);
+      H[0][4 * mb + v] = y;
+#pragma unroll
+      for (int t = 1; t < T; ++t)
+        if (t <= nt) H[t][4 * mb + v] = dy * acc[t][mb][v];
+    }
+}
+
+// Accumulators start from the layer's bias (plain order) or zero (tangents).
+template <int W, int T>
+__device__ __forceinline__ void init16(f32x4 (&acc)[T][W / 16], const float* bias, int g) {
+#pragma unroll
+  for (int mb = 0; mb < W / 16; ++mb) {
+    acc[0][mb] = *reinterpret_cast<const f32x4*>(bias + 16 * mb + 4 * g);
+#pragma unroll
+    for (int t = 1; t < T; ++t) acc[t][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+}
+
+// One hidden layer from LDS: A is [W/16 output blocks][W/16 K-groups][64 lanes] f32x4,
+// read in halves (two K-steps) one half ahead of its use.
+template <int W, int T>
+__device__ __forceinline__ void hidden16(f32x4 (&acc)[T][W / 16], const float (&H)[T][W / 4],
+                                         const f32x4* A, int lane, int nt) {
+  constexpr int MB = W / 16, SG = W / 16, HS = 2 * SG;
+  const f32x2* A2 = reinterpret_cast<const f32x2*>(A);
+  auto at = [&](int mb, int hs) { return A2[2 * ((mb * SG + (hs >> 1)) * 64 + lane) + (hs & 1)]; };
+  f32x2 a2[2][MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) a2[0][mb] = at(mb, 0);
+#pragma unroll
+  for (int hs = 0; hs < HS; ++hs) {
+    if (hs + 1 < HS) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) a2[(hs + 1) & 1][mb] = at(mb, hs + 1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        acc[0][mb] = mfma16(a2[hs & 1][mb][j], H[0][2 * hs + j], acc[0][mb]);
+#pragma unroll
+        for (int t = 1; t < T; ++t)
+          if (t <= nt) acc[t][mb] = mfma16(a2[hs & 1][mb][j], H[t][2 * hs + j], acc[t][mb]);
+      }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// out_o = sum_n W6[o][n] H[n] over the lane group's neurons, then over the four groups
+// (every lane ends with the same sum: the pairwise additions commute).
+template <int W>
+__device__ __forceinline__ float output_dot16(const float* w6q, int o, int g, const float (&Hrow)[W / 4]) {
+  const float* w = w6q + o * W + 4 * g;
+  float s = 0.f;
+#pragma unroll
+  for (int mb = 0; mb < W / 16; ++mb) {
+    const f32x4 w4 = *reinterpret_cast<const f32x4*>(w + 16 * mb);
+    s += w4[0] * Hrow[4 * mb + 0];
+    s += w4[1] * Hrow[4 * mb + 1];
+    s += w4[2] * Hrow[4 * mb + 2];
+    s += w4[3] * Hrow[4 * mb + 3];
+  }
+  s += __shfl_xor(s, 16);
+  return s + __shfl_xor(s, 32);
+}
+
+template <int W, int T>
+__device__ __forceinline__ void save_preact16(const FieldJob& jb, const f32x4 (&acc)[T][W / 16],
+                                              int layer, int p, bool valid, int g) {
+  if (jb.saved == nullptr || !valid) return;
+  float* row = jb.saved + ((int64_t)layer * jb.n + p) * W;
+#pragma unroll
+  for (int mb = 0; mb < W / 16; ++mb) *reinterpret_cast<f32x4*>(row + 16 * mb + 4 * g) = acc[0][mb];
+}
+
 // Bytes of one packed hidden layer and of one LDS DMA instruction per wave (64 lanes x 16 B).
 template <int W, bool BF>
 struct HiddenLayer {
@@ -228,20 +296,16 @@ struct HiddenLayer {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// Copy hidden layer k of `w` into LDS buffer dst with direct global->LDS loads; every
-// wave of the workgroup moves its share of the 1 KB chunks.
+// Copy hidden layer k of `w` into LDS buffer dst with direct global->LDS loads; the 1 KB
+// chunks are dealt to the waves of the workgroup round-robin.
 template <int W, bool BF, int WPG>
 __device__ __forceinline__ void dma_layer(const FieldPack& w, int k, char* dst, int wave, int lane) {
-  constexpr int kPer = HiddenLayer<W, BF>::kChunks / WPG;
-  static_assert(HiddenLayer<W, BF>::kChunks % WPG == 0, "layer must split evenly over waves");
   const char* src = (BF ? reinterpret_cast<const char*>(w.whb) : reinterpret_cast<const char*>(w.whp)) +
                     (size_t)k * HiddenLayer<W, BF>::kBytes;
 #pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const int chunk = wave * kPer + i;
+  for (int chunk = wave; chunk < HiddenLayer<W, BF>::kChunks; chunk += WPG)
     __builtin_amdgcn_global_load_lds(src + chunk * 1024 + lane * 16,
                                       (lds_void*)(dst + chunk * 1024), 16, 0, 0);
-  }
 }
 
 // Copy all four hidden layers of `w` (contiguous in the pack) into LDS; chunks are dealt
@@ -271,6 +335,7 @@ __device__ __forceinline__ void wait_dma_and_sync() {
 template <int W, int NT, bool BF, int WPG, bool RES = false, class NextFn>
 __device__ __forceinline__ void run_group(const FieldJob& jb, int p0, int t0, NextFn&& next,
                                           char* lds, int wave, int lane) {
+  static_assert(BF, "FP32 tiles run in run_group16");
   constexpr int MB = W / 32;
   constexpr int T = 1 + NT;
   constexpr int nt = NT;  // compile-time: no per-MFMA guards
@@ -330,11 +395,8 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0, int t0, Ne
 
   if constexpr (NT == 0) save_preact<W, T>(jb, acc, 0, p, valid, h);
   float H[T][KH];
-  if constexpr (!BF) {
-    activate_f32<W, T>(acc, H, nt);
-  }
-  bf16x8 Hb[T][BF ? W / 16 : 1];
-  if constexpr (BF) activate_bf16<W, T>(acc, Hb, nt);
+  bf16x8 Hb[T][W / 16];
+  activate_bf16<W, T>(acc, Hb, nt);
   // Hidden layers 2..5 (k = 0..3): wait for layer k in LDS, start fetching layer k + 1
   // (after the last layer: the next group's first layer), multiply, activate.
 #pragma unroll 1
@@ -345,15 +407,9 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0, int t0, Ne
       dma_layer<W, BF, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
     }
     init_hidden<W, T>(acc, jb.w.bhp + k * W, h);
-    if constexpr (!BF) {
-      hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(cur), lane, nt);
-      if constexpr (NT == 0) save_preact<W, T>(jb, acc, k + 1, p, valid, h);
-      activate_f32<W, T>(acc, H, nt);
-    } else {
-      hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(cur), lane, nt);
-      if constexpr (NT == 0) save_preact<W, T>(jb, acc, k + 1, p, valid, h);
-      activate_bf16<W, T>(acc, Hb, nt);
-    }
+    hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(cur), lane, nt);
+    if constexpr (NT == 0) save_preact<W, T>(jb, acc, k + 1, p, valid, h);
+    activate_bf16<W, T>(acc, Hb, nt);
   }
   if constexpr (!RES) {
     wait_dma_and_sync();
@@ -362,8 +418,7 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0, int t0, Ne
   }
   char* last = lds + (RES ? 3 : 1) * LB;
   init_hidden<W, T>(acc, jb.w.bhp + 3 * W, h);
-  if constexpr (!BF) hidden_f32<W, T>(acc, H, reinterpret_cast<const f32x4*>(last), lane, nt);
-  else hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(last), lane, nt);
+  hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(last), lane, nt);
   if constexpr (NT == 0) save_preact<W, T>(jb, acc, 4, p, valid, h);
   activate_f32<W, T>(acc, H, nt);
 
@@ -380,9 +435,10 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0, int t0, Ne
   }
   // Output layer, primal.
   if (t0 == 0) {
-#pragma unroll
-    for (int o = 0; o < 9; ++o) {
-      if (o < d) {
+    // one output at a time: unrolled, the weight loads of all nine would be hoisted
+#pragma unroll 1
+    for (int o = 0; o < d; ++o) {
+      {
         const float y = output_dot<W>(jb.w.w6p, o, h, H[0]) + jb.w.b6[o];
         float v = jb.scale[o] * y + jb.shift[o];
         if (jb.mode == 1) v += (o == 0) ? X0 : (o == 1) ? X1 : X2;
@@ -404,15 +460,131 @@ __device__ __forceinline__ void run_group(const FieldJob& jb, int p0, int t0, Ne
   }
 }
 
+// FP32 precision: one wave evaluates a 16-point tile (see kTile16) with streamed weights,
+// in the same barrier sequence as run_group.
+template <int W, int NT, int WPG, class NextFn>
+__device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, NextFn&& next,
+                                            char* lds, int wave, int lane) {
+  constexpr int MB = W / 16;
+  constexpr int T = 1 + NT;
+  constexpr int nt = NT;
+  constexpr int LB = HiddenLayer<W, false>::kBytes;
+  const int g = lane >> 4;
+  const int p = p0 + (lane & 15);
+  const bool valid = p < jb.n;
+  int gi = jb.p_off + (valid ? p : jb.n - 1);
+  if (jb.idx != nullptr) {
+    const int32_t* row = jb.idx;
+    if (jb.step != nullptr) row += (*jb.step % jb.plan_steps) * (int64_t)jb.plan_ld;
+    gi = row[gi];
+  }
+  const float X0 = jb.X[gi];
+  const float X1 = jb.X[jb.ldx + gi];
+  const float X2 = jb.X[2 * jb.ldx + gi];
+  const int r = jb.r;
+
+  f32x4 acc[T][MB];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // Layer 1: input rows 0..2 = X, 3..2+r = z, 3+r = 1 (bias column), four per K-step.
+  const int K1q = (r + 7) >> 2;
+  const bool jvp = jb.jvp != 0;
+  for (int s4 = 0; s4 < K1q; ++s4) {
+    const int k = 4 * s4 + g;
+    float b0 = 0.f, bt = 0.f;
+    if (k == 0) b0 = X0;
+    else if (k == 1) b0 = X1;
+    else if (k == 2) b0 = X2;
+    else if (k < 3 + r && jb.zrows != nullptr) {
+      b0 = jb.zrows[(int64_t)(valid ? p : jb.n - 1) * r + (k - 3)];
+    } else if (k < 3 + r) {
+      const double zk = jb.z[k - 3];
+      if (jvp) {
+        const double z2k = jb.z2[k - 3];
+        b0 = (float)(0.5 * (zk + z2k));
+        bt = (float)(zk - z2k);
+      } else {
+        b0 = (float)zk;
+      }
+    } else if (k == 3 + r) b0 = 1.f;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const float a = jb.w.w1q[(mb * K1q + s4) * 64 + lane];
+      acc[0][mb] = mfma16(a, b0, acc[0][mb]);
+#pragma unroll
+      for (int t = 1; t < T; ++t)
+        if (t <= nt) acc[t][mb] = mfma16(a, jvp ? bt : ((k == 3 + t0 + t - 1) ? 1.f : 0.f), acc[t][mb]);
+    }
+  }
+  if constexpr (NT == 0) save_preact16<W, T>(jb, acc, 0, p, valid, g);
+  float H[T][W / 4];
+  activate16<W, T>(acc, H, nt);
+  // Hidden layers 2..5 (k = 0..3), as in run_group.
+#pragma unroll 1
+  for (int k = 0; k < 4; ++k) {
+    char* cur = lds + (k & 1) * LB;
+    wait_dma_and_sync();
+    if (k < 3) dma_layer<W, false, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
+    else if (const FieldPack* next_w = next()) dma_layer<W, false, WPG>(*next_w, 0, lds, wave, lane);
+    init16<W, T>(acc, jb.w.bhq + k * W, g);
+    hidden16<W, T>(acc, H, reinterpret_cast<const f32x4*>(cur), lane, nt);
+    if constexpr (NT == 0) save_preact16<W, T>(jb, acc, k + 1, p, valid, g);
+    activate16<W, T>(acc, H, nt);
+  }
+
+  const int d = jb.d;
+  if constexpr (NT >= 1) {
+    if (jvp) {  // directional derivative only: out = scale * (W6 T) * jvp_scale
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float y = output_dot16<W>(jb.w.w6q, c, g, H[1]);
+        if (valid && g == c) jb.out[c * jb.ldo + p] = jb.scale[c] * y * jb.jvp_scale;
+      }
+      return;
+    }
+  }
+  if (t0 == 0) {
+    // one output at a time: unrolled, the weight loads of all nine would be hoisted
+#pragma unroll 1
+    for (int o = 0; o < d; ++o) {
+      {
+        const float y = output_dot16<W>(jb.w.w6q, o, g, H[0]) + jb.w.b6[o];
+        float v = jb.scale[o] * y + jb.shift[o];
+        if (jb.mode == 1) v += (o == 0) ? X0 : (o == 1) ? X1 : X2;
+        if (valid && g == (o & 3)) jb.out[o * jb.ldo + p] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 1; t < T; ++t) {
+    if (t <= nt) {
+      const int j = t0 + t - 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float y = output_dot16<W>(jb.w.w6q, c, g, H[t]);
+        if (valid && g == c) jb.jac[(c * r + j) * jb.ldj + p] = jb.scale[c] * y;
+      }
+    }
+  }
+}
+
 // Run a group with its tangent count as a template argument (0 .. TC).
 template <int W, int TC, bool BF, int WPG, class NextFn>
 __device__ __forceinline__ void dispatch_nt(const FieldJob& jb, int p0, int t0, int nt,
                                             NextFn&& next, char* lds, int wave, int lane) {
   if constexpr (TC > 0) {
-    if (nt == TC) { run_group<W, TC, BF, WPG>(jb, p0 + kTile * wave, t0, next, lds, wave, lane); return; }
+    if (nt == TC) {
+      if constexpr (BF) run_group<W, TC, true, WPG>(jb, p0 + kTile * wave, t0, next, lds, wave, lane);
+      else run_group16<W, TC, WPG>(jb, p0 + kTile16 * wave, t0, next, lds, wave, lane);
+      return;
+    }
     dispatch_nt<W, TC - 1, BF, WPG>(jb, p0, t0, nt, next, lds, wave, lane);
   } else {
-    run_group<W, 0, BF, WPG>(jb, p0 + kTile * wave, t0, next, lds, wave, lane);
+    if constexpr (BF) run_group<W, 0, true, WPG>(jb, p0 + kTile * wave, t0, next, lds, wave, lane);
+    else run_group16<W, 0, WPG>(jb, p0 + kTile16 * wave, t0, next, lds, wave, lane);
   }
 }
 
@@ -466,30 +638,31 @@ __device__ __forceinline__ void idle_group(const FieldJob& jb, NextFn&& next, ch
   if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
 }
 
-// One job over n points (decode), weights streamed, persistent workgroups. Tiles are dealt
+// One job over n points (FP32 decode), weights streamed, persistent workgroups, 16-point
+// tiles. Tiles are dealt
 // so that every round but the last fills all waves of all workgroups, and the last round's
 // tiles go to wave 0 of distinct workgroups, which then run alone on their SIMDs:
 // tile t = round * gridDim.x * WPG + wave * gridDim.x + blockIdx.x.
-template <int W, bool BF, int WPG>
+template <int W, int WPG>
 __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, int n_tiles) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int G = gridDim.x, b = blockIdx.x, per_round = G * WPG;
   if (b >= n_tiles) return;
-  dma_layer<W, BF, WPG>(job.w, 0, lds, wave, lane);
+  dma_layer<W, false, WPG>(job.w, 0, lds, wave, lane);
 #pragma unroll 1
   for (int base = 0; base + b < n_tiles; base += per_round) {
     const bool more = base + per_round + b < n_tiles;
     auto next = [&]() -> const FieldPack* { return more ? &job.w : nullptr; };
     const int t = base + wave * G + b;
-    if (t < n_tiles) run_group<W, 0, BF, WPG>(job, t * kTile, 0, next, lds, wave, lane);
-    else idle_group<W, BF, WPG>(job, next, lds, wave, lane);
+    if (t < n_tiles) run_group16<W, 0, WPG>(job, t * kTile16, 0, next, lds, wave, lane);
+    else idle_group<W, false, WPG>(job, next, lds, wave, lane);
   }
 }
 
-// One job over n points (decode), weights resident: every workgroup loads the four hidden
-// layers once, then each wave takes tiles blockIdx.x * WPG + wave, + gridDim.x * WPG, ...
+// One job over n points (BF16 decode), weights resident: every workgroup loads the four
+// hidden layers once, then each wave runs its tiles independently.
 template <int W, bool BF, int WPG>
 __global__ __launch_bounds__(64 * WPG) void fields_dense_res_kernel(FieldJob job, int n_tiles) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -498,8 +671,10 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_res_kernel(FieldJob job
   dma_all_layers<W, BF, WPG>(job.w, lds, wave, lane);
   wait_dma_and_sync();
   auto none = []() -> const FieldPack* { return nullptr; };
+  // tile t = round * gridDim.x * WPG + wave * gridDim.x + blockIdx.x: the last, partial
+  // round's tiles go to distinct workgroups
 #pragma unroll 1
-  for (int t = blockIdx.x * WPG + wave; t < n_tiles; t += gridDim.x * WPG) {
+  for (int t = wave * (int)gridDim.x + blockIdx.x; t < n_tiles; t += gridDim.x * WPG) {
     // keep the weight reads inside the tile: the LDS contents never change, and hoisting
     // them out of the loop would only exhaust registers
     __asm__ volatile("" ::: "memory");
@@ -510,14 +685,21 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_res_kernel(FieldJob job
 // Tangents one wave carries next to the primal, by register budget (512 per lane).
 constexpr int kTcF32W64 = 3, kTcF32W128 = 2, kTcBf16W64 = 4, kTcBf16W128 = 2;
 
-// Waves per workgroup: kernels with tangents hold ~500 registers (one wave per SIMD),
-// primal-only kernels fit two waves per SIMD.
-template <int TC> struct Wpg { static constexpr int value = TC > 0 ? 4 : 8; };
+// Waves per workgroup (one workgroup per CU: its two LDS layer buffers take 128 KB at
+// width 128). BF16, 32-point tiles: with tangents ~500 registers (one wave per SIMD),
+// primal only two waves per SIMD. FP32, 16-point tiles: two waves per SIMD with tangents,
+// four for the primal. Either way a group spans the same points.
+template <int TC, bool BF> struct Wpg {
+  static constexpr int value = BF ? (TC > 0 ? 4 : 8) : (TC > 0 ? 8 : 16);
+};
+static_assert(kTile * Wpg<1, true>::value == kTile16 * Wpg<1, false>::value &&
+                  kTile * Wpg<0, true>::value == kTile16 * Wpg<0, false>::value,
+              "a group spans the same points in both precisions");
 
 template <int W, int TC, bool BF>
 hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int32_t* n_groups,
                         int32_t* claim, int grid, hipStream_t s) {
-  constexpr int WPG = Wpg<TC>::value;
+  constexpr int WPG = Wpg<TC, BF>::value;
   constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes;
   auto k = fields_table_kernel<W, TC, BF, WPG>;
   static bool attr = false;
@@ -531,11 +713,15 @@ hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int
 }
 
 // Streamed-weight decode: as many persistent workgroups as fit on the device at once.
-template <int W, bool BF>
+// FP32 decode: eight waves per workgroup (two per SIMD) hold a 16-point tile each without
+// spilling; sixteen spill and measured slower.
+constexpr int kDenseWpg16 = 8;
+
+template <int W>
 hipError_t launch_dense(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
-  constexpr int WPG = Wpg<0>::value;
-  constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes;
-  auto k = fields_dense_kernel<W, BF, WPG>;
+  constexpr int WPG = kDenseWpg16;
+  constexpr int lds = 2 * HiddenLayer<W, false>::kBytes;
+  auto k = fields_dense_kernel<W, WPG>;
   static int per_cu = 0;
   if (per_cu == 0) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -549,27 +735,25 @@ hipError_t launch_dense(const FieldJob& job, int n_tiles, int cus, hipStream_t s
   return hipGetLastError();
 }
 
-#ifndef NSF_DENSE_RES_WPG
-#define NSF_DENSE_RES_WPG 8
-#endif
-constexpr int kDenseResWpg = NSF_DENSE_RES_WPG;
+// BF16 decode: twelve waves per workgroup (three per SIMD) measured fastest.
+constexpr int kDenseResWpg = 12;
 
-// Resident-weight decode: one workgroup per CU (the four hidden layers take 4 W^2 x 2 B =
-// 128 KB of LDS at width 128 in BF16).
+// Resident-weight decode: one workgroup per CU at width 128 (the four hidden layers take
+// 4 W^2 x 2 B = 128 KB of LDS in BF16).
 template <int W, bool BF>
 hipError_t launch_dense_res(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
   constexpr int WPG = kDenseResWpg;
   constexpr int lds = 4 * HiddenLayer<W, BF>::kBytes;
   static_assert(lds <= 160 * 1024, "resident weights must fit in LDS");
   auto k = fields_dense_res_kernel<W, BF, WPG>;
-  static bool attr = false;
-  if (!attr) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * WPG, lds);
     if (e != hipSuccess) return e;
-    attr = true;
+    if (per_cu < 1) per_cu = 1;
   }
-  const int per_cu = (160 * 1024) / lds;
-  int grid = cus * (per_cu < 1 ? 1 : per_cu);
+  int grid = cus * per_cu;
   const int need = (n_tiles + WPG - 1) / WPG;
   if (grid > need) grid = need;
   hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, job, n_tiles);
@@ -583,7 +767,7 @@ int fields_max_tangents(int width, bool bf16) {
   return bf16 ? kTcBf16W128 : kTcF32W128;
 }
 
-int fields_group_waves(int tc) { return tc > 0 ? Wpg<1>::value : Wpg<0>::value; }
+int fields_group_points(int tc) { return kTile * (tc > 0 ? Wpg<1, true>::value : Wpg<0, true>::value); }
 
 hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
                                const FieldTile* groups, const int32_t* n_groups, int32_t* claim,
@@ -633,14 +817,15 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
     if (e != hipSuccess) return e;
   }
   const int cus = max_cus > 0 && max_cus < dev_cus ? max_cus : dev_cus;
-  const int tiles = (n_points + kTile - 1) / kTile;
   if (bf16) {
+    const int tiles = (n_points + kTile - 1) / kTile;
     if (width == 64) return launch_dense_res<64, true>(job, tiles, cus, s);
     if (width == 128) return launch_dense_res<128, true>(job, tiles, cus, s);
     return hipErrorInvalidValue;
   }
-  if (width == 64) return launch_dense<64, false>(job, tiles, cus, s);
-  if (width == 128) return launch_dense<128, false>(job, tiles, cus, s);
+  const int tiles = (n_points + kTile16 - 1) / kTile16;
+  if (width == 64) return launch_dense<64>(job, tiles, cus, s);
+  if (width == 128) return launch_dense<128>(job, tiles, cus, s);
   return hipErrorInvalidValue;
 }
 

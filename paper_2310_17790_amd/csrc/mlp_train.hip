@@ -37,6 +37,7 @@ __device__ __forceinline__ float scaled(float w, double f) { return (float)((dou
 // ---- device packing (same orders as pack.cpp, plus transposed hidden layers) --------
 struct Packed {
   float* w1p; float* whp; uint16_t* whb; float* bhp; float* w6p; float* b6; float* whtp;
+  float* w1q; float* bhq; float* w6q;
 };
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -53,8 +54,10 @@ __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int 
   const float* hid = b1 + W;   // W2 b2 W3 b3 W4 b4 W5 b5
   const float* W6 = hid + 4 * ((size_t)W * W + W);
   const float* b6 = W6 + (size_t)d * W;
+  const int MQ = W / 16, K1q = (r + 7) / 4;
   const int64_t n1 = (int64_t)MB * K1s * 64, nh = (int64_t)4 * W * W, nb = 4 * W, n6 = (int64_t)d * W;
-  const int64_t total = n1 + 3 * nh + nb + n6 + d;
+  const int64_t n1q = (int64_t)MQ * K1q * 64;
+  const int64_t total = n1 + 3 * nh + nb + n6 + d + n1q + nb + n6;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t t = e;
     if (t < n1) {
@@ -64,10 +67,10 @@ __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int 
       continue;
     }
     t -= n1;
-    if (t < nh) {   // FP32 forward: [4][MB][W/8][64][4]
-      const int j = t % 4, l = (t / 4) % 64, sg = (t / 256) % (W / 8), mb = (t / (256 * (W / 8))) % MB;
+    if (t < nh) {   // FP32 forward, 16x16x4 layout: [4][W/16][W/16][64][4]
+      const int j = t % 4, l = (t / 4) % 64, sg = (t / 256) % (W / 16), mb = (t / (256 * (W / 16))) % MQ;
       const int kk = t / ((int64_t)W * W);
-      const int s = 4 * sg + j, m = 32 * mb + (l & 31), nn = acc_n(s / 16, s % 16, l >> 5);
+      const int m = 16 * mb + (l & 15), nn = 16 * sg + 4 * (l >> 4) + j;
       P.whp[t] = hid[kk * ((size_t)W * W + W) + (size_t)m * W + nn];
       continue;
     }
@@ -100,7 +103,28 @@ __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int 
       continue;
     }
     t -= n6;
-    P.b6[t] = b6[t];
+    if (t < d) {
+      P.b6[t] = b6[t];
+      continue;
+    }
+    t -= d;
+    if (t < n1q) {   // FP32 forward, 16x16x4 layer 1
+      const int l = t % 64, s4 = (t / 64) % K1q, mb = t / (64 * K1q);
+      const int m = 16 * mb + (l & 15), k = 4 * s4 + (l >> 4);
+      P.w1q[t] = k < in1 ? scaled(W1[(size_t)m * in1 + k], kLog2e) : (k == in1 ? scaled(b1[m], kLog2e) : 0.f);
+      continue;
+    }
+    t -= n1q;
+    if (t < nb) {    // FP32 forward, plain-order biases
+      const int n = t % W, kk = t / W;
+      P.bhq[t] = scaled(hid[kk * ((size_t)W * W + W) + (size_t)W * W + n], kLog2e);
+      continue;
+    }
+    t -= nb;
+    {                // FP32 forward, plain-order output weights
+      const int n = t % W, o = t / W;
+      P.w6q[t] = scaled(W6[(size_t)o * W + n], kLn2);
+    }
   }
 }
 
@@ -384,6 +408,9 @@ TrainWs carve(char* base, int r, int W, int d, int64_t n, bool backward) {
   w.pk.w6p = (float*)take(ps.w6p * 4);
   w.pk.b6 = (float*)take(ps.b6 * 4);
   w.pk.whtp = (float*)take(ps.whp * 4);
+  w.pk.w1q = (float*)take(ps.w1q * 4);
+  w.pk.bhq = (float*)take(ps.bhq * 4);
+  w.pk.w6q = (float*)take(ps.w6q * 4);
   if (backward) {
     w.delta = (float*)take((size_t)5 * n * W * 4);
     const int64_t chunks = (n + kChunk - 1) / kChunk;
@@ -435,6 +462,9 @@ nsf_status nsf_mlp_forward(const nsf_mlp* m, const float* X, const float* z_rows
   j.w.bhp = ws.pk.bhp;
   j.w.w6p = ws.pk.w6p;
   j.w.b6 = ws.pk.b6;
+  j.w.w1q = ws.pk.w1q;
+  j.w.bhq = ws.pk.bhq;
+  j.w.w6q = ws.pk.w6q;
   j.X = X;
   j.ldx = n;
   j.zrows = z_rows;

@@ -28,12 +28,17 @@ __host__ __device__ inline int acc_neuron(int mb, int i, int h) {
 // Packed parameters of one field (one MLP), all in device memory. See pack.cpp for how
 // the host builds each array from the row-major masters.
 struct FieldPack {
-  const float* w1p;      // layer 1 incl. bias column: [MB][K1s][64] MFMA A operands
-  const float* whp;      // hidden layers 2..5, FP32 A operands: [4][MB][W/8][64][4]
-  const bf16x8* whb;     // hidden layers 2..5, BF16 A operands: [4][MB][W/16][64]
+  // BF16 precision (32-point tiles, 32x32 MFMA layouts)
+  const float* w1p;      // layer 1 incl. bias column: [W/32][K1s][64] 32x32x2 A operands
+  const bf16x8* whb;     // hidden layers 2..5, BF16 A operands: [4][W/32][W/16][64]
   const float* bhp;      // hidden biases in accumulator order: [4][2][W/2]
   const float* w6p;      // output weights in accumulator order: [d][2][W/2]
-  const float* b6;       // output bias [d]
+  // FP32 precision (16-point tiles, 16x16x4 MFMA layouts)
+  const float* w1q;      // layer 1 incl. bias column: [W/16][K1q][64] 16x16x4 A operands
+  const float* whp;      // hidden layers 2..5: [4][W/16][W/16][64][4]
+  const float* bhq;      // hidden biases, plain order: [4][W]
+  const float* w6q;      // output weights, plain order: [d][W]
+  const float* b6;       // output bias [d] (both)
 };
 
 // One batch of MLP evaluations: a field at one latent over a list of points.
@@ -134,7 +139,7 @@ hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s);   // n <= 64
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
                                hipStream_t s, int max_cus = 0);
 int fields_max_tangents(int width, bool bf16);
-int fields_group_waves(int tc);   // waves (32-point tiles) per workgroup
+int fields_group_points(int tc);  // points one work group (table entry) spans
 
 // MPM transfers: bin (per integration particle; also zeroes the step's claim counters and,
 // for pipelined decodes, snapshots z_n), then allocate and place (per sim), sort and write

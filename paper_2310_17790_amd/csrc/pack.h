@@ -18,13 +18,19 @@ struct MlpView {
 
 struct PackSizes {
   size_t w1p, whp, whb, bhp, w6p, b6;  // element counts (whb in bf16 elements)
+  size_t w1q, bhq, w6q;
+};
+
+// The packed arrays of one field (host or device buffers of PackSizes elements).
+struct PackOut {
+  float* w1p; float* whp; uint16_t* whb; float* bhp; float* w6p; float* b6;
+  float* w1q; float* bhq; float* w6q;
 };
 
 size_t mlp_param_count(int r, int width, int d);
 MlpView view_master(const float* p, int r, int width, int d);
 PackSizes pack_sizes(int r, int width, int d);
 uint16_t float_to_bf16(float f);
-void pack_field(const float* master, int r, int width, int d, float* w1p, float* whp,
-                uint16_t* whb, float* bhp, float* w6p, float* b6);
+void pack_field(const float* master, int r, int width, int d, const PackOut& out);
 
 }  // namespace nsf
