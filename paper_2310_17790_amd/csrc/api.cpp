@@ -56,7 +56,7 @@ struct Carver {
 // Byte offsets of every buffer of a sim inside its arena.
 struct Layout {
   size_t simdev;
-  size_t w1p[3], whp[3], whb[3], bhp[3], w6p[3], b6[3], w1q[3], bhq[3], w6q[3];
+  size_t whp[3], whb[3], b6[3], w1q[3], bhq[3], w6q[3];
   size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, zdec, step, flags, gn_part;
   size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active,
       nonempty, n_active;
@@ -76,11 +76,8 @@ Layout make_layout(const nsf_sim_desc* d) {
   L.simdev = c.take(sizeof(SimDev));
   for (int f = 0; f < 3; ++f) {
     const PackSizes ps = pack_sizes(r, W, kFieldOut[f]);
-    L.w1p[f] = c.take(ps.w1p * 4);
     L.whp[f] = c.take(ps.whp * 4);
     L.whb[f] = c.take(ps.whb * 2);
-    L.bhp[f] = c.take(ps.bhp * 4);
-    L.w6p[f] = c.take(ps.w6p * 4);
     L.b6[f] = c.take(ps.b6 * 4);
     L.w1q[f] = c.take(ps.w1q * 4);
     L.bhq[f] = c.take(ps.bhq * 4);
@@ -672,35 +669,27 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   for (int f = 0; f < 3; ++f) {
     const int dd = kFieldOut[f];
     const PackSizes ps = pack_sizes(r, W, dd);
-    std::vector<float> w1p(ps.w1p), whp(ps.whp), bhp(ps.bhp), w6p(ps.w6p), b6(ps.b6), w1q(ps.w1q),
-        bhq(ps.bhq), w6q(ps.w6q);
+    std::vector<float> whp(ps.whp), b6(ps.b6), w1q(ps.w1q), bhq(ps.bhq), w6q(ps.w6q);
     std::vector<uint16_t> whb(ps.whb);
     pack_field(d->weights[f], r, W, dd,
-               PackOut{w1p.data(), whp.data(), whb.data(), bhp.data(), w6p.data(), b6.data(), w1q.data(),
-                       bhq.data(), w6q.data()});
+               PackOut{whp.data(), whb.data(), b6.data(), w1q.data(), bhq.data(), w6q.data()});
     auto up = [&](size_t off, const void* src, size_t bytes) {
       return hipMemcpyAsync(A + off, src, bytes, hipMemcpyHostToDevice, s);
     };
-    NSF_HIP(up(L.w1p[f], w1p.data(), w1p.size() * 4));
     NSF_HIP(up(L.whp[f], whp.data(), whp.size() * 4));
     NSF_HIP(up(L.whb[f], whb.data(), whb.size() * 2));
-    NSF_HIP(up(L.bhp[f], bhp.data(), bhp.size() * 4));
-    NSF_HIP(up(L.w6p[f], w6p.data(), w6p.size() * 4));
     NSF_HIP(up(L.b6[f], b6.data(), b6.size() * 4));
     NSF_HIP(up(L.w1q[f], w1q.data(), w1q.size() * 4));
     NSF_HIP(up(L.bhq[f], bhq.data(), bhq.size() * 4));
     NSF_HIP(up(L.w6q[f], w6q.data(), w6q.size() * 4));
     NSF_HIP(hipStreamSynchronize(s));  // host staging vectors die at the end of this scope
     FieldPack& fp = sim->pack[f];
-    fp.w1p = reinterpret_cast<const float*>(A + L.w1p[f]);
     fp.whp = reinterpret_cast<const float*>(A + L.whp[f]);
     fp.whb = reinterpret_cast<const bf16x8*>(A + L.whb[f]);
-    fp.bhp = reinterpret_cast<const float*>(A + L.bhp[f]);
-    fp.w6p = reinterpret_cast<const float*>(A + L.w6p[f]);
+    fp.b6 = reinterpret_cast<const float*>(A + L.b6[f]);
     fp.w1q = reinterpret_cast<const float*>(A + L.w1q[f]);
     fp.bhq = reinterpret_cast<const float*>(A + L.bhq[f]);
     fp.w6q = reinterpret_cast<const float*>(A + L.w6q[f]);
-    fp.b6 = reinterpret_cast<const float*>(A + L.b6[f]);
   }
   const int64_t P = d->n_particles;
   NSF_HIP(hipMemcpyAsync(A + L.X, d->X, (size_t)3 * P * 4, hipMemcpyHostToDevice, s));

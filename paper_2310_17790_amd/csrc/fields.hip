@@ -7,34 +7,43 @@
 // phi'(a1) * W1[:, 3 + j], each hidden layer maps T -> phi'(a_k) * (W_k T), and the output
 // is W6 T.
 //
-// Mapping to the hardware. One wave owns 32 points (the MFMA N dimension) and carries
-// them through all six layers in registers. A layer is Y = W H with W the A operand
-// (M = output neurons, 32 per block) and H the B operand. The 32x32 accumulator layout
-// gives each lane one point (column) and 16 neurons per M-block; instead of re-laying
-// the activations out between layers, the host permutes the columns of every weight
-// matrix so that K-step s of the next layer consumes exactly the registers each lane
-// already holds (see acc_neuron and pack.cpp). Tangent columns of the same 32 points
-// ride in extra N-tiles of the same wave, so phi'(a) of the primal is available
-// in-lane. A wave processes the primal plus up to TC tangents; a Jacobian with more
-// tangents is split over several waves, each recomputing the primal.
+// Mapping to the hardware. One wave owns a tile of 16 points (the MFMA N dimension) and
+// carries it through all six layers in registers. A layer is Y = W H with W the A operand
+// (M = output neurons, 16 per block) and H the B operand. In the 16x16 accumulator lane l
+// holds point l % 16 and, of M-block mb, the four neurons 16 mb + 4 g + v (v = 0..3) of its
+// lane group g = l / 16. Instead of re-laying the activations out between layers, the host
+// permutes the columns of every weight matrix so that the next layer's K-steps consume
+// exactly the registers each lane already holds (pack.cpp):
+//  - FP32 (v_mfma_f32_16x16x4_f32): K-step 4 mb + v takes register v of M-block mb, i.e.
+//    lane group g supplies input 16 mb + 4 g + v;
+//  - BF16 (v_mfma_f32_16x16x32_bf16): K-step s takes M-blocks 2s and 2s + 1, eight BF16
+//    values per lane: lane group g supplies inputs 16 (2s + e / 4) + 4 g + e % 4, e = 0..7.
+// Biases and output weights are then read in plain neuron order. Tangent columns of the
+// same points ride in extra N-tiles of the same wave, so phi'(a) of the primal is
+// available in-lane. A wave processes the primal plus up to TC tangents; a Jacobian with
+// more tangents is split over several waves, each recomputing the primal. A 16-point tile
+// needs a quarter of the registers of a 32-point one, so two waves fit per SIMD with two
+// tangents and three or four for the primal: the activations of one wave then overlap
+// the matrix products of another.
 //
-// Pre-activations are carried scaled by log2(e) (see elu_pair and pack.cpp).
-// Layer 1 also runs on FP32 MFMA, with the bias folded in as an input row equal to 1
-// and the tangent seeds as one-hot input columns. FP32 precision: hidden layers on
-// v_mfma_f32_32x32x2_f32. BF16 precision: hidden layers on v_mfma_f32_32x32x16_bf16
-// with FP32 accumulation; layer 1 and the output layer stay FP32. The output layer
-// (d <= 9 rows) is a per-lane dot product plus one cross-half lane exchange.
+// Pre-activations are carried scaled by log2(e) (see elu_pair and pack.cpp). Layer 1 runs
+// on FP32 MFMA in both precisions, with the bias folded in as an input row equal to 1 and
+// the tangent seeds as one-hot input columns; so does the output layer's dot product. BF16
+// precision rounds the hidden layers' weights and input activations to BF16 and
+// accumulates in FP32.
 #include "nsf_dev.h"
 
 namespace nsf {
 namespace {
 
-__device__ __forceinline__ f32x16 mfma_f32(float a, float b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+constexpr int kTile16 = 16;   // points per wave tile
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x4 mfma16_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // ELU (alpha = 1) on scaled pre-activations. The kernels carry a' = log2(e) a and
@@ -61,148 +70,7 @@ __device__ __forceinline__ void elu_pair(float a, float& y, float& dy) {
   }
 }
 
-template <int W, int T>
-__device__ __forceinline__ void activate_f32(const f32x16 (&acc)[T][W / 32], float (&H)[T][W / 2],
-                                             int nt) {
-#pragma unroll
-  for (int mb = 0; mb < W / 32; ++mb)
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      float y, dy;
-      elu_pair<false>(acc[0][mb][i], y, dy);
-      H[0][16 * mb + i] = y;
-#pragma unroll
-      for (int t = 1; t < T; ++t)
-        if (t <= nt) H[t][16 * mb + i] = dy * acc[t][mb][i];
-    }
-}
-
-// K-step s = 2 mb + q of a BF16 layer reads registers 8q .. 8q + 7 of M-block mb.
-template <int W, int T>
-__device__ __forceinline__ void activate_bf16(const f32x16 (&acc)[T][W / 32],
-                                              bf16x8 (&Hb)[T][W / 16], int nt) {
-#pragma unroll
-  for (int mb = 0; mb < W / 32; ++mb)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      bf16x8 p0;
-      float dys[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        float y;
-        elu_pair<true>(acc[0][mb][8 * q + j], y, dys[j]);
-        p0[j] = (__bf16)y;
-      }
-      Hb[0][2 * mb + q] = p0;
-#pragma unroll
-      for (int t = 1; t < T; ++t)
-        if (t <= nt) {
-          bf16x8 pt;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) pt[j] = (__bf16)(dys[j] * acc[t][mb][8 * q + j]);
-          Hb[t][2 * mb + q] = pt;
-        }
-    }
-}
-
-// Accumulators of a hidden layer start from the bias (primal) or zero (tangents).
-template <int W, int T>
-__device__ __forceinline__ void init_hidden(f32x16 (&acc)[T][W / 32], const float* bhp_layer,
-                                            int h) {
-  const f32x4* bias = reinterpret_cast<const f32x4*>(bhp_layer + h * (W / 2));
-#pragma unroll
-  for (int mb = 0; mb < W / 32; ++mb) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const f32x4 b4 = bias[mb * 4 + q];
-      acc[0][mb][4 * q + 0] = b4[0];
-      acc[0][mb][4 * q + 1] = b4[1];
-      acc[0][mb][4 * q + 2] = b4[2];
-      acc[0][mb][4 * q + 3] = b4[3];
-    }
-#pragma unroll
-    for (int t = 1; t < T; ++t) acc[t][mb] = f32x16{};
-  }
-}
-
-template <int W, int T, class APtr>
-__device__ __forceinline__ void hidden_bf16(f32x16 (&acc)[T][W / 32],
-                                            const bf16x8 (&Hb)[T][W / 16],
-                                            APtr whb_layer, int lane, int nt) {
-  constexpr int MB = W / 32, S = W / 16;
-  // A fragments come from LDS two K-steps ahead of their use (a ring of three steps), so
-  // each matrix product does not wait on its own LDS read; scheduling barriers keep the
-  // compiler from sinking the reads back next to their uses.
-  constexpr int D = 2;
-  bf16x8 a[D + 1][MB];
-#pragma unroll
-  for (int s = 0; s < D; ++s)
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) a[s][mb] = whb_layer[(mb * S + s) * 64 + lane];
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    if (s + D < S) {
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) a[(s + D) % (D + 1)][mb] = whb_layer[(mb * S + s + D) * 64 + lane];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      acc[0][mb] = mfma_bf16(a[s % (D + 1)][mb], Hb[0][s], acc[0][mb]);
-#pragma unroll
-      for (int t = 1; t < T; ++t)
-        if (t <= nt) acc[t][mb] = mfma_bf16(a[s % (D + 1)][mb], Hb[t][s], acc[t][mb]);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
-// out_o = sum_n W6[o][n] H[n] over this lane's half of the neurons, then both halves.
-template <int W>
-__device__ __forceinline__ float output_dot(const float* w6p, int o, int h, const float (&Hrow)[W / 2]) {
-  const f32x4* w6 = reinterpret_cast<const f32x4*>(w6p + (o * 2 + h) * (W / 2));
-  float s = 0.f;
-#pragma unroll
-  for (int sg = 0; sg < W / 8; ++sg) {
-    const f32x4 w = w6[sg];
-    s += w[0] * Hrow[4 * sg + 0];
-    s += w[1] * Hrow[4 * sg + 1];
-    s += w[2] * Hrow[4 * sg + 2];
-    s += w[3] * Hrow[4 * sg + 3];
-  }
-  return s + __shfl_xor(s, 32);
-}
-
-// Training: store the (scaled) pre-activations of one layer, point-major saved[layer][p][W]. The
-// 16 registers of M-block mb hold neurons 32 mb + 8 q + 4 h + (0..3), q = 0..3.
-template <int W, int T>
-__device__ __forceinline__ void save_preact(const FieldJob& jb, const f32x16 (&acc)[T][W / 32],
-                                            int layer, int p, bool valid, int h) {
-  if (jb.saved == nullptr || !valid) return;
-  float* row = jb.saved + ((int64_t)layer * jb.n + p) * W;
-#pragma unroll
-  for (int mb = 0; mb < W / 32; ++mb)
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      *reinterpret_cast<f32x4*>(row + 32 * mb + 8 * q + 4 * h) =
-          f32x4{acc[0][mb][4 * q], acc[0][mb][4 * q + 1], acc[0][mb][4 * q + 2], acc[0][mb][4 * q + 3]};
-}
-
-// ---- FP32 precision: 16-point tiles on v_mfma_f32_16x16x4_f32 ------------------------
-// Lane l holds point l % 16 of the tile and lane group g = l / 16. The 16x16 accumulator
-// gives lane (point, g) neurons 16 mb + 4 g + v (v = 0..3) of M-block mb, and K-step
-// s = 4 mb + v of the next layer consumes exactly those registers: the host stores, for
-// output row m and K-group sg, the inputs 16 sg + 4 g + 0..3 of row m as lane (m % 16 + 16 g)'s
-// four floats. Biases and output weights are then read in plain neuron order. A tile
-// holds a quarter of the registers of a 32-point tile, so twice as many waves fit on a
-// SIMD (two with two tangents, four for the primal), which is what hides the activations
-// of one wave behind the matrix products of another.
-constexpr int kTile16 = 16;
-
-__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
+// FP32 activations: H[t][4 mb + v] from register v of M-block mb.
 template <int W, int T>
 __device__ __forceinline__ void activate16(const f32x4 (&acc)[T][W / 16], float (&H)[T][W / 4], int nt) {
 #pragma unroll
@@ -218,6 +86,32 @@ __device__ __forceinline__ void activate16(const f32x4 (&acc)[T][W / 16], float 
     }
 }
 
+// BF16 activations: K-step s of the next layer packs M-blocks 2s and 2s + 1.
+template <int W, int T>
+__device__ __forceinline__ void activate16_bf16(const f32x4 (&acc)[T][W / 16], bf16x8 (&Hb)[T][W / 32],
+                                                int nt) {
+#pragma unroll
+  for (int s = 0; s < W / 32; ++s) {
+    bf16x8 p0;
+    float dys[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float y;
+      elu_pair<true>(acc[0][2 * s + (e >> 2)][e & 3], y, dys[e]);
+      p0[e] = (__bf16)y;
+    }
+    Hb[0][s] = p0;
+#pragma unroll
+    for (int t = 1; t < T; ++t)
+      if (t <= nt) {
+        bf16x8 pt;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) pt[e] = (__bf16)(dys[e] * acc[t][2 * s + (e >> 2)][e & 3]);
+        Hb[t][s] = pt;
+      }
+  }
+}
+
 // Accumulators start from the layer's bias (plain order) or zero (tangents).
 template <int W, int T>
 __device__ __forceinline__ void init16(f32x4 (&acc)[T][W / 16], const float* bias, int g) {
@@ -229,33 +123,62 @@ __device__ __forceinline__ void init16(f32x4 (&acc)[T][W / 16], const float* bia
   }
 }
 
-// One hidden layer from LDS: A is [W/16 output blocks][W/16 K-groups][64 lanes] f32x4,
-// read in halves (two K-steps) one half ahead of its use.
+// The A fragments of a hidden layer are consumed in a fixed sequence of steps (K-step
+// outer, output block inner) and read from LDS kPrefetch steps ahead of their use into a
+// small ring; scheduling barriers keep the compiler from sinking the reads back next to
+// their uses or hoisting more of them (which only costs registers).
+constexpr int kPrefetch = 4;
+
+// One FP32 hidden layer from LDS: A is [W/16 output blocks][W/16 K-groups][64 lanes]
+// f32x4 (K-steps 4 sg .. 4 sg + 3), consumed in halves (two K-steps per step).
 template <int W, int T>
 __device__ __forceinline__ void hidden16(f32x4 (&acc)[T][W / 16], const float (&H)[T][W / 4],
                                          const f32x4* A, int lane, int nt) {
-  constexpr int MB = W / 16, SG = W / 16, HS = 2 * SG;
+  constexpr int MB = W / 16, SG = W / 16, N = 2 * SG * MB, RING = kPrefetch + 1;
   const f32x2* A2 = reinterpret_cast<const f32x2*>(A);
-  auto at = [&](int mb, int hs) { return A2[2 * ((mb * SG + (hs >> 1)) * 64 + lane) + (hs & 1)]; };
-  f32x2 a2[2][MB];
+  // step i: half-group hs = i / MB of output block mb = i % MB
+  auto at = [&](int i) {
+    const int hs = i / MB, mb = i % MB;
+    return A2[2 * ((mb * SG + (hs >> 1)) * 64 + lane) + (hs & 1)];
+  };
+  f32x2 ring[RING];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) a2[0][mb] = at(mb, 0);
+  for (int i = 0; i < kPrefetch; ++i) ring[i] = at(i);
 #pragma unroll
-  for (int hs = 0; hs < HS; ++hs) {
-    if (hs + 1 < HS) {
+  for (int i = 0; i < N; ++i) {
+    if (i + kPrefetch < N) ring[(i + kPrefetch) % RING] = at(i + kPrefetch);
+    __builtin_amdgcn_sched_barrier(0);
+    const int hs = i / MB, mb = i % MB;
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) a2[(hs + 1) & 1][mb] = at(mb, hs + 1);
+    for (int j = 0; j < 2; ++j) {
+      acc[0][mb] = mfma16(ring[i % RING][j], H[0][2 * hs + j], acc[0][mb]);
+#pragma unroll
+      for (int t = 1; t < T; ++t)
+        if (t <= nt) acc[t][mb] = mfma16(ring[i % RING][j], H[t][2 * hs + j], acc[t][mb]);
     }
     __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// One BF16 hidden layer from LDS: A is [W/16 output blocks][W/32 K-steps][64 lanes] bf16x8.
+template <int W, int T>
+__device__ __forceinline__ void hidden16_bf16(f32x4 (&acc)[T][W / 16], const bf16x8 (&Hb)[T][W / 32],
+                                              const bf16x8* A, int lane, int nt) {
+  constexpr int MB = W / 16, S = W / 32, N = S * MB, RING = kPrefetch + 1;
+  // step i: K-step s = i / MB of output block mb = i % MB
+  auto at = [&](int i) { return A[((i % MB) * S + i / MB) * 64 + lane]; };
+  bf16x8 ring[RING];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+  for (int i = 0; i < kPrefetch; ++i) ring[i] = at(i);
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        acc[0][mb] = mfma16(a2[hs & 1][mb][j], H[0][2 * hs + j], acc[0][mb]);
+  for (int i = 0; i < N; ++i) {
+    if (i + kPrefetch < N) ring[(i + kPrefetch) % RING] = at(i + kPrefetch);
+    __builtin_amdgcn_sched_barrier(0);
+    const int s = i / MB, mb = i % MB;
+    acc[0][mb] = mfma16_bf16(ring[i % RING], Hb[0][s], acc[0][mb]);
 #pragma unroll
-        for (int t = 1; t < T; ++t)
-          if (t <= nt) acc[t][mb] = mfma16(a2[hs & 1][mb][j], H[t][2 * hs + j], acc[t][mb]);
-      }
+    for (int t = 1; t < T; ++t)
+      if (t <= nt) acc[t][mb] = mfma16_bf16(ring[i % RING], Hb[t][s], acc[t][mb]);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -278,6 +201,7 @@ __device__ __forceinline__ float output_dot16(const float* w6q, int o, int g, co
   return s + __shfl_xor(s, 32);
 }
 
+// Training: store the (scaled) pre-activations of one layer, point-major saved[layer][p][W].
 template <int W, int T>
 __device__ __forceinline__ void save_preact16(const FieldJob& jb, const f32x4 (&acc)[T][W / 16],
                                               int layer, int p, bool valid, int g) {
@@ -296,24 +220,27 @@ struct HiddenLayer {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+template <bool BF>
+__device__ __forceinline__ const char* hidden_src(const FieldPack& w) {
+  return BF ? reinterpret_cast<const char*>(w.whb) : reinterpret_cast<const char*>(w.whp);
+}
+
 // Copy hidden layer k of `w` into LDS buffer dst with direct global->LDS loads; the 1 KB
 // chunks are dealt to the waves of the workgroup round-robin.
 template <int W, bool BF, int WPG>
 __device__ __forceinline__ void dma_layer(const FieldPack& w, int k, char* dst, int wave, int lane) {
-  const char* src = (BF ? reinterpret_cast<const char*>(w.whb) : reinterpret_cast<const char*>(w.whp)) +
-                    (size_t)k * HiddenLayer<W, BF>::kBytes;
+  const char* src = hidden_src<BF>(w) + (size_t)k * HiddenLayer<W, BF>::kBytes;
 #pragma unroll
   for (int chunk = wave; chunk < HiddenLayer<W, BF>::kChunks; chunk += WPG)
     __builtin_amdgcn_global_load_lds(src + chunk * 1024 + lane * 16,
                                       (lds_void*)(dst + chunk * 1024), 16, 0, 0);
 }
 
-// Copy all four hidden layers of `w` (contiguous in the pack) into LDS; chunks are dealt
-// to the waves round-robin.
+// Copy all four hidden layers of `w` (contiguous in the pack) into LDS, round-robin.
 template <int W, bool BF, int WPG>
 __device__ __forceinline__ void dma_all_layers(const FieldPack& w, char* dst, int wave, int lane) {
   constexpr int kTotal = 4 * HiddenLayer<W, BF>::kChunks;
-  const char* src = BF ? reinterpret_cast<const char*>(w.whb) : reinterpret_cast<const char*>(w.whp);
+  const char* src = hidden_src<BF>(w);
   for (int chunk = wave; chunk < kTotal; chunk += WPG)
     __builtin_amdgcn_global_load_lds(src + chunk * 1024 + lane * 16, (lds_void*)(dst + chunk * 1024), 16, 0, 0);
 }
@@ -323,152 +250,21 @@ __device__ __forceinline__ void wait_dma_and_sync() {
   __syncthreads();
 }
 
-// One wave evaluates a tile of 32 points of a job, starting at point p0: the primal plus
+// One wave evaluates a 16-point tile of a job, starting at point p0: the primal plus
 // tangents [t0, t0 + nt). Two ways to hold the hidden-layer weights:
 //  - streamed (RES = false): the WPG waves of a workgroup run tiles of the same job in
 //    step; layers stream through two LDS buffers, layer k + 1 (or the next group's first
 //    hidden layer) fetched while layer k computes, with a workgroup barrier per layer;
-//  - resident (RES = true): all four hidden layers sit in LDS for the whole kernel, and
-//    waves run their tiles independently, without barriers, so one wave's activations
-//    overlap another's matrix products on the same SIMD.
+//  - resident (RES = true, BF16 decode): all four hidden layers sit in LDS for the whole
+//    kernel, and waves run their tiles independently, without barriers.
 // Returns after the output layer.
 template <int W, int NT, bool BF, int WPG, bool RES = false, class NextFn>
-__device__ __forceinline__ void run_group(const FieldJob& jb, int p0, int t0, NextFn&& next,
-                                          char* lds, int wave, int lane) {
-  static_assert(BF, "FP32 tiles run in run_group16");
-  constexpr int MB = W / 32;
-  constexpr int T = 1 + NT;
-  constexpr int nt = NT;  // compile-time: no per-MFMA guards
-  constexpr int KH = W / 2;
-  constexpr int LB = HiddenLayer<W, BF>::kBytes;
-  const int h = lane >> 5;
-  const int p = p0 + (lane & 31);
-  const bool valid = p < jb.n;
-  int gi = jb.p_off + (valid ? p : jb.n - 1);
-  if (jb.idx != nullptr) {
-    const int32_t* row = jb.idx;
-    if (jb.step != nullptr) row += (*jb.step % jb.plan_steps) * (int64_t)jb.plan_ld;
-    gi = row[gi];
-  }
-  const float X0 = jb.X[gi];
-  const float X1 = jb.X[jb.ldx + gi];
-  const float X2 = jb.X[2 * jb.ldx + gi];
-  const int r = jb.r;
-
-  f32x16 acc[T][MB];
-#pragma unroll
-  for (int t = 0; t < T; ++t)
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f32x16{};
-
-  // Layer 1: input rows 0..2 = X, 3..2+r = z, 3+r = 1 (bias column of the packed W1).
-  // Tangent columns are one-hot in z (Jacobian) or the direction z - z2 (JVP job).
-  const int K1s = (r + 5) >> 1;
-  const bool jvp = jb.jvp != 0;
-  for (int s2 = 0; s2 < K1s; ++s2) {
-    const int k = 2 * s2 + h;
-    float b0 = 0.f, bt = 0.f;
-    if (k == 0) b0 = X0;
-    else if (k == 1) b0 = X1;
-    else if (k == 2) b0 = X2;
-    else if (k < 3 + r && jb.zrows != nullptr) {
-      b0 = jb.zrows[(int64_t)(valid ? p : jb.n - 1) * r + (k - 3)];
-    } else if (k < 3 + r) {
-      const double zk = jb.z[k - 3];
-      if (jvp) {
-        const double z2k = jb.z2[k - 3];
-        b0 = (float)(0.5 * (zk + z2k));
-        bt = (float)(zk - z2k);
-      } else {
-        b0 = (float)zk;
-      }
-    } else if (k == 3 + r) b0 = 1.f;
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const float a = jb.w.w1p[(mb * K1s + s2) * 64 + lane];
-      acc[0][mb] = mfma_f32(a, b0, acc[0][mb]);
-#pragma unroll
-      for (int t = 1; t < T; ++t)
-        if (t <= nt) acc[t][mb] = mfma_f32(a, jvp ? bt : ((k == 3 + t0 + t - 1) ? 1.f : 0.f), acc[t][mb]);
-    }
-  }
-
-  if constexpr (NT == 0) save_preact<W, T>(jb, acc, 0, p, valid, h);
-  float H[T][KH];
-  bf16x8 Hb[T][W / 16];
-  activate_bf16<W, T>(acc, Hb, nt);
-  // Hidden layers 2..5 (k = 0..3): wait for layer k in LDS, start fetching layer k + 1
-  // (after the last layer: the next group's first layer), multiply, activate.
-#pragma unroll 1
-  for (int k = 0; k < 3; ++k) {
-    char* cur = lds + (RES ? k : (k & 1)) * LB;
-    if constexpr (!RES) {
-      wait_dma_and_sync();
-      dma_layer<W, BF, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
-    }
-    init_hidden<W, T>(acc, jb.w.bhp + k * W, h);
-    hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(cur), lane, nt);
-    if constexpr (NT == 0) save_preact<W, T>(jb, acc, k + 1, p, valid, h);
-    activate_bf16<W, T>(acc, Hb, nt);
-  }
-  if constexpr (!RES) {
-    wait_dma_and_sync();
-    // decide the workgroup's next group now and start fetching its first hidden layer
-    if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
-  }
-  char* last = lds + (RES ? 3 : 1) * LB;
-  init_hidden<W, T>(acc, jb.w.bhp + 3 * W, h);
-  hidden_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(last), lane, nt);
-  if constexpr (NT == 0) save_preact<W, T>(jb, acc, 4, p, valid, h);
-  activate_f32<W, T>(acc, H, nt);
-
-  const int d = jb.d;
-  if constexpr (NT >= 1) {
-    if (jvp) {  // directional derivative only: out = scale * (W6 T) * jvp_scale
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float y = output_dot<W>(jb.w.w6p, c, h, H[1]);
-        if (valid && h == (c & 1)) jb.out[c * jb.ldo + p] = jb.scale[c] * y * jb.jvp_scale;
-      }
-      return;
-    }
-  }
-  // Output layer, primal.
-  if (t0 == 0) {
-    // one output at a time: unrolled, the weight loads of all nine would be hoisted
-#pragma unroll 1
-    for (int o = 0; o < d; ++o) {
-      {
-        const float y = output_dot<W>(jb.w.w6p, o, h, H[0]) + jb.w.b6[o];
-        float v = jb.scale[o] * y + jb.shift[o];
-        if (jb.mode == 1) v += (o == 0) ? X0 : (o == 1) ? X1 : X2;
-        if (valid && h == (o & 1)) jb.out[o * jb.ldo + p] = v;
-      }
-    }
-  }
-  // Output layer, tangents (deformation field only: d = 3).
-#pragma unroll
-  for (int t = 1; t < T; ++t) {
-    if (t <= nt) {
-      const int j = t0 + t - 1;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float y = output_dot<W>(jb.w.w6p, c, h, H[t]);
-        if (valid && h == (c & 1)) jb.jac[(c * r + j) * jb.ldj + p] = jb.scale[c] * y;
-      }
-    }
-  }
-}
-
-// FP32 precision: one wave evaluates a 16-point tile (see kTile16) with streamed weights,
-// in the same barrier sequence as run_group.
-template <int W, int NT, int WPG, class NextFn>
 __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, NextFn&& next,
                                             char* lds, int wave, int lane) {
   constexpr int MB = W / 16;
   constexpr int T = 1 + NT;
-  constexpr int nt = NT;
-  constexpr int LB = HiddenLayer<W, false>::kBytes;
+  constexpr int nt = NT;  // compile-time: no per-MFMA guards
+  constexpr int LB = HiddenLayer<W, BF>::kBytes;
   const int g = lane >> 4;
   const int p = p0 + (lane & 15);
   const bool valid = p < jb.n;
@@ -490,6 +286,7 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
     for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   // Layer 1: input rows 0..2 = X, 3..2+r = z, 3+r = 1 (bias column), four per K-step.
+  // Tangent columns are one-hot in z (Jacobian) or the direction z - z2 (JVP job).
   const int K1q = (r + 7) >> 2;
   const bool jvp = jb.jvp != 0;
   for (int s4 = 0; s4 < K1q; ++s4) {
@@ -520,25 +317,51 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
     }
   }
   if constexpr (NT == 0) save_preact16<W, T>(jb, acc, 0, p, valid, g);
-  float H[T][W / 4];
-  activate16<W, T>(acc, H, nt);
-  // Hidden layers 2..5 (k = 0..3), as in run_group.
-#pragma unroll 1
-  for (int k = 0; k < 4; ++k) {
-    char* cur = lds + (k & 1) * LB;
-    wait_dma_and_sync();
-    if (k < 3) dma_layer<W, false, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
-    else if (const FieldPack* next_w = next()) dma_layer<W, false, WPG>(*next_w, 0, lds, wave, lane);
+
+  // Hidden layers 2..5 (k = 0..3). Streamed: wait for layer k in LDS, then start fetching
+  // layer k + 1 (after the last layer: the next group's first layer) while k computes.
+  // The last layer's activations stay FP32 for the FP32 output layer.
+  // Layer k's products (after its weights are in LDS) into acc.
+  auto layer = [&](int k, auto&& hidden) {
+    char* cur = lds + (RES ? k : (k & 1)) * LB;
+    if constexpr (!RES) {
+      wait_dma_and_sync();
+      if (k < 3) dma_layer<W, BF, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
+      else if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
+    }
     init16<W, T>(acc, jb.w.bhq + k * W, g);
-    hidden16<W, T>(acc, H, reinterpret_cast<const f32x4*>(cur), lane, nt);
+    hidden(cur);
     if constexpr (NT == 0) save_preact16<W, T>(jb, acc, k + 1, p, valid, g);
+  };
+  float H[T][W / 4];
+  if constexpr (BF) {
+    // BF16 activations between layers; the last layer's are FP32, for the output layer
+    // (peeled off the loop, so H and Hb are never live together)
+    bf16x8 Hb[T][W / 32];
+    activate16_bf16<W, T>(acc, Hb, nt);
+    auto hb = [&](char* cur) { hidden16_bf16<W, T>(acc, Hb, reinterpret_cast<const bf16x8*>(cur), lane, nt); };
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k) {
+      layer(k, hb);
+      activate16_bf16<W, T>(acc, Hb, nt);
+    }
+    layer(3, hb);
+  } else {
     activate16<W, T>(acc, H, nt);
+    auto hf = [&](char* cur) { hidden16<W, T>(acc, H, reinterpret_cast<const f32x4*>(cur), lane, nt); };
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k) {
+      layer(k, hf);
+      activate16<W, T>(acc, H, nt);
+    }
+    layer(3, hf);
   }
+  activate16<W, T>(acc, H, nt);
 
   const int d = jb.d;
   if constexpr (NT >= 1) {
     if (jvp) {  // directional derivative only: out = scale * (W6 T) * jvp_scale
-#pragma unroll
+#pragma unroll 1
       for (int c = 0; c < 3; ++c) {
         const float y = output_dot16<W>(jb.w.w6q, c, g, H[1]);
         if (valid && g == c) jb.out[c * jb.ldo + p] = jb.scale[c] * y * jb.jvp_scale;
@@ -546,26 +369,26 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
       return;
     }
   }
+  // Output layer, primal (one output at a time: unrolled, the weight loads of all nine
+  // would be hoisted).
   if (t0 == 0) {
-    // one output at a time: unrolled, the weight loads of all nine would be hoisted
 #pragma unroll 1
     for (int o = 0; o < d; ++o) {
-      {
-        const float y = output_dot16<W>(jb.w.w6q, o, g, H[0]) + jb.w.b6[o];
-        float v = jb.scale[o] * y + jb.shift[o];
-        if (jb.mode == 1) v += (o == 0) ? X0 : (o == 1) ? X1 : X2;
-        if (valid && g == (o & 3)) jb.out[o * jb.ldo + p] = v;
-      }
+      const float y = output_dot16<W>(jb.w.w6q, o, g, H[0]) + jb.w.b6[o];
+      float v = jb.scale[o] * y + jb.shift[o];
+      if (jb.mode == 1) v += (o == 0) ? X0 : (o == 1) ? X1 : X2;
+      if (valid && g == (o & 3)) jb.out[o * jb.ldo + p] = v;
     }
   }
+  // Output layer, tangents (deformation field only: d = 3), one output row at a time:
+  // unrolled, the weight loads of all three rows would be hoisted.
+  if constexpr (NT >= 1) {
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
 #pragma unroll
-  for (int t = 1; t < T; ++t) {
-    if (t <= nt) {
-      const int j = t0 + t - 1;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int t = 1; t < T; ++t) {
         const float y = output_dot16<W>(jb.w.w6q, c, g, H[t]);
-        if (valid && g == c) jb.jac[(c * r + j) * jb.ldj + p] = jb.scale[c] * y;
+        if (valid && g == c) jb.jac[(c * r + t0 + t - 1) * jb.ldj + p] = jb.scale[c] * y;
       }
     }
   }
@@ -577,14 +400,12 @@ __device__ __forceinline__ void dispatch_nt(const FieldJob& jb, int p0, int t0, 
                                             NextFn&& next, char* lds, int wave, int lane) {
   if constexpr (TC > 0) {
     if (nt == TC) {
-      if constexpr (BF) run_group<W, TC, true, WPG>(jb, p0 + kTile * wave, t0, next, lds, wave, lane);
-      else run_group16<W, TC, WPG>(jb, p0 + kTile16 * wave, t0, next, lds, wave, lane);
+      run_group16<W, TC, BF, WPG>(jb, p0 + kTile16 * wave, t0, next, lds, wave, lane);
       return;
     }
     dispatch_nt<W, TC - 1, BF, WPG>(jb, p0, t0, nt, next, lds, wave, lane);
   } else {
-    if constexpr (BF) run_group<W, 0, true, WPG>(jb, p0 + kTile * wave, t0, next, lds, wave, lane);
-    else run_group16<W, 0, WPG>(jb, p0 + kTile16 * wave, t0, next, lds, wave, lane);
+    run_group16<W, 0, BF, WPG>(jb, p0 + kTile16 * wave, t0, next, lds, wave, lane);
   }
 }
 
@@ -608,7 +429,7 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
   if (g >= total) return;
   dma_layer<W, BF, WPG>(jobs[groups[g].job].w, 0, lds, wave, lane);
   int gn = total;
-  // called by every thread at the same point of run_group (after a barrier)
+  // called by every thread at the same point of run_group16 (after a barrier)
   auto next = [&]() -> const FieldPack* {
     if (threadIdx.x == 0) s_claim = atomicAdd(claim, 1);
     __syncthreads();
@@ -623,8 +444,8 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
   }
 }
 
-// The barrier and DMA sequence of run_group (streamed weights) for a wave with no tile in
-// this round: it keeps the workgroup's per-layer barriers and weight copies in step.
+// The barrier and DMA sequence of run_group16 (streamed weights) for a wave with no tile
+// in this round: it keeps the workgroup's per-layer barriers and weight copies in step.
 template <int W, bool BF, int WPG, class NextFn>
 __device__ __forceinline__ void idle_group(const FieldJob& jb, NextFn&& next, char* lds, int wave,
                                            int lane) {
@@ -638,68 +459,72 @@ __device__ __forceinline__ void idle_group(const FieldJob& jb, NextFn&& next, ch
   if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
 }
 
-// One job over n points (FP32 decode), weights streamed, persistent workgroups, 16-point
-// tiles. Tiles are dealt
-// so that every round but the last fills all waves of all workgroups, and the last round's
-// tiles go to wave 0 of distinct workgroups, which then run alone on their SIMDs:
-// tile t = round * gridDim.x * WPG + wave * gridDim.x + blockIdx.x.
+// Decode tile t of a persistent workgroup's waves: every round but the last fills all
+// waves of all workgroups, and the last round's tiles go to waves 0 and 1 of distinct
+// workgroups, which then run alone on their SIMDs. Waves 2q and 2q + 1 take adjacent
+// tiles, so each 128-byte line of the point arrays is read by one workgroup:
+// t = round * gridDim.x * WPG + q * 2 gridDim.x + 2 blockIdx.x + (wave & 1), q = wave / 2.
+__device__ __forceinline__ int dense_tile(int base, int wave, int G, int b) {
+  return base + (wave >> 1) * 2 * G + 2 * b + (wave & 1);
+}
+
+// One job over n points (FP32 decode), weights streamed, persistent workgroups.
 template <int W, int WPG>
 __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, int n_tiles) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  static_assert(WPG % 2 == 0, "waves take tiles in pairs");
   const int G = gridDim.x, b = blockIdx.x, per_round = G * WPG;
-  if (b >= n_tiles) return;
+  if (2 * b >= n_tiles) return;
   dma_layer<W, false, WPG>(job.w, 0, lds, wave, lane);
 #pragma unroll 1
-  for (int base = 0; base + b < n_tiles; base += per_round) {
-    const bool more = base + per_round + b < n_tiles;
+  for (int base = 0; base + 2 * b < n_tiles; base += per_round) {
+    const bool more = base + per_round + 2 * b < n_tiles;
     auto next = [&]() -> const FieldPack* { return more ? &job.w : nullptr; };
-    const int t = base + wave * G + b;
-    if (t < n_tiles) run_group16<W, 0, WPG>(job, t * kTile16, 0, next, lds, wave, lane);
+    const int t = dense_tile(base, wave, G, b);
+    if (t < n_tiles) run_group16<W, 0, false, WPG>(job, t * kTile16, 0, next, lds, wave, lane);
     else idle_group<W, false, WPG>(job, next, lds, wave, lane);
   }
 }
 
 // One job over n points (BF16 decode), weights resident: every workgroup loads the four
 // hidden layers once, then each wave runs its tiles independently.
-template <int W, bool BF, int WPG>
+template <int W, int WPG>
 __global__ __launch_bounds__(64 * WPG) void fields_dense_res_kernel(FieldJob job, int n_tiles) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  dma_all_layers<W, BF, WPG>(job.w, lds, wave, lane);
+  static_assert(WPG % 2 == 0, "waves take tiles in pairs");
+  const int G = gridDim.x, b = blockIdx.x;
+  if (2 * b >= n_tiles) return;
+  dma_all_layers<W, true, WPG>(job.w, lds, wave, lane);
   wait_dma_and_sync();
   auto none = []() -> const FieldPack* { return nullptr; };
-  // tile t = round * gridDim.x * WPG + wave * gridDim.x + blockIdx.x: the last, partial
-  // round's tiles go to distinct workgroups
 #pragma unroll 1
-  for (int t = wave * (int)gridDim.x + blockIdx.x; t < n_tiles; t += gridDim.x * WPG) {
+  for (int base = 0; base + 2 * b < n_tiles; base += G * WPG) {
+    const int t = dense_tile(base, wave, G, b);
+    if (t >= n_tiles) break;
     // keep the weight reads inside the tile: the LDS contents never change, and hoisting
     // them out of the loop would only exhaust registers
     __asm__ volatile("" ::: "memory");
-    run_group<W, 0, BF, WPG, true>(job, t * kTile, 0, none, lds, wave, lane);
+    run_group16<W, 0, true, WPG, true>(job, t * kTile16, 0, none, lds, wave, lane);
   }
 }
 
-// Tangents one wave carries next to the primal, by register budget (512 per lane).
+// Tangents one wave carries next to the primal, by register budget (256 per lane at two
+// waves per SIMD).
 constexpr int kTcF32W64 = 3, kTcF32W128 = 2, kTcBf16W64 = 4, kTcBf16W128 = 2;
 
-// Waves per workgroup (one workgroup per CU: its two LDS layer buffers take 128 KB at
-// width 128). BF16, 32-point tiles: with tangents ~500 registers (one wave per SIMD),
-// primal only two waves per SIMD. FP32, 16-point tiles: two waves per SIMD with tangents,
-// four for the primal. Either way a group spans the same points.
-template <int TC, bool BF> struct Wpg {
-  static constexpr int value = BF ? (TC > 0 ? 4 : 8) : (TC > 0 ? 8 : 16);
-};
-static_assert(kTile * Wpg<1, true>::value == kTile16 * Wpg<1, false>::value &&
-                  kTile * Wpg<0, true>::value == kTile16 * Wpg<0, false>::value,
-              "a group spans the same points in both precisions");
+// Waves per workgroup of the table kernels (one workgroup per CU at width 128: its two
+// LDS layer buffers take 128 KB in FP32): two waves per SIMD with tangents, four for the
+// primal. A group spans WPG tiles of 16 points.
+template <int TC> struct Wpg { static constexpr int value = TC > 0 ? 8 : 16; };
 
 template <int W, int TC, bool BF>
 hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int32_t* n_groups,
                         int32_t* claim, int grid, hipStream_t s) {
-  constexpr int WPG = Wpg<TC, BF>::value;
+  constexpr int WPG = Wpg<TC>::value;
   constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes;
   auto k = fields_table_kernel<W, TC, BF, WPG>;
   static bool attr = false;
@@ -712,51 +537,47 @@ hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int
   return hipGetLastError();
 }
 
-// Streamed-weight decode: as many persistent workgroups as fit on the device at once.
-// FP32 decode: eight waves per workgroup (two per SIMD) hold a 16-point tile each without
-// spilling; sixteen spill and measured slower.
-constexpr int kDenseWpg16 = 8;
+// Persistent decode grid: as many workgroups as fit on `cus` CUs at once.
+template <class K>
+hipError_t decode_grid(K k, int wpg, int lds, int cus, int* per_cu, int* grid) {
+  if (*per_cu == 0) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, 64 * wpg, lds);
+    if (e != hipSuccess) return e;
+    if (*per_cu < 1) *per_cu = 1;
+  }
+  *grid = cus * *per_cu;
+  return hipSuccess;
+}
+
+// FP32 decode: eight waves per workgroup (two per SIMD) hold a tile each without spilling;
+// sixteen spill and measured slower.
+constexpr int kDenseWpg = 12;
+// BF16 decode: weights resident (four hidden layers, 4 W^2 x 2 B = 128 KB at width 128).
+constexpr int kDenseResWpg = 16;
 
 template <int W>
 hipError_t launch_dense(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
-  constexpr int WPG = kDenseWpg16;
   constexpr int lds = 2 * HiddenLayer<W, false>::kBytes;
-  auto k = fields_dense_kernel<W, WPG>;
+  auto k = fields_dense_kernel<W, kDenseWpg>;
   static int per_cu = 0;
-  if (per_cu == 0) {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * WPG, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-  }
-  int grid = cus * per_cu;
-  if (grid > n_tiles) grid = n_tiles;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, job, n_tiles);
+  int grid = 0;
+  const hipError_t e = decode_grid(k, kDenseWpg, lds, cus, &per_cu, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kDenseWpg), lds, s, job, n_tiles);
   return hipGetLastError();
 }
 
-// BF16 decode: twelve waves per workgroup (three per SIMD) measured fastest.
-constexpr int kDenseResWpg = 12;
-
-// Resident-weight decode: one workgroup per CU at width 128 (the four hidden layers take
-// 4 W^2 x 2 B = 128 KB of LDS in BF16).
-template <int W, bool BF>
+template <int W>
 hipError_t launch_dense_res(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
-  constexpr int WPG = kDenseResWpg;
-  constexpr int lds = 4 * HiddenLayer<W, BF>::kBytes;
+  constexpr int lds = 4 * HiddenLayer<W, true>::kBytes;
   static_assert(lds <= 160 * 1024, "resident weights must fit in LDS");
-  auto k = fields_dense_res_kernel<W, BF, WPG>;
+  auto k = fields_dense_res_kernel<W, kDenseResWpg>;
   static int per_cu = 0;
-  if (per_cu == 0) {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * WPG, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-  }
-  int grid = cus * per_cu;
-  const int need = (n_tiles + WPG - 1) / WPG;
-  if (grid > need) grid = need;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, job, n_tiles);
+  int grid = 0;
+  const hipError_t e = decode_grid(k, kDenseResWpg, lds, cus, &per_cu, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kDenseResWpg), lds, s, job, n_tiles);
   return hipGetLastError();
 }
 
@@ -767,7 +588,7 @@ int fields_max_tangents(int width, bool bf16) {
   return bf16 ? kTcBf16W128 : kTcF32W128;
 }
 
-int fields_group_points(int tc) { return kTile * (tc > 0 ? Wpg<1, true>::value : Wpg<0, true>::value); }
+int fields_group_points(int tc) { return kTile16 * (tc > 0 ? Wpg<1>::value : Wpg<0>::value); }
 
 hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
                                const FieldTile* groups, const int32_t* n_groups, int32_t* claim,
@@ -788,13 +609,12 @@ hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* job
 }
 
 int fields_table_blocks_per_cu(int width, bool bf16, int tc) {
-  // dynamic LDS (two hidden layers) bounds residency: 160 KB per CU
-  const int lds = 2 * (bf16 ? width * width * 2 : width * width * 4);
-  int by_lds = (160 * 1024) / (lds + 1024);
-  if (by_lds < 1) by_lds = 1;
-  // registers: the tangent kernels run one wave per SIMD, the primal ones two
-  const int by_regs = tc > 0 ? 1 : 1;
-  return by_lds < by_regs ? by_lds : by_regs;
+  // registers bound residency to one workgroup per CU (two waves per SIMD with tangents,
+  // four for the primal), before LDS (two hidden layers, at most 128 KB) does
+  (void)width;
+  (void)bf16;
+  (void)tc;
+  return 1;
 }
 
 __global__ void reset_counters_kernel(int32_t* c, int n) {
@@ -817,13 +637,12 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
     if (e != hipSuccess) return e;
   }
   const int cus = max_cus > 0 && max_cus < dev_cus ? max_cus : dev_cus;
+  const int tiles = (n_points + kTile16 - 1) / kTile16;
   if (bf16) {
-    const int tiles = (n_points + kTile - 1) / kTile;
-    if (width == 64) return launch_dense_res<64, true>(job, tiles, cus, s);
-    if (width == 128) return launch_dense_res<128, true>(job, tiles, cus, s);
+    if (width == 64) return launch_dense_res<64>(job, tiles, cus, s);
+    if (width == 128) return launch_dense_res<128>(job, tiles, cus, s);
     return hipErrorInvalidValue;
   }
-  const int tiles = (n_points + kTile16 - 1) / kTile16;
   if (width == 64) return launch_dense<64>(job, tiles, cus, s);
   if (width == 128) return launch_dense<128>(job, tiles, cus, s);
   return hipErrorInvalidValue;

@@ -36,8 +36,8 @@ __device__ __forceinline__ float scaled(float w, double f) { return (float)((dou
 
 // ---- device packing (same orders as pack.cpp, plus transposed hidden layers) --------
 struct Packed {
-  float* w1p; float* whp; uint16_t* whb; float* bhp; float* w6p; float* b6; float* whtp;
-  float* w1q; float* bhq; float* w6q;
+  float* whp; uint16_t* whb; float* b6; float* w1q; float* bhq; float* w6q;  // forward
+  float* w6p; float* whtp;                                                     // backward
 };
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -48,26 +48,24 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 }
 
 __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int d, Packed P) {
-  const int in1 = 3 + r, MB = W / 32, K1s = (r + 5) / 2;
+  const int in1 = 3 + r, MB = W / 32, MQ = W / 16, K1q = (r + 7) / 4;
   const float* W1 = master;
   const float* b1 = W1 + (size_t)W * in1;
   const float* hid = b1 + W;   // W2 b2 W3 b3 W4 b4 W5 b5
   const float* W6 = hid + 4 * ((size_t)W * W + W);
   const float* b6 = W6 + (size_t)d * W;
-  const int MQ = W / 16, K1q = (r + 7) / 4;
-  const int64_t n1 = (int64_t)MB * K1s * 64, nh = (int64_t)4 * W * W, nb = 4 * W, n6 = (int64_t)d * W;
-  const int64_t n1q = (int64_t)MQ * K1q * 64;
-  const int64_t total = n1 + 3 * nh + nb + n6 + d + n1q + nb + n6;
+  const int64_t n1q = (int64_t)MQ * K1q * 64, nh = (int64_t)4 * W * W, nb = 4 * W, n6 = (int64_t)d * W;
+  const int64_t total = n1q + 3 * nh + nb + 2 * n6 + d;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t t = e;
-    if (t < n1) {
-      const int l = t % 64, s2 = (t / 64) % K1s, mb = t / (64 * K1s);
-      const int m = 32 * mb + (l & 31), k = 2 * s2 + (l >> 5);
-      P.w1p[t] = k < in1 ? scaled(W1[(size_t)m * in1 + k], kLog2e) : (k == in1 ? scaled(b1[m], kLog2e) : 0.f);
+    if (t < n1q) {   // layer 1, 16x16x4 A operands
+      const int l = t % 64, s4 = (t / 64) % K1q, mb = t / (64 * K1q);
+      const int m = 16 * mb + (l & 15), k = 4 * s4 + (l >> 4);
+      P.w1q[t] = k < in1 ? scaled(W1[(size_t)m * in1 + k], kLog2e) : (k == in1 ? scaled(b1[m], kLog2e) : 0.f);
       continue;
     }
-    t -= n1;
-    if (t < nh) {   // FP32 forward, 16x16x4 layout: [4][W/16][W/16][64][4]
+    t -= n1q;
+    if (t < nh) {   // FP32 forward: [4][W/16][W/16][64][4]
       const int j = t % 4, l = (t / 4) % 64, sg = (t / 256) % (W / 16), mb = (t / (256 * (W / 16))) % MQ;
       const int kk = t / ((int64_t)W * W);
       const int m = 16 * mb + (l & 15), nn = 16 * sg + 4 * (l >> 4) + j;
@@ -75,10 +73,10 @@ __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int 
       continue;
     }
     t -= nh;
-    if (t < nh) {   // BF16 forward: [4][MB][W/16][64][8]
-      const int j = t % 8, l = (t / 8) % 64, s = (t / 512) % (W / 16), mb = (t / (512 * (W / 16))) % MB;
+    if (t < nh) {   // BF16 forward: [4][W/16][W/32][64][8]
+      const int j = t % 8, l = (t / 8) % 64, s = (t / 512) % (W / 32), mb = (t / (512 * (W / 32))) % MQ;
       const int kk = t / ((int64_t)W * W);
-      const int m = 32 * mb + (l & 31), nn = acc_n(s / 2, 8 * (s % 2) + j, l >> 5);
+      const int m = 16 * mb + (l & 15), nn = 16 * (2 * s + (j >> 2)) + 4 * (l >> 4) + (j & 3);
       P.whb[t] = to_bf16(hid[kk * ((size_t)W * W + W) + (size_t)m * W + nn]);
       continue;
     }
@@ -91,40 +89,25 @@ __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int 
       continue;
     }
     t -= nh;
-    if (t < nb) {
-      const int s = t % (W / 2), h = (t / (W / 2)) % 2, kk = t / W;
-      P.bhp[t] = scaled(hid[kk * ((size_t)W * W + W) + (size_t)W * W + acc_n(s / 16, s % 16, h)], kLog2e);
-      continue;
-    }
-    t -= nb;
-    if (t < n6) {
-      const int s = t % (W / 2), h = (t / (W / 2)) % 2, o = t / W;
-      P.w6p[t] = scaled(W6[(size_t)o * W + acc_n(s / 16, s % 16, h)], kLn2);
-      continue;
-    }
-    t -= n6;
-    if (t < d) {
-      P.b6[t] = b6[t];
-      continue;
-    }
-    t -= d;
-    if (t < n1q) {   // FP32 forward, 16x16x4 layer 1
-      const int l = t % 64, s4 = (t / 64) % K1q, mb = t / (64 * K1q);
-      const int m = 16 * mb + (l & 15), k = 4 * s4 + (l >> 4);
-      P.w1q[t] = k < in1 ? scaled(W1[(size_t)m * in1 + k], kLog2e) : (k == in1 ? scaled(b1[m], kLog2e) : 0.f);
-      continue;
-    }
-    t -= n1q;
-    if (t < nb) {    // FP32 forward, plain-order biases
+    if (t < nb) {   // hidden biases, plain order
       const int n = t % W, kk = t / W;
       P.bhq[t] = scaled(hid[kk * ((size_t)W * W + W) + (size_t)W * W + n], kLog2e);
       continue;
     }
     t -= nb;
-    {                // FP32 forward, plain-order output weights
+    if (t < n6) {   // output weights, plain order (forward)
       const int n = t % W, o = t / W;
       P.w6q[t] = scaled(W6[(size_t)o * W + n], kLn2);
+      continue;
     }
+    t -= n6;
+    if (t < n6) {   // output weights in 32x32 accumulator order (backward)
+      const int s = t % (W / 2), h = (t / (W / 2)) % 2, o = t / W;
+      P.w6p[t] = scaled(W6[(size_t)o * W + acc_n(s / 16, s % 16, h)], kLn2);
+      continue;
+    }
+    t -= n6;
+    P.b6[t] = b6[t];
   }
 }
 
@@ -401,16 +384,14 @@ TrainWs carve(char* base, int r, int W, int d, int64_t n, bool backward) {
   const PackSizes ps = pack_sizes(r, W, d);
   size_t off = 0;
   auto take = [&](size_t bytes) { char* p = base ? base + off : nullptr; off += align256(bytes); return p; };
-  w.pk.w1p = (float*)take(ps.w1p * 4);
   w.pk.whp = (float*)take(ps.whp * 4);
   w.pk.whb = (uint16_t*)take(ps.whb * 2);
-  w.pk.bhp = (float*)take(ps.bhp * 4);
-  w.pk.w6p = (float*)take(ps.w6p * 4);
   w.pk.b6 = (float*)take(ps.b6 * 4);
-  w.pk.whtp = (float*)take(ps.whp * 4);
   w.pk.w1q = (float*)take(ps.w1q * 4);
   w.pk.bhq = (float*)take(ps.bhq * 4);
   w.pk.w6q = (float*)take(ps.w6q * 4);
+  w.pk.w6p = (float*)take(ps.w6p * 4);
+  w.pk.whtp = (float*)take(ps.whp * 4);
   if (backward) {
     w.delta = (float*)take((size_t)5 * n * W * 4);
     const int64_t chunks = (n + kChunk - 1) / kChunk;
@@ -456,11 +437,8 @@ nsf_status nsf_mlp_forward(const nsf_mlp* m, const float* X, const float* z_rows
   hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s, m->weights, m->r, m->width, m->d, ws.pk);
   if (hipGetLastError() != hipSuccess) return NSF_EHIP;
   FieldJob j{};
-  j.w.w1p = ws.pk.w1p;
   j.w.whp = ws.pk.whp;
   j.w.whb = reinterpret_cast<const bf16x8*>(ws.pk.whb);
-  j.w.bhp = ws.pk.bhp;
-  j.w.w6p = ws.pk.w6p;
   j.w.b6 = ws.pk.b6;
   j.w.w1q = ws.pk.w1q;
   j.w.bhq = ws.pk.bhq;

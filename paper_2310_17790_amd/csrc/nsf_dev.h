@@ -7,7 +7,6 @@
 namespace nsf {
 
 constexpr int kMaxR = 32;          // largest latent dimension
-constexpr int kTile = 32;          // points per wave tile (MFMA N dimension)
 constexpr int kGnChunk = 128;      // sample points per Gauss-Newton reduction block
 constexpr int kGnThreads = 256;    // threads of a Gauss-Newton reduction block
 constexpr int kClaimCounters = 8;  // work-claim counters of the field kernels, zeroed per step
@@ -18,27 +17,15 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Hidden neuron held in accumulator register i of M-block mb by lane half h (lanes 0-31:
-// h = 0, lanes 32-63: h = 1) for the 32x32 MFMA output layout: within each group of 8
-// rows, lanes 0-31 hold rows 0-3 and lanes 32-63 rows 4-7.
-__host__ __device__ inline int acc_neuron(int mb, int i, int h) {
-  return 32 * mb + 8 * (i >> 2) + 4 * h + (i & 3);
-}
-
 // Packed parameters of one field (one MLP), all in device memory. See pack.cpp for how
 // the host builds each array from the row-major masters.
 struct FieldPack {
-  // BF16 precision (32-point tiles, 32x32 MFMA layouts)
-  const float* w1p;      // layer 1 incl. bias column: [W/32][K1s][64] 32x32x2 A operands
-  const bf16x8* whb;     // hidden layers 2..5, BF16 A operands: [4][W/32][W/16][64]
-  const float* bhp;      // hidden biases in accumulator order: [4][2][W/2]
-  const float* w6p;      // output weights in accumulator order: [d][2][W/2]
-  // FP32 precision (16-point tiles, 16x16x4 MFMA layouts)
   const float* w1q;      // layer 1 incl. bias column: [W/16][K1q][64] 16x16x4 A operands
-  const float* whp;      // hidden layers 2..5: [4][W/16][W/16][64][4]
+  const float* whp;      // FP32 hidden layers 2..5: [4][W/16][W/16][64][4]
+  const bf16x8* whb;     // BF16 hidden layers 2..5: [4][W/16][W/32][64]
   const float* bhq;      // hidden biases, plain order: [4][W]
   const float* w6q;      // output weights, plain order: [d][W]
-  const float* b6;       // output bias [d] (both)
+  const float* b6;       // output bias [d]
 };
 
 // One batch of MLP evaluations: a field at one latent over a list of points.
@@ -66,8 +53,8 @@ struct FieldJob {
   float scale[9], shift[9];
 };
 
-// One workgroup's work: WPG consecutive 32-point tiles of a job starting at point p0
-// (wave w takes p0 + 32 w), the primal plus tangents [t0, t0 + nt). Only groups with
+// One workgroup's work: WPG consecutive 16-point tiles of a job starting at point p0
+// (wave w takes p0 + 16 w), the primal plus tangents [t0, t0 + nt). Only groups with
 // t0 == 0 write the primal output.
 struct FieldTile {
   int32_t job, p0, t0, nt;

@@ -23,8 +23,7 @@ struct PackSizes {
 
 // The packed arrays of one field (host or device buffers of PackSizes elements).
 struct PackOut {
-  float* w1p; float* whp; uint16_t* whb; float* bhp; float* w6p; float* b6;
-  float* w1q; float* bhq; float* w6q;
+  float* whp; uint16_t* whb; float* b6; float* w1q; float* bhq; float* w6q;
 };
 
 size_t mlp_param_count(int r, int width, int d);
