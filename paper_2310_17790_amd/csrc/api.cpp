@@ -473,20 +473,11 @@ nsf_status enqueue_inference(Plan& P, hipStream_t s) {
   return NSF_OK;
 }
 
-// A pipelined decode leaves 1 / kPipelinedFreeCuDiv of the compute units to the MPM and
-// Gauss-Newton kernels that run beside it.
-#ifndef NSF_PIPE_DIV
-#define NSF_PIPE_DIV 4
-#endif
-constexpr int kPipelinedFreeCuDiv = NSF_PIPE_DIV;
-
-// Decode of all particles, on the side stream between a fork and a join recorded on s
-// (inline on s when there is no side stream).
 // Decode of all particles on stream s: the dense kernel for one sim, else the primal
 // table kernel over every sim's decode groups.
-nsf_status launch_decode(Plan& P, hipStream_t s, int max_cus) {
+nsf_status launch_decode(Plan& P, hipStream_t s, bool beside) {
   if (P.nsims == 1 && !P.persistent)
-    NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, s, max_cus));
+    NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, s, beside));
   else
     NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
                                 P.d_counts + kClaimD, P.gF0, s));
@@ -494,12 +485,13 @@ nsf_status launch_decode(Plan& P, hipStream_t s, int max_cus) {
 }
 
 // Pipelined decode: on the side stream between a fork and a join recorded on s (inline on
-// s when there is no side stream), on all but 1 / kPipelinedFreeCuDiv of the CUs.
+// s when there is no side stream), on three quarters of the CUs: the latency-bound MPM and
+// Gauss-Newton kernels run on the rest meanwhile.
 nsf_status fork_decode(Plan& P, hipStream_t s) {
-  if (s == nullptr || !P.side) return launch_decode(P, s, 0);
+  if (s == nullptr || !P.side) return launch_decode(P, s, false);
   NSF_HIP(hipEventRecord(P.ev_fork, s));
   NSF_HIP(hipStreamWaitEvent(P.side, P.ev_fork, 0));
-  const nsf_status st = launch_decode(P, P.side, device_cus() - device_cus() / kPipelinedFreeCuDiv);
+  const nsf_status st = launch_decode(P, P.side, true);
   if (st != NSF_OK) return st;
   NSF_HIP(hipEventRecord(P.ev_join, P.side));
   return NSF_OK;
@@ -517,7 +509,7 @@ nsf_status join_decode(Plan& P, hipStream_t s) {
 nsf_status enqueue_refresh_body(Plan& P, hipStream_t s, bool decode) {
   NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
                               P.d_counts + kClaimA, P.gF, s));
-  return decode ? launch_decode(P, s, 0) : NSF_OK;
+  return decode ? launch_decode(P, s, false) : NSF_OK;
 }
 
 // Refresh outside a step (nsf_refresh): a pipelined sim first points its decode at the

@@ -550,35 +550,40 @@ hipError_t decode_grid(K k, int wpg, int lds, int cus, int* per_cu, int* grid) {
   return hipSuccess;
 }
 
-// FP32 decode: eight waves per workgroup (two per SIMD) hold a tile each without spilling;
-// sixteen spill and measured slower.
-constexpr int kDenseWpg = 12;
-// BF16 decode: weights resident (four hidden layers, 4 W^2 x 2 B = 128 KB at width 128).
-constexpr int kDenseResWpg = 16;
+// Waves per decode workgroup: FP32 three per SIMD (137 registers), BF16 four (106), the
+// fastest measured.
+constexpr int kDenseWpg = 12, kDenseResWpg = 16;
 
-template <int W>
+template <int W, int WPG>
 hipError_t launch_dense(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
   constexpr int lds = 2 * HiddenLayer<W, false>::kBytes;
-  auto k = fields_dense_kernel<W, kDenseWpg>;
+  auto k = fields_dense_kernel<W, WPG>;
   static int per_cu = 0;
   int grid = 0;
-  const hipError_t e = decode_grid(k, kDenseWpg, lds, cus, &per_cu, &grid);
+  const hipError_t e = decode_grid(k, WPG, lds, cus, &per_cu, &grid);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kDenseWpg), lds, s, job, n_tiles);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, job, n_tiles);
+  return hipGetLastError();
+}
+
+// BF16: all four hidden layers resident (4 W^2 x 2 B = 128 KB at width 128).
+template <int W, int WPG>
+hipError_t launch_dense_res(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
+  constexpr int lds = 4 * HiddenLayer<W, true>::kBytes;
+  static_assert(lds <= 160 * 1024, "resident weights must fit in LDS");
+  auto k = fields_dense_res_kernel<W, WPG>;
+  static int per_cu = 0;
+  int grid = 0;
+  const hipError_t e = decode_grid(k, WPG, lds, cus, &per_cu, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, job, n_tiles);
   return hipGetLastError();
 }
 
 template <int W>
-hipError_t launch_dense_res(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
-  constexpr int lds = 4 * HiddenLayer<W, true>::kBytes;
-  static_assert(lds <= 160 * 1024, "resident weights must fit in LDS");
-  auto k = fields_dense_res_kernel<W, kDenseResWpg>;
-  static int per_cu = 0;
-  int grid = 0;
-  const hipError_t e = decode_grid(k, kDenseResWpg, lds, cus, &per_cu, &grid);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kDenseResWpg), lds, s, job, n_tiles);
-  return hipGetLastError();
+hipError_t launch_decode_width(bool bf16, const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
+  if (bf16) return launch_dense_res<W, kDenseResWpg>(job, n_tiles, cus, s);
+  return launch_dense<W, kDenseWpg>(job, n_tiles, cus, s);
 }
 
 }  // namespace
@@ -627,7 +632,7 @@ hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s) {
 }
 
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
-                               hipStream_t s, int max_cus) {
+                               hipStream_t s, bool beside) {
   if (n_points <= 0) return hipSuccess;
   static int dev_cus = 0;
   if (dev_cus == 0) {
@@ -636,15 +641,12 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
     if (e == hipSuccess) e = hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
   }
-  const int cus = max_cus > 0 && max_cus < dev_cus ? max_cus : dev_cus;
+  // beside the latency-bound MPM and Gauss-Newton kernels: a quarter of the CUs stay free
+  // for them (sharing a CU with a decode workgroup, they measured no faster than waiting)
+  const int cus = beside ? dev_cus - dev_cus / 4 : dev_cus;
   const int tiles = (n_points + kTile16 - 1) / kTile16;
-  if (bf16) {
-    if (width == 64) return launch_dense_res<64>(job, tiles, cus, s);
-    if (width == 128) return launch_dense_res<128>(job, tiles, cus, s);
-    return hipErrorInvalidValue;
-  }
-  if (width == 64) return launch_dense<64>(job, tiles, cus, s);
-  if (width == 128) return launch_dense<128>(job, tiles, cus, s);
+  if (width == 64) return launch_decode_width<64>(bf16, job, tiles, cus, s);
+  if (width == 128) return launch_decode_width<128>(bf16, job, tiles, cus, s);
   return hipErrorInvalidValue;
 }
 
