@@ -129,18 +129,15 @@ __device__ __forceinline__ void init16(f32x4 (&acc)[T][W / 16], const float* bia
 // their uses or hoisting more of them (which only costs registers).
 constexpr int kPrefetch = 4;
 
-// One FP32 hidden layer from LDS: A is [W/16 output blocks][W/16 K-groups][64 lanes]
-// f32x4 (K-steps 4 sg .. 4 sg + 3), consumed in halves (two K-steps per step).
+// One FP32 hidden layer from LDS: A is [W/16 output blocks][W/8 K-step pairs][64 lanes]
+// f32x2 (K-steps 2 hs, 2 hs + 1; lane-contiguous, so the reads are free of bank
+// conflicts), one pair per step.
 template <int W, int T>
 __device__ __forceinline__ void hidden16(f32x4 (&acc)[T][W / 16], const float (&H)[T][W / 4],
-                                         const f32x4* A, int lane, int nt) {
-  constexpr int MB = W / 16, SG = W / 16, N = 2 * SG * MB, RING = kPrefetch + 1;
-  const f32x2* A2 = reinterpret_cast<const f32x2*>(A);
-  // step i: half-group hs = i / MB of output block mb = i % MB
-  auto at = [&](int i) {
-    const int hs = i / MB, mb = i % MB;
-    return A2[2 * ((mb * SG + (hs >> 1)) * 64 + lane) + (hs & 1)];
-  };
+                                         const f32x2* A2, int lane, int nt) {
+  constexpr int MB = W / 16, HS = W / 8, N = HS * MB, RING = kPrefetch + 1;
+  // step i: K-step pair hs = i / MB of output block mb = i % MB
+  auto at = [&](int i) { return A2[((i % MB) * HS + i / MB) * 64 + lane]; };
   f32x2 ring[RING];
 #pragma unroll
   for (int i = 0; i < kPrefetch; ++i) ring[i] = at(i);
@@ -348,7 +345,7 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
     layer(3, hb);
   } else {
     activate16<W, T>(acc, H, nt);
-    auto hf = [&](char* cur) { hidden16<W, T>(acc, H, reinterpret_cast<const f32x4*>(cur), lane, nt); };
+    auto hf = [&](char* cur) { hidden16<W, T>(acc, H, reinterpret_cast<const f32x2*>(cur), lane, nt); };
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
       layer(k, hf);

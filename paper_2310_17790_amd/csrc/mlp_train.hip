@@ -65,10 +65,10 @@ __global__ void pack_kernel(const float* __restrict__ master, int r, int W, int 
       continue;
     }
     t -= n1q;
-    if (t < nh) {   // FP32 forward: [4][W/16][W/16][64][4]
-      const int j = t % 4, l = (t / 4) % 64, sg = (t / 256) % (W / 16), mb = (t / (256 * (W / 16))) % MQ;
+    if (t < nh) {   // FP32 forward: [4][W/16][W/8][64][2]
+      const int j = t % 2, l = (t / 2) % 64, hs = (t / 128) % (W / 8), mb = (t / (128 * (W / 8))) % MQ;
       const int kk = t / ((int64_t)W * W);
-      const int m = 16 * mb + (l & 15), nn = 16 * sg + 4 * (l >> 4) + j;
+      const int m = 16 * mb + (l & 15), nn = 16 * (hs >> 1) + 4 * (l >> 4) + 2 * (hs & 1) + j;
       P.whp[t] = hid[kk * ((size_t)W * W + W) + (size_t)m * W + nn];
       continue;
     }

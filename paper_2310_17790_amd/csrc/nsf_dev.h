@@ -21,7 +21,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // the host builds each array from the row-major masters.
 struct FieldPack {
   const float* w1q;      // layer 1 incl. bias column: [W/16][K1q][64] 16x16x4 A operands
-  const float* whp;      // FP32 hidden layers 2..5: [4][W/16][W/16][64][4]
+  const float* whp;      // FP32 hidden layers 2..5: [4][W/16][W/8][64][2]
   const bf16x8* whb;     // BF16 hidden layers 2..5: [4][W/16][W/32][64]
   const float* bhq;      // hidden biases, plain order: [4][W]
   const float* w6q;      // output weights, plain order: [d][W]

@@ -77,16 +77,17 @@ void pack_field(const float* master, int r, int width, int d, const PackOut& o) 
       }
   for (int kk = 0; kk < 4; ++kk) {
     const float* Wk = v.Wh[kk];
-    // FP32 A operands [W/16][W/16][64][4]: output block mb, K-group sg, lane l: row
-    // 16 mb + l % 16, inputs 16 sg + 4 (l / 16) + j (the accumulator registers of lane
-    // group l / 16 in the previous layer).
+    // FP32 A operands [W/16][W/8][64][2]: output block mb, K-step pair hs, lane l: row
+    // 16 mb + l % 16, inputs 16 (hs / 2) + 4 (l / 16) + 2 (hs % 2) + j (K-steps 2 hs + j read
+    // the accumulator registers 2 (hs % 2) + j of M-block hs / 2 of lane group l / 16 in the
+    // previous layer).
     float* dst = o.whp + (size_t)kk * W * W;
     for (int mb = 0; mb < MQ; ++mb)
-      for (int sg = 0; sg < W / 16; ++sg)
+      for (int hs = 0; hs < W / 8; ++hs)
         for (int l = 0; l < 64; ++l)
-          for (int j = 0; j < 4; ++j) {
-            const int m = 16 * mb + (l & 15), n = 16 * sg + 4 * (l >> 4) + j;
-            dst[(((size_t)mb * (W / 16) + sg) * 64 + l) * 4 + j] = Wk[(size_t)m * W + n];
+          for (int j = 0; j < 2; ++j) {
+            const int m = 16 * mb + (l & 15), n = 16 * (hs >> 1) + 4 * (l >> 4) + 2 * (hs & 1) + j;
+            dst[(((size_t)mb * (W / 8) + hs) * 64 + l) * 2 + j] = Wk[(size_t)m * W + n];
           }
     // BF16 A operands [W/16][W/32][64][8]: output block mb, K-step s, lane l: row
     // 16 mb + l % 16, inputs 16 (2s + e / 4) + 4 (l / 16) + e % 4 (M-blocks 2s and 2s + 1
