@@ -13,9 +13,9 @@
 //    LDS and stores its partial H (upper triangle) and b. Iteration 0 runs it inside the
 //    G2P kernel (mpm.hip), where r = -dt v is at hand; later iterations in
 //    gn_partial_kernel, after the field kernel evaluated u and J at the iterate.
-//  - gn_solve_kernel: one wave per simulation adds the partials in chunk order
-//    (deterministic), factors H with a column-parallel Cholesky in LDS, solves, and
-//    updates the latent; the last iteration also shifts z_{n-1} <- z_n <- z_{n+1} and
+//  - gn_solve_kernel: one workgroup per simulation adds the partials in a fixed order
+//    (deterministic); its first wave factors H with a column-parallel Cholesky in LDS,
+//    solves, and updates the latent; the last iteration also shifts z_{n-1} <- z_n <- z_{n+1} and
 //    advances the step counter.
 // The kernel boundary publishes the partials to the solving block on whichever XCD it
 // runs (a device-scope release inside one kernel would write back every block's L2).
@@ -26,9 +26,16 @@
 namespace nsf {
 namespace {
 
-constexpr int kSolveThreads = 64;   // one wave: the solve's barriers cost nothing
+// The chunk partials are summed by the whole workgroup (more loads in flight); the solve
+// itself runs in wave 0, synchronised at wave scope.
+constexpr int kSolveThreads = 1024;
 
-// Factor and solve in one wave. H and y live in LDS.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Factor and solve in one wave (lane = threadIdx.x < 64). H and y live in LDS.
 __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 1], double* y,
                                  int* bad) {
   const int r = S.r, tid = threadIdx.x;
@@ -38,31 +45,31 @@ __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 
       if (!(dj > 0.0)) *bad = 1;
       else H[j][j] = sqrt(dj);
     }
-    __syncthreads();
+    wave_sync();
     if (*bad) break;
     const double ljj = H[j][j];
-    for (int i = j + 1 + tid; i < r; i += blockDim.x) H[i][j] /= ljj;
-    __syncthreads();
+    for (int i = j + 1 + tid; i < r; i += 64) H[i][j] /= ljj;
+    wave_sync();
     const int m = r - j - 1;
-    for (int e = tid; e < m * m; e += blockDim.x) {
+    for (int e = tid; e < m * m; e += 64) {
       const int i = j + 1 + e / m, k = j + 1 + e % m;
       if (k <= i) H[i][k] -= H[i][j] * H[k][j];
     }
-    __syncthreads();
+    wave_sync();
   }
-  __syncthreads();
+  wave_sync();
   if (*bad == 0) {
     for (int j = 0; j < r; ++j) {            // L w = -b
       if (tid == 0) y[j] /= H[j][j];
-      __syncthreads();
-      for (int i = j + 1 + tid; i < r; i += blockDim.x) y[i] -= H[i][j] * y[j];
-      __syncthreads();
+      wave_sync();
+      for (int i = j + 1 + tid; i < r; i += 64) y[i] -= H[i][j] * y[j];
+      wave_sync();
     }
     for (int j = r - 1; j >= 0; --j) {       // L^T delta = w
       if (tid == 0) y[j] /= H[j][j];
-      __syncthreads();
-      for (int i = tid; i < j; i += blockDim.x) y[i] -= H[j][i] * y[j];
-      __syncthreads();
+      wave_sync();
+      for (int i = tid; i < j; i += 64) y[i] -= H[j][i] * y[j];
+      wave_sync();
     }
   }
   const bool final_iter = (iter == S.gn_iters - 1);
@@ -70,7 +77,7 @@ __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 
   double* zc = S.z + r;
   double* zi = S.z + 2 * r;
   if (tid == 0 && *bad) atomicOr(S.flags, (*bad & 2) ? FLAG_NONFINITE : FLAG_SINGULAR);
-  for (int j = tid; j < r; j += blockDim.x) {
+  for (int j = tid; j < r; j += 64) {
     const double base = (iter == 0) ? zc[j] : zi[j];
     const double zn = *bad ? base : base + y[j];
     if (!isfinite(zn)) atomicOr(S.flags, FLAG_NONFINITE);
@@ -183,7 +190,7 @@ __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* _
       }
       __syncthreads();
     }
-    solve_and_update(S, iter, H, y, &bad);
+    if (tid < 64) solve_and_update(S, iter, H, y, &bad);
     __syncthreads();
   }
 }
