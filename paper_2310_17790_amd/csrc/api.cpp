@@ -56,7 +56,7 @@ struct Carver {
 // Byte offsets of every buffer of a sim inside its arena.
 struct Layout {
   size_t simdev;
-  size_t whp[3], whb[3], b6[3], w1q[3], bhq[3], w6q[3];
+  size_t whp[3], whb[3], b6[3], w1q[3], bhq[3], w6q[3], whpt[3], whbt[3], w1zt[3];
   size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, zdec, step, flags, gn_part;
   size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active,
       nonempty, n_active;
@@ -82,6 +82,9 @@ Layout make_layout(const nsf_sim_desc* d) {
     L.w1q[f] = c.take(ps.w1q * 4);
     L.bhq[f] = c.take(ps.bhq * 4);
     L.w6q[f] = c.take(ps.w6q * 4);
+    L.whpt[f] = c.take(ps.whp * 4);
+    L.whbt[f] = c.take(ps.whb * 2);
+    L.w1zt[f] = c.take(ps.w1zt * 4);
   }
   L.X = c.take((size_t)3 * P * 4);
   L.plan = c.take((size_t)d->plan_steps * N * 4);
@@ -276,11 +279,19 @@ FieldJob base_job(const nsf_sim* s, int field, const double* z) {
   return j;
 }
 
+// Groups of one job over n points: primal only (ntan = 0), or with the Jacobian's ntan
+// latent columns. Forward mode takes ceil(ntan / tc) groups per span of points, each
+// recomputing the primal; reverse mode (FieldTile.nt < 0, t0 = output component) takes
+// one group per output component and pays off once forward mode needs more than two.
+bool reverse_jacobian(int ntan, int tc) { return ntan > 2 * tc; }
+
 void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc) {
   const int span = fields_group_points(ntan > 0 ? tc : 0);
   for (int p0 = 0; p0 < n; p0 += span) {
     if (ntan == 0) {
       out.push_back({job, p0, 0, 0});
+    } else if (reverse_jacobian(ntan, tc)) {
+      for (int c = 0; c < 3; ++c) out.push_back({job, p0, c, -1});
     } else {
       for (int t0 = 0; t0 < ntan; t0 += tc) out.push_back({job, p0, t0, std::min(tc, ntan - t0)});
     }
@@ -661,10 +672,12 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   for (int f = 0; f < 3; ++f) {
     const int dd = kFieldOut[f];
     const PackSizes ps = pack_sizes(r, W, dd);
-    std::vector<float> whp(ps.whp), b6(ps.b6), w1q(ps.w1q), bhq(ps.bhq), w6q(ps.w6q);
-    std::vector<uint16_t> whb(ps.whb);
+    std::vector<float> whp(ps.whp), b6(ps.b6), w1q(ps.w1q), bhq(ps.bhq), w6q(ps.w6q), whpt(ps.whp),
+        w1zt(ps.w1zt);
+    std::vector<uint16_t> whb(ps.whb), whbt(ps.whb);
     pack_field(d->weights[f], r, W, dd,
-               PackOut{whp.data(), whb.data(), b6.data(), w1q.data(), bhq.data(), w6q.data()});
+               PackOut{whp.data(), whb.data(), b6.data(), w1q.data(), bhq.data(), w6q.data(), whpt.data(),
+                       whbt.data(), w1zt.data()});
     auto up = [&](size_t off, const void* src, size_t bytes) {
       return hipMemcpyAsync(A + off, src, bytes, hipMemcpyHostToDevice, s);
     };
@@ -674,6 +687,9 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
     NSF_HIP(up(L.w1q[f], w1q.data(), w1q.size() * 4));
     NSF_HIP(up(L.bhq[f], bhq.data(), bhq.size() * 4));
     NSF_HIP(up(L.w6q[f], w6q.data(), w6q.size() * 4));
+    NSF_HIP(up(L.whpt[f], whpt.data(), whpt.size() * 4));
+    NSF_HIP(up(L.whbt[f], whbt.data(), whbt.size() * 2));
+    NSF_HIP(up(L.w1zt[f], w1zt.data(), w1zt.size() * 4));
     NSF_HIP(hipStreamSynchronize(s));  // host staging vectors die at the end of this scope
     FieldPack& fp = sim->pack[f];
     fp.whp = reinterpret_cast<const float*>(A + L.whp[f]);
@@ -682,6 +698,9 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
     fp.w1q = reinterpret_cast<const float*>(A + L.w1q[f]);
     fp.bhq = reinterpret_cast<const float*>(A + L.bhq[f]);
     fp.w6q = reinterpret_cast<const float*>(A + L.w6q[f]);
+    fp.whpt = reinterpret_cast<const float*>(A + L.whpt[f]);
+    fp.whbt = reinterpret_cast<const bf16x8*>(A + L.whbt[f]);
+    fp.w1zt = reinterpret_cast<const float*>(A + L.w1zt[f]);
   }
   const int64_t P = d->n_particles;
   NSF_HIP(hipMemcpyAsync(A + L.X, d->X, (size_t)3 * P * 4, hipMemcpyHostToDevice, s));

@@ -112,12 +112,12 @@ __device__ __forceinline__ void activate16_bf16(const f32x4 (&acc)[T][W / 16], b
   }
 }
 
-// Accumulators start from the layer's bias (plain order) or zero (tangents).
+// Accumulators start from the layer's bias (plain order; none: zero) or zero (tangents).
 template <int W, int T>
 __device__ __forceinline__ void init16(f32x4 (&acc)[T][W / 16], const float* bias, int g) {
 #pragma unroll
   for (int mb = 0; mb < W / 16; ++mb) {
-    acc[0][mb] = *reinterpret_cast<const f32x4*>(bias + 16 * mb + 4 * g);
+    acc[0][mb] = bias ? *reinterpret_cast<const f32x4*>(bias + 16 * mb + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 1; t < T; ++t) acc[t][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
@@ -218,15 +218,17 @@ struct HiddenLayer {
 typedef __attribute__((address_space(3))) void lds_void;
 
 template <bool BF>
-__device__ __forceinline__ const char* hidden_src(const FieldPack& w) {
+__device__ __forceinline__ const char* hidden_src(const FieldPack& w, bool tr = false) {
+  if (tr) return BF ? reinterpret_cast<const char*>(w.whbt) : reinterpret_cast<const char*>(w.whpt);
   return BF ? reinterpret_cast<const char*>(w.whb) : reinterpret_cast<const char*>(w.whp);
 }
 
-// Copy hidden layer k of `w` into LDS buffer dst with direct global->LDS loads; the 1 KB
-// chunks are dealt to the waves of the workgroup round-robin.
+// Copy hidden layer k of `w` (tr: its transpose) into LDS buffer dst with direct
+// global->LDS loads; the 1 KB chunks are dealt to the waves of the workgroup round-robin.
 template <int W, bool BF, int WPG>
-__device__ __forceinline__ void dma_layer(const FieldPack& w, int k, char* dst, int wave, int lane) {
-  const char* src = hidden_src<BF>(w) + (size_t)k * HiddenLayer<W, BF>::kBytes;
+__device__ __forceinline__ void dma_layer(const FieldPack& w, int k, char* dst, int wave, int lane,
+                                          bool tr = false) {
+  const char* src = hidden_src<BF>(w, tr) + (size_t)k * HiddenLayer<W, BF>::kBytes;
 #pragma unroll
   for (int chunk = wave; chunk < HiddenLayer<W, BF>::kChunks; chunk += WPG)
     __builtin_amdgcn_global_load_lds(src + chunk * 1024 + lane * 16,
@@ -247,53 +249,50 @@ __device__ __forceinline__ void wait_dma_and_sync() {
   __syncthreads();
 }
 
-// One wave evaluates a 16-point tile of a job, starting at point p0: the primal plus
-// tangents [t0, t0 + nt). Two ways to hold the hidden-layer weights:
-//  - streamed (RES = false): the WPG waves of a workgroup run tiles of the same job in
-//    step; layers stream through two LDS buffers, layer k + 1 (or the next group's first
-//    hidden layer) fetched while layer k computes, with a workgroup barrier per layer;
-//  - resident (RES = true, BF16 decode): all four hidden layers sit in LDS for the whole
-//    kernel, and waves run their tiles independently, without barriers.
-// Returns after the output layer.
-template <int W, int NT, bool BF, int WPG, bool RES = false, class NextFn>
-__device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, NextFn&& next,
-                                            char* lds, int wave, int lane) {
-  constexpr int MB = W / 16;
-  constexpr int T = 1 + NT;
-  constexpr int nt = NT;  // compile-time: no per-MFMA guards
-  constexpr int LB = HiddenLayer<W, BF>::kBytes;
-  const int g = lane >> 4;
-  const int p = p0 + (lane & 15);
-  const bool valid = p < jb.n;
-  int gi = jb.p_off + (valid ? p : jb.n - 1);
+// The point of lane l in a 16-point tile starting at p0 (clamped for the ragged tail) and
+// its reference position.
+struct TilePoint {
+  int p;
+  bool valid;
+  float X[3];
+};
+
+__device__ __forceinline__ TilePoint tile_point(const FieldJob& jb, int p0, int lane) {
+  TilePoint tp;
+  tp.p = p0 + (lane & 15);
+  tp.valid = tp.p < jb.n;
+  int gi = jb.p_off + (tp.valid ? tp.p : jb.n - 1);
   if (jb.idx != nullptr) {
     const int32_t* row = jb.idx;
     if (jb.step != nullptr) row += (*jb.step % jb.plan_steps) * (int64_t)jb.plan_ld;
     gi = row[gi];
   }
-  const float X0 = jb.X[gi];
-  const float X1 = jb.X[jb.ldx + gi];
-  const float X2 = jb.X[2 * jb.ldx + gi];
-  const int r = jb.r;
+  tp.X[0] = jb.X[gi];
+  tp.X[1] = jb.X[jb.ldx + gi];
+  tp.X[2] = jb.X[2 * jb.ldx + gi];
+  return tp;
+}
 
-  f32x4 acc[T][MB];
+// Layer 1: input rows 0..2 = X, 3..2+r = z, 3+r = 1 (bias column), four per K-step, into
+// zeroed accumulators. Tangent columns (t = 1..NT) are one-hot in z at t0 + t - 1
+// (Jacobian) or the direction z - z2 (JVP job).
+template <int W, int T, int NT>
+__device__ __forceinline__ void layer1_16(const FieldJob& jb, const TilePoint& tp, int t0, int lane,
+                                          f32x4 (&acc)[T][W / 16]) {
+  constexpr int MB = W / 16;
+  const int g = lane >> 4, r = jb.r;
 #pragma unroll
   for (int t = 0; t < T; ++t)
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  // Layer 1: input rows 0..2 = X, 3..2+r = z, 3+r = 1 (bias column), four per K-step.
-  // Tangent columns are one-hot in z (Jacobian) or the direction z - z2 (JVP job).
   const int K1q = (r + 7) >> 2;
   const bool jvp = jb.jvp != 0;
   for (int s4 = 0; s4 < K1q; ++s4) {
     const int k = 4 * s4 + g;
     float b0 = 0.f, bt = 0.f;
-    if (k == 0) b0 = X0;
-    else if (k == 1) b0 = X1;
-    else if (k == 2) b0 = X2;
+    if (k < 3) b0 = (k == 0) ? tp.X[0] : (k == 1) ? tp.X[1] : tp.X[2];
     else if (k < 3 + r && jb.zrows != nullptr) {
-      b0 = jb.zrows[(int64_t)(valid ? p : jb.n - 1) * r + (k - 3)];
+      b0 = jb.zrows[(int64_t)(tp.valid ? tp.p : jb.n - 1) * r + (k - 3)];
     } else if (k < 3 + r) {
       const double zk = jb.z[k - 3];
       if (jvp) {
@@ -310,9 +309,34 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
       acc[0][mb] = mfma16(a, b0, acc[0][mb]);
 #pragma unroll
       for (int t = 1; t < T; ++t)
-        if (t <= nt) acc[t][mb] = mfma16(a, jvp ? bt : ((k == 3 + t0 + t - 1) ? 1.f : 0.f), acc[t][mb]);
+        if (t <= NT) acc[t][mb] = mfma16(a, jvp ? bt : ((k == 3 + t0 + t - 1) ? 1.f : 0.f), acc[t][mb]);
     }
   }
+}
+
+// One wave evaluates a 16-point tile of a job, starting at point p0: the primal plus
+// tangents [t0, t0 + nt). Two ways to hold the hidden-layer weights:
+//  - streamed (RES = false): the WPG waves of a workgroup run tiles of the same job in
+//    step; layers stream through two LDS buffers, layer k + 1 (or the next group's first
+//    hidden layer) fetched while layer k computes, with a workgroup barrier per layer;
+//  - resident (RES = true, BF16 decode): all four hidden layers sit in LDS for the whole
+//    kernel, and waves run their tiles independently, without barriers.
+// Returns after the output layer.
+template <int W, int NT, bool BF, int WPG, bool RES = false, class NextFn>
+__device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, NextFn&& next,
+                                            char* lds, int wave, int lane) {
+  constexpr int MB = W / 16;
+  constexpr int T = 1 + NT;
+  constexpr int nt = NT;  // compile-time: no per-MFMA guards
+  constexpr int LB = HiddenLayer<W, BF>::kBytes;
+  const int g = lane >> 4;
+  const TilePoint tp = tile_point(jb, p0, lane);
+  const int p = tp.p;
+  const bool valid = tp.valid;
+  const int r = jb.r;
+  const bool jvp = jb.jvp != 0;
+  f32x4 acc[T][MB];
+  layer1_16<W, T, NT>(jb, tp, t0, lane, acc);
   if constexpr (NT == 0) save_preact16<W, T>(jb, acc, 0, p, valid, g);
 
   // Hidden layers 2..5 (k = 0..3). Streamed: wait for layer k in LDS, then start fetching
@@ -373,7 +397,7 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
     for (int o = 0; o < d; ++o) {
       const float y = output_dot16<W>(jb.w.w6q, o, g, H[0]) + jb.w.b6[o];
       float v = jb.scale[o] * y + jb.shift[o];
-      if (jb.mode == 1) v += (o == 0) ? X0 : (o == 1) ? X1 : X2;
+      if (jb.mode == 1) v += ((o == 0) ? tp.X[0] : (o == 1) ? tp.X[1] : tp.X[2]);
       if (valid && g == (o & 3)) jb.out[o * jb.ldo + p] = v;
     }
   }
@@ -386,6 +410,182 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
       for (int t = 1; t < T; ++t) {
         const float y = output_dot16<W>(jb.w.w6q, c, g, H[t]);
         if (valid && g == c) jb.jac[(c * r + t0 + t - 1) * jb.ldj + p] = jb.scale[c] * y;
+      }
+    }
+  }
+}
+
+// ---- reverse-mode Jacobian ----------------------------------------------------------
+// For a Jacobian with many latent columns the tangent groups above recompute the primal
+// once per TC columns. Reverse mode instead runs the primal once and pulls one output
+// component c back through the layers: delta_5 = W6[c, :] . phi'(a_5),
+// delta_{k-1} = (W_k^T delta_k) . phi'(a_{k-1}), du_c/dz = W1_z^T delta_1, where W1_z are
+// layer 1's latent columns. Each matrix product is the same MFMA pattern as the forward
+// one with the transposed weights (packed in the same operand order), so the cotangent
+// stays in the accumulator layout and phi' of every layer is applied in-lane. A wave keeps
+// phi'(a_1..a_4) of its tile in registers (4 x W/4 floats). One group per output component:
+// a 16-point tile costs two matrix passes per wave instead of 1 + TC per TC latent
+// columns.
+
+// Activation that also keeps phi': FP32 into H, BF16 into Hb (the next layer's operands).
+template <int W, bool BF>
+__device__ __forceinline__ void activate_keep(const f32x4 (&acc)[1][W / 16], float (&H)[1][W / 4],
+                                              bf16x8 (&Hb)[1][BF ? W / 32 : 1], float (&D)[W / 4]) {
+  if constexpr (BF) {
+#pragma unroll
+    for (int s = 0; s < W / 32; ++s) {
+      bf16x8 p0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float y;
+        elu_pair<true>(acc[0][2 * s + (e >> 2)][e & 3], y, D[4 * (2 * s + (e >> 2)) + (e & 3)]);
+        p0[e] = (__bf16)y;
+      }
+      Hb[0][s] = p0;
+    }
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < W / 16; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) elu_pair<false>(acc[0][mb][v], H[0][4 * mb + v], D[4 * mb + v]);
+  }
+}
+
+// Cotangent acc . D into the next product's operands (FP32 H, or BF16 Hb).
+template <int W, bool BF>
+__device__ __forceinline__ void cotangent_operand(const f32x4 (&acc)[1][W / 16], const float (&D)[W / 4],
+                                                  float (&H)[1][W / 4], bf16x8 (&Hb)[1][BF ? W / 32 : 1]) {
+  if constexpr (BF) {
+#pragma unroll
+    for (int s = 0; s < W / 32; ++s) {
+      bf16x8 p0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int mb = 2 * s + (e >> 2), v = e & 3;
+        p0[e] = (__bf16)(acc[0][mb][v] * D[4 * mb + v]);
+      }
+      Hb[0][s] = p0;
+    }
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < W / 16; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) H[0][4 * mb + v] = acc[0][mb][v] * D[4 * mb + v];
+  }
+}
+
+// One wave: the primal of a 16-point tile (written by the c = 0 group) and row c of its
+// Jacobian, with streamed weights: the four hidden layers, then their transposes in
+// reverse order, through the two LDS buffers with one workgroup barrier per layer.
+template <int W, bool BF, int WPG, class NextFn>
+__device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, NextFn&& next, char* lds,
+                                          int wave, int lane) {
+  constexpr int MB = W / 16;
+  constexpr int LB = HiddenLayer<W, BF>::kBytes;
+  const int g = lane >> 4;
+  const TilePoint tp = tile_point(jb, p0, lane);
+  const int p = tp.p, r = jb.r;
+  const bool valid = tp.valid;
+  f32x4 acc[1][MB];
+  layer1_16<W, 1, 0>(jb, tp, 0, lane, acc);
+  float D[4][W / 4];   // phi'(a_1) .. phi'(a_4)
+  float H[1][W / 4];
+  bf16x8 Hb[1][BF ? W / 32 : 1];
+  activate_keep<W, BF>(acc, H, Hb, D[0]);
+  // stage i = 0..3: hidden layer i; i = 4..7: the transpose of hidden layer 7 - i
+  auto stage = [&](int i) -> const char* {
+    wait_dma_and_sync();
+    if (i < 7) {
+      const int kn = i + 1;
+      dma_layer<W, BF, WPG>(jb.w, kn < 4 ? kn : 7 - kn, lds + (kn & 1) * LB, wave, lane, kn >= 4);
+    } else if (const FieldPack* next_w = next()) {
+      dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
+    }
+    return lds + (i & 1) * LB;
+  };
+  auto product = [&](const char* cur) {
+    if constexpr (BF) hidden16_bf16<W, 1>(acc, Hb, reinterpret_cast<const bf16x8*>(cur), lane, 0);
+    else hidden16<W, 1>(acc, H, reinterpret_cast<const f32x2*>(cur), lane, 0);
+  };
+  // unrolled: D is indexed by the layer, and registers cannot be indexed at run time
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const char* cur = stage(k);
+    init16<W, 1>(acc, jb.w.bhq + k * W, g);
+    product(cur);
+    activate_keep<W, BF>(acc, H, Hb, D[k + 1]);
+  }
+  {
+    const char* cur = stage(3);
+    init16<W, 1>(acc, jb.w.bhq + 3 * W, g);
+    product(cur);
+  }
+  // layer 5: the primal output from FP32 activations, then delta_5 = W6[c, :] . phi'(a_5)
+  // (phi'(a_5) recomputed from a_5, which acc still holds, rather than kept)
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float dy;
+      elu_pair<false>(acc[0][mb][v], H[0][4 * mb + v], dy);
+    }
+  if (c == 0) {
+#pragma unroll 1
+    for (int o = 0; o < 3; ++o) {
+      const float y = output_dot16<W>(jb.w.w6q, o, g, H[0]) + jb.w.b6[o];
+      if (valid && g == o) jb.out[o * jb.ldo + p] = jb.scale[o] * y + jb.shift[o];
+    }
+  }
+  {
+    const float* w6 = jb.w.w6q + c * W + 4 * g;
+    float ones[W / 4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const f32x4 w4 = *reinterpret_cast<const f32x4*>(w6 + 16 * mb);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float y, dy;
+        elu_pair<false>(acc[0][mb][v], y, dy);
+        acc[0][mb][v] = w4[v] * dy;
+        ones[4 * mb + v] = 1.f;
+      }
+    }
+    cotangent_operand<W, BF>(acc, ones, H, Hb);
+  }
+  // back through W5^T .. W2^T; delta_1 stays FP32 for the latent columns of layer 1
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const char* cur = stage(4 + j);
+    init16<W, 1>(acc, nullptr, g);
+    product(cur);
+    cotangent_operand<W, BF>(acc, D[3 - j], H, Hb);
+  }
+  {
+    const char* cur = stage(7);
+    init16<W, 1>(acc, nullptr, g);
+    product(cur);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) H[0][4 * mb + v] = acc[0][mb][v] * D[0][4 * mb + v];
+  }
+  // du_c/dz_j = sum_m W1[m][3 + j] delta_1[m], rows j in blocks of 16 (at most two)
+  const int MZ = (r + 15) >> 4;
+  const f32x2* Z = reinterpret_cast<const f32x2*>(jb.w.w1zt);
+  f32x4 jz[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+  for (int mz = 0; mz < 2; ++mz) {
+    if (mz < MZ) {
+#pragma unroll
+      for (int hs = 0; hs < W / 8; ++hs) {
+        const f32x2 a = Z[((size_t)mz * (W / 8) + hs) * 64 + lane];
+        jz[mz] = mfma16(a[0], H[0][2 * hs], jz[mz]);
+        jz[mz] = mfma16(a[1], H[0][2 * hs + 1], jz[mz]);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = 16 * mz + 4 * g + v;
+        if (valid && jj < r) jb.jac[(c * r + jj) * jb.ldj + p] = jb.scale[c] * jz[mz][v];
       }
     }
   }
@@ -435,6 +635,14 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
   };
   while (true) {
     const FieldTile tl = groups[g];
+    if constexpr (TC > 0) {   // reverse-mode Jacobian groups come with the tangent tables
+      if (tl.nt < 0) {
+        run_rev16<W, BF, WPG>(jobs[tl.job], tl.p0 + kTile16 * wave, tl.t0, next, lds, wave, lane);
+        if (gn >= total) break;
+        g = gn;
+        continue;
+      }
+    }
     dispatch_nt<W, TC, BF, WPG>(jobs[tl.job], tl.p0, tl.t0, tl.nt, next, lds, wave, lane);
     if (gn >= total) break;
     g = gn;

@@ -26,6 +26,11 @@ struct FieldPack {
   const float* bhq;      // hidden biases, plain order: [4][W]
   const float* w6q;      // output weights, plain order: [d][W]
   const float* b6;       // output bias [d]
+  // reverse-mode Jacobian (deformation field): transposed hidden layers in the layouts of
+  // whp / whb, and layer 1's latent columns as an r x W matrix [ceil(r/16)][W/8][64][2]
+  const float* whpt;
+  const bf16x8* whbt;
+  const float* w1zt;
 };
 
 // One batch of MLP evaluations: a field at one latent over a list of points.
@@ -54,8 +59,9 @@ struct FieldJob {
 };
 
 // One workgroup's work: WPG consecutive 16-point tiles of a job starting at point p0
-// (wave w takes p0 + 16 w), the primal plus tangents [t0, t0 + nt). Only groups with
-// t0 == 0 write the primal output.
+// (wave w takes p0 + 16 w), the primal plus tangents [t0, t0 + nt) (only groups with
+// t0 == 0 write the primal output), or with nt < 0 the primal and Jacobian row t0 in
+// reverse mode (the t0 == 0 group writes the primal output).
 struct FieldTile {
   int32_t job, p0, t0, nt;
 };

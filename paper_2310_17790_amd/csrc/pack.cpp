@@ -58,7 +58,39 @@ PackSizes pack_sizes(int r, int width, int d) {
   s.w1q = (size_t)(width / 16) * ((r + 7) / 4) * 64;
   s.bhq = (size_t)4 * width;
   s.w6q = (size_t)d * width;
+  s.w1zt = (size_t)((r + 15) / 16) * 16 * width;
   return s;
+}
+
+// A operands of an M x K FP32 matrix A(m, k) for v_mfma_f32_16x16x4_f32, read by the
+// kernels one K-step pair at a time: [ceil(M/16)][K/8][64][2]. Output block mb, pair hs,
+// lane l hold row 16 mb + l % 16 and inputs 16 (hs / 2) + 4 (l / 16) + 2 (hs % 2) + j, i.e.
+// K-steps 2 hs + j read the accumulator registers 2 (hs % 2) + j of M-block hs / 2 that lane
+// group l / 16 holds in the layer before. Rows past M are zero.
+template <class F>
+static void pack_a_f32(F A, int M, int K, float* dst) {
+  const int MB = (M + 15) / 16;
+  for (int mb = 0; mb < MB; ++mb)
+    for (int hs = 0; hs < K / 8; ++hs)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 2; ++j) {
+          const int m = 16 * mb + (l & 15), n = 16 * (hs >> 1) + 4 * (l >> 4) + 2 * (hs & 1) + j;
+          dst[(((size_t)mb * (K / 8) + hs) * 64 + l) * 2 + j] = m < M ? A(m, n) : 0.f;
+        }
+}
+
+// The same for v_mfma_f32_16x16x32_bf16: [M/16][K/32][64][8]; K-step s, lane l hold row
+// 16 mb + l % 16 and inputs 16 (2s + e / 4) + 4 (l / 16) + e % 4 (M-blocks 2s and 2s + 1 of
+// the layer before).
+template <class F>
+static void pack_a_bf16(F A, int M, int K, uint16_t* dst) {
+  for (int mb = 0; mb < M / 16; ++mb)
+    for (int s = 0; s < K / 32; ++s)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+          const int m = 16 * mb + (l & 15), n = 16 * (2 * s + (e >> 2)) + 4 * (l >> 4) + (e & 3);
+          dst[(((size_t)mb * (K / 32) + s) * 64 + l) * 8 + e] = float_to_bf16(A(m, n));
+        }
 }
 
 void pack_field(const float* master, int r, int width, int d, const PackOut& o) {
@@ -75,31 +107,17 @@ void pack_field(const float* master, int r, int width, int d, const PackOut& o) 
         else if (k == in1) val = scaled(v.b1[m], kLog2e);
         o.w1q[((size_t)mb * K1q + s4) * 64 + l] = val;
       }
+  // reverse mode: dJ/dz = W1_z^T delta_1, the latent columns of layer 1 as an r x W matrix
+  if (o.w1zt)
+    pack_a_f32([&](int j, int m) { return scaled(v.W1[(size_t)m * in1 + 3 + j], kLog2e); }, r, W, o.w1zt);
   for (int kk = 0; kk < 4; ++kk) {
     const float* Wk = v.Wh[kk];
-    // FP32 A operands [W/16][W/8][64][2]: output block mb, K-step pair hs, lane l: row
-    // 16 mb + l % 16, inputs 16 (hs / 2) + 4 (l / 16) + 2 (hs % 2) + j (K-steps 2 hs + j read
-    // the accumulator registers 2 (hs % 2) + j of M-block hs / 2 of lane group l / 16 in the
-    // previous layer).
-    float* dst = o.whp + (size_t)kk * W * W;
-    for (int mb = 0; mb < MQ; ++mb)
-      for (int hs = 0; hs < W / 8; ++hs)
-        for (int l = 0; l < 64; ++l)
-          for (int j = 0; j < 2; ++j) {
-            const int m = 16 * mb + (l & 15), n = 16 * (hs >> 1) + 4 * (l >> 4) + 2 * (hs & 1) + j;
-            dst[(((size_t)mb * (W / 8) + hs) * 64 + l) * 2 + j] = Wk[(size_t)m * W + n];
-          }
-    // BF16 A operands [W/16][W/32][64][8]: output block mb, K-step s, lane l: row
-    // 16 mb + l % 16, inputs 16 (2s + e / 4) + 4 (l / 16) + e % 4 (M-blocks 2s and 2s + 1
-    // of the previous layer).
-    uint16_t* dstb = o.whb + (size_t)kk * W * W;
-    for (int mb = 0; mb < MQ; ++mb)
-      for (int s = 0; s < W / 32; ++s)
-        for (int l = 0; l < 64; ++l)
-          for (int e = 0; e < 8; ++e) {
-            const int m = 16 * mb + (l & 15), n = 16 * (2 * s + (e >> 2)) + 4 * (l >> 4) + (e & 3);
-            dstb[(((size_t)mb * (W / 32) + s) * 64 + l) * 8 + e] = float_to_bf16(Wk[(size_t)m * W + n]);
-          }
+    auto fwd = [&](int m, int n) { return Wk[(size_t)m * W + n]; };
+    auto tr = [&](int m, int n) { return Wk[(size_t)n * W + m]; };
+    pack_a_f32(fwd, W, W, o.whp + (size_t)kk * W * W);
+    pack_a_bf16(fwd, W, W, o.whb + (size_t)kk * W * W);
+    if (o.whpt) pack_a_f32(tr, W, W, o.whpt + (size_t)kk * W * W);
+    if (o.whbt) pack_a_bf16(tr, W, W, o.whbt + (size_t)kk * W * W);
     for (int n = 0; n < W; ++n) o.bhq[(size_t)kk * W + n] = scaled(v.bh[kk][n], kLog2e);
   }
   for (int oo = 0; oo < d; ++oo) {

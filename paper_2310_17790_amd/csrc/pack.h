@@ -19,11 +19,14 @@ struct MlpView {
 struct PackSizes {
   size_t w1p, whp, whb, bhp, w6p, b6;  // element counts (whb in bf16 elements)
   size_t w1q, bhq, w6q;
+  size_t w1zt;                         // layer 1's latent columns, transposed (reverse mode)
 };
 
-// The packed arrays of one field (host or device buffers of PackSizes elements).
+// The packed arrays of one field (host or device buffers of PackSizes elements). whpt and
+// whbt are the transposed hidden layers (sizes whp, whb) of the reverse-mode Jacobian.
 struct PackOut {
   float* whp; uint16_t* whb; float* b6; float* w1q; float* bhq; float* w6q;
+  float* whpt; uint16_t* whbt; float* w1zt;
 };
 
 size_t mlp_param_count(int r, int width, int d);
