@@ -65,8 +65,13 @@ def primal_flops(width: int, r: int, d: int) -> int:
 
 
 def tangent_flops(width: int, r: int) -> int:
-    """Forward-mode latent Jacobian of g on top of the primal: r (8 w^2 + 6 w)."""
-    return r * (8 * width * width + 6 * width)
+    """Latent Jacobian of g on top of the primal, in the mode the library runs: forward,
+    r (8 w^2 + 6 w), while it needs at most two tangent groups (r <= 4 at width 128,
+    two tangents per wave), else reverse, 3 (8 w^2 + 2 w r) (three cotangents back through
+    the four hidden layers and the latent columns of layer 1)."""
+    if r <= 2 * (2 if width == 128 else 3):
+        return r * (8 * width * width + 6 * width)
+    return 3 * (8 * width * width + 2 * width * r)
 
 
 def step_flops(width, r, n_int, n_samp, n_part, gn_iters=2):
