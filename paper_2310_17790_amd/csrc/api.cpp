@@ -221,6 +221,7 @@ struct Plan {
   FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tD = nullptr;
   BlockWork *d_bP = nullptr, *d_bGN = nullptr;
   int nA = 0, nG = 0, nD = 0, nP = 0, nGN = 0, nsims = 0;
+  int nAstep = 0, nGnext = 0;     // see build_plan (velocity job moved into the first G pass)
   // launch grids (fixed for persistent plans)
   int gF = 0, gF0 = 0, gP = 0, gGN = 0, gSims = 0, gBlk = 0;
   FieldJob decode_job{};          // single-sim plans decode with the dense kernel
@@ -332,8 +333,14 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   if (P.persistent) P.r_cap = kMaxR;
   std::vector<SimDev> sims;
   std::vector<FieldJob> jobs;
-  std::vector<FieldTile> tA_jac, tA_prim, tG, tD;  // tD: decode groups (primal kernel)
+  std::vector<FieldTile> tA_jac, tA_prim, tA_vel, tG, tG_vel, tD;  // tD: decode groups
   std::vector<BlockWork> bP, bGN;
+  // The FP32 velocity takes g at z_{n-1} on the step's points. Inside a step with at least
+  // one iterate pass, the latent it needs (z_n) is known from the first Gauss-Newton solve
+  // on, so that pass (which leaves part of the device idle) evaluates it for the next
+  // step's points, after this step's P2G has read the buffer. The end-of-step inference
+  // then skips it; a refresh outside a step still runs it at z_{n-1}.
+  const bool vel_in_g = !s0->bf16 && P.gn_iters >= 2;
   for (size_t si = 0; si < P.members.size(); ++si) {
     nsf_sim* s = P.members[si];
     const SimDev& H = s->hd;
@@ -363,7 +370,14 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
       for (int p0 = 0; p0 < N; p0 += fields_group_points(P.tc))
         tA_jac.push_back({(int)jobs.size(), p0, 0, 1});
     } else {
-      add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
+      add_prim_tiles(tA_vel, (int)jobs.size(), N, P.tc);
+      if (vel_in_g) {
+        FieldJob c1 = c;
+        c1.z = zc; c1.step_off = 1;
+        add_prim_tiles(tG_vel, (int)jobs.size() + 1, N, P.tc);
+        jobs.push_back(c);
+        c = c1;
+      }
     }
     jobs.push_back(c);
     FieldJob h = base_job(s, NSF_FIELD_H, zc);
@@ -390,13 +404,22 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     for (int p0 = 0; p0 < N; p0 += kMpmBlock) bP.push_back({(int)si, p0});
     for (int p0 = 0; p0 < S; p0 += kGnChunk) bGN.push_back({(int)si, p0});
   }
-  // Longest groups first: Jacobian groups, then the primal-only groups.
+  // Longest groups first: Jacobian groups, then the primal-only groups; the velocity
+  // groups that a step moves into its first G pass come last in both tables, so the
+  // step's inference and the other G passes run a prefix of them.
   std::vector<FieldTile> tA(tA_jac);
   tA.insert(tA.end(), tA_prim.begin(), tA_prim.end());
+  tA.insert(tA.end(), tA_vel.begin(), tA_vel.end());
+  tG.insert(tG.end(), tG_vel.begin(), tG_vel.end());
   P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nD = (int)tD.size();
+  P.nAstep = P.nA - (vel_in_g ? (int)tA_vel.size() : 0);
+  P.nGnext = P.nG;
+  P.nG -= (int)tG_vel.size();
   P.nP = (int)bP.size(); P.nGN = (int)bGN.size();
   P.nsims = (int)sims.size();
-  std::vector<int32_t> counts = {P.nA, P.nG, 0 /* unused */, P.nP, 0 /* unused */, P.nGN, P.nsims, P.nD,
+  // work counts: [0] step inference, [1] G pass, [2] full inference, [3] MPM blocks,
+  // [4] first G pass, [5] Gauss-Newton chunks, [6] sims, [7] decode groups
+  std::vector<int32_t> counts = {P.nAstep, P.nG, P.nA, P.nP, P.nGnext, P.nGN, P.nsims, P.nD,
                                  0, 0, 0, 0, 0, 0, 0, 0};
   // Regions of the device buffer. A persistent plan keeps fixed region capacities (grown
   // by half when exceeded), so its captured graph stays valid while tables are rewritten.
@@ -457,7 +480,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   const int fcap = cus * fields_table_blocks_per_cu(P.width, P.bf16, P.tc);
   const int fcap0 = cus * fields_table_blocks_per_cu(P.width, P.bf16, 0);
   auto mn = [](int a, int b) { return a < b ? a : b; };
-  P.gF = P.persistent ? fcap : mn(fcap, std::max(P.nA, P.nG));
+  P.gF = P.persistent ? fcap : mn(fcap, std::max(P.nA, P.nGnext));
   P.gF0 = P.persistent ? fcap0 : mn(fcap0, P.nD);
   P.gP = P.persistent ? 4 * cus : P.nP;
   P.gGN = P.persistent ? 4 * cus : P.nGN;
@@ -479,7 +502,7 @@ constexpr int kClaimA = 8, kClaimG = 9, kClaimD = 14;
 // set_latent).
 nsf_status enqueue_inference(Plan& P, hipStream_t s) {
   NSF_HIP(launch_reset_counters(P.d_counts + 8, 8, s));
-  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 2,
                               P.d_counts + kClaimA, std::min(P.gF, std::max(P.nA, 1)), s));
   return NSF_OK;
 }
@@ -513,12 +536,13 @@ nsf_status join_decode(Plan& P, hipStream_t s) {
   return NSF_OK;
 }
 
-// The next step's field inference at the current latent, then (decode = true) the decode
-// of all particles at the same latent, on the same stream: the two persistent kernels fill
-// the device one after the other (run side by side they only contend for the same CUs).
-// Counters must have been reset in this sequence.
-nsf_status enqueue_refresh_body(Plan& P, hipStream_t s, bool decode) {
-  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 0,
+// The next step's field inference at the current latent (in_step: without the groups the
+// step's first G pass ran), then (decode = true) the decode of all particles at the same
+// latent, on the same stream: the two persistent kernels fill the device one after the
+// other (run side by side they only contend for the same CUs). Counters must have been
+// reset in this sequence.
+nsf_status enqueue_refresh_body(Plan& P, hipStream_t s, bool decode, bool in_step) {
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + (in_step ? 0 : 2),
                               P.d_counts + kClaimA, P.gF, s));
   return decode ? launch_decode(P, s, false) : NSF_OK;
 }
@@ -530,7 +554,7 @@ nsf_status enqueue_refresh(Plan& P, hipStream_t s) {
   if (P.pipelined)
     for (nsf_sim* m : P.members)
       NSF_HIP(hipMemcpyAsync(m->hd.zdec, m->hd.z + m->r, (size_t)m->r * 8, hipMemcpyDeviceToDevice, s));
-  return enqueue_refresh_body(P, s, P.decode);
+  return enqueue_refresh_body(P, s, P.decode, false);
 }
 
 // One latent step, given its field inference in the buffers: MPM step, Gauss-Newton
@@ -547,17 +571,17 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
   NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.r_cap, P.gGN, s));
   NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + 1,
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + (k == 1 ? 4 : 1),
                                 P.d_counts + kClaimG + (k - 1), P.gF, s));
     NSF_HIP(launch_gn_partial(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.r_cap, P.gGN, s));
     NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, k, P.gSims, s));
   }
   if (P.decode && P.pipelined) {
-    const nsf_status st = enqueue_refresh_body(P, s, false);
+    const nsf_status st = enqueue_refresh_body(P, s, false, true);
     if (st != NSF_OK) return st;
     return join_decode(P, s);
   }
-  return enqueue_refresh_body(P, s, P.decode);
+  return enqueue_refresh_body(P, s, P.decode, true);
 }
 
 constexpr int kGraphSteps = 8;

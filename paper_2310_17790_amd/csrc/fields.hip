@@ -264,7 +264,7 @@ __device__ __forceinline__ TilePoint tile_point(const FieldJob& jb, int p0, int 
   int gi = jb.p_off + (tp.valid ? tp.p : jb.n - 1);
   if (jb.idx != nullptr) {
     const int32_t* row = jb.idx;
-    if (jb.step != nullptr) row += (*jb.step % jb.plan_steps) * (int64_t)jb.plan_ld;
+    if (jb.step != nullptr) row += ((*jb.step + jb.step_off) % jb.plan_steps) * (int64_t)jb.plan_ld;
     gi = row[gi];
   }
   tp.X[0] = jb.X[gi];

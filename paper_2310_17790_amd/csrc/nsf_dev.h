@@ -39,7 +39,7 @@ struct FieldJob {
   const double* z;           // device latent (r)
   const float* X;            // reference positions SoA, leading dimension ldx
   const int32_t* idx;        // gather list (NULL: point index is the row of X)
-  const int64_t* step;       // if non-NULL, idx += (step mod plan_steps) * plan_ld
+  const int64_t* step;       // if non-NULL, idx += ((step + step_off) mod plan_steps) * plan_ld
   int64_t ldx;
   int32_t plan_steps, plan_ld;
   int32_t p_off;             // point p of this job reads list entry p_off + p
@@ -50,7 +50,7 @@ struct FieldJob {
   const double* z2;          // jvp: evaluate at (z + z2) / 2 with the one tangent along
                              // z - z2, and write scale * (tangent output) * jvp_scale
   float jvp_scale;
-  int32_t pad1;
+  int32_t step_off;          // 1: the points of the step after the counter's (see step)
   const float* zrows;        // training: per-point latents [n][r] instead of z (NULL in the step)
   float* saved;              // training: pre-activations of layers 1..5, [5][n][W] (or NULL)
   float* out; int64_t ldo;   // SoA [d][ldo], already offset to this job's first point
