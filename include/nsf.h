@@ -106,6 +106,13 @@ typedef struct {
                                   latent; nsf_refresh decodes the current latent       */
   const double *z0;            /* host [r]                                                */
   const double *z_prev;        /* host [r] or NULL (then z_{-1} = z_0, zero velocity)     */
+  double gn_damping;           /* lambda >= 0 (at most 1e6): every Gauss-Newton iteration
+                                  solves (J^T J + lambda diag(J^T J)) delta = -J^T r, the
+                                  Levenberg-Marquardt step with Marquardt's scaling, for
+                                  ill-conditioned Jacobians. 0: the plain Gauss-Newton
+                                  step of Sec. 5.3; with gn_iters = 1 that is the
+                                  first-order (linearised) projection Sec. 5.3 offers as a
+                                  speed-up: one solve with the Jacobian at z_n          */
 } nsf_sim_desc;
 
 typedef struct nsf_sim nsf_sim;  /* opaque, owned by the library */

@@ -3,8 +3,14 @@
 z_{n+1} = argmin_z sum_{p in S} || g(X_p, z) - x_p^{n+1} ||^2, solved from z_n by
 Gauss-Newton: at each iterate, with residual r (3|S| entries) and Jacobian J (3|S| x r),
 solve (J^T J) delta = -J^T r by Cholesky and set z <- z + delta. The paper reports
-convergence in 2-3 iterations; the project fixes K = 2 iterations, undamped, with the
-unweighted residual. A non-positive pivot raises SingularSystem.
+convergence in 2-3 iterations and offers a first-order (linearised) projection as a
+speed-up, which is one such solve with the Jacobian at z_n. The residual is unweighted;
+K iterations are a parameter (2 by default). A non-positive pivot raises
+SingularSystem.
+
+Damping (a variant for ill-conditioned Jacobians, not in the paper): Levenberg-Marquardt
+with Marquardt's diagonal scaling, (J^T J + lambda diag(J^T J)) delta = -J^T r. It is the
+minimiser of |J delta + r|^2 + lambda |diag(J^T J)^(1/2) delta|^2.
 """
 from __future__ import annotations
 
@@ -38,9 +44,12 @@ def normal_equations(J: np.ndarray, res: np.ndarray):
     return J.T @ J, J.T @ res
 
 
-def gn_delta(J: np.ndarray, res: np.ndarray) -> np.ndarray:
-    """The Gauss-Newton step delta solving (J^T J) delta = -J^T r."""
+def gn_delta(J: np.ndarray, res: np.ndarray, damping: float = 0.0) -> np.ndarray:
+    """The Gauss-Newton step delta solving (J^T J) delta = -J^T r, or with damping
+    lambda > 0 the Levenberg-Marquardt step (J^T J + lambda diag(J^T J)) delta = -J^T r."""
     H, b = normal_equations(J, res)
+    if damping:
+        H = H + damping * np.diag(np.diag(H))
     L = cholesky_lower(H)
     y = np.linalg.solve(L, -b)          # forward substitution
     return np.linalg.solve(L.T, y)      # back substitution

@@ -81,7 +81,7 @@ class OracleSim:
             res = (self.u(XS, z) - target_u).reshape(-1)
             J = self.jac(XS, z).reshape(-1, z.shape[0])
             try:
-                z = z + gn.gn_delta(J, res)
+                z = z + gn.gn_delta(J, res, getattr(self.w, "gn_damping", 0.0))
             except gn.SingularSystem:
                 self.flags |= self.FLAG_SINGULAR
                 raise

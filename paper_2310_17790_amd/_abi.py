@@ -47,7 +47,8 @@ class nsf_sim_desc(C.Structure):
                 ("n_integration", C.c_int32), ("n_sample", C.c_int32),
                 ("plan_steps", C.c_int32), ("sample_plan", C.POINTER(C.c_int32)),
                 ("gn_iters", C.c_int32), ("decode_every_step", C.c_int32),
-                ("z0", C.POINTER(C.c_double)), ("z_prev", C.POINTER(C.c_double))]
+                ("z0", C.POINTER(C.c_double)), ("z_prev", C.POINTER(C.c_double)),
+                ("gn_damping", C.c_double)]
 
 
 class nsf_mlp(C.Structure):

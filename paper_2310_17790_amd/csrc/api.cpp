@@ -145,6 +145,8 @@ nsf_status validate(const nsf_sim_desc* d) {
   if (!(d->rho > 0) || !(d->body_volume > 0)) return fail(NSF_EINVAL, "rho and body_volume must be positive");
   if (d->wall_nodes < 0 || 2 * d->wall_nodes >= d->grid_n) return fail(NSF_EINVAL, "wall_nodes = %d", d->wall_nodes);
   if (d->gn_iters < 1 || d->gn_iters > 4) return fail(NSF_EINVAL, "gn_iters = %d outside 1..4", d->gn_iters);
+  if (!(d->gn_damping >= 0.0 && d->gn_damping <= 1e6))
+    return fail(NSF_EINVAL, "gn_damping = %g outside [0, 1e6]", d->gn_damping);
   if (d->decode_every_step < 0 || d->decode_every_step > 2)
     return fail(NSF_EINVAL, "decode_every_step = %d (0, 1 or 2)", d->decode_every_step);
   if (!d->z0) return fail(NSF_EINVAL, "z0 is NULL");
@@ -756,6 +758,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.grid_n = d->grid_n;
   H.wall = d->wall_nodes;
   H.gn_iters = d->gn_iters;
+  H.gn_damping = d->gn_damping;
   H.knife_on = d->knife.enabled ? 1 : 0;
   H.n_gn_chunks = ceil_div(d->n_sample, kGnChunk);
   H.width = W;

@@ -4,9 +4,10 @@
 // Iterate k has residual r_p = u(X_p, z^(k)) - u^n_p - dt v^{n+1}_p (3 |S| entries; at
 // k = 0 the first two terms are the same value, so r = -dt v) and Jacobian J (3|S| x r)
 // from the field kernel. The step solves (J^T J) delta = -J^T r by Cholesky and sets
-// z^(k+1) = z^(k) + delta. Everything from the residual on is FP64: J and u enter as the
-// FP32 values the field kernel stored, widened (a product of two FP32 values is exact in
-// FP64).
+// z^(k+1) = z^(k) + delta. Optional damping lambda (Levenberg-Marquardt with Marquardt's
+// scaling) solves (J^T J + lambda diag(J^T J)) delta = -J^T r instead. Everything from
+// the residual on is FP64: J and u enter as the FP32 values the field kernel stored,
+// widened (a product of two FP32 values is exact in FP64).
 //
 // Two launches per iteration.
 //  - the chunk reduction (gn_reduce.h): each block stages 128 sample points of J and r in
@@ -184,6 +185,7 @@ __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* _
         if (is_b) {
           y[j] = -acc;  // right-hand side -J^T r
         } else {
+          if (j == k) acc += S.gn_damping * acc;  // Marquardt: H + lambda diag(H)
           H[j][k] = acc;
           H[k][j] = acc;
         }

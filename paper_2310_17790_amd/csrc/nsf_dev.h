@@ -79,6 +79,7 @@ struct SimDev {
   float stress_k;                    // dt V_p 4 / dx^2
   float grav[3];
   double dt_d, dx_d;
+  double gn_damping;                 // lambda: Gauss-Newton solves use H + lambda diag(H)
   double grav_d[3];
   double kn[3], koff, khalf, kz0, kspeed, kv[3];
   const float* X;                    // [3][n_part]

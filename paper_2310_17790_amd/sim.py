@@ -67,6 +67,7 @@ def build_desc(w, precision: str, decode_every_step: bool):
     d.plan_steps = int(plan.shape[0])
     d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
     d.gn_iters = int(w.gn_iters)
+    d.gn_damping = float(getattr(w, "gn_damping", 0.0))
     d.decode_every_step = int(decode_every_step)   # 0, 1 (True) or 2 (pipelined)
     d.z0 = dptr(w.z0)
     d.z_prev = dptr(w.z_prev) if w.z_prev is not None else None

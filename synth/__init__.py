@@ -126,6 +126,7 @@ class Workload:
     gn_iters: int
     steps: int
     knife: Knife = dataclasses.field(default_factory=Knife)
+    gn_damping: float = 0.0            # Marquardt damping of the Gauss-Newton solves
 
     @property
     def n_particles(self) -> int:

@@ -66,7 +66,8 @@ def test_sim_bytes_and_validation():
     assert nbytes % 256 == 0
     bad = []
     for field, val in [("r", 0), ("r", 33), ("width", 96), ("n_hidden", 4), ("gn_iters", 0),
-                       ("grid_n", 4), ("n_sample", 0), ("wall_nodes", 16)]:
+                       ("grid_n", 4), ("n_sample", 0), ("wall_nodes", 16), ("gn_damping", -1e-3),
+                       ("gn_damping", float("nan")), ("gn_damping", 2e6)]:
         old = getattr(d, field)
         setattr(d, field, val)
         if A.nsf_sim_bytes(d) != 0:

@@ -54,3 +54,53 @@ def test_singular_system_raises():
     assert np.all(J[:, 2] == 0.0)
     with pytest.raises(gn.SingularSystem):
         gn.gn_delta(J, np.ones(J.shape[0]))
+
+
+@pytest.mark.parametrize("lam", [1e-3, 0.5, 10.0])
+def test_damped_step_is_augmented_least_squares(lam):
+    """(J^T J + lambda D) delta = -J^T r with D = diag(J^T J) is the least-squares solution
+    of the stacked system [J; sqrt(lambda D)] delta = [-r; 0] (QR / SVD route of the
+    library, not the normal equations). Column scales spread over three decades so the
+    diagonal scaling matters."""
+    rng = np.random.default_rng(2)
+    J = rng.normal(size=(240, 6)) * np.logspace(-2, 1, 6)[None, :]
+    r = rng.normal(size=240)
+    D = np.diag(J.T @ J)
+    A = np.vstack([J, np.diag(np.sqrt(lam * D))])
+    rhs = np.concatenate([-r, np.zeros(6)])
+    ref = np.linalg.lstsq(A, rhs, rcond=None)[0]
+    np.testing.assert_allclose(gn.gn_delta(J, r, lam), ref, rtol=1e-10, atol=1e-14)
+    # and it differs from the undamped step
+    assert np.abs(gn.gn_delta(J, r, lam) - gn.gn_delta(J, r)).max() > 1e-6 * np.abs(ref).max()
+
+
+def test_heavy_damping_is_a_scaled_gradient_step():
+    """lambda -> infinity: lambda delta -> -D^-1 J^T r, the diagonally scaled steepest
+    descent direction of |J z + r|^2 / 2."""
+    rng = np.random.default_rng(3)
+    J = rng.normal(size=(120, 5))
+    r = rng.normal(size=120)
+    lam = 1e9
+    D = np.diag(J.T @ J)
+    np.testing.assert_allclose(lam * gn.gn_delta(J, r, lam), -(J.T @ r) / D, rtol=1e-7, atol=0)
+
+
+def test_damped_iteration_keeps_the_root():
+    """Damping changes the path, not the fixed point: on a well-conditioned zero-residual
+    problem r(z) = A z + 0.1 sin(B z) - t the damped iteration converges to z* (linearly,
+    about lambda / (1 + lambda) per iteration), while one damped step is only partial."""
+    rng = np.random.default_rng(7)
+    m, r = 90, 6
+    A = rng.normal(size=(m, r))
+    B = rng.normal(size=(m, r))
+    zs = rng.normal(size=r)
+    t = A @ zs + 0.1 * np.sin(B @ zs)
+    z = zs + 0.05 * rng.normal(size=r)
+    errs = []
+    for _ in range(25):
+        res = A @ z + 0.1 * np.sin(B @ z) - t
+        J = A + 0.1 * np.cos(B @ z)[:, None] * B
+        z = z + gn.gn_delta(J, res, 0.1)
+        errs.append(np.linalg.norm(z - zs))
+    assert errs[0] > 1e-3
+    assert errs[-1] <= 1e-12

@@ -9,12 +9,16 @@ from oracle.step import OracleSim, relative_error
 from tests.helpers import affine_manifold
 
 
-def test_affine_manifold_free_fall_closed_form():
+@pytest.mark.parametrize("gn_iters", [1, 2, 3])
+def test_affine_manifold_free_fall_closed_form(gn_iters):
     """With g affine in z (r = 3, invertible latent map), tau = C = 0 and no boundary
     nodes touched, every particle has the same velocity, the grid adds dt*g, and the
-    inversion is exact in one Gauss-Newton iteration. Starting at rest the decoded
-    positions after n steps are X + u(X, z0) + g dt^2 n (n + 1) / 2 (symplectic Euler)."""
+    inversion is exact in one Gauss-Newton iteration, so the first-order projection
+    (gn_iters = 1) is exact too and further iterations change nothing. Starting at rest
+    the decoded positions after n steps are X + u(X, z0) + g dt^2 n (n + 1) / 2
+    (symplectic Euler)."""
     w = affine_manifold(synth.small_cube(seed=0, r=3, width=16, n=256))
+    w.gn_iters = gn_iters
     sim = OracleSim(w)
     x0 = sim.decode()
     n = 6
@@ -23,6 +27,26 @@ def test_affine_manifold_free_fall_closed_form():
     expect = x0 + g[None, :] * w.dt ** 2 * n * (n + 1) / 2
     np.testing.assert_allclose(sim.decode(), expect, rtol=0, atol=1e-12)
     assert sim.flags == 0
+
+
+def test_damping_on_the_affine_manifold_is_a_partial_step():
+    """Counter-check of the damped solve inside the step: on the affine manifold one
+    damped iteration moves the latent by (A^T A + lambda D)^-1 A^T A times the exact
+    step, which is not the exact step, while enough damped iterations reach it."""
+    w = affine_manifold(synth.small_cube(seed=0, r=3, width=16, n=256))
+    exact = OracleSim(w)
+    exact.step(1)
+    w1 = copy.deepcopy(w)
+    w1.gn_iters, w1.gn_damping = 1, 0.5
+    one = OracleSim(w1)
+    one.step(1)
+    d_exact = exact.z - w.z0
+    assert np.abs(one.z - exact.z).max() > 0.1 * np.abs(d_exact).max()
+    w4 = copy.deepcopy(w)
+    w4.gn_iters, w4.gn_damping = 4, 1e-3
+    four = OracleSim(w4)
+    four.step(1)
+    np.testing.assert_allclose(four.z - w.z0, d_exact, rtol=1e-7, atol=1e-14)
 
 
 def test_mass_and_volume_scale_invariance():
