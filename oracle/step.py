@@ -15,11 +15,18 @@ Readings: m_p = rho V_p with V_p = body_volume / |N| (each integration particle 
 for an equal share of the body); z_{-1} = z_0 unless given (zero initial velocity); the
 sample set S_n is the first n_sample entries of the step's index list; the step's list is
 row (n mod plan_steps) of the plan.
+
+With integration = "closure" the sample set S is the first n_sample entries of the plan's
+single row, fixed over time (its size can be reduced between steps, as the paper does
+half-way through the cake), and N_n is the closure of S's stencils at the positions
+g(X, z_n) of all particles (Sec. 5.4, `closure.py`). Each particle then stands for its own
+share of the body, V_p = body_volume / |P|, as in the full-order step it reproduces.
 """
 from __future__ import annotations
 
 import numpy as np
 
+from . import closure
 from . import fields as F
 from . import gn
 from . import mpm
@@ -38,6 +45,13 @@ class OracleSim:
         self.z_prev = np.array(w.z_prev, np.float64)
         self.n = 0
         self.flags = 0
+        self.closure = getattr(w, "integration", "plan") == "closure"
+        self.n_sample = int(w.n_sample)
+
+    def set_sample_count(self, n_sample: int) -> None:
+        """Closure mode: keep the first n_sample sample particles from the next step on."""
+        assert self.closure and 3 * n_sample >= self.z.shape[0] and n_sample <= self.w.plan.shape[1]
+        self.n_sample = int(n_sample)
 
     # -- pieces --------------------------------------------------------------------
     def u(self, X, z):
@@ -47,8 +61,15 @@ class OracleSim:
         return F.jacobian_z(self.w.fields["g"], X, z, self.w.out_scale["g"])
 
     def indices(self, n=None):
+        """The step's integration list (S first). Closure mode: at the current latent."""
+        if self.closure:
+            S = self.w.plan[0][: self.n_sample]
+            return closure.integration_set(self.decode(), S, self.w.grid_n, self.w.dx)
         n = self.n if n is None else n
         return self.w.plan[n % self.w.plan.shape[0]]
+
+    def particle_volume(self, n_integration: int) -> float:
+        return self.w.body_volume / (self.X.shape[0] if self.closure else n_integration)
 
     def inference(self, idx):
         """Sec. 5.1 on the integration particles: x, v, tau, C, u (all FP64)."""
@@ -63,7 +84,7 @@ class OracleSim:
         """Sec. 5.2: one MPM step on N, returning v^{n+1} on S."""
         w = self.w
         nN = x.shape[0]
-        V = np.full(nN, w.body_volume / nN)
+        V = np.full(nN, self.particle_volume(nN))
         m = w.rho * V
         A = mpm.affine_matrix(C, tau, m, V, w.dt, w.dx)
         mass, mom, bad1 = mpm.p2g(x, v, A, m, w.grid_n, w.dx)
@@ -92,7 +113,7 @@ class OracleSim:
         for _ in range(n_steps):
             w = self.w
             idx = self.indices()
-            nS = w.n_sample
+            nS = self.n_sample
             x, v, tau, C, u_n = self.inference(idx)
             v_new = self.mpm_step(x, v, tau, C, nS)
             target_u = u_n[:nS] + w.dt * v_new

@@ -127,6 +127,10 @@ class Workload:
     steps: int
     knife: Knife = dataclasses.field(default_factory=Knife)
     gn_damping: float = 0.0            # Marquardt damping of the Gauss-Newton solves
+    # "plan": N = S = the step's plan row. "closure": S = plan[0][:n_sample], fixed, and N
+    # is the closure of S's stencils each step, with room for closure_cap particles.
+    integration: str = "plan"
+    closure_cap: int = 0
 
     @property
     def n_particles(self) -> int:
@@ -178,6 +182,33 @@ def cake_slab(seed: int = 0, r: int = 6, width: int = 128, n: int = 200_000,
         dt=5e-5, gravity=(0.0, 0.0, -9.8), wall_nodes=3, rho=1.0,
         body_volume=0.3 * 0.3 * 0.15, out_scale=scale, out_shift=shift, gn_iters=2,
         steps=steps, knife=knife)
+
+
+def clustered_samples(seed: int, X: np.ndarray, n: int, center: Sequence[float],
+                      sigma: float) -> np.ndarray:
+    """n distinct particle indices drawn without replacement with weights
+    exp(-|X_p - center|^2 / (2 sigma^2)): a sample set clustered around `center`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d2 = ((np.asarray(X, np.float64).T - np.asarray(center, np.float64)[None, :]) ** 2).sum(1)
+    p = np.exp(-d2 / (2.0 * sigma * sigma))
+    return rng.choice(X.shape[1], size=n, replace=False, p=p / p.sum()).astype(np.int32)
+
+
+def cake_closure(seed: int = 0, r: int = 6, width: int = 128, n: int = 200_000,
+                 n_sample: int = 700, sigma: float = 0.02, closure_cap: int = 32_768,
+                 steps: int = 100, grid_n: int = 128, bias_scale: float = 0.0) -> Workload:
+    """The cake slab with the paper's own integration set: n_sample sample particles
+    clustered around the middle of the slab (fixed over time) and N the closure of their
+    stencils, recomputed every step."""
+    w = cake_slab(seed=seed, r=r, width=width, n=n, n_integration=1, steps=steps, plan_steps=1,
+                  grid_n=grid_n, bias_scale=bias_scale)
+    S = clustered_samples(seed + 5, w.X, n_sample, (0.5, 0.5, 0.125), sigma)
+    w.plan = S[None, :]
+    w.n_sample = n_sample
+    w.integration = "closure"
+    w.closure_cap = closure_cap
+    w.name = f"slab{n}_closure{n_sample}_w{width}_r{r}"
+    return w
 
 
 def served_mix(n_requests: int = 256, seed: int = 4, rate_hz: float = 200.0,
