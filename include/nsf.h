@@ -40,13 +40,29 @@ typedef enum {
   NSF_ENODEV = -4,       /* no gfx950 device is visible                                   */
   NSF_EDOMAIN = -5,      /* sticky: a particle stencil left the grid                      */
   NSF_ESINGULAR = -6,    /* sticky: Gauss-Newton normal matrix had a pivot <= 0           */
-  NSF_ENONFINITE = -7    /* sticky: the latent or the residual became non-finite          */
+  NSF_ENONFINITE = -7,   /* sticky: the latent or the residual became non-finite          */
+  NSF_ECAPACITY = -8     /* sticky: a closure integration set outgrew n_integration       */
 } nsf_status;
 
 typedef enum { NSF_FP32 = 0, NSF_BF16 = 1 } nsf_precision;
 
 /* sticky device status bits, see nsf_status_flags */
-enum { NSF_FLAG_DOMAIN = 1u, NSF_FLAG_NONFINITE = 2u, NSF_FLAG_SINGULAR = 4u };
+enum { NSF_FLAG_DOMAIN = 1u, NSF_FLAG_NONFINITE = 2u, NSF_FLAG_SINGULAR = 4u,
+       NSF_FLAG_CAPACITY = 8u };
+
+/* How the integration particles N of each step are chosen (Sec. 5.4).
+ * NSF_INTEGRATION_PLAN: step n integrates row (n mod plan_steps) of sample_plan, whose first
+ *   n_sample entries are S. Particle volumes are body_volume / n_integration.
+ * NSF_INTEGRATION_CLOSURE: S is fixed (sample_plan holds one row of n_sample distinct
+ *   indices), and each step N is the closure of S's stencils: I = the grid nodes in the
+ *   3 x 3 x 3 B-spline stencil of some p in S, N = S followed by every other particle whose
+ *   in-grid stencil meets I, by ascending index, both at the decoded positions
+ *   x = X + u(X, z_n). Then the MPM step on N gives S the result of a full-order step on
+ *   all particles (Sec. 5.2). n_integration is the capacity of N: a closure that
+ *   outgrows it is truncated and raises NSF_FLAG_CAPACITY. Particle volumes are
+ *   body_volume / n_particles. Requires decode_every_step = 1 (the closure reads the
+ *   decoded positions) and steps alone (not in nsf_step_batch). */
+typedef enum { NSF_INTEGRATION_PLAN = 0, NSF_INTEGRATION_CLOSURE = 1 } nsf_integration;
 
 /* Fields and their output widths (supplementary "Network architecture"): g -> 3
  * (displacement u, x = X + u), h -> 6 (Kirchhoff stress, Voigt xx yy zz yz xz xy),
@@ -92,10 +108,11 @@ typedef struct {
   double gravity[3];
   int32_t wall_nodes;          /* sticky band: nodes with any index < b or >= n - b       */
   nsf_knife knife;
-  int32_t n_integration;       /* |N| per step                                            */
+  int32_t n_integration;       /* |N| per step (closure integration: the capacity of N)   */
   int32_t n_sample;            /* |S| <= |N|; S = first n_sample entries of the step list */
   int32_t plan_steps;          /* rows in sample_plan; step n uses row n mod plan_steps   */
-  const int32_t *sample_plan;  /* host, [plan_steps][n_integration] indices into P        */
+  const int32_t *sample_plan;  /* host, [plan_steps][n_integration] indices into P
+                                  (closure integration: plan_steps = 1, [n_sample] = S)  */
   int32_t gn_iters;            /* Gauss-Newton iterations per step, 1..4 (paper: 2-3)     */
   int32_t decode_every_step;   /* 0: no decode in the step. 1: each step ends by decoding
                                   all P into the decoded-position buffer (nsf_sim_buffer
@@ -113,6 +130,7 @@ typedef struct {
                                   step of Sec. 5.3; with gn_iters = 1 that is the
                                   first-order (linearised) projection Sec. 5.3 offers as a
                                   speed-up: one solve with the Jacobian at z_n          */
+  int32_t integration;         /* nsf_integration (0: plan rows, 1: closure of S)         */
 } nsf_sim_desc;
 
 typedef struct nsf_sim nsf_sim;  /* opaque, owned by the library */
@@ -164,9 +182,16 @@ nsf_status nsf_get_latent(nsf_sim *s, double *z, double *z_prev, int64_t *step, 
 nsf_status nsf_set_latent(nsf_sim *s, const double *z, const double *z_prev, int64_t step,
                           void *stream);
 
+/* Closure integration (Sec. 5.4; the paper's cake halves its sample set half-way): keep
+ * only the first n_sample entries of the sample list from the next step on, async.
+ * 1 <= n_sample <= the n_sample given at creation, 3 n_sample >= r. The next nsf_step
+ * first recomputes the integration set and the field inference for the smaller S at the
+ * current latent. NSF_EINVAL for a plan sim. */
+nsf_status nsf_set_sample_count(nsf_sim *s, int32_t n_sample, void *stream);
+
 /* Read the sticky device flags (synchronises). Returns NSF_OK with *flags = 0, or, with
  * *flags set, the status of the first set condition in the order NONFINITE, SINGULAR,
- * DOMAIN (a non-finite latent also throws particles off the grid). */
+ * DOMAIN, CAPACITY (a non-finite latent also throws particles off the grid). */
 nsf_status nsf_status_flags(nsf_sim *s, uint32_t *flags, void *stream);
 
 /* Inspect a per-step device buffer of the sim (read-only views for tests and callers
@@ -184,9 +209,14 @@ nsf_status nsf_status_flags(nsf_sim *s, uint32_t *flags, void *stream);
  *                   node (i, j, k) at (i grid_n + j) grid_n + k; valid on the node blocks
  *                   the step's particles reach (others hold older values)
  *   NSF_BUF_Z       double [3][r]: z_{n-1}, z_n, last Gauss-Newton iterate
- * Buffers hold the values of the last completed step. */
+ *   NSF_BUF_NLIST   int32 integration lists: [plan_steps][n_integration] (plan), or the
+ *                   current list [n_integration] (closure; entries past its live length
+ *                   are stale)
+ *   NSF_BUF_NLIVE   int32 [1]: live length of the closure list (closure only)
+ * Buffers hold the values of the last completed step; with closure integration the
+ * per-particle buffers (U, UPREV, TAU, C) follow the current list. */
 enum { NSF_BUF_U = 0, NSF_BUF_UPREV, NSF_BUF_TAU, NSF_BUF_C, NSF_BUF_JAC, NSF_BUF_VNEW,
-       NSF_BUF_XDEC, NSF_BUF_GRID, NSF_BUF_Z };
+       NSF_BUF_XDEC, NSF_BUF_GRID, NSF_BUF_Z, NSF_BUF_NLIST, NSF_BUF_NLIVE };
 nsf_status nsf_sim_buffer(nsf_sim *s, int32_t which, void **ptr, int64_t *count);
 
 /* Release host-side state and any captured graphs. The arena stays the caller's. */

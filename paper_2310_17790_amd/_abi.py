@@ -13,18 +13,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnsf.so")
 
 NSF_OK, NSF_EINVAL, NSF_ENOMEM, NSF_EHIP, NSF_ENODEV = 0, -1, -2, -3, -4
-NSF_EDOMAIN, NSF_ESINGULAR, NSF_ENONFINITE = -5, -6, -7
+NSF_EDOMAIN, NSF_ESINGULAR, NSF_ENONFINITE, NSF_ECAPACITY = -5, -6, -7, -8
 NSF_FP32, NSF_BF16 = 0, 1
-NSF_FLAG_DOMAIN, NSF_FLAG_NONFINITE, NSF_FLAG_SINGULAR = 1, 2, 4
+NSF_FLAG_DOMAIN, NSF_FLAG_NONFINITE, NSF_FLAG_SINGULAR, NSF_FLAG_CAPACITY = 1, 2, 4, 8
+NSF_INTEGRATION_PLAN, NSF_INTEGRATION_CLOSURE = 0, 1
 NSF_FIELD_G, NSF_FIELD_H, NSF_FIELD_L = 0, 1, 2
 (NSF_BUF_U, NSF_BUF_UPREV, NSF_BUF_TAU, NSF_BUF_C, NSF_BUF_JAC, NSF_BUF_VNEW, NSF_BUF_XDEC,
- NSF_BUF_GRID, NSF_BUF_Z) = range(9)
+ NSF_BUF_GRID, NSF_BUF_Z, NSF_BUF_NLIST, NSF_BUF_NLIVE) = range(11)
 
 STATUS_NAMES = {0: "NSF_OK", -1: "NSF_EINVAL", -2: "NSF_ENOMEM", -3: "NSF_EHIP", -4: "NSF_ENODEV",
-                -5: "NSF_EDOMAIN", -6: "NSF_ESINGULAR", -7: "NSF_ENONFINITE"}
+                -5: "NSF_EDOMAIN", -6: "NSF_ESINGULAR", -7: "NSF_ENONFINITE", -8: "NSF_ECAPACITY"}
 
 EXPORTED = ["nsf_sim_bytes", "nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_refresh", "nsf_decode",
-            "nsf_get_latent", "nsf_set_latent", "nsf_status_flags", "nsf_sim_buffer",
+            "nsf_get_latent", "nsf_set_latent", "nsf_set_sample_count", "nsf_status_flags", "nsf_sim_buffer",
             "nsf_destroy_sim", "nsf_last_error", "nsf_device_count", "nsf_mlp_param_count",
             "nsf_mlp_saved_floats", "nsf_mlp_workspace_bytes", "nsf_mlp_forward",
             "nsf_mlp_backward"]
@@ -48,7 +49,7 @@ class nsf_sim_desc(C.Structure):
                 ("plan_steps", C.c_int32), ("sample_plan", C.POINTER(C.c_int32)),
                 ("gn_iters", C.c_int32), ("decode_every_step", C.c_int32),
                 ("z0", C.POINTER(C.c_double)), ("z_prev", C.POINTER(C.c_double)),
-                ("gn_damping", C.c_double)]
+                ("gn_damping", C.c_double), ("integration", C.c_int32)]
 
 
 class nsf_mlp(C.Structure):
@@ -83,6 +84,7 @@ def lib() -> C.CDLL:
         L.nsf_get_latent.argtypes = [vp, vp, vp, vp, vp]
         L.nsf_set_latent.argtypes = [vp, vp, vp, i64, vp]
         L.nsf_status_flags.argtypes = [vp, C.POINTER(C.c_uint32), vp]
+        L.nsf_set_sample_count.argtypes = [vp, i32, vp]
         L.nsf_sim_buffer.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64)]
         L.nsf_destroy_sim.argtypes = [vp]
         L.nsf_last_error.argtypes = []
@@ -151,6 +153,10 @@ def nsf_set_latent(sim: int, z, z_prev, step: int, stream: int) -> None:
     za = (C.c_double * r)(*[float(v) for v in z])
     zpa = (C.c_double * r)(*[float(v) for v in z_prev]) if z_prev is not None else None
     check(lib().nsf_set_latent(sim, za, zpa, step, stream or None))
+
+
+def nsf_set_sample_count(sim: int, n_sample: int, stream: int) -> None:
+    check(lib().nsf_set_sample_count(sim, n_sample, stream or None))
 
 
 def nsf_status_flags(sim: int, stream: int):

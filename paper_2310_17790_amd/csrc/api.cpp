@@ -60,10 +60,14 @@ struct Layout {
   size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, zdec, step, flags, gn_part;
   size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active,
       nonempty, n_active;
+  size_t node_mask, is_sample, member, cl_block, n_live;   // closure integration only
   size_t total;
 };
 
 int gn_entries(int r) { return r * (r + 1) / 2 + r; }
+// node bitmask of a closure sim: one bit per node plus a pad word (the membership test
+// reads two consecutive words)
+size_t mask_words(int grid_n) { return ((size_t)grid_n * grid_n * grid_n + 31) / 32 + 1; }
 // P2G bins: cubes of bin_edge^3 cells, at most 32 per axis
 int bin_edge(int grid_n) { return grid_n <= 128 ? 4 : 8; }
 int bins_per_axis(int grid_n) { return (grid_n + bin_edge(grid_n) - 1) / bin_edge(grid_n); }
@@ -118,6 +122,13 @@ Layout make_layout(const nsf_sim_desc* d) {
   L.active = c.take(nb * 4);
   L.nonempty = c.take(nb * 4);
   L.n_active = c.take(8);
+  if (d->integration == NSF_INTEGRATION_CLOSURE) {
+    L.node_mask = c.take((mask_words(d->grid_n)) * 4);
+    L.is_sample = c.take((size_t)P);
+    L.member = c.take((size_t)P);
+    L.cl_block = c.take((size_t)ceil_div(P, 1024) * 4);
+    L.n_live = c.take(4);
+  }
   L.total = c.off;
   return L;
 }
@@ -149,14 +160,29 @@ nsf_status validate(const nsf_sim_desc* d) {
     return fail(NSF_EINVAL, "gn_damping = %g outside [0, 1e6]", d->gn_damping);
   if (d->decode_every_step < 0 || d->decode_every_step > 2)
     return fail(NSF_EINVAL, "decode_every_step = %d (0, 1 or 2)", d->decode_every_step);
+  if (d->integration != NSF_INTEGRATION_PLAN && d->integration != NSF_INTEGRATION_CLOSURE)
+    return fail(NSF_EINVAL, "integration = %d (0 plan, 1 closure)", d->integration);
+  const bool closure = d->integration == NSF_INTEGRATION_CLOSURE;
+  if (closure) {
+    if (d->plan_steps != 1) return fail(NSF_EINVAL, "closure integration takes one sample row (plan_steps = 1)");
+    if (d->decode_every_step != 1)
+      return fail(NSF_EINVAL, "closure integration needs decode_every_step = 1 (it reads the decoded positions)");
+  }
   if (!d->z0) return fail(NSF_EINVAL, "z0 is NULL");
   for (int j = 0; j < d->r; ++j)
     if (!std::isfinite(d->z0[j]) || (d->z_prev && !std::isfinite(d->z_prev[j])))
       return fail(NSF_EINVAL, "initial latent is not finite");
-  const int64_t cnt = (int64_t)d->plan_steps * d->n_integration;
+  const int64_t cnt = closure ? d->n_sample : (int64_t)d->plan_steps * d->n_integration;
   for (int64_t i = 0; i < cnt; ++i)
     if (d->sample_plan[i] < 0 || d->sample_plan[i] >= d->n_particles)
       return fail(NSF_EINVAL, "sample_plan[%lld] = %d out of range", (long long)i, d->sample_plan[i]);
+  if (closure) {
+    std::vector<uint8_t> seen((size_t)d->n_particles, 0);
+    for (int64_t i = 0; i < cnt; ++i) {
+      if (seen[d->sample_plan[i]]) return fail(NSF_EINVAL, "sample particle %d listed twice", d->sample_plan[i]);
+      seen[d->sample_plan[i]] = 1;
+    }
+  }
   return NSF_OK;
 }
 
@@ -191,6 +217,8 @@ struct nsf_sim {
   int64_t n_part = 0;
   int n_int = 0, n_samp = 0, gn_iters = 2;
   int decode_mode = 0;    // decode_every_step: 0, 1 or 2 (pipelined)
+  bool closure = false;   // integration set = closure of the sample stencils
+  std::vector<int32_t> samples;   // closure: the sample list given at creation
   char* arena = nullptr;
   size_t arena_bytes = 0;
   Layout L{};
@@ -213,6 +241,7 @@ struct Plan {
   int width = 0, gn_iters = 0, tc = 0;
   int r_cap = kMaxR;             // largest latent the Gauss-Newton chunk kernels serve
   bool bf16 = false, decode = false, pipelined = false, persistent = false;
+  bool closure = false;           // its one member rebuilds its integration set every step
   void* dbuf = nullptr;
   size_t dcap = 0;
   void* staging = nullptr;        // pinned host copy of the tables (persistent plans)
@@ -328,6 +357,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.gn_iters = s0->gn_iters;
   P.decode = s0->decode_mode != 0;
   P.pipelined = s0->decode_mode == 2;
+  P.closure = s0->closure;
   P.tc = fields_max_tangents(P.width, P.bf16);
   // a persistent plan's graph outlives its members: its chunk kernels take the largest size
   P.r_cap = 1;
@@ -342,7 +372,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   // on, so that pass (which leaves part of the device idle) evaluates it for the next
   // step's points, after this step's P2G has read the buffer. The end-of-step inference
   // then skips it; a refresh outside a step still runs it at z_{n-1}.
-  const bool vel_in_g = !s0->bf16 && P.gn_iters >= 2;
+  const bool vel_in_g = !s0->bf16 && P.gn_iters >= 2 && !s0->closure;
   for (size_t si = 0; si < P.members.size(); ++si) {
     nsf_sim* s = P.members[si];
     const SimDev& H = s->hd;
@@ -352,6 +382,8 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     const double* zi = H.z + 2 * s->r;
     const int N = s->n_int, S = s->n_samp, r = s->r;
     const int j0 = (int)jobs.size();
+    // closure sims: the jobs over N stop at the list's live length
+    const int32_t* live = s->closure ? H.n_live : nullptr;
     // inference: g with its Jacobian on S, g on N \ S, velocity, h, l
     FieldJob a = base_job(s, NSF_FIELD_G, zc);
     a.n = S; a.out = H.u_n; a.ldo = N; a.jac = H.J; a.ldj = S;
@@ -359,12 +391,12 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     add_tiles(tA_jac, j0, S, r, P.tc);
     if (N > S) {
       FieldJob b = base_job(s, NSF_FIELD_G, zc);
-      b.n = N - S; b.p_off = S; b.out = H.u_n + S; b.ldo = N;
+      b.n = N - S; b.p_off = S; b.out = H.u_n + S; b.ldo = N; b.live = live;
       add_prim_tiles(tA_prim, (int)jobs.size(), N - S, P.tc);
       jobs.push_back(b);
     }
     FieldJob c = base_job(s, NSF_FIELD_G, zp);
-    c.n = N; c.out = H.u_prev; c.ldo = N;
+    c.n = N; c.out = H.u_prev; c.ldo = N; c.live = live;
     if (H.tangent_forms) {
       // velocity as the directional derivative at the midpoint:
       // v = J((z_n + z_{n-1}) / 2) (z_n - z_{n-1}) / dt
@@ -383,11 +415,11 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     }
     jobs.push_back(c);
     FieldJob h = base_job(s, NSF_FIELD_H, zc);
-    h.n = N; h.out = H.tau; h.ldo = N;
+    h.n = N; h.out = H.tau; h.ldo = N; h.live = live;
     add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
     jobs.push_back(h);
     FieldJob l = base_job(s, NSF_FIELD_L, zc);
-    l.n = N; l.out = H.C; l.ldo = N;
+    l.n = N; l.out = H.C; l.ldo = N; l.live = live;
     add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
     jobs.push_back(l);
     // Gauss-Newton iterate: g and its Jacobian on S
@@ -500,10 +532,24 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
 // Gauss-Newton iterate pass k, 13 refresh (inference + decode), 14 decode alone.
 constexpr int kClaimA = 8, kClaimG = 9, kClaimD = 14;
 
+nsf_status launch_decode(Plan& P, hipStream_t s, bool beside);
+
+// Closure sims: the integration set from the decoded positions (the decode runs first).
+nsf_status enqueue_closure(Plan& P, hipStream_t s) {
+  for (nsf_sim* m : P.members)
+    if (m->closure) NSF_HIP(launch_closure(m->dd, m->n_samp, m->n_part, s));
+  return NSF_OK;
+}
+
 // Field inference of the step for the current latent, alone (prologue after create or
-// set_latent).
+// set_latent; a closure sim decodes and builds its integration set first).
 nsf_status enqueue_inference(Plan& P, hipStream_t s) {
   NSF_HIP(launch_reset_counters(P.d_counts + 8, 8, s));
+  if (P.closure) {
+    nsf_status st = launch_decode(P, s, false);
+    if (st == NSF_OK) st = enqueue_closure(P, s);
+    if (st != NSF_OK) return st;
+  }
   NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 2,
                               P.d_counts + kClaimA, std::min(P.gF, std::max(P.nA, 1)), s));
   return NSF_OK;
@@ -544,6 +590,14 @@ nsf_status join_decode(Plan& P, hipStream_t s) {
 // other (run side by side they only contend for the same CUs). Counters must have been
 // reset in this sequence.
 nsf_status enqueue_refresh_body(Plan& P, hipStream_t s, bool decode, bool in_step) {
+  if (P.closure) {   // decode, then the integration set at the new positions, then the inference
+    nsf_status st = launch_decode(P, s, false);
+    if (st == NSF_OK) st = enqueue_closure(P, s);
+    if (st != NSF_OK) return st;
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + (in_step ? 0 : 2),
+                                P.d_counts + kClaimA, P.gF, s));
+    return NSF_OK;
+  }
   NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + (in_step ? 0 : 2),
                               P.d_counts + kClaimA, P.gF, s));
   return decode ? launch_decode(P, s, false) : NSF_OK;
@@ -683,6 +737,8 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   sim->n_samp = d->n_sample;
   sim->gn_iters = d->gn_iters;
   sim->decode_mode = d->decode_every_step;
+  sim->closure = d->integration == NSF_INTEGRATION_CLOSURE;
+  if (sim->closure) sim->samples.assign(d->sample_plan, d->sample_plan + d->n_sample);
   sim->arena = static_cast<char*>(arena);
   sim->arena_bytes = arena_bytes;
   sim->L = L;
@@ -730,8 +786,22 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   }
   const int64_t P = d->n_particles;
   NSF_HIP(hipMemcpyAsync(A + L.X, d->X, (size_t)3 * P * 4, hipMemcpyHostToDevice, s));
-  NSF_HIP(hipMemcpyAsync(A + L.plan, d->sample_plan, (size_t)d->plan_steps * d->n_integration * 4,
-                         hipMemcpyHostToDevice, s));
+  std::vector<int32_t> list0;
+  std::vector<uint8_t> is_s;
+  if (sim->closure) {
+    // the list starts as S; entries past its live length only ever hold valid indices
+    list0.assign((size_t)d->n_integration, d->sample_plan[0]);
+    std::copy(d->sample_plan, d->sample_plan + d->n_sample, list0.begin());
+    NSF_HIP(hipMemcpyAsync(A + L.plan, list0.data(), list0.size() * 4, hipMemcpyHostToDevice, s));
+    is_s.assign((size_t)P, 0);
+    for (int i = 0; i < d->n_sample; ++i) is_s[d->sample_plan[i]] = 1;
+    NSF_HIP(hipMemcpyAsync(A + L.is_sample, is_s.data(), is_s.size(), hipMemcpyHostToDevice, s));
+    NSF_HIP(hipMemsetAsync(A + L.node_mask, 0, mask_words(d->grid_n) * 4, s));
+    NSF_HIP(hipMemcpyAsync(A + L.n_live, &d->n_sample, 4, hipMemcpyHostToDevice, s));
+  } else {
+    NSF_HIP(hipMemcpyAsync(A + L.plan, d->sample_plan, (size_t)d->plan_steps * d->n_integration * 4,
+                           hipMemcpyHostToDevice, s));
+  }
   std::vector<double> z(3 * r);
   for (int j = 0; j < r; ++j) {
     z[j] = d->z_prev ? d->z_prev[j] : d->z0[j];
@@ -764,7 +834,9 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.width = W;
   H.tangent_forms = sim->bf16 ? 1 : 0;
   H.pipelined_decode = sim->decode_mode == 2 ? 1 : 0;
-  const double Vp = d->body_volume / d->n_integration;
+  // each integration particle stands for an equal share of the body (plan), or for its
+  // own share, as in the full-order step the closure reproduces
+  const double Vp = d->body_volume / (sim->closure ? (double)d->n_particles : (double)d->n_integration);
   H.dx = (float)d->dx;
   H.inv_dx = (float)(1.0 / d->dx);
   H.dt = (float)d->dt;
@@ -814,6 +886,16 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.active = reinterpret_cast<int32_t*>(A + L.active);
   H.nonempty = reinterpret_cast<int32_t*>(A + L.nonempty);
   H.n_active = reinterpret_cast<int32_t*>(A + L.n_active);
+  if (sim->closure) {
+    H.closure = 1;
+    H.mask_words = (int32_t)mask_words(d->grid_n);
+    H.nlist = reinterpret_cast<int32_t*>(A + L.plan);
+    H.n_live = reinterpret_cast<int32_t*>(A + L.n_live);
+    H.node_mask = reinterpret_cast<uint32_t*>(A + L.node_mask);
+    H.is_sample = reinterpret_cast<uint8_t*>(A + L.is_sample);
+    H.member = reinterpret_cast<uint8_t*>(A + L.member);
+    H.cl_block = reinterpret_cast<int32_t*>(A + L.cl_block);
+  }
   sim->dd = reinterpret_cast<SimDev*>(A + L.simdev);
   NSF_HIP(hipMemcpyAsync(sim->dd, &H, sizeof(SimDev), hipMemcpyHostToDevice, s));
   NSF_HIP(hipStreamSynchronize(s));
@@ -843,6 +925,7 @@ nsf_status nsf_step_batch(nsf_sim* const* sims, int32_t n, int32_t n_steps, void
   std::vector<nsf_sim*> key(sims, sims + n);
   for (int i = 0; i < n; ++i) {
     if (!key[i]) return fail(NSF_EINVAL, "sims[%d] is NULL", i);
+    if (key[i]->closure) return fail(NSF_EINVAL, "sims[%d] uses closure integration, which steps alone", i);
     if (key[i]->width != key[0]->width || key[i]->bf16 != key[0]->bf16 ||
         key[i]->gn_iters != key[0]->gn_iters || key[i]->decode_mode != key[0]->decode_mode)
       return fail(NSF_EINVAL, "sims[%d] differs in width, precision, gn_iters or decode mode", i);
@@ -932,6 +1015,28 @@ nsf_status nsf_refresh(nsf_sim* s, void* stream) {
   return e;
 }
 
+nsf_status nsf_set_sample_count(nsf_sim* s, int32_t n_sample, void* stream) {
+  if (!s) return fail(NSF_EINVAL, "sim is NULL");
+  if (!s->closure) return fail(NSF_EINVAL, "the sample count changes only with closure integration");
+  if (n_sample < 1 || n_sample > (int32_t)s->samples.size())
+    return fail(NSF_EINVAL, "n_sample = %d outside 1..%zu", n_sample, s->samples.size());
+  if (3 * n_sample < s->r) return fail(NSF_EINVAL, "n_sample = %d < r / 3: the inversion is under-determined", n_sample);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  NSF_HIP(hipStreamSynchronize(st));   // no step of the old plan is in flight
+  drop_batch_plans_with(s);
+  s->solo.reset();
+  s->n_samp = n_sample;
+  s->hd.n_samp = n_sample;
+  s->hd.n_gn_chunks = ceil_div(n_sample, kGnChunk);
+  std::vector<uint8_t> is_s((size_t)s->n_part, 0);
+  for (int i = 0; i < n_sample; ++i) is_s[s->samples[i]] = 1;
+  NSF_HIP(hipMemcpyAsync(s->hd.is_sample, is_s.data(), is_s.size(), hipMemcpyHostToDevice, st));
+  NSF_HIP(hipMemcpyAsync(s->dd, &s->hd, sizeof(SimDev), hipMemcpyHostToDevice, st));
+  NSF_HIP(hipStreamSynchronize(st));
+  s->inference_ready = false;
+  return NSF_OK;
+}
+
 nsf_status nsf_status_flags(nsf_sim* s, uint32_t* flags, void* stream) {
   if (!s || !flags) return fail(NSF_EINVAL, "sim or flags is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -942,6 +1047,7 @@ nsf_status nsf_status_flags(nsf_sim* s, uint32_t* flags, void* stream) {
   if (f & FLAG_NONFINITE) return fail(NSF_ENONFINITE, "the latent or the residual became non-finite");
   if (f & FLAG_SINGULAR) return fail(NSF_ESINGULAR, "Gauss-Newton normal matrix is not positive definite");
   if (f & FLAG_DOMAIN) return fail(NSF_EDOMAIN, "a particle stencil left the grid");
+  if (f & FLAG_CAPACITY) return fail(NSF_ECAPACITY, "the integration set outgrew n_integration and was truncated");
   return NSF_OK;
 }
 
@@ -959,6 +1065,15 @@ nsf_status nsf_sim_buffer(nsf_sim* s, int32_t which, void** ptr, int64_t* count)
     case NSF_BUF_XDEC: *ptr = H.xdec; *count = 3 * P; break;
     case NSF_BUF_GRID: *ptr = H.grid; *count = (int64_t)4 * H.grid_n * H.grid_n * H.grid_n; break;
     case NSF_BUF_Z: *ptr = H.z; *count = 3 * r; break;
+    case NSF_BUF_NLIST:
+      *ptr = const_cast<int32_t*>(H.plan);
+      *count = (int64_t)H.plan_steps * N;
+      break;
+    case NSF_BUF_NLIVE:
+      if (!s->closure) return fail(NSF_EINVAL, "NSF_BUF_NLIVE needs closure integration");
+      *ptr = H.n_live;
+      *count = 1;
+      break;
     default: return fail(NSF_EINVAL, "unknown buffer %d", which);
   }
   return NSF_OK;

@@ -43,7 +43,11 @@ struct Stencil {
   bool ok;
 };
 
+// Every operation rounds to FP32 on its own (no contraction into FMAs), so the stencil
+// base, which decides membership in the integration set, is a reproducible function of
+// the FP32 position.
 __device__ __forceinline__ Stencil make_stencil(const float x[3], float inv_dx, int n) {
+#pragma clang fp contract(off)
   Stencil st;
   st.ok = true;
 #pragma unroll
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(kMpmBlock) void bin_kernel(const SimDev* __restrict
       if (S.pipelined_decode && (int)threadIdx.x < S.r) S.zdec[threadIdx.x] = S.z[S.r + threadIdx.x];
     }
     const int p = wk.p0 + threadIdx.x;
-    if (p >= S.n_int) continue;
+    if (p >= live_count(S)) continue;
     float x[3];
     particle_x(S, p, plan_row(S)[p], x);
     const Stencil st = make_stencil(x, S.inv_dx, S.grid_n);
@@ -159,7 +163,7 @@ __global__ __launch_bounds__(kAllocThreads) void alloc_place_kernel(const SimDev
   const int tid = threadIdx.x;
   for (int s = blockIdx.x; s < *n_sims; s += gridDim.x) {
     const SimDev& S = sims[s];
-    const int n = S.n_int, nb = S.n_bins, nbs = S.nbs;
+    const int n = live_count(S), nb = S.n_bins, nbs = S.nbs;
     const int nwords = (nb + 31) / 32;
     for (int wd = tid; wd < nwords; wd += kAllocThreads) mark[wd] = 0u;
     // Thread t owns particles t, t + T, t + 2T, ... (coalesced); the first particle of each
@@ -538,7 +542,103 @@ __global__ __launch_bounds__(kGnThreads) void g2p_gn_kernel(const SimDev* __rest
   }
 }
 
+// ---- integration set: closure of the sample stencils (Sec. 5.4) ----------------------
+// One closure sim per launch. Its integration list holds the samples in its first n_samp
+// entries (they never move) and the other members after them, by ascending particle
+// index. Positions are the decoded x = X + u(X, z_n) of every particle.
+
+__device__ __forceinline__ void decoded_x(const SimDev& S, int p, float x[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x[c] = S.xdec[(int64_t)c * S.n_part + p];
+}
+
+// a. I = the stencil nodes of the sample particles (a stencil that leaves the grid marks
+// nothing; the MPM step flags that particle).
+__global__ __launch_bounds__(kAllocThreads) void closure_mark_kernel(const SimDev* __restrict__ sim) {
+  const SimDev& S = *sim;
+  const int n = S.grid_n;
+  for (int q = blockIdx.x * kAllocThreads + threadIdx.x; q < S.n_samp; q += gridDim.x * kAllocThreads) {
+    float x[3];
+    decoded_x(S, S.nlist[q], x);
+    const Stencil st = make_stencil(x, S.inv_dx, n);
+    if (!st.ok) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int node = ((st.base[0] + a) * n + st.base[1] + b) * n + st.base[2] + c;
+          atomicOr(&S.node_mask[node >> 5], 1u << (node & 31));
+        }
+  }
+}
+
+// b. The particles other than the samples whose in-grid stencil meets I: a flag per
+// particle and a count per workgroup. The three nodes of a stencil row are consecutive
+// bits, read as one 64-bit window (the mask has a pad word at its end).
+__global__ __launch_bounds__(kAllocThreads) void closure_member_kernel(const SimDev* __restrict__ sim) {
+  const SimDev& S = *sim;
+  const int n = S.grid_n;
+  const int p = blockIdx.x * kAllocThreads + threadIdx.x;
+  int m = 0;
+  if (p < S.n_part && !S.is_sample[p]) {
+    float x[3];
+    decoded_x(S, p, x);
+    const Stencil st = make_stencil(x, S.inv_dx, n);
+    if (st.ok) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const int node = ((st.base[0] + a) * n + st.base[1] + b) * n + st.base[2];
+          const uint64_t win = (uint64_t)S.node_mask[node >> 5] | ((uint64_t)S.node_mask[(node >> 5) + 1] << 32);
+          m |= ((win >> (node & 31)) & 7u) != 0;
+        }
+    }
+  }
+  if (p < S.n_part) S.member[p] = (uint8_t)m;
+  const int cnt = __syncthreads_count(m);
+  if (threadIdx.x == 0) S.cl_block[blockIdx.x] = cnt;
+}
+
+// c. The members go after the samples in ascending index (workgroup offsets from the
+// counts of the workgroups before it, then a workgroup scan); entries beyond the list's
+// capacity are dropped and flagged. The last workgroup writes the live length; the mask
+// is cleared for the next step.
+__global__ __launch_bounds__(kAllocThreads) void closure_write_kernel(const SimDev* __restrict__ sim) {
+  __shared__ int wave_sums[kAllocThreads / 64];
+  const SimDev& S = *sim;
+  const int tid = threadIdx.x;
+  int before = 0;
+  for (int b = tid; b < (int)blockIdx.x; b += kAllocThreads) before += S.cl_block[b];
+  int base;
+  (void)block_exclusive_scan(before, wave_sums, &base);
+  const int p = blockIdx.x * kAllocThreads + tid;
+  const int m = p < S.n_part ? S.member[p] : 0;
+  int here;
+  const int pos = block_exclusive_scan(m, wave_sums, &here);
+  const int slot = S.n_samp + base + pos;
+  if (m) {
+    if (slot < S.n_int) S.nlist[slot] = p;
+    else flag(S, FLAG_CAPACITY);
+  }
+  if (blockIdx.x == gridDim.x - 1 && tid == 0) *S.n_live = min(S.n_samp + base + here, S.n_int);
+  for (int w = blockIdx.x * kAllocThreads + tid; w < S.mask_words; w += gridDim.x * kAllocThreads)
+    S.node_mask[w] = 0u;
+}
+
 }  // namespace
+
+hipError_t launch_closure(const SimDev* sim, int n_samp, int64_t n_part, hipStream_t s) {
+  if (n_samp < 1 || n_part < 1) return hipErrorInvalidValue;
+  const int blocks = (int)((n_part + kAllocThreads - 1) / kAllocThreads);
+  hipLaunchKernelGGL(closure_mark_kernel, dim3((n_samp + kAllocThreads - 1) / kAllocThreads), dim3(kAllocThreads), 0,
+                     s, sim);
+  hipLaunchKernelGGL(closure_member_kernel, dim3(blocks), dim3(kAllocThreads), 0, s, sim);
+  hipLaunchKernelGGL(closure_write_kernel, dim3(blocks), dim3(kAllocThreads), 0, s, sim);
+  return hipGetLastError();
+}
 
 hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
                       int32_t* claims, int grid_particles, hipStream_t s) {

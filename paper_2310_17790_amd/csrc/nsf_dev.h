@@ -44,6 +44,8 @@ struct FieldJob {
   int32_t plan_steps, plan_ld;
   int32_t p_off;             // point p of this job reads list entry p_off + p
   int32_t n;                 // number of points
+  const int32_t* live;       // if non-NULL, only list entries below *live are evaluated (the
+                             // integration list of a closure sim changes length per step)
   int32_t r, d;
   int32_t mode;              // 0: out = field; 1: out = X + field (decode)
   int32_t jvp;               // 1: directional derivative job (see z2)
@@ -113,9 +115,21 @@ struct SimDev {
   int32_t* active;                   // [n_bins] node blocks that receive mass this step
   int32_t* nonempty;                 // [n_bins] bins holding particles this step
   int32_t* n_active;                 // [2]: active node blocks, non-empty bins
+  // closure integration set (closure = 1): the integration list `nlist` (the plan's single
+  // row, samples first) is rebuilt every step from the decoded positions
+  int32_t closure, mask_words;
+  int32_t* nlist;                    // [n_int] writable alias of plan
+  int32_t* n_live;                   // [1] live length of nlist (NULL: n_int, fixed)
+  uint32_t* node_mask;               // [mask_words] grid nodes in a sample stencil (+1 pad word)
+  uint8_t* is_sample;                // [n_part]
+  uint8_t* member;                   // [n_part] member of N \ S this step
+  int32_t* cl_block;                 // [ceil(n_part / 1024)] members per workgroup
 };
 
-enum : uint32_t { FLAG_DOMAIN = 1u, FLAG_NONFINITE = 2u, FLAG_SINGULAR = 4u };
+// Integration particles this step: the live length of a closure list, else n_int.
+__device__ __forceinline__ int live_count(const SimDev& S) { return S.n_live ? *S.n_live : S.n_int; }
+
+enum : uint32_t { FLAG_DOMAIN = 1u, FLAG_NONFINITE = 2u, FLAG_SINGULAR = 4u, FLAG_CAPACITY = 8u };
 
 // Work item of a per-particle MPM kernel or a Gauss-Newton reduction block.
 struct BlockWork {
@@ -153,5 +167,8 @@ hipError_t launch_gn_partial(const SimDev* sims, const BlockWork* work, const in
                              int iter, int r_cap, int grid, hipStream_t s);
 hipError_t launch_gn_solve(const SimDev* sims, const int32_t* n_sims, int iter, int grid_sims,
                            hipStream_t s);
+// Integration set of one closure sim from its decoded positions: mark the samples' stencil
+// nodes, flag and count the members, write the list and its live length.
+hipError_t launch_closure(const SimDev* sim, int n_samp, int64_t n_part, hipStream_t s);
 
 }  // namespace nsf

@@ -64,6 +64,10 @@ def build_desc(w, precision: str, decode_every_step: bool):
     plan = np.ascontiguousarray(w.plan, np.int32)
     keep.append(plan)
     d.n_integration, d.n_sample = int(plan.shape[1]), int(w.n_sample)
+    if getattr(w, "integration", "plan") == "closure":
+        # one row of sample indices; n_integration is the capacity of the closure list
+        d.integration = A.NSF_INTEGRATION_CLOSURE
+        d.n_integration = int(w.closure_cap)
     d.plan_steps = int(plan.shape[0])
     d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
     d.gn_iters = int(w.gn_iters)
@@ -92,7 +96,8 @@ class Sim:
         self.r = int(w.r)
         self.width = int(w.width)
         self.n_particles = int(w.X.shape[1])
-        self.n_integration = int(w.plan.shape[1])
+        self.closure = getattr(w, "integration", "plan") == "closure"
+        self.n_integration = int(w.closure_cap) if self.closure else int(w.plan.shape[1])
         self.n_sample = int(w.n_sample)
         self.grid_n = int(w.grid_n)
         self.precision = precision
@@ -151,6 +156,19 @@ class Sim:
         A.nsf_set_latent(self.handle, list(z), None if z_prev is None else list(z_prev), step,
                          _stream_handle(stream))
 
+    def set_sample_count(self, n_sample: int, stream=None) -> None:
+        """Closure integration: keep the first n_sample sample particles from the next step."""
+        A.nsf_set_sample_count(self.handle, int(n_sample), _stream_handle(stream))
+        self.n_sample = int(n_sample)
+
+    def integration_list(self, stream=None) -> np.ndarray:
+        """The current integration list (closure: its live part; plan: all rows)."""
+        lst = self.buffer(A.NSF_BUF_NLIST)
+        if not self.closure:
+            return lst.cpu().numpy()
+        n = int(self.buffer(A.NSF_BUF_NLIVE).cpu().numpy()[0])
+        return lst[:n].cpu().numpy()
+
     def flags(self, stream=None) -> Tuple[int, int]:
         """(status, flag bits) of the sticky device flags."""
         return A.nsf_status_flags(self.handle, _stream_handle(stream))
@@ -160,7 +178,8 @@ class Sim:
         ptr, count = A.nsf_sim_buffer(self.handle, which)
         off = ptr - self.arena.data_ptr()
         esize = 8 if which == A.NSF_BUF_Z else 4
-        dtype = torch.float64 if which == A.NSF_BUF_Z else torch.float32
+        dtype = (torch.float64 if which == A.NSF_BUF_Z else
+                 torch.int32 if which in (A.NSF_BUF_NLIST, A.NSF_BUF_NLIVE) else torch.float32)
         return self.arena[off:off + count * esize].view(dtype)
 
     def close(self) -> None:

@@ -115,3 +115,33 @@ def test_null_arguments_are_rejected():
     assert L.nsf_destroy_sim(None) == A.NSF_OK
     arr = (C.c_void_p * 1)(None)
     assert L.nsf_step_batch(arr, 0, 1, None) == A.NSF_EINVAL
+
+
+def test_closure_descriptor_validation():
+    """Closure integration: one sample row of distinct indices, decode every step, and an
+    integration mode the library knows; its arena holds the node mask and flags."""
+    from paper_2310_17790_amd.sim import build_desc
+    w = synth.cake_closure(seed=0, r=6, width=64, n=2000, n_sample=10, sigma=0.03,
+                           closure_cap=1024, grid_n=32)
+    d, keep = build_desc(w, "fp32", True)
+    n_closure = A.nsf_sim_bytes(d)
+    assert n_closure > 0, A.nsf_last_error()
+    # the node mask alone is 32^3 bits
+    d.integration = A.NSF_INTEGRATION_PLAN
+    d.n_integration = 10
+    assert 0 < A.nsf_sim_bytes(d) < n_closure - 32 ** 3 // 8
+    d.integration = A.NSF_INTEGRATION_CLOSURE
+    d.n_integration = 1024
+    for field, val in [("plan_steps", 2), ("decode_every_step", 0), ("decode_every_step", 2),
+                       ("integration", 5)]:
+        old = getattr(d, field)
+        setattr(d, field, val)
+        assert A.nsf_sim_bytes(d) == 0, field
+        assert A.nsf_last_error() != ""
+        setattr(d, field, old)
+    dup = np.array(w.plan[0], np.int32)
+    dup[3] = dup[2]
+    keep.append(dup)
+    d.sample_plan = dup.ctypes.data_as(C.POINTER(C.c_int32))
+    assert A.nsf_sim_bytes(d) == 0
+    assert "twice" in A.nsf_last_error()

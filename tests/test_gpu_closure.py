@@ -1,0 +1,126 @@
+"""Closure integration sets (Sec. 5.4) on the GPU, through the C ABI, against the oracle.
+
+The list is index work, so it is compared entry for entry. The membership decision is
+taken on float32 positions on both sides: the oracle builds the list from the GPU's own
+decoded positions with the float32 stencil rule (`oracle.closure.integration_set_f32`).
+The trajectory runs the oracle's closure step, which takes the decision on its FP64
+positions. A particle can only change sides where its stencil base flips, and there its
+B-spline weight on the node that decides it is ~0. So the trajectory keeps the FP32
+gate (delta_x <= 1e-5) and the BF16 gate (1e-4).
+"""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle.closure import integration_set_f32
+from oracle.step import OracleSim, relative_error
+from paper_2310_17790_amd import _abi as A
+from paper_2310_17790_amd.sim import Sim, step_batch
+
+pytestmark = pytest.mark.gpu
+
+
+def _soa(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _workload(cap=8192, n_sample=40):
+    w = synth.cake_closure(seed=3, r=6, width=64, n=20_000, n_sample=n_sample, sigma=0.02,
+                           closure_cap=cap, steps=8, grid_n=64, bias_scale=0.05)
+    w.z_prev = w.z0 - 2e-3 * np.random.default_rng(8).normal(size=w.r)
+    return w
+
+
+def _expected_list(sim, w, n_sample):
+    x32 = sim.buffer(A.NSF_BUF_XDEC).cpu().numpy().reshape(3, -1).T
+    return integration_set_f32(x32, w.plan[0][:n_sample], w.grid_n, np.float32(1.0 / w.dx))
+
+
+def test_closure_list_matches_oracle_each_step():
+    w = _workload()
+    print("\n[case] closure list parity n=20000 S=40 grid=64", flush=True)
+    s = torch.cuda.Stream()
+    sim = Sim(w, stream=s)
+    sim.refresh(stream=s)
+    s.synchronize()
+    for k in range(4):
+        got = sim.integration_list()
+        ref = _expected_list(sim, w, w.n_sample)
+        print(f"step {k}: |N| = {len(got)} (oracle {len(ref)})", flush=True)
+        assert 40 < len(ref) < w.closure_cap
+        np.testing.assert_array_equal(got, ref)
+        sim.step(1, stream=s)
+        s.synchronize()
+    assert sim.flags(stream=s) == (0, 0)
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_closure_trajectory_with_shrinking_samples(precision):
+    """5 steps against the oracle's closure step, the sample set halved after step 2 (as
+    the paper's cake does half-way); the list after the change follows the new S."""
+    w = _workload()
+    print(f"\n[case] closure trajectory {precision}", flush=True)
+    s = torch.cuda.Stream()
+    sim = Sim(w, precision=precision, stream=s)
+    o = OracleSim(w)
+    gate = 1e-5 if precision == "fp32" else 1e-4
+    for k in range(5):
+        if k == 2:
+            sim.set_sample_count(20, stream=s)
+            o.set_sample_count(20)
+        sim.step(1, stream=s)
+        o.step(1)
+        s.synchronize()
+        xg = _soa(sim.buffer(A.NSF_BUF_XDEC)).reshape(3, -1).T
+        d = relative_error(xg, o.decode())
+        zg, _, st = sim.latent(stream=s)
+        print(f"step {k + 1}: delta_x={d:.2e} dz={np.abs(zg - o.z).max():.2e} |N|={len(sim.integration_list())}",
+              flush=True)
+        assert st == k + 1
+        assert d <= gate
+    np.testing.assert_array_equal(sim.integration_list(), _expected_list(sim, w, 20))
+    assert sim.flags(stream=s) == (0, 0)
+    sim.close()
+
+
+def test_closure_capacity_truncates_and_flags():
+    """A capacity below the closure keeps its first entries, sets the live length to the
+    capacity and raises the CAPACITY flag (NSF_ECAPACITY from the status call)."""
+    w = _workload(cap=3000)
+    print("\n[case] closure capacity 3000", flush=True)
+    s = torch.cuda.Stream()
+    sim = Sim(w, stream=s)
+    sim.refresh(stream=s)
+    s.synchronize()
+    ref = _expected_list(sim, w, w.n_sample)
+    assert len(ref) > 3000
+    got = sim.integration_list()
+    np.testing.assert_array_equal(got, ref[:3000])
+    st, bits = sim.flags(stream=s)
+    assert bits == A.NSF_FLAG_CAPACITY and st == A.NSF_ECAPACITY
+    sim.close()
+
+
+def test_closure_api_errors():
+    """A plan sim has no sample count to change; closure sims do not batch; the sample
+    count stays within 3 |S| >= r and the size given at creation."""
+    wp = synth.small_cube(seed=1, r=3, width=64, n=64)
+    s = torch.cuda.Stream()
+    plan_sim = Sim(wp, stream=s)
+    with pytest.raises(A.NsfError):
+        plan_sim.set_sample_count(10, stream=s)
+    w = _workload()
+    sim = Sim(w, stream=s)
+    with pytest.raises(A.NsfError):
+        sim.set_sample_count(1, stream=s)      # 3 * 1 < r = 6
+    with pytest.raises(A.NsfError):
+        sim.set_sample_count(41, stream=s)     # more than at creation
+    other = Sim(copy.deepcopy(w), stream=s)
+    with pytest.raises(A.NsfError):
+        step_batch([sim, other], 1, stream=s)
+    for x in (plan_sim, sim, other):
+        x.close()
