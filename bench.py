@@ -22,6 +22,10 @@ The headline value is the plain FP32 single instance. The same line carries, und
     step, HBM budget half the total demand): aggregate latent steps/s and decoded
     points/s from first arrival to last retirement, p50/p99 of the per-step latency every
     request sees (its tick's device time), admission waits.
+  closure_fp32, closure_bf16: the paper's own cake set-up: 700 sample particles clustered
+    around the middle of the same slab, the integration particles the closure of their
+    stencils recomputed every step (Sec. 5.4), the sample set cut to its first 400
+    half-way; per phase latent steps/s, step latency and the closure's size.
 """
 from __future__ import annotations
 
@@ -158,6 +162,33 @@ def single_leg(precision, r, K, W, stream, torch, synth, A, Sim, width=128, P=20
                         "avg_ms": dec_ms}), wl
 
 
+def closure_leg(precision, K, W, stream, torch, synth, Sim):
+    """The cake with closure integration: S = 700 clustered samples for K timed steps, then
+    the first 400 of them for K more (each phase timed as in time_steps)."""
+    wl = synth.cake_closure(seed=0, r=6, width=128, n=200_000, n_sample=700, sigma=0.012,
+                            closure_cap=32_768, steps=4 * K + 2 * W)
+    sim = Sim(wl, precision=precision, stream=stream)
+    sim.step(max(W, 1), stream=stream)
+    stream.synchronize()
+    phases, wall_total = {}, 0.0
+    for n_s in (700, 400):
+        if n_s != 700:
+            sim.set_sample_count(n_s, stream=stream)
+            sim.step(max(W, 1), stream=stream)
+            stream.synchronize()
+        wall, lat = time_steps(sim, K, stream, torch)
+        wall_total += wall
+        phases[f"samples_{n_s}"] = dict(
+            steps_per_s=K / wall, ms_per_step=1e3 * wall / K,
+            p50_step_ms=float(np.percentile(lat, 50)), p99_step_ms=float(np.percentile(lat, 99)),
+            n_integration=int(len(sim.integration_list())))
+    status, flags = sim.flags(stream=stream)
+    sim.close()
+    return dict(steps_per_s=2 * K / wall_total, ms_per_step=1e3 * wall_total / (2 * K),
+                decoded_pts_per_s=2 * K / wall_total * 200_000, phases=phases,
+                device_status=status, device_flags=flags)
+
+
 def served_leg(n_requests, steps, budget_frac, torch, synth):
     """The continuous-batching server (BF16) over the Poisson request stream."""
     from paper_2310_17790_amd.serve import GpuBackend, Request, Server
@@ -215,7 +246,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="bf16_r6,bf16_r24,fp32_pipelined,bf16_pipelined,served_bf16,fit_bf16",
+    ap.add_argument("--legs", default="bf16_r6,bf16_r24,fp32_pipelined,bf16_pipelined,served_bf16,fit_bf16,"
+                                      "closure_fp32,closure_bf16",
                     help="comma-separated extra legs ('' for none)")
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--served-steps", type=int, default=1000)
@@ -278,6 +310,10 @@ def main() -> int:
             legs[name] = leg
         elif name == "fit_bf16":
             legs[name] = fit_leg(10, torch)
+        elif name in ("closure_fp32", "closure_bf16"):
+            leg = closure_leg(name[-4:], K, W, stream, torch, synth, Sim)
+            leg["vs_fp32_single"] = {"steps_per_s": leg["steps_per_s"] / main_leg["steps_per_s"]}
+            legs[name] = leg
         elif name == "served_bf16":
             leg = served_leg(args.served_requests, args.served_steps, args.served_budget, torch, synth)
             leg["vs_fp32_single"] = {"latent_steps_per_s": leg["latent_steps_per_s"] / main_leg["steps_per_s"],
