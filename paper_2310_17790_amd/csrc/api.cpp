@@ -240,8 +240,10 @@ struct Plan {
   std::vector<nsf_sim*> members;
   int width = 0, gn_iters = 0, tc = 0;
   int r_cap = kMaxR;             // largest latent the Gauss-Newton chunk kernels serve
+  int grid_cap = 256;            // largest grid_n the P2G kernels serve
   bool bf16 = false, decode = false, pipelined = false, persistent = false;
   bool closure = false;           // its one member rebuilds its integration set every step
+  ListJobs list_jobs{};           // closure: the jobs over the integration list
   void* dbuf = nullptr;
   size_t dcap = 0;
   void* staging = nullptr;        // pinned host copy of the tables (persistent plans)
@@ -363,6 +365,9 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.r_cap = 1;
   for (nsf_sim* m : P.members) P.r_cap = std::max(P.r_cap, m->r);
   if (P.persistent) P.r_cap = kMaxR;
+  P.grid_cap = 8;
+  for (nsf_sim* m : P.members) P.grid_cap = std::max(P.grid_cap, m->hd.grid_n);
+  if (P.persistent) P.grid_cap = 256;
   std::vector<SimDev> sims;
   std::vector<FieldJob> jobs;
   std::vector<FieldTile> tA_jac, tA_prim, tA_vel, tG, tG_vel, tD;  // tD: decode groups
@@ -382,8 +387,9 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     const double* zi = H.z + 2 * s->r;
     const int N = s->n_int, S = s->n_samp, r = s->r;
     const int j0 = (int)jobs.size();
-    // closure sims: the jobs over N stop at the list's live length
-    const int32_t* live = s->closure ? H.n_live : nullptr;
+    // closure sims: the jobs over N take their point counts from the list each step
+    ListJobs lj{};
+    auto over_list = [&](int job) { if (s->closure) lj.idx[lj.n++] = job; };
     // inference: g with its Jacobian on S, g on N \ S, velocity, h, l
     FieldJob a = base_job(s, NSF_FIELD_G, zc);
     a.n = S; a.out = H.u_n; a.ldo = N; a.jac = H.J; a.ldj = S;
@@ -391,12 +397,14 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     add_tiles(tA_jac, j0, S, r, P.tc);
     if (N > S) {
       FieldJob b = base_job(s, NSF_FIELD_G, zc);
-      b.n = N - S; b.p_off = S; b.out = H.u_n + S; b.ldo = N; b.live = live;
+      b.n = N - S; b.p_off = S; b.out = H.u_n + S; b.ldo = N;
       add_prim_tiles(tA_prim, (int)jobs.size(), N - S, P.tc);
+      over_list((int)jobs.size());
       jobs.push_back(b);
     }
     FieldJob c = base_job(s, NSF_FIELD_G, zp);
-    c.n = N; c.out = H.u_prev; c.ldo = N; c.live = live;
+    c.n = N; c.out = H.u_prev; c.ldo = N;
+    over_list((int)jobs.size() + (vel_in_g ? 1 : 0));
     if (H.tangent_forms) {
       // velocity as the directional derivative at the midpoint:
       // v = J((z_n + z_{n-1}) / 2) (z_n - z_{n-1}) / dt
@@ -415,12 +423,15 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     }
     jobs.push_back(c);
     FieldJob h = base_job(s, NSF_FIELD_H, zc);
-    h.n = N; h.out = H.tau; h.ldo = N; h.live = live;
+    h.n = N; h.out = H.tau; h.ldo = N;
     add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
+    over_list((int)jobs.size());
     jobs.push_back(h);
     FieldJob l = base_job(s, NSF_FIELD_L, zc);
-    l.n = N; l.out = H.C; l.ldo = N; l.live = live;
+    l.n = N; l.out = H.C; l.ldo = N;
     add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
+    over_list((int)jobs.size());
+    if (s->closure) P.list_jobs = lj;
     jobs.push_back(l);
     // Gauss-Newton iterate: g and its Jacobian on S
     FieldJob g = base_job(s, NSF_FIELD_G, zi);
@@ -537,7 +548,7 @@ nsf_status launch_decode(Plan& P, hipStream_t s, bool beside);
 // Closure sims: the integration set from the decoded positions (the decode runs first).
 nsf_status enqueue_closure(Plan& P, hipStream_t s) {
   for (nsf_sim* m : P.members)
-    if (m->closure) NSF_HIP(launch_closure(m->dd, m->n_samp, m->n_part, s));
+    if (m->closure) NSF_HIP(launch_closure(m->dd, m->n_samp, m->n_part, P.d_jobs, P.list_jobs, s));
   return NSF_OK;
 }
 
@@ -623,7 +634,7 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
     const nsf_status st = fork_decode(P, s);
     if (st != NSF_OK) return st;
   }
-  NSF_HIP(launch_p2g_after_bin(P.d_sims, P.d_counts + 6, P.gSims, P.gBlk, s));
+  NSF_HIP(launch_p2g_after_bin(P.d_sims, P.d_counts + 6, P.gSims, P.gBlk, P.closure, P.grid_cap, s));
   NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.r_cap, P.gGN, s));
   NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {

@@ -260,7 +260,7 @@ struct TilePoint {
 __device__ __forceinline__ TilePoint tile_point(const FieldJob& jb, int p0, int lane) {
   TilePoint tp;
   tp.p = p0 + (lane & 15);
-  tp.valid = tp.p < jb.n && (jb.live == nullptr || jb.p_off + tp.p < *jb.live);
+  tp.valid = tp.p < jb.n;
   int gi = jb.p_off + (tp.valid ? tp.p : jb.n - 1);
   if (jb.idx != nullptr) {
     const int32_t* row = jb.idx;
@@ -635,9 +635,9 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
   };
   while (true) {
     const FieldTile tl = groups[g];
-    const FieldJob& jg = jobs[tl.job];
-    if (jg.live != nullptr && jg.p_off + tl.p0 >= *jg.live) {
-      // past this step's integration list: keep the weight pipeline going for the next group
+    if (tl.p0 >= jobs[tl.job].n) {
+      // past the job's points this step (a closure sim's list is shorter than its
+      // capacity): keep the weight pipeline going for the next group
       wait_dma_and_sync();
       if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
       if (gn >= total) break;

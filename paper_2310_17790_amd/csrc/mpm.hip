@@ -17,13 +17,14 @@
 //            listed as non-empty and the node blocks its particles reach are marked in an
 //            LDS bitmap, which is then compacted into the list of active node blocks;
 //            finally every particle writes its index at its bin's slot + rank;
-//   sort     one wave per non-empty bin sorts the bin's indices and writes the P2G
+//   sort     one workgroup per non-empty bin sorts the bin's indices and writes the P2G
 //            records (x, m v, A, index) in that order;
-//   gather   one workgroup per active node block stages the records of the 2 x 2 x 2 bins
-//            whose particles reach it in LDS, sums every node's mass and momentum in that
-//            order (deterministic: where each bin's slots lie does not matter, only the
-//            sorted order inside a bin and the fixed order of the bins), applies the grid
-//            update and stores the node's new velocity;
+//   gather   one workgroup per active node block stages, window by window, the records of
+//            the 2 x 2 x 2 bins whose particles can reach it whose stencil does reach it,
+//            in LDS, sums every node's mass and momentum in that order (deterministic:
+//            where each bin's slots lie does not matter, only the sorted order inside a
+//            bin and the fixed order of the bins), applies the grid update and stores the
+//            node's new velocity;
 //   g2p      each sample particle sums w_ip v_i over its 27 stencil nodes, and the block
 //            reduces its chunk of the first Gauss-Newton system (gn_reduce.h).
 // A node block only holds values written this step; nodes outside active blocks are never
@@ -280,13 +281,15 @@ __device__ __forceinline__ void write_record(const SimDev& S, int p, float* r) {
   r4[3] = make_float4(A[6], A[7], A[8], __int_as_float(p));
 }
 
-// One 64-thread workgroup per non-empty bin: sort the bin's particle indices (in
+// One workgroup per non-empty bin: sort the bin's particle indices (in the first wave's
 // registers up to 64, in LDS up to kSegMax; a larger bin keeps its arrival order) and
-// write the records in that order.
-__global__ __launch_bounds__(64) void bin_sort_kernel(const SimDev* __restrict__ sims,
-                                                      const int32_t* __restrict__ n_sims) {
+// write the records in that order, four waves at a time (a dense integration set has
+// hundreds of particles per bin).
+constexpr int kSortThreads = 256;
+__global__ __launch_bounds__(kSortThreads) void bin_sort_kernel(const SimDev* __restrict__ sims,
+                                                                const int32_t* __restrict__ n_sims) {
   __shared__ int s_buf[kSegMax];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int total_sims = *n_sims;
   const SimShare sh(total_sims);
   for (int s = sh.first; s < total_sims; s += sh.groups) {
@@ -298,22 +301,24 @@ __global__ __launch_bounds__(64) void bin_sort_kernel(const SimDev* __restrict__
       const int cnt = S.seg_cnt[b];
       int32_t* seg = S.sorted + start;
       if (cnt <= 64) {
-        int v = lane < cnt ? seg[lane] : 0x7fffffff;
-        for (int kk = 2; kk <= 64; kk <<= 1)
-          for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            const int o = __shfl_xor(v, jj);
-            const bool lower = (lane & jj) == 0, up = (lane & kk) == 0;
-            v = (lower == up) ? min(v, o) : max(v, o);
-          }
-        if (lane < cnt) write_record(S, v, S.rec + (int64_t)(start + lane) * 16);
+        if (tid < 64) {
+          int v = lane < cnt ? seg[lane] : 0x7fffffff;
+          for (int kk = 2; kk <= 64; kk <<= 1)
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+              const int o = __shfl_xor(v, jj);
+              const bool lower = (lane & jj) == 0, up = (lane & kk) == 0;
+              v = (lower == up) ? min(v, o) : max(v, o);
+            }
+          if (lane < cnt) write_record(S, v, S.rec + (int64_t)(start + lane) * 16);
+        }
       } else if (cnt <= kSegMax) {
         int p2 = 64;
         while (p2 < cnt) p2 <<= 1;
-        for (int i = lane; i < p2; i += 64) s_buf[i] = i < cnt ? seg[i] : 0x7fffffff;
+        for (int i = tid; i < p2; i += kSortThreads) s_buf[i] = i < cnt ? seg[i] : 0x7fffffff;
         __syncthreads();
         for (int kk = 2; kk <= p2; kk <<= 1)
           for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int i = lane; i < p2; i += 64) {
+            for (int i = tid; i < p2; i += kSortThreads) {
               const int l = i ^ jj;
               if (l > i) {
                 const int a = s_buf[i], c = s_buf[l];
@@ -322,18 +327,20 @@ __global__ __launch_bounds__(64) void bin_sort_kernel(const SimDev* __restrict__
             }
             __syncthreads();
           }
-        for (int i = lane; i < cnt; i += 64) write_record(S, s_buf[i], S.rec + (int64_t)(start + i) * 16);
+        for (int i = tid; i < cnt; i += kSortThreads) write_record(S, s_buf[i], S.rec + (int64_t)(start + i) * 16);
         __syncthreads();
       } else {
-        for (int i = lane; i < cnt; i += 64) write_record(S, seg[i], S.rec + (int64_t)(start + i) * 16);
+        for (int i = tid; i < cnt; i += kSortThreads) write_record(S, seg[i], S.rec + (int64_t)(start + i) * 16);
       }
     }
   }
 }
 
 // ---- gather + grid update ----------------------------------------------------------
-constexpr int kGatherThreads = 256;   // 4 groups of 64 lanes
-constexpr int kGatherStage = 256;     // records staged in LDS at a time (~30 KB: 5 blocks per CU)
+// T threads (T / 64 groups of 64 lanes) per workgroup, and a window of T records staged
+// in LDS at a time (~30 KB at T = 256: 5 workgroups per CU). A plan sim's sparse blocks
+// use T = 256; a closure sim's dense blocks (hundreds of records per bin) T = 512.
+constexpr int kGatherThreads = 256, kGatherThreadsDense = 512;
 constexpr int kMaxNodesPerLane = 8;   // bin_edge <= 8
 
 // New velocity of node (i, j, k) from its mass and momentum (grid update + boundaries).
@@ -355,18 +362,23 @@ __device__ __forceinline__ void node_velocity(const SimDev& S, float m, const fl
   }
 }
 
-__global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __restrict__ sims,
-                                                                const int32_t* __restrict__ n_sims) {
+// NPL: nodes per lane the kernel provides for (1 for 4^3-node blocks, grids up to 128^3;
+// kMaxNodesPerLane for any grid); the accumulators of unused nodes cost registers.
+template <int T, int NPL>
+__global__ __launch_bounds__(T) void gather_kernel(const SimDev* __restrict__ sims,
+                                                  const int32_t* __restrict__ n_sims) {
+  constexpr int NG = T / 64;   // lane groups
   // staged records, structure of arrays
-  __shared__ float s_mv[3][kGatherStage];
-  __shared__ float s_A[9][kGatherStage];
-  __shared__ float s_w[9][kGatherStage];
-  __shared__ float s_f[3][kGatherStage];
-  __shared__ int s_base[kGatherStage];   // packed base cell (10 bits per axis)
-  __shared__ float s_red[4][64][4];
+  __shared__ float s_mv[3][T];
+  __shared__ float s_A[9][T];
+  __shared__ float s_w[9][T];
+  __shared__ float s_f[3][T];
+  __shared__ int s_base[T];   // packed base cell (10 bits per axis)
+  __shared__ float s_red[NG][64][4];
   __shared__ int s_seg[9];            // the source bins' record ranges, concatenated
   __shared__ int s_from[8];
   __shared__ int s_cnt[8];
+  __shared__ int s_wkeep[NG];
   const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
   const int total_sims = *n_sims;
   const SimShare share(total_sims);
@@ -409,18 +421,44 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
       }
       __syncthreads();
       const int total = s_seg[8];
-      float acc[kMaxNodesPerLane][4];
+      float acc[NPL][4];
 #pragma unroll
-      for (int q = 0; q < kMaxNodesPerLane; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
-      // records in concatenated order (bin order, each bin sorted by particle index),
-      // staged kGatherStage at a time
-      for (int c0 = 0; c0 < total; c0 += kGatherStage) {
-        const int cnt = min(kGatherStage, total - c0);
-        for (int i = tid; i < cnt; i += kGatherThreads) {
-          const int g = c0 + i;
+      for (int q = 0; q < NPL; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
+      // records in concatenated order (bin order, each bin sorted by particle index), a
+      // window of T at a time. A block with more than one window stages only the records
+      // whose stencil reaches it (base + 2 >= the block's first node on every axis: the
+      // source bins lie at or below it), compacted in order.
+      const bool dense = total > T;
+      for (int c0 = 0; c0 < total; c0 += T) {
+        const int g = c0 + tid;
+        bool keep = false;
+        const float4* r4 = nullptr;
+        if (g < total) {
           int d = 0;
           while (g >= s_seg[d + 1]) ++d;
-          const float4* r4 = reinterpret_cast<const float4*>(S.rec + (int64_t)(s_from[d] + g - s_seg[d]) * 16);
+          r4 = reinterpret_cast<const float4*>(S.rec + (int64_t)(s_from[d] + g - s_seg[d]) * 16);
+          keep = true;
+          if (dense) {
+            const float4 a = r4[0];
+            const float x[3] = {a.x, a.y, a.z};
+            const Stencil st = make_stencil(x, S.inv_dx, n);
+            keep = st.base[0] + 2 >= bx * B && st.base[1] + 2 >= by * B && st.base[2] + 2 >= bz * B;
+          }
+        }
+        int i = tid, cnt = total;
+        if (dense) {
+          const uint64_t kept = __ballot(keep);
+          if (lane == 0) s_wkeep[grp] = __popcll(kept);
+          __syncthreads();
+          i = __popcll(kept & ((1ull << lane) - 1));
+          cnt = 0;
+#pragma unroll
+          for (int w = 0; w < NG; ++w) {
+            if (w < grp) i += s_wkeep[w];
+            cnt += s_wkeep[w];
+          }
+        }
+        if (keep) {
           const float4 a = r4[0], b4 = r4[1], c4 = r4[2], e4 = r4[3];
           const float x[3] = {a.x, a.y, a.z};
           const Stencil st = make_stencil(x, S.inv_dx, n);
@@ -440,11 +478,11 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
         __syncthreads();
         // group g adds records g, g + 4, ... of this stage
 #pragma unroll
-        for (int q = 0; q < kMaxNodesPerLane; ++q) {
+        for (int q = 0; q < NPL; ++q) {
           const int node = lane + 64 * q;
           if (q >= npl || node >= nodes) continue;
           const int ni = bx * B + node / (B * B), nj = by * B + (node / B) % B, nk = bz * B + node % B;
-          for (int i = grp; i < cnt; i += 4) {
+          for (int i = grp; i < cnt; i += NG) {
             const int pb = s_base[i];
             const int di = ni - (pb >> 20), dj = nj - ((pb >> 10) & 1023), dk = nk - (pb & 1023);
             if ((unsigned)di > 2u || (unsigned)dj > 2u || (unsigned)dk > 2u) continue;
@@ -462,7 +500,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
       }
       // add the four groups in order, grid update, store
 #pragma unroll
-      for (int q = 0; q < kMaxNodesPerLane; ++q) {
+      for (int q = 0; q < NPL; ++q) {
         if (q >= npl) break;
         const int node = lane + 64 * q;
         s_red[grp][lane][0] = acc[q][0];
@@ -472,7 +510,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const SimDev* __
         __syncthreads();
         if (grp == 0 && node < nodes) {
           float m = 0.f, pm[3] = {0.f, 0.f, 0.f};
-          for (int g = 0; g < 4; ++g) {
+          for (int g = 0; g < NG; ++g) {
             m += s_red[g][lane][0];
             pm[0] += s_red[g][lane][1];
             pm[1] += s_red[g][lane][2];
@@ -553,24 +591,21 @@ __device__ __forceinline__ void decoded_x(const SimDev& S, int p, float x[3]) {
 }
 
 // a. I = the stencil nodes of the sample particles (a stencil that leaves the grid marks
-// nothing; the MPM step flags that particle).
+// nothing; the MPM step flags that particle). One thread per stencil row (sample q, row
+// 3a + b): its three nodes are consecutive bits, set with one or two atomic ORs.
 __global__ __launch_bounds__(kAllocThreads) void closure_mark_kernel(const SimDev* __restrict__ sim) {
   const SimDev& S = *sim;
   const int n = S.grid_n;
-  for (int q = blockIdx.x * kAllocThreads + threadIdx.x; q < S.n_samp; q += gridDim.x * kAllocThreads) {
+  for (int t = blockIdx.x * kAllocThreads + threadIdx.x; t < 9 * S.n_samp; t += gridDim.x * kAllocThreads) {
+    const int q = t / 9, row = t % 9;
     float x[3];
     decoded_x(S, S.nlist[q], x);
     const Stencil st = make_stencil(x, S.inv_dx, n);
     if (!st.ok) continue;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int node = ((st.base[0] + a) * n + st.base[1] + b) * n + st.base[2] + c;
-          atomicOr(&S.node_mask[node >> 5], 1u << (node & 31));
-        }
+    const int node = ((st.base[0] + row / 3) * n + st.base[1] + row % 3) * n + st.base[2];
+    const int w = node >> 5, sh = node & 31;
+    atomicOr(&S.node_mask[w], 7u << sh);
+    if (sh > 29) atomicOr(&S.node_mask[w + 1], 7u >> (32 - sh));
   }
 }
 
@@ -628,15 +663,28 @@ __global__ __launch_bounds__(kAllocThreads) void closure_write_kernel(const SimD
     S.node_mask[w] = 0u;
 }
 
+// d. The field jobs over the list evaluate its live part.
+__global__ void closure_job_counts_kernel(const SimDev* __restrict__ sim, FieldJob* __restrict__ jobs,
+                                          ListJobs lj) {
+  const int k = threadIdx.x;
+  if (k < lj.n) {
+    FieldJob& j = jobs[lj.idx[k]];
+    j.n = max(*sim->n_live - j.p_off, 0);
+  }
+}
+
 }  // namespace
 
-hipError_t launch_closure(const SimDev* sim, int n_samp, int64_t n_part, hipStream_t s) {
-  if (n_samp < 1 || n_part < 1) return hipErrorInvalidValue;
+hipError_t launch_closure(const SimDev* sim, int n_samp, int64_t n_part, FieldJob* jobs,
+                          ListJobs list_jobs, hipStream_t s) {
+  if (n_samp < 1 || n_part < 1 || list_jobs.n < 0 || list_jobs.n > 4) return hipErrorInvalidValue;
   const int blocks = (int)((n_part + kAllocThreads - 1) / kAllocThreads);
-  hipLaunchKernelGGL(closure_mark_kernel, dim3((n_samp + kAllocThreads - 1) / kAllocThreads), dim3(kAllocThreads), 0,
+  const int rows = 9 * n_samp;
+  hipLaunchKernelGGL(closure_mark_kernel, dim3((rows + kAllocThreads - 1) / kAllocThreads), dim3(kAllocThreads), 0,
                      s, sim);
   hipLaunchKernelGGL(closure_member_kernel, dim3(blocks), dim3(kAllocThreads), 0, s, sim);
   hipLaunchKernelGGL(closure_write_kernel, dim3(blocks), dim3(kAllocThreads), 0, s, sim);
+  hipLaunchKernelGGL(closure_job_counts_kernel, dim3(1), dim3(64), 0, s, sim, jobs, list_jobs);
   return hipGetLastError();
 }
 
@@ -648,7 +696,7 @@ hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32
 }
 
 hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int grid_sims,
-                                int grid_blocks, hipStream_t s) {
+                                int grid_blocks, bool dense, int max_grid_n, hipStream_t s) {
   constexpr int alloc_lds = kMaxBins * 4;
   static bool attr = false;
   if (!attr) {
@@ -658,8 +706,21 @@ hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int g
     attr = true;
   }
   hipLaunchKernelGGL(alloc_place_kernel, dim3(grid_sims), dim3(kAllocThreads), alloc_lds, s, sims, n_sims);
-  hipLaunchKernelGGL(bin_sort_kernel, dim3(grid_blocks), dim3(64), 0, s, sims, n_sims);
-  hipLaunchKernelGGL(gather_kernel, dim3(grid_blocks), dim3(kGatherThreads), 0, s, sims, n_sims);
+  hipLaunchKernelGGL(bin_sort_kernel, dim3(grid_blocks), dim3(kSortThreads), 0, s, sims, n_sims);
+  // 4^3-node blocks (one node per lane) up to 128^3 grids, 8^3 above
+  const bool small = max_grid_n <= 128;
+  if (dense && small)
+    hipLaunchKernelGGL((gather_kernel<kGatherThreadsDense, 1>), dim3(grid_blocks), dim3(kGatherThreadsDense), 0, s,
+                       sims, n_sims);
+  else if (dense)
+    hipLaunchKernelGGL((gather_kernel<kGatherThreadsDense, kMaxNodesPerLane>), dim3(grid_blocks),
+                       dim3(kGatherThreadsDense), 0, s, sims, n_sims);
+  else if (small)
+    hipLaunchKernelGGL((gather_kernel<kGatherThreads, 1>), dim3(grid_blocks), dim3(kGatherThreads), 0, s, sims,
+                       n_sims);
+  else
+    hipLaunchKernelGGL((gather_kernel<kGatherThreads, kMaxNodesPerLane>), dim3(grid_blocks), dim3(kGatherThreads), 0,
+                       s, sims, n_sims);
   return hipGetLastError();
 }
 

@@ -43,9 +43,8 @@ struct FieldJob {
   int64_t ldx;
   int32_t plan_steps, plan_ld;
   int32_t p_off;             // point p of this job reads list entry p_off + p
-  int32_t n;                 // number of points
-  const int32_t* live;       // if non-NULL, only list entries below *live are evaluated (the
-                             // integration list of a closure sim changes length per step)
+  int32_t n;                 // number of points (a closure sim's jobs over N: rewritten on
+                             // the device each step from the list's live length)
   int32_t r, d;
   int32_t mode;              // 0: out = field; 1: out = X + field (decode)
   int32_t jvp;               // 1: directional derivative job (see z2)
@@ -154,21 +153,29 @@ int fields_group_points(int tc);  // points one work group (table entry) spans
 // records (per non-empty bin), gather + grid update (per active node block).
 hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
                       int32_t* claims, int grid_particles, hipStream_t s);
+// dense: the integration particles fill their cells (closure sims): wider gather
+// workgroups. max_grid_n bounds grid_n of every sim the launch can see.
 hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int grid_sims,
-                                int grid_blocks, hipStream_t s);
+                                int grid_blocks, bool dense, int max_grid_n, hipStream_t s);
 // G2P at the sample particles fused with the first Gauss-Newton reduction: work items are
 // Gauss-Newton chunks (kGnChunk sample particles). r_cap (<= kMaxR) bounds the latent size
 // of every sim in the launch and sizes the chunk's LDS.
 hipError_t launch_g2p_gn(const SimDev* sims, const BlockWork* work_gn, const int32_t* n_work_gn,
                          int r_cap, int grid, hipStream_t s);
-constexpr int kSegMax = 512;   // bin segments up to this size are summed in index order
+constexpr int kSegMax = 2048;  // bin segments up to this size are summed in index order
 // Gauss-Newton: chunk reduction of iteration iter >= 1, and the per-sim solve of any iteration.
 hipError_t launch_gn_partial(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
                              int iter, int r_cap, int grid, hipStream_t s);
 hipError_t launch_gn_solve(const SimDev* sims, const int32_t* n_sims, int iter, int grid_sims,
                            hipStream_t s);
 // Integration set of one closure sim from its decoded positions: mark the samples' stencil
-// nodes, flag and count the members, write the list and its live length.
-hipError_t launch_closure(const SimDev* sim, int n_samp, int64_t n_part, hipStream_t s);
+// nodes, flag and count the members, write the list and its live length, and set the
+// point count of the field jobs over the list (jobs[idx[k]].n = live - p_off).
+struct ListJobs {
+  int32_t idx[4];
+  int32_t n;
+};
+hipError_t launch_closure(const SimDev* sim, int n_samp, int64_t n_part, FieldJob* jobs,
+                          ListJobs list_jobs, hipStream_t s);
 
 }  // namespace nsf
