@@ -131,6 +131,11 @@ typedef struct {
                                   first-order (linearised) projection Sec. 5.3 offers as a
                                   speed-up: one solve with the Jacobian at z_n          */
   int32_t integration;         /* nsf_integration (0: plan rows, 1: closure of S)         */
+  int32_t n_mu;                /* problem parameters mu (Sec. 4.3: a stress field may
+                                  depend on a parameter of the return mapping), 0..4:
+                                  h takes [X; z; mu] and its W1 is
+                                  [width x (3 + r + n_mu)]; r + n_mu <= 32              */
+  double mu[4];                /* their values (finite)                                   */
 } nsf_sim_desc;
 
 typedef struct nsf_sim nsf_sim;  /* opaque, owned by the library */
@@ -188,6 +193,11 @@ nsf_status nsf_set_latent(nsf_sim *s, const double *z, const double *z_prev, int
  * first recomputes the integration set and the field inference for the smaller S at the
  * current latent. NSF_EINVAL for a plan sim. */
 nsf_status nsf_set_sample_count(nsf_sim *s, int32_t n_sample, void *stream);
+
+/* Problem parameters of the stress field h(X, z, mu) (Sec. 4.3), host [n_mu], async: the
+ * next nsf_step first re-evaluates the field inference with the new values. NSF_EINVAL
+ * if n_mu differs from the descriptor's or a value is not finite. */
+nsf_status nsf_set_parameters(nsf_sim *s, const double *mu, int32_t n_mu, void *stream);
 
 /* Read the sticky device flags (synchronises). Returns NSF_OK with *flags = 0, or, with
  * *flags set, the status of the first set condition in the order NONFINITE, SINGULAR,

@@ -71,10 +71,12 @@ def voigt_to_matrix(t: np.ndarray) -> np.ndarray:
 
 
 def eval_fields(fields: Dict[str, Sequence[Layer]], X: np.ndarray, z: np.ndarray,
-                scale: Dict[str, np.ndarray], shift: Dict[str, np.ndarray]):
-    """Network inference at one latent (Sec. 5.1): u (n,3), tau (n,3,3), C (n,3,3)."""
+                scale: Dict[str, np.ndarray], shift: Dict[str, np.ndarray], mu=None):
+    """Network inference at one latent (Sec. 5.1): u (n,3), tau (n,3,3), C (n,3,3). With
+    problem parameters mu the stress field is h(X, z, mu) (Sec. 4.3), input [X; z; mu]."""
     u = field(fields["g"], X, z, scale["g"], shift["g"])
-    tau = voigt_to_matrix(field(fields["h"], X, z, scale["h"], shift["h"]))
+    zh = z if mu is None or len(mu) == 0 else np.concatenate([np.asarray(z, np.float64), np.asarray(mu, np.float64)])
+    tau = voigt_to_matrix(field(fields["h"], X, zh, scale["h"], shift["h"]))
     C = field(fields["l"], X, z, scale["l"], shift["l"]).reshape(-1, 3, 3)
     return u, tau, C
 

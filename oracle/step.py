@@ -47,6 +47,13 @@ class OracleSim:
         self.flags = 0
         self.closure = getattr(w, "integration", "plan") == "closure"
         self.n_sample = int(w.n_sample)
+        self.mu = np.array(getattr(w, "mu", ()), np.float64).ravel()
+
+    def set_parameters(self, mu) -> None:
+        """Problem parameters of the stress field h(X, z, mu) from the next step on."""
+        mu = np.array(mu, np.float64).ravel()
+        assert mu.shape == self.mu.shape
+        self.mu = mu
 
     def set_sample_count(self, n_sample: int) -> None:
         """Closure mode: keep the first n_sample sample particles from the next step on."""
@@ -75,7 +82,7 @@ class OracleSim:
         """Sec. 5.1 on the integration particles: x, v, tau, C, u (all FP64)."""
         w = self.w
         XN = self.X[idx]
-        u_n, tau, C = F.eval_fields(w.fields, XN, self.z, w.out_scale, w.out_shift)
+        u_n, tau, C = F.eval_fields(w.fields, XN, self.z, w.out_scale, w.out_shift, self.mu)
         u_prev = self.u(XN, self.z_prev)
         v = (u_n - u_prev) / w.dt
         return XN + u_n, v, tau, C, u_n

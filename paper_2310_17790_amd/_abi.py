@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "NSF_OK", -1: "NSF_EINVAL", -2: "NSF_ENOMEM", -3: "NSF_EHIP",
                 -5: "NSF_EDOMAIN", -6: "NSF_ESINGULAR", -7: "NSF_ENONFINITE", -8: "NSF_ECAPACITY"}
 
 EXPORTED = ["nsf_sim_bytes", "nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_refresh", "nsf_decode",
-            "nsf_get_latent", "nsf_set_latent", "nsf_set_sample_count", "nsf_status_flags", "nsf_sim_buffer",
+            "nsf_get_latent", "nsf_set_latent", "nsf_set_sample_count", "nsf_set_parameters",
+            "nsf_status_flags", "nsf_sim_buffer",
             "nsf_destroy_sim", "nsf_last_error", "nsf_device_count", "nsf_mlp_param_count",
             "nsf_mlp_saved_floats", "nsf_mlp_workspace_bytes", "nsf_mlp_forward",
             "nsf_mlp_backward"]
@@ -49,7 +50,8 @@ class nsf_sim_desc(C.Structure):
                 ("plan_steps", C.c_int32), ("sample_plan", C.POINTER(C.c_int32)),
                 ("gn_iters", C.c_int32), ("decode_every_step", C.c_int32),
                 ("z0", C.POINTER(C.c_double)), ("z_prev", C.POINTER(C.c_double)),
-                ("gn_damping", C.c_double), ("integration", C.c_int32)]
+                ("gn_damping", C.c_double), ("integration", C.c_int32),
+                ("n_mu", C.c_int32), ("mu", C.c_double * 4)]
 
 
 class nsf_mlp(C.Structure):
@@ -85,6 +87,7 @@ def lib() -> C.CDLL:
         L.nsf_set_latent.argtypes = [vp, vp, vp, i64, vp]
         L.nsf_status_flags.argtypes = [vp, C.POINTER(C.c_uint32), vp]
         L.nsf_set_sample_count.argtypes = [vp, i32, vp]
+        L.nsf_set_parameters.argtypes = [vp, vp, i32, vp]
         L.nsf_sim_buffer.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64)]
         L.nsf_destroy_sim.argtypes = [vp]
         L.nsf_last_error.argtypes = []
@@ -157,6 +160,12 @@ def nsf_set_latent(sim: int, z, z_prev, step: int, stream: int) -> None:
 
 def nsf_set_sample_count(sim: int, n_sample: int, stream: int) -> None:
     check(lib().nsf_set_sample_count(sim, n_sample, stream or None))
+
+
+def nsf_set_parameters(sim: int, mu, stream: int) -> None:
+    n = len(mu)
+    arr = (C.c_double * max(n, 1))(*[float(v) for v in mu])
+    check(lib().nsf_set_parameters(sim, arr, n, stream or None))
 
 
 def nsf_status_flags(sim: int, stream: int):

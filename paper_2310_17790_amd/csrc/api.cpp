@@ -57,7 +57,7 @@ struct Carver {
 struct Layout {
   size_t simdev;
   size_t whp[3], whb[3], b6[3], w1q[3], bhq[3], w6q[3], whpt[3], whbt[3], w1zt[3];
-  size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, zdec, step, flags, gn_part;
+  size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, zdec, zh, step, flags, gn_part;
   size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active,
       nonempty, n_active;
   size_t node_mask, is_sample, member, cl_block, n_live;   // closure integration only
@@ -65,6 +65,8 @@ struct Layout {
 };
 
 int gn_entries(int r) { return r * (r + 1) / 2 + r; }
+// inputs after X of field f: the latent, and for the stress field the problem parameters
+int field_r(const nsf_sim_desc* d, int f) { return d->r + (f == NSF_FIELD_H ? d->n_mu : 0); }
 // node bitmask of a closure sim: one bit per node plus a pad word (the membership test
 // reads two consecutive words)
 size_t mask_words(int grid_n) { return ((size_t)grid_n * grid_n * grid_n + 31) / 32 + 1; }
@@ -79,7 +81,7 @@ Layout make_layout(const nsf_sim_desc* d) {
   const int64_t P = d->n_particles, N = d->n_integration, S = d->n_sample;
   L.simdev = c.take(sizeof(SimDev));
   for (int f = 0; f < 3; ++f) {
-    const PackSizes ps = pack_sizes(r, W, kFieldOut[f]);
+    const PackSizes ps = pack_sizes(field_r(d, f), W, kFieldOut[f]);
     L.whp[f] = c.take(ps.whp * 4);
     L.whb[f] = c.take(ps.whb * 2);
     L.b6[f] = c.take(ps.b6 * 4);
@@ -105,6 +107,7 @@ Layout make_layout(const nsf_sim_desc* d) {
   L.grid = c.take(n3 * 16);
   L.z = c.take((size_t)3 * r * 8);
   L.zdec = c.take((size_t)r * 8);
+  if (d->n_mu > 0) L.zh = c.take((size_t)(r + d->n_mu) * 8);
   L.step = c.take(8);
   L.flags = c.take(4);
   L.gn_part = c.take((size_t)ceil_div(S, kGnChunk) * gn_entries(r) * 8);
@@ -160,6 +163,10 @@ nsf_status validate(const nsf_sim_desc* d) {
     return fail(NSF_EINVAL, "gn_damping = %g outside [0, 1e6]", d->gn_damping);
   if (d->decode_every_step < 0 || d->decode_every_step > 2)
     return fail(NSF_EINVAL, "decode_every_step = %d (0, 1 or 2)", d->decode_every_step);
+  if (d->n_mu < 0 || d->n_mu > 4 || d->r + d->n_mu > kMaxR)
+    return fail(NSF_EINVAL, "n_mu = %d (0..4, r + n_mu <= %d)", d->n_mu, kMaxR);
+  for (int i = 0; i < d->n_mu; ++i)
+    if (!std::isfinite(d->mu[i])) return fail(NSF_EINVAL, "mu[%d] is not finite", i);
   if (d->integration != NSF_INTEGRATION_PLAN && d->integration != NSF_INTEGRATION_CLOSURE)
     return fail(NSF_EINVAL, "integration = %d (0 plan, 1 closure)", d->integration);
   const bool closure = d->integration == NSF_INTEGRATION_CLOSURE;
@@ -218,6 +225,7 @@ struct nsf_sim {
   int n_int = 0, n_samp = 0, gn_iters = 2;
   int decode_mode = 0;    // decode_every_step: 0, 1 or 2 (pipelined)
   bool closure = false;   // integration set = closure of the sample stencils
+  int n_mu = 0;           // problem parameters of the stress field
   std::vector<int32_t> samples;   // closure: the sample list given at creation
   char* arena = nullptr;
   size_t arena_bytes = 0;
@@ -424,6 +432,10 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     jobs.push_back(c);
     FieldJob h = base_job(s, NSF_FIELD_H, zc);
     h.n = N; h.out = H.tau; h.ldo = N;
+    if (s->n_mu > 0) {   // h(X, z_n, mu): the solve keeps zh's latent part current
+      h.z = H.zh;
+      h.r = s->r + s->n_mu;
+    }
     add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
     over_list((int)jobs.size());
     jobs.push_back(h);
@@ -763,12 +775,12 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   // pack weights on the host, one upload per field
   std::vector<char> staging;
   for (int f = 0; f < 3; ++f) {
-    const int dd = kFieldOut[f];
-    const PackSizes ps = pack_sizes(r, W, dd);
+    const int dd = kFieldOut[f], rf = field_r(d, f);
+    const PackSizes ps = pack_sizes(rf, W, dd);
     std::vector<float> whp(ps.whp), b6(ps.b6), w1q(ps.w1q), bhq(ps.bhq), w6q(ps.w6q), whpt(ps.whp),
         w1zt(ps.w1zt);
     std::vector<uint16_t> whb(ps.whb), whbt(ps.whb);
-    pack_field(d->weights[f], r, W, dd,
+    pack_field(d->weights[f], rf, W, dd,
                PackOut{whp.data(), whb.data(), b6.data(), w1q.data(), bhq.data(), w6q.data(), whpt.data(),
                        whbt.data(), w1zt.data()});
     auto up = [&](size_t off, const void* src, size_t bytes) {
@@ -821,6 +833,12 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   }
   NSF_HIP(hipMemcpyAsync(A + L.z, z.data(), z.size() * 8, hipMemcpyHostToDevice, s));
   NSF_HIP(hipMemcpyAsync(A + L.zdec, z.data() + r, (size_t)r * 8, hipMemcpyHostToDevice, s));
+  std::vector<double> zh0;
+  if (d->n_mu > 0) {
+    zh0.assign(z.begin() + r, z.begin() + 2 * r);
+    zh0.insert(zh0.end(), d->mu, d->mu + d->n_mu);
+    NSF_HIP(hipMemcpyAsync(A + L.zh, zh0.data(), zh0.size() * 8, hipMemcpyHostToDevice, s));
+  }
   const size_t n3 = (size_t)d->grid_n * d->grid_n * d->grid_n;
   NSF_HIP(hipMemsetAsync(A + L.grid, 0, n3 * 16, s));
   NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
@@ -879,6 +897,8 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.grid = reinterpret_cast<float4*>(A + L.grid);
   H.z = reinterpret_cast<double*>(A + L.z);
   H.zdec = reinterpret_cast<double*>(A + L.zdec);
+  H.zh = d->n_mu > 0 ? reinterpret_cast<double*>(A + L.zh) : nullptr;
+  sim->n_mu = d->n_mu;
   H.step = reinterpret_cast<int64_t*>(A + L.step);
   H.flags = reinterpret_cast<uint32_t*>(A + L.flags);
   H.gn_part = reinterpret_cast<double*>(A + L.gn_part);
@@ -1004,6 +1024,7 @@ nsf_status nsf_set_latent(nsf_sim* s, const double* z, const double* z_prev, int
   }
   const uint32_t zero = 0;
   NSF_HIP(hipMemcpyAsync(s->hd.z, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, st));
+  if (s->hd.zh) NSF_HIP(hipMemcpyAsync(s->hd.zh, z, s->r * 8, hipMemcpyHostToDevice, st));
   NSF_HIP(hipMemcpyAsync(s->hd.step, &step, 8, hipMemcpyHostToDevice, st));
   NSF_HIP(hipMemcpyAsync(s->hd.flags, &zero, 4, hipMemcpyHostToDevice, st));
   NSF_HIP(hipStreamSynchronize(st));
@@ -1044,6 +1065,20 @@ nsf_status nsf_set_sample_count(nsf_sim* s, int32_t n_sample, void* stream) {
   NSF_HIP(hipMemcpyAsync(s->hd.is_sample, is_s.data(), is_s.size(), hipMemcpyHostToDevice, st));
   NSF_HIP(hipMemcpyAsync(s->dd, &s->hd, sizeof(SimDev), hipMemcpyHostToDevice, st));
   NSF_HIP(hipStreamSynchronize(st));
+  s->inference_ready = false;
+  return NSF_OK;
+}
+
+nsf_status nsf_set_parameters(nsf_sim* s, const double* mu, int32_t n_mu, void* stream) {
+  if (!s) return fail(NSF_EINVAL, "sim is NULL");
+  if (n_mu != s->n_mu) return fail(NSF_EINVAL, "n_mu = %d, the sim has %d problem parameters", n_mu, s->n_mu);
+  if (n_mu == 0) return NSF_OK;
+  if (!mu) return fail(NSF_EINVAL, "mu is NULL");
+  for (int i = 0; i < n_mu; ++i)
+    if (!std::isfinite(mu[i])) return fail(NSF_EINVAL, "mu[%d] is not finite", i);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  NSF_HIP(hipMemcpyAsync(s->hd.zh + s->r, mu, (size_t)n_mu * 8, hipMemcpyHostToDevice, st));
+  NSF_HIP(hipStreamSynchronize(st));   // mu is a host array read during the call only
   s->inference_ready = false;
   return NSF_OK;
 }

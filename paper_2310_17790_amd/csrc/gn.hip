@@ -85,6 +85,7 @@ __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 
     if (final_iter) {
       zp[j] = zc[j];
       zc[j] = zn;
+      if (S.zh) S.zh[j] = zn;   // the stress field's latent input
     } else {
       zi[j] = zn;
     }

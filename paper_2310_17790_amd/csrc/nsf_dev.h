@@ -97,6 +97,8 @@ struct SimDev {
   float4* grid;                      // [grid_n^3] (m, p_x, p_y, p_z)
   double* z;                         // [3][r]: z_{n-1}, z_n, iterate
   double* zdec;                      // [r]: the latent a pipelined decode reads
+  double* zh;                        // [r + n_mu]: (z_n, mu), the stress field's input
+                                     // after X (NULL without problem parameters)
   int64_t* step;
   uint32_t* flags;
   double* gn_part;                   // [n_gn_chunks][E], E = r(r+1)/2 + r

@@ -72,6 +72,10 @@ def build_desc(w, precision: str, decode_every_step: bool):
     d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
     d.gn_iters = int(w.gn_iters)
     d.gn_damping = float(getattr(w, "gn_damping", 0.0))
+    mu = np.asarray(getattr(w, "mu", ()), np.float64).ravel()
+    d.n_mu = int(mu.shape[0])
+    for i, v in enumerate(mu[:4]):
+        d.mu[i] = float(v)
     d.decode_every_step = int(decode_every_step)   # 0, 1 (True) or 2 (pipelined)
     d.z0 = dptr(w.z0)
     d.z_prev = dptr(w.z_prev) if w.z_prev is not None else None
@@ -160,6 +164,10 @@ class Sim:
         """Closure integration: keep the first n_sample sample particles from the next step."""
         A.nsf_set_sample_count(self.handle, int(n_sample), _stream_handle(stream))
         self.n_sample = int(n_sample)
+
+    def set_parameters(self, mu, stream=None) -> None:
+        """New problem parameters mu of the stress field h(X, z, mu)."""
+        A.nsf_set_parameters(self.handle, [float(v) for v in np.ravel(mu)], _stream_handle(stream))
 
     def integration_list(self, stream=None) -> np.ndarray:
         """The current integration list (closure: its live part; plan: all rows)."""

@@ -49,10 +49,12 @@ def xavier_mlp(rng: np.random.Generator, in_dim: int, width: int, out_dim: int,
     return layers
 
 
-def make_fields(seed: int, r: int, width: int, bias_scale: float = 0.0) -> Dict[str, List[Layer]]:
-    """Weights for the three fields g (3 out), h (6 out), l (9 out); draw order g, h, l."""
+def make_fields(seed: int, r: int, width: int, bias_scale: float = 0.0,
+                n_mu: int = 0) -> Dict[str, List[Layer]]:
+    """Weights for the three fields g (3 out), h (6 out), l (9 out); draw order g, h, l.
+    With n_mu > 0 the stress field h takes n_mu problem parameters after the latent."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return {name: xavier_mlp(rng, 3 + r, width, FIELD_OUT[name], bias_scale)
+    return {name: xavier_mlp(rng, 3 + r + (n_mu if name == "h" else 0), width, FIELD_OUT[name], bias_scale)
             for name in FIELD_NAMES}
 
 
@@ -131,6 +133,8 @@ class Workload:
     # is the closure of S's stencils each step, with room for closure_cap particles.
     integration: str = "plan"
     closure_cap: int = 0
+    # problem parameters of the stress field h(X, z, mu) (empty: h(X, z))
+    mu: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
 
     @property
     def n_particles(self) -> int:

@@ -145,3 +145,30 @@ def test_closure_descriptor_validation():
     d.sample_plan = dup.ctypes.data_as(C.POINTER(C.c_int32))
     assert A.nsf_sim_bytes(d) == 0
     assert "twice" in A.nsf_last_error()
+
+
+def test_problem_parameter_validation():
+    """n_mu in 0..4 with r + n_mu <= 32 and finite values; the stress field's W1 grows by
+    n_mu columns, so the arena grows with it."""
+    from paper_2310_17790_amd.sim import build_desc
+    w = synth.small_cube(seed=0, r=6, width=64, n=256)
+    w.fields = synth.make_fields(0, 6, 64, n_mu=2)
+    w.mu = np.array([0.1, 0.2])
+    d, keep = build_desc(w, "fp32", True)
+    assert d.n_mu == 2
+    n2 = A.nsf_sim_bytes(d)
+    assert n2 > 0, A.nsf_last_error()
+    w0 = synth.small_cube(seed=0, r=6, width=64, n=256)
+    d0, keep0 = build_desc(w0, "fp32", True)
+    assert 0 < A.nsf_sim_bytes(d0) < n2
+    for field, val in [("n_mu", 5), ("n_mu", -1)]:
+        old = getattr(d, field)
+        setattr(d, field, val)
+        assert A.nsf_sim_bytes(d) == 0
+        setattr(d, field, old)
+    d.mu[1] = float("nan")
+    assert A.nsf_sim_bytes(d) == 0
+    d.mu[1] = 0.2
+    d.r, d.n_mu = 30, 3
+    assert A.nsf_sim_bytes(d) == 0
+    assert "n_mu" in A.nsf_last_error()

@@ -299,3 +299,48 @@ def test_inversion_variants(precision, gn_iters, damping):
     if not (gn_iters == 3 and damping == 0.0):
         assert err < 0.1 * apart
     sim.close()
+
+
+def test_problem_parameters_on_gpu():
+    """h(X, z, mu) with two parameters: the stress of the inference against the oracle's
+    (FP32 gate 2e-5), again after nsf_set_parameters, and 4 steps with the parameter
+    changed after the second (delta_x <= 1e-5). The change must move the stress far more
+    than the FP32 error (the parameters reach the kernel)."""
+    w = _with_velocity(synth.small_cube(seed=6, r=6, width=128, n=1000, steps=4, bias_scale=0.1))
+    w.fields = synth.make_fields(6, 6, 128, bias_scale=0.1, n_mu=2)
+    w.mu = np.array([0.4, -0.8])
+    print("\n[case] problem parameters n_mu=2 width=128", flush=True)
+    s = _stream()
+    sim = Sim(w, stream=s)
+    o = OracleSim(w)
+    N = w.n_integration
+
+    def tau_err():
+        sim.refresh(stream=s)
+        s.synchronize()
+        _, _, tau, _, _ = o.inference(o.indices())
+        t6 = _soa(sim.buffer(A.NSF_BUF_TAU)).reshape(6, N).T
+        voigt = np.stack([tau[:, 0, 0], tau[:, 1, 1], tau[:, 2, 2], tau[:, 1, 2], tau[:, 0, 2], tau[:, 0, 1]], 1)
+        return _rel_max(t6, voigt), t6
+
+    e0, t_a = tau_err()
+    sim.set_parameters([-0.3, 1.1], stream=s)
+    o.set_parameters([-0.3, 1.1])
+    e1, t_b = tau_err()
+    moved = float(np.abs(t_b - t_a).max() / np.abs(t_a).max())
+    print(f"tau errors {e0:.2e} {e1:.2e}; change with mu {moved:.2e}", flush=True)
+    assert e0 < 2e-5 and e1 < 2e-5 and moved > 1e-3
+    for k in range(4):
+        if k == 2:
+            sim.set_parameters([0.9, 0.0], stream=s)
+            o.set_parameters([0.9, 0.0])
+        sim.step(1, stream=s)
+        o.step(1)
+        s.synchronize()
+        d = relative_error(_soa(sim.buffer(A.NSF_BUF_XDEC)).reshape(3, -1).T, o.decode())
+        print(f"step {k + 1}: delta_x={d:.2e}", flush=True)
+        assert d <= 1e-5
+    assert sim.flags(stream=s) == (0, 0)
+    with pytest.raises(A.NsfError):
+        sim.set_parameters([1.0], stream=s)
+    sim.close()

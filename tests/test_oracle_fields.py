@@ -78,3 +78,28 @@ def test_voigt_matrix_is_symmetric_and_complete():
     np.testing.assert_array_equal(M, M.T)
     assert sorted(np.unique(M).tolist()) == [1, 2, 3, 4, 5, 6]
     np.testing.assert_array_equal(np.diag(M), [1, 2, 3])
+
+
+def test_stress_field_with_problem_parameters_matches_torch():
+    """h(X, z, mu) (Sec. 4.3): eval_fields feeds [X; z; mu] to the stress field only; an
+    independent torch evaluation builds the rows [X; z; mu] itself. g and l ignore mu."""
+    r, n_mu = 4, 2
+    fl = synth.make_fields(7, r, 32, bias_scale=0.1, n_mu=n_mu)
+    assert fl["h"][0][0].shape[1] == 3 + r + n_mu and fl["g"][0][0].shape[1] == 3 + r
+    X = synth.box_points(8, 50, (0.3, 0.3, 0.3), (0.7, 0.7, 0.7)).T
+    z = synth.latent(9, r, 0.2)
+    mu = np.array([0.7, -1.3])
+    scale, shift = synth.default_scales()
+    u, tau, C = F.eval_fields(fl, X, z, scale, shift, mu)
+    ref_h = _torch_mlp(fl["h"], X, np.concatenate([z, mu]))
+    np.testing.assert_allclose(tau[:, 0, 0], ref_h[:, 0], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(tau[:, 1, 2], ref_h[:, 3], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(u, 1e-2 * _torch_mlp(fl["g"], X, z), rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(C.reshape(-1, 9), _torch_mlp(fl["l"], X, z), rtol=1e-12, atol=1e-14)
+    # zero mu columns: the parameters drop out
+    h0 = [(W.copy(), b) for W, b in fl["h"]]
+    h0[0][0][:, 3 + r:] = 0.0
+    fl0 = dict(fl, h=h0)
+    _, tau_a, _ = F.eval_fields(fl0, X, z, scale, shift, mu)
+    _, tau_b, _ = F.eval_fields(fl0, X, z, scale, shift, -mu)
+    np.testing.assert_array_equal(tau_a, tau_b)

@@ -104,3 +104,28 @@ def test_small_cube_runs_and_moves():
 def test_relative_error_definition():
     x_ref = np.array([[3.0, 4.0, 0.0]])
     assert relative_error(x_ref + np.array([[0.0, 0.0, 0.5]]), x_ref) == pytest.approx(0.1)
+
+
+def test_problem_parameters_steer_the_stress():
+    """With h(X, z, mu) the parameter enters the step through the stress alone: two values
+    of mu give different trajectories; zeroing h's mu columns makes them identical."""
+    w = synth.small_cube(seed=4, r=6, width=32, n=256, bias_scale=0.1)
+    w.fields = synth.make_fields(4, 6, 32, bias_scale=0.1, n_mu=1)
+    w.z_prev = w.z0 - 2e-3 * np.random.default_rng(3).normal(size=6)
+    w.mu = np.array([0.5])
+    a = OracleSim(w)
+    a.step(2)
+    b = OracleSim(w)
+    b.set_parameters([-0.5])
+    b.step(2)
+    assert np.abs(a.z - b.z).max() > 1e-9
+    w0 = copy.deepcopy(w)
+    W1, b1 = w0.fields["h"][0]
+    W1 = W1.copy()
+    W1[:, 3 + 6:] = 0.0
+    w0.fields["h"][0] = (W1, b1)
+    c, d = OracleSim(w0), OracleSim(w0)
+    d.set_parameters([-0.5])
+    c.step(2)
+    d.step(2)
+    np.testing.assert_array_equal(c.z, d.z)
