@@ -269,6 +269,49 @@ nsf_status nsf_mlp_backward(const nsf_mlp *m, const float *X, const float *z_row
                             const float *saved, const float *dout, float *dW, float *dz,
                             void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---- Full-order MLS-MPM (the model the reduced step is measured against) -------------
+ * Every particle is integrated (Sec. 3.3): P2G with APIC and the MLS stress impulse, grid
+ * update with gravity, sticky walls and a separating ground (the bottom wall_nodes layers
+ * keep v_z >= 0), G2P of v and C, F_trial = (I + dt C) F^E, the von Mises return map in
+ * log strain and fixed corotated elasticity (supplementary "Elasticity and plasticity
+ * details"): with F_trial = U S V^T, eps = log S, eps_hat = eps - mean(eps),
+ * dgamma = |eps_hat| - tau_y / (2 mu); if dgamma > 0, eps -= dgamma eps_hat / |eps_hat|;
+ * F^E = U exp(eps) V^T and tau = 2 mu (F^E - R) F^E^T + lambda (J - 1) J I, R = U V^T.
+ * Positions, velocities and C are FP32 and F^E FP64; each particle's SVD comes from a
+ * Jacobi eigen-decomposition of F^T F in FP64. Particle volume body_volume / n_particles.
+ * All particles start with velocity v0, C = 0 and F^E = I. */
+typedef struct {
+  int64_t n_particles;
+  const float *X;              /* host [3][n_particles] initial positions                 */
+  double v0[3];                /* initial velocity                                        */
+  double rho, body_volume;
+  double youngs, poisson;      /* E, nu: mu = E / (2 (1 + nu)), lambda = E nu / ((1 + nu)(1 - 2 nu)) */
+  double yield_stress;         /* tau_y of the von Mises return map (> 0)                 */
+  int32_t grid_n;              /* nodes per axis, 8..256, dx = 1 / grid_n                 */
+  double dt;
+  double gravity[3];
+  int32_t wall_nodes;          /* wall band; its bottom layers are the separating ground  */
+} nsf_fo_desc;
+
+typedef struct nsf_fo nsf_fo;
+
+/* Device bytes of the full-order sim's arena (0 if d is invalid). */
+size_t nsf_fo_bytes(const nsf_fo_desc *d);
+/* Create in a caller-owned arena (device, 256-byte aligned, >= nsf_fo_bytes); the call
+ * returns after the set-up work on `stream` completes. */
+nsf_status nsf_fo_create(const nsf_fo_desc *d, void *arena, size_t arena_bytes, void *stream,
+                         nsf_fo **out);
+/* Advance n_steps full-order steps, async (a captured graph after the first call). */
+nsf_status nsf_fo_step(nsf_fo *f, int32_t n_steps, void *stream);
+/* Device views: NSF_FO_U displacement x - X [3][P], NSF_FO_V velocity [3][P], NSF_FO_C
+ * affine C [9][P] (row-major), NSF_FO_TAU Kirchhoff stress, Voigt [6][P] (all float),
+ * NSF_FO_F elastic F^E, double [9][P]. */
+enum { NSF_FO_U = 0, NSF_FO_V, NSF_FO_C, NSF_FO_TAU, NSF_FO_F };
+nsf_status nsf_fo_buffer(nsf_fo *f, int32_t which, void **ptr, int64_t *count);
+/* Sticky flags as nsf_status_flags (DOMAIN if a particle leaves the grid). */
+nsf_status nsf_fo_flags(nsf_fo *f, uint32_t *flags, void *stream);
+nsf_status nsf_fo_destroy(nsf_fo *f);
+
 #ifdef __cplusplus
 }
 #endif

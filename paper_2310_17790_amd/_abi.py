@@ -29,7 +29,9 @@ EXPORTED = ["nsf_sim_bytes", "nsf_create_sim", "nsf_step", "nsf_step_batch", "ns
             "nsf_status_flags", "nsf_sim_buffer",
             "nsf_destroy_sim", "nsf_last_error", "nsf_device_count", "nsf_mlp_param_count",
             "nsf_mlp_saved_floats", "nsf_mlp_workspace_bytes", "nsf_mlp_forward",
-            "nsf_mlp_backward"]
+            "nsf_mlp_backward", "nsf_fo_bytes", "nsf_fo_create", "nsf_fo_step", "nsf_fo_buffer",
+            "nsf_fo_flags", "nsf_fo_destroy"]
+NSF_FO_U, NSF_FO_V, NSF_FO_C, NSF_FO_TAU, NSF_FO_F = range(5)
 
 
 class nsf_knife(C.Structure):
@@ -52,6 +54,13 @@ class nsf_sim_desc(C.Structure):
                 ("z0", C.POINTER(C.c_double)), ("z_prev", C.POINTER(C.c_double)),
                 ("gn_damping", C.c_double), ("integration", C.c_int32),
                 ("n_mu", C.c_int32), ("mu", C.c_double * 4)]
+
+
+class nsf_fo_desc(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("X", C.POINTER(C.c_float)), ("v0", C.c_double * 3),
+                ("rho", C.c_double), ("body_volume", C.c_double), ("youngs", C.c_double),
+                ("poisson", C.c_double), ("yield_stress", C.c_double), ("grid_n", C.c_int32),
+                ("dt", C.c_double), ("gravity", C.c_double * 3), ("wall_nodes", C.c_int32)]
 
 
 class nsf_mlp(C.Structure):
@@ -88,6 +97,13 @@ def lib() -> C.CDLL:
         L.nsf_status_flags.argtypes = [vp, C.POINTER(C.c_uint32), vp]
         L.nsf_set_sample_count.argtypes = [vp, i32, vp]
         L.nsf_set_parameters.argtypes = [vp, vp, i32, vp]
+        L.nsf_fo_bytes.argtypes = [C.POINTER(nsf_fo_desc)]
+        L.nsf_fo_bytes.restype = sz
+        L.nsf_fo_create.argtypes = [C.POINTER(nsf_fo_desc), vp, sz, vp, C.POINTER(vp)]
+        L.nsf_fo_step.argtypes = [vp, i32, vp]
+        L.nsf_fo_buffer.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64)]
+        L.nsf_fo_flags.argtypes = [vp, C.POINTER(C.c_uint32), vp]
+        L.nsf_fo_destroy.argtypes = [vp]
         L.nsf_sim_buffer.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64)]
         L.nsf_destroy_sim.argtypes = [vp]
         L.nsf_last_error.argtypes = []

@@ -1133,3 +1133,268 @@ nsf_status nsf_destroy_sim(nsf_sim* s) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Full-order MLS-MPM: every particle integrated, state in the reduced step's buffers
+// (u_n = x - X, u_prev = v with tangent forms, tau, C) plus F^E, so the reduced step's
+// P2G kernels run unchanged over the identity list, followed by the full-order G2P.
+struct nsf_fo {
+  int64_t n_part = 0;
+  int grid_n = 0;
+  char* arena = nullptr;
+  SimDev hd{};
+  SimDev* dd = nullptr;
+  int32_t* d_counts = nullptr;    // [0..7] work counts ([3] P2G blocks, [6] sims), [8..15] claims
+  BlockWork* d_bP = nullptr;
+  int nP = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~nsf_fo() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+namespace {
+
+struct FoLayout {
+  size_t simdev, counts, bP, X, plan, u, v, tau, C, F, grid, step, flags;
+  size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active, nonempty, n_active;
+  size_t z;
+  size_t total;
+};
+
+nsf_status fo_validate(const nsf_fo_desc* d) {
+  if (!d) return fail(NSF_EINVAL, "descriptor is NULL");
+  if (d->n_particles < 1 || d->n_particles > (int64_t)INT32_MAX / 16)
+    return fail(NSF_EINVAL, "n_particles = %lld", (long long)d->n_particles);
+  if (!d->X) return fail(NSF_EINVAL, "X is NULL");
+  if (d->grid_n < 8 || d->grid_n > 256) return fail(NSF_EINVAL, "grid_n = %d outside 8..256", d->grid_n);
+  if (!(d->dt > 0) || !(d->rho > 0) || !(d->body_volume > 0)) return fail(NSF_EINVAL, "dt, rho and body_volume must be positive");
+  if (!(d->youngs > 0) || !(d->poisson > -1.0 && d->poisson < 0.5)) return fail(NSF_EINVAL, "need E > 0 and -1 < nu < 0.5");
+  if (!(d->yield_stress > 0)) return fail(NSF_EINVAL, "yield_stress must be positive");
+  if (d->wall_nodes < 0 || 2 * d->wall_nodes >= d->grid_n) return fail(NSF_EINVAL, "wall_nodes = %d", d->wall_nodes);
+  return NSF_OK;
+}
+
+FoLayout fo_layout(const nsf_fo_desc* d) {
+  FoLayout L{};
+  Carver c;
+  const int64_t P = d->n_particles;
+  const size_t n3 = (size_t)d->grid_n * d->grid_n * d->grid_n;
+  const int nbs = bins_per_axis(d->grid_n);
+  const size_t nb = (size_t)nbs * nbs * nbs;
+  L.simdev = c.take(sizeof(SimDev));
+  L.counts = c.take(16 * 4);
+  L.bP = c.take((size_t)ceil_div(P, kMpmBlock) * sizeof(BlockWork));
+  L.X = c.take((size_t)3 * P * 4);
+  L.plan = c.take((size_t)P * 4);
+  L.u = c.take((size_t)3 * P * 4);
+  L.v = c.take((size_t)3 * P * 4);
+  L.tau = c.take((size_t)6 * P * 4);
+  L.C = c.take((size_t)9 * P * 4);
+  L.F = c.take((size_t)9 * P * 8);
+  L.grid = c.take(n3 * 16);
+  L.step = c.take(8);
+  L.flags = c.take(4);
+  L.bin_cnt = c.take(nb * 4);
+  L.bin_start = c.take(nb * 4);
+  L.seg_cnt = c.take(nb * 4);
+  L.bin_epoch = c.take(nb * 4);
+  L.epoch = c.take(4);
+  L.pbin = c.take((size_t)P * 4);
+  L.prank = c.take((size_t)P * 4);
+  L.rec = c.take((size_t)P * 64);
+  L.sorted = c.take((size_t)P * 4);
+  L.active = c.take(nb * 4);
+  L.nonempty = c.take(nb * 4);
+  L.n_active = c.take(8);
+  L.z = c.take(3 * 8);
+  L.total = c.off;
+  return L;
+}
+
+nsf_status fo_enqueue_step(nsf_fo& f, hipStream_t s) {
+  NSF_HIP(launch_bin(f.dd, f.d_bP, f.d_counts + 3, f.d_counts + 8, f.nP, s));
+  NSF_HIP(launch_p2g_after_bin(f.dd, f.d_counts + 6, 1, 5 * device_cus(), true, f.grid_n, s));
+  NSF_HIP(launch_fo_g2p(f.dd, f.n_part, s));
+  return NSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t nsf_fo_bytes(const nsf_fo_desc* d) {
+  if (fo_validate(d) != NSF_OK) return 0;
+  return fo_layout(d).total;
+}
+
+nsf_status nsf_fo_create(const nsf_fo_desc* d, void* arena, size_t arena_bytes, void* stream, nsf_fo** out) {
+  if (!out) return fail(NSF_EINVAL, "out is NULL");
+  *out = nullptr;
+  nsf_status st = fo_validate(d);
+  if (st != NSF_OK) return st;
+  std::string why;
+  if (!device_ok(&why)) return fail(NSF_ENODEV, "%s", why.c_str());
+  const FoLayout L = fo_layout(d);
+  if (!arena) return fail(NSF_EINVAL, "arena is NULL");
+  if ((reinterpret_cast<uintptr_t>(arena) & (kAlign - 1)) != 0) return fail(NSF_EINVAL, "arena must be 256-byte aligned");
+  if (arena_bytes < L.total) return fail(NSF_ENOMEM, "arena has %zu bytes, needs %zu", arena_bytes, L.total);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::unique_ptr<nsf_fo> f(new nsf_fo());
+  char* A = static_cast<char*>(arena);
+  const int64_t P = d->n_particles;
+  f->n_part = P;
+  f->grid_n = d->grid_n;
+  f->arena = A;
+  // initial state: x = X, v = v0, C = 0, F^E = I, tau = 0 (the stress of F = I)
+  std::vector<int32_t> ident((size_t)P);
+  for (int64_t i = 0; i < P; ++i) ident[i] = (int32_t)i;
+  std::vector<float> v0((size_t)3 * P);
+  for (int c = 0; c < 3; ++c) std::fill(v0.begin() + c * P, v0.begin() + (c + 1) * P, (float)d->v0[c]);
+  std::vector<double> F0((size_t)9 * P, 0.0);
+  for (int c = 0; c < 3; ++c) std::fill(F0.begin() + (4 * c) * P, F0.begin() + (4 * c + 1) * P, 1.0);
+  std::vector<BlockWork> bP;
+  for (int64_t p0 = 0; p0 < P; p0 += kMpmBlock) bP.push_back({0, (int32_t)p0});
+  f->nP = (int)bP.size();
+  std::vector<int32_t> counts(16, 0);
+  counts[3] = f->nP;
+  counts[6] = 1;
+  NSF_HIP(hipMemcpyAsync(A + L.X, d->X, (size_t)3 * P * 4, hipMemcpyHostToDevice, s));
+  NSF_HIP(hipMemcpyAsync(A + L.plan, ident.data(), ident.size() * 4, hipMemcpyHostToDevice, s));
+  NSF_HIP(hipMemsetAsync(A + L.u, 0, (size_t)3 * P * 4, s));
+  NSF_HIP(hipMemcpyAsync(A + L.v, v0.data(), v0.size() * 4, hipMemcpyHostToDevice, s));
+  NSF_HIP(hipMemsetAsync(A + L.tau, 0, (size_t)6 * P * 4, s));
+  NSF_HIP(hipMemsetAsync(A + L.C, 0, (size_t)9 * P * 4, s));
+  NSF_HIP(hipMemcpyAsync(A + L.F, F0.data(), F0.size() * 8, hipMemcpyHostToDevice, s));
+  const size_t n3 = (size_t)d->grid_n * d->grid_n * d->grid_n;
+  NSF_HIP(hipMemsetAsync(A + L.grid, 0, n3 * 16, s));
+  NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
+  NSF_HIP(hipMemsetAsync(A + L.flags, 0, 4, s));
+  NSF_HIP(hipMemsetAsync(A + L.bin_cnt, 0, L.bin_start - L.bin_cnt, s));
+  NSF_HIP(hipMemsetAsync(A + L.bin_epoch, 0, L.epoch + 4 - L.bin_epoch, s));
+  NSF_HIP(hipMemcpyAsync(A + L.counts, counts.data(), counts.size() * 4, hipMemcpyHostToDevice, s));
+  NSF_HIP(hipMemcpyAsync(A + L.bP, bP.data(), bP.size() * sizeof(BlockWork), hipMemcpyHostToDevice, s));
+  SimDev& H = f->hd;
+  H.r = 1;
+  H.n_part = (int32_t)P;
+  H.n_int = (int32_t)P;
+  H.n_samp = 0;
+  H.plan_steps = 1;
+  H.grid_n = d->grid_n;
+  H.wall = d->wall_nodes;
+  H.gn_iters = 1;
+  H.tangent_forms = 1;   // u_prev holds the velocity itself
+  H.ground = 1;
+  const double dx = 1.0 / d->grid_n, Vp = d->body_volume / (double)P;
+  H.dx = (float)dx;
+  H.inv_dx = (float)d->grid_n;
+  H.dt = (float)d->dt;
+  H.mp = (float)(d->rho * Vp);
+  H.stress_k = (float)(d->dt * Vp * 4.0 / (dx * dx));
+  for (int c = 0; c < 3; ++c) {
+    H.grav[c] = (float)d->gravity[c];
+    H.grav_d[c] = d->gravity[c];
+  }
+  H.dt_d = d->dt;
+  H.dx_d = dx;
+  H.fo_mu = d->youngs / (2.0 * (1.0 + d->poisson));
+  H.fo_lambda = d->youngs * d->poisson / ((1.0 + d->poisson) * (1.0 - 2.0 * d->poisson));
+  H.fo_tau_y = d->yield_stress;
+  H.X = reinterpret_cast<const float*>(A + L.X);
+  H.plan = reinterpret_cast<const int32_t*>(A + L.plan);
+  H.u_n = reinterpret_cast<float*>(A + L.u);
+  H.u_prev = reinterpret_cast<float*>(A + L.v);
+  H.tau = reinterpret_cast<float*>(A + L.tau);
+  H.C = reinterpret_cast<float*>(A + L.C);
+  H.F = reinterpret_cast<double*>(A + L.F);
+  H.grid = reinterpret_cast<float4*>(A + L.grid);
+  H.z = reinterpret_cast<double*>(A + L.z);
+  H.step = reinterpret_cast<int64_t*>(A + L.step);
+  H.flags = reinterpret_cast<uint32_t*>(A + L.flags);
+  H.bin_edge = bin_edge(d->grid_n);
+  H.nbs = bins_per_axis(d->grid_n);
+  H.n_bins = H.nbs * H.nbs * H.nbs;
+  H.bin_cnt = reinterpret_cast<int32_t*>(A + L.bin_cnt);
+  H.bin_start = reinterpret_cast<int32_t*>(A + L.bin_start);
+  H.seg_cnt = reinterpret_cast<int32_t*>(A + L.seg_cnt);
+  H.bin_epoch = reinterpret_cast<int32_t*>(A + L.bin_epoch);
+  H.epoch = reinterpret_cast<int32_t*>(A + L.epoch);
+  H.pbin = reinterpret_cast<int32_t*>(A + L.pbin);
+  H.prank = reinterpret_cast<int32_t*>(A + L.prank);
+  H.rec = reinterpret_cast<float*>(A + L.rec);
+  H.sorted = reinterpret_cast<int32_t*>(A + L.sorted);
+  H.active = reinterpret_cast<int32_t*>(A + L.active);
+  H.nonempty = reinterpret_cast<int32_t*>(A + L.nonempty);
+  H.n_active = reinterpret_cast<int32_t*>(A + L.n_active);
+  f->dd = reinterpret_cast<SimDev*>(A + L.simdev);
+  f->d_counts = reinterpret_cast<int32_t*>(A + L.counts);
+  f->d_bP = reinterpret_cast<BlockWork*>(A + L.bP);
+  NSF_HIP(hipMemcpyAsync(f->dd, &H, sizeof(SimDev), hipMemcpyHostToDevice, s));
+  NSF_HIP(hipStreamSynchronize(s));
+  *out = f.release();
+  return NSF_OK;
+}
+
+nsf_status nsf_fo_step(nsf_fo* f, int32_t n_steps, void* stream) {
+  if (!f) return fail(NSF_EINVAL, "full-order sim is NULL");
+  if (n_steps < 0) return fail(NSF_EINVAL, "n_steps < 0");
+  if (n_steps == 0) return NSF_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (s == nullptr) {
+    for (int i = 0; i < n_steps; ++i) {
+      const nsf_status st = fo_enqueue_step(*f, s);
+      if (st != NSF_OK) return st;
+    }
+    return NSF_OK;
+  }
+  if (!f->exec) {
+    NSF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const nsf_status st = fo_enqueue_step(*f, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != NSF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(NSF_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    f->graph = g;
+    NSF_HIP(hipGraphInstantiate(&f->exec, g, nullptr, nullptr, 0));
+  }
+  for (int i = 0; i < n_steps; ++i) NSF_HIP(hipGraphLaunch(f->exec, s));
+  return NSF_OK;
+}
+
+nsf_status nsf_fo_buffer(nsf_fo* f, int32_t which, void** ptr, int64_t* count) {
+  if (!f || !ptr || !count) return fail(NSF_EINVAL, "NULL argument");
+  const SimDev& H = f->hd;
+  const int64_t P = f->n_part;
+  switch (which) {
+    case NSF_FO_U: *ptr = H.u_n; *count = 3 * P; break;
+    case NSF_FO_V: *ptr = H.u_prev; *count = 3 * P; break;
+    case NSF_FO_C: *ptr = H.C; *count = 9 * P; break;
+    case NSF_FO_TAU: *ptr = H.tau; *count = 6 * P; break;
+    case NSF_FO_F: *ptr = H.F; *count = 9 * P; break;
+    default: return fail(NSF_EINVAL, "unknown full-order buffer %d", which);
+  }
+  return NSF_OK;
+}
+
+nsf_status nsf_fo_flags(nsf_fo* f, uint32_t* flags, void* stream) {
+  if (!f || !flags) return fail(NSF_EINVAL, "full-order sim or flags is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t v = 0;
+  NSF_HIP(hipMemcpyAsync(&v, f->hd.flags, 4, hipMemcpyDeviceToHost, st));
+  NSF_HIP(hipStreamSynchronize(st));
+  *flags = v;
+  if (v & FLAG_DOMAIN) return fail(NSF_EDOMAIN, "a particle stencil left the grid");
+  return NSF_OK;
+}
+
+nsf_status nsf_fo_destroy(nsf_fo* f) {
+  delete f;
+  return NSF_OK;
+}
+
+}  // extern "C"

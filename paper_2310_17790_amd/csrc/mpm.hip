@@ -350,7 +350,9 @@ __device__ __forceinline__ void node_velocity(const SimDev& S, float m, const fl
 #pragma unroll
   for (int c = 0; c < 3; ++c) out[c] = pm[c] / m + S.dt * S.grav[c];
   const int n = S.grid_n, b = S.wall;
-  if (i < b || j < b || k < b || i >= n - b || j >= n - b || k >= n - b) out[0] = out[1] = out[2] = 0.f;
+  const bool side = i < b || j < b || i >= n - b || j >= n - b || k >= n - b;
+  if (side || (k < b && !S.ground)) out[0] = out[1] = out[2] = 0.f;
+  else if (k < b) out[2] = fmaxf(out[2], 0.f);   // separating ground
   if (S.knife_on) {
     const double xi = i * S.dx_d, yi = j * S.dx_d, zi = k * S.dx_d;
     const double dist = S.kn[0] * xi + S.kn[1] * yi + S.kn[2] * zi - S.koff;
@@ -580,6 +582,182 @@ __global__ __launch_bounds__(kGnThreads) void g2p_gn_kernel(const SimDev* __rest
   }
 }
 
+// ---- full-order G2P, deformation update, return map, stress -------------------------
+// Every particle (identity integration list) after P2G and the grid update: v and the
+// APIC matrix C from the 27 stencil nodes, x += dt v (kept as the displacement u = x - X),
+// F_trial = (I + dt C) F^E, then the von Mises return map in log strain and the fixed
+// corotated stress of the new F^E, for the next step's P2G.
+//
+// The SVD F_trial = U S V^T comes from the symmetric eigen-decomposition
+// F_trial^T F_trial = V S^2 V^T (cyclic Jacobi rotations, FP64). U is never formed: with
+// G(h) = V diag(h) V^T, F^E = U diag(e^eps') V^T = F_trial G(e^eps' / S) and the polar
+// rotation R = U V^T = F_trial G(1 / S), whatever basis Jacobi picks inside a repeated
+// singular value.
+
+// A = V diag(A_ii) V^T in place (A symmetric 3 x 3; on return A is diagonal to rounding).
+__device__ void jacobi_eig3(double (&a)[3][3], double (&V)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 10; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (!(off > 1e-32 * dia)) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      const double apq = a[p][q];
+      if (apq == 0.0) continue;
+      // rotation J in the (p, q) plane that zeroes a_pq: t = tan, the smaller root of
+      // t^2 + 2 theta t - 1 = 0 with theta = (a_qq - a_pp) / (2 a_pq)
+      const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double akp = a[k][p], akq = a[k][q];
+        a[k][p] = c * akp - sn * akq;
+        a[k][q] = sn * akp + c * akq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double apk = a[p][k], aqk = a[q][k];
+        a[p][k] = c * apk - sn * aqk;
+        a[q][k] = sn * apk + c * aqk;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double vkp = V[k][p], vkq = V[k][q];
+        V[k][p] = c * vkp - sn * vkq;
+        V[k][q] = sn * vkp + c * vkq;
+      }
+    }
+  }
+}
+
+constexpr int kFoThreads = 256;
+
+__global__ __launch_bounds__(kFoThreads) void fo_g2p_kernel(const SimDev* __restrict__ sim) {
+  const SimDev& S = *sim;
+  const int p = blockIdx.x * kFoThreads + threadIdx.x;
+  if (p >= S.n_part) return;
+  if (p == 0) *S.step += 1;
+  const int n = S.grid_n;
+  const int64_t P = S.n_part;
+  float u[3], x[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    u[c] = S.u_n[c * P + p];
+    x[c] = S.X[c * P + p] + u[c];
+  }
+  const Stencil st = make_stencil(x, S.inv_dx, n);
+  if (!st.ok) {
+    flag(S, FLAG_DOMAIN);
+    return;
+  }
+  float v[3] = {0.f, 0.f, 0.f}, Cm[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float w = st.w[0][a] * st.w[1][b] * st.w[2][c];
+        const float4 g = S.grid[((int64_t)(st.base[0] + a) * n + st.base[1] + b) * n + st.base[2] + c];
+        const float vi[3] = {g.x, g.y, g.z};
+        const float d[3] = {((float)a - st.f[0]) * S.dx, ((float)b - st.f[1]) * S.dx, ((float)c - st.f[2]) * S.dx};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          v[r] += w * vi[r];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) Cm[3 * r + k] += w * vi[r] * d[k];
+        }
+      }
+  const float k4 = 4.f * S.inv_dx * S.inv_dx;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) Cm[e] *= k4;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    S.u_n[c * P + p] = u[c] + S.dt * v[c];
+    S.u_prev[c * P + p] = v[c];
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) S.C[e * P + p] = Cm[e];
+  // F_trial = (I + dt C) F^E
+  double F[3][3], Ft[3][3];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) F[e / 3][e % 3] = S.F[e * P + p];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double acc = F[r][c];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc += S.dt_d * (double)Cm[3 * r + k] * F[k][c];
+      Ft[r][c] = acc;
+    }
+  double A[3][3], V[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) A[r][c] = Ft[0][r] * Ft[0][c] + Ft[1][r] * Ft[1][c] + Ft[2][r] * Ft[2][c];
+  jacobi_eig3(A, V);
+  double sig[3], eps[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    sig[i] = sqrt(fmax(A[i][i], 0.0));
+    eps[i] = log(fmax(sig[i], 1e-12));
+  }
+  // von Mises in log strain
+  const double mean = (eps[0] + eps[1] + eps[2]) / 3.0;
+  const double eh[3] = {eps[0] - mean, eps[1] - mean, eps[2] - mean};
+  const double norm = sqrt(eh[0] * eh[0] + eh[1] * eh[1] + eh[2] * eh[2]);
+  const double dgamma = norm - S.fo_tau_y / (2.0 * S.fo_mu);
+  if (dgamma > 0.0 && norm > 0.0)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) eps[i] -= dgamma * eh[i] / norm;
+  double ge[3], gr[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double si = fmax(sig[i], 1e-300);
+    ge[i] = exp(eps[i]) / si;
+    gr[i] = 1.0 / si;
+  }
+  // F^E = Ft V diag(ge) V^T, R = Ft V diag(gr) V^T
+  double FE[3][3], R[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double me = 0.0, mr = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double fv = Ft[r][0] * V[0][k] + Ft[r][1] * V[1][k] + Ft[r][2] * V[2][k];
+        me += fv * ge[k] * V[c][k];
+        mr += fv * gr[k] * V[c][k];
+      }
+      FE[r][c] = me;
+      R[r][c] = mr;
+    }
+  const double J = exp(eps[0] + eps[1] + eps[2]);
+  double tau[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc += (FE[r][k] - R[r][k]) * FE[c][k];
+      tau[r][c] = 2.0 * S.fo_mu * acc + (r == c ? S.fo_lambda * (J - 1.0) * J : 0.0);
+    }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) S.F[e * P + p] = FE[e / 3][e % 3];
+  const double t6[6] = {tau[0][0], tau[1][1], tau[2][2], tau[1][2], tau[0][2], tau[0][1]};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) S.tau[c * P + p] = (float)t6[c];
+}
+
 // ---- integration set: closure of the sample stencils (Sec. 5.4) ----------------------
 // One closure sim per launch. Its integration list holds the samples in its first n_samp
 // entries (they never move) and the other members after them, by ascending particle
@@ -674,6 +852,13 @@ __global__ void closure_job_counts_kernel(const SimDev* __restrict__ sim, FieldJ
 }
 
 }  // namespace
+
+hipError_t launch_fo_g2p(const SimDev* sim, int64_t n_part, hipStream_t s) {
+  if (n_part < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fo_g2p_kernel, dim3((unsigned)((n_part + kFoThreads - 1) / kFoThreads)), dim3(kFoThreads), 0, s,
+                     sim);
+  return hipGetLastError();
+}
 
 hipError_t launch_closure(const SimDev* sim, int n_samp, int64_t n_part, FieldJob* jobs,
                           ListJobs list_jobs, hipStream_t s) {

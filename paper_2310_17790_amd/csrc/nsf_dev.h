@@ -125,6 +125,11 @@ struct SimDev {
   uint8_t* is_sample;                // [n_part]
   uint8_t* member;                   // [n_part] member of N \ S this step
   int32_t* cl_block;                 // [ceil(n_part / 1024)] members per workgroup
+  // full-order sims (every particle integrated; the reduced buffers hold the state:
+  // u_n = x - X, u_prev = v with tangent_forms = 1, tau, C)
+  int32_t ground, pad3;              // 1: the bottom wall layers only keep v_z >= 0
+  double* F;                         // [9][n_part] elastic deformation gradient
+  double fo_mu, fo_lambda, fo_tau_y;  // Lame parameters and yield stress
 };
 
 // Integration particles this step: the live length of a closure list, else n_int.
@@ -170,6 +175,10 @@ hipError_t launch_gn_partial(const SimDev* sims, const BlockWork* work, const in
                              int iter, int r_cap, int grid, hipStream_t s);
 hipError_t launch_gn_solve(const SimDev* sims, const int32_t* n_sims, int iter, int grid_sims,
                            hipStream_t s);
+// Full-order step after P2G: G2P of v and C for every particle, x += dt v, F update,
+// return map and the stress of the next step.
+hipError_t launch_fo_g2p(const SimDev* sim, int64_t n_part, hipStream_t s);
+
 // Integration set of one closure sim from its decoded positions: mark the samples' stencil
 // nodes, flag and count the members, write the list and its live length, and set the
 // point count of the field jobs over the list (jobs[idx[k]].n = live - p_off).
