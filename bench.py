@@ -26,6 +26,9 @@ The headline value is the plain FP32 single instance. The same line carries, und
     around the middle of the same slab, the integration particles the closure of their
     stencils recomputed every step (Sec. 5.4), the sample set cut to its first 400
     half-way; per phase latent steps/s, step latency and the closure's size.
+  full_order_fp32: the full-order MLS-MPM step (every one of the 200,000 particles
+    integrated, fixed corotated + von Mises, rho = 1000, E = 5e4, nu = 0.3, yield 2e3)
+    on the same slab, grid and dt, and how many times slower it is than the reduced step.
 """
 from __future__ import annotations
 
@@ -189,6 +192,33 @@ def closure_leg(precision, K, W, stream, torch, synth, Sim):
                 device_status=status, device_flags=flags)
 
 
+def full_order_leg(K, W, stream, torch, synth):
+    """The full-order step over the cake slab's 200,000 particles (same grid and dt)."""
+    from paper_2310_17790_amd.fullorder import FullOrderSim
+    wl = synth.cake_slab(seed=0, r=6, width=128, n=200_000, n_integration=1, steps=1, plan_steps=1)
+    fo = FullOrderSim(wl.X, (0.0, 0.0, 0.0), 1000.0, wl.body_volume, 5e4, 0.3, 2e3, wl.grid_n, wl.dt,
+                      gravity=wl.gravity, wall_nodes=wl.wall_nodes, stream=stream)
+    fo.step(max(W, 1), stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fo.step(K, stream=stream)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for i in range(K):
+        evs[i][0].record(stream)
+        fo.step(1, stream=stream)
+        evs[i][1].record(stream)
+    stream.synchronize()
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    status, flags = fo.flags(stream=stream)
+    fo.close()
+    return dict(steps_per_s=K / wall, ms_per_step=1e3 * wall / K, p50_step_ms=float(np.percentile(lat, 50)),
+                p99_step_ms=float(np.percentile(lat, 99)), particles=200_000, device_status=status,
+                device_flags=flags)
+
+
 def served_leg(n_requests, steps, budget_frac, torch, synth):
     """The continuous-batching server (BF16) over the Poisson request stream."""
     from paper_2310_17790_amd.serve import GpuBackend, Request, Server
@@ -247,7 +277,7 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="bf16_r6,bf16_r24,fp32_pipelined,bf16_pipelined,served_bf16,fit_bf16,"
-                                      "closure_fp32,closure_bf16",
+                                      "closure_fp32,closure_bf16,full_order_fp32",
                     help="comma-separated extra legs ('' for none)")
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--served-steps", type=int, default=1000)
@@ -310,6 +340,14 @@ def main() -> int:
             legs[name] = leg
         elif name == "fit_bf16":
             legs[name] = fit_leg(10, torch)
+        elif name == "full_order_fp32":
+            leg = full_order_leg(K, W, stream, torch, synth)
+            # how many reduced steps (the headline, and the closure set-up when measured) fit
+            # in one full-order step
+            leg["reduced_speedup"] = {"fp32_single": leg["ms_per_step"] / main_leg["ms_per_step"]}
+            if "closure_fp32" in legs:
+                leg["reduced_speedup"]["closure_fp32"] = leg["ms_per_step"] / legs["closure_fp32"]["ms_per_step"]
+            legs[name] = leg
         elif name in ("closure_fp32", "closure_bf16"):
             leg = closure_leg(name[-4:], K, W, stream, torch, synth, Sim)
             leg["vs_fp32_single"] = {"steps_per_s": leg["steps_per_s"] / main_leg["steps_per_s"]}
