@@ -249,6 +249,7 @@ struct Plan {
   int width = 0, gn_iters = 0, tc = 0;
   int r_cap = kMaxR;             // largest latent the Gauss-Newton chunk kernels serve
   int grid_cap = 256;            // largest grid_n the P2G kernels serve
+  bool place = true;             // some member may exceed kAllocByParticles integration particles
   bool bf16 = false, decode = false, pipelined = false, persistent = false;
   bool closure = false;           // its one member rebuilds its integration set every step
   ListJobs list_jobs{};           // closure: the jobs over the integration list
@@ -376,6 +377,8 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.grid_cap = 8;
   for (nsf_sim* m : P.members) P.grid_cap = std::max(P.grid_cap, m->hd.grid_n);
   if (P.persistent) P.grid_cap = 256;
+  P.place = P.persistent;
+  for (nsf_sim* m : P.members) P.place = P.place || m->n_int > kAllocByParticles;
   std::vector<SimDev> sims;
   std::vector<FieldJob> jobs;
   std::vector<FieldTile> tA_jac, tA_prim, tA_vel, tG, tG_vel, tD;  // tD: decode groups
@@ -646,7 +649,8 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
     const nsf_status st = fork_decode(P, s);
     if (st != NSF_OK) return st;
   }
-  NSF_HIP(launch_p2g_after_bin(P.d_sims, P.d_counts + 6, P.gSims, P.gBlk, P.closure, P.grid_cap, s));
+  NSF_HIP(launch_p2g_after_bin(P.d_sims, P.d_counts + 6, P.gSims, P.d_bP, P.d_counts + 3, P.gP, P.gBlk, P.closure,
+                               P.grid_cap, P.place, s));
   NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.r_cap, P.gGN, s));
   NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {
@@ -1216,7 +1220,8 @@ FoLayout fo_layout(const nsf_fo_desc* d) {
 
 nsf_status fo_enqueue_step(nsf_fo& f, hipStream_t s) {
   NSF_HIP(launch_bin(f.dd, f.d_bP, f.d_counts + 3, f.d_counts + 8, f.nP, s));
-  NSF_HIP(launch_p2g_after_bin(f.dd, f.d_counts + 6, 1, 5 * device_cus(), true, f.grid_n, s));
+  NSF_HIP(launch_p2g_after_bin(f.dd, f.d_counts + 6, 1, f.d_bP, f.d_counts + 3, f.nP, 5 * device_cus(), true,
+                               f.grid_n, f.n_part > kAllocByParticles, s));
   NSF_HIP(launch_fo_g2p(f.dd, f.n_part, s));
   return NSF_OK;
 }

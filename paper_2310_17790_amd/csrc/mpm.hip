@@ -12,11 +12,13 @@
 // Kernels of one step:
 //   bin      each integration particle finds its stencil base cell and its bin (a cube
 //            of bin_edge^3 cells), counts itself in the bin and remembers its rank;
-//   alloc    one workgroup per simulation: the first particle of each bin (in particle
-//            order) gets the bin's record slots from a block-wide prefix sum, the bin is
-//            listed as non-empty and the node blocks its particles reach are marked in an
-//            LDS bitmap, which is then compacted into the list of active node blocks;
-//            finally every particle writes its index at its bin's slot + rank;
+//   alloc    one workgroup per simulation: a block-wide prefix sum of the bin counts (over
+//            the first particle of each bin, or over the bins for large sets) gives each
+//            non-empty bin its record slots, the bin is listed as non-empty and the node
+//            blocks its particles reach are marked in an LDS bitmap, which is then
+//            compacted into the list of active node blocks;
+//   place    every particle writes its index at its bin's slot + rank (for small sets the
+//            allocation does it itself);
 //   sort     one workgroup per non-empty bin sorts the bin's indices and writes the P2G
 //            records (x, m v, A, index) in that order;
 //   gather   one workgroup per active node block stages, window by window, the records of
@@ -124,8 +126,8 @@ __global__ __launch_bounds__(kMpmBlock) void bin_kernel(const SimDev* __restrict
 
 // ---- allocate + place ---------------------------------------------------------------
 constexpr int kAllocThreads = 1024;
-constexpr int kAllocBatch = 8;    // particles per thread per batch of loads
 constexpr int kMaxBins = 32768;   // 32 bins per axis at most
+constexpr int kBinsPerThread = kMaxBins / kAllocThreads;   // contiguous bins per alloc thread
 
 // Exclusive scan of one value per thread over the workgroup; returns the prefix and the
 // workgroup total in *total.
@@ -156,70 +158,129 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wave_sums, int* 
   return excl;
 }
 
-__global__ __launch_bounds__(kAllocThreads) void alloc_place_kernel(const SimDev* __restrict__ sims,
-                                                                    const int32_t* __restrict__ n_sims) {
+// Slot allocation, one workgroup per sim, in one of two ways (both deterministic; where a
+// bin's slots lie does not change any sum):
+//  - up to kAllocByParticles particles it walks the particles: the first particle of each
+//    bin (rank 0) allocates the bin's slots from a workgroup prefix sum in particle order,
+//    and every particle is placed at its bin's slot + rank right away;
+//  - above that it walks the bins (a cost that does not grow with the particle count):
+//    thread t owns kBinsPerThread consecutive bins, the prefix sum runs in bin order, and
+//    place_kernel places the particles afterwards.
+// Either way the bin is listed as non-empty and its node blocks (bin + {0, 1}^3: the
+// stencils of its particles reach at most one block further on each axis) are marked in
+// an LDS bitmap, which is then compacted into the active-block list.
+constexpr int kAllocBatch = 8;               // particles per thread per batch of loads
+
+__device__ __forceinline__ void list_bin(const SimDev& S, int b, int c, int start, int ep, int& ne_pos,
+                                         uint32_t* mark) {
+  S.bin_cnt[b] = 0;   // counts start from zero next step
+  S.seg_cnt[b] = c;
+  S.bin_start[b] = start;
+  S.bin_epoch[b] = ep;
+  S.nonempty[ne_pos++] = b;
+  const int nbs = S.nbs;
+  const int bx = b / (nbs * nbs), by = (b / nbs) % nbs, bz = b % nbs;
+  for (int d = 0; d < 8; ++d) {
+    const int x = bx + (d >> 2), y = by + ((d >> 1) & 1), z = bz + (d & 1);
+    if (x < nbs && y < nbs && z < nbs) {
+      const int k = (x * nbs + y) * nbs + z;
+      atomicOr(&mark[k >> 5], 1u << (k & 31));
+    }
+  }
+}
+
+__device__ __forceinline__ int alloc_by_particles(const SimDev& S, int n, uint32_t* mark, int* wave_sums,
+                                                  int* s_start) {
+  const int tid = threadIdx.x;
+  // thread t owns particles t, t + T, t + 2T, ... (coalesced); loads go kAllocBatch at a
+  // time, and with one round (at most T kAllocBatch particles) they stay in registers
+  const int round = kAllocThreads * kAllocBatch;
+  const bool one = n <= round;
+  int pb[kAllocBatch], rk[kAllocBatch], cnt[kAllocBatch];
+  auto load = [&](int p0) {
+#pragma unroll
+    for (int u = 0; u < kAllocBatch; ++u) {
+      const int p = p0 + u * kAllocThreads + tid;
+      pb[u] = p < n ? S.pbin[p] : -1;
+      rk[u] = p < n ? S.prank[p] : 1;
+    }
+#pragma unroll
+    for (int u = 0; u < kAllocBatch; ++u) cnt[u] = (pb[u] >= 0 && rk[u] == 0) ? S.bin_cnt[pb[u]] : 0;
+  };
+  int local = 0, ne = 0;
+  for (int p0 = 0; p0 < n; p0 += round) {
+    load(p0);
+#pragma unroll
+    for (int u = 0; u < kAllocBatch; ++u) {
+      local += cnt[u];
+      ne += (pb[u] >= 0 && rk[u] == 0);
+    }
+  }
+  int used, n_ne;
+  int run = block_exclusive_scan(local, wave_sums, &used);
+  int ne_pos = block_exclusive_scan(ne, wave_sums, &n_ne);
+  const int ep = *S.epoch;
+  for (int p0 = 0; p0 < n; p0 += round) {
+    if (!one) load(p0);
+#pragma unroll
+    for (int u = 0; u < kAllocBatch; ++u) {
+      const int b = pb[u];
+      if (b < 0 || rk[u] != 0) continue;
+      s_start[b] = run;
+      list_bin(S, b, cnt[u], run, ep, ne_pos, mark);
+      run += cnt[u];
+    }
+  }
+  __syncthreads();
+  for (int p0 = 0; p0 < n; p0 += round) {
+    if (!one) load(p0);
+#pragma unroll
+    for (int u = 0; u < kAllocBatch; ++u)
+      if (pb[u] >= 0) S.sorted[s_start[pb[u]] + rk[u]] = p0 + u * kAllocThreads + tid;
+  }
+  return n_ne;
+}
+
+__device__ __forceinline__ int alloc_by_bins(const SimDev& S, uint32_t* mark, int* wave_sums) {
+  const int tid = threadIdx.x, nb = S.n_bins;
+  // the thread's bin counts, loaded together (all in flight at once) and kept
+  const int blo = tid * kBinsPerThread;
+  int cnt[kBinsPerThread];
+#pragma unroll
+  for (int u = 0; u < kBinsPerThread; ++u) cnt[u] = blo + u < nb ? S.bin_cnt[blo + u] : 0;
+  int local = 0, ne = 0;
+#pragma unroll
+  for (int u = 0; u < kBinsPerThread; ++u) {
+    local += cnt[u];
+    ne += cnt[u] > 0;
+  }
+  int used, n_ne;
+  int run = block_exclusive_scan(local, wave_sums, &used);
+  int ne_pos = block_exclusive_scan(ne, wave_sums, &n_ne);
+  const int ep = *S.epoch;
+#pragma unroll
+  for (int u = 0; u < kBinsPerThread; ++u) {
+    if (cnt[u] == 0) continue;
+    list_bin(S, blo + u, cnt[u], run, ep, ne_pos, mark);
+    run += cnt[u];
+  }
+  return n_ne;
+}
+
+__global__ __launch_bounds__(kAllocThreads) void alloc_kernel(const SimDev* __restrict__ sims,
+                                                              const int32_t* __restrict__ n_sims) {
   extern __shared__ int s_start[];              // [n_bins] first slot of each non-empty bin
   __shared__ uint32_t mark[kMaxBins / 32];      // node blocks reached this step
   __shared__ int wave_sums[kAllocThreads / 64];
   const int tid = threadIdx.x;
   for (int s = blockIdx.x; s < *n_sims; s += gridDim.x) {
     const SimDev& S = sims[s];
-    const int n = live_count(S), nb = S.n_bins, nbs = S.nbs;
-    const int nwords = (nb + 31) / 32;
+    const int n = live_count(S);
+    const int nwords = (S.n_bins + 31) / 32;
     for (int wd = tid; wd < nwords; wd += kAllocThreads) mark[wd] = 0u;
-    // Thread t owns particles t, t + T, t + 2T, ... (coalesced); the first particle of each
-    // bin (rank 0) allocates the bin. Loads are issued kAllocBatch at a time; with at most
-    // T kAllocBatch particles (one round) they are loaded once and kept in registers.
-    const int round = kAllocThreads * kAllocBatch;
-    const bool one = n <= round;
-    int pb[kAllocBatch], rk[kAllocBatch], cnt[kAllocBatch];
-    auto load = [&](int p0) {
-#pragma unroll
-      for (int u = 0; u < kAllocBatch; ++u) {
-        const int p = p0 + u * kAllocThreads + tid;
-        pb[u] = p < n ? S.pbin[p] : -1;
-        rk[u] = p < n ? S.prank[p] : 1;
-      }
-#pragma unroll
-      for (int u = 0; u < kAllocBatch; ++u) cnt[u] = (pb[u] >= 0 && rk[u] == 0) ? S.bin_cnt[pb[u]] : 0;
-    };
-    int local = 0, ne = 0;
-    for (int p0 = 0; p0 < n; p0 += round) {
-      load(p0);
-#pragma unroll
-      for (int u = 0; u < kAllocBatch; ++u) {
-        local += cnt[u];
-        ne += (pb[u] >= 0 && rk[u] == 0);
-      }
-    }
-    int used, n_ne;
-    int run = block_exclusive_scan(local, wave_sums, &used);
-    int ne_pos = block_exclusive_scan(ne, wave_sums, &n_ne);
-    const int ep = *S.epoch;
-    for (int p0 = 0; p0 < n; p0 += round) {
-      if (!one) load(p0);
-#pragma unroll
-      for (int u = 0; u < kAllocBatch; ++u) {
-        const int b = pb[u];
-        if (b < 0 || rk[u] != 0) continue;
-        S.bin_cnt[b] = 0;   // counts start from zero next step
-        S.seg_cnt[b] = cnt[u];
-        S.bin_start[b] = run;
-        S.bin_epoch[b] = ep;
-        s_start[b] = run;
-        run += cnt[u];
-        S.nonempty[ne_pos++] = b;
-        // node blocks reached by the bin's particles: bin + {0, 1}^3
-        const int bx = b / (nbs * nbs), by = (b / nbs) % nbs, bz = b % nbs;
-        for (int d = 0; d < 8; ++d) {
-          const int x = bx + (d >> 2), y = by + ((d >> 1) & 1), z = bz + (d & 1);
-          if (x < nbs && y < nbs && z < nbs) {
-            const int k = (x * nbs + y) * nbs + z;
-            atomicOr(&mark[k >> 5], 1u << (k & 31));
-          }
-        }
-      }
-    }
+    __syncthreads();
+    const int n_ne = n <= kAllocByParticles ? alloc_by_particles(S, n, mark, wave_sums, s_start)
+                                            : alloc_by_bins(S, mark, wave_sums);
     __syncthreads();
     // compact the marked node blocks in index order
     const int wper = (nwords + kAllocThreads - 1) / kAllocThreads;
@@ -236,18 +297,28 @@ __global__ __launch_bounds__(kAllocThreads) void alloc_place_kernel(const SimDev
         S.active[pos++] = wd * 32 + bit;
       }
     }
-    // place: every particle's index at its bin's slot + rank
-    for (int p0 = 0; p0 < n; p0 += round) {
-      if (!one) load(p0);
-#pragma unroll
-      for (int u = 0; u < kAllocBatch; ++u)
-        if (pb[u] >= 0) S.sorted[s_start[pb[u]] + rk[u]] = p0 + u * kAllocThreads + tid;
-    }
     if (tid == 0) {
       S.n_active[0] = n_act;
       S.n_active[1] = n_ne;
     }
     __syncthreads();
+  }
+}
+
+// Every integration particle's index at its bin's first slot + its rank.
+__global__ __launch_bounds__(kMpmBlock) void place_kernel(const SimDev* __restrict__ sims,
+                                                          const BlockWork* __restrict__ work,
+                                                          const int32_t* __restrict__ n_work) {
+  const int total = *n_work;
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    const BlockWork wk = work[b];
+    const SimDev& S = sims[wk.sim];
+    const int n = live_count(S);
+    if (n <= kAllocByParticles) continue;   // placed by the allocation itself
+    const int p = wk.p0 + threadIdx.x;
+    if (p >= n) continue;
+    const int pb = S.pbin[p];
+    if (pb >= 0) S.sorted[S.bin_start[pb] + S.prank[p]] = p;
   }
 }
 
@@ -881,16 +952,19 @@ hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32
 }
 
 hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int grid_sims,
-                                int grid_blocks, bool dense, int max_grid_n, hipStream_t s) {
+                                const BlockWork* work_int, const int32_t* n_work_int, int grid_particles,
+                                int grid_blocks, bool dense, int max_grid_n, bool place, hipStream_t s) {
   constexpr int alloc_lds = kMaxBins * 4;
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)alloc_place_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, alloc_lds);
+    const hipError_t e = hipFuncSetAttribute((const void*)alloc_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             alloc_lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(alloc_place_kernel, dim3(grid_sims), dim3(kAllocThreads), alloc_lds, s, sims, n_sims);
+  hipLaunchKernelGGL(alloc_kernel, dim3(grid_sims), dim3(kAllocThreads), alloc_lds, s, sims, n_sims);
+  if (place)
+    hipLaunchKernelGGL(place_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int);
   hipLaunchKernelGGL(bin_sort_kernel, dim3(grid_blocks), dim3(kSortThreads), 0, s, sims, n_sims);
   // 4^3-node blocks (one node per lane) up to 128^3 grids, 8^3 above
   const bool small = max_grid_n <= 128;

@@ -11,6 +11,9 @@ constexpr int kGnChunk = 128;      // sample points per Gauss-Newton reduction b
 constexpr int kGnThreads = 256;    // threads of a Gauss-Newton reduction block
 constexpr int kClaimCounters = 8;  // work-claim counters of the field kernels, zeroed per step
 constexpr int kMpmBlock = 256;     // particles per P2G / G2P block
+// up to this many integration particles the slot allocation places them itself; above
+// it a separate pass does (launch_p2g_after_bin's `place`)
+constexpr int kAllocByParticles = 32768;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -161,9 +164,11 @@ int fields_group_points(int tc);  // points one work group (table entry) spans
 hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
                       int32_t* claims, int grid_particles, hipStream_t s);
 // dense: the integration particles fill their cells (closure sims): wider gather
-// workgroups. max_grid_n bounds grid_n of every sim the launch can see.
+// workgroups. max_grid_n bounds grid_n of every sim the launch can see; place: some sim
+// may have more than kAllocByParticles integration particles.
 hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int grid_sims,
-                                int grid_blocks, bool dense, int max_grid_n, hipStream_t s);
+                                const BlockWork* work_int, const int32_t* n_work_int, int grid_particles,
+                                int grid_blocks, bool dense, int max_grid_n, bool place, hipStream_t s);
 // G2P at the sample particles fused with the first Gauss-Newton reduction: work items are
 // Gauss-Newton chunks (kGnChunk sample particles). r_cap (<= kMaxR) bounds the latent size
 // of every sim in the launch and sizes the chunk's LDS.

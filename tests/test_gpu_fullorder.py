@@ -82,3 +82,23 @@ def test_full_order_descriptor_validation():
         FullOrderSim(X, (0, 0, 0), 1000.0, 1.0, 5e4, 0.5, 2e3, 64, 1e-4)   # nu = 0.5
     with pytest.raises(A.NsfError):
         FullOrderSim(X, (0, 0, 0), 1000.0, 1.0, 5e4, 0.3, 0.0, 64, 1e-4)   # tau_y = 0
+
+
+def test_full_order_large_set_allocates_over_bins():
+    """Above 32,768 particles the slot allocation walks the bins and a separate pass places
+    the particles; 40,000 particles for 5 steps against the oracle (gate as above)."""
+    X = _cube(P=40_000, seed=12)
+    print("\n[case] full-order cube P=40000 grid=64", flush=True)
+    o = FO.FullOrder(X, (0.0, 0.0, -2.0), rho=1000.0, volume=0.2 ** 3, E=5e4, nu=0.3, tau_y=50.0, n=64, dt=1e-4)
+    s = torch.cuda.Stream()
+    g = FullOrderSim(X.T.astype(np.float32), (0.0, 0.0, -2.0), 1000.0, 0.2 ** 3, 5e4, 0.3, 50.0, 64, 1e-4,
+                     stream=s)
+    for _ in range(5):
+        o.step()
+    g.step(5, stream=s)
+    s.synchronize()
+    d = relative_error(g.positions().double().cpu().numpy().T, o.x)
+    print(f"delta_x={d:.2e}", flush=True)
+    assert d <= 1e-5
+    assert g.flags(stream=s) == (0, 0)
+    g.close()
