@@ -264,6 +264,7 @@ struct Plan {
   BlockWork *d_bP = nullptr, *d_bGN = nullptr;
   int nA = 0, nG = 0, nD = 0, nP = 0, nGN = 0, nsims = 0;
   int nAstep = 0, nGnext = 0;     // see build_plan (velocity job moved into the first G pass)
+  int nGvel = 0;                  // velocity groups at the start of the G table
   // launch grids (fixed for persistent plans)
   int gF = 0, gF0 = 0, gP = 0, gGN = 0, gSims = 0, gBlk = 0;
   FieldJob decode_job{};          // single-sim plans decode with the dense kernel
@@ -328,7 +329,11 @@ FieldJob base_job(const nsf_sim* s, int field, const double* z) {
 // one group per output component and pays off once forward mode needs more than two.
 bool reverse_jacobian(int ntan, int tc) { return ntan > 2 * tc; }
 
-void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc) {
+void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc, bool team = false) {
+  if (team && reverse_jacobian(ntan, tc)) {   // one workgroup per 16-point tile
+    for (int p0 = 0; p0 < n; p0 += 16) out.push_back({job, p0, 0, -2});
+    return;
+  }
   const int span = fields_group_points(ntan > 0 ? tc : 0);
   for (int p0 = 0; p0 < n; p0 += span) {
     if (ntan == 0) {
@@ -381,14 +386,17 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   for (nsf_sim* m : P.members) P.place = P.place || m->n_int > kAllocByParticles;
   std::vector<SimDev> sims;
   std::vector<FieldJob> jobs;
-  std::vector<FieldTile> tA_jac, tA_prim, tA_vel, tG, tG_vel, tD;  // tD: decode groups
+  std::vector<FieldTile> tA_jac, tA_prim, tA_team, tA_vel, tG, tG_vel, tD;  // tD: decode groups
+  // team Jacobian groups (half a primal group's time each) go after the primal groups
   std::vector<BlockWork> bP, bGN;
   // The FP32 velocity takes g at z_{n-1} on the step's points. Inside a step with at least
   // one iterate pass, the latent it needs (z_n) is known from the first Gauss-Newton solve
   // on, so that pass (which leaves part of the device idle) evaluates it for the next
   // step's points, after this step's P2G has read the buffer. The end-of-step inference
   // then skips it; a refresh outside a step still runs it at z_{n-1}.
-  const bool vel_in_g = !s0->bf16 && P.gn_iters >= 2 && !s0->closure;
+  // (solo plans: the first pass's groups then start at an offset its graph keeps)
+  const bool vel_in_g = !s0->bf16 && P.gn_iters >= 2 && !s0->closure && !P.persistent;
+  const bool team = fields_team_jacobian(P.width, P.bf16);
   for (size_t si = 0; si < P.members.size(); ++si) {
     nsf_sim* s = P.members[si];
     const SimDev& H = s->hd;
@@ -405,7 +413,8 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     FieldJob a = base_job(s, NSF_FIELD_G, zc);
     a.n = S; a.out = H.u_n; a.ldo = N; a.jac = H.J; a.ldj = S;
     jobs.push_back(a);
-    add_tiles(tA_jac, j0, S, r, P.tc);
+    if (team && reverse_jacobian(r, P.tc)) add_tiles(tA_team, j0, S, r, P.tc, true);
+    else add_tiles(tA_jac, j0, S, r, P.tc);
     if (N > S) {
       FieldJob b = base_job(s, NSF_FIELD_G, zc);
       b.n = N - S; b.p_off = S; b.out = H.u_n + S; b.ldo = N;
@@ -451,7 +460,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     // Gauss-Newton iterate: g and its Jacobian on S
     FieldJob g = base_job(s, NSF_FIELD_G, zi);
     g.n = S; g.out = H.u_gn; g.ldo = S; g.jac = H.J2; g.ldj = S;
-    add_tiles(tG, (int)jobs.size(), S, r, P.tc);
+    add_tiles(tG, (int)jobs.size(), S, r, P.tc, team);
     jobs.push_back(g);
     // decode all particles at the new latent
     // (a pipelined decode reads the snapshot of z_n the step's first kernel takes)
@@ -469,12 +478,16 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   // step's inference and the other G passes run a prefix of them.
   std::vector<FieldTile> tA(tA_jac);
   tA.insert(tA.end(), tA_prim.begin(), tA_prim.end());
+  tA.insert(tA.end(), tA_team.begin(), tA_team.end());
   tA.insert(tA.end(), tA_vel.begin(), tA_vel.end());
-  tG.insert(tG.end(), tG_vel.begin(), tG_vel.end());
+  // the first Gauss-Newton pass starts with the velocity groups (longer than team groups);
+  // later passes start after them
+  tG.insert(tG.begin(), tG_vel.begin(), tG_vel.end());
+  P.nGvel = (int)tG_vel.size();
   P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nD = (int)tD.size();
   P.nAstep = P.nA - (vel_in_g ? (int)tA_vel.size() : 0);
   P.nGnext = P.nG;
-  P.nG -= (int)tG_vel.size();
+  P.nG -= P.nGvel;
   P.nP = (int)bP.size(); P.nGN = (int)bGN.size();
   P.nsims = (int)sims.size();
   // work counts: [0] step inference, [1] G pass, [2] full inference, [3] MPM blocks,
@@ -654,7 +667,8 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
   NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.r_cap, P.gGN, s));
   NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG, P.d_counts + (k == 1 ? 4 : 1),
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG + (k == 1 ? 0 : P.nGvel),
+                                P.d_counts + (k == 1 ? 4 : 1),
                                 P.d_counts + kClaimG + (k - 1), P.gF, s));
     NSF_HIP(launch_gn_partial(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.r_cap, P.gGN, s));
     NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, k, P.gSims, s));

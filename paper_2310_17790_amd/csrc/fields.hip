@@ -591,6 +591,189 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
   }
 }
 
+// ---- reverse-mode Jacobian of one tile per workgroup (FP32, width 128) -----------------
+// The eight waves of a workgroup share one 16-point tile: wave q owns output block q (16
+// neurons) of every layer. A layer's product needs the whole previous layer as the MFMA
+// B operand, so each wave publishes its block through LDS (K-steps 4q .. 4q + 3 of the
+// operand, lane-major, conflict-free) and reads back all of them. The forward pass runs
+// once, phi'(a_1..a_4) of the wave's block stays in its registers, and the three output
+// components are pulled back together: three cotangent operands share each weight
+// fragment. Work per tile: 4 forward + 3 x 4 backward block products per wave, against
+// three groups of 8 full-layer products each with one tile per wave. The output layer's
+// dot products and du_c/dz = W1_z^T delta_1 are summed over the waves' blocks through LDS
+// in a fixed order.
+template <int W>
+__device__ __forceinline__ f32x4 layer1_block(const FieldJob& jb, const TilePoint& tp, int lane, int mb) {
+  const int g = lane >> 4, r = jb.r;
+  const int K1q = (r + 7) >> 2;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int s4 = 0; s4 < K1q; ++s4) {
+    const int k = 4 * s4 + g;
+    float b0 = 0.f;
+    if (k < 3) b0 = (k == 0) ? tp.X[0] : (k == 1) ? tp.X[1] : tp.X[2];
+    else if (k < 3 + r) b0 = (float)jb.z[k - 3];
+    else if (k == 3 + r) b0 = 1.f;
+    acc = mfma16(jb.w.w1q[(mb * K1q + s4) * 64 + lane], b0, acc);
+  }
+  return acc;
+}
+
+// LDS the team groups use beside the two weight buffers: three exchanged operands.
+template <int W>
+constexpr int team_lds_bytes() { return 3 * (W / 4) * 64 * 4; }
+
+template <int W, int WPG, class NextFn>
+__device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&& next, char* lds, int wave,
+                                             int lane) {
+  static_assert(W / 16 == WPG, "one output block per wave");
+  constexpr int LB = HiddenLayer<W, false>::kBytes;
+  constexpr int KS = W / 4, HS = W / 8;
+  const int g = lane >> 4, q = wave;
+  const TilePoint tp = tile_point(jb, p0, lane);
+  float* X = reinterpret_cast<float*>(lds + 2 * LB);   // [3][KS][64]
+  // stage i = 0..3: hidden layer i; i = 4..7: the transpose of hidden layer 7 - i
+  auto stage = [&](int i) -> const f32x2* {
+    wait_dma_and_sync();
+    if (i < 7) {
+      const int kn = i + 1;
+      dma_layer<W, false, WPG>(jb.w, kn < 4 ? kn : 7 - kn, lds + (kn & 1) * LB, wave, lane, kn >= 4);
+    } else if (const FieldPack* next_w = next()) {
+      dma_layer<W, false, WPG>(*next_w, 0, lds, wave, lane);
+    }
+    return reinterpret_cast<const f32x2*>(lds + (i & 1) * LB);
+  };
+  f32x4 a = layer1_block<W>(jb, tp, lane, q);
+  float D[4][4], h[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) elu_pair<false>(a[v], h[v], D[0][v]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[(4 * q + v) * 64 + lane] = h[v];
+    const f32x2* A2 = stage(k);   // the barrier publishes X; layer k is in LDS
+    float Hf[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) Hf[s] = X[s * 64 + lane];
+    __syncthreads();              // every wave holds its operand: X may be rewritten
+    a = *reinterpret_cast<const f32x4*>(jb.w.bhq + k * W + 16 * q + 4 * g);
+#pragma unroll
+    for (int hs = 0; hs < HS; ++hs) {
+      const f32x2 w = A2[(q * HS + hs) * 64 + lane];
+      a = mfma16(w[0], Hf[2 * hs], a);
+      a = mfma16(w[1], Hf[2 * hs + 1], a);
+    }
+    if (k < 3) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) elu_pair<false>(a[v], h[v], D[k + 1][v]);
+    }
+  }
+  // a = a_5 of block q. The primal output: per-block partial dot products, summed over the
+  // blocks in order by wave 0 (lanes 16 o + point).
+  float dphi5[4], h5[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) elu_pair<false>(a[v], h5[v], dphi5[v]);
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    const f32x4 w4 = *reinterpret_cast<const f32x4*>(jb.w.w6q + o * W + 16 * q + 4 * g);
+    float sdot = w4[0] * h5[0] + w4[1] * h5[1] + w4[2] * h5[2] + w4[3] * h5[3];
+    sdot += __shfl_xor(sdot, 16);
+    sdot += __shfl_xor(sdot, 32);
+    if (lane < 16) X[(q * 3 + o) * 16 + lane] = sdot;
+  }
+  __syncthreads();
+  if (q == 0 && lane < 48) {
+    const int o = lane >> 4, pt = lane & 15, p = p0 + pt;
+    float sum = 0.f;
+#pragma unroll
+    for (int qq = 0; qq < WPG; ++qq) sum += X[(qq * 3 + o) * 16 + pt];
+    if (p < jb.n) jb.out[o * jb.ldo + p] = jb.scale[o] * (sum + jb.w.b6[o]) + jb.shift[o];
+  }
+  __syncthreads();
+  // delta_5 of the three components, then back through W5^T .. W2^T
+  float d[3][4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const f32x4 w4 = *reinterpret_cast<const f32x4*>(jb.w.w6q + c * W + 16 * q + 4 * g);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[c][v] = w4[v] * dphi5[v];
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[(c * KS + 4 * q + v) * 64 + lane] = d[c][v];
+    const f32x2* A2 = stage(4 + j);
+    // the block's weight fragments once, then one component at a time (its operand read
+    // back, its 32 products), so only one exchanged operand is live
+    f32x2 wf[HS];
+#pragma unroll
+    for (int hs = 0; hs < HS; ++hs) wf[hs] = A2[(q * HS + hs) * 64 + lane];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      __builtin_amdgcn_sched_barrier(0);   // keep the next component's reads after these products
+      float Hc[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) Hc[s] = X[(c * KS + s) * 64 + lane];
+      f32x4 ac = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int hs = 0; hs < HS; ++hs) {
+        ac = mfma16(wf[hs][0], Hc[2 * hs], ac);
+        ac = mfma16(wf[hs][1], Hc[2 * hs + 1], ac);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) d[c][v] = ac[v] * D[3 - j][v];
+    }
+    __syncthreads();   // every wave has read the three operands: X may be rewritten
+  }
+  // d = delta_1 of block q (K-steps 4q + v of W1_z^T's product): partial du_c/dz over the
+  // block, rows in blocks of 16 (at most two), summed over the waves by wave c
+  const int r = jb.r, MZ = (r + 15) >> 4;
+  const f32x2* Z = reinterpret_cast<const f32x2*>(jb.w.w1zt);
+  f32x4 jz[3][2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) jz[c][0] = jz[c][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int mz = 0; mz < 2; ++mz) {
+    if (mz < MZ) {
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const f32x2 z2 = Z[((size_t)mz * HS + 2 * q + hh) * 64 + lane];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          jz[c][mz] = mfma16(z2[0], d[c][2 * hh], jz[c][mz]);
+          jz[c][mz] = mfma16(z2[1], d[c][2 * hh + 1], jz[c][mz]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int mz = 0; mz < 2; ++mz)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[((q * 2 + mz) * 4 + v) * 64 + lane] = jz[c][mz][v];
+    __syncthreads();
+    if (q == c) {
+      const int p = p0 + (lane & 15);
+#pragma unroll
+      for (int mz = 0; mz < 2; ++mz) {
+        if (mz < MZ) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float sum = 0.f;
+#pragma unroll
+            for (int qq = 0; qq < WPG; ++qq) sum += X[((qq * 2 + mz) * 4 + v) * 64 + lane];
+            const int jj = 16 * mz + 4 * g + v;
+            if (p < jb.n && jj < r) jb.jac[(c * r + jj) * jb.ldj + p] = jb.scale[c] * sum;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Run a group with its tangent count as a template argument (0 .. TC).
 template <int W, int TC, bool BF, int WPG, class NextFn>
 __device__ __forceinline__ void dispatch_nt(const FieldJob& jb, int p0, int t0, int nt,
@@ -644,7 +827,15 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
       g = gn;
       continue;
     }
-    if constexpr (TC > 0) {   // reverse-mode Jacobian groups come with the tangent tables
+    if constexpr (TC > 0 && !BF && W / 16 == WPG) {   // one tile per workgroup (nt == -2)
+      if (tl.nt == -2) {
+        run_rev_team<W, WPG>(jobs[tl.job], tl.p0, next, lds, wave, lane);
+        if (gn >= total) break;
+        g = gn;
+        continue;
+      }
+    }
+    if constexpr (TC > 0 && !(!BF && W / 16 == WPG)) {   // one wave per tile and component
       if (tl.nt < 0) {
         run_rev16<W, BF, WPG>(jobs[tl.job], tl.p0 + kTile16 * wave, tl.t0, next, lds, wave, lane);
         if (gn >= total) break;
@@ -739,7 +930,8 @@ template <int W, int TC, bool BF>
 hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int32_t* n_groups,
                         int32_t* claim, int grid, hipStream_t s) {
   constexpr int WPG = Wpg<TC>::value;
-  constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes;
+  constexpr bool team = TC > 0 && !BF && W / 16 == WPG;
+  constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes + (team ? team_lds_bytes<W>() : 0);
   auto k = fields_table_kernel<W, TC, BF, WPG>;
   static bool attr = false;
   if (!attr) {
@@ -808,6 +1000,8 @@ int fields_max_tangents(int width, bool bf16) {
 }
 
 int fields_group_points(int tc) { return kTile16 * (tc > 0 ? Wpg<1>::value : Wpg<0>::value); }
+
+bool fields_team_jacobian(int width, bool bf16) { return !bf16 && width / 16 == Wpg<1>::value; }
 
 hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
                                const FieldTile* groups, const int32_t* n_groups, int32_t* claim,

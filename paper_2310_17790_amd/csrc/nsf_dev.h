@@ -157,6 +157,9 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
                                hipStream_t s, bool beside = false);
 int fields_max_tangents(int width, bool bf16);
 int fields_group_points(int tc);  // points one work group (table entry) spans
+// Jacobians with more latent columns than forward mode carries take one workgroup per
+// 16-point tile (FieldTile.nt = -2) in this configuration
+bool fields_team_jacobian(int width, bool bf16);
 
 // MPM transfers: bin (per integration particle; also zeroes the step's claim counters and,
 // for pipelined decodes, snapshots z_n), then allocate and place (per sim), sort and write
