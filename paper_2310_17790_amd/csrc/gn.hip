@@ -36,61 +36,83 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Factor and solve in one wave (lane = threadIdx.x < 64). H and y live in LDS.
-__device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 1], double* y,
-                                 int* bad) {
-  const int r = S.r, tid = threadIdx.x;
-  for (int j = 0; j < r && *bad == 0; ++j) {
-    if (tid == 0) {
-      const double dj = H[j][j];
-      if (!(dj > 0.0)) *bad = 1;
-      else H[j][j] = sqrt(dj);
-    }
-    wave_sync();
-    if (*bad) break;
-    const double ljj = H[j][j];
-    for (int i = j + 1 + tid; i < r; i += 64) H[i][j] /= ljj;
-    wave_sync();
-    const int m = r - j - 1;
-    for (int e = tid; e < m * m; e += 64) {
-      const int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) H[i][k] -= H[i][j] * H[k][j];
-    }
-    wave_sync();
+// The latent values the update needs, loaded by lane j < r of the solving wave before
+// the partials are summed, so their latency overlaps that of the sums: the value the update
+// starts from (z_n at iteration 0, else the iterate) and z_n.
+struct GnLatent {
+  double base, zc;
+};
+
+__device__ __forceinline__ GnLatent load_latent(const SimDev& S, int iter) {
+  GnLatent L{0.0, 0.0};
+  const int j = threadIdx.x, r = S.r;
+  if (j < r) {
+    L.zc = S.z[r + j];
+    L.base = iter == 0 ? L.zc : S.z[2 * r + j];
   }
-  wave_sync();
-  if (*bad == 0) {
-    for (int j = 0; j < r; ++j) {            // L w = -b
-      if (tid == 0) y[j] /= H[j][j];
+  return L;
+}
+
+// Factor and solve in one wave (lane = threadIdx.x < 64), then update the latent.
+// Cholesky H = L L^T is right-looking, one column per round: every lane reads the pivot
+// d and forms sqrt(d) and its reciprocals itself; the trailing update subtracts
+// H[i][j] H[k][j] / d below the diagonal while column j is still unscaled, then the
+// column is scaled, so one wave synchronisation per column suffices. The substitutions
+// multiply by the stored reciprocal pivots idg. H, y and idg live in LDS; *bad (LDS) is
+// 2 if the summed system is not finite.
+__device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 1], double* y,
+                                 double* idg, const int* bad, const GnLatent& zl) {
+  const int r = S.r, tid = threadIdx.x;
+  int b = *bad;
+  if (b == 0) {
+    for (int j = 0; j < r; ++j) {
+      const double d = H[j][j];
+      if (!(d > 0.0)) {   // every lane read the same pivot
+        b = 1;
+        break;
+      }
+      const double l = sqrt(d), il = 1.0 / l, id = il * il;
+      const int m = r - j - 1;
+      for (int e = tid; e < m * m; e += 64) {
+        const int i = j + 1 + e / m, k = j + 1 + e % m;
+        if (k <= i) H[i][k] -= H[i][j] * H[k][j] * id;
+      }
+      for (int i = j + 1 + tid; i < r; i += 64) H[i][j] *= il;
+      if (tid == 0) {
+        H[j][j] = l;
+        idg[j] = il;
+      }
       wave_sync();
-      for (int i = j + 1 + tid; i < r; i += 64) y[i] -= H[i][j] * y[j];
+    }
+  }
+  if (b == 0) {
+    for (int j = 0; j < r; ++j) {            // L w = -b
+      const double t = y[j] * idg[j];
+      for (int i = j + 1 + tid; i < r; i += 64) y[i] -= H[i][j] * t;
+      if (tid == 0) y[j] = t;
       wave_sync();
     }
     for (int j = r - 1; j >= 0; --j) {       // L^T delta = w
-      if (tid == 0) y[j] /= H[j][j];
-      wave_sync();
-      for (int i = tid; i < j; i += 64) y[i] -= H[j][i] * y[j];
+      const double t = y[j] * idg[j];
+      for (int i = tid; i < j; i += 64) y[i] -= H[j][i] * t;
+      if (tid == 0) y[j] = t;
       wave_sync();
     }
   }
   const bool final_iter = (iter == S.gn_iters - 1);
-  double* zp = S.z;
-  double* zc = S.z + r;
-  double* zi = S.z + 2 * r;
-  if (tid == 0 && *bad) atomicOr(S.flags, (*bad & 2) ? FLAG_NONFINITE : FLAG_SINGULAR);
-  for (int j = tid; j < r; j += 64) {
-    const double base = (iter == 0) ? zc[j] : zi[j];
-    const double zn = *bad ? base : base + y[j];
+  if (tid == 0 && b) atomicOr(S.flags, (b & 2) ? FLAG_NONFINITE : FLAG_SINGULAR);
+  if (tid < r) {
+    const double zn = b ? zl.base : zl.base + y[tid];
     if (!isfinite(zn)) atomicOr(S.flags, FLAG_NONFINITE);
     if (final_iter) {
-      zp[j] = zc[j];
-      zc[j] = zn;
-      if (S.zh) S.zh[j] = zn;   // the stress field's latent input
+      S.z[tid] = zl.zc;
+      S.z[r + tid] = zn;
+      if (S.zh) S.zh[tid] = zn;   // the stress field's latent input
     } else {
-      zi[j] = zn;
+      S.z[2 * r + tid] = zn;
     }
   }
-  if (final_iter && tid == 0) *S.step += 1;
+  if (final_iter && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(S.step), 1ull);
 }
 
 // Iterations k >= 1: residual r = u(z^(k)) - u^n - dt v^{n+1}, from the field kernel's
@@ -144,6 +166,7 @@ __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* _
   __shared__ double part[kSolveThreads];
   __shared__ double H[kMaxR][kMaxR + 1];
   __shared__ double y[kMaxR];
+  __shared__ double idg[kMaxR];
   __shared__ int bad;
   const int tid = threadIdx.x;
   for (int si = blockIdx.x; si < *n_sims; si += gridDim.x) {
@@ -153,6 +176,7 @@ __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* _
     const int E = gn_entries_dev(r);
     const int G = E >= kSolveThreads ? 1 : kSolveThreads / E;
     if (tid == 0) bad = 0;
+    const GnLatent zl = load_latent(S, iter);
     __syncthreads();
     // Sum the chunk partials: thread (e, g) adds chunks g, g + G, ... (16 loads in flight
     // per batch, four running sums), then the G groups are added in a fixed order.
@@ -193,7 +217,7 @@ __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* _
       }
       __syncthreads();
     }
-    if (tid < 64) solve_and_update(S, iter, H, y, &bad);
+    if (tid < 64) solve_and_update(S, iter, H, y, idg, &bad, zl);
     __syncthreads();
   }
 }
