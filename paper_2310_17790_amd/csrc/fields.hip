@@ -112,12 +112,23 @@ __device__ __forceinline__ void activate16_bf16(const f32x4 (&acc)[T][W / 16], b
   }
 }
 
+// Weight-pack pointers taken from a job table in memory are generic; read through the
+// global address space, their loads are counted by the vector-memory counter alone, so a
+// product waits for the loads it needs and not for the LDS copies issued after them.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // Accumulators start from the layer's bias (plain order; none: zero) or zero (tangents).
-template <int W, int T>
+// LDS: the bias is in LDS (a generic pointer into it would be read with flat loads too).
+template <int W, int T, bool LDS = false>
 __device__ __forceinline__ void init16(f32x4 (&acc)[T][W / 16], const float* bias, int g) {
 #pragma unroll
   for (int mb = 0; mb < W / 16; ++mb) {
-    acc[0][mb] = bias ? *reinterpret_cast<const f32x4*>(bias + 16 * mb + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
+    if (!bias) acc[0][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    else if constexpr (LDS) acc[0][mb] = *reinterpret_cast<const f32x4*>(bias + 16 * mb + 4 * g);
+    else acc[0][mb] = *global_ptr(reinterpret_cast<const f32x4*>(bias + 16 * mb + 4 * g));
 #pragma unroll
     for (int t = 1; t < T; ++t) acc[t][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
@@ -249,6 +260,14 @@ __device__ __forceinline__ void wait_dma_and_sync() {
   __syncthreads();
 }
 
+// Workgroup barrier that orders LDS accesses only: it waits for the wave's LDS operations
+// but not for its global loads, so a weight copy in flight keeps going across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // The point of lane l in a 16-point tile starting at p0 (clamped for the ragged tail) and
 // its reference position.
 struct TilePoint {
@@ -322,7 +341,9 @@ __device__ __forceinline__ void layer1_16(const FieldJob& jb, const TilePoint& t
 //  - resident (RES = true, BF16 decode): all four hidden layers sit in LDS for the whole
 //    kernel, and waves run their tiles independently, without barriers.
 // Returns after the output layer.
-template <int W, int NT, bool BF, int WPG, bool RES = false, class NextFn>
+// BIAS_LDS: the four hidden layers' biases sit in LDS after the two layer buffers (a
+// kernel with one weight set); otherwise they are read from the pack in global memory.
+template <int W, int NT, bool BF, int WPG, bool RES = false, bool BIAS_LDS = false, class NextFn>
 __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, NextFn&& next,
                                             char* lds, int wave, int lane) {
   constexpr int MB = W / 16;
@@ -342,15 +363,18 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
   // Hidden layers 2..5 (k = 0..3). Streamed: wait for layer k in LDS, then start fetching
   // layer k + 1 (after the last layer: the next group's first layer) while k computes.
   // The last layer's activations stay FP32 for the FP32 output layer.
-  // Layer k's products (after its weights are in LDS) into acc.
+  // Layer k's products (after its weights are in LDS) into acc. The bias loads go out
+  // before the next layer's copy: loads complete in order, so the first product then
+  // waits for the bias alone and the copy overlaps the products.
   auto layer = [&](int k, auto&& hidden) {
     char* cur = lds + (RES ? k : (k & 1)) * LB;
+    if constexpr (!RES) wait_dma_and_sync();
+    if constexpr (BIAS_LDS) init16<W, T, true>(acc, reinterpret_cast<const float*>(lds + 2 * LB) + k * W, g);
+    else init16<W, T>(acc, jb.w.bhq + k * W, g);
     if constexpr (!RES) {
-      wait_dma_and_sync();
       if (k < 3) dma_layer<W, BF, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
       else if (const FieldPack* next_w = next()) dma_layer<W, BF, WPG>(*next_w, 0, lds, wave, lane);
     }
-    init16<W, T>(acc, jb.w.bhq + k * W, g);
     hidden(cur);
     if constexpr (NT == 0) save_preact16<W, T>(jb, acc, k + 1, p, valid, g);
   };
@@ -492,9 +516,12 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
   float H[1][W / 4];
   bf16x8 Hb[1][BF ? W / 32 : 1];
   activate_keep<W, BF>(acc, H, Hb, D[0]);
-  // stage i = 0..3: hidden layer i; i = 4..7: the transpose of hidden layer 7 - i
+  // stage i = 0..3: hidden layer i; i = 4..7: the transpose of hidden layer 7 - i. A
+  // forward stage loads its bias into acc between the barrier and the next copy (loads
+  // complete in order: the products then wait for the bias, not for the copy).
   auto stage = [&](int i) -> const char* {
     wait_dma_and_sync();
+    if (i < 4) init16<W, 1>(acc, jb.w.bhq + i * W, g);
     if (i < 7) {
       const int kn = i + 1;
       dma_layer<W, BF, WPG>(jb.w, kn < 4 ? kn : 7 - kn, lds + (kn & 1) * LB, wave, lane, kn >= 4);
@@ -511,13 +538,11 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const char* cur = stage(k);
-    init16<W, 1>(acc, jb.w.bhq + k * W, g);
     product(cur);
     activate_keep<W, BF>(acc, H, Hb, D[k + 1]);
   }
   {
     const char* cur = stage(3);
-    init16<W, 1>(acc, jb.w.bhq + 3 * W, g);
     product(cur);
   }
   // layer 5: the primal output from FP32 activations, then delta_5 = W6[c, :] . phi'(a_5)
@@ -642,6 +667,10 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
     }
     return reinterpret_cast<const f32x2*>(lds + (i & 1) * LB);
   };
+  // the block's bias of hidden layer k, loaded one stage ahead (the barrier that waits for
+  // the layer's copy also covers it)
+  auto bias = [&](int k) { return *global_ptr(reinterpret_cast<const f32x4*>(jb.w.bhq + k * W + 16 * q + 4 * g)); };
+  f32x4 bnext = bias(0);
   f32x4 a = layer1_block<W>(jb, tp, lane, q);
   float D[4][4], h[4];
 #pragma unroll
@@ -651,11 +680,12 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
 #pragma unroll
     for (int v = 0; v < 4; ++v) X[(4 * q + v) * 64 + lane] = h[v];
     const f32x2* A2 = stage(k);   // the barrier publishes X; layer k is in LDS
+    a = bnext;
+    if (k < 3) bnext = bias(k + 1);
     float Hf[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) Hf[s] = X[s * 64 + lane];
-    __syncthreads();              // every wave holds its operand: X may be rewritten
-    a = *reinterpret_cast<const f32x4*>(jb.w.bhq + k * W + 16 * q + 4 * g);
+    lds_barrier();              // every wave holds its operand: X may be rewritten
 #pragma unroll
     for (int hs = 0; hs < HS; ++hs) {
       const f32x2 w = A2[(q * HS + hs) * 64 + lane];
@@ -680,7 +710,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
     sdot += __shfl_xor(sdot, 32);
     if (lane < 16) X[(q * 3 + o) * 16 + lane] = sdot;
   }
-  __syncthreads();
+  lds_barrier();
   if (q == 0 && lane < 48) {
     const int o = lane >> 4, pt = lane & 15, p = p0 + pt;
     float sum = 0.f;
@@ -688,7 +718,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
     for (int qq = 0; qq < WPG; ++qq) sum += X[(qq * 3 + o) * 16 + pt];
     if (p < jb.n) jb.out[o * jb.ldo + p] = jb.scale[o] * (sum + jb.w.b6[o]) + jb.shift[o];
   }
-  __syncthreads();
+  lds_barrier();
   // delta_5 of the three components, then back through W5^T .. W2^T
   float d[3][4];
 #pragma unroll
@@ -724,7 +754,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
 #pragma unroll
       for (int v = 0; v < 4; ++v) d[c][v] = ac[v] * D[3 - j][v];
     }
-    __syncthreads();   // every wave has read the three operands: X may be rewritten
+    lds_barrier();   // every wave has read the three operands: X may be rewritten
   }
   // d = delta_1 of block q (K-steps 4q + v of W1_z^T's product): partial du_c/dz over the
   // block, rows in blocks of 16 (at most two), summed over the waves by wave c
@@ -753,7 +783,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
     for (int mz = 0; mz < 2; ++mz)
 #pragma unroll
       for (int v = 0; v < 4; ++v) X[((q * 2 + mz) * 4 + v) * 64 + lane] = jz[c][mz][v];
-    __syncthreads();
+    lds_barrier();
     if (q == c) {
       const int p = p0 + (lane & 15);
 #pragma unroll
@@ -770,7 +800,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -883,12 +913,16 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, in
   const int G = gridDim.x, b = blockIdx.x, per_round = G * WPG;
   if (2 * b >= n_tiles) return;
   dma_layer<W, false, WPG>(job.w, 0, lds, wave, lane);
+  // the four hidden layers' biases, once, after the two layer buffers (published by the
+  // first layer's barrier)
+  float* bias = reinterpret_cast<float*>(lds + 2 * HiddenLayer<W, false>::kBytes);
+  for (int i = threadIdx.x; i < 4 * W; i += 64 * WPG) bias[i] = job.w.bhq[i];
 #pragma unroll 1
   for (int base = 0; base + 2 * b < n_tiles; base += per_round) {
     const bool more = base + per_round + 2 * b < n_tiles;
     auto next = [&]() -> const FieldPack* { return more ? &job.w : nullptr; };
     const int t = dense_tile(base, wave, G, b);
-    if (t < n_tiles) run_group16<W, 0, false, WPG>(job, t * kTile16, 0, next, lds, wave, lane);
+    if (t < n_tiles) run_group16<W, 0, false, WPG, false, true>(job, t * kTile16, 0, next, lds, wave, lane);
     else idle_group<W, false, WPG>(job, next, lds, wave, lane);
   }
 }
@@ -962,7 +996,7 @@ constexpr int kDenseWpg = 12, kDenseResWpg = 16;
 
 template <int W, int WPG>
 hipError_t launch_dense(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
-  constexpr int lds = 2 * HiddenLayer<W, false>::kBytes;
+  constexpr int lds = 2 * HiddenLayer<W, false>::kBytes + 4 * W * 4;   // + the biases
   auto k = fields_dense_kernel<W, WPG>;
   static int per_cu = 0;
   int grid = 0;
