@@ -341,9 +341,39 @@ __device__ __forceinline__ void layer1_16(const FieldJob& jb, const TilePoint& t
 //  - resident (RES = true, BF16 decode): all four hidden layers sit in LDS for the whole
 //    kernel, and waves run their tiles independently, without barriers.
 // Returns after the output layer.
-// BIAS_LDS: the four hidden layers' biases sit in LDS after the two layer buffers (a
-// kernel with one weight set); otherwise they are read from the pack in global memory.
-template <int W, int NT, bool BF, int WPG, bool RES = false, bool BIAS_LDS = false, class NextFn>
+// A kernel that evaluates one weight set (the decode) keeps its small parameters in LDS
+// after the two layer buffers, copied once per launch (floats): the four hidden biases
+// (4 W), the output rows (up to 9 W), layer 1's B-operand rows k >= 3 (the latent, the
+// bias row 1, zeros: 64) and layer 1's A fragments (W / 16 x up to 9 K-steps x 64 lanes).
+// Tiles then start and end without waiting for global memory.
+template <int W>
+struct ParamsLds {
+  static constexpr int kBias = 0, kOut = 4 * W, kZ = 13 * W, kW1 = 13 * W + 64;
+  static constexpr int kFloats = kW1 + (W / 16) * ((kMaxR + 7) / 4) * 64;
+};
+
+// Layer 1 of a primal tile with its A fragments and latent rows in LDS (see ParamsLds).
+template <int W>
+__device__ __forceinline__ void layer1_16_lds(const FieldJob& jb, const TilePoint& tp, int lane,
+                                              f32x4 (&acc)[1][W / 16], const float* prm) {
+  constexpr int MB = W / 16;
+  const int g = lane >> 4;
+  const int K1q = (jb.r + 7) >> 2;
+  const float* zrow = prm + ParamsLds<W>::kZ;
+  const float* w1 = prm + ParamsLds<W>::kW1;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) acc[0][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int s4 = 0; s4 < K1q; ++s4) {
+    const int k = 4 * s4 + g;
+    const float b0 = k < 3 ? ((k == 0) ? tp.X[0] : (k == 1) ? tp.X[1] : tp.X[2]) : zrow[k];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[0][mb] = mfma16(w1[(mb * K1q + s4) * 64 + lane], b0, acc[0][mb]);
+  }
+}
+
+// PARAMS_LDS: the weight set's small parameters are in LDS (ParamsLds; primal groups
+// only); otherwise they are read from the pack in global memory.
+template <int W, int NT, bool BF, int WPG, bool RES = false, bool PARAMS_LDS = false, class NextFn>
 __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, NextFn&& next,
                                             char* lds, int wave, int lane) {
   constexpr int MB = W / 16;
@@ -357,7 +387,13 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
   const int r = jb.r;
   const bool jvp = jb.jvp != 0;
   f32x4 acc[T][MB];
-  layer1_16<W, T, NT>(jb, tp, t0, lane, acc);
+  const float* prm = reinterpret_cast<const float*>(lds + 2 * LB);   // PARAMS_LDS only
+  if constexpr (PARAMS_LDS) {
+    static_assert(NT == 0 && !BF && !RES, "LDS parameters serve the FP32 primal");
+    layer1_16_lds<W>(jb, tp, lane, acc, prm);
+  } else {
+    layer1_16<W, T, NT>(jb, tp, t0, lane, acc);
+  }
   if constexpr (NT == 0) save_preact16<W, T>(jb, acc, 0, p, valid, g);
 
   // Hidden layers 2..5 (k = 0..3). Streamed: wait for layer k in LDS, then start fetching
@@ -369,7 +405,7 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
   auto layer = [&](int k, auto&& hidden) {
     char* cur = lds + (RES ? k : (k & 1)) * LB;
     if constexpr (!RES) wait_dma_and_sync();
-    if constexpr (BIAS_LDS) init16<W, T, true>(acc, reinterpret_cast<const float*>(lds + 2 * LB) + k * W, g);
+    if constexpr (PARAMS_LDS) init16<W, T, true>(acc, prm + ParamsLds<W>::kBias + k * W, g);
     else init16<W, T>(acc, jb.w.bhq + k * W, g);
     if constexpr (!RES) {
       if (k < 3) dma_layer<W, BF, WPG>(jb.w, k + 1, lds + ((k + 1) & 1) * LB, wave, lane);
@@ -419,7 +455,8 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
   if (t0 == 0) {
 #pragma unroll 1
     for (int o = 0; o < d; ++o) {
-      const float y = output_dot16<W>(jb.w.w6q, o, g, H[0]) + jb.w.b6[o];
+      const float* w6 = PARAMS_LDS ? prm + ParamsLds<W>::kOut : jb.w.w6q;
+      const float y = output_dot16<W>(w6, o, g, H[0]) + jb.w.b6[o];
       float v = jb.scale[o] * y + jb.shift[o];
       if (jb.mode == 1) v += ((o == 0) ? tp.X[0] : (o == 1) ? tp.X[1] : tp.X[2]);
       if (valid && g == (o & 3)) jb.out[o * jb.ldo + p] = v;
@@ -903,8 +940,10 @@ __device__ __forceinline__ int dense_tile(int base, int wave, int G, int b) {
   return base + (wave >> 1) * 2 * G + 2 * b + (wave & 1);
 }
 
-// One job over n points (FP32 decode), weights streamed, persistent workgroups.
-template <int W, int WPG>
+// One job over n points (FP32 decode), weights streamed, persistent workgroups. PL: the
+// job's small parameters are copied to LDS once (ParamsLds; a job with one latent for all
+// points), else read from global memory (per-point latents of the training forward).
+template <int W, int WPG, bool PL>
 __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, int n_tiles) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int lane = threadIdx.x & 63;
@@ -913,16 +952,26 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, in
   const int G = gridDim.x, b = blockIdx.x, per_round = G * WPG;
   if (2 * b >= n_tiles) return;
   dma_layer<W, false, WPG>(job.w, 0, lds, wave, lane);
-  // the four hidden layers' biases, once, after the two layer buffers (published by the
-  // first layer's barrier)
-  float* bias = reinterpret_cast<float*>(lds + 2 * HiddenLayer<W, false>::kBytes);
-  for (int i = threadIdx.x; i < 4 * W; i += 64 * WPG) bias[i] = job.w.bhq[i];
+  // the weight set's small parameters, once, after the two layer buffers (the first
+  // tile's layer 1 reads them before any layer barrier: published by their own)
+  float* prm = reinterpret_cast<float*>(lds + 2 * HiddenLayer<W, false>::kBytes);
+  if constexpr (PL) {
+    const int K1q = (job.r + 7) >> 2, n1 = (W / 16) * K1q * 64;
+    for (int i = threadIdx.x; i < 4 * W; i += 64 * WPG) prm[ParamsLds<W>::kBias + i] = job.w.bhq[i];
+    for (int i = threadIdx.x; i < job.d * W; i += 64 * WPG) prm[ParamsLds<W>::kOut + i] = job.w.w6q[i];
+    for (int i = threadIdx.x; i < n1; i += 64 * WPG) prm[ParamsLds<W>::kW1 + i] = job.w.w1q[i];
+    if (threadIdx.x < 64) {
+      const int k = threadIdx.x;
+      prm[ParamsLds<W>::kZ + k] = (k >= 3 && k < 3 + job.r) ? (float)job.z[k - 3] : (k == 3 + job.r ? 1.f : 0.f);
+    }
+    lds_barrier();
+  }
 #pragma unroll 1
   for (int base = 0; base + 2 * b < n_tiles; base += per_round) {
     const bool more = base + per_round + 2 * b < n_tiles;
     auto next = [&]() -> const FieldPack* { return more ? &job.w : nullptr; };
     const int t = dense_tile(base, wave, G, b);
-    if (t < n_tiles) run_group16<W, 0, false, WPG, false, true>(job, t * kTile16, 0, next, lds, wave, lane);
+    if (t < n_tiles) run_group16<W, 0, false, WPG, false, PL>(job, t * kTile16, 0, next, lds, wave, lane);
     else idle_group<W, false, WPG>(job, next, lds, wave, lane);
   }
 }
@@ -994,16 +1043,23 @@ hipError_t decode_grid(K k, int wpg, int lds, int cus, int* per_cu, int* grid) {
 // fastest measured.
 constexpr int kDenseWpg = 12, kDenseResWpg = 16;
 
-template <int W, int WPG>
-hipError_t launch_dense(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
-  constexpr int lds = 2 * HiddenLayer<W, false>::kBytes + 4 * W * 4;   // + the biases
-  auto k = fields_dense_kernel<W, WPG>;
+template <int W, int WPG, bool PL>
+hipError_t launch_dense_pl(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
+  constexpr int lds = 2 * HiddenLayer<W, false>::kBytes + (PL ? ParamsLds<W>::kFloats * 4 : 0);
+  static_assert(lds <= 160 * 1024, "layer buffers and parameters must fit in LDS");
+  auto k = fields_dense_kernel<W, WPG, PL>;
   static int per_cu = 0;
   int grid = 0;
   const hipError_t e = decode_grid(k, WPG, lds, cus, &per_cu, &grid);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, job, n_tiles);
   return hipGetLastError();
+}
+
+template <int W, int WPG>
+hipError_t launch_dense(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
+  const bool pl = job.zrows == nullptr && job.jvp == 0 && job.r <= kMaxR && job.d <= 9;
+  return pl ? launch_dense_pl<W, WPG, true>(job, n_tiles, cus, s) : launch_dense_pl<W, WPG, false>(job, n_tiles, cus, s);
 }
 
 // BF16: all four hidden layers resident (4 W^2 x 2 B = 128 KB at width 128).
