@@ -708,6 +708,20 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
   // the layer's copy also covers it)
   auto bias = [&](int k) { return *global_ptr(reinterpret_cast<const f32x4*>(jb.w.bhq + k * W + 16 * q + 4 * g)); };
   f32x4 bnext = bias(0);
+  // the block's output rows and latent-column fragments of layer 1, used only at the end
+  // of the tile, are loaded now: their latency then passes under the hidden layers
+  // instead of stalling all eight waves together
+  f32x4 w6v[3];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) w6v[o] = *reinterpret_cast<const f32x4*>(jb.w.w6q + o * W + 16 * q + 4 * g);
+  const int MZ = (jb.r + 15) >> 4;
+  const f32x2* Z = reinterpret_cast<const f32x2*>(jb.w.w1zt);
+  f32x2 zf[2][2];
+#pragma unroll
+  for (int mz = 0; mz < 2; ++mz)
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh)
+      zf[mz][hh] = mz < MZ ? Z[((size_t)mz * HS + 2 * q + hh) * 64 + lane] : f32x2{0.f, 0.f};
   f32x4 a = layer1_block<W>(jb, tp, lane, q);
   float D[4][4], h[4];
 #pragma unroll
@@ -741,7 +755,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
   for (int v = 0; v < 4; ++v) elu_pair<false>(a[v], h5[v], dphi5[v]);
 #pragma unroll
   for (int o = 0; o < 3; ++o) {
-    const f32x4 w4 = *reinterpret_cast<const f32x4*>(jb.w.w6q + o * W + 16 * q + 4 * g);
+    const f32x4 w4 = w6v[o];
     float sdot = w4[0] * h5[0] + w4[1] * h5[1] + w4[2] * h5[2] + w4[3] * h5[3];
     sdot += __shfl_xor(sdot, 16);
     sdot += __shfl_xor(sdot, 32);
@@ -760,7 +774,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
   float d[3][4];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const f32x4 w4 = *reinterpret_cast<const f32x4*>(jb.w.w6q + c * W + 16 * q + 4 * g);
+    const f32x4 w4 = w6v[c];
 #pragma unroll
     for (int v = 0; v < 4; ++v) d[c][v] = w4[v] * dphi5[v];
   }
@@ -795,8 +809,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
   }
   // d = delta_1 of block q (K-steps 4q + v of W1_z^T's product): partial du_c/dz over the
   // block, rows in blocks of 16 (at most two), summed over the waves by wave c
-  const int r = jb.r, MZ = (r + 15) >> 4;
-  const f32x2* Z = reinterpret_cast<const f32x2*>(jb.w.w1zt);
+  const int r = jb.r;
   f32x4 jz[3][2];
 #pragma unroll
   for (int c = 0; c < 3; ++c) jz[c][0] = jz[c][1] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -805,7 +818,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
     if (mz < MZ) {
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
-        const f32x2 z2 = Z[((size_t)mz * HS + 2 * q + hh) * 64 + lane];
+        const f32x2 z2 = zf[mz][hh];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           jz[c][mz] = mfma16(z2[0], d[c][2 * hh], jz[c][mz]);
