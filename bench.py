@@ -51,7 +51,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # dense MFMA peaks of MI355X
 # by what the same counter reads for a plain 256 MiB device copy (bench.py --copy-probe:
 # FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them). Valid only for the
 # kernel source they were taken on (SHA-256 of csrc/fields.hip); null otherwise.
-DECODE_COUNTERS = {"fields_hip_sha256": "5935b5a20eda3853988501bbbfe06337224ab8068af82a9762306010875f954a",
+DECODE_COUNTERS = {"fields_hip_sha256": "14d3fce45c7c292a43a0f7892e8cafc6436ad71e073e9bea9f7c3ab73001598a",
                    "fetch_kib": 2349.4, "write_kib": 2343.75, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
