@@ -297,8 +297,8 @@ def main() -> int:
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 5}))
         return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only: the latent step of one "
-                                   "simulation is not sharded across GPUs in this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the library steps each "
+                                   "simulation on one device and has no multi-GPU path",
                           "n_gpus": args.gpus}))
         return 2
 
