@@ -55,6 +55,31 @@ DECODE_COUNTERS = {"fields_hip_sha256": "14d3fce45c7c292a43a0f7892e8cafc6436ad71
                    "fetch_kib": 2349.4, "write_kib": 2343.75, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
+# HBM bytes of one MPM stage (bin, alloc, place, bin_sort, gather, g2p_gn summed), from two
+# rocprofv3 --pmc passes over `bench.py --legs p2g_served` (FETCH_SIZE, then WRITE_SIZE, KiB
+# per dispatch, summed over the stage's kernels and averaged over the timed calls), scaled
+# like the decode's. Valid only for the kernel source they were taken on (SHA-256 of
+# csrc/mpm.hip).
+MPM_COUNTERS = {"mpm_hip_sha256": None,
+                "single": {"fetch_kib": None, "write_kib": None},
+                "served": {"fetch_kib": None, "write_kib": None},
+                "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def mpm_traffic_bytes(which):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2310_17790_amd", "csrc", "mpm.hip")
+    c = MPM_COUNTERS
+    if c["mpm_hip_sha256"] is None or not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != c["mpm_hip_sha256"]:
+        return None
+    k = c[which]
+    if k["fetch_kib"] is None:
+        return None
+    return 1024.0 * (k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"])
+
+
 def decode_traffic_bytes():
     import hashlib
     src = os.path.join(ROOT, "paper_2310_17790_amd", "csrc", "fields.hip")
@@ -87,6 +112,61 @@ def step_flops(width, r, n_int, n_samp, n_part, gn_iters=2):
     g = (gn_iters - 1) * n_samp * (primal_flops(width, r, 3) + tangent_flops(width, r))
     d = n_part * primal_flops(width, r, 3)
     return a + g + d
+
+
+# ---- P2G / grid update / G2P: algorithmic bytes over the transfer kernels' time ----------
+# Per unit (the hot-path table's model of the transfers): 60 B per integration particle
+# (position, velocity, APIC/stress matrix read), 56 B per touched grid node (mass and
+# momentum written and read, velocity written and read), 24 B per sample particle (position
+# read, new velocity written). Dense-grid clears are work the method avoids and are not
+# counted.
+MPM_BYTES = {"per_integration": 60, "per_node": 56, "per_sample": 24}
+
+
+def touched_nodes(X, row, u, grid_n):
+    """Distinct grid nodes in the 27-node stencils of the integration particles x = X + u
+    (float32, as the kernels form it)."""
+    x = X[:, row].astype(np.float32) + u.astype(np.float32)
+    base = np.floor(x * np.float32(grid_n) - np.float32(0.5)).astype(np.int64)
+    o = np.array([(a, b, c) for a in range(3) for b in range(3) for c in range(3)], np.int64)
+    nodes = base.T[:, None, :] + o[None]
+    ids = (nodes[..., 0] * grid_n + nodes[..., 1]) * grid_n + nodes[..., 2]
+    return int(np.unique(ids).size)
+
+
+def mpm_units(sim, w, A):
+    """(integration particles, sample particles, touched nodes) of the sim's current step."""
+    _, _, step = sim.latent()
+    N = sim.n_integration
+    plan = sim.buffer(A.NSF_BUF_NLIST).cpu().numpy().reshape(-1, N)
+    row = plan[step % plan.shape[0]]
+    u = sim.buffer(A.NSF_BUF_U).cpu().numpy().reshape(3, N)
+    return N, sim.n_sample, touched_nodes(w.X, row, u, sim.grid_n)
+
+
+def mpm_stage_ms(sims, reps, stream, torch):
+    """Average duration of the MPM stage (binning, P2G with the grid update, G2P at the
+    samples) of the given sims, over reps back-to-back calls with HIP events on `stream`."""
+    from paper_2310_17790_amd.sim import mpm_stage
+    mpm_stage(sims, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        mpm_stage(sims, stream=stream)
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def mpm_roofline(units, ms, traffic):
+    N = sum(u[0] for u in units)
+    S = sum(u[1] for u in units)
+    T = sum(u[2] for u in units)
+    b = MPM_BYTES["per_integration"] * N + MPM_BYTES["per_node"] * T + MPM_BYTES["per_sample"] * S
+    gbs = b / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+            "traffic": traffic, "avg_us": 1e3 * ms, "algorithmic_bytes": b, "sims": len(units),
+            "integration": N, "samples": S, "touched_nodes": T}
 
 
 def cpu_baseline(workload, n_steps: int):
@@ -154,6 +234,8 @@ def single_leg(precision, r, K, W, stream, torch, synth, A, Sim, width=128, P=20
     wall, lat = time_steps(sim, K, stream, torch)
     status, flags = sim.flags(stream=stream)
     dec_ms = decode_kernel_ms(sim, P, max(K, 10), stream, torch, A)
+    p2g = mpm_roofline([mpm_units(sim, wl, A)], mpm_stage_ms([sim], max(K, 20), stream, torch),
+                       mpm_traffic_bytes("single"))
     achieved = P * primal_flops(width, r, 3) / (dec_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[precision]
     sim.close()
@@ -162,7 +244,7 @@ def single_leg(precision, r, K, W, stream, torch, synth, A, Sim, width=128, P=20
                 step_tflops=step_flops(width, r, NI, NI, P) / (wall / K) / 1e12,
                 device_status=status, device_flags=flags,
                 decode={"achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                        "avg_ms": dec_ms}), wl
+                        "avg_ms": dec_ms}, p2g=p2g), wl
 
 
 def closure_leg(precision, K, W, stream, torch, synth, Sim):
@@ -241,6 +323,27 @@ def served_leg(n_requests, steps, budget_frac, torch, synth):
     return st
 
 
+def p2g_served_leg(n_requests, reps, stream, torch, synth, A):
+    """The served mix's transfers with every request resident at once (BF16 sims, each
+    after one batched step): one MPM stage over all of them, timed as mpm_stage_ms."""
+    from paper_2310_17790_amd.sim import Sim, step_batch
+    sims, wls = [], []
+    for q in synth.served_mix(n_requests=n_requests):
+        w = synth.served_instance(q, width=128, steps=16, plan_steps=16)
+        sims.append(Sim(w, precision="bf16", stream=stream))
+        wls.append(w)
+    step_batch(sims, 1, stream=stream)
+    stream.synchronize()
+    ms = mpm_stage_ms(sims, reps, stream, torch)
+    units = [mpm_units(s, w, A) for s, w in zip(sims, wls)]
+    bad = [s.flags(stream=stream)[0] for s in sims]
+    for s in sims:
+        s.close()
+    out = mpm_roofline(units, ms, mpm_traffic_bytes("served"))
+    out["device_status"] = int(min(bad)) if bad else 0
+    return out
+
+
 def fit_leg(iters, torch):
     """One Adam iteration of the deformation field with per-snapshot latents at the fitting
     configuration: 2^18 (particle, snapshot) pairs per minibatch, r = 12, width 128, BF16
@@ -276,8 +379,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="bf16_r6,bf16_r24,fp32_pipelined,bf16_pipelined,served_bf16,fit_bf16,"
-                                      "closure_fp32,closure_bf16,full_order_fp32",
+    ap.add_argument("--legs", default="bf16_r6,bf16_r24,fp32_pipelined,bf16_pipelined,served_bf16,p2g_served,"
+                                      "fit_bf16,closure_fp32,closure_bf16,full_order_fp32",
                     help="comma-separated extra legs ('' for none)")
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--served-steps", type=int, default=1000)
@@ -340,6 +443,8 @@ def main() -> int:
             legs[name] = leg
         elif name == "fit_bf16":
             legs[name] = fit_leg(10, torch)
+        elif name == "p2g_served":
+            legs[name] = p2g_served_leg(args.served_requests, max(K, 20), stream, torch, synth, A)
         elif name == "full_order_fp32":
             leg = full_order_leg(K, W, stream, torch, synth)
             # how many reduced steps (the headline, and the closure set-up when measured) fit
@@ -415,6 +520,8 @@ def main() -> int:
                      "kernel": f"decode MLP (fields_dense_kernel, width {width}), {P} points, "
                                f"{primal_flops(width, r, 3)} FLOP/point",
                      "avg_ms": dec_ms},
+        "p2g_roofline": {"single": main_leg["p2g"], "served": legs.get("p2g_served"),
+                         "bytes_per_unit": MPM_BYTES},
         "cpu_baseline": res_cpu,
         "legs": legs,
     }

@@ -169,6 +169,18 @@ nsf_status nsf_step(nsf_sim *s, int32_t n_steps, void *stream);
  * their capacity). */
 nsf_status nsf_step_batch(nsf_sim *const *sims, int32_t n, int32_t n_steps, void *stream);
 
+/* The MPM stage of the current step alone (Sec. 5.2, with the algorithm of Sec. 3.3),
+ * async: P2G of the integration particles with APIC and the stress impulse, the grid
+ * update (gravity, walls, knife) and G2P of the new velocity at the samples, from the
+ * field inference the step starts from (run first if the sims do not hold it yet, as
+ * after create or nsf_set_latent). It writes NSF_BUF_GRID and NSF_BUF_VNEW and the first
+ * Gauss-Newton partial sums, exactly as the step's own MPM kernels do; it advances
+ * neither the latent nor the step counter, so repeated calls recompute the same values
+ * (the way to time the transfers alone). sims: host array of n distinct sims; n > 1
+ * runs one launch per kernel over the union of their work under the same rules as
+ * nsf_step_batch. */
+nsf_status nsf_mpm_stage(nsf_sim *const *sims, int32_t n, void *stream);
+
 /* Evaluate the fields at the current latent in one launch, async: decode all particles
  * into the decoded-position buffer (when decode_every_step is 1 or 2) and the field inference the
  * next step starts from (Sec. 5.1). nsf_step ends every step with this launch; call it
@@ -249,8 +261,9 @@ int32_t nsf_device_count(void);
  *   (width, n) elements, receiving the five hidden pre-activations for the backward in
  *   the kernels' internal format (scaled by log2 e; NULL = inference only).
  * nsf_mlp_backward: given dout [d][n] = dLoss/dout, accumulate (+=) dW (device, same
- *   layout and size as the weights) and write dz device [n][r] = dLoss/dz_rows (NULL to
- *   skip). Requires `saved` from the forward of the same weights and inputs.
+ *   layout and size as the weights), write dz device [n][r] = dLoss/dz_rows and dX device
+ *   [3][n] = dLoss/dX (SoA like X), each NULL to skip. Requires `saved` from the forward
+ *   of the same weights and inputs.
  * Precision: NSF_FP32 (also used by the finite-difference check) or NSF_BF16 (hidden
  * layers on BF16 MFMA, FP32 accumulation). */
 typedef struct {
@@ -267,30 +280,47 @@ nsf_status nsf_mlp_forward(const nsf_mlp *m, const float *X, const float *z_rows
                            void *stream);
 nsf_status nsf_mlp_backward(const nsf_mlp *m, const float *X, const float *z_rows, int64_t n,
                             const float *saved, const float *dout, float *dW, float *dz,
-                            void *workspace, size_t workspace_bytes, void *stream);
+                            float *dX, void *workspace, size_t workspace_bytes, void *stream);
 
 /* ---- Full-order MLS-MPM (the model the reduced step is measured against) -------------
  * Every particle is integrated (Sec. 3.3): P2G with APIC and the MLS stress impulse, grid
  * update with gravity, sticky walls and a separating ground (the bottom wall_nodes layers
- * keep v_z >= 0), G2P of v and C, F_trial = (I + dt C) F^E, the von Mises return map in
- * log strain and fixed corotated elasticity (supplementary "Elasticity and plasticity
- * details"): with F_trial = U S V^T, eps = log S, eps_hat = eps - mean(eps),
- * dgamma = |eps_hat| - tau_y / (2 mu); if dgamma > 0, eps -= dgamma eps_hat / |eps_hat|;
- * F^E = U exp(eps) V^T and tau = 2 mu (F^E - R) F^E^T + lambda (J - 1) J I, R = U V^T.
+ * keep v_z >= 0), G2P of v and C, F_trial = (I + dt C) F^E, then one of three return maps
+ * and its elasticity (supplementary "Elasticity and plasticity details"). With
+ * F_trial = U S V^T, eps = log S, eps_hat = eps - mean(eps):
+ *   NSF_FO_VON_MISES: dgamma = |eps_hat| - tau_y / (2 mu); if dgamma > 0,
+ *     eps -= dgamma eps_hat / |eps_hat|; F^E = U exp(eps) V^T; fixed corotated stress
+ *     tau = 2 mu (F^E - R) F^E^T + lambda (J - 1) J I, R = U V^T.
+ *   NSF_FO_DRUCKER_PRAGER: dgamma = |eps_hat| + alpha (3 lambda + 2 mu) sum(eps) / (2 mu),
+ *     alpha = sqrt(2/3) 2 sin(phi_f) / (3 - sin(phi_f)); sum(eps) > 0 gives F^E = U V^T,
+ *     dgamma <= 0 leaves F_trial, otherwise eps -= dgamma eps_hat / |eps_hat|; StVK stress
+ *     in log strain tau = U diag(2 mu eps + lambda sum(eps)) U^T.
+ *   NSF_FO_HERSCHEL_BULKLEY (h = 1): with bbar = J^(-2/3) S^2 and s_t = mu |dev(bbar)|, if
+ *     s_t > sqrt(2/3) tau_y the deviator is scaled to
+ *     s = s_t - (s_t - sqrt(2/3) tau_y) / (1 + viscosity / (2 mu dt)) and bbar becomes
+ *     (s / s_t) dev(bbar) + c I with det(bbar) = 1 (volume and rotations kept), so
+ *     F^E = U J^(1/3) sqrt(bbar) V^T; stress tau = kappa/2 (J^2 - 1) I + mu dev(bbar)
+ *     (kappa = E / (3 (1 - 2 nu))).
  * Positions, velocities and C are FP32 and F^E FP64; each particle's SVD comes from a
  * Jacobi eigen-decomposition of F^T F in FP64. Particle volume body_volume / n_particles.
  * All particles start with velocity v0, C = 0 and F^E = I. */
+enum { NSF_FO_VON_MISES = 0, NSF_FO_DRUCKER_PRAGER = 1, NSF_FO_HERSCHEL_BULKLEY = 2 };
 typedef struct {
   int64_t n_particles;
   const float *X;              /* host [3][n_particles] initial positions                 */
   double v0[3];                /* initial velocity                                        */
   double rho, body_volume;
   double youngs, poisson;      /* E, nu: mu = E / (2 (1 + nu)), lambda = E nu / ((1 + nu)(1 - 2 nu)) */
-  double yield_stress;         /* tau_y of the von Mises return map (> 0)                 */
+  double yield_stress;         /* tau_y of von Mises and Herschel-Bulkley (> 0; unused by
+                                  Drucker-Prager)                                       */
   int32_t grid_n;              /* nodes per axis, 8..256, dx = 1 / grid_n                 */
   double dt;
   double gravity[3];
   int32_t wall_nodes;          /* wall band; its bottom layers are the separating ground  */
+  int32_t plasticity;          /* NSF_FO_VON_MISES, NSF_FO_DRUCKER_PRAGER or
+                                  NSF_FO_HERSCHEL_BULKLEY                              */
+  double friction_angle;       /* Drucker-Prager phi_f in degrees, 0 <= phi_f < 90        */
+  double viscosity;            /* Herschel-Bulkley eta >= 0                               */
 } nsf_fo_desc;
 
 typedef struct nsf_fo nsf_fo;

@@ -24,7 +24,8 @@ NSF_FIELD_G, NSF_FIELD_H, NSF_FIELD_L = 0, 1, 2
 STATUS_NAMES = {0: "NSF_OK", -1: "NSF_EINVAL", -2: "NSF_ENOMEM", -3: "NSF_EHIP", -4: "NSF_ENODEV",
                 -5: "NSF_EDOMAIN", -6: "NSF_ESINGULAR", -7: "NSF_ENONFINITE", -8: "NSF_ECAPACITY"}
 
-EXPORTED = ["nsf_sim_bytes", "nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_refresh", "nsf_decode",
+EXPORTED = ["nsf_sim_bytes", "nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_mpm_stage",
+            "nsf_refresh", "nsf_decode",
             "nsf_get_latent", "nsf_set_latent", "nsf_set_sample_count", "nsf_set_parameters",
             "nsf_status_flags", "nsf_sim_buffer",
             "nsf_destroy_sim", "nsf_last_error", "nsf_device_count", "nsf_mlp_param_count",
@@ -32,6 +33,7 @@ EXPORTED = ["nsf_sim_bytes", "nsf_create_sim", "nsf_step", "nsf_step_batch", "ns
             "nsf_mlp_backward", "nsf_fo_bytes", "nsf_fo_create", "nsf_fo_step", "nsf_fo_buffer",
             "nsf_fo_flags", "nsf_fo_destroy"]
 NSF_FO_U, NSF_FO_V, NSF_FO_C, NSF_FO_TAU, NSF_FO_F = range(5)
+NSF_FO_VON_MISES, NSF_FO_DRUCKER_PRAGER, NSF_FO_HERSCHEL_BULKLEY = range(3)
 
 
 class nsf_knife(C.Structure):
@@ -60,7 +62,8 @@ class nsf_fo_desc(C.Structure):
     _fields_ = [("n_particles", C.c_int64), ("X", C.POINTER(C.c_float)), ("v0", C.c_double * 3),
                 ("rho", C.c_double), ("body_volume", C.c_double), ("youngs", C.c_double),
                 ("poisson", C.c_double), ("yield_stress", C.c_double), ("grid_n", C.c_int32),
-                ("dt", C.c_double), ("gravity", C.c_double * 3), ("wall_nodes", C.c_int32)]
+                ("dt", C.c_double), ("gravity", C.c_double * 3), ("wall_nodes", C.c_int32),
+                ("plasticity", C.c_int32), ("friction_angle", C.c_double), ("viscosity", C.c_double)]
 
 
 class nsf_mlp(C.Structure):
@@ -90,6 +93,7 @@ def lib() -> C.CDLL:
         L.nsf_create_sim.argtypes = [C.POINTER(nsf_sim_desc), vp, sz, vp, C.POINTER(vp)]
         L.nsf_step.argtypes = [vp, i32, vp]
         L.nsf_step_batch.argtypes = [C.POINTER(vp), i32, i32, vp]
+        L.nsf_mpm_stage.argtypes = [C.POINTER(vp), i32, vp]
         L.nsf_refresh.argtypes = [vp, vp]
         L.nsf_decode.argtypes = [vp, vp, i64, vp, vp]
         L.nsf_get_latent.argtypes = [vp, vp, vp, vp, vp]
@@ -117,8 +121,8 @@ def lib() -> C.CDLL:
         L.nsf_mlp_workspace_bytes.argtypes = [C.POINTER(nsf_mlp), i64]
         L.nsf_mlp_workspace_bytes.restype = sz
         L.nsf_mlp_forward.argtypes = [C.POINTER(nsf_mlp), vp, vp, i64, vp, vp, vp, sz, vp]
-        L.nsf_mlp_backward.argtypes = [C.POINTER(nsf_mlp), vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
-        for name in ("nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_refresh", "nsf_decode", "nsf_get_latent",
+        L.nsf_mlp_backward.argtypes = [C.POINTER(nsf_mlp), vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+        for name in ("nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_mpm_stage", "nsf_refresh", "nsf_decode", "nsf_get_latent",
                      "nsf_set_latent", "nsf_status_flags", "nsf_sim_buffer", "nsf_destroy_sim",
                      "nsf_mlp_forward", "nsf_mlp_backward"):
             getattr(L, name).restype = C.c_int
@@ -149,6 +153,11 @@ def nsf_step(sim: int, n_steps: int, stream: int) -> None:
 def nsf_step_batch(sims, n_steps: int, stream: int) -> None:
     arr = (C.c_void_p * len(sims))(*sims)
     check(lib().nsf_step_batch(arr, len(sims), n_steps, stream or None))
+
+
+def nsf_mpm_stage(sims, stream: int) -> None:
+    arr = (C.c_void_p * len(sims))(*sims)
+    check(lib().nsf_mpm_stage(arr, len(sims), stream or None))
 
 
 def nsf_refresh(sim: int, stream: int) -> None:

@@ -183,12 +183,16 @@ nsf_status validate(const nsf_sim_desc* d) {
   for (int64_t i = 0; i < cnt; ++i)
     if (d->sample_plan[i] < 0 || d->sample_plan[i] >= d->n_particles)
       return fail(NSF_EINVAL, "sample_plan[%lld] = %d out of range", (long long)i, d->sample_plan[i]);
-  if (closure) {
-    std::vector<uint8_t> seen((size_t)d->n_particles, 0);
-    for (int64_t i = 0; i < cnt; ++i) {
-      if (seen[d->sample_plan[i]]) return fail(NSF_EINVAL, "sample particle %d listed twice", d->sample_plan[i]);
-      seen[d->sample_plan[i]] = 1;
-    }
+  // a particle listed twice in one step's list would be integrated twice (its mass and
+  // momentum counted twice in P2G, its residual twice in the inversion)
+  std::vector<int32_t> seen((size_t)d->n_particles, -1);   // last row that listed the particle
+  const int64_t row_len = closure ? d->n_sample : d->n_integration;
+  for (int64_t i = 0; i < cnt; ++i) {
+    const int32_t row = (int32_t)(i / row_len), p = d->sample_plan[i];
+    if (seen[p] == row)
+      return closure ? fail(NSF_EINVAL, "sample particle %d listed twice", p)
+                     : fail(NSF_EINVAL, "particle %d listed twice in sample_plan row %d", p, row);
+    seen[p] = row;
   }
   return NSF_OK;
 }
@@ -656,15 +660,25 @@ nsf_status enqueue_refresh(Plan& P, hipStream_t s) {
 // iterations, then the inference of step n + 1. The decode of all particles runs at
 // z_{n+1} together with that inference, or (pipelined) at z_n alongside the whole step,
 // forked right after the first kernel has taken its latent snapshot.
-nsf_status enqueue_step(Plan& P, hipStream_t s) {
+// The MPM stage of a step (Sec. 5.2): binning (which also zeroes the step's claim
+// counters), P2G with the grid update, and G2P at the samples fused with the first
+// Gauss-Newton chunk sums. A pipelined decode forks after the binning kernel, which takes
+// its latent snapshot.
+nsf_status enqueue_mpm(Plan& P, hipStream_t s, bool fork) {
   NSF_HIP(launch_bin(P.d_sims, P.d_bP, P.d_counts + 3, P.d_counts + 8, P.gP, s));
-  if (P.decode && P.pipelined) {
+  if (fork) {
     const nsf_status st = fork_decode(P, s);
     if (st != NSF_OK) return st;
   }
   NSF_HIP(launch_p2g_after_bin(P.d_sims, P.d_counts + 6, P.gSims, P.d_bP, P.d_counts + 3, P.gP, P.gBlk, P.closure,
                                P.grid_cap, P.place, s));
   NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.r_cap, P.gGN, s));
+  return NSF_OK;
+}
+
+nsf_status enqueue_step(Plan& P, hipStream_t s) {
+  const nsf_status sm = enqueue_mpm(P, s, P.decode && P.pipelined);
+  if (sm != NSF_OK) return sm;
   NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {
     NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG + (k == 1 ? 0 : P.nGvel),
@@ -725,6 +739,53 @@ nsf_status run_plan(Plan& P, int32_t n_steps, hipStream_t s) {
     for (int i = 0; i < n_steps % kGraphSteps; ++i) NSF_HIP(hipGraphLaunch(P.exec, s));
   }
   for (nsf_sim* m : P.members) m->inference_ready = true;
+  return NSF_OK;
+}
+
+nsf_status check_batch(nsf_sim* const* sims, int32_t n) {
+  if (!sims || n < 1) return fail(NSF_EINVAL, "empty batch");
+  for (int i = 0; i < n; ++i) {
+    if (!sims[i]) return fail(NSF_EINVAL, "sims[%d] is NULL", i);
+    if (n > 1 && sims[i]->closure)
+      return fail(NSF_EINVAL, "sims[%d] uses closure integration, which steps alone", i);
+    if (sims[i]->width != sims[0]->width || sims[i]->bf16 != sims[0]->bf16 ||
+        sims[i]->gn_iters != sims[0]->gn_iters || sims[i]->decode_mode != sims[0]->decode_mode)
+      return fail(NSF_EINVAL, "sims[%d] differs in width, precision, gn_iters or decode mode", i);
+    for (int j = 0; j < i; ++j)
+      if (sims[j] == sims[i]) return fail(NSF_EINVAL, "sim listed twice in a batch");
+  }
+  return NSF_OK;
+}
+
+// The persistent batch plan of this set of sims (caller holds g_plans_mu); its tables are
+// rewritten when the set differs from the one it last stepped.
+nsf_status batch_plan(nsf_sim* const* sims, int32_t n, hipStream_t st, Plan** out) {
+  std::vector<nsf_sim*> key(sims, sims + n);
+  std::unique_ptr<Plan>& slot = g_batch_plans[batch_signature(key[0])];
+  if (!slot) {
+    slot.reset(new Plan());
+    slot->persistent = true;
+  }
+  Plan& P = *slot;
+  if (P.members != key) {
+    P.members = key;
+    const nsf_status e = build_plan(P, st);
+    if (e != NSF_OK) {
+      P.members.clear();
+      return e;
+    }
+  }
+  *out = &P;
+  return NSF_OK;
+}
+
+nsf_status solo_plan(nsf_sim* s, hipStream_t st) {
+  if (s->solo) return NSF_OK;
+  std::unique_ptr<Plan> p(new Plan());
+  p->members.push_back(s);
+  const nsf_status e = build_plan(*p, st);
+  if (e != NSF_OK) return e;
+  s->solo = std::move(p);
   return NSF_OK;
 }
 
@@ -957,13 +1018,8 @@ nsf_status nsf_step(nsf_sim* s, int32_t n_steps, void* stream) {
   if (n_steps < 0) return fail(NSF_EINVAL, "n_steps < 0");
   if (n_steps == 0) return NSF_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (!s->solo) {
-    std::unique_ptr<Plan> p(new Plan());
-    p->members.push_back(s);
-    const nsf_status e = build_plan(*p, st);
-    if (e != NSF_OK) return e;
-    s->solo = std::move(p);
-  }
+  const nsf_status e = solo_plan(s, st);
+  if (e != NSF_OK) return e;
   return run_plan(*s->solo, n_steps, st);
 }
 
@@ -971,34 +1027,40 @@ nsf_status nsf_step_batch(nsf_sim* const* sims, int32_t n, int32_t n_steps, void
   if (!sims || n < 1) return fail(NSF_EINVAL, "empty batch");
   if (n_steps < 0) return fail(NSF_EINVAL, "n_steps < 0");
   if (n == 1) return nsf_step(sims[0], n_steps, stream);
-  std::vector<nsf_sim*> key(sims, sims + n);
-  for (int i = 0; i < n; ++i) {
-    if (!key[i]) return fail(NSF_EINVAL, "sims[%d] is NULL", i);
-    if (key[i]->closure) return fail(NSF_EINVAL, "sims[%d] uses closure integration, which steps alone", i);
-    if (key[i]->width != key[0]->width || key[i]->bf16 != key[0]->bf16 ||
-        key[i]->gn_iters != key[0]->gn_iters || key[i]->decode_mode != key[0]->decode_mode)
-      return fail(NSF_EINVAL, "sims[%d] differs in width, precision, gn_iters or decode mode", i);
-    for (int j = 0; j < i; ++j)
-      if (key[j] == key[i]) return fail(NSF_EINVAL, "sim listed twice in a batch");
-  }
+  const nsf_status chk = check_batch(sims, n);
+  if (chk != NSF_OK) return chk;
   if (n_steps == 0) return NSF_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(g_plans_mu);
-  std::unique_ptr<Plan>& slot = g_batch_plans[batch_signature(key[0])];
-  if (!slot) {
-    slot.reset(new Plan());
-    slot->persistent = true;
+  Plan* P = nullptr;
+  const nsf_status e = batch_plan(sims, n, st, &P);
+  if (e != NSF_OK) return e;
+  return run_plan(*P, n_steps, st);
+}
+
+nsf_status nsf_mpm_stage(nsf_sim* const* sims, int32_t n, void* stream) {
+  const nsf_status chk = check_batch(sims, n);
+  if (chk != NSF_OK) return chk;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Plan* P = nullptr;
+  std::unique_lock<std::mutex> lk(g_plans_mu, std::defer_lock);
+  if (n == 1) {
+    const nsf_status e = solo_plan(sims[0], st);
+    if (e != NSF_OK) return e;
+    P = sims[0]->solo.get();
+  } else {
+    lk.lock();
+    const nsf_status e = batch_plan(sims, n, st, &P);
+    if (e != NSF_OK) return e;
   }
-  Plan& P = *slot;
-  if (P.members != key) {
-    P.members = key;
-    const nsf_status e = build_plan(P, st);
-    if (e != NSF_OK) {
-      P.members.clear();
-      return e;
-    }
+  bool ready = true;
+  for (nsf_sim* m : P->members) ready = ready && m->inference_ready;
+  if (!ready) {
+    const nsf_status e = enqueue_inference(*P, st);
+    if (e != NSF_OK) return e;
+    for (nsf_sim* m : P->members) m->inference_ready = true;
   }
-  return run_plan(P, n_steps, st);
+  return enqueue_mpm(*P, st, false);
 }
 
 nsf_status nsf_decode(nsf_sim* s, const float* X, int64_t n, float* x_out, void* stream) {
@@ -1053,13 +1115,8 @@ nsf_status nsf_set_latent(nsf_sim* s, const double* z, const double* z_prev, int
 nsf_status nsf_refresh(nsf_sim* s, void* stream) {
   if (!s) return fail(NSF_EINVAL, "sim is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (!s->solo) {
-    std::unique_ptr<Plan> p(new Plan());
-    p->members.push_back(s);
-    const nsf_status e = build_plan(*p, st);
-    if (e != NSF_OK) return e;
-    s->solo = std::move(p);
-  }
+  const nsf_status sp = solo_plan(s, st);
+  if (sp != NSF_OK) return sp;
   const nsf_status e = enqueue_refresh(*s->solo, st);
   if (e == NSF_OK) s->inference_ready = true;
   return e;
@@ -1190,7 +1247,15 @@ nsf_status fo_validate(const nsf_fo_desc* d) {
   if (d->grid_n < 8 || d->grid_n > 256) return fail(NSF_EINVAL, "grid_n = %d outside 8..256", d->grid_n);
   if (!(d->dt > 0) || !(d->rho > 0) || !(d->body_volume > 0)) return fail(NSF_EINVAL, "dt, rho and body_volume must be positive");
   if (!(d->youngs > 0) || !(d->poisson > -1.0 && d->poisson < 0.5)) return fail(NSF_EINVAL, "need E > 0 and -1 < nu < 0.5");
-  if (!(d->yield_stress > 0)) return fail(NSF_EINVAL, "yield_stress must be positive");
+  if (d->plasticity != NSF_FO_VON_MISES && d->plasticity != NSF_FO_DRUCKER_PRAGER &&
+      d->plasticity != NSF_FO_HERSCHEL_BULKLEY)
+    return fail(NSF_EINVAL, "plasticity = %d (0 von Mises, 1 Drucker-Prager, 2 Herschel-Bulkley)", d->plasticity);
+  if (d->plasticity != NSF_FO_DRUCKER_PRAGER && !(d->yield_stress > 0))
+    return fail(NSF_EINVAL, "yield_stress must be positive");
+  if (d->plasticity == NSF_FO_DRUCKER_PRAGER && !(d->friction_angle >= 0.0 && d->friction_angle < 90.0))
+    return fail(NSF_EINVAL, "friction_angle = %g outside [0, 90)", d->friction_angle);
+  if (d->plasticity == NSF_FO_HERSCHEL_BULKLEY && !(d->viscosity >= 0.0 && std::isfinite(d->viscosity)))
+    return fail(NSF_EINVAL, "viscosity = %g must be finite and >= 0", d->viscosity);
   if (d->wall_nodes < 0 || 2 * d->wall_nodes >= d->grid_n) return fail(NSF_EINVAL, "wall_nodes = %d", d->wall_nodes);
   return NSF_OK;
 }
@@ -1321,6 +1386,15 @@ nsf_status nsf_fo_create(const nsf_fo_desc* d, void* arena, size_t arena_bytes, 
   H.fo_mu = d->youngs / (2.0 * (1.0 + d->poisson));
   H.fo_lambda = d->youngs * d->poisson / ((1.0 + d->poisson) * (1.0 - 2.0 * d->poisson));
   H.fo_tau_y = d->yield_stress;
+  H.fo_model = d->plasticity;
+  H.fo_kappa = d->youngs / (3.0 * (1.0 - 2.0 * d->poisson));
+  {
+    const double sphi = std::sin(d->friction_angle * M_PI / 180.0);
+    const double alpha = std::sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi);
+    H.fo_dp_k = alpha * (3.0 * H.fo_lambda + 2.0 * H.fo_mu) / (2.0 * H.fo_mu);
+  }
+  H.fo_hb_lim = std::sqrt(2.0 / 3.0) * d->yield_stress;
+  H.fo_hb_relax = 1.0 / (1.0 + d->viscosity / (2.0 * H.fo_mu * d->dt));
   H.X = reinterpret_cast<const float*>(A + L.X);
   H.plan = reinterpret_cast<const int32_t*>(A + L.plan);
   H.u_n = reinterpret_cast<float*>(A + L.u);

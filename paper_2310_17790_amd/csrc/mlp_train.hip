@@ -6,13 +6,13 @@
 // (k = 1..4), out = W_6 h_5 + b_6. Given dout = dLoss/dout per point:
 //   delta_6 = dout,  delta_k = (W_{k+1}^T delta_{k+1}) * ELU'(a_k)   (k = 5 .. 1)
 //   dW_k += sum_p delta_k h_{k-1}^T, db_k += sum_p delta_k          (h_0 = [X; z])
-//   dz = W_1[:, 3:]^T delta_1.
+//   dz = W_1[:, 3:]^T delta_1, dX = W_1[:, :3]^T delta_1.
 //
 // Kernels. The forward is the field kernel of the latent step (per-point latents, raw
 // output, pre-activations stored point-major). The backward-data kernel carries 32 points
 // per wave through the five W^T products on MFMA (the same accumulator-layout chaining as
-// the forward, with the transposed weights packed on the device) and computes dz on the
-// VALU. The weight gradients are reductions over points on MFMA: each workgroup sums a
+// the forward, with the transposed weights packed on the device) and computes dz and dX
+// on the VALU. The weight gradients are reductions over points on MFMA: each workgroup sums a
 // chunk of points for one layer into a partial, and the partials are added in chunk order
 // (deterministic) into dW.
 #include <hip/hip_runtime.h>
@@ -126,6 +126,7 @@ __global__ __launch_bounds__(256) void backward_data_kernel(const float* __restr
                                                             const float* __restrict__ dout,
                                                             float* __restrict__ delta,
                                                             float* __restrict__ dz,
+                                                            float* __restrict__ dX,
                                                             int n, int r, int d) {
   constexpr int MB = W / 32, KH = W / 2;
   const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -193,6 +194,15 @@ __global__ __launch_bounds__(256) void backward_data_kernel(const float* __restr
       s += __shfl_xor(s, 32);
       if (valid && h == (j & 1) && dz != nullptr) dz[(int64_t)p * r + j] = s;
     }
+    // dX_c = sum_n W1[n][c] delta_1[n], SoA like X
+    if (dX != nullptr)
+      for (int c = 0; c < 3; ++c) {
+        float s = 0.f;
+#pragma unroll
+        for (int s_ = 0; s_ < KH; ++s_) s += master[(size_t)acc_n(s_ / 16, s_ % 16, h) * in1 + c] * D[s_];
+        s += __shfl_xor(s, 32);
+        if (valid && h == (c & 1)) dX[(int64_t)c * n + p] = s;
+      }
   }
 }
 
@@ -458,7 +468,7 @@ nsf_status nsf_mlp_forward(const nsf_mlp* m, const float* X, const float* z_rows
 }
 
 nsf_status nsf_mlp_backward(const nsf_mlp* m, const float* X, const float* z_rows, int64_t n,
-                            const float* saved, const float* dout, float* dW, float* dz,
+                            const float* saved, const float* dout, float* dW, float* dz, float* dX,
                             void* workspace, size_t workspace_bytes, void* stream) {
   if (check_mlp(m, n) != NSF_OK || !X || !z_rows || !saved || !dout || !dW || !workspace)
     return NSF_EINVAL;
@@ -471,10 +481,10 @@ nsf_status nsf_mlp_backward(const nsf_mlp* m, const float* X, const float* z_row
   const int grid = (waves + 3) / 4;
   if (W == 64)
     hipLaunchKernelGGL(backward_data_kernel<64>, dim3(grid), dim3(256), 0, s, m->weights, ws.pk.whtp,
-                       ws.pk.w6p, saved, dout, ws.delta, dz, (int)n, r, d);
+                       ws.pk.w6p, saved, dout, ws.delta, dz, dX, (int)n, r, d);
   else
     hipLaunchKernelGGL(backward_data_kernel<128>, dim3(grid), dim3(256), 0, s, m->weights, ws.pk.whtp,
-                       ws.pk.w6p, saved, dout, ws.delta, dz, (int)n, r, d);
+                       ws.pk.w6p, saved, dout, ws.delta, dz, dX, (int)n, r, d);
   if (hipGetLastError() != hipSuccess) return NSF_EHIP;
   // parameter offsets in the master layout
   const size_t in1 = 3 + r;

@@ -656,8 +656,10 @@ __global__ __launch_bounds__(kGnThreads) void g2p_gn_kernel(const SimDev* __rest
 // ---- full-order G2P, deformation update, return map, stress -------------------------
 // Every particle (identity integration list) after P2G and the grid update: v and the
 // APIC matrix C from the 27 stencil nodes, x += dt v (kept as the displacement u = x - X),
-// F_trial = (I + dt C) F^E, then the von Mises return map in log strain and the fixed
-// corotated stress of the new F^E, for the next step's P2G.
+// F_trial = (I + dt C) F^E, then the return map of the sim's model and the stress of the
+// new F^E for the next step's P2G (supplementary "Elasticity and plasticity details"):
+// von Mises in log strain with fixed corotated stress, Drucker-Prager with the StVK
+// stress in log strain, or Herschel-Bulkley (h = 1) with its own stress.
 //
 // The SVD F_trial = U S V^T comes from the symmetric eigen-decomposition
 // F_trial^T F_trial = V S^2 V^T (cyclic Jacobi rotations, FP64). U is never formed: with
@@ -780,23 +782,92 @@ __global__ __launch_bounds__(kFoThreads) void fo_g2p_kernel(const SimDev* __rest
     sig[i] = sqrt(fmax(A[i][i], 0.0));
     eps[i] = log(fmax(sig[i], 1e-12));
   }
-  // von Mises in log strain
+  // return map: new log singular values eps (von Mises, Drucker-Prager) or the new
+  // isochoric stretch bbar (Herschel-Bulkley), then F^E = U diag(sig_new) V^T
   const double mean = (eps[0] + eps[1] + eps[2]) / 3.0;
   const double eh[3] = {eps[0] - mean, eps[1] - mean, eps[2] - mean};
   const double norm = sqrt(eh[0] * eh[0] + eh[1] * eh[1] + eh[2] * eh[2]);
-  const double dgamma = norm - S.fo_tau_y / (2.0 * S.fo_mu);
-  if (dgamma > 0.0 && norm > 0.0)
+  double sn[3];      // singular values of the new F^E
+  double tp[3];      // principal Kirchhoff stresses (log-strain and Herschel-Bulkley stresses)
+  if (S.fo_model == 1) {
+    // Drucker-Prager: expansion returns to Sigma = 1, outside the cone onto it
+    const double tr = 3.0 * mean;
+    const double dgamma = norm + S.fo_dp_k * tr;
+    if (tr > 0.0) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) eps[i] -= dgamma * eh[i] / norm;
-  double ge[3], gr[3];
+      for (int i = 0; i < 3; ++i) eps[i] = 0.0;
+    } else if (dgamma > 0.0 && norm > 0.0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) eps[i] -= dgamma * eh[i] / norm;
+    }
+    const double tre = eps[0] + eps[1] + eps[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      sn[i] = exp(eps[i]);
+      tp[i] = 2.0 * S.fo_mu * eps[i] + S.fo_lambda * tre;
+    }
+  } else if (S.fo_model == 2) {
+    // Herschel-Bulkley: scale the deviator of bbar = J^(-2/3) S^2, keep det(bbar) = 1
+    const double Jt = exp(3.0 * mean);
+    const double j23 = exp(-2.0 * mean);
+    double bb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) bb[i] = j23 * sig[i] * sig[i];
+    const double bm = (bb[0] + bb[1] + bb[2]) / 3.0;
+    double a[3] = {bb[0] - bm, bb[1] - bm, bb[2] - bm};
+    const double st = S.fo_mu * sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    if (st > S.fo_hb_lim) {
+      const double sc = (st - (st - S.fo_hb_lim) * S.fo_hb_relax) / st;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) a[i] *= sc;
+      // Newton on f(c) = prod(a_i + c) - 1, convex and increasing where every a_i + c > 0
+      // (bm is there: a_i shrank towards 0); converges from either side of the root
+      double c = bm;
+      for (int it = 0; it < 40; ++it) {
+        const double p0 = a[0] + c, p1 = a[1] + c, p2 = a[2] + c;
+        const double f = p0 * p1 * p2 - 1.0;
+        const double df = p1 * p2 + p0 * p2 + p0 * p1;
+        const double dc = f / df;
+        c -= dc;
+        if (fabs(dc) <= 1e-15 * fabs(c)) break;
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) bb[i] = a[i] + c;
+    }
+    const double bmn = (bb[0] + bb[1] + bb[2]) / 3.0;
+    const double j13 = exp(mean);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      sn[i] = j13 * sqrt(fmax(bb[i], 0.0));
+      tp[i] = 0.5 * S.fo_kappa * (Jt * Jt - 1.0) + S.fo_mu * (bb[i] - bmn);
+    }
+  } else {
+    // von Mises in log strain, yield test on the plastic multiplier
+    const double dgamma = norm - S.fo_tau_y / (2.0 * S.fo_mu);
+    if (dgamma > 0.0 && norm > 0.0)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) eps[i] -= dgamma * eh[i] / norm;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      sn[i] = exp(eps[i]);
+      tp[i] = 0.0;
+    }
+  }
+  double ge[3], gr[3], gt[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const double si = fmax(sig[i], 1e-300);
-    ge[i] = exp(eps[i]) / si;
+    ge[i] = sn[i] / si;
     gr[i] = 1.0 / si;
+    gt[i] = tp[i] / (si * si);
   }
-  // F^E = Ft V diag(ge) V^T, R = Ft V diag(gr) V^T
-  double FE[3][3], R[3][3];
+  // F^E = Ft V diag(ge) V^T, R = Ft V diag(gr) V^T; for the principal-stress models
+  // tau = U diag(tp) U^T = (Ft V) diag(tp / S^2) (Ft V)^T
+  double FE[3][3], R[3][3], FV[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) FV[r][k] = Ft[r][0] * V[0][k] + Ft[r][1] * V[1][k] + Ft[r][2] * V[2][k];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -804,24 +875,32 @@ __global__ __launch_bounds__(kFoThreads) void fo_g2p_kernel(const SimDev* __rest
       double me = 0.0, mr = 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        double fv = Ft[r][0] * V[0][k] + Ft[r][1] * V[1][k] + Ft[r][2] * V[2][k];
-        me += fv * ge[k] * V[c][k];
-        mr += fv * gr[k] * V[c][k];
+        me += FV[r][k] * ge[k] * V[c][k];
+        mr += FV[r][k] * gr[k] * V[c][k];
       }
       FE[r][c] = me;
       R[r][c] = mr;
     }
-  const double J = exp(eps[0] + eps[1] + eps[2]);
   double tau[3][3];
+  if (S.fo_model == 0) {
+    // fixed corotated: tau = 2 mu (F^E - R) F^E^T + lambda (J - 1) J I
+    const double J = sn[0] * sn[1] * sn[2];
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double acc = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) acc += (FE[r][k] - R[r][k]) * FE[c][k];
-      tau[r][c] = 2.0 * S.fo_mu * acc + (r == c ? S.fo_lambda * (J - 1.0) * J : 0.0);
-    }
+        for (int k = 0; k < 3; ++k) acc += (FE[r][k] - R[r][k]) * FE[c][k];
+        tau[r][c] = 2.0 * S.fo_mu * acc + (r == c ? S.fo_lambda * (J - 1.0) * J : 0.0);
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        tau[r][c] = FV[r][0] * gt[0] * FV[c][0] + FV[r][1] * gt[1] * FV[c][1] + FV[r][2] * gt[2] * FV[c][2];
+  }
 #pragma unroll
   for (int e = 0; e < 9; ++e) S.F[e * P + p] = FE[e / 3][e % 3];
   const double t6[6] = {tau[0][0], tau[1][1], tau[2][2], tau[1][2], tau[0][2], tau[0][1]};

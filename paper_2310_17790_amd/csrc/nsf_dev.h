@@ -133,6 +133,10 @@ struct SimDev {
   int32_t ground, pad3;              // 1: the bottom wall layers only keep v_z >= 0
   double* F;                         // [9][n_part] elastic deformation gradient
   double fo_mu, fo_lambda, fo_tau_y;  // Lame parameters and yield stress
+  int32_t fo_model, pad4;            // return map: 0 von Mises, 1 Drucker-Prager, 2 Herschel-Bulkley
+  double fo_kappa;                   // bulk modulus (Herschel-Bulkley stress)
+  double fo_dp_k;                    // Drucker-Prager: alpha (3 lambda + 2 mu) / (2 mu)
+  double fo_hb_lim, fo_hb_relax;     // Herschel-Bulkley: sqrt(2/3) tau_y, 1 / (1 + eta / (2 mu dt))
 };
 
 // Integration particles this step: the live length of a closure list, else n_int.

@@ -1,8 +1,9 @@
 """Full-order MLS-MPM on the GPU through the C ABI (nsf_fo_*): every particle integrated
-with the same P2G kernels as the reduced step, then G2P with the C and F updates, the
-von Mises return map and fixed corotated elasticity (Sec. 3.3 and the supplementary
-"Elasticity and plasticity details"). It is the model the reduced step is measured
-against.
+with the same P2G kernels as the reduced step, then G2P with the C and F updates and one
+of three return maps with its elasticity: von Mises with fixed corotated stress,
+Drucker-Prager with the StVK stress in log strain, Herschel-Bulkley with its own stress
+(Sec. 3.3 and the supplementary "Elasticity and plasticity details"). It is the model the
+reduced step is measured against.
 """
 from __future__ import annotations
 
@@ -13,6 +14,10 @@ import numpy as np
 import torch
 
 from . import _abi as A
+
+
+MODELS = {"von_mises": A.NSF_FO_VON_MISES, "drucker_prager": A.NSF_FO_DRUCKER_PRAGER,
+          "herschel_bulkley": A.NSF_FO_HERSCHEL_BULKLEY}
 
 
 def _stream_handle(stream) -> int:
@@ -27,7 +32,8 @@ class FullOrderSim:
     def __init__(self, X: np.ndarray, v0: Sequence[float], rho: float, body_volume: float,
                  youngs: float, poisson: float, yield_stress: float, grid_n: int, dt: float,
                  gravity: Sequence[float] = (0.0, 0.0, -9.8), wall_nodes: int = 3,
-                 stream: Optional[torch.cuda.Stream] = None, device: Optional[torch.device] = None):
+                 stream: Optional[torch.cuda.Stream] = None, device: Optional[torch.device] = None,
+                 model: str = "von_mises", friction_angle: float = 30.0, viscosity: float = 0.0):
         X = np.ascontiguousarray(X, np.float32)
         assert X.ndim == 2 and X.shape[0] == 3
         self.n_particles = int(X.shape[1])
@@ -41,6 +47,8 @@ class FullOrderSim:
         d.rho, d.body_volume = float(rho), float(body_volume)
         d.youngs, d.poisson, d.yield_stress = float(youngs), float(poisson), float(yield_stress)
         d.grid_n, d.dt, d.wall_nodes = int(grid_n), float(dt), int(wall_nodes)
+        d.plasticity = MODELS[model]
+        d.friction_angle, d.viscosity = float(friction_angle), float(viscosity)
         nbytes = A.lib().nsf_fo_bytes(C.byref(d))
         if nbytes == 0:
             raise A.NsfError(A.NSF_EINVAL, A.nsf_last_error())

@@ -204,3 +204,10 @@ class Sim:
 
 def step_batch(sims: List[Sim], n: int = 1, stream=None) -> None:
     A.nsf_step_batch([s.handle for s in sims], n, _stream_handle(stream))
+
+
+def mpm_stage(sims: List[Sim], stream=None) -> None:
+    """The MPM stage of the current step alone (P2G, grid update, G2P at the samples), one
+    launch per kernel over the sims' union; it advances nothing, so repeated calls
+    recompute the same grid and velocities."""
+    A.nsf_mpm_stage([s.handle for s in sims], _stream_handle(stream))

@@ -3,7 +3,8 @@
 FieldFn.apply(X, z_rows, weights, width, d, precision) evaluates one field MLP at the
 points X (n, 3) with per-point latents z_rows (n, r) and flat weights (layout of
 nsf_sim_desc.weights) and returns (n, d). Its backward calls nsf_mlp_backward, which
-returns dLoss/dweights (same flat layout) and dLoss/dz_rows; X gets no gradient.
+returns dLoss/dweights (same flat layout), dLoss/dz_rows and, when X requires it,
+dLoss/dX.
 """
 from __future__ import annotations
 
@@ -56,10 +57,12 @@ class FieldFn(torch.autograd.Function):
         m = _mlp(w, r, width, d, precision)
         dout = gout.t().contiguous().float()
         dW = torch.zeros_like(w)
-        dz = torch.empty_like(zr)
+        dz = torch.empty_like(zr) if ctx.needs_input_grad[1] else None
+        dX = torch.empty_like(Xs) if ctx.needs_input_grad[0] else None
         ws_bytes = L.nsf_mlp_workspace_bytes(C.byref(m), n)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=w.device)
         A.check(L.nsf_mlp_backward(C.byref(m), Xs.data_ptr(), zr.data_ptr(), n, saved.data_ptr(),
-                                   dout.data_ptr(), dW.data_ptr(), dz.data_ptr(), ws.data_ptr(),
-                                   ws_bytes, _stream()))
-        return None, dz, dW, None, None, None
+                                   dout.data_ptr(), dW.data_ptr(), None if dz is None else dz.data_ptr(),
+                                   None if dX is None else dX.data_ptr(), ws.data_ptr(), ws_bytes,
+                                   _stream()))
+        return None if dX is None else dX.t(), dz, dW, None, None, None

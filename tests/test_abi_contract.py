@@ -88,6 +88,62 @@ def test_sim_bytes_and_validation():
     d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
     assert A.nsf_sim_bytes(d) == 0
     assert "out of range" in A.nsf_last_error()
+    # a particle listed twice in one row would be integrated twice
+    plan = np.array(w.plan, np.int32)
+    plan[0, 9] = plan[0, 4]
+    keep.append(plan)
+    d.sample_plan = plan.ctypes.data_as(C.POINTER(C.c_int32))
+    assert A.nsf_sim_bytes(d) == 0
+    assert "twice" in A.nsf_last_error()
+
+
+def test_plan_rows_may_share_particles():
+    """Rows are independent draws: the same particle in two rows is fine."""
+    from paper_2310_17790_amd.sim import build_desc
+    w = synth.cake_slab(seed=0, r=6, width=64, n=2000, n_integration=500, steps=4, grid_n=32)
+    d, keep = build_desc(w, "fp32", True)
+    plan = np.array(w.plan, np.int32)
+    assert plan.shape[0] >= 2 and len(np.intersect1d(plan[0], plan[1])) > 0
+    assert A.nsf_sim_bytes(d) > 0, A.nsf_last_error()
+
+
+def _fo_desc(keep, **kw):
+    rng = np.random.default_rng(0)
+    X = np.ascontiguousarray(rng.uniform(0.4, 0.6, size=(3, 100)), np.float32)
+    keep.append(X)
+    d = A.nsf_fo_desc()
+    d.n_particles = 100
+    d.X = X.ctypes.data_as(C.POINTER(C.c_float))
+    d.rho, d.body_volume, d.youngs, d.poisson, d.yield_stress = 1000.0, 1e-3, 5e4, 0.3, 2e3
+    d.grid_n, d.dt, d.wall_nodes = 32, 1e-4, 3
+    d.gravity[2] = -9.8
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_full_order_descriptor_validation_on_host():
+    """The three return maps and their parameters (supplementary "Elasticity and
+    plasticity details"): Drucker-Prager needs 0 <= phi_f < 90 and no yield stress,
+    Herschel-Bulkley a yield stress and a finite viscosity >= 0."""
+    keep = []
+    assert A.lib().nsf_fo_bytes(C.byref(_fo_desc(keep))) > 0, A.nsf_last_error()
+    ok = [dict(plasticity=A.NSF_FO_DRUCKER_PRAGER, friction_angle=30.0, yield_stress=0.0),
+          dict(plasticity=A.NSF_FO_DRUCKER_PRAGER, friction_angle=0.0),
+          dict(plasticity=A.NSF_FO_HERSCHEL_BULKLEY, viscosity=0.0),
+          dict(plasticity=A.NSF_FO_HERSCHEL_BULKLEY, viscosity=5.0)]
+    for kw in ok:
+        assert A.lib().nsf_fo_bytes(C.byref(_fo_desc(keep, **kw))) > 0, (kw, A.nsf_last_error())
+    bad = [dict(plasticity=3), dict(plasticity=-1),
+           dict(plasticity=A.NSF_FO_DRUCKER_PRAGER, friction_angle=90.0),
+           dict(plasticity=A.NSF_FO_DRUCKER_PRAGER, friction_angle=-1.0),
+           dict(plasticity=A.NSF_FO_HERSCHEL_BULKLEY, viscosity=-1.0),
+           dict(plasticity=A.NSF_FO_HERSCHEL_BULKLEY, viscosity=float("inf")),
+           dict(plasticity=A.NSF_FO_HERSCHEL_BULKLEY, yield_stress=0.0),
+           dict(plasticity=A.NSF_FO_VON_MISES, yield_stress=0.0)]
+    for kw in bad:
+        assert A.lib().nsf_fo_bytes(C.byref(_fo_desc(keep, **kw))) == 0, kw
+        assert A.nsf_last_error() != ""
 
 
 def test_sim_bytes_scales_with_grid_and_particles():

@@ -2,9 +2,10 @@
 FieldFn) against finite differences of the FP64 oracle and against torch autograd in FP64.
 
 Loss L = sum_{p, o} c_{p,o} f_o(X_p, z_p) with fixed random c, on 64 points (the
-finite-difference check of the fitting configuration). FP32 kernels: gradients agree with
-central differences of the FP64 oracle (step 1e-6 relative) to 1e-4 of each parameter
-block's largest gradient, and with FP64 autograd to 2e-5. BF16 hidden layers: 5e-2.
+finite-difference check of the fitting configuration). FP32 kernels: gradients of the
+weights, the latents and the input positions agree with central differences of the FP64
+oracle (step 1e-6 relative) to 1e-4 of each block's largest gradient, and with FP64
+autograd to 2e-5. BF16 hidden layers: 5e-2.
 """
 import numpy as np
 import pytest
@@ -32,14 +33,15 @@ def _oracle_loss(layers, X, Z, c):
     return float((out * c).sum())
 
 
-def _gpu_grads(layers, X, Z, c, width, d, precision):
+def _gpu_grads(layers, X, Z, c, width, d, precision, want_x=False):
     w = torch.from_numpy(flatten_mlp(layers)).cuda().requires_grad_(True)
-    Xt = torch.from_numpy(X.astype(np.float32)).cuda()
+    Xt = torch.from_numpy(X.astype(np.float32)).cuda().requires_grad_(want_x)
     Zt = torch.from_numpy(Z).cuda().requires_grad_(True)
     out = FieldFn.apply(Xt, Zt, w, width, d, precision)
     loss = (out.double() * torch.from_numpy(c).cuda()).sum()
     loss.backward()
-    return out.detach().cpu().numpy(), w.grad.cpu().numpy(), Zt.grad.cpu().numpy()
+    res = (out.detach().cpu().numpy(), w.grad.cpu().numpy(), Zt.grad.cpu().numpy())
+    return res + (Xt.grad.cpu().numpy(),) if want_x else res
 
 
 def _blocks(r, width, d):
@@ -55,11 +57,12 @@ def _blocks(r, width, d):
     return out
 
 
-def _torch_grads(layers, X, Z, c):
+def _torch_grads(layers, X, Z, c, want_x=False):
     Ws = [torch.tensor(W, dtype=torch.float64, requires_grad=True) for W, _ in layers]
     bs = [torch.tensor(b, dtype=torch.float64, requires_grad=True) for _, b in layers]
     Zt = torch.tensor(Z, dtype=torch.float64, requires_grad=True)
-    h = torch.cat([torch.tensor(X, dtype=torch.float64), Zt], 1)
+    Xt = torch.tensor(X, dtype=torch.float64, requires_grad=want_x)
+    h = torch.cat([Xt, Zt], 1)
     for k in range(6):
         h = torch.nn.functional.linear(h, Ws[k], bs[k])
         if k < 5:
@@ -67,20 +70,26 @@ def _torch_grads(layers, X, Z, c):
     (h * torch.tensor(c)).sum().backward()
     flat = np.concatenate([np.concatenate([W.grad.numpy().ravel(), b.grad.numpy().ravel()])
                            for W, b in zip(Ws, bs)])
-    return h.detach().numpy(), flat, Zt.grad.numpy()
+    res = (h.detach().numpy(), flat, Zt.grad.numpy())
+    return res + (Xt.grad.numpy(),) if want_x else res
 
 
 @pytest.mark.parametrize("d", [3, 9])
 def test_backward_matches_fp64_autograd(d):
     r, width = 12, 128
     layers, X, Z, c = _problem(r, width, d, n=200)
-    out, gW, gZ = _gpu_grads(layers, X, Z, c, width, d, "fp32")
-    ref_out, rW, rZ = _torch_grads(layers, X, Z, c)
+    out, gW, gZ, gX = _gpu_grads(layers, X, Z, c, width, d, "fp32", want_x=True)
+    ref_out, rW, rZ, rX = _torch_grads(layers, X, Z, c, want_x=True)
     assert np.abs(out - ref_out).max() <= 2e-5 * np.abs(ref_out).max()
     for name, o, s in _blocks(r, width, d):
         err = np.abs(gW[o:o + s] - rW[o:o + s]).max() / np.abs(rW[o:o + s]).max()
         assert err < 2e-5, (name, err)
     assert np.abs(gZ - rZ).max() <= 2e-5 * np.abs(rZ).max()
+    assert np.abs(gX - rX).max() <= 2e-5 * np.abs(rX).max()
+    # without X requiring a gradient the backward skips dX (NULL) and the rest is unchanged
+    _, gW2, gZ2 = _gpu_grads(layers, X, Z, c, width, d, "fp32")
+    np.testing.assert_array_equal(gW2, gW)
+    np.testing.assert_array_equal(gZ2, gZ)
 
 
 def test_backward_matches_fp64_finite_differences():
@@ -88,7 +97,7 @@ def test_backward_matches_fp64_finite_differences():
     parameter block and every latent of 4 points."""
     r, width, d = 12, 128, 3
     layers, X, Z, c = _problem(r, width, d, n=64)
-    _, gW, gZ = _gpu_grads(layers, X, Z, c, width, d, "fp32")
+    _, gW, gZ, gX = _gpu_grads(layers, X, Z, c, width, d, "fp32", want_x=True)
     flat = np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers]).astype(np.float64)
     shapes = [(W.shape, b.shape) for W, b in layers]
 
@@ -119,6 +128,18 @@ def test_backward_matches_fp64_finite_differences():
             Zm[p, j] -= e
             fd = (_oracle_loss(layers, X, Zp, c) - _oracle_loss(layers, X, Zm, c)) / (2 * e)
             assert abs(gZ[p, j] - fd) <= 1e-4 * np.abs(gZ).max(), (p, j)
+    # input positions: every coordinate of all 64 points (a point's X moves only its own
+    # output, so its term of the loss is differenced alone)
+    X64 = X.astype(np.float64)
+    for p in range(X.shape[0]):
+        for k in range(3):
+            e = 1e-6 * (1 + abs(X64[p, k]))
+            Xp, Xm = X64[p:p + 1].copy(), X64[p:p + 1].copy()
+            Xp[0, k] += e
+            Xm[0, k] -= e
+            fd = (_oracle_loss(layers, Xp, Z64[p:p + 1], c[p:p + 1])
+                  - _oracle_loss(layers, Xm, Z64[p:p + 1], c[p:p + 1])) / (2 * e)
+            assert abs(gX[p, k] - fd) <= 1e-4 * np.abs(gX).max(), (p, k, gX[p, k], fd)
 
 
 def test_bf16_backward_close_to_fp64():
