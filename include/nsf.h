@@ -282,6 +282,19 @@ nsf_status nsf_mlp_backward(const nsf_mlp *m, const float *X, const float *z_row
                             const float *saved, const float *dout, float *dW, float *dz,
                             float *dX, void *workspace, size_t workspace_bytes, void *stream);
 
+/* nsf_mlp_forward without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). It allocates nothing: the packed weights go to a library-owned device array
+ * of 1 MiB per GPU (enough for any nsf_mlp this header accepts: width 128, r = 32, d = 9
+ * packs to ~0.7 MB), resolved once per device on that device's first call. Arguments,
+ * layouts and results are those of nsf_mlp_forward. Returns NSF_EINVAL for an invalid m
+ * or NULL X / z_rows / out, NSF_ENOMEM if the packed weights would exceed the array,
+ * NSF_EHIP if the array's address cannot be resolved. Every call on one GPU shares its
+ * array and the array keeps the last call's packed weights: calls that overlap on one GPU
+ * (different streams, or threads) race and must be serialised by the caller. */
+nsf_status nsf_mlp_forward_noalloc(const nsf_mlp *m, const float *X, const float *z_rows,
+                                   int64_t n, float *out, float *saved, void *stream);
+
 /* ---- Full-order MLS-MPM (the model the reduced step is measured against) -------------
  * Every particle is integrated (Sec. 3.3): P2G with APIC and the MLS stress impulse, grid
  * update with gravity, sticky walls and a separating ground (the bottom wall_nodes layers

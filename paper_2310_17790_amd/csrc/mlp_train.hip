@@ -17,6 +17,8 @@
 // (deterministic) into dW.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "nsf.h"
 #include "nsf_dev.h"
 #include "pack.h"
@@ -421,29 +423,11 @@ nsf_status check_mlp(const nsf_mlp* m, int64_t n) {
   return NSF_OK;
 }
 
-}  // namespace
-}  // namespace nsf
-
-using namespace nsf;
-
-extern "C" {
-
-size_t nsf_mlp_param_count(int32_t r, int32_t width, int32_t d) { return mlp_param_count(r, width, d); }
-
-size_t nsf_mlp_saved_floats(int32_t width, int64_t n) { return (size_t)5 * width * n; }
-
-size_t nsf_mlp_workspace_bytes(const nsf_mlp* m, int64_t n) {
-  if (check_mlp(m, n) != NSF_OK) return 0;
-  return carve(nullptr, m->r, m->width, m->d, n, true).bytes;
-}
-
-nsf_status nsf_mlp_forward(const nsf_mlp* m, const float* X, const float* z_rows, int64_t n,
-                           float* out, float* saved, void* workspace, size_t workspace_bytes,
-                           void* stream) {
+nsf_status mlp_forward(const nsf_mlp* m, const float* X, const float* z_rows, int64_t n, float* out,
+                       float* saved, char* workspace, size_t workspace_bytes, hipStream_t s) {
   if (check_mlp(m, n) != NSF_OK || !X || !z_rows || !out || !workspace) return NSF_EINVAL;
-  const TrainWs ws = carve(static_cast<char*>(workspace), m->r, m->width, m->d, n, false);
+  const TrainWs ws = carve(workspace, m->r, m->width, m->d, n, false);
   if (workspace_bytes < ws.bytes) return NSF_ENOMEM;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(pack_kernel, dim3(256), dim3(256), 0, s, m->weights, m->r, m->width, m->d, ws.pk);
   if (hipGetLastError() != hipSuccess) return NSF_EHIP;
   FieldJob j{};
@@ -465,6 +449,64 @@ nsf_status nsf_mlp_forward(const nsf_mlp* m, const float* X, const float* z_rows
   for (int c = 0; c < 9; ++c) { j.scale[c] = 1.f; j.shift[c] = 0.f; }
   if (launch_fields_dense(m->width, m->precision == NSF_BF16, j, (int)n, s) != hipSuccess) return NSF_EHIP;
   return NSF_OK;
+}
+
+// The allocation-free forward's workspace: the packed weights of one field, at most
+// ~0.7 MB (width 128, r = 32, d = 9). Each device holds its own copy for the life of the
+// process; host code uses it only through the address hipGetSymbolAddress returns for the
+// current device, never through the symbol itself.
+constexpr size_t kScratchBytes = (size_t)1 << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+nsf_status scratch_address(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return NSF_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NSF_EHIP;
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return NSF_OK;
+}
+
+}  // namespace
+}  // namespace nsf
+
+using namespace nsf;
+
+extern "C" {
+
+size_t nsf_mlp_param_count(int32_t r, int32_t width, int32_t d) { return mlp_param_count(r, width, d); }
+
+size_t nsf_mlp_saved_floats(int32_t width, int64_t n) { return (size_t)5 * width * n; }
+
+size_t nsf_mlp_workspace_bytes(const nsf_mlp* m, int64_t n) {
+  if (check_mlp(m, n) != NSF_OK) return 0;
+  return carve(nullptr, m->r, m->width, m->d, n, true).bytes;
+}
+
+nsf_status nsf_mlp_forward(const nsf_mlp* m, const float* X, const float* z_rows, int64_t n,
+                           float* out, float* saved, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  return mlp_forward(m, X, z_rows, n, out, saved, static_cast<char*>(workspace), workspace_bytes,
+                     static_cast<hipStream_t>(stream));
+}
+
+nsf_status nsf_mlp_forward_noalloc(const nsf_mlp* m, const float* X, const float* z_rows, int64_t n,
+                                   float* out, float* saved, void* stream) {
+  if (check_mlp(m, n) != NSF_OK || !X || !z_rows || !out) return NSF_EINVAL;
+  const size_t need = carve(nullptr, m->r, m->width, m->d, n, false).bytes;
+  if (need > kScratchBytes) return NSF_ENOMEM;
+  char* base = nullptr;
+  const nsf_status e = scratch_address(&base);
+  if (e != NSF_OK) return e;
+  return mlp_forward(m, X, z_rows, n, out, saved, base, kScratchBytes, static_cast<hipStream_t>(stream));
 }
 
 nsf_status nsf_mlp_backward(const nsf_mlp* m, const float* X, const float* z_rows, int64_t n,
