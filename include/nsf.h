@@ -166,7 +166,7 @@ nsf_status nsf_step(nsf_sim *s, int32_t n_steps, void *stream);
  * alone. All sims must share width and precision. The launch shape is planned for this
  * set of sims on first use; when the set changes, the work tables are rewritten and the
  * captured graph is replayed unchanged (it is re-captured only when the tables outgrow
- * their capacity). */
+ * their capacity). At most 1024 sims per call (NSF_EINVAL beyond). */
 nsf_status nsf_step_batch(nsf_sim *const *sims, int32_t n, int32_t n_steps, void *stream);
 
 /* The MPM stage of the current step alone (Sec. 5.2, with the algorithm of Sec. 3.3),

@@ -58,7 +58,7 @@ struct Layout {
   size_t simdev;
   size_t whp[3], whb[3], b6[3], w1q[3], bhq[3], w6q[3], whpt[3], whbt[3], w1zt[3];
   size_t X, plan, u_n, u_prev, tau, C, J, vnew, u_gn, J2, xdec, grid, z, zdec, zh, step, flags, gn_part;
-  size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active,
+  size_t bin_cnt, bin_meta, epoch, pbin, prank, rec, rec_p, sorted, active,
       nonempty, n_active;
   size_t node_mask, is_sample, member, cl_block, n_live;   // closure integration only
   size_t total;
@@ -114,13 +114,12 @@ Layout make_layout(const nsf_sim_desc* d) {
   const int nbs = bins_per_axis(d->grid_n);
   const size_t nb = (size_t)nbs * nbs * nbs;
   L.bin_cnt = c.take(nb * 4);
-  L.bin_start = c.take(nb * 4);
-  L.seg_cnt = c.take(nb * 4);
-  L.bin_epoch = c.take(nb * 4);
+  L.bin_meta = c.take(nb * 16);
   L.epoch = c.take(4);
   L.pbin = c.take((size_t)N * 4);
   L.prank = c.take((size_t)N * 4);
-  L.rec = c.take((size_t)N * 64);
+  L.rec = c.take((size_t)N * 128);
+  L.rec_p = c.take((size_t)N * 128);
   L.sorted = c.take((size_t)N * 4);
   L.active = c.take(nb * 4);
   L.nonempty = c.take(nb * 4);
@@ -665,13 +664,16 @@ nsf_status enqueue_refresh(Plan& P, hipStream_t s) {
 // Gauss-Newton chunk sums. A pipelined decode forks after the binning kernel, which takes
 // its latent snapshot.
 nsf_status enqueue_mpm(Plan& P, hipStream_t s, bool fork) {
-  NSF_HIP(launch_bin(P.d_sims, P.d_bP, P.d_counts + 3, P.d_counts + 8, P.gP, s));
+  // every sparse (plan-mode) sim takes the wave-per-block gather, alone or in a batch, so a
+  // sim's sums are the same bits either way
+  const bool batch = !P.closure;
+  NSF_HIP(launch_bin(P.d_sims, P.d_bP, P.d_counts + 3, P.d_counts + 8, P.gP, batch, s));
   if (fork) {
     const nsf_status st = fork_decode(P, s);
     if (st != NSF_OK) return st;
   }
   NSF_HIP(launch_p2g_after_bin(P.d_sims, P.d_counts + 6, P.gSims, P.d_bP, P.d_counts + 3, P.gP, P.gBlk, P.closure,
-                               P.grid_cap, P.place, s));
+                               P.grid_cap, P.place, batch, s));
   NSF_HIP(launch_g2p_gn(P.d_sims, P.d_bGN, P.d_counts + 5, P.r_cap, P.gGN, s));
   return NSF_OK;
 }
@@ -744,6 +746,7 @@ nsf_status run_plan(Plan& P, int32_t n_steps, hipStream_t s) {
 
 nsf_status check_batch(nsf_sim* const* sims, int32_t n) {
   if (!sims || n < 1) return fail(NSF_EINVAL, "empty batch");
+  if (n > kMaxBatchSims) return fail(NSF_EINVAL, "batch of %d sims exceeds %d", n, kMaxBatchSims);
   for (int i = 0; i < n; ++i) {
     if (!sims[i]) return fail(NSF_EINVAL, "sims[%d] is NULL", i);
     if (n > 1 && sims[i]->closure)
@@ -922,8 +925,8 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   NSF_HIP(hipMemsetAsync(A + L.grid, 0, n3 * 16, s));
   NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
   NSF_HIP(hipMemsetAsync(A + L.flags, 0, 4, s));
-  NSF_HIP(hipMemsetAsync(A + L.bin_cnt, 0, L.bin_start - L.bin_cnt, s));
-  NSF_HIP(hipMemsetAsync(A + L.bin_epoch, 0xff, L.epoch - L.bin_epoch, s));   // epoch -1: never set
+  NSF_HIP(hipMemsetAsync(A + L.bin_cnt, 0, L.bin_meta - L.bin_cnt, s));
+  NSF_HIP(hipMemsetAsync(A + L.bin_meta, 0xff, L.epoch - L.bin_meta, s));   // epoch -1: never set
   NSF_HIP(hipMemsetAsync(A + L.epoch, 0, 4, s));
   NSF_HIP(hipMemsetAsync(A + L.xdec, 0, (size_t)3 * P * 4, s));
 
@@ -985,13 +988,12 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   H.nbs = bins_per_axis(d->grid_n);
   H.n_bins = H.nbs * H.nbs * H.nbs;
   H.bin_cnt = reinterpret_cast<int32_t*>(A + L.bin_cnt);
-  H.bin_start = reinterpret_cast<int32_t*>(A + L.bin_start);
-  H.seg_cnt = reinterpret_cast<int32_t*>(A + L.seg_cnt);
-  H.bin_epoch = reinterpret_cast<int32_t*>(A + L.bin_epoch);
+  H.bin_meta = reinterpret_cast<int4*>(A + L.bin_meta);
   H.epoch = reinterpret_cast<int32_t*>(A + L.epoch);
   H.pbin = reinterpret_cast<int32_t*>(A + L.pbin);
   H.prank = reinterpret_cast<int32_t*>(A + L.prank);
   H.rec = reinterpret_cast<float*>(A + L.rec);
+  H.rec_p = reinterpret_cast<float*>(A + L.rec_p);
   H.sorted = reinterpret_cast<int32_t*>(A + L.sorted);
   H.active = reinterpret_cast<int32_t*>(A + L.active);
   H.nonempty = reinterpret_cast<int32_t*>(A + L.nonempty);
@@ -1025,6 +1027,7 @@ nsf_status nsf_step(nsf_sim* s, int32_t n_steps, void* stream) {
 
 nsf_status nsf_step_batch(nsf_sim* const* sims, int32_t n, int32_t n_steps, void* stream) {
   if (!sims || n < 1) return fail(NSF_EINVAL, "empty batch");
+  if (n > kMaxBatchSims) return fail(NSF_EINVAL, "batch of %d sims exceeds %d", n, kMaxBatchSims);
   if (n_steps < 0) return fail(NSF_EINVAL, "n_steps < 0");
   if (n == 1) return nsf_step(sims[0], n_steps, stream);
   const nsf_status chk = check_batch(sims, n);
@@ -1234,7 +1237,7 @@ namespace {
 
 struct FoLayout {
   size_t simdev, counts, bP, X, plan, u, v, tau, C, F, grid, step, flags;
-  size_t bin_cnt, bin_start, seg_cnt, bin_epoch, epoch, pbin, prank, rec, sorted, active, nonempty, n_active;
+  size_t bin_cnt, bin_meta, epoch, pbin, prank, rec, rec_p, sorted, active, nonempty, n_active;
   size_t z;
   size_t total;
 };
@@ -1281,13 +1284,12 @@ FoLayout fo_layout(const nsf_fo_desc* d) {
   L.step = c.take(8);
   L.flags = c.take(4);
   L.bin_cnt = c.take(nb * 4);
-  L.bin_start = c.take(nb * 4);
-  L.seg_cnt = c.take(nb * 4);
-  L.bin_epoch = c.take(nb * 4);
+  L.bin_meta = c.take(nb * 16);
   L.epoch = c.take(4);
   L.pbin = c.take((size_t)P * 4);
   L.prank = c.take((size_t)P * 4);
-  L.rec = c.take((size_t)P * 64);
+  L.rec = c.take((size_t)P * 128);
+  L.rec_p = c.take((size_t)P * 128);
   L.sorted = c.take((size_t)P * 4);
   L.active = c.take(nb * 4);
   L.nonempty = c.take(nb * 4);
@@ -1298,9 +1300,9 @@ FoLayout fo_layout(const nsf_fo_desc* d) {
 }
 
 nsf_status fo_enqueue_step(nsf_fo& f, hipStream_t s) {
-  NSF_HIP(launch_bin(f.dd, f.d_bP, f.d_counts + 3, f.d_counts + 8, f.nP, s));
+  NSF_HIP(launch_bin(f.dd, f.d_bP, f.d_counts + 3, f.d_counts + 8, f.nP, false, s));
   NSF_HIP(launch_p2g_after_bin(f.dd, f.d_counts + 6, 1, f.d_bP, f.d_counts + 3, f.nP, 5 * device_cus(), true,
-                               f.grid_n, f.n_part > kAllocByParticles, s));
+                               f.grid_n, f.n_part > kAllocByParticles, false, s));
   NSF_HIP(launch_fo_g2p(f.dd, f.n_part, s));
   return NSF_OK;
 }
@@ -1356,8 +1358,8 @@ nsf_status nsf_fo_create(const nsf_fo_desc* d, void* arena, size_t arena_bytes, 
   NSF_HIP(hipMemsetAsync(A + L.grid, 0, n3 * 16, s));
   NSF_HIP(hipMemsetAsync(A + L.step, 0, 8, s));
   NSF_HIP(hipMemsetAsync(A + L.flags, 0, 4, s));
-  NSF_HIP(hipMemsetAsync(A + L.bin_cnt, 0, L.bin_start - L.bin_cnt, s));
-  NSF_HIP(hipMemsetAsync(A + L.bin_epoch, 0, L.epoch + 4 - L.bin_epoch, s));
+  NSF_HIP(hipMemsetAsync(A + L.bin_cnt, 0, L.bin_meta - L.bin_cnt, s));
+  NSF_HIP(hipMemsetAsync(A + L.bin_meta, 0, L.epoch + 4 - L.bin_meta, s));
   NSF_HIP(hipMemcpyAsync(A + L.counts, counts.data(), counts.size() * 4, hipMemcpyHostToDevice, s));
   NSF_HIP(hipMemcpyAsync(A + L.bP, bP.data(), bP.size() * sizeof(BlockWork), hipMemcpyHostToDevice, s));
   SimDev& H = f->hd;
@@ -1410,13 +1412,12 @@ nsf_status nsf_fo_create(const nsf_fo_desc* d, void* arena, size_t arena_bytes, 
   H.nbs = bins_per_axis(d->grid_n);
   H.n_bins = H.nbs * H.nbs * H.nbs;
   H.bin_cnt = reinterpret_cast<int32_t*>(A + L.bin_cnt);
-  H.bin_start = reinterpret_cast<int32_t*>(A + L.bin_start);
-  H.seg_cnt = reinterpret_cast<int32_t*>(A + L.seg_cnt);
-  H.bin_epoch = reinterpret_cast<int32_t*>(A + L.bin_epoch);
+  H.bin_meta = reinterpret_cast<int4*>(A + L.bin_meta);
   H.epoch = reinterpret_cast<int32_t*>(A + L.epoch);
   H.pbin = reinterpret_cast<int32_t*>(A + L.pbin);
   H.prank = reinterpret_cast<int32_t*>(A + L.prank);
   H.rec = reinterpret_cast<float*>(A + L.rec);
+  H.rec_p = reinterpret_cast<float*>(A + L.rec_p);
   H.sorted = reinterpret_cast<int32_t*>(A + L.sorted);
   H.active = reinterpret_cast<int32_t*>(A + L.active);
   H.nonempty = reinterpret_cast<int32_t*>(A + L.nonempty);

@@ -91,11 +91,78 @@ __device__ __forceinline__ void particle_x(const SimDev& S, int p, int gi, float
   for (int c = 0; c < 3; ++c) x[c] = S.X[(int64_t)c * S.n_part + gi] + S.u_n[c * S.n_int + p];
 }
 
+// P2G record of an integration particle, kRec floats (128 bytes), in one of two layouts.
+// Workgroup layout (solo plans, dense sets and grids above 128^3; the gather recomputes
+// the stencil from x):
+//   [0..2] x, [3..5] m_p v, [6..14] A = m_p C - dt V_p (4/dx^2) tau (row-major),
+//   [15] the stencil base cell packed 10 bits per axis (x << 20 | y << 10 | z).
+// Wave layout (sparse sims on grids up to 128^3 in a batch), everything a node needs to add
+// the particle's contribution with a few FMAs: with node offset o = (a, b, c) in {0,1,2}^3
+// from the base, the contribution to mass is m_p w and to momentum w (q + dx A o), where
+// q = m_p v - dx A f (f = x / dx - base), and each axis weight is a quadratic in o through
+// the three B-spline weights (w(o) = alpha + o (beta + gamma o)):
+//   [0..2] q, [3..11] dx A (row-major), [12..20] (alpha, beta, gamma) per axis,
+//   [21] the packed base, [22..31] unused.
+// The binning writes the record in particle order (every field array is read coalesced),
+// the sort copies it into bin order.
+constexpr int kRec = 32;
+
+__device__ __forceinline__ void write_record(const SimDev& S, int p, const float x[3], const Stencil& st,
+                                             bool wave_layout, float* r) {
+  const int n_int = S.n_int;
+  float v[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float u = S.u_n[c * n_int + p];
+    const float up = S.u_prev[c * n_int + p];
+    v[c] = S.tangent_forms ? up : (u - up) / S.dt;  // u_prev holds v itself in tangent form
+  }
+  float t6[6], C[9];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) t6[c] = S.tau[c * n_int + p];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) C[c] = S.C[c * n_int + p];
+  // Voigt (xx, yy, zz, yz, xz, xy) -> symmetric tau
+  const float tau[9] = {t6[0], t6[5], t6[4], t6[5], t6[1], t6[3], t6[4], t6[3], t6[2]};
+  float A[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) A[e] = S.mp * C[e] - S.stress_k * tau[e];
+  const int pb = (st.base[0] << 20) | (st.base[1] << 10) | st.base[2];
+  float4* r4 = reinterpret_cast<float4*>(r);
+  if (!wave_layout) {
+    r4[0] = make_float4(x[0], x[1], x[2], S.mp * v[0]);
+    r4[1] = make_float4(S.mp * v[1], S.mp * v[2], A[0], A[1]);
+    r4[2] = make_float4(A[2], A[3], A[4], A[5]);
+    r4[3] = make_float4(A[6], A[7], A[8], __int_as_float(pb));
+    return;
+  }
+  const float dx = S.dx;
+  float dA[9], q[3], poly[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) dA[e] = dx * A[e];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) q[c] = S.mp * v[c] - (dA[3 * c] * st.f[0] + dA[3 * c + 1] * st.f[1] + dA[3 * c + 2] * st.f[2]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float w0 = st.w[c][0], w1 = st.w[c][1], w2 = st.w[c][2];
+    const float g = 0.5f * (w0 - 2.f * w1 + w2);
+    poly[3 * c] = w0;
+    poly[3 * c + 1] = w1 - w0 - g;
+    poly[3 * c + 2] = g;
+  }
+  r4[0] = make_float4(q[0], q[1], q[2], dA[0]);
+  r4[1] = make_float4(dA[1], dA[2], dA[3], dA[4]);
+  r4[2] = make_float4(dA[5], dA[6], dA[7], dA[8]);
+  r4[3] = make_float4(poly[0], poly[1], poly[2], poly[3]);
+  r4[4] = make_float4(poly[4], poly[5], poly[6], poly[7]);
+  r4[5] = make_float4(poly[8], __int_as_float(pb), 0.f, 0.f);
+}
+
 // ---- bin ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kMpmBlock) void bin_kernel(const SimDev* __restrict__ sims,
                                                         const BlockWork* __restrict__ work,
                                                         const int32_t* __restrict__ n_work,
-                                                        int32_t* __restrict__ claims) {
+                                                        int32_t* __restrict__ claims, int full) {
   // the field kernels' claim counters of this step start from zero
   if (blockIdx.x == 0 && threadIdx.x < kClaimCounters) claims[threadIdx.x] = 0;
   const int total = *n_work;
@@ -121,6 +188,7 @@ __global__ __launch_bounds__(kMpmBlock) void bin_kernel(const SimDev* __restrict
     const int bin = ((st.base[0] / B) * nbs + st.base[1] / B) * nbs + st.base[2] / B;
     S.pbin[p] = bin;
     S.prank[p] = atomicAdd(&S.bin_cnt[bin], 1);
+    write_record(S, p, x, st, full != 0 && S.bin_edge == 4, S.rec_p + (int64_t)p * kRec);
   }
 }
 
@@ -129,9 +197,10 @@ constexpr int kAllocThreads = 1024;
 constexpr int kMaxBins = 32768;   // 32 bins per axis at most
 constexpr int kBinsPerThread = kMaxBins / kAllocThreads;   // contiguous bins per alloc thread
 
-// Exclusive scan of one value per thread over the workgroup; returns the prefix and the
-// workgroup total in *total.
-__device__ __forceinline__ int block_exclusive_scan(int v, int* wave_sums, int* total) {
+// Exclusive scan of one value per thread over a workgroup of T threads; returns the prefix
+// and the workgroup total in *total. wave_sums holds T / 64 ints.
+template <int T>
+__device__ __forceinline__ int block_scan(int v, int* wave_sums, int* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int incl = v;
 #pragma unroll
@@ -143,19 +212,68 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wave_sums, int* 
   __syncthreads();
   if (threadIdx.x < 64) {
     const int w = threadIdx.x;
-    int x = w < kAllocThreads / 64 ? wave_sums[w] : 0;
+    int x = w < T / 64 ? wave_sums[w] : 0;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int t = __shfl_up(x, o);
       if (w >= o) x += t;
     }
-    if (w < kAllocThreads / 64) wave_sums[w] = x;   // inclusive over waves
+    if (w < T / 64) wave_sums[w] = x;   // inclusive over waves
   }
   __syncthreads();
   const int excl = (wave > 0 ? wave_sums[wave - 1] : 0) + incl - v;
-  *total = wave_sums[kAllocThreads / 64 - 1];
+  *total = wave_sums[T / 64 - 1];
   __syncthreads();
   return excl;
+}
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* wave_sums, int* total) {
+  return block_scan<kAllocThreads>(v, wave_sums, total);
+}
+
+// Work items spread over the sims of a launch, one item per wave: count(S) items in sim S.
+// Every thread of the workgroup computes the exclusive prefix s_pre[s] (items of the sims
+// before s; s_pre[nsims] = the total, returned) in LDS; find_sim maps an item to its sim.
+// nsims <= kMaxBatchSims.
+template <int T, class Count>
+__device__ __forceinline__ int sims_prefix(const SimDev* __restrict__ sims, int nsims, int* s_pre,
+                                           int* wave_sums, Count count) {
+  const int per = (nsims + T - 1) / T;
+  const int lo = min(nsims, (int)threadIdx.x * per), hi = min(nsims, lo + per);
+  int local = 0;
+  for (int s = lo; s < hi; ++s) {
+    const int c = count(sims[s]);
+    s_pre[s] = c;
+    local += c;
+  }
+  int total;
+  int run = block_scan<T>(local, wave_sums, &total);
+  for (int s = lo; s < hi; ++s) {
+    const int c = s_pre[s];
+    s_pre[s] = run;
+    run += c;
+  }
+  if (threadIdx.x == 0) s_pre[nsims] = total;
+  __syncthreads();
+  return total;
+}
+
+// The sim whose items [s_pre[s], s_pre[s + 1]) hold item v (0 <= v < s_pre[nsims]).
+__device__ __forceinline__ int find_sim(const int* s_pre, int nsims, int v) {
+  int lo = 0, hi = nsims;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s_pre[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Orders this wave's earlier LDS accesses before its later ones (the wave owns the region:
+// no workgroup barrier is involved).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 // Slot allocation, one workgroup per sim, in one of two ways (both deterministic; where a
@@ -174,9 +292,7 @@ constexpr int kAllocBatch = 8;               // particles per thread per batch o
 __device__ __forceinline__ void list_bin(const SimDev& S, int b, int c, int start, int ep, int& ne_pos,
                                          uint32_t* mark) {
   S.bin_cnt[b] = 0;   // counts start from zero next step
-  S.seg_cnt[b] = c;
-  S.bin_start[b] = start;
-  S.bin_epoch[b] = ep;
+  S.bin_meta[b] = make_int4(ep, start, c, 0);
   S.nonempty[ne_pos++] = b;
   const int nbs = S.nbs;
   const int bx = b / (nbs * nbs), by = (b / nbs) % nbs, bz = b % nbs;
@@ -318,91 +434,81 @@ __global__ __launch_bounds__(kMpmBlock) void place_kernel(const SimDev* __restri
     const int p = wk.p0 + threadIdx.x;
     if (p >= n) continue;
     const int pb = S.pbin[p];
-    if (pb >= 0) S.sorted[S.bin_start[pb] + S.prank[p]] = p;
+    if (pb >= 0) S.sorted[S.bin_meta[pb].y + S.prank[p]] = p;
   }
 }
 
-// ---- sort each bin, write records ---------------------------------------------------
-// P2G record of particle p: x, m_p v, A = m_p C - dt V_p (4/dx^2) tau, and p itself.
-__device__ __forceinline__ void write_record(const SimDev& S, int p, float* r) {
-  const int n_int = S.n_int;
-  const int gi = plan_row(S)[p];
-  float x[3], v[3];
+// One wave per non-empty bin (bins spread over the launch's sims): sort the bin's particle
+// indices (in registers up to 64, in the wave's LDS up to kSegMax; a larger bin keeps its
+// arrival order) and copy the records into bin order.
+constexpr int kSortWaves = 4, kSortThreads = 64 * kSortWaves;
+
+template <int NQ>
+__device__ __forceinline__ void copy_record(const SimDev& S, int p, int slot) {
+  const float4* src = reinterpret_cast<const float4*>(S.rec_p + (int64_t)p * kRec);
+  float4* dst = reinterpret_cast<float4*>(S.rec + (int64_t)slot * kRec);
+  float4 q[NQ];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const float u = S.u_n[c * n_int + p];
-    const float up = S.u_prev[c * n_int + p];
-    x[c] = S.X[(int64_t)c * S.n_part + gi] + u;
-    v[c] = S.tangent_forms ? up : (u - up) / S.dt;  // u_prev holds v itself in tangent form
-  }
-  float t6[6], C[9];
+  for (int k = 0; k < NQ; ++k) q[k] = src[k];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) t6[c] = S.tau[c * n_int + p];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) C[c] = S.C[c * n_int + p];
-  // Voigt (xx, yy, zz, yz, xz, xy) -> symmetric tau
-  const float tau[9] = {t6[0], t6[5], t6[4], t6[5], t6[1], t6[3], t6[4], t6[3], t6[2]};
-  float A[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) A[e] = S.mp * C[e] - S.stress_k * tau[e];
-  float4* r4 = reinterpret_cast<float4*>(r);
-  r4[0] = make_float4(x[0], x[1], x[2], S.mp * v[0]);
-  r4[1] = make_float4(S.mp * v[1], S.mp * v[2], A[0], A[1]);
-  r4[2] = make_float4(A[2], A[3], A[4], A[5]);
-  r4[3] = make_float4(A[6], A[7], A[8], __int_as_float(p));
+  for (int k = 0; k < NQ; ++k) dst[k] = q[k];
 }
 
-// One workgroup per non-empty bin: sort the bin's particle indices (in the first wave's
-// registers up to 64, in LDS up to kSegMax; a larger bin keeps its arrival order) and
-// write the records in that order, four waves at a time (a dense integration set has
-// hundreds of particles per bin).
-constexpr int kSortThreads = 256;
+// the first NQ float4 of the record: 6 for the wave layout, 4 for the workgroup layout
+template <int NQ>
+__device__ __forceinline__ void copy_records(const SimDev& S, const int* idx, int start, int cnt, int lane) {
+  for (int i = lane; i < cnt; i += 64) copy_record<NQ>(S, idx[i], start + i);
+}
+
+template <int NQ>
 __global__ __launch_bounds__(kSortThreads) void bin_sort_kernel(const SimDev* __restrict__ sims,
                                                                 const int32_t* __restrict__ n_sims) {
-  __shared__ int s_buf[kSegMax];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int total_sims = *n_sims;
-  const SimShare sh(total_sims);
-  for (int s = sh.first; s < total_sims; s += sh.groups) {
+  __shared__ int s_pre[kMaxBatchSims + 1];
+  __shared__ int wave_sums[kSortWaves];
+  __shared__ int s_buf[kSortWaves][kSegMax];
+  const int nsims = *n_sims;
+  const int total = sims_prefix<kSortThreads>(sims, nsims, s_pre, wave_sums,
+                                              [](const SimDev& S) { return S.n_active[1]; });
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  int* buf = s_buf[wv];
+  for (int v = blockIdx.x * kSortWaves + wv; v < total; v += gridDim.x * kSortWaves) {
+    // wave-uniform, so the sim's constants and the bin's slot range come through scalar loads
+    const int s = __builtin_amdgcn_readfirstlane(find_sim(s_pre, nsims, v));
     const SimDev& S = sims[s];
-    const int ne = S.n_active[1];
-    for (int k = sh.q; k < ne; k += sh.per) {
-      const int b = S.nonempty[k];
-      const int start = S.bin_start[b];
-      const int cnt = S.seg_cnt[b];
-      int32_t* seg = S.sorted + start;
-      if (cnt <= 64) {
-        if (tid < 64) {
-          int v = lane < cnt ? seg[lane] : 0x7fffffff;
-          for (int kk = 2; kk <= 64; kk <<= 1)
-            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-              const int o = __shfl_xor(v, jj);
-              const bool lower = (lane & jj) == 0, up = (lane & kk) == 0;
-              v = (lower == up) ? min(v, o) : max(v, o);
-            }
-          if (lane < cnt) write_record(S, v, S.rec + (int64_t)(start + lane) * 16);
+    const int b = __builtin_amdgcn_readfirstlane(S.nonempty[v - s_pre[s]]);
+    const int4 meta = S.bin_meta[b];
+    const int start = meta.y;
+    const int cnt = meta.z;
+    const int32_t* seg = S.sorted + start;
+    if (cnt <= 64) {
+      int x = lane < cnt ? seg[lane] : 0x7fffffff;
+      for (int kk = 2; kk <= 64; kk <<= 1)
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+          const int o = __shfl_xor(x, jj);
+          const bool lower = (lane & jj) == 0, up = (lane & kk) == 0;
+          x = (lower == up) ? min(x, o) : max(x, o);
         }
-      } else if (cnt <= kSegMax) {
-        int p2 = 64;
-        while (p2 < cnt) p2 <<= 1;
-        for (int i = tid; i < p2; i += kSortThreads) s_buf[i] = i < cnt ? seg[i] : 0x7fffffff;
-        __syncthreads();
-        for (int kk = 2; kk <= p2; kk <<= 1)
-          for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < p2; i += kSortThreads) {
-              const int l = i ^ jj;
-              if (l > i) {
-                const int a = s_buf[i], c = s_buf[l];
-                if ((a > c) == ((i & kk) == 0)) { s_buf[i] = c; s_buf[l] = a; }
-              }
+      if (lane < cnt) copy_record<NQ>(S, x, start + lane);
+    } else if (cnt <= kSegMax) {
+      int p2 = 128;
+      while (p2 < cnt) p2 <<= 1;
+      for (int i = lane; i < p2; i += 64) buf[i] = i < cnt ? seg[i] : 0x7fffffff;
+      wave_lds_sync();
+      for (int kk = 2; kk <= p2; kk <<= 1)
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+          for (int i = lane; i < p2; i += 64) {
+            const int l = i ^ jj;
+            if (l > i) {
+              const int a = buf[i], c = buf[l];
+              if ((a > c) == ((i & kk) == 0)) { buf[i] = c; buf[l] = a; }
             }
-            __syncthreads();
           }
-        for (int i = tid; i < cnt; i += kSortThreads) write_record(S, s_buf[i], S.rec + (int64_t)(start + i) * 16);
-        __syncthreads();
-      } else {
-        for (int i = tid; i < cnt; i += kSortThreads) write_record(S, seg[i], S.rec + (int64_t)(start + i) * 16);
-      }
+          wave_lds_sync();
+        }
+      copy_records<NQ>(S, buf, start, cnt, lane);
+      wave_lds_sync();
+    } else {
+      copy_records<NQ>(S, seg, start, cnt, lane);
     }
   }
 }
@@ -439,7 +545,7 @@ __device__ __forceinline__ void node_velocity(const SimDev& S, float m, const fl
 // kMaxNodesPerLane for any grid); the accumulators of unused nodes cost registers.
 template <int T, int NPL>
 __global__ __launch_bounds__(T) void gather_kernel(const SimDev* __restrict__ sims,
-                                                  const int32_t* __restrict__ n_sims) {
+                                                  const int32_t* __restrict__ n_sims, int edge_only) {
   constexpr int NG = T / 64;   // lane groups
   // staged records, structure of arrays
   __shared__ float s_mv[3][T];
@@ -457,6 +563,7 @@ __global__ __launch_bounds__(T) void gather_kernel(const SimDev* __restrict__ si
   const SimShare share(total_sims);
   for (int s = share.first; s < total_sims; s += share.groups) {
     const SimDev& S = sims[s];
+    if (edge_only && S.bin_edge != edge_only) continue;   // served by gather_wave_kernel
     const int nact = S.n_active[0];
     const int B = S.bin_edge, nbs = S.nbs, n = S.grid_n;
     const int nodes = B * B * B;
@@ -474,7 +581,8 @@ __global__ __launch_bounds__(T) void gather_kernel(const SimDev* __restrict__ si
         int c = 0, from = 0;
         if (sx >= 0 && sy >= 0 && sz >= 0) {
           const int sb = (sx * nbs + sy) * nbs + sz;
-          const int e = S.bin_epoch[sb], f = S.bin_start[sb], cc = S.seg_cnt[sb];
+          const int4 meta = S.bin_meta[sb];
+          const int e = meta.x, f = meta.y, cc = meta.z;
           if (e == ep) {
             from = f;
             c = cc;
@@ -509,7 +617,7 @@ __global__ __launch_bounds__(T) void gather_kernel(const SimDev* __restrict__ si
         if (g < total) {
           int d = 0;
           while (g >= s_seg[d + 1]) ++d;
-          r4 = reinterpret_cast<const float4*>(S.rec + (int64_t)(s_from[d] + g - s_seg[d]) * 16);
+          r4 = reinterpret_cast<const float4*>(S.rec + (int64_t)(s_from[d] + g - s_seg[d]) * kRec);
           keep = true;
           if (dense) {
             const float4 a = r4[0];
@@ -599,6 +707,149 @@ __global__ __launch_bounds__(T) void gather_kernel(const SimDev* __restrict__ si
         __syncthreads();
       }
     }
+  }
+}
+
+// Gather with one wave per active node block, for sims whose bins are 4^3 cells (grids up
+// to 128^3) and whose integration particles are sparse (under one particle per cell on
+// average, as a uniform sample of a few percent is). Node blocks of every sim of the launch
+// form one list, dealt to waves in order. Lane q of the wave owns node q of the block and
+// keeps its mass and momentum sums in registers. The records of the block's 2 x 2 x 2
+// source bins are taken 64 at a time in the fixed order (bin order, each bin sorted by
+// particle index): lane j loads record j's stencil base, and the wave walks the records
+// whose stencil reaches the block in lane order, reading each through scalar loads into
+// scalar registers (a vector load of one address would return a copy to every lane), the
+// lanes whose node lies in its stencil adding its contribution. No LDS, no barrier: the sums
+// depend only on the sim's own records, so a sim stepped alone or in any batch gives the
+// same bits.
+// global-address-space views (vector loads that complete in order, not flat loads)
+typedef const __attribute__((address_space(1))) float* GlobalF;
+typedef const __attribute__((address_space(1))) int* GlobalI;
+// constant-address-space view: uniform loads through it are scalar loads
+typedef const __attribute__((address_space(4))) float* ConstRec;
+constexpr int kGsWaves = 4, kGsThreads = 64 * kGsWaves;
+constexpr int kGsBatch = 2;   // records per batch of scalar loads (3: no faster, one wave fewer per SIMD)
+
+__global__ __launch_bounds__(kGsThreads) void gather_lanes_kernel(const SimDev* __restrict__ sims,
+                                                                  const int32_t* __restrict__ n_sims) {
+  __shared__ int s_pre[kMaxBatchSims + 1];
+  __shared__ int wave_sums[kGsWaves];
+  const int nsims = *n_sims;
+  const int total = sims_prefix<kGsThreads>(sims, nsims, s_pre, wave_sums,
+                                            [](const SimDev& S) { return S.bin_edge == 4 ? S.n_active[0] : 0; });
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lx = lane >> 4, ly = (lane >> 2) & 3, lz = lane & 3;   // node of the lane in its block
+  const int stride = gridDim.x * kGsWaves;
+  int v = blockIdx.x * kGsWaves + wave;
+  int s = 0, blk = 0;
+  if (v < total) {
+    s = __builtin_amdgcn_readfirstlane(find_sim(s_pre, nsims, v));
+    blk = __builtin_amdgcn_readfirstlane(sims[s].active[v - s_pre[s]]);
+  }
+  for (; v < total; v += stride) {
+    const SimDev& S = sims[s];
+    // the next block's sim and index, loaded while this one is summed
+    const int vn = v + stride;
+    int sn = s, bn = 0;
+    if (vn < total) {
+      sn = __builtin_amdgcn_readfirstlane(find_sim(s_pre, nsims, vn));
+      bn = __builtin_amdgcn_readfirstlane(sims[sn].active[vn - s_pre[sn]]);
+    }
+    const int nbs = S.nbs, n = S.grid_n;
+    const int bx = blk / (nbs * nbs), by = (blk / nbs) % nbs, bz = blk % nbs;
+    const int ox = 4 * bx, oy = 4 * by, oz = 4 * bz;
+    const int ep = *S.epoch;
+    const float mp = S.mp;
+    // source bins d = 0..7 (the block's own bin and its lower neighbours) on lanes 0..7
+    int from = 0, cnt = 0;
+    if (lane < 8) {
+      const int sx = bx - (lane >> 2), sy = by - ((lane >> 1) & 1), sz = bz - (lane & 1);
+      if (sx >= 0 && sy >= 0 && sz >= 0) {
+        const GlobalI meta = (GlobalI)S.bin_meta + 4 * ((sx * nbs + sy) * nbs + sz);
+        if (meta[0] == ep) {
+          from = meta[1];
+          cnt = meta[2];
+        }
+      }
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int k = 1; k < 8; k <<= 1) {
+      const int t = __shfl_up(incl, k);
+      if (lane >= k) incl += t;
+    }
+    const int excl = incl - cnt;
+    int seg_lo[8], seg_off[8];   // wave-uniform: first concatenated index, slot - index
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      seg_lo[d] = __builtin_amdgcn_readlane(excl, d);
+      seg_off[d] = __builtin_amdgcn_readlane(from, d) - seg_lo[d];
+    }
+    const int total_rec = __builtin_amdgcn_readlane(incl, 7);
+    const GlobalF recs = (GlobalF)S.rec;
+    const ConstRec crec = (ConstRec)S.rec;
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+    for (int c0 = 0; c0 < total_rec; c0 += 64) {
+      // lane j tests record c0 + j: does its stencil reach the block?
+      const int g = min(c0 + lane, total_rec - 1);
+      int off = seg_off[0];
+#pragma unroll
+      for (int d = 1; d < 8; ++d)
+        if (g >= seg_lo[d]) off = seg_off[d];
+      const int slot = off + g;
+      const int pb = __float_as_int(recs[(int64_t)slot * kRec + 21]);
+      const bool keep = c0 + lane < total_rec && (pb >> 20) + 2 >= ox && ((pb >> 10) & 1023) + 2 >= oy &&
+                        (pb & 1023) + 2 >= oz;
+      // the kept records in lane order, kGsBatch at a time, read through scalar loads (their
+      // loads in flight together; nothing in this kernel writes the records)
+      uint64_t ball = __ballot(keep);
+      // contribution of one record to the lane's node, or zero (branch-free, so that all
+      // the batch's loads are issued before the first use)
+      auto add = [&](const float (&rr)[22], bool use) {
+        const int pbj = __float_as_int(rr[21]);
+        const int di = lx - ((pbj >> 20) - ox), dj = ly - (((pbj >> 10) & 1023) - oy), dk = lz - ((pbj & 1023) - oz);
+        const bool in = use && (unsigned)di <= 2u && (unsigned)dj <= 2u && (unsigned)dk <= 2u;
+        const float a = (float)di, b = (float)dj, c = (float)dk;
+        // q = rr[0..2], dx A = rr[3..11], weight polynomials rr[12..20]
+        const float wp = (rr[12] + a * (rr[13] + rr[14] * a)) * (rr[15] + b * (rr[16] + rr[17] * b)) *
+                         (rr[18] + c * (rr[19] + rr[20] * c));
+        const float w = in ? wp : 0.f;
+        acc0 += w * mp;
+        acc1 += w * (rr[0] + rr[3] * a + rr[4] * b + rr[5] * c);
+        acc2 += w * (rr[1] + rr[6] * a + rr[7] * b + rr[8] * c);
+        acc3 += w * (rr[2] + rr[9] * a + rr[10] * b + rr[11] * c);
+      };
+      while (ball) {
+        int sl[kGsBatch];
+        bool use[kGsBatch];
+#pragma unroll
+        for (int t = 0; t < kGsBatch; ++t) {
+          use[t] = ball != 0;
+          sl[t] = use[t] ? __builtin_amdgcn_readlane(slot, __builtin_ctzll(ball)) : sl[0];
+          if (use[t]) ball &= ball - 1;
+        }
+        float rr[kGsBatch][22];
+#pragma unroll
+        for (int t = 0; t < kGsBatch; ++t) {
+          const ConstRec q = crec + (int64_t)sl[t] * kRec;
+#pragma unroll
+          for (int i = 0; i < 22; ++i) rr[t][i] = q[i];
+        }
+#pragma unroll
+        for (int t = 0; t < kGsBatch; ++t) add(rr[t], use[t]);
+      }
+    }
+    const int ni = ox + lx, nj = oy + ly, nk = oz + lz;
+    if (ni < n && nj < n && nk < n) {
+      const double t_new = (double)(*S.step + 1) * S.dt_d;
+      const float pm[3] = {acc1, acc2, acc3};
+      float vel[3];
+      node_velocity(S, acc0, pm, ni, nj, nk, t_new, vel);
+      S.grid[((int64_t)ni * n + nj) * n + nk] = make_float4(vel[0], vel[1], vel[2], acc0);
+    }
+    s = sn;
+    blk = bn;
   }
 }
 
@@ -1024,15 +1275,17 @@ hipError_t launch_closure(const SimDev* sim, int n_samp, int64_t n_part, FieldJo
 }
 
 hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
-                      int32_t* claims, int grid_particles, hipStream_t s) {
+                      int32_t* claims, int grid_particles, bool batch, hipStream_t s) {
   if (grid_particles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bin_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int, claims);
+  hipLaunchKernelGGL(bin_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int, claims,
+                     batch ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int grid_sims,
                                 const BlockWork* work_int, const int32_t* n_work_int, int grid_particles,
-                                int grid_blocks, bool dense, int max_grid_n, bool place, hipStream_t s) {
+                                int grid_blocks, bool dense, int max_grid_n, bool place, bool batch,
+                                hipStream_t s) {
   constexpr int alloc_lds = kMaxBins * 4;
   static bool attr = false;
   if (!attr) {
@@ -1044,21 +1297,29 @@ hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int g
   hipLaunchKernelGGL(alloc_kernel, dim3(grid_sims), dim3(kAllocThreads), alloc_lds, s, sims, n_sims);
   if (place)
     hipLaunchKernelGGL(place_kernel, dim3(grid_particles), dim3(kMpmBlock), 0, s, sims, work_int, n_work_int);
-  hipLaunchKernelGGL(bin_sort_kernel, dim3(grid_blocks), dim3(kSortThreads), 0, s, sims, n_sims);
-  // 4^3-node blocks (one node per lane) up to 128^3 grids, 8^3 above
+  const bool full = batch && !dense;   // the records the wave-per-block gather reads
+  if (full) hipLaunchKernelGGL(bin_sort_kernel<6>, dim3(grid_blocks), dim3(kSortThreads), 0, s, sims, n_sims);
+  else hipLaunchKernelGGL(bin_sort_kernel<4>, dim3(grid_blocks), dim3(kSortThreads), 0, s, sims, n_sims);
+  // Dense sets (closure, full order) and a single sparse sim: one workgroup per node block
+  // (4^3-node blocks, one node per lane, up to 128^3 grids, 8^3 above). Batches of sparse
+  // sims: one wave per 4^3-node block over a list of every sim's blocks, with the
+  // workgroup variant for the sims on grids above 128^3.
   const bool small = max_grid_n <= 128;
   if (dense && small)
     hipLaunchKernelGGL((gather_kernel<kGatherThreadsDense, 1>), dim3(grid_blocks), dim3(kGatherThreadsDense), 0, s,
-                       sims, n_sims);
+                       sims, n_sims, 0);
   else if (dense)
     hipLaunchKernelGGL((gather_kernel<kGatherThreadsDense, kMaxNodesPerLane>), dim3(grid_blocks),
-                       dim3(kGatherThreadsDense), 0, s, sims, n_sims);
-  else if (small)
+                       dim3(kGatherThreadsDense), 0, s, sims, n_sims, 0);
+  else if (!batch && small)
     hipLaunchKernelGGL((gather_kernel<kGatherThreads, 1>), dim3(grid_blocks), dim3(kGatherThreads), 0, s, sims,
-                       n_sims);
-  else
-    hipLaunchKernelGGL((gather_kernel<kGatherThreads, kMaxNodesPerLane>), dim3(grid_blocks), dim3(kGatherThreads), 0,
-                       s, sims, n_sims);
+                       n_sims, 0);
+  else {
+    hipLaunchKernelGGL(gather_lanes_kernel, dim3(2 * grid_blocks), dim3(kGsThreads), 0, s, sims, n_sims);
+    if (!small)
+      hipLaunchKernelGGL((gather_kernel<kGatherThreads, kMaxNodesPerLane>), dim3(grid_blocks), dim3(kGatherThreads),
+                         0, s, sims, n_sims, 8);
+  }
   return hipGetLastError();
 }
 

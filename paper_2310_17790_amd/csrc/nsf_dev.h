@@ -108,13 +108,13 @@ struct SimDev {
   // particle binning for the gather-form P2G: bins of bin_edge^3 cells, nbs per axis
   int32_t bin_edge, nbs, n_bins, pad2;
   int32_t* bin_cnt;                  // [n_bins] particles per bin (zero between steps)
-  int32_t* bin_start;                // [n_bins] first record slot of each bin (this step)
-  int32_t* seg_cnt;                  // [n_bins] records of each bin (this step)
-  int32_t* bin_epoch;                // [n_bins] epoch in which bin_start / seg_cnt were set
+  int4* bin_meta;                    // [n_bins] (epoch in which it was set, first record slot,
+                                     // record count, unused) of each bin
   int32_t* epoch;                    // binning epoch, +1 every step
   int32_t* pbin;                     // [n_int] bin of each integration particle, -1 if off-grid
   int32_t* prank;                    // [n_int] slot of the particle inside its bin
   float* rec;                        // [n_int][16] P2G records, each bin contiguous
+  float* rec_p;                      // [n_int][16] P2G records in particle order (binning)
   int32_t* sorted;                   // [n_int] particle indices, each bin contiguous
   int32_t* active;                   // [n_bins] node blocks that receive mass this step
   int32_t* nonempty;                 // [n_bins] bins holding particles this step
@@ -169,19 +169,22 @@ bool fields_team_jacobian(int width, bool bf16);
 // for pipelined decodes, snapshots z_n), then allocate and place (per sim), sort and write
 // records (per non-empty bin), gather + grid update (per active node block).
 hipError_t launch_bin(const SimDev* sims, const BlockWork* work_int, const int32_t* n_work_int,
-                      int32_t* claims, int grid_particles, hipStream_t s);
+                      int32_t* claims, int grid_particles, bool batch, hipStream_t s);
 // dense: the integration particles fill their cells (closure sims): wider gather
 // workgroups. max_grid_n bounds grid_n of every sim the launch can see; place: some sim
-// may have more than kAllocByParticles integration particles.
+// may have more than kAllocByParticles integration particles; batch: the launch may serve
+// more than one sim (a batch plan).
 hipError_t launch_p2g_after_bin(const SimDev* sims, const int32_t* n_sims, int grid_sims,
                                 const BlockWork* work_int, const int32_t* n_work_int, int grid_particles,
-                                int grid_blocks, bool dense, int max_grid_n, bool place, hipStream_t s);
+                                int grid_blocks, bool dense, int max_grid_n, bool place, bool batch,
+                                hipStream_t s);
 // G2P at the sample particles fused with the first Gauss-Newton reduction: work items are
 // Gauss-Newton chunks (kGnChunk sample particles). r_cap (<= kMaxR) bounds the latent size
 // of every sim in the launch and sizes the chunk's LDS.
 hipError_t launch_g2p_gn(const SimDev* sims, const BlockWork* work_gn, const int32_t* n_work_gn,
                          int r_cap, int grid, hipStream_t s);
 constexpr int kSegMax = 2048;  // bin segments up to this size are summed in index order
+constexpr int kMaxBatchSims = 1024;  // sims one batched launch serves
 // Gauss-Newton: chunk reduction of iteration iter >= 1, and the per-sim solve of any iteration.
 hipError_t launch_gn_partial(const SimDev* sims, const BlockWork* work, const int32_t* n_work,
                              int iter, int r_cap, int grid, hipStream_t s);

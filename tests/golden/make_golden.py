@@ -4,7 +4,7 @@ Calls only the FP64 oracle and the seeded input generators. For the cake-scale w
 (200,000 particles in the slab, 8,192 integration = sample particles resampled per step,
 width-128 fields from seed 0, 128^3 grid, dt = 5e-5, knife, 2 Gauss-Newton iterations)
 at r = 6 and r = 24 it stores the latent after every step, and the decoded positions and
-the Kirchhoff stress (Voigt) of 2,048 fixed particles after steps 10, 50 and 100.
+the Kirchhoff stress (Voigt) of 2,048 fixed particles after steps 10, 50, 75 and 100.
 
 Usage: python tests/golden/make_golden.py [r ...]
 """
@@ -23,7 +23,7 @@ from oracle.step import OracleSim  # noqa: E402
 
 STEPS = 100
 SAMPLE_SEED, N_SAMPLED = 123, 2048
-CHECKPOINTS = (10, 50, 100)
+CHECKPOINTS = (10, 50, 75, 100)
 
 
 def golden_path(r: int) -> str:

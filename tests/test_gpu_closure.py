@@ -87,6 +87,48 @@ def test_closure_trajectory_with_shrinking_samples(precision):
     sim.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_closure_width128_cake(precision):
+    """The bench's closure workload at width 128: the 200,000-particle cake slab, S = 700
+    clustered samples cut to 400 after step 2, 128^3 grid. This runs the width-128 kernel
+    forms the smaller test does not reach: the FP32 team Jacobian groups over the fixed S,
+    the device-written job lengths of the field tables, and the 512-thread gathers over the
+    closure's full bins. The list is compared entry for entry after every step, the
+    trajectory at the position gates and delta_u <= 1e-4 (FP32; the stage tests' FP32
+    field error, ~1e-6 of |u|, amplified by the inversion) or 5e-2 (BF16, ten times one
+    BF16 evaluation of u)."""
+    w = synth.cake_closure(seed=0, r=6, width=128, n=200_000, n_sample=700, steps=4)
+    print(f"\n[case] closure width 128 cake {precision}", flush=True)
+    s = torch.cuda.Stream()
+    sim = Sim(w, precision=precision, stream=s)
+    o = OracleSim(w)
+    sim.refresh(stream=s)
+    s.synchronize()
+    n_s = 700
+    gate_x, gate_u = (1e-5, 1e-4) if precision == "fp32" else (1e-4, 5e-2)
+    for k in range(4):
+        np.testing.assert_array_equal(sim.integration_list(), _expected_list(sim, w, n_s))
+        if k == 2:
+            n_s = 400
+            sim.set_sample_count(n_s, stream=s)
+            o.set_sample_count(n_s)
+        sim.step(1, stream=s)
+        o.step(1)
+        s.synchronize()
+        xg = _soa(sim.buffer(A.NSF_BUF_XDEC)).reshape(3, -1).T
+        xo = o.decode()
+        d = relative_error(xg, xo)
+        du = relative_error(xg - o.X, xo - o.X)
+        zg, _, st = sim.latent(stream=s)
+        print(f"step {k + 1}: delta_x={d:.2e} delta_u={du:.2e} dz={np.abs(zg - o.z).max():.2e} "
+              f"|N|={len(sim.integration_list())}", flush=True)
+        assert st == k + 1
+        assert d <= gate_x and du <= gate_u
+    np.testing.assert_array_equal(sim.integration_list(), _expected_list(sim, w, n_s))
+    assert sim.flags(stream=s) == (0, 0)
+    sim.close()
+
+
 def test_closure_capacity_truncates_and_flags():
     """A capacity below the closure keeps its first entries, sets the live length to the
     capacity and raises the CAPACITY flag (NSF_ECAPACITY from the status call)."""
