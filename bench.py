@@ -60,9 +60,9 @@ DECODE_COUNTERS = {"fields_hip_sha256": "14d3fce45c7c292a43a0f7892e8cafc6436ad71
 # per dispatch, summed over the stage's kernels and averaged over the timed calls), scaled
 # like the decode's. Valid only for the kernel source they were taken on (SHA-256 of
 # csrc/mpm.hip).
-MPM_COUNTERS = {"mpm_hip_sha256": None,
-                "single": {"fetch_kib": None, "write_kib": None},
-                "served": {"fetch_kib": None, "write_kib": None},
+MPM_COUNTERS = {"mpm_hip_sha256": "3c88cac80e23e2a78a7010adbee31b92a110e7559e0fc83df4283342565fadd2",
+                "single": {"fetch_kib": 9663.4, "write_kib": 3625.2},
+                "served": {"fetch_kib": 792037.4, "write_kib": 340451.7},
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
