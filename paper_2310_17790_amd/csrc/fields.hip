@@ -139,6 +139,7 @@ __device__ __forceinline__ void init16(f32x4 (&acc)[T][W / 16], const float* bia
 // small ring; scheduling barriers keep the compiler from sinking the reads back next to
 // their uses or hoisting more of them (which only costs registers).
 constexpr int kPrefetch = 4;
+constexpr int kPrefetchBf16Primal = 8;
 
 // One FP32 hidden layer from LDS: A is [W/16 output blocks][W/8 K-step pairs][64 lanes]
 // f32x2 (K-steps 2 hs, 2 hs + 1; lane-contiguous, so the reads are free of bank
@@ -172,6 +173,9 @@ __device__ __forceinline__ void hidden16(f32x4 (&acc)[T][W / 16], const float (&
 template <int W, int T>
 __device__ __forceinline__ void hidden16_bf16(f32x4 (&acc)[T][W / 16], const bf16x8 (&Hb)[T][W / 32],
                                               const bf16x8* A, int lane, int nt) {
+  // a primal tile has registers for a deeper ring: its products are 16 cycles apart, so
+  // four steps ahead is shorter than an LDS read's latency
+  constexpr int kPrefetch = T == 1 ? kPrefetchBf16Primal : nsf::kPrefetch;
   constexpr int MB = W / 16, S = W / 32, N = S * MB, RING = kPrefetch + 1;
   // step i: K-step s = i / MB of output block mb = i % MB
   auto at = [&](int i) { return A[((i % MB) * S + i / MB) * 64 + lane]; };
@@ -387,9 +391,10 @@ __device__ __forceinline__ void run_group16(const FieldJob& jb, int p0, int t0, 
   const int r = jb.r;
   const bool jvp = jb.jvp != 0;
   f32x4 acc[T][MB];
-  const float* prm = reinterpret_cast<const float*>(lds + 2 * LB);   // PARAMS_LDS only
+  // PARAMS_LDS only: after the two streamed layer buffers, or after the four resident layers
+  const float* prm = reinterpret_cast<const float*>(lds + (RES ? 4 : 2) * LB);
   if constexpr (PARAMS_LDS) {
-    static_assert(NT == 0 && !BF && !RES, "LDS parameters serve the FP32 primal");
+    static_assert(NT == 0 && BF == RES, "LDS parameters serve the FP32 primal and the resident BF16 decode");
     layer1_16_lds<W>(jb, tp, lane, acc, prm);
   } else {
     layer1_16<W, T, NT>(jb, tp, t0, lane, acc);
@@ -956,6 +961,20 @@ __device__ __forceinline__ int dense_tile(int base, int wave, int G, int b) {
 // One job over n points (FP32 decode), weights streamed, persistent workgroups. PL: the
 // job's small parameters are copied to LDS once (ParamsLds; a job with one latent for all
 // points), else read from global memory (per-point latents of the training forward).
+// Copy one weight set's small parameters into LDS (ParamsLds layout), every thread of the
+// workgroup taking part; the caller publishes them with a barrier.
+template <int W, int WPG>
+__device__ __forceinline__ void copy_params(const FieldJob& job, float* prm) {
+  const int K1q = (job.r + 7) >> 2, n1 = (W / 16) * K1q * 64;
+  for (int i = threadIdx.x; i < 4 * W; i += 64 * WPG) prm[ParamsLds<W>::kBias + i] = job.w.bhq[i];
+  for (int i = threadIdx.x; i < job.d * W; i += 64 * WPG) prm[ParamsLds<W>::kOut + i] = job.w.w6q[i];
+  for (int i = threadIdx.x; i < n1; i += 64 * WPG) prm[ParamsLds<W>::kW1 + i] = job.w.w1q[i];
+  if (threadIdx.x < 64) {
+    const int k = threadIdx.x;
+    prm[ParamsLds<W>::kZ + k] = (k >= 3 && k < 3 + job.r) ? (float)job.z[k - 3] : (k == 3 + job.r ? 1.f : 0.f);
+  }
+}
+
 template <int W, int WPG, bool PL>
 __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, int n_tiles) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -967,16 +986,8 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, in
   dma_layer<W, false, WPG>(job.w, 0, lds, wave, lane);
   // the weight set's small parameters, once, after the two layer buffers (the first
   // tile's layer 1 reads them before any layer barrier: published by their own)
-  float* prm = reinterpret_cast<float*>(lds + 2 * HiddenLayer<W, false>::kBytes);
   if constexpr (PL) {
-    const int K1q = (job.r + 7) >> 2, n1 = (W / 16) * K1q * 64;
-    for (int i = threadIdx.x; i < 4 * W; i += 64 * WPG) prm[ParamsLds<W>::kBias + i] = job.w.bhq[i];
-    for (int i = threadIdx.x; i < job.d * W; i += 64 * WPG) prm[ParamsLds<W>::kOut + i] = job.w.w6q[i];
-    for (int i = threadIdx.x; i < n1; i += 64 * WPG) prm[ParamsLds<W>::kW1 + i] = job.w.w1q[i];
-    if (threadIdx.x < 64) {
-      const int k = threadIdx.x;
-      prm[ParamsLds<W>::kZ + k] = (k >= 3 && k < 3 + job.r) ? (float)job.z[k - 3] : (k == 3 + job.r ? 1.f : 0.f);
-    }
+    copy_params<W, WPG>(job, reinterpret_cast<float*>(lds + 2 * HiddenLayer<W, false>::kBytes));
     lds_barrier();
   }
 #pragma unroll 1
@@ -991,7 +1002,7 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_kernel(FieldJob job, in
 
 // One job over n points (BF16 decode), weights resident: every workgroup loads the four
 // hidden layers once, then each wave runs its tiles independently.
-template <int W, int WPG>
+template <int W, int WPG, bool PL>
 __global__ __launch_bounds__(64 * WPG) void fields_dense_res_kernel(FieldJob job, int n_tiles) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int lane = threadIdx.x & 63;
@@ -1000,6 +1011,9 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_res_kernel(FieldJob job
   const int G = gridDim.x, b = blockIdx.x;
   if (2 * b >= n_tiles) return;
   dma_all_layers<W, true, WPG>(job.w, lds, wave, lane);
+  // the small parameters after the four layers (layer 1 and the output layer then read
+  // LDS instead of global memory in every tile)
+  if constexpr (PL) copy_params<W, WPG>(job, reinterpret_cast<float*>(lds + 4 * HiddenLayer<W, true>::kBytes));
   wait_dma_and_sync();
   auto none = []() -> const FieldPack* { return nullptr; };
 #pragma unroll 1
@@ -1009,7 +1023,7 @@ __global__ __launch_bounds__(64 * WPG) void fields_dense_res_kernel(FieldJob job
     // keep the weight reads inside the tile: the LDS contents never change, and hoisting
     // them out of the loop would only exhaust registers
     __asm__ volatile("" ::: "memory");
-    run_group16<W, 0, true, WPG, true>(job, t * kTile16, 0, none, lds, wave, lane);
+    run_group16<W, 0, true, WPG, true, PL>(job, t * kTile16, 0, none, lds, wave, lane);
   }
 }
 
@@ -1075,18 +1089,26 @@ hipError_t launch_dense(const FieldJob& job, int n_tiles, int cus, hipStream_t s
   return pl ? launch_dense_pl<W, WPG, true>(job, n_tiles, cus, s) : launch_dense_pl<W, WPG, false>(job, n_tiles, cus, s);
 }
 
-// BF16: all four hidden layers resident (4 W^2 x 2 B = 128 KB at width 128).
-template <int W, int WPG>
-hipError_t launch_dense_res(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
-  constexpr int lds = 4 * HiddenLayer<W, true>::kBytes;
+// BF16: all four hidden layers resident (4 W^2 x 2 B = 128 KB at width 128), and with PL
+// the weight set's small parameters after them (25 KB at width 128).
+template <int W, int WPG, bool PL>
+hipError_t launch_dense_res_pl(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
+  constexpr int lds = 4 * HiddenLayer<W, true>::kBytes + (PL ? ParamsLds<W>::kFloats * 4 : 0);
   static_assert(lds <= 160 * 1024, "resident weights must fit in LDS");
-  auto k = fields_dense_res_kernel<W, WPG>;
+  auto k = fields_dense_res_kernel<W, WPG, PL>;
   static int per_cu = 0;
   int grid = 0;
   const hipError_t e = decode_grid(k, WPG, lds, cus, &per_cu, &grid);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WPG), lds, s, job, n_tiles);
   return hipGetLastError();
+}
+
+template <int W, int WPG>
+hipError_t launch_dense_res(const FieldJob& job, int n_tiles, int cus, hipStream_t s) {
+  const bool pl = job.zrows == nullptr && job.jvp == 0 && job.r <= kMaxR && job.d <= 9;
+  return pl ? launch_dense_res_pl<W, WPG, true>(job, n_tiles, cus, s)
+            : launch_dense_res_pl<W, WPG, false>(job, n_tiles, cus, s);
 }
 
 template <int W>
