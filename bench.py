@@ -16,6 +16,10 @@ error against the FP64 oracle, and the oracle itself timed on the host cores.
 The headline value is the plain FP32 single instance. The same line carries, under
 "legs", the forms measured against it on the same GPU:
   bf16_r6, bf16_r24: the same workload with BF16 hidden layers and Jacobian, r = 6 and 24;
+  mixed_r6: BF16 hidden layers for the stress and affine fields and the decode, the
+    deformation field FP32 where the inversion reads it (mixed_r24 on request: over the
+    bench's ~110 steps its FP32 Jacobian, like the FP32 r = 24 run's, reaches the chaotic
+    part of the random-weight trajectory and stops with NSF_ESINGULAR);
   served_bf16: the continuous-batching server over a Poisson stream of requests (256 at
     200/s, particle counts log-uniform in 5k-200k, 4% integration particles, r uniform in
     {6, 12, 24}, 64^3 or 128^3 grids, independent weights, 1,000 steps each, decode every
@@ -44,7 +48,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "latent steps/s & decoded pts/s vs plain FP32; p99 step latency at 1e-4 err"
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # dense MFMA peaks of MI355X
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "mixed": 2500.0}   # dense MFMA peaks of MI355X
+# (the mixed map's decode runs on BF16 MFMA)
 
 # HBM bytes of one FP32 decode launch (fields_dense_kernel, width 128, 200,000 points) from
 # two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled
@@ -379,7 +384,7 @@ def main() -> int:
     ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="bf16_r6,bf16_r24,fp32_pipelined,bf16_pipelined,served_bf16,p2g_served,"
+    ap.add_argument("--legs", default="bf16_r6,bf16_r24,mixed_r6,fp32_pipelined,bf16_pipelined,served_bf16,p2g_served,"
                                       "fit_bf16,closure_fp32,closure_bf16,full_order_fp32",
                     help="comma-separated extra legs ('' for none)")
     ap.add_argument("--served-requests", type=int, default=256)
@@ -435,9 +440,9 @@ def main() -> int:
             leg["vs_fp32_single"] = {"steps_per_s": leg["steps_per_s"] / main_leg["steps_per_s"],
                                      "decoded_pts_per_s": leg["decoded_pts_per_s"] / main_leg["decoded_pts_per_s"]}
             legs[name] = leg
-        elif name.startswith("bf16_r"):
-            lr = int(name[len("bf16_r"):])
-            leg, _ = single_leg("bf16", lr, K, W, stream, torch, synth, A, Sim)
+        elif name.startswith("bf16_r") or name.startswith("mixed_r"):
+            prec, lr = name.split("_r")
+            leg, _ = single_leg(prec, int(lr), K, W, stream, torch, synth, A, Sim)
             leg["vs_fp32_single"] = {"steps_per_s": leg["steps_per_s"] / main_leg["steps_per_s"],
                                      "decoded_pts_per_s": leg["decoded_pts_per_s"] / main_leg["decoded_pts_per_s"]}
             legs[name] = leg

@@ -44,7 +44,13 @@ typedef enum {
   NSF_ECAPACITY = -8     /* sticky: a closure integration set outgrew n_integration       */
 } nsf_status;
 
-typedef enum { NSF_FP32 = 0, NSF_BF16 = 1 } nsf_precision;
+/* NSF_FP32: every field layer on FP32 MFMA. NSF_BF16: hidden layers of every field on BF16
+ * MFMA with FP32 accumulation (layer 1 and the output layer FP32). NSF_BF16_MIXED: BF16
+ * hidden layers for the stress and affine fields (h, l) and the decode of all particles;
+ * the deformation field where the inversion reads it (inference at the integration
+ * particles, its latent Jacobian at the samples, the Gauss-Newton iterate) in FP32, with
+ * the step's exact differences (sim steps only; the MLP calls take FP32 or BF16). */
+typedef enum { NSF_FP32 = 0, NSF_BF16 = 1, NSF_BF16_MIXED = 2 } nsf_precision;
 
 /* sticky device status bits, see nsf_status_flags */
 enum { NSF_FLAG_DOMAIN = 1u, NSF_FLAG_NONFINITE = 2u, NSF_FLAG_SINGULAR = 4u,
@@ -95,7 +101,7 @@ typedef struct {
   int32_t r;                   /* latent dimension, 1 <= r <= 32                          */
   int32_t width;               /* hidden width: 64 or 128                                 */
   int32_t n_hidden;            /* must be 5                                               */
-  nsf_precision precision;     /* FP32, or BF16 hidden layers with FP32 accumulation      */
+  nsf_precision precision;     /* FP32, BF16 or BF16_MIXED (see nsf_precision)            */
   const float *weights[3];     /* host, see above                                         */
   double out_scale[3][9];
   double out_shift[3][9];

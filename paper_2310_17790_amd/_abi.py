@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libnsf.so")
 
 NSF_OK, NSF_EINVAL, NSF_ENOMEM, NSF_EHIP, NSF_ENODEV = 0, -1, -2, -3, -4
 NSF_EDOMAIN, NSF_ESINGULAR, NSF_ENONFINITE, NSF_ECAPACITY = -5, -6, -7, -8
-NSF_FP32, NSF_BF16 = 0, 1
+NSF_FP32, NSF_BF16, NSF_BF16_MIXED = 0, 1, 2
 NSF_FLAG_DOMAIN, NSF_FLAG_NONFINITE, NSF_FLAG_SINGULAR, NSF_FLAG_CAPACITY = 1, 2, 4, 8
 NSF_INTEGRATION_PLAN, NSF_INTEGRATION_CLOSURE = 0, 1
 NSF_FIELD_G, NSF_FIELD_H, NSF_FIELD_L = 0, 1, 2

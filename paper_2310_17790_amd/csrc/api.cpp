@@ -140,7 +140,8 @@ nsf_status validate(const nsf_sim_desc* d) {
   if (d->r < 1 || d->r > kMaxR) return fail(NSF_EINVAL, "r = %d outside 1..%d", d->r, kMaxR);
   if (d->width != 64 && d->width != 128) return fail(NSF_EINVAL, "width = %d (64 or 128)", d->width);
   if (d->n_hidden != 5) return fail(NSF_EINVAL, "n_hidden = %d (the fields have 5 hidden layers)", d->n_hidden);
-  if (d->precision != NSF_FP32 && d->precision != NSF_BF16) return fail(NSF_EINVAL, "unknown precision");
+  if (d->precision != NSF_FP32 && d->precision != NSF_BF16 && d->precision != NSF_BF16_MIXED)
+    return fail(NSF_EINVAL, "unknown precision");
   for (int f = 0; f < 3; ++f)
     if (!d->weights[f]) return fail(NSF_EINVAL, "weights[%d] is NULL", f);
   if (d->n_particles < 1 || d->n_particles > (int64_t)INT32_MAX / 4)
@@ -169,6 +170,8 @@ nsf_status validate(const nsf_sim_desc* d) {
   if (d->integration != NSF_INTEGRATION_PLAN && d->integration != NSF_INTEGRATION_CLOSURE)
     return fail(NSF_EINVAL, "integration = %d (0 plan, 1 closure)", d->integration);
   const bool closure = d->integration == NSF_INTEGRATION_CLOSURE;
+  if (closure && d->precision == NSF_BF16_MIXED)
+    return fail(NSF_EINVAL, "closure integration runs in FP32 or BF16, not BF16_MIXED");
   if (closure) {
     if (d->plan_steps != 1) return fail(NSF_EINVAL, "closure integration takes one sample row (plan_steps = 1)");
     if (d->decode_every_step != 1)
@@ -223,7 +226,8 @@ struct Plan;
 struct nsf_sim {
   int device = 0;
   int r = 0, width = 0;
-  bool bf16 = false;
+  bool bf16 = false;       // deformation field where the inversion reads it (BF16 precision)
+  bool bf16_hl = false;    // stress and affine fields and the decode (BF16 and BF16_MIXED)
   int64_t n_part = 0;
   int n_int = 0, n_samp = 0, gn_iters = 2;
   int decode_mode = 0;    // decode_every_step: 0, 1 or 2 (pipelined)
@@ -254,6 +258,9 @@ struct Plan {
   int grid_cap = 256;            // largest grid_n the P2G kernels serve
   bool place = true;             // some member may exceed kAllocByParticles integration particles
   bool bf16 = false, decode = false, pipelined = false, persistent = false;
+  bool bf16_hl = false;           // precision of the h and l jobs and of the decode
+  bool mixed = false;             // bf16_hl != bf16: h and l run in a table of their own
+  int nH = 0;                     // groups of that table
   bool closure = false;           // its one member rebuilds its integration set every step
   ListJobs list_jobs{};           // closure: the jobs over the integration list
   void* dbuf = nullptr;
@@ -263,13 +270,13 @@ struct Plan {
   int32_t* d_counts = nullptr;    // [0..7] work counts, [8..15] claim counters
   SimDev* d_sims = nullptr;
   FieldJob* d_jobs = nullptr;
-  FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tD = nullptr;
+  FieldTile *d_tA = nullptr, *d_tG = nullptr, *d_tD = nullptr, *d_tH = nullptr;
   BlockWork *d_bP = nullptr, *d_bGN = nullptr;
   int nA = 0, nG = 0, nD = 0, nP = 0, nGN = 0, nsims = 0;
   int nAstep = 0, nGnext = 0;     // see build_plan (velocity job moved into the first G pass)
   int nGvel = 0;                  // velocity groups at the start of the G table
   // launch grids (fixed for persistent plans)
-  int gF = 0, gF0 = 0, gP = 0, gGN = 0, gSims = 0, gBlk = 0;
+  int gF = 0, gF0 = 0, gP = 0, gGN = 0, gSims = 0, gBlk = 0, gH = 0;
   FieldJob decode_job{};          // single-sim plans decode with the dense kernel
   // Decode runs on a side stream, concurrently with the next step's inference.
   hipStream_t side = nullptr;
@@ -304,7 +311,7 @@ std::mutex g_plans_mu;
 std::map<int, std::unique_ptr<Plan>> g_batch_plans;
 
 int batch_signature(const nsf_sim* s) {
-  return s->width * 64 + (s->bf16 ? 32 : 0) + s->gn_iters * 4 + s->decode_mode;
+  return s->width * 256 + (s->bf16 ? 32 : 0) + (s->bf16_hl ? 128 : 0) + s->gn_iters * 4 + s->decode_mode;
 }
 
 FieldJob base_job(const nsf_sim* s, int field, const double* z) {
@@ -373,6 +380,8 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   nsf_sim* s0 = P.members[0];
   P.width = s0->width;
   P.bf16 = s0->bf16;
+  P.bf16_hl = s0->bf16_hl;
+  P.mixed = P.bf16 != P.bf16_hl;
   P.gn_iters = s0->gn_iters;
   P.decode = s0->decode_mode != 0;
   P.pipelined = s0->decode_mode == 2;
@@ -390,6 +399,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   std::vector<SimDev> sims;
   std::vector<FieldJob> jobs;
   std::vector<FieldTile> tA_jac, tA_prim, tA_team, tA_vel, tG, tG_vel, tD;  // tD: decode groups
+  std::vector<FieldTile> tH;   // mixed precision: the h and l groups (BF16, primal table)
   // team Jacobian groups (half a primal group's time each) go after the primal groups
   std::vector<BlockWork> bP, bGN;
   // The FP32 velocity takes g at z_{n-1} on the step's points. Inside a step with at least
@@ -451,12 +461,14 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
       h.z = H.zh;
       h.r = s->r + s->n_mu;
     }
-    add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
+    if (P.mixed) add_prim_tiles(tH, (int)jobs.size(), N, 0);
+    else add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
     over_list((int)jobs.size());
     jobs.push_back(h);
     FieldJob l = base_job(s, NSF_FIELD_L, zc);
     l.n = N; l.out = H.C; l.ldo = N;
-    add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
+    if (P.mixed) add_prim_tiles(tH, (int)jobs.size(), N, 0);
+    else add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
     over_list((int)jobs.size());
     if (s->closure) P.list_jobs = lj;
     jobs.push_back(l);
@@ -493,19 +505,22 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.nG -= P.nGvel;
   P.nP = (int)bP.size(); P.nGN = (int)bGN.size();
   P.nsims = (int)sims.size();
+  P.nH = (int)tH.size();
   // work counts: [0] step inference, [1] G pass, [2] full inference, [3] MPM blocks,
-  // [4] first G pass, [5] Gauss-Newton chunks, [6] sims, [7] decode groups
+  // [4] first G pass, [5] Gauss-Newton chunks, [6] sims, [7] decode groups; [8..15] claim
+  // counters; [16] the h and l groups of a mixed-precision plan
   std::vector<int32_t> counts = {P.nAstep, P.nG, P.nA, P.nP, P.nGnext, P.nGN, P.nsims, P.nD,
-                                 0, 0, 0, 0, 0, 0, 0, 0};
+                                 0, 0, 0, 0, 0, 0, 0, 0, P.nH, 0, 0, 0, 0, 0, 0, 0};
   // Regions of the device buffer. A persistent plan keeps fixed region capacities (grown
   // by half when exceeded), so its captured graph stays valid while tables are rewritten.
   struct Region { const void* data; size_t bytes; };
-  constexpr int kRegions = 8;
+  constexpr int kRegions = 9;
   const Region reg[kRegions] = {
       {counts.data(), counts.size() * 4}, {sims.data(), sims.size() * sizeof(SimDev)},
       {jobs.data(), jobs.size() * sizeof(FieldJob)}, {tA.data(), tA.size() * sizeof(FieldTile)},
       {tG.data(), tG.size() * sizeof(FieldTile)}, {tD.data(), tD.size() * sizeof(FieldTile)},
-      {bP.data(), bP.size() * sizeof(BlockWork)}, {bGN.data(), bGN.size() * sizeof(BlockWork)}};
+      {bP.data(), bP.size() * sizeof(BlockWork)}, {bGN.data(), bGN.size() * sizeof(BlockWork)},
+      {tH.data(), tH.size() * sizeof(FieldTile)}};
   bool relayout = P.caps.empty();
   for (int i = 0; i < kRegions && !relayout; ++i) relayout = reg[i].bytes > P.caps[i];
   if (relayout) {
@@ -535,6 +550,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.d_tD = reinterpret_cast<FieldTile*>(b + off[5]);
   P.d_bP = reinterpret_cast<BlockWork*>(b + off[6]);
   P.d_bGN = reinterpret_cast<BlockWork*>(b + off[7]);
+  P.d_tH = reinterpret_cast<FieldTile*>(b + off[8]);
   if (P.persistent) {
     NSF_HIP(hipStreamSynchronize(stream));  // the previous upload has been consumed
     char* st = static_cast<char*>(P.staging);
@@ -558,6 +574,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   auto mn = [](int a, int b) { return a < b ? a : b; };
   P.gF = P.persistent ? fcap : mn(fcap, std::max(P.nA, P.nGnext));
   P.gF0 = P.persistent ? fcap0 : mn(fcap0, P.nD);
+  P.gH = P.persistent ? cus * fields_table_blocks_per_cu(P.width, true, 0) : mn(cus, P.nH);
   P.gP = P.persistent ? 4 * cus : P.nP;
   P.gGN = P.persistent ? 4 * cus : P.nGN;
   P.gSims = P.persistent ? cus : P.nsims;
@@ -572,7 +589,15 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
 
 // Claim counters (zeroed at the start of every launch sequence): 8 inference, 9 + k the
 // Gauss-Newton iterate pass k, 13 refresh (inference + decode), 14 decode alone.
-constexpr int kClaimA = 8, kClaimG = 9, kClaimD = 14;
+constexpr int kClaimA = 8, kClaimG = 9, kClaimD = 14, kClaimH = 15;
+
+// Mixed precision: the h and l groups of the inference, in a BF16 primal table after the
+// FP32 table of the deformation field's jobs.
+nsf_status launch_hl(Plan& P, hipStream_t s) {
+  if (!P.mixed || P.gH <= 0) return NSF_OK;
+  NSF_HIP(launch_fields_table(P.width, true, 0, P.d_jobs, P.d_tH, P.d_counts + 16, P.d_counts + kClaimH, P.gH, s));
+  return NSF_OK;
+}
 
 nsf_status launch_decode(Plan& P, hipStream_t s, bool beside);
 
@@ -594,16 +619,16 @@ nsf_status enqueue_inference(Plan& P, hipStream_t s) {
   }
   NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 2,
                               P.d_counts + kClaimA, std::min(P.gF, std::max(P.nA, 1)), s));
-  return NSF_OK;
+  return launch_hl(P, s);
 }
 
 // Decode of all particles on stream s: the dense kernel for one sim, else the primal
 // table kernel over every sim's decode groups.
 nsf_status launch_decode(Plan& P, hipStream_t s, bool beside) {
   if (P.nsims == 1 && !P.persistent)
-    NSF_HIP(launch_fields_dense(P.width, P.bf16, P.decode_job, P.decode_job.n, s, beside));
+    NSF_HIP(launch_fields_dense(P.width, P.bf16_hl, P.decode_job, P.decode_job.n, s, beside));
   else
-    NSF_HIP(launch_fields_table(P.width, P.bf16, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
+    NSF_HIP(launch_fields_table(P.width, P.bf16_hl, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
                                 P.d_counts + kClaimD, P.gF0, s));
   return NSF_OK;
 }
@@ -642,6 +667,8 @@ nsf_status enqueue_refresh_body(Plan& P, hipStream_t s, bool decode, bool in_ste
   }
   NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + (in_step ? 0 : 2),
                               P.d_counts + kClaimA, P.gF, s));
+  const nsf_status hl = launch_hl(P, s);
+  if (hl != NSF_OK) return hl;
   return decode ? launch_decode(P, s, false) : NSF_OK;
 }
 
@@ -751,7 +778,7 @@ nsf_status check_batch(nsf_sim* const* sims, int32_t n) {
     if (!sims[i]) return fail(NSF_EINVAL, "sims[%d] is NULL", i);
     if (n > 1 && sims[i]->closure)
       return fail(NSF_EINVAL, "sims[%d] uses closure integration, which steps alone", i);
-    if (sims[i]->width != sims[0]->width || sims[i]->bf16 != sims[0]->bf16 ||
+    if (sims[i]->width != sims[0]->width || sims[i]->bf16 != sims[0]->bf16 || sims[i]->bf16_hl != sims[0]->bf16_hl ||
         sims[i]->gn_iters != sims[0]->gn_iters || sims[i]->decode_mode != sims[0]->decode_mode)
       return fail(NSF_EINVAL, "sims[%d] differs in width, precision, gn_iters or decode mode", i);
     for (int j = 0; j < i; ++j)
@@ -837,6 +864,7 @@ nsf_status nsf_create_sim(const nsf_sim_desc* d, void* arena, size_t arena_bytes
   sim->r = d->r;
   sim->width = d->width;
   sim->bf16 = d->precision == NSF_BF16;
+  sim->bf16_hl = d->precision != NSF_FP32;
   sim->n_part = d->n_particles;
   sim->n_int = d->n_integration;
   sim->n_samp = d->n_sample;
@@ -1081,7 +1109,7 @@ nsf_status nsf_decode(nsf_sim* s, const float* X, int64_t n, float* x_out, void*
   j.mode = 1;
   j.out = x_out;
   j.ldo = n;
-  NSF_HIP(launch_fields_dense(s->width, s->bf16, j, (int)n, static_cast<hipStream_t>(stream)));
+  NSF_HIP(launch_fields_dense(s->width, s->bf16_hl, j, (int)n, static_cast<hipStream_t>(stream)));
   return NSF_OK;
 }
 

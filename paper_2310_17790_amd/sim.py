@@ -41,7 +41,10 @@ def build_desc(w, precision: str, decode_every_step: bool):
 
     d = A.nsf_sim_desc()
     d.r, d.width, d.n_hidden = int(w.r), int(w.width), 5
-    d.precision = A.NSF_BF16 if precision == "bf16" else A.NSF_FP32
+    precisions = {"fp32": A.NSF_FP32, "bf16": A.NSF_BF16, "mixed": A.NSF_BF16_MIXED}
+    if precision not in precisions:
+        raise ValueError(f"precision {precision!r}: one of {sorted(precisions)}")
+    d.precision = precisions[precision]
     for f, name in enumerate(("g", "h", "l")):
         d.weights[f] = fptr(flatten_mlp(w.fields[name]))
         for c in range(FIELD_OUT[f]):
@@ -92,7 +95,8 @@ class Sim:
     """One reduced-order simulation resident on the current GPU.
 
     ``w`` is any object with the attributes of ``synth.Workload`` (fields, X, z0, plan,
-    constants). ``precision`` is "fp32" or "bf16".
+    constants). ``precision`` is "fp32", "bf16" or "mixed" (BF16 stress and affine fields
+    and decode, FP32 deformation field for the inversion).
     """
 
     def __init__(self, w, precision: str = "fp32", decode_every_step: bool = True,

@@ -45,7 +45,7 @@ def _close(a, b, w):
     np.testing.assert_array_equal(xa, xb)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "mixed"])
 def test_batch_equals_alone(precision):
     print(f"\n[case] batch equals alone {precision}", flush=True)
     s = torch.cuda.Stream()
