@@ -225,6 +225,29 @@ def test_problem_parameter_validation():
     d.mu[1] = float("nan")
     assert A.nsf_sim_bytes(d) == 0
     d.mu[1] = 0.2
+    assert A.nsf_sim_bytes(d) > 0
     d.r, d.n_mu = 30, 3
     assert A.nsf_sim_bytes(d) == 0
     assert "n_mu" in A.nsf_last_error()
+
+
+def test_precision_validation():
+    """FP32, BF16 and BF16_MIXED are accepted and take the same arena; any other value is
+    rejected, and the mixed map does not take closure integration."""
+    from paper_2310_17790_amd.sim import build_desc
+    w = synth.small_cube(seed=0, r=6, width=64, n=256)
+    sizes = set()
+    for prec in ("fp32", "bf16", "mixed"):
+        d, keep = build_desc(w, prec, True)
+        sizes.add(A.nsf_sim_bytes(d))
+    assert len(sizes) == 1 and min(sizes) > 0
+    d.precision = 3
+    assert A.nsf_sim_bytes(d) == 0
+    assert "precision" in A.nsf_last_error()
+    wc = synth.cake_closure(seed=3, r=6, width=64, n=4000, n_sample=40, sigma=0.02, closure_cap=4000,
+                            steps=2, grid_n=64)
+    d, keep = build_desc(wc, "mixed", True)
+    assert A.nsf_sim_bytes(d) == 0
+    assert "BF16_MIXED" in A.nsf_last_error()
+    d, keep = build_desc(wc, "bf16", True)
+    assert A.nsf_sim_bytes(d) > 0
