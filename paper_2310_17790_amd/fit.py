@@ -18,11 +18,20 @@ from typing import Dict, List, Optional
 import numpy as np
 import torch
 
+from . import _abi as A
+from .fullorder import FullOrderSim
 from .train import FieldFn
 
 OUT_DIM = {"g": 3, "h": 6, "l": 9}
 # learning rates of the supplementary "Training Details", one per equal share of the run
 LR_STAGES = (1e-3, 5e-4, 2e-4, 1e-4, 5e-5)
+
+# The falling cube whose full-order run is the fitting data: density, body volume (a cube
+# of side 0.2), fixed corotated elasticity with von Mises plasticity, initial velocity
+# -2 m/s onto the ground, 64^3 grid, dt = 1e-4 (5,000 steps cover the fall, the impact and
+# the flow that follows).
+FALLING_CUBE = dict(v0=(0.0, 0.0, -2.0), rho=1000.0, body_volume=0.2 ** 3, youngs=5e4, poisson=0.3,
+                    yield_stress=2e3, grid_n=64, dt=1e-4)
 
 
 @dataclasses.dataclass
@@ -33,6 +42,34 @@ class Snapshots:
     x: np.ndarray      # (T, P, 3)
     tau: np.ndarray    # (T, P, 6)
     C: np.ndarray      # (T, P, 9)
+
+
+def falling_cube_sim(X: np.ndarray, stream=None, **overrides) -> FullOrderSim:
+    """The GPU full-order sim of the falling cube from reference positions X (n, 3)."""
+    kw = dict(FALLING_CUBE)
+    kw.update(overrides)
+    return FullOrderSim(np.ascontiguousarray(np.asarray(X, np.float32).T), stream=stream, **kw)
+
+
+def full_order_snapshots(sim: FullOrderSim, n_snapshots: int = 200, every: int = 25,
+                         stream=None) -> Snapshots:
+    """Step the full-order sim and keep a snapshot (positions, Voigt stress, affine C) after
+    every `every` steps; the snapshots stay on the device until the run ends."""
+    P = sim.n_particles
+    dev = sim.device
+    xs = torch.empty(n_snapshots, 3, P, device=dev)
+    taus = torch.empty(n_snapshots, 6, P, device=dev)
+    Cs = torch.empty(n_snapshots, 9, P, device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.stream(s):
+        for t in range(n_snapshots):
+            sim.step(every, stream=s)
+            xs[t].copy_(sim.positions())
+            taus[t].copy_(sim.buffer(A.NSF_FO_TAU).view(6, P))
+            Cs[t].copy_(sim.buffer(A.NSF_FO_C).view(9, P))
+    s.synchronize()
+    return Snapshots(X=sim.X.T.double().cpu().numpy(), x=xs.transpose(1, 2).cpu().numpy(),
+                     tau=taus.transpose(1, 2).cpu().numpy(), C=Cs.transpose(1, 2).cpu().numpy())
 
 
 def xavier_flat(r: int, width: int, d: int, gen: torch.Generator) -> torch.Tensor:
@@ -92,8 +129,10 @@ class Fitter:
         """Adam over `iters` minibatches with the staged learning rates. g also trains the
         latent table; h and l see it frozen."""
         params = [self.w[f]] + ([self.z] if f == "g" else [])
-        opt = torch.optim.Adam(params, lr=LR_STAGES[0], betas=(0.9, 0.999), eps=1e-8)
-        losses = []
+        # one fused kernel updates every parameter; the losses stay on the device until the
+        # end, so the host queues iterations ahead of the device instead of waiting on each
+        opt = torch.optim.Adam(params, lr=LR_STAGES[0], betas=(0.9, 0.999), eps=1e-8, fused=True)
+        losses = torch.empty(iters, device=self.dev)
         for it in range(iters):
             for grp in opt.param_groups:
                 grp["lr"] = LR_STAGES[min(len(LR_STAGES) - 1, it * len(LR_STAGES) // max(iters, 1))]
@@ -103,9 +142,10 @@ class Fitter:
             L = self.loss(f, t, p, z)
             L.backward()
             opt.step()
-            losses.append(float(L.detach()))
-        self.history[f] += losses
-        return losses
+            losses[it] = L.detach()
+        out = [float(v) for v in losses.cpu().numpy()]
+        self.history[f] += out
+        return out
 
     @torch.no_grad()
     def relative_error(self, f: str, snapshot: int) -> float:

@@ -67,6 +67,13 @@ def box_points(seed: int, n: int, lo: Sequence[float], hi: Sequence[float]) -> n
     return X.astype(np.float32)
 
 
+def falling_cube_points(seed: int = 0, n: int = 50_000) -> np.ndarray:
+    """The fitting workload's cube: n reference positions uniform in the cube of side 0.2
+    centred at (0.5, 0.5, 0.4), float64 (n, 3) (one U(-0.1, 0.1) draw of shape (n, 3))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-0.1, 0.1, size=(n, 3)) + np.array([0.5, 0.5, 0.4])
+
+
 def latent(seed: int, r: int, std: float) -> np.ndarray:
     """z0 ~ N(0, std^2), float64."""
     rng = np.random.Generator(np.random.PCG64(seed))
