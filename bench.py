@@ -398,6 +398,8 @@ def main() -> int:
     ap.add_argument("--legs", default="bf16_r6,bf16_r24,mixed_r6,fp32_pipelined,bf16_pipelined,served_bf16,p2g_served,"
                                       "fit_bf16,closure_fp32,closure_bf16,full_order_fp32",
                     help="comma-separated extra legs ('' for none)")
+    ap.add_argument("--fit-iters", type=int, default=6000,
+                    help="Adam iterations of the fit_bf16 leg (fewer for profiling)")
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--served-steps", type=int, default=1000)
     ap.add_argument("--served-budget", type=float, default=0.5,
@@ -458,7 +460,7 @@ def main() -> int:
                                      "decoded_pts_per_s": leg["decoded_pts_per_s"] / main_leg["decoded_pts_per_s"]}
             legs[name] = leg
         elif name == "fit_bf16":
-            legs[name] = fit_leg(6000, torch, synth)
+            legs[name] = fit_leg(args.fit_iters, torch, synth)
         elif name == "p2g_served":
             legs[name] = p2g_served_leg(args.served_requests, max(K, 20), stream, torch, synth, A)
         elif name == "full_order_fp32":

@@ -265,13 +265,15 @@ int32_t nsf_device_count(void);
  *
  * nsf_mlp_forward: out device [d][n] (SoA); saved device float32 of nsf_mlp_saved_floats
  *   (width, n) elements, receiving the five hidden pre-activations for the backward in
- *   the kernels' internal format (scaled by log2 e; NULL = inference only).
+ *   the kernels' internal format (scaled by log2 e; NULL = inference only). With NSF_BF16
+ *   they are stored rounded to BF16 and fill the first half of the buffer.
  * nsf_mlp_backward: given dout [d][n] = dLoss/dout, accumulate (+=) dW (device, same
  *   layout and size as the weights), write dz device [n][r] = dLoss/dz_rows and dX device
  *   [3][n] = dLoss/dX (SoA like X), each NULL to skip. Requires `saved` from the forward
  *   of the same weights and inputs.
  * Precision: NSF_FP32 (also used by the finite-difference check) or NSF_BF16 (hidden
- * layers on BF16 MFMA, FP32 accumulation). */
+ * layers on BF16 MFMA with FP32 accumulation, forward and backward; the backward's deltas
+ * and the saved pre-activations are BF16, dz and dX are formed in FP32). */
 typedef struct {
   int32_t r, width, d;
   nsf_precision precision;
@@ -287,6 +289,15 @@ nsf_status nsf_mlp_forward(const nsf_mlp *m, const float *X, const float *z_rows
 nsf_status nsf_mlp_backward(const nsf_mlp *m, const float *X, const float *z_rows, int64_t n,
                             const float *saved, const float *dout, float *dW, float *dz,
                             float *dX, void *workspace, size_t workspace_bytes, void *stream);
+
+/* One Adam step (Sec. 4.5 trains the fields with Adam) over n FP32 parameters on the
+ * device: m and v are the first and second moment buffers (device, n each, zero before
+ * the first step), step counts from 1. With g = grad, in PyTorch's order of operations:
+ * m = beta1 m + (1 - beta1) g; v = beta2 v + (1 - beta2) g^2;
+ * w -= (lr / (1 - beta1^step)) m / (sqrt(v) / sqrt(1 - beta2^step) + eps).
+ * NSF_EINVAL for NULL buffers, n < 1, step < 1 or betas outside [0, 1), eps <= 0. */
+nsf_status nsf_adam_step(float *w, const float *grad, float *m, float *v, int64_t n, double lr,
+                         double beta1, double beta2, double eps, int64_t step, void *stream);
 
 /* nsf_mlp_forward without a workspace argument, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that forbid

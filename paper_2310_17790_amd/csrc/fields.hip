@@ -213,11 +213,22 @@ __device__ __forceinline__ float output_dot16(const float* w6q, int o, int g, co
   return s + __shfl_xor(s, 32);
 }
 
-// Training: store the (scaled) pre-activations of one layer, point-major saved[layer][p][W].
+// Training: store the (scaled) pre-activations of one layer, point-major saved[layer][p][W],
+// as FP32 or rounded to BF16 (BF16 training).
 template <int W, int T>
 __device__ __forceinline__ void save_preact16(const FieldJob& jb, const f32x4 (&acc)[T][W / 16],
                                               int layer, int p, bool valid, int g) {
   if (jb.saved == nullptr || !valid) return;
+  if (jb.saved_bf16) {
+    __bf16* row = reinterpret_cast<__bf16*>(jb.saved) + ((int64_t)layer * jb.n + p) * W;
+#pragma unroll
+    for (int mb = 0; mb < W / 16; ++mb) {
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      const bf16x4 v = {(__bf16)acc[0][mb][0], (__bf16)acc[0][mb][1], (__bf16)acc[0][mb][2], (__bf16)acc[0][mb][3]};
+      *reinterpret_cast<bf16x4*>(row + 16 * mb + 4 * g) = v;
+    }
+    return;
+  }
   float* row = jb.saved + ((int64_t)layer * jb.n + p) * W;
 #pragma unroll
   for (int mb = 0; mb < W / 16; ++mb) *reinterpret_cast<f32x4*>(row + 16 * mb + 4 * g) = acc[0][mb];

@@ -55,6 +55,7 @@ struct FieldJob {
                              // z - z2, and write scale * (tangent output) * jvp_scale
   float jvp_scale;
   int32_t step_off;          // 1: the points of the step after the counter's (see step)
+  int32_t saved_bf16;        // training: saved holds BF16 values (else FP32)
   const float* zrows;        // training: per-point latents [n][r] instead of z (NULL in the step)
   float* saved;              // training: pre-activations of layers 1..5, [5][n][W] (or NULL)
   float* out; int64_t ldo;   // SoA [d][ldo], already offset to this job's first point

@@ -20,7 +20,7 @@ import torch
 
 from . import _abi as A
 from .fullorder import FullOrderSim
-from .train import FieldFn
+from .train import Adam, FieldFn
 
 OUT_DIM = {"g": 3, "h": 6, "l": 9}
 # learning rates of the supplementary "Training Details", one per equal share of the run
@@ -94,6 +94,7 @@ class Fitter:
         self.gen.manual_seed(seed)
         cpu_gen = torch.Generator().manual_seed(seed)
         self.X = torch.as_tensor(np.asarray(data.X, np.float32), device=dev)
+        self.XT = self.X.t().contiguous()   # (3, P): a minibatch's positions in one gather
         X64 = np.asarray(data.X, np.float64)
         targets = {"g": np.asarray(data.x, np.float64) - X64[None], "h": np.asarray(data.tau, np.float64),
                    "l": np.asarray(data.C, np.float64)}
@@ -105,7 +106,10 @@ class Fitter:
             sd = y.reshape(-1, y.shape[-1]).std(0)
             sd = np.where(sd > 0, sd, 1.0)
             self.shift[f], self.scale[f] = mu, sd
-            self.Y[f] = torch.as_tensor(((y - mu) / sd).astype(np.float32), device=dev)   # (T, P, d)
+            # structure of arrays (d, T P), pair (t, p) at column t P + p: a minibatch's targets
+            # are one gather along the columns, in the [d][n] order the kernels write
+            yn = ((y - mu) / sd).astype(np.float32).reshape(-1, y.shape[-1])
+            self.Y[f] = torch.as_tensor(np.ascontiguousarray(yn.T), device=dev)
         self.w = {f: xavier_flat(r, width, OUT_DIM[f], cpu_gen).to(dev).requires_grad_(True)
                   for f in OUT_DIM}
         self.z = torch.zeros(self.T, r, device=dev, requires_grad=True)
@@ -121,24 +125,24 @@ class Fitter:
         # index_select: its backward adds the per-pair latent gradients into the table with
         # one scatter-add (indexing's backward would sort the indices first)
         zr = torch.index_select(z, 0, t)
-        out = FieldFn.apply(torch.index_select(self.X, 0, p), zr, self.w[f], self.width, OUT_DIM[f],
-                            self.precision)
-        return ((out - self.Y[f][t, p]) ** 2).mean()
+        Xp = torch.index_select(self.XT, 1, p).t()   # (n, 3) view of the SoA rows FieldFn takes
+        out = FieldFn.apply(Xp, zr, self.w[f], self.width, OUT_DIM[f], self.precision)
+        y = torch.index_select(self.Y[f], 1, t * self.P + p)   # (d, n)
+        return ((out.t() - y) ** 2).mean()
 
     def fit(self, f: str, iters: int) -> List[float]:
         """Adam over `iters` minibatches with the staged learning rates. g also trains the
         latent table; h and l see it frozen."""
         params = [self.w[f]] + ([self.z] if f == "g" else [])
-        # one fused kernel updates every parameter; the losses stay on the device until the
-        # end, so the host queues iterations ahead of the device instead of waiting on each
-        opt = torch.optim.Adam(params, lr=LR_STAGES[0], betas=(0.9, 0.999), eps=1e-8, fused=True)
+        # the library's Adam kernel updates each parameter tensor in one launch; the losses
+        # stay on the device until the end, so the host queues iterations ahead of the device
+        opt = Adam(params, lr=LR_STAGES[0], betas=(0.9, 0.999), eps=1e-8)
         losses = torch.empty(iters, device=self.dev)
         for it in range(iters):
-            for grp in opt.param_groups:
-                grp["lr"] = LR_STAGES[min(len(LR_STAGES) - 1, it * len(LR_STAGES) // max(iters, 1))]
+            opt.lr = LR_STAGES[min(len(LR_STAGES) - 1, it * len(LR_STAGES) // max(iters, 1))]
             t, p = self._batch()
             z = self.z if f == "g" else self.z.detach()
-            opt.zero_grad(set_to_none=True)
+            opt.zero_grad()
             L = self.loss(f, t, p, z)
             L.backward()
             opt.step()
@@ -156,7 +160,7 @@ class Fitter:
         sc = torch.as_tensor(self.scale[f], device=self.dev, dtype=torch.float64)
         sh = torch.as_tensor(self.shift[f], device=self.dev, dtype=torch.float64)
         y = out.double() * sc + sh
-        ref = self.Y[f][snapshot].double() * sc + sh
+        ref = self.Y[f][:, snapshot * self.P:(snapshot + 1) * self.P].t().double() * sc + sh
         if f == "g":
             y, ref = y + self.X.double(), ref + self.X.double()
         return float(torch.sqrt(((y - ref) ** 2).sum() / (ref ** 2).sum()))

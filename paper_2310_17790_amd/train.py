@@ -66,3 +66,29 @@ class FieldFn(torch.autograd.Function):
                                    None if dX is None else dX.data_ptr(), ws.data_ptr(), ws_bytes,
                                    _stream()))
         return None if dX is None else dX.t(), dz, dW, None, None, None
+
+
+class Adam:
+    """Adam on FP32 device tensors through nsf_adam_step (PyTorch's update order, no weight
+    decay); lr may change between steps."""
+
+    def __init__(self, params, lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8):
+        self.params = list(params)
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.m = [torch.zeros_like(p) for p in self.params]
+        self.v = [torch.zeros_like(p) for p in self.params]
+        self.t = 0
+
+    def zero_grad(self) -> None:
+        for p in self.params:
+            p.grad = None
+
+    @torch.no_grad()
+    def step(self) -> None:
+        self.t += 1
+        for p, m, v in zip(self.params, self.m, self.v):
+            if p.grad is None:
+                continue
+            assert p.dtype == torch.float32 and p.is_contiguous() and p.grad.is_contiguous()
+            A.check(A.lib().nsf_adam_step(p.data_ptr(), p.grad.data_ptr(), m.data_ptr(), v.data_ptr(), p.numel(),
+                                          self.lr, self.betas[0], self.betas[1], self.eps, self.t, _stream()))
