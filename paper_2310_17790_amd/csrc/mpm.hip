@@ -289,11 +289,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 // an LDS bitmap, which is then compacted into the active-block list.
 constexpr int kAllocBatch = 8;               // particles per thread per batch of loads
 
-__device__ __forceinline__ void list_bin(const SimDev& S, int b, int c, int start, int ep, int& ne_pos,
-                                         uint32_t* mark) {
+// Record non-empty bin b (count c, first slot start) and mark its node blocks.
+__device__ __forceinline__ void describe_bin(const SimDev& S, int b, int c, int start, int ep, uint32_t* mark) {
   S.bin_cnt[b] = 0;   // counts start from zero next step
   S.bin_meta[b] = make_int4(ep, start, c, 0);
-  S.nonempty[ne_pos++] = b;
   const int nbs = S.nbs;
   const int bx = b / (nbs * nbs), by = (b / nbs) % nbs, bz = b % nbs;
   for (int d = 0; d < 8; ++d) {
@@ -304,6 +303,16 @@ __device__ __forceinline__ void list_bin(const SimDev& S, int b, int c, int star
     }
   }
 }
+
+__device__ __forceinline__ void list_bin(const SimDev& S, int b, int c, int start, int ep, int& ne_pos,
+                                         uint32_t* mark) {
+  S.nonempty[ne_pos++] = b;
+  describe_bin(S, b, c, start, ep, mark);
+}
+
+// s_start[b] packs the bin's first slot (high 16 bits) and its count (low 16 bits): both
+// are at most kAllocByParticles.
+static_assert(kAllocByParticles <= 32768, "slot and count packed in 16 bits each");
 
 __device__ __forceinline__ int alloc_by_particles(const SimDev& S, int n, uint32_t* mark, int* wave_sums,
                                                   int* s_start) {
@@ -335,24 +344,31 @@ __device__ __forceinline__ int alloc_by_particles(const SimDev& S, int n, uint32
   int used, n_ne;
   int run = block_exclusive_scan(local, wave_sums, &used);
   int ne_pos = block_exclusive_scan(ne, wave_sums, &n_ne);
-  const int ep = *S.epoch;
+  // the first particle of each bin takes the bin's slots and list position (particle order)
   for (int p0 = 0; p0 < n; p0 += round) {
     if (!one) load(p0);
 #pragma unroll
     for (int u = 0; u < kAllocBatch; ++u) {
       const int b = pb[u];
       if (b < 0 || rk[u] != 0) continue;
-      s_start[b] = run;
-      list_bin(S, b, cnt[u], run, ep, ne_pos, mark);
+      s_start[b] = (run << 16) | cnt[u];
+      S.nonempty[ne_pos++] = b;
       run += cnt[u];
     }
   }
   __syncthreads();
+  // then every thread takes part in describing the listed bins and placing the particles
+  const int ep = *S.epoch;
+  for (int i = tid; i < n_ne; i += kAllocThreads) {
+    const int b = S.nonempty[i];
+    const int v = s_start[b];
+    describe_bin(S, b, v & 0xffff, v >> 16, ep, mark);
+  }
   for (int p0 = 0; p0 < n; p0 += round) {
     if (!one) load(p0);
 #pragma unroll
     for (int u = 0; u < kAllocBatch; ++u)
-      if (pb[u] >= 0) S.sorted[s_start[pb[u]] + rk[u]] = p0 + u * kAllocThreads + tid;
+      if (pb[u] >= 0) S.sorted[(s_start[pb[u]] >> 16) + rk[u]] = p0 + u * kAllocThreads + tid;
   }
   return n_ne;
 }

@@ -67,7 +67,9 @@ def test_noalloc_forward_matches_workspace_forward(precision):
         out, saved = _forward(L, m, X, Z, n, width, d, True, stream)
         assert torch.isfinite(ref_out).all()
         assert torch.equal(out, ref_out)
-        assert torch.equal(saved, ref_saved)
+        # bit patterns: BF16 training fills the first half of the buffer and leaves the
+        # rest (NaN here) as it was
+        assert torch.equal(saved.view(torch.int32), ref_saved.view(torch.int32))
 
 
 def test_noalloc_forward_rejects_invalid_arguments():
