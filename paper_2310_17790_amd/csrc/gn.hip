@@ -15,8 +15,9 @@
 //    G2P kernel (mpm.hip), where r = -dt v is at hand; later iterations in
 //    gn_partial_kernel, after the field kernel evaluated u and J at the iterate.
 //  - gn_solve_kernel: one workgroup per simulation adds the partials in a fixed order
-//    (deterministic); its first wave factors H with a column-parallel Cholesky in LDS,
-//    solves, and updates the latent; the last iteration also shifts z_{n-1} <- z_n <- z_{n+1} and
+//    (deterministic); up to kSerialR latents one lane factors H by Cholesky and solves in
+//    its registers, above that the first wave runs a column-parallel Cholesky in LDS; then
+//    it updates the latent; the last iteration also shifts z_{n-1} <- z_n <- z_{n+1} and
 //    advances the step counter.
 // The kernel boundary publishes the partials to the solving block on whichever XCD it
 // runs (a device-scope release inside one kernel would write back every block's L2).
@@ -27,9 +28,12 @@
 namespace nsf {
 namespace {
 
-// The chunk partials are summed by the whole workgroup (more loads in flight); the solve
-// itself runs in wave 0, synchronised at wave scope.
-constexpr int kSolveThreads = 1024;
+// The chunk partials are summed by the whole workgroup, one wave per entry at a time; the
+// solve itself runs in wave 0 (in lane 0's registers up to kSerialR latents, else over the
+// wave, synchronised at wave scope).
+constexpr int kSolveThreads = 256;
+constexpr int kSolveWaves = kSolveThreads / 64;
+constexpr int kSerialR = 8;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -60,11 +64,72 @@ __device__ __forceinline__ GnLatent load_latent(const SimDev& S, int iter) {
 // column is scaled, so one wave synchronisation per column suffices. The substitutions
 // multiply by the stored reciprocal pivots idg. H, y and idg live in LDS; *bad (LDS) is
 // 2 if the summed system is not finite.
+// Small systems (r <= kSerialR): one lane factors H = L L^T column by column
+// (left-looking: L[i][j] = (H[i][j] - sum_{k<j} L[i][k] L[j][k]) / L[j][j]) and runs both
+// substitutions in its registers, with no synchronisation; the solution goes to y.
+// Returns 1 for a pivot <= 0.
+__device__ __forceinline__ int solve_serial(const double (*H)[kMaxR + 1], double* y, int r) {
+  double L[kSerialR][kSerialR];
+  double il[kSerialR], w[kSerialR];
+#pragma unroll
+  for (int i = 0; i < kSerialR; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) L[i][j] = i < r ? H[i][j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kSerialR; ++j) {
+    if (j >= r) break;
+    double d = L[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(d > 0.0)) return 1;
+    const double l = sqrt(d);
+    il[j] = 1.0 / l;
+    L[j][j] = l;
+#pragma unroll
+    for (int i = j + 1; i < kSerialR; ++i) {
+      if (i >= r) break;
+      double t = L[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+      L[i][j] = t * il[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kSerialR; ++j) {   // L w = -b
+    if (j >= r) break;
+    double t = y[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) t -= L[j][k] * w[k];
+    w[j] = t * il[j];
+  }
+#pragma unroll
+  for (int j = kSerialR - 1; j >= 0; --j) {   // L^T delta = w
+    if (j >= r) continue;
+    double t = w[j];
+#pragma unroll
+    for (int k = j + 1; k < kSerialR; ++k)
+      if (k < r) t -= L[k][j] * w[k];
+    w[j] = t * il[j];
+  }
+#pragma unroll
+  for (int j = 0; j < kSerialR; ++j)
+    if (j < r) y[j] = w[j];
+  return 0;
+}
+
 __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 1], double* y,
                                  double* idg, const int* bad, const GnLatent& zl) {
   const int r = S.r, tid = threadIdx.x;
   int b = *bad;
-  if (b == 0) {
+  if (b == 0 && r <= kSerialR) {
+    int bs = 0;
+    if (tid == 0) {
+      bs = solve_serial(H, y, r);
+      idg[0] = (double)bs;   // hand the pivot test to the wave through LDS
+    }
+    wave_sync();
+    b = idg[0] != 0.0 ? 1 : 0;
+  } else if (b == 0) {
     for (int j = 0; j < r; ++j) {
       const double d = H[j][j];
       if (!(d > 0.0)) {   // every lane read the same pivot
@@ -85,7 +150,7 @@ __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 
       wave_sync();
     }
   }
-  if (b == 0) {
+  if (b == 0 && r > kSerialR) {
     for (int j = 0; j < r; ++j) {            // L w = -b
       const double t = y[j] * idg[j];
       for (int i = j + 1 + tid; i < r; i += 64) y[i] -= H[i][j] * t;
@@ -163,7 +228,6 @@ __global__ __launch_bounds__(kGnThreads) void gn_partial_kernel(const SimDev* __
 __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* __restrict__ sims,
                                                                  const int32_t* __restrict__ n_sims,
                                                                  int iter) {
-  __shared__ double part[kSolveThreads];
   __shared__ double H[kMaxR][kMaxR + 1];
   __shared__ double y[kMaxR];
   __shared__ double idg[kMaxR];
@@ -174,49 +238,50 @@ __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* _
     if (iter >= S.gn_iters) continue;
     const int r = S.r;
     const int E = gn_entries_dev(r);
-    const int G = E >= kSolveThreads ? 1 : kSolveThreads / E;
     if (tid == 0) bad = 0;
     const GnLatent zl = load_latent(S, iter);
     __syncthreads();
-    // Sum the chunk partials: thread (e, g) adds chunks g, g + G, ... (16 loads in flight
-    // per batch, four running sums), then the G groups are added in a fixed order.
+    // Sum the chunk partials: wave w takes entries w, w + W, ... (W waves), kGnBatch at a
+    // time; lane l adds chunks l, l + 64, ... of each in order, then the lanes' sums are
+    // added by a fixed butterfly (every lane ends with the same value).
     const int nch = S.n_gn_chunks;
-    for (int e0 = 0; e0 < E; e0 += kSolveThreads / G) {
-      const int e = e0 + tid % (kSolveThreads / G);
-      const int g = tid / (kSolveThreads / G);
-      double a[4] = {0.0, 0.0, 0.0, 0.0};
-      if (e < E && g < G) {
-        const double* src = S.gn_part + e;
-        for (int c0 = g; c0 < nch; c0 += 16 * G) {
-          double v[16];
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int kGnBatch = 4;
+    for (int e0 = wv * kGnBatch; e0 < E; e0 += kSolveWaves * kGnBatch) {
+      double acc[kGnBatch];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int c = c0 + u * G;
-            v[u] = c < nch ? src[(int64_t)c * E] : 0.0;
-          }
+      for (int u = 0; u < kGnBatch; ++u) acc[u] = 0.0;
+      for (int c = lane; c < nch; c += 64) {
+        const double* src = S.gn_part + (int64_t)c * E + e0;
+        double v[kGnBatch];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) a[u & 3] += v[u];
-        }
+        for (int u = 0; u < kGnBatch; ++u) v[u] = e0 + u < E ? src[u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kGnBatch; ++u) acc[u] += v[u];
       }
-      part[tid] = (a[0] + a[1]) + (a[2] + a[3]);
-      __syncthreads();
-      if (tid < kSolveThreads / G && e0 + tid < E) {
-        double acc = 0.0;
-        for (int gg = 0; gg < G; ++gg) acc += part[gg * (kSolveThreads / G) + tid];
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1)
+#pragma unroll
+        for (int u = 0; u < kGnBatch; ++u) acc[u] += __shfl_xor(acc[u], o);
+      if (lane < kGnBatch && e0 + lane < E) {
+        double a = acc[0];
+#pragma unroll
+        for (int u = 1; u < kGnBatch; ++u)
+          if (lane == u) a = acc[u];
         int j, k;
         bool is_b;
-        gn_decode_entry(e0 + tid, r, j, k, is_b);
-        if (!isfinite(acc)) atomicOr(&bad, 2);
+        gn_decode_entry(e0 + lane, r, j, k, is_b);
+        if (!isfinite(a)) atomicOr(&bad, 2);
         if (is_b) {
-          y[j] = -acc;  // right-hand side -J^T r
+          y[j] = -a;  // right-hand side -J^T r
         } else {
-          if (j == k) acc += S.gn_damping * acc;  // Marquardt: H + lambda diag(H)
-          H[j][k] = acc;
-          H[k][j] = acc;
+          if (j == k) a += S.gn_damping * a;  // Marquardt: H + lambda diag(H)
+          H[j][k] = a;
+          H[k][j] = a;
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
     if (tid < 64) solve_and_update(S, iter, H, y, idg, &bad, zl);
     __syncthreads();
   }

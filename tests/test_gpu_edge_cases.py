@@ -124,3 +124,27 @@ def test_pipelined_decode_lags_one_step(precision):
     assert ref.flags(stream=s) == (0, 0) and pip.flags(stream=s) == (0, 0)
     ref.close()
     pip.close()
+
+
+@pytest.mark.parametrize("r", [3, 12])
+def test_singular_normal_equations_flagged(r):
+    """A latent coordinate the deformation field ignores (its layer-1 column zero) makes
+    J^T J singular with an exactly zero pivot: both solve paths (one lane's registers up to
+    eight latents, the wave's column-parallel factorisation above) raise the SINGULAR flag
+    and leave the latent where it was."""
+    w = synth.small_cube(seed=2, r=r, width=64, n=512)
+    W1, b1 = w.fields["g"][0]
+    W1 = W1.copy()
+    W1[:, 3 + 1] = 0.0
+    w.fields["g"] = [(W1, b1)] + list(w.fields["g"][1:])
+    s = torch.cuda.Stream()
+    sim = Sim(w, stream=s)
+    z0, _, _ = sim.latent(stream=s)
+    sim.step(1, stream=s)
+    s.synchronize()
+    z1, _, st = sim.latent(stream=s)
+    status, flags = sim.flags(stream=s)
+    print(f"[case] r={r}: status {status}, flags {flags}", flush=True)
+    assert flags & A.NSF_FLAG_SINGULAR
+    np.testing.assert_array_equal(z1, z0)
+    sim.close()
