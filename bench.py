@@ -52,22 +52,23 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "mixed": 2500.0}   # dense MFMA pe
 # (the mixed map's decode runs on BF16 MFMA)
 
 # HBM bytes of one FP32 decode launch (fields_dense_kernel, width 128, 200,000 points) from
-# two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled
-# by what the same counter reads for a plain 256 MiB device copy (bench.py --copy-probe:
-# FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them). Valid only for the
-# kernel source they were taken on (SHA-256 of csrc/fields.hip); null otherwise.
-DECODE_COUNTERS = {"fields_hip_sha256": "14d3fce45c7c292a43a0f7892e8cafc6436ad71e073e9bea9f7c3ab73001598a",
-                   "fetch_kib": 2349.4, "write_kib": 2343.75, "fetch_scale": 2.0, "write_scale": 1.0}
+# two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch; medians over
+# the back-to-back launches this script times), each scaled by what the same counter reads
+# for a plain 256 MiB device copy (bench.py --copy-probe: FETCH_SIZE reads half the copied
+# bytes, WRITE_SIZE all of them). Valid only for the kernel source they were taken on
+# (SHA-256 of csrc/fields.hip); null otherwise.
+DECODE_COUNTERS = {"fields_hip_sha256": "f6c4f34cf51bb31157b29ba724e6f0b0d32efb44fb9e95e65be7ba39eb6d1605",
+                   "fetch_kib": 2357.9, "write_kib": 2343.75, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 # HBM bytes of one MPM stage (bin, alloc, place, bin_sort, gather, g2p_gn summed), from two
 # rocprofv3 --pmc passes over `bench.py --legs p2g_served` (FETCH_SIZE, then WRITE_SIZE, KiB
-# per dispatch, summed over the stage's kernels and averaged over the timed calls), scaled
-# like the decode's. Valid only for the kernel source they were taken on (SHA-256 of
+# per dispatch, summed over the stage's kernels, medians over the stages), scaled like the
+# decode's. Valid only for the kernel source they were taken on (SHA-256 of
 # csrc/mpm.hip).
-MPM_COUNTERS = {"mpm_hip_sha256": "3c88cac80e23e2a78a7010adbee31b92a110e7559e0fc83df4283342565fadd2",
-                "single": {"fetch_kib": 9663.4, "write_kib": 3625.2},
-                "served": {"fetch_kib": 792037.4, "write_kib": 340451.7},
+MPM_COUNTERS = {"mpm_hip_sha256": "9d15bbc44eb3a04ba0f52297252cdee6e54daabd1a0706f7fd4b21956e4aead5",
+                "single": {"fetch_kib": 9660.0, "write_kib": 3625.2},
+                "served": {"fetch_kib": 792291.7, "write_kib": 340495.9},
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 

@@ -28,12 +28,19 @@
 namespace nsf {
 namespace {
 
-// The chunk partials are summed by the whole workgroup, one wave per entry at a time; the
-// solve itself runs in wave 0 (in lane 0's registers up to kSerialR latents, else over the
-// wave, synchronised at wave scope).
-constexpr int kSolveThreads = 256;
-constexpr int kSolveWaves = kSolveThreads / 64;
-constexpr int kSerialR = 8;
+// The chunk partials are summed by the whole workgroup (more loads in flight); the solve
+// itself runs in wave 0 (in lane 0's registers up to kSerialR latents, else over the wave,
+// synchronised at wave scope).
+constexpr int kSolveThreads = 1024;
+constexpr int kSerialR = 6;
+
+// Lane l's value of v in every lane (l wave-uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -59,11 +66,11 @@ __device__ __forceinline__ GnLatent load_latent(const SimDev& S, int iter) {
 
 // Factor and solve in one wave (lane = threadIdx.x < 64), then update the latent.
 // Cholesky H = L L^T is right-looking, one column per round: every lane reads the pivot
-// d and forms sqrt(d) and its reciprocals itself; the trailing update subtracts
-// H[i][j] H[k][j] / d below the diagonal while column j is still unscaled, then the
-// column is scaled, so one wave synchronisation per column suffices. The substitutions
-// multiply by the stored reciprocal pivots idg. H, y and idg live in LDS; *bad (LDS) is
-// 2 if the summed system is not finite.
+// d and forms sqrt(d) and its reciprocal itself; each lane scales its row's entry of the
+// column and, once the column is visible, subtracts L[i][j] L[k][j] from its row of the
+// trailing matrix (two wave synchronisations per column, no index arithmetic per entry).
+// The substitutions multiply by the stored reciprocal pivots idg. H, y and idg live in
+// LDS; *bad (LDS) is 2 if the summed system is not finite.
 // Small systems (r <= kSerialR): one lane factors H = L L^T column by column
 // (left-looking: L[i][j] = (H[i][j] - sum_{k<j} L[i][k] L[j][k]) / L[j][j]) and runs both
 // substitutions in its registers, with no synchronisation; the solution goes to y.
@@ -130,39 +137,74 @@ __device__ void solve_and_update(const SimDev& S, int iter, double (*H)[kMaxR + 
     wave_sync();
     b = idg[0] != 0.0 ? 1 : 0;
   } else if (b == 0) {
+    // lane t owns row j + 1 + t of the trailing matrix (r <= kMaxR <= 64): it scales its
+    // entry of column j, then (after the column is visible) updates its row
     for (int j = 0; j < r; ++j) {
       const double d = H[j][j];
       if (!(d > 0.0)) {   // every lane read the same pivot
         b = 1;
         break;
       }
-      const double l = sqrt(d), il = 1.0 / l, id = il * il;
-      const int m = r - j - 1;
-      for (int e = tid; e < m * m; e += 64) {
-        const int i = j + 1 + e / m, k = j + 1 + e % m;
-        if (k <= i) H[i][k] -= H[i][j] * H[k][j] * id;
+      const double l = sqrt(d), il = 1.0 / l;
+      const int i = j + 1 + tid;
+      double lij = 0.0;
+      if (i < r) {
+        lij = H[i][j] * il;
+        H[i][j] = lij;
       }
-      for (int i = j + 1 + tid; i < r; i += 64) H[i][j] *= il;
       if (tid == 0) {
         H[j][j] = l;
         idg[j] = il;
       }
       wave_sync();
+      // the row in chunks of eight: all sixteen reads issued before the writes
+      if (i < r)
+        for (int k0 = j + 1; k0 <= i; k0 += 8) {
+          double c[8], h[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = min(k0 + u, i);
+            c[u] = H[k][j];
+            h[u] = H[i][k];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (k0 + u <= i) H[i][k0 + u] = h[u] - lij * c[u];
+        }
+      wave_sync();
     }
   }
   if (b == 0 && r > kSerialR) {
+    // lane i keeps y_i in a register; round j broadcasts the finished y_j with readlane, so
+    // the substitutions need no synchronisation
+    // (each round's matrix entry and pivot are read one round ahead)
+    const int ti = min(tid, r - 1);
+    double yi = tid < r ? y[tid] : 0.0;
+    double hn = H[ti][0], gn = idg[0];
     for (int j = 0; j < r; ++j) {            // L w = -b
-      const double t = y[j] * idg[j];
-      for (int i = j + 1 + tid; i < r; i += 64) y[i] -= H[i][j] * t;
-      if (tid == 0) y[j] = t;
-      wave_sync();
+      const double hj = hn, gj = gn;
+      if (j + 1 < r) {
+        hn = H[ti][j + 1];
+        gn = idg[j + 1];
+      }
+      const double t = readlane_f64(yi, j) * gj;
+      if (tid == j) yi = t;
+      else if (tid > j && tid < r) yi -= hj * t;
     }
+    hn = H[r - 1][ti];
+    gn = idg[r - 1];
     for (int j = r - 1; j >= 0; --j) {       // L^T delta = w
-      const double t = y[j] * idg[j];
-      for (int i = tid; i < j; i += 64) y[i] -= H[j][i] * t;
-      if (tid == 0) y[j] = t;
-      wave_sync();
+      const double hj = hn, gj = gn;
+      if (j > 0) {
+        hn = H[j - 1][ti];
+        gn = idg[j - 1];
+      }
+      const double t = readlane_f64(yi, j) * gj;
+      if (tid == j) yi = t;
+      else if (tid < j) yi -= hj * t;
     }
+    if (tid < r) y[tid] = yi;
+    wave_sync();
   }
   const bool final_iter = (iter == S.gn_iters - 1);
   if (tid == 0 && b) atomicOr(S.flags, (b & 2) ? FLAG_NONFINITE : FLAG_SINGULAR);
@@ -228,6 +270,7 @@ __global__ __launch_bounds__(kGnThreads) void gn_partial_kernel(const SimDev* __
 __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* __restrict__ sims,
                                                                  const int32_t* __restrict__ n_sims,
                                                                  int iter) {
+  __shared__ double part[kSolveThreads];
   __shared__ double H[kMaxR][kMaxR + 1];
   __shared__ double y[kMaxR];
   __shared__ double idg[kMaxR];
@@ -238,50 +281,49 @@ __global__ __launch_bounds__(kSolveThreads) void gn_solve_kernel(const SimDev* _
     if (iter >= S.gn_iters) continue;
     const int r = S.r;
     const int E = gn_entries_dev(r);
+    const int G = E >= kSolveThreads ? 1 : kSolveThreads / E;
     if (tid == 0) bad = 0;
     const GnLatent zl = load_latent(S, iter);
     __syncthreads();
-    // Sum the chunk partials: wave w takes entries w, w + W, ... (W waves), kGnBatch at a
-    // time; lane l adds chunks l, l + 64, ... of each in order, then the lanes' sums are
-    // added by a fixed butterfly (every lane ends with the same value).
+    // Sum the chunk partials: thread (e, g) adds chunks g, g + G, ... (16 loads in flight
+    // per batch, four running sums), then the G groups are added in a fixed order.
     const int nch = S.n_gn_chunks;
-    const int lane = tid & 63, wv = tid >> 6;
-    constexpr int kGnBatch = 4;
-    for (int e0 = wv * kGnBatch; e0 < E; e0 += kSolveWaves * kGnBatch) {
-      double acc[kGnBatch];
+    for (int e0 = 0; e0 < E; e0 += kSolveThreads / G) {
+      const int e = e0 + tid % (kSolveThreads / G);
+      const int g = tid / (kSolveThreads / G);
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+      if (e < E && g < G) {
+        const double* src = S.gn_part + e;
+        for (int c0 = g; c0 < nch; c0 += 16 * G) {
+          double v[16];
 #pragma unroll
-      for (int u = 0; u < kGnBatch; ++u) acc[u] = 0.0;
-      for (int c = lane; c < nch; c += 64) {
-        const double* src = S.gn_part + (int64_t)c * E + e0;
-        double v[kGnBatch];
+          for (int u = 0; u < 16; ++u) {
+            const int c = c0 + u * G;
+            v[u] = c < nch ? src[(int64_t)c * E] : 0.0;
+          }
 #pragma unroll
-        for (int u = 0; u < kGnBatch; ++u) v[u] = e0 + u < E ? src[u] : 0.0;
-#pragma unroll
-        for (int u = 0; u < kGnBatch; ++u) acc[u] += v[u];
-      }
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1)
-#pragma unroll
-        for (int u = 0; u < kGnBatch; ++u) acc[u] += __shfl_xor(acc[u], o);
-      if (lane < kGnBatch && e0 + lane < E) {
-        double a = acc[0];
-#pragma unroll
-        for (int u = 1; u < kGnBatch; ++u)
-          if (lane == u) a = acc[u];
-        int j, k;
-        bool is_b;
-        gn_decode_entry(e0 + lane, r, j, k, is_b);
-        if (!isfinite(a)) atomicOr(&bad, 2);
-        if (is_b) {
-          y[j] = -a;  // right-hand side -J^T r
-        } else {
-          if (j == k) a += S.gn_damping * a;  // Marquardt: H + lambda diag(H)
-          H[j][k] = a;
-          H[k][j] = a;
+          for (int u = 0; u < 16; ++u) a[u & 3] += v[u];
         }
       }
+      part[tid] = (a[0] + a[1]) + (a[2] + a[3]);
+      __syncthreads();
+      if (tid < kSolveThreads / G && e0 + tid < E) {
+        double acc = 0.0;
+        for (int gg = 0; gg < G; ++gg) acc += part[gg * (kSolveThreads / G) + tid];
+        int j, k;
+        bool is_b;
+        gn_decode_entry(e0 + tid, r, j, k, is_b);
+        if (!isfinite(acc)) atomicOr(&bad, 2);
+        if (is_b) {
+          y[j] = -acc;  // right-hand side -J^T r
+        } else {
+          if (j == k) acc += S.gn_damping * acc;  // Marquardt: H + lambda diag(H)
+          H[j][k] = acc;
+          H[k][j] = acc;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (tid < 64) solve_and_update(S, iter, H, y, idg, &bad, zl);
     __syncthreads();
   }

@@ -130,7 +130,7 @@ def test_pipelined_decode_lags_one_step(precision):
 def test_singular_normal_equations_flagged(r):
     """A latent coordinate the deformation field ignores (its layer-1 column zero) makes
     J^T J singular with an exactly zero pivot: both solve paths (one lane's registers up to
-    eight latents, the wave's column-parallel factorisation above) raise the SINGULAR flag
+    six latents, the wave's column-parallel factorisation above) raise the SINGULAR flag
     and leave the latent where it was."""
     w = synth.small_cube(seed=2, r=r, width=64, n=512)
     W1, b1 = w.fields["g"][0]
