@@ -536,8 +536,8 @@ def main() -> int:
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": decode_traffic_bytes() if args.precision == "fp32" else None,
-                     "kernel": f"decode MLP (fields_dense_kernel, width {width}), {P} points, "
-                               f"{primal_flops(width, r, 3)} FLOP/point",
+                     "kernel": f"decode MLP ({'fields_dense_kernel' if args.precision == 'fp32' else 'fields_dense_res_kernel'}, "
+                               f"width {width}), {P} points, {primal_flops(width, r, 3)} FLOP/point",
                      "avg_ms": dec_ms},
         "p2g_roofline": {"single": main_leg["p2g"], "served": legs.get("p2g_served"),
                          "bytes_per_unit": MPM_BYTES},
