@@ -299,6 +299,18 @@ nsf_status nsf_mlp_backward(const nsf_mlp *m, const float *X, const float *z_row
 nsf_status nsf_adam_step(float *w, const float *grad, float *m, float *v, int64_t n, double lr,
                          double beta1, double beta2, double eps, int64_t step, void *stream);
 
+/* The latent rows of a minibatch whose (particle, snapshot) pairs are grouped by snapshot
+ * (the per-snapshot latents of Sec. 4.5): segment s covers rows [offsets[s], offsets[s+1])
+ * of a row-major [n][width] FP32 device array, offsets device int64 [segments + 1],
+ * non-decreasing from 0. nsf_rows_expand writes out[i][:] = table[s][:] for every row i
+ * of segment s (table [segments][width]); nsf_rows_segment_sum, its adjoint, writes
+ * out[s][:] = the sum of rows[i][:] over segment s, added in a fixed order. width 1..256;
+ * NSF_EINVAL for NULL buffers or widths out of range. */
+nsf_status nsf_rows_expand(const float *table, const int64_t *offsets, int32_t segments, int32_t width,
+                           float *out, void *stream);
+nsf_status nsf_rows_segment_sum(const float *rows, const int64_t *offsets, int32_t segments,
+                                int32_t width, float *out, void *stream);
+
 /* nsf_mlp_forward without a workspace argument, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc). It allocates nothing: the packed weights go to a library-owned device array

@@ -789,6 +789,39 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const 
   }
 }
 
+// Per-snapshot latent rows of a minibatch whose pairs are grouped by snapshot: segment s
+// covers rows [off[s], off[s + 1]). One workgroup per segment.
+__global__ __launch_bounds__(256) void rows_expand_kernel(const float* __restrict__ table,
+                                                          const int64_t* __restrict__ off, int width,
+                                                          float* __restrict__ out) {
+  const int s = blockIdx.x;
+  const int64_t a = off[s] * width, b = off[s + 1] * width;
+  const float* src = table + (int64_t)s * width;
+  for (int64_t e = a + threadIdx.x; e < b; e += blockDim.x) out[e] = src[(e - a) % width];
+}
+
+// out[s][j] = sum of rows[i][j] over segment s: thread (j, g) adds rows g, g + G, ... of
+// column j (G = 256 / width groups), then thread j adds the G sums in order.
+__global__ __launch_bounds__(256) void rows_segment_sum_kernel(const float* __restrict__ rows,
+                                                               const int64_t* __restrict__ off, int width,
+                                                               float* __restrict__ out) {
+  __shared__ float part[256];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int G = 256 / width;
+  const int j = tid % width, g = tid / width;
+  const int64_t a = off[s], b = off[s + 1];
+  float acc = 0.f;
+  if (g < G)
+    for (int64_t i = a + g; i < b; i += G) acc += rows[i * width + j];
+  part[tid] = acc;
+  __syncthreads();
+  if (tid < width) {
+    float t = 0.f;
+    for (int gg = 0; gg < G; ++gg) t += part[gg * width + tid];
+    out[(int64_t)s * width + tid] = t;
+  }
+}
+
 struct TrainWs {
   Packed pk;
   float* delta;     // [5][n][W]
@@ -929,6 +962,24 @@ nsf_status nsf_adam_step(float* w, const float* grad, float* m, float* v, int64_
   const int grid = (int)std::min<int64_t>(1024, (n + 255) / 256);
   hipLaunchKernelGGL(adam_kernel, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(stream), w, grad, m, v, n,
                      (float)beta1, (float)beta2, (float)eps, (float)(lr / bc1), (float)(1.0 / std::sqrt(bc2)));
+  return hipGetLastError() == hipSuccess ? NSF_OK : NSF_EHIP;
+}
+
+nsf_status nsf_rows_expand(const float* table, const int64_t* offsets, int32_t segments, int32_t width,
+                           float* out, void* stream) {
+  if (!table || !offsets || !out || segments < 0 || width < 1 || width > 256) return NSF_EINVAL;
+  if (segments == 0) return NSF_OK;
+  hipLaunchKernelGGL(rows_expand_kernel, dim3(segments), dim3(256), 0, static_cast<hipStream_t>(stream), table,
+                     offsets, width, out);
+  return hipGetLastError() == hipSuccess ? NSF_OK : NSF_EHIP;
+}
+
+nsf_status nsf_rows_segment_sum(const float* rows, const int64_t* offsets, int32_t segments, int32_t width,
+                                float* out, void* stream) {
+  if (!rows || !offsets || !out || segments < 0 || width < 1 || width > 256) return NSF_EINVAL;
+  if (segments == 0) return NSF_OK;
+  hipLaunchKernelGGL(rows_segment_sum_kernel, dim3(segments), dim3(256), 0, static_cast<hipStream_t>(stream), rows,
+                     offsets, width, out);
   return hipGetLastError() == hipSuccess ? NSF_OK : NSF_EHIP;
 }
 

@@ -20,7 +20,7 @@ import torch
 
 from . import _abi as A
 from .fullorder import FullOrderSim
-from .train import Adam, FieldFn
+from .train import Adam, FieldFn, RowsExpand, SquaredError
 
 OUT_DIM = {"g": 3, "h": 6, "l": 9}
 # learning rates of the supplementary "Training Details", one per equal share of the run
@@ -114,21 +114,29 @@ class Fitter:
                   for f in OUT_DIM}
         self.z = torch.zeros(self.T, r, device=dev, requires_grad=True)
         self.history: Dict[str, List[float]] = {f: [] for f in OUT_DIM}
+        # A minibatch is stratified over the snapshots: snapshot t holds counts[t] of its
+        # pairs (batch / T, the remainder spread over the first snapshots), each with a
+        # particle drawn uniformly. Every pair is uniform over (snapshot, particle) up to
+        # that remainder, and the pairs come grouped by snapshot, so a snapshot's latent is
+        # expanded to its rows and its gradient summed over them without atomics.
+        counts = np.full(self.T, batch // self.T, np.int64)
+        counts[:batch % self.T] += 1
+        self.offsets = torch.as_tensor(np.concatenate([[0], np.cumsum(counts)]), device=dev)
+        self.t_rows = torch.repeat_interleave(torch.arange(self.T, device=dev),
+                                              torch.as_tensor(counts, device=dev))
 
     def _batch(self):
-        t = torch.randint(0, self.T, (self.batch,), device=self.dev, generator=self.gen)
         p = torch.randint(0, self.P, (self.batch,), device=self.dev, generator=self.gen)
-        return t, p
+        return self.t_rows, p
 
     def loss(self, f: str, t: torch.Tensor, p: torch.Tensor, z: torch.Tensor) -> torch.Tensor:
-        """Mean squared error of field f on the normalised targets at pairs (t, p)."""
-        # index_select: its backward adds the per-pair latent gradients into the table with
-        # one scatter-add (indexing's backward would sort the indices first)
-        zr = torch.index_select(z, 0, t)
+        """Mean squared error of field f on the normalised targets at pairs (t, p), the
+        pairs grouped by snapshot as self.offsets says."""
+        zr = RowsExpand.apply(z, self.offsets, self.batch)
         Xp = torch.index_select(self.XT, 1, p).t()   # (n, 3) view of the SoA rows FieldFn takes
         out = FieldFn.apply(Xp, zr, self.w[f], self.width, OUT_DIM[f], self.precision)
         y = torch.index_select(self.Y[f], 1, t * self.P + p)   # (d, n)
-        return ((out.t() - y) ** 2).mean()
+        return SquaredError.apply(out.t(), y)
 
     def fit(self, f: str, iters: int) -> List[float]:
         """Adam over `iters` minibatches with the staged learning rates. g also trains the

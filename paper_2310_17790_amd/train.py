@@ -68,6 +68,49 @@ class FieldFn(torch.autograd.Function):
         return None if dX is None else dX.t(), dz, dW, None, None, None
 
 
+class SquaredError(torch.autograd.Function):
+    """SquaredError.apply(out_t, y) = mean((out_t - y)^2) with its gradient formed in one
+    operation (fewer launches per fitting iteration than the composed loss)."""
+
+    @staticmethod
+    def forward(ctx, out_t, y):
+        d = out_t - y
+        ctx.save_for_backward(d)
+        return torch.mean(d * d)
+
+    @staticmethod
+    def backward(ctx, g):
+        (d,) = ctx.saved_tensors
+        return d * (g * (2.0 / d.numel())), None
+
+
+class RowsExpand(torch.autograd.Function):
+    """RowsExpand.apply(table, offsets, n) -> (n, width): row i is table[s] for
+    offsets[s] <= i < offsets[s + 1] (nsf_rows_expand); the backward sums each segment's
+    gradient rows into the table's gradient (nsf_rows_segment_sum, fixed order)."""
+
+    @staticmethod
+    def forward(ctx, table, offsets, n: int):
+        segments, width = table.shape
+        assert table.dtype == torch.float32 and offsets.dtype == torch.int64 and offsets.numel() == segments + 1
+        t = table.contiguous()
+        out = torch.empty((n, width), dtype=torch.float32, device=table.device)
+        A.check(A.lib().nsf_rows_expand(t.data_ptr(), offsets.data_ptr(), segments, width, out.data_ptr(), _stream()))
+        ctx.save_for_backward(offsets)
+        ctx.shape = (segments, width)
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        (offsets,) = ctx.saved_tensors
+        segments, width = ctx.shape
+        g = gout.contiguous().float()
+        out = torch.empty((segments, width), dtype=torch.float32, device=g.device)
+        A.check(A.lib().nsf_rows_segment_sum(g.data_ptr(), offsets.data_ptr(), segments, width, out.data_ptr(),
+                                             _stream()))
+        return out, None, None
+
+
 class Adam:
     """Adam on FP32 device tensors through nsf_adam_step (PyTorch's update order, no weight
     decay); lr may change between steps."""
