@@ -66,9 +66,9 @@ DECODE_COUNTERS = {"fields_hip_sha256": "f6c4f34cf51bb31157b29ba724e6f0b0d32efb4
 # per dispatch, summed over the stage's kernels, medians over the stages), scaled like the
 # decode's. Valid only for the kernel source they were taken on (SHA-256 of
 # csrc/mpm.hip).
-MPM_COUNTERS = {"mpm_hip_sha256": "9d15bbc44eb3a04ba0f52297252cdee6e54daabd1a0706f7fd4b21956e4aead5",
-                "single": {"fetch_kib": 9660.0, "write_kib": 3625.2},
-                "served": {"fetch_kib": 792291.7, "write_kib": 340495.9},
+MPM_COUNTERS = {"mpm_hip_sha256": "7a72354e75d27841cc18a6837739137f38aef29f386ef07dff0114ca380706c1",
+                "single": {"fetch_kib": 9352.3, "write_kib": 2814.0},
+                "served": {"fetch_kib": 788347.3, "write_kib": 276947.9},
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 

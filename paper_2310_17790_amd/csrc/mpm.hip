@@ -459,21 +459,45 @@ __global__ __launch_bounds__(kMpmBlock) void place_kernel(const SimDev* __restri
 // arrival order) and copy the records into bin order.
 constexpr int kSortWaves = 4, kSortThreads = 64 * kSortWaves;
 
+// (native 4-float vectors: an array of HIP's float4 structs is not promoted to registers
+// and would live in scratch memory)
 template <int NQ>
 __device__ __forceinline__ void copy_record(const SimDev& S, int p, int slot) {
-  const float4* src = reinterpret_cast<const float4*>(S.rec_p + (int64_t)p * kRec);
-  float4* dst = reinterpret_cast<float4*>(S.rec + (int64_t)slot * kRec);
-  float4 q[NQ];
+  const f32x4* src = reinterpret_cast<const f32x4*>(S.rec_p + (int64_t)p * kRec);
+  f32x4* dst = reinterpret_cast<f32x4*>(S.rec + (int64_t)slot * kRec);
+  f32x4 q[NQ];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) q[k] = src[k];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) dst[k] = q[k];
 }
 
-// the first NQ float4 of the record: 6 for the wave layout, 4 for the workgroup layout
+// the first NQ float4 of the record: 6 for the wave layout, 4 for the workgroup layout;
+// four records per lane are loaded before any is stored, so their latencies overlap
 template <int NQ>
 __device__ __forceinline__ void copy_records(const SimDev& S, const int* idx, int start, int cnt, int lane) {
-  for (int i = lane; i < cnt; i += 64) copy_record<NQ>(S, idx[i], start + i);
+  constexpr int U = 4;
+  for (int i0 = lane; i0 < cnt; i0 += 64 * U) {
+    f32x4 q[U][NQ];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 64 * u;
+      if (i < cnt) {
+        const f32x4* src = reinterpret_cast<const f32x4*>(S.rec_p + (int64_t)idx[i] * kRec);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) q[u][k] = src[k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 64 * u;
+      if (i < cnt) {
+        f32x4* dst = reinterpret_cast<f32x4*>(S.rec + (int64_t)(start + i) * kRec);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) dst[k] = q[u][k];
+      }
+    }
+  }
 }
 
 template <int NQ>
@@ -510,13 +534,27 @@ __global__ __launch_bounds__(kSortThreads) void bin_sort_kernel(const SimDev* __
       while (p2 < cnt) p2 <<= 1;
       for (int i = lane; i < p2; i += 64) buf[i] = i < cnt ? seg[i] : 0x7fffffff;
       wave_lds_sync();
+      // each pass touches every element once, from one lane (the lane of the pair's lower
+      // index), so a lane reads its pairs eight at a time before writing any of them
       for (int kk = 2; kk <= p2; kk <<= 1)
         for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-          for (int i = lane; i < p2; i += 64) {
-            const int l = i ^ jj;
-            if (l > i) {
-              const int a = buf[i], c = buf[l];
-              if ((a > c) == ((i & kk) == 0)) { buf[i] = c; buf[l] = a; }
+          for (int i0 = lane; i0 < p2; i0 += 64 * 8) {
+            int a[8], c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int i = i0 + 64 * u, l = i ^ jj;
+              if (i < p2 && l > i) {
+                a[u] = buf[i];
+                c[u] = buf[l];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int i = i0 + 64 * u, l = i ^ jj;
+              if (i < p2 && l > i && (a[u] > c[u]) == ((i & kk) == 0)) {
+                buf[i] = c[u];
+                buf[l] = a[u];
+              }
             }
           }
           wave_lds_sync();
