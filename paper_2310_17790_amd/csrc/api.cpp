@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cassert>
+#include <initializer_list>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -275,6 +277,7 @@ struct Plan {
   int nA = 0, nG = 0, nD = 0, nP = 0, nGN = 0, nsims = 0;
   int nAstep = 0, nGnext = 0;     // see build_plan (velocity job moved into the first G pass)
   int nGvel = 0;                  // velocity groups at the start of the G table
+  int kindsA = kTableTangents, kindsG = kTableTangents;   // group kinds of the A and G tables
   // launch grids (fixed for persistent plans)
   int gF = 0, gF0 = 0, gP = 0, gGN = 0, gSims = 0, gBlk = 0, gH = 0;
   FieldJob decode_job{};          // single-sim plans decode with the dense kernel
@@ -339,9 +342,23 @@ FieldJob base_job(const nsf_sim* s, int field, const double* z) {
 // one group per output component and pays off once forward mode needs more than two.
 bool reverse_jacobian(int ntan, int tc) { return ntan > 2 * tc; }
 
-void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc, bool team = false) {
-  if (team && reverse_jacobian(ntan, tc)) {   // one workgroup per 16-point tile
-    for (int p0 = 0; p0 < n; p0 += 16) out.push_back({job, p0, 0, -2});
+// A team group's extra jobs (at most three, forward only over the group's points) as
+// FieldTile.t0: signed byte offsets from the group's job.
+int32_t team_extras(int job, std::initializer_list<int> extra) {
+  uint32_t code = 0;
+  int i = 0;
+  for (int x : extra) {
+    const int dj = x - job;
+    assert(i < 3 && dj != 0 && dj >= -128 && dj <= 127);
+    code |= (uint32_t)(uint8_t)(int8_t)dj << (8 * i++);
+  }
+  return (int32_t)code;
+}
+
+void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc, bool team = false,
+               int32_t extras = 0) {
+  if (team && reverse_jacobian(ntan, tc)) {   // one workgroup per fields_team_points() points
+    for (int p0 = 0; p0 < n; p0 += fields_team_points()) out.push_back({job, p0, extras, -2});
     return;
   }
   const int span = fields_group_points(ntan > 0 ? tc : 0);
@@ -410,6 +427,15 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   // (solo plans: the first pass's groups then start at an offset its graph keeps)
   const bool vel_in_g = !s0->bf16 && P.gn_iters >= 2 && !s0->closure && !P.persistent;
   const bool team = fields_team_jacobian(P.width, P.bf16);
+  // Team groups carry the jobs over the same points when the sample set is the integration
+  // set: the inference's h and l (and the velocity's g at z_{n-1} when it stays in the
+  // inference) with its Jacobian job, and the velocity's g at the next step's points with
+  // the first Gauss-Newton pass's. Every member must qualify, so that each table holds one
+  // kind of team group (not in persistent plans, whose members change under one graph).
+  bool fuse = team && !P.mixed && !P.closure && !P.persistent;
+  for (nsf_sim* m : P.members)
+    fuse = fuse && m->n_int == m->n_samp && reverse_jacobian(m->r, P.tc) && !m->hd.tangent_forms;
+  const bool fuse_g = fuse && vel_in_g;
   for (size_t si = 0; si < P.members.size(); ++si) {
     nsf_sim* s = P.members[si];
     const SimDev& H = s->hd;
@@ -426,8 +452,10 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     FieldJob a = base_job(s, NSF_FIELD_G, zc);
     a.n = S; a.out = H.u_n; a.ldo = N; a.jac = H.J; a.ldj = S;
     jobs.push_back(a);
-    if (team && reverse_jacobian(r, P.tc)) add_tiles(tA_team, j0, S, r, P.tc, true);
-    else add_tiles(tA_jac, j0, S, r, P.tc);
+    if (!fuse) {
+      if (team && reverse_jacobian(r, P.tc)) add_tiles(tA_team, j0, S, r, P.tc, true);
+      else add_tiles(tA_jac, j0, S, r, P.tc);
+    }
     if (N > S) {
       FieldJob b = base_job(s, NSF_FIELD_G, zc);
       b.n = N - S; b.p_off = S; b.out = H.u_n + S; b.ldo = N;
@@ -445,15 +473,17 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
       for (int p0 = 0; p0 < N; p0 += fields_group_points(P.tc))
         tA_jac.push_back({(int)jobs.size(), p0, 0, 1});
     } else {
-      add_prim_tiles(tA_vel, (int)jobs.size(), N, P.tc);
+      const int jc = (int)jobs.size();
+      if (!fuse || vel_in_g) add_prim_tiles(tA_vel, jc, N, P.tc);
       if (vel_in_g) {
         FieldJob c1 = c;
         c1.z = zc; c1.step_off = 1;
-        add_prim_tiles(tG_vel, (int)jobs.size() + 1, N, P.tc);
+        if (!fuse_g) add_prim_tiles(tG_vel, jc + 1, N, P.tc);
         jobs.push_back(c);
         c = c1;
       }
     }
+    const int jvel = (int)jobs.size();   // the velocity job the step's first G pass (or inference) runs
     jobs.push_back(c);
     FieldJob h = base_job(s, NSF_FIELD_H, zc);
     h.n = N; h.out = H.tau; h.ldo = N;
@@ -461,21 +491,27 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
       h.z = H.zh;
       h.r = s->r + s->n_mu;
     }
-    if (P.mixed) add_prim_tiles(tH, (int)jobs.size(), N, 0);
-    else add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
+    const int jh = (int)jobs.size();
+    if (P.mixed) add_prim_tiles(tH, jh, N, 0);
+    else if (!fuse) add_prim_tiles(tA_prim, jh, N, P.tc);
     over_list((int)jobs.size());
     jobs.push_back(h);
     FieldJob l = base_job(s, NSF_FIELD_L, zc);
     l.n = N; l.out = H.C; l.ldo = N;
-    if (P.mixed) add_prim_tiles(tH, (int)jobs.size(), N, 0);
-    else add_prim_tiles(tA_prim, (int)jobs.size(), N, P.tc);
+    const int jl = (int)jobs.size();
+    if (P.mixed) add_prim_tiles(tH, jl, N, 0);
+    else if (!fuse) add_prim_tiles(tA_prim, jl, N, P.tc);
     over_list((int)jobs.size());
     if (s->closure) P.list_jobs = lj;
     jobs.push_back(l);
+    if (fuse)
+      add_tiles(tA_team, j0, S, r, P.tc, true, vel_in_g ? team_extras(j0, {jh, jl}) : team_extras(j0, {jh, jl, jvel}));
     // Gauss-Newton iterate: g and its Jacobian on S
     FieldJob g = base_job(s, NSF_FIELD_G, zi);
     g.n = S; g.out = H.u_gn; g.ldo = S; g.jac = H.J2; g.ldj = S;
-    add_tiles(tG, (int)jobs.size(), S, r, P.tc, team);
+    const int jg = (int)jobs.size();
+    add_tiles(tG, jg, S, r, P.tc, team);
+    if (fuse_g) add_tiles(tG_vel, jg, S, r, P.tc, true, team_extras(jg, {jvel}));
     jobs.push_back(g);
     // decode all particles at the new latent
     // (a pipelined decode reads the snapshot of z_n the step's first kernel takes)
@@ -495,14 +531,23 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   tA.insert(tA.end(), tA_prim.begin(), tA_prim.end());
   tA.insert(tA.end(), tA_team.begin(), tA_team.end());
   tA.insert(tA.end(), tA_vel.begin(), tA_vel.end());
-  // the first Gauss-Newton pass starts with the velocity groups (longer than team groups);
-  // later passes start after them
+  // the first Gauss-Newton pass starts with the velocity groups (longer than team groups)
+  // and later passes start after them; with team groups that carry the velocity, the first
+  // pass runs those alone and later passes the plain ones
   tG.insert(tG.begin(), tG_vel.begin(), tG_vel.end());
   P.nGvel = (int)tG_vel.size();
   P.nA = (int)tA.size(); P.nG = (int)tG.size(); P.nD = (int)tD.size();
   P.nAstep = P.nA - (vel_in_g ? (int)tA_vel.size() : 0);
-  P.nGnext = P.nG;
+  P.nGnext = fuse_g ? P.nGvel : P.nG;
   P.nG -= P.nGvel;
+  auto kinds = [](const std::vector<FieldTile>& t) {
+    int k = 0;
+    for (const FieldTile& f : t) k |= f.nt == -2 ? kTableTeam : (f.nt != 0 ? kTableTangents : 0);
+    return k ? k : kTableTangents;
+  };
+  // a persistent plan's graph outlives its tables: its kernels take every kind
+  P.kindsA = P.persistent ? kTableTangents | kTableTeam : kinds(tA);
+  P.kindsG = P.persistent ? kTableTangents | kTableTeam : kinds(tG);
   P.nP = (int)bP.size(); P.nGN = (int)bGN.size();
   P.nsims = (int)sims.size();
   P.nH = (int)tH.size();
@@ -595,7 +640,7 @@ constexpr int kClaimA = 8, kClaimG = 9, kClaimD = 14, kClaimH = 15;
 // FP32 table of the deformation field's jobs.
 nsf_status launch_hl(Plan& P, hipStream_t s) {
   if (!P.mixed || P.gH <= 0) return NSF_OK;
-  NSF_HIP(launch_fields_table(P.width, true, 0, P.d_jobs, P.d_tH, P.d_counts + 16, P.d_counts + kClaimH, P.gH, s));
+  NSF_HIP(launch_fields_table(P.width, true, 0, kTableTangents, P.d_jobs, P.d_tH, P.d_counts + 16, P.d_counts + kClaimH, P.gH, s));
   return NSF_OK;
 }
 
@@ -617,7 +662,7 @@ nsf_status enqueue_inference(Plan& P, hipStream_t s) {
     if (st == NSF_OK) st = enqueue_closure(P, s);
     if (st != NSF_OK) return st;
   }
-  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + 2,
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.kindsA, P.d_jobs, P.d_tA, P.d_counts + 2,
                               P.d_counts + kClaimA, std::min(P.gF, std::max(P.nA, 1)), s));
   return launch_hl(P, s);
 }
@@ -628,7 +673,7 @@ nsf_status launch_decode(Plan& P, hipStream_t s, bool beside) {
   if (P.nsims == 1 && !P.persistent)
     NSF_HIP(launch_fields_dense(P.width, P.bf16_hl, P.decode_job, P.decode_job.n, s, beside));
   else
-    NSF_HIP(launch_fields_table(P.width, P.bf16_hl, 0, P.d_jobs, P.d_tD, P.d_counts + 7,
+    NSF_HIP(launch_fields_table(P.width, P.bf16_hl, 0, kTableTangents, P.d_jobs, P.d_tD, P.d_counts + 7,
                                 P.d_counts + kClaimD, P.gF0, s));
   return NSF_OK;
 }
@@ -661,11 +706,11 @@ nsf_status enqueue_refresh_body(Plan& P, hipStream_t s, bool decode, bool in_ste
     nsf_status st = launch_decode(P, s, false);
     if (st == NSF_OK) st = enqueue_closure(P, s);
     if (st != NSF_OK) return st;
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + (in_step ? 0 : 2),
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.kindsA, P.d_jobs, P.d_tA, P.d_counts + (in_step ? 0 : 2),
                                 P.d_counts + kClaimA, P.gF, s));
     return NSF_OK;
   }
-  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tA, P.d_counts + (in_step ? 0 : 2),
+  NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.kindsA, P.d_jobs, P.d_tA, P.d_counts + (in_step ? 0 : 2),
                               P.d_counts + kClaimA, P.gF, s));
   const nsf_status hl = launch_hl(P, s);
   if (hl != NSF_OK) return hl;
@@ -710,7 +755,7 @@ nsf_status enqueue_step(Plan& P, hipStream_t s) {
   if (sm != NSF_OK) return sm;
   NSF_HIP(launch_gn_solve(P.d_sims, P.d_counts + 6, 0, P.gSims, s));
   for (int k = 1; k < P.gn_iters; ++k) {
-    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.d_jobs, P.d_tG + (k == 1 ? 0 : P.nGvel),
+    NSF_HIP(launch_fields_table(P.width, P.bf16, P.tc, P.kindsG, P.d_jobs, P.d_tG + (k == 1 ? 0 : P.nGvel),
                                 P.d_counts + (k == 1 ? 4 : 1),
                                 P.d_counts + kClaimG + (k - 1), P.gF, s));
     NSF_HIP(launch_gn_partial(P.d_sims, P.d_bGN, P.d_counts + 5, k, P.r_cap, P.gGN, s));

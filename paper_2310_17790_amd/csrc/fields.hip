@@ -289,6 +289,7 @@ struct TilePoint {
   int p;
   bool valid;
   float X[3];
+  float xg;   // X[lane / 16] for the lanes of groups 0..2 (layer 1's position rows)
 };
 
 __device__ __forceinline__ TilePoint tile_point(const FieldJob& jb, int p0, int lane) {
@@ -304,12 +305,41 @@ __device__ __forceinline__ TilePoint tile_point(const FieldJob& jb, int p0, int 
   tp.X[0] = jb.X[gi];
   tp.X[1] = jb.X[jb.ldx + gi];
   tp.X[2] = jb.X[2 * jb.ldx + gi];
+  // layer 1's input row k = lane group g < 3 (chosen here from the loaded values: a
+  // choice among X[] by a lane-varying index later can become an indexed load from memory)
+  const int g = lane >> 4;
+  tp.xg = g == 0 ? tp.X[0] : g == 1 ? tp.X[1] : tp.X[2];
   return tp;
 }
 
 // Layer 1: input rows 0..2 = X, 3..2+r = z, 3+r = 1 (bias column), four per K-step, into
 // zeroed accumulators. Tangent columns (t = 1..NT) are one-hot in z at t0 + t - 1
 // (Jacobian) or the direction z - z2 (JVP job).
+// f(0) .. f(n - 1) for the K-step counts of layer 1 (2 .. 9): with the count fixed at
+// compile time the steps are straight-line code, so all their loads are issued before the
+// first product instead of one step's loads per round trip (for a single output block:
+// a whole tile's steps would hold too many loads in flight).
+template <int N, class F>
+__device__ __forceinline__ void unroll_n(F&& f) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) f(i);
+}
+template <class F>
+__device__ __forceinline__ void for_k1_steps(int n, F&& f) {
+  switch (n) {
+    case 2: unroll_n<2>(f); break;
+    case 3: unroll_n<3>(f); break;
+    case 4: unroll_n<4>(f); break;
+    case 5: unroll_n<5>(f); break;
+    case 6: unroll_n<6>(f); break;
+    case 7: unroll_n<7>(f); break;
+    case 8: unroll_n<8>(f); break;
+    case 9: unroll_n<9>(f); break;
+    default:
+      for (int i = 0; i < n; ++i) f(i);
+  }
+}
+
 template <int W, int T, int NT>
 __device__ __forceinline__ void layer1_16(const FieldJob& jb, const TilePoint& tp, int t0, int lane,
                                           f32x4 (&acc)[T][W / 16]) {
@@ -324,7 +354,7 @@ __device__ __forceinline__ void layer1_16(const FieldJob& jb, const TilePoint& t
   for (int s4 = 0; s4 < K1q; ++s4) {
     const int k = 4 * s4 + g;
     float b0 = 0.f, bt = 0.f;
-    if (k < 3) b0 = (k == 0) ? tp.X[0] : (k == 1) ? tp.X[1] : tp.X[2];
+    if (k < 3) b0 = tp.xg;
     else if (k < 3 + r && jb.zrows != nullptr) {
       b0 = jb.zrows[(int64_t)(tp.valid ? tp.p : jb.n - 1) * r + (k - 3)];
     } else if (k < 3 + r) {
@@ -380,7 +410,7 @@ __device__ __forceinline__ void layer1_16_lds(const FieldJob& jb, const TilePoin
   for (int mb = 0; mb < MB; ++mb) acc[0][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int s4 = 0; s4 < K1q; ++s4) {
     const int k = 4 * s4 + g;
-    const float b0 = k < 3 ? ((k == 0) ? tp.X[0] : (k == 1) ? tp.X[1] : tp.X[2]) : zrow[k];
+    const float b0 = k < 3 ? tp.xg : zrow[k];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[0][mb] = mfma16(w1[(mb * K1q + s4) * 64 + lane], b0, acc[0][mb]);
   }
@@ -669,189 +699,297 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
   }
 }
 
-// ---- reverse-mode Jacobian of one tile per workgroup (FP32, width 128) -----------------
-// The eight waves of a workgroup share one 16-point tile: wave q owns output block q (16
-// neurons) of every layer. A layer's product needs the whole previous layer as the MFMA
-// B operand, so each wave publishes its block through LDS (K-steps 4q .. 4q + 3 of the
-// operand, lane-major, conflict-free) and reads back all of them. The forward pass runs
-// once, phi'(a_1..a_4) of the wave's block stays in its registers, and the three output
-// components are pulled back together: three cotangent operands share each weight
-// fragment. Work per tile: 4 forward + 3 x 4 backward block products per wave, against
-// three groups of 8 full-layer products each with one tile per wave. The output layer's
-// dot products and du_c/dz = W1_z^T delta_1 are summed over the waves' blocks through LDS
-// in a fixed order.
+// ---- team groups: reverse-mode Jacobian over two tiles per workgroup (FP32, width 128) --
+// The W / 16 waves of a workgroup share kTeamTiles 16-point tiles: wave q owns output block
+// q (16 neurons) of every layer for all of them. A layer's product needs the whole previous
+// layer as the MFMA B operand, so each wave publishes its block through LDS (K-steps
+// 4q .. 4q + 3 of each tile's operand, lane-major, conflict-free) and reads back all of
+// them. The forward pass runs once, phi'(a_1..a_4) of the wave's block stays in its
+// registers, and the three output components are pulled back together: three cotangent
+// operands per tile share each weight fragment. du_c/dz = W1_z^T delta_1 is summed over
+// the waves' blocks through LDS in a fixed order.
+//
+// A wave reads only block q of a layer (W / 8 fragments, 8 KB at width 128), so the
+// layers need no workgroup-wide copy: each wave copies its block of the next stage's layer
+// into its own slot of the first LDS buffer while the current stage computes (block q at
+// q x 8 KB, which is also where a whole-layer copy puts it), and reads it into registers
+// at the start of that stage. The exchanged operands live in the second buffer. With two
+// tiles per group, a stage's products are twice those of one tile between the same
+// barriers.
+//
+// After the Jacobian job, a group can evaluate up to three more jobs over the same point
+// range, forward only, in the same way (FieldTile.t0: their job offsets from the group's
+// job, one signed byte each, 0 = none): the step's stress and affine fields, or the
+// velocity's deformation field at the next step's points. A pass then holds one group per
+// CU of equal length instead of Jacobian groups beside longer primal groups.
+constexpr int kTeamTiles = 2;
+constexpr int kTeamW6 = 3;   // output rows per thread (9 rows of W floats over W / 16 waves)
+
+template <int W>
+struct TeamFrag {
+  f32x2 f[W / 8];
+};
+
+template <int W>
+constexpr int team_block_bytes() { return (W / 8) * 64 * 8; }
+
+// The layer a team stage copies for the next one: hidden layer k of pk (tr: its
+// transpose), or none.
+struct TeamNext {
+  const FieldPack* pk;
+  int k;
+  bool tr;
+};
+
+// Copy block q of nx's layer into the wave's slot (wave-private: no barrier orders it).
+template <int W>
+__device__ __forceinline__ void team_stage_copy(const TeamNext& nx, char* lds, int q, int lane) {
+  if (nx.pk == nullptr) return;
+  constexpr int BB = team_block_bytes<W>();
+  const char* src = hidden_src<false>(*nx.pk, nx.tr) + (size_t)nx.k * HiddenLayer<W, false>::kBytes + q * BB;
+#pragma unroll
+  for (int c = 0; c < BB / 1024; ++c)
+    __builtin_amdgcn_global_load_lds(src + c * 1024 + lane * 16, (lds_void*)(lds + q * BB + c * 1024), 16, 0, 0);
+}
+
+// The stage's fragments from the wave's slot, once the wave's copy has landed.
+template <int W>
+__device__ __forceinline__ void team_stage_read(TeamFrag<W>& w, const char* lds, int q, int lane) {
+  __builtin_amdgcn_s_waitcnt(0);
+  const f32x2* blk = reinterpret_cast<const f32x2*>(lds + q * team_block_bytes<W>());
+#pragma unroll
+  for (int hs = 0; hs < W / 8; ++hs) w.f[hs] = blk[hs * 64 + lane];
+}
+
+// s_waitcnt lgkmcnt(0) alone: the wave's LDS reads have returned (its slot may be
+// overwritten by the next copy).
+__device__ __forceinline__ void wait_lds_reads() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
 template <int W>
 __device__ __forceinline__ f32x4 layer1_block(const FieldJob& jb, const TilePoint& tp, int lane, int mb) {
   const int g = lane >> 4, r = jb.r;
   const int K1q = (r + 7) >> 2;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int s4 = 0; s4 < K1q; ++s4) {
+  for_k1_steps(K1q, [&](int s4) __attribute__((always_inline)) {
     const int k = 4 * s4 + g;
     float b0 = 0.f;
-    if (k < 3) b0 = (k == 0) ? tp.X[0] : (k == 1) ? tp.X[1] : tp.X[2];
+    if (k < 3) b0 = tp.xg;
     else if (k < 3 + r) b0 = (float)jb.z[k - 3];
     else if (k == 3 + r) b0 = 1.f;
     acc = mfma16(jb.w.w1q[(mb * K1q + s4) * 64 + lane], b0, acc);
-  }
+  });
   return acc;
 }
 
-// LDS the team groups use beside the two weight buffers: three exchanged operands.
-template <int W>
-constexpr int team_lds_bytes() { return 3 * (W / 4) * 64 * 4; }
-
-template <int W, int WPG, class NextFn>
-__device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&& next, char* lds, int wave,
-                                             int lane) {
-  static_assert(W / 16 == WPG, "one output block per wave");
-  constexpr int LB = HiddenLayer<W, false>::kBytes;
+// Forward pass of a team job over NT tiles: layer 1 and the four hidden layers of block
+// q (hidden layer 0 already in the wave's slot; the last stage copies `after`). KEEP:
+// phi'(a_1 .. a_4) of the block into D. Returns a_5's activation h5 and derivative dphi5,
+// and this thread's share of the output rows in w6.
+template <int W, int NT, bool KEEP>
+__device__ __forceinline__ void team_forward(const FieldJob& jb, const TilePoint (&tp)[NT], const TeamNext& after,
+                                             float* X, char* lds, int q, int lane, float (&D)[NT][4][4],
+                                             float (&h5)[NT][4], float (&dphi5)[NT][4], float (&w6)[kTeamW6]) {
   constexpr int KS = W / 4, HS = W / 8;
-  const int g = lane >> 4, q = wave;
-  const TilePoint tp = tile_point(jb, p0, lane);
-  float* X = reinterpret_cast<float*>(lds + 2 * LB);   // [3][KS][64]
-  // stage i = 0..3: hidden layer i; i = 4..7: the transpose of hidden layer 7 - i
-  auto stage = [&](int i) -> const f32x2* {
-    wait_dma_and_sync();
-    if (i < 7) {
-      const int kn = i + 1;
-      dma_layer<W, false, WPG>(jb.w, kn < 4 ? kn : 7 - kn, lds + (kn & 1) * LB, wave, lane, kn >= 4);
-    } else if (const FieldPack* next_w = next()) {
-      dma_layer<W, false, WPG>(*next_w, 0, lds, wave, lane);
-    }
-    return reinterpret_cast<const f32x2*>(lds + (i & 1) * LB);
-  };
-  // the block's bias of hidden layer k, loaded one stage ahead (the barrier that waits for
-  // the layer's copy also covers it)
+  const int g = lane >> 4;
   auto bias = [&](int k) { return *global_ptr(reinterpret_cast<const f32x4*>(jb.w.bhq + k * W + 16 * q + 4 * g)); };
   f32x4 bnext = bias(0);
-  // the block's output rows and latent-column fragments of layer 1, used only at the end
-  // of the tile, are loaded now: their latency then passes under the hidden layers
-  // instead of stalling all eight waves together
+  f32x4 a[NT];
+  float h[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    a[t] = layer1_block<W>(jb, tp[t], lane, q);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float dy;
+      elu_pair<false>(a[t][v], h[t][v], dy);
+      if constexpr (KEEP) D[t][0][v] = dy;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    // two exchange buffers by layer parity: a stage's writes never meet the previous
+    // stage's reads, so one barrier per stage
+    float* Xk = X + (k & 1) * NT * KS * 64;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xk[(t * KS + 4 * q + v) * 64 + lane] = h[t][v];
+    lds_barrier();   // publish the blocks
+    TeamFrag<W> wc;
+    team_stage_read<W>(wc, lds, q, lane);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) a[t] = bnext;
+    if (k < 3) {
+      bnext = bias(k + 1);
+    } else {
+      // this thread's share of the output rows, for the output layer
+#pragma unroll
+      for (int i = 0; i < kTeamW6; ++i) {
+        const int e = (int)threadIdx.x + i * 4 * W;   // 4 W = 64 lanes x W / 16 waves
+        w6[i] = e < jb.d * W ? jb.w.w6q[e] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      float Hf[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) Hf[s] = Xk[(t * KS + s) * 64 + lane];
+      if (t == 0) {
+        wait_lds_reads();
+        team_stage_copy<W>(k < 3 ? TeamNext{&jb.w, k + 1, false} : after, lds, q, lane);
+      }
+      __builtin_amdgcn_sched_barrier(0);   // the operand's reads all go out before its products
+#pragma unroll
+      for (int hs = 0; hs < HS; ++hs) {
+        a[t] = mfma16(wc.f[hs][0], Hf[2 * hs], a[t]);
+        a[t] = mfma16(wc.f[hs][1], Hf[2 * hs + 1], a[t]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (k < 3) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float dy;
+          elu_pair<false>(a[t][v], h[t][v], dy);
+          if constexpr (KEEP) D[t][k + 1][v] = dy;
+        }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) elu_pair<false>(a[t][v], h5[t][v], dphi5[t][v]);
+}
+
+// Output layer of a team job. The blocks of h5 are published like a layer's operand, with
+// the job's output rows (w6: this thread's share), and output row o of tile t is then
+// formed by one wave over the whole row, with the primal groups' own operation order
+// (output_dot16): a job gives the same bits in a team group and in a primal group. Wave
+// q takes tile q % NT and outputs q / NT + i WPG / NT.
+template <int W, int WPG, int NT>
+__device__ __forceinline__ void team_output(const FieldJob& jb, int p0, const float (&h5)[NT][4],
+                                            const float (&w6)[kTeamW6], float* X, int q, int lane) {
+  constexpr int KS = W / 4, OPW = (9 * NT + WPG - 1) / WPG;   // outputs per wave at most
+  static_assert(WPG % NT == 0, "waves split evenly over the tiles");
+  const int d = jb.d, g = lane >> 4, t = q % NT, o0 = q / NT;
+  // the output rows, [d][W], past both forward exchange buffers: a slower wave may still
+  // read the last hidden layer's operand from the second one
+  float* Xw = X + 2 * NT * KS * 64;
+#pragma unroll
+  for (int i = 0; i < kTeamW6; ++i) {
+    const int e = (int)threadIdx.x + i * 64 * WPG;   // as loaded in team_forward
+    if (e < d * W) Xw[e] = w6[i];
+  }
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[(tt * KS + 4 * q + v) * 64 + lane] = h5[tt][v];
+  lds_barrier();
+  float Hrow[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) Hrow[s] = X[(t * KS + s) * 64 + lane];
+  const int p = p0 + 16 * t + (lane & 15);
+#pragma unroll
+  for (int i = 0; i < OPW; ++i) {
+    const int o = o0 + i * (WPG / NT);
+    if (o < d) {
+      const float y = output_dot16<W>(Xw, o, g, Hrow) + jb.w.b6[o];
+      if (p < jb.n && g == (o & 3)) jb.out[o * jb.ldo + p] = jb.scale[o] * y + jb.shift[o];
+    }
+  }
+  lds_barrier();   // X may be rewritten
+}
+
+// Reverse pass of the Jacobian job: delta_5 of the three components, back through
+// W5^T .. W2^T (the transpose of hidden layer 3 already in the wave's slot; the last stage
+// copies `after`), then du_c/dz = W1_z^T delta_1 summed over the blocks.
+template <int W, int WPG, int NT>
+__device__ __forceinline__ void team_reverse(const FieldJob& jb, int p0, const TeamNext& after, float* X,
+                                             char* lds, int q, int lane, const float (&D)[NT][4][4],
+                                             const float (&dphi5)[NT][4]) {
+  constexpr int KS = W / 4, HS = W / 8;
+  const int g = lane >> 4, r = jb.r;
   f32x4 w6v[3];
 #pragma unroll
-  for (int o = 0; o < 3; ++o) w6v[o] = *reinterpret_cast<const f32x4*>(jb.w.w6q + o * W + 16 * q + 4 * g);
-  const int MZ = (jb.r + 15) >> 4;
-  const f32x2* Z = reinterpret_cast<const f32x2*>(jb.w.w1zt);
+  for (int c = 0; c < 3; ++c) w6v[c] = *global_ptr(reinterpret_cast<const f32x4*>(jb.w.w6q + c * W + 16 * q + 4 * g));
+  const int MZ = (r + 15) >> 4;
+  const auto* Z = global_ptr(reinterpret_cast<const f32x2*>(jb.w.w1zt));
   f32x2 zf[2][2];
 #pragma unroll
   for (int mz = 0; mz < 2; ++mz)
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh)
       zf[mz][hh] = mz < MZ ? Z[((size_t)mz * HS + 2 * q + hh) * 64 + lane] : f32x2{0.f, 0.f};
-  f32x4 a = layer1_block<W>(jb, tp, lane, q);
-  float D[4][4], h[4];
+  float d[NT][3][4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) elu_pair<false>(a[v], h[v], D[0][v]);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) X[(4 * q + v) * 64 + lane] = h[v];
-    const f32x2* A2 = stage(k);   // the barrier publishes X; layer k is in LDS
-    a = bnext;
-    if (k < 3) bnext = bias(k + 1);
-    float Hf[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) Hf[s] = X[s * 64 + lane];
-    lds_barrier();              // every wave holds its operand: X may be rewritten
-#pragma unroll
-    for (int hs = 0; hs < HS; ++hs) {
-      const f32x2 w = A2[(q * HS + hs) * 64 + lane];
-      a = mfma16(w[0], Hf[2 * hs], a);
-      a = mfma16(w[1], Hf[2 * hs + 1], a);
-    }
-    if (k < 3) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) elu_pair<false>(a[v], h[v], D[k + 1][v]);
-    }
-  }
-  // a = a_5 of block q. The primal output: per-block partial dot products, summed over the
-  // blocks in order by wave 0 (lanes 16 o + point).
-  float dphi5[4], h5[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) elu_pair<false>(a[v], h5[v], dphi5[v]);
-#pragma unroll
-  for (int o = 0; o < 3; ++o) {
-    const f32x4 w4 = w6v[o];
-    float sdot = w4[0] * h5[0] + w4[1] * h5[1] + w4[2] * h5[2] + w4[3] * h5[3];
-    sdot += __shfl_xor(sdot, 16);
-    sdot += __shfl_xor(sdot, 32);
-    if (lane < 16) X[(q * 3 + o) * 16 + lane] = sdot;
-  }
-  lds_barrier();
-  if (q == 0 && lane < 48) {
-    const int o = lane >> 4, pt = lane & 15, p = p0 + pt;
-    float sum = 0.f;
-#pragma unroll
-    for (int qq = 0; qq < WPG; ++qq) sum += X[(qq * 3 + o) * 16 + pt];
-    if (p < jb.n) jb.out[o * jb.ldo + p] = jb.scale[o] * (sum + jb.w.b6[o]) + jb.shift[o];
-  }
-  lds_barrier();
-  // delta_5 of the three components, then back through W5^T .. W2^T
-  float d[3][4];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const f32x4 w4 = w6v[c];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) d[c][v] = w4[v] * dphi5[v];
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) X[(c * KS + 4 * q + v) * 64 + lane] = d[c][v];
-    const f32x2* A2 = stage(4 + j);
-    // the block's weight fragments once, then one component at a time (its operand read
-    // back, its 32 products), so only one exchanged operand is live
-    f32x2 wf[HS];
+      for (int v = 0; v < 4; ++v) d[t][c][v] = w6v[c][v] * dphi5[t][v];
 #pragma unroll
-    for (int hs = 0; hs < HS; ++hs) wf[hs] = A2[(q * HS + hs) * 64 + lane];
+  for (int j = 0; j < 4; ++j) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      __builtin_amdgcn_sched_barrier(0);   // keep the next component's reads after these products
-      float Hc[KS];
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int s = 0; s < KS; ++s) Hc[s] = X[(c * KS + s) * 64 + lane];
-      f32x4 ac = {0.f, 0.f, 0.f, 0.f};
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int hs = 0; hs < HS; ++hs) {
-        ac = mfma16(wf[hs][0], Hc[2 * hs], ac);
-        ac = mfma16(wf[hs][1], Hc[2 * hs + 1], ac);
+        for (int v = 0; v < 4; ++v) X[((t * 3 + c) * KS + 4 * q + v) * 64 + lane] = d[t][c][v];
+    lds_barrier();   // publish the blocks
+    TeamFrag<W> wc;
+    team_stage_read<W>(wc, lds, q, lane);
+    // one (tile, component) operand at a time: its 32 reads, then its 32 products
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        __builtin_amdgcn_sched_barrier(0);
+        float Hc[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) Hc[s] = X[((t * 3 + c) * KS + s) * 64 + lane];
+        if (t == 0 && c == 0) {
+          wait_lds_reads();
+          team_stage_copy<W>(j < 3 ? TeamNext{&jb.w, 2 - j, true} : after, lds, q, lane);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // the operand's reads all go out before its products
+        f32x4 ac = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int hs = 0; hs < HS; ++hs) {
+          ac = mfma16(wc.f[hs][0], Hc[2 * hs], ac);
+          ac = mfma16(wc.f[hs][1], Hc[2 * hs + 1], ac);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d[t][c][v] = ac[v] * D[t][3 - j][v];
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) d[c][v] = ac[v] * D[3 - j][v];
-    }
-    lds_barrier();   // every wave has read the three operands: X may be rewritten
+    lds_barrier();   // every wave has read the operands: X may be rewritten
   }
   // d = delta_1 of block q (K-steps 4q + v of W1_z^T's product): partial du_c/dz over the
-  // block, rows in blocks of 16 (at most two), summed over the waves by wave c
-  const int r = jb.r;
-  f32x4 jz[3][2];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) jz[c][0] = jz[c][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int mz = 0; mz < 2; ++mz) {
-    if (mz < MZ) {
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        const f32x2 z2 = zf[mz][hh];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          jz[c][mz] = mfma16(z2[0], d[c][2 * hh], jz[c][mz]);
-          jz[c][mz] = mfma16(z2[1], d[c][2 * hh + 1], jz[c][mz]);
-        }
-      }
-    }
-  }
+  // block, rows in blocks of 16 (at most two), summed over the waves
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
-    for (int mz = 0; mz < 2; ++mz)
+    for (int t = 0; t < NT; ++t) {
+      f32x4 jz[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) X[((q * 2 + mz) * 4 + v) * 64 + lane] = jz[c][mz][v];
+      for (int mz = 0; mz < 2; ++mz) {
+        if (mz < MZ) {
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            jz[mz] = mfma16(zf[mz][hh][0], d[t][c][2 * hh], jz[mz]);
+            jz[mz] = mfma16(zf[mz][hh][1], d[t][c][2 * hh + 1], jz[mz]);
+          }
+        }
+      }
+#pragma unroll
+      for (int mz = 0; mz < 2; ++mz)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[(((t * WPG + q) * 2 + mz) * 4 + v) * 64 + lane] = jz[mz][v];
+    }
     lds_barrier();
-    if (q == c) {
-      const int p = p0 + (lane & 15);
+    if (q < NT) {
+      const int t = q, p = p0 + 16 * t + (lane & 15);
 #pragma unroll
       for (int mz = 0; mz < 2; ++mz) {
         if (mz < MZ) {
@@ -859,7 +997,7 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
           for (int v = 0; v < 4; ++v) {
             float sum = 0.f;
 #pragma unroll
-            for (int qq = 0; qq < WPG; ++qq) sum += X[((qq * 2 + mz) * 4 + v) * 64 + lane];
+            for (int qq = 0; qq < WPG; ++qq) sum += X[(((t * WPG + qq) * 2 + mz) * 4 + v) * 64 + lane];
             const int jj = 16 * mz + 4 * g + v;
             if (p < jb.n && jj < r) jb.jac[(c * r + jj) * jb.ldj + p] = jb.scale[c] * sum;
           }
@@ -868,6 +1006,57 @@ __device__ __forceinline__ void run_rev_team(const FieldJob& jb, int p0, NextFn&
     }
     lds_barrier();
   }
+}
+
+// Extra job e of a team group (see above): the group's job plus t0's signed byte e (e < 3;
+// 0: no such job).
+__device__ __forceinline__ int team_extra(const FieldTile& tl, int e) {
+  return (int)(int8_t)((tl.t0 >> (8 * e)) & 0xff);
+}
+
+// One team group; hidden layer 0 of its job is in the first LDS buffer on entry (copied by
+// the previous group, or at the kernel's start). `claim` claims the following group (every
+// thread calls it at the same point) and returns its index; a following team group's
+// first layer is then copied by the last stage, a primal group's after the last barrier.
+template <int W, int WPG, class ClaimFn>
+__device__ __forceinline__ void run_team(const FieldJob* __restrict__ jobs, const FieldTile& tl, ClaimFn&& claim,
+                                         const FieldTile* __restrict__ groups, int total, char* lds, int wave,
+                                         int lane) {
+  static_assert(W / 16 == WPG, "one output block per wave");
+  constexpr int NT = kTeamTiles, LB = HiddenLayer<W, false>::kBytes;
+  static_assert(NT * 3 * (W / 4) * 64 * 4 <= LB && NT * WPG * 2 * 4 * 64 * 4 <= LB &&
+                    (2 * NT * (W / 4) * 64 + 9 * W) * 4 <= LB &&
+                    kTeamW6 * 64 * WPG >= 9 * W && 64 * WPG == 4 * W && WPG * team_block_bytes<W>() == LB,
+                "the exchanged operands fit in the second buffer; the blocks tile the first");
+  const int q = wave;
+  float* X = reinterpret_cast<float*>(lds + LB);
+  const FieldJob& jb = jobs[tl.job];
+  const int nx = team_extra(tl, 2) != 0 ? 3 : team_extra(tl, 1) != 0 ? 2 : team_extra(tl, 0) != 0 ? 1 : 0;
+  // the previous group's LDS reads and copies are complete
+  wait_dma_and_sync();
+  TilePoint tp[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) tp[t] = tile_point(jb, tl.p0 + 16 * t, lane);
+  float D[NT][4][4], h5[NT][4], dphi5[NT][4], w6[kTeamW6];
+  team_forward<W, NT, true>(jb, tp, TeamNext{&jb.w, 3, true}, X, lds, q, lane, D, h5, dphi5, w6);
+  team_output<W, WPG, NT>(jb, tl.p0, h5, w6, X, q, lane);
+  const int gn = claim();
+  const bool next_team = gn < total && groups[gn].nt == -2;
+  const TeamNext next_first{next_team ? &jobs[groups[gn].job].w : nullptr, 0, false};
+  team_reverse<W, WPG, NT>(jb, tl.p0, nx > 0 ? TeamNext{&jobs[tl.job + team_extra(tl, 0)].w, 0, false} : next_first,
+                           X, lds, q, lane, D, dphi5);
+#pragma unroll 1
+  for (int e = 0; e < nx; ++e) {
+    const FieldJob& xb = jobs[tl.job + team_extra(tl, e)];
+    TilePoint xp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) xp[t] = tile_point(xb, tl.p0 + 16 * t, lane);
+    const TeamNext xn = e + 1 < nx ? TeamNext{&jobs[tl.job + team_extra(tl, e + 1)].w, 0, false} : next_first;
+    team_forward<W, NT, false>(xb, xp, xn, X, lds, q, lane, D, h5, dphi5, w6);
+    team_output<W, WPG, NT>(xb, tl.p0, h5, w6, X, q, lane);
+  }
+  // a primal group copies its layers over the whole buffer: after every wave's last read
+  if (gn < total && !next_team) dma_layer<W, false, WPG>(jobs[groups[gn].job].w, 0, lds, wave, lane);
 }
 
 // Run a group with its tangent count as a template argument (0 .. TC).
@@ -888,8 +1077,11 @@ __device__ __forceinline__ void dispatch_nt(const FieldJob& jb, int p0, int t0, 
 // Work groups from a table (several jobs; a group is WPG tiles of one job). Workgroups
 // claim groups dynamically from a counter (zero at launch), one group ahead so the next
 // group's first hidden layer can be fetched while the current group finishes; groups
-// are ordered longest first, so the claims balance the load.
-template <int W, int TC, bool BF, int WPG>
+// are ordered longest first, so the claims balance the load. KINDS: the group kinds
+// besides primal ones the kernel is built for (kTableTangents, kTableTeam): the tangent
+// groups and the team groups each need nearly all registers, and a kernel built for both
+// spills.
+template <int W, int TC, bool BF, int WPG, int KINDS>
 __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* __restrict__ jobs,
                                                                 const FieldTile* __restrict__ groups,
                                                                 const int32_t* __restrict__ n_groups,
@@ -905,13 +1097,14 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
   if (g >= total) return;
   dma_layer<W, BF, WPG>(jobs[groups[g].job].w, 0, lds, wave, lane);
   int gn = total;
-  // called by every thread at the same point of run_group16 (after a barrier)
-  auto next = [&]() -> const FieldPack* {
+  // called by every thread at the same point of a group (after a barrier)
+  auto claim_next = [&]() -> int {
     if (threadIdx.x == 0) s_claim = atomicAdd(claim, 1);
     __syncthreads();
     gn = s_claim;
-    return gn < total ? &jobs[groups[gn].job].w : nullptr;
+    return gn;
   };
+  auto next = [&]() -> const FieldPack* { return claim_next() < total ? &jobs[groups[gn].job].w : nullptr; };
   while (true) {
     const FieldTile tl = groups[g];
     if (tl.p0 >= jobs[tl.job].n) {
@@ -923,9 +1116,9 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
       g = gn;
       continue;
     }
-    if constexpr (TC > 0 && !BF && W / 16 == WPG) {   // one tile per workgroup (nt == -2)
+    if constexpr (TC > 0 && !BF && W / 16 == WPG && (KINDS & kTableTeam)) {   // team groups (nt == -2)
       if (tl.nt == -2) {
-        run_rev_team<W, WPG>(jobs[tl.job], tl.p0, next, lds, wave, lane);
+        run_team<W, WPG>(jobs, tl, claim_next, groups, total, lds, wave, lane);
         if (gn >= total) break;
         g = gn;
         continue;
@@ -939,7 +1132,8 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
         continue;
       }
     }
-    dispatch_nt<W, TC, BF, WPG>(jobs[tl.job], tl.p0, tl.t0, tl.nt, next, lds, wave, lane);
+    if constexpr ((KINDS & kTableTangents) != 0) dispatch_nt<W, TC, BF, WPG>(jobs[tl.job], tl.p0, tl.t0, tl.nt, next, lds, wave, lane);
+    else run_group16<W, 0, BF, WPG>(jobs[tl.job], tl.p0 + kTile16 * wave, tl.t0, next, lds, wave, lane);
     if (gn >= total) break;
     g = gn;
   }
@@ -1047,13 +1241,12 @@ constexpr int kTcF32W64 = 3, kTcF32W128 = 2, kTcBf16W64 = 4, kTcBf16W128 = 2;
 // primal. A group spans WPG tiles of 16 points.
 template <int TC> struct Wpg { static constexpr int value = TC > 0 ? 8 : 16; };
 
-template <int W, int TC, bool BF>
+template <int W, int TC, bool BF, int KINDS = kTableTangents>
 hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int32_t* n_groups,
                         int32_t* claim, int grid, hipStream_t s) {
   constexpr int WPG = Wpg<TC>::value;
-  constexpr bool team = TC > 0 && !BF && W / 16 == WPG;
-  constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes + (team ? team_lds_bytes<W>() : 0);
-  auto k = fields_table_kernel<W, TC, BF, WPG>;
+  constexpr int lds = 2 * HiddenLayer<W, BF>::kBytes;   // team groups exchange in the second buffer
+  auto k = fields_table_kernel<W, TC, BF, WPG, KINDS>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -1137,9 +1330,11 @@ int fields_max_tangents(int width, bool bf16) {
 
 int fields_group_points(int tc) { return kTile16 * (tc > 0 ? Wpg<1>::value : Wpg<0>::value); }
 
+int fields_team_points() { return kTile16 * kTeamTiles; }
+
 bool fields_team_jacobian(int width, bool bf16) { return !bf16 && width / 16 == Wpg<1>::value; }
 
-hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
+hipError_t launch_fields_table(int width, bool bf16, int tc, int kinds, const FieldJob* jobs,
                                const FieldTile* groups, const int32_t* n_groups, int32_t* claim,
                                int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
@@ -1150,6 +1345,11 @@ hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* job
     return full ? NSF_TABLE(64, kTcBf16W64, true) : NSF_TABLE(64, 0, true);
   }
   if (width == 128) {
+    if (!bf16 && full && (kinds & kTableTeam)) {
+      if (kinds & kTableTangents)
+        return launch_table<128, kTcF32W128, false, kTableTangents | kTableTeam>(jobs, groups, n_groups, claim, grid, s);
+      return launch_table<128, kTcF32W128, false, kTableTeam>(jobs, groups, n_groups, claim, grid, s);
+    }
     if (!bf16) return full ? NSF_TABLE(128, kTcF32W128, false) : NSF_TABLE(128, 0, false);
     return full ? NSF_TABLE(128, kTcBf16W128, true) : NSF_TABLE(128, 0, true);
   }

@@ -151,7 +151,10 @@ struct BlockWork {
 };
 
 // ---- launchers (defined in the .hip files) ----
-hipError_t launch_fields_table(int width, bool bf16, int tc, const FieldJob* jobs,
+// Group kinds a table holds besides primal groups (launch_fields_table's `kinds`, for
+// tc > 0): tangent or one-wave reverse groups (nt > 0, nt == -1), team groups (nt == -2).
+enum : int { kTableTangents = 1, kTableTeam = 2 };
+hipError_t launch_fields_table(int width, bool bf16, int tc, int kinds, const FieldJob* jobs,
                                const FieldTile* groups, const int32_t* n_groups, int32_t* claim,
                                int grid, hipStream_t s);
 int fields_table_blocks_per_cu(int width, bool bf16, int tc);
@@ -163,8 +166,11 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
 int fields_max_tangents(int width, bool bf16);
 int fields_group_points(int tc);  // points one work group (table entry) spans
 // Jacobians with more latent columns than forward mode carries take one workgroup per
-// 16-point tile (FieldTile.nt = -2) in this configuration
+// fields_team_points() points (FieldTile.nt = -2) in this configuration; such a group also
+// evaluates up to three more jobs over the same points, forward only (FieldTile.t0: their
+// job offsets from FieldTile.job, one signed byte each, 0 = none)
 bool fields_team_jacobian(int width, bool bf16);
+int fields_team_points();
 
 // MPM transfers: bin (per integration particle; also zeroes the step's claim counters and,
 // for pipelined decodes, snapshots z_n), then allocate and place (per sim), sort and write
