@@ -356,9 +356,9 @@ int32_t team_extras(int job, std::initializer_list<int> extra) {
 }
 
 void add_tiles(std::vector<FieldTile>& out, int job, int n, int ntan, int tc, bool team = false,
-               int32_t extras = 0) {
+               int32_t extras = 0, int team_nt = -2) {
   if (team && reverse_jacobian(ntan, tc)) {   // one workgroup per fields_team_points() points
-    for (int p0 = 0; p0 < n; p0 += fields_team_points()) out.push_back({job, p0, extras, -2});
+    for (int p0 = 0; p0 < n; p0 += fields_team_points(team_nt)) out.push_back({job, p0, extras, team_nt});
     return;
   }
   const int span = fields_group_points(ntan > 0 ? tc : 0);
@@ -432,10 +432,18 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   // inference) with its Jacobian job, and the velocity's g at the next step's points with
   // the first Gauss-Newton pass's. Every member must qualify, so that each table holds one
   // kind of team group (not in persistent plans, whose members change under one graph).
-  bool fuse = team && !P.mixed && !P.closure && !P.persistent;
-  for (nsf_sim* m : P.members)
+  // (nor beside a pipelined decode, which holds most CUs while the step's passes run: there
+  // shorter groups share the rest better). Team groups take two tiles when the pairs of
+  // one pass still fill the device, else one.
+  bool fuse = team && !P.mixed && !P.closure && !P.persistent && !P.pipelined;
+  int team_pairs = 0;
+  for (nsf_sim* m : P.members) {
     fuse = fuse && m->n_int == m->n_samp && reverse_jacobian(m->r, P.tc) && !m->hd.tangent_forms;
+    team_pairs += (m->n_samp + fields_team_points(-2) - 1) / fields_team_points(-2);
+  }
   const bool fuse_g = fuse && vel_in_g;
+  // (a persistent plan keeps one tiles per group for any set of members: its graph's kernels)
+  const int team_nt = !P.pipelined && !P.persistent && team_pairs >= device_cus() ? -2 : -3;
   for (size_t si = 0; si < P.members.size(); ++si) {
     nsf_sim* s = P.members[si];
     const SimDev& H = s->hd;
@@ -453,7 +461,7 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     a.n = S; a.out = H.u_n; a.ldo = N; a.jac = H.J; a.ldj = S;
     jobs.push_back(a);
     if (!fuse) {
-      if (team && reverse_jacobian(r, P.tc)) add_tiles(tA_team, j0, S, r, P.tc, true);
+      if (team && reverse_jacobian(r, P.tc)) add_tiles(tA_team, j0, S, r, P.tc, true, 0, team_nt);
       else add_tiles(tA_jac, j0, S, r, P.tc);
     }
     if (N > S) {
@@ -505,13 +513,14 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
     if (s->closure) P.list_jobs = lj;
     jobs.push_back(l);
     if (fuse)
-      add_tiles(tA_team, j0, S, r, P.tc, true, vel_in_g ? team_extras(j0, {jh, jl}) : team_extras(j0, {jh, jl, jvel}));
+      add_tiles(tA_team, j0, S, r, P.tc, true, vel_in_g ? team_extras(j0, {jh, jl}) : team_extras(j0, {jh, jl, jvel}),
+                team_nt);
     // Gauss-Newton iterate: g and its Jacobian on S
     FieldJob g = base_job(s, NSF_FIELD_G, zi);
     g.n = S; g.out = H.u_gn; g.ldo = S; g.jac = H.J2; g.ldj = S;
     const int jg = (int)jobs.size();
-    add_tiles(tG, jg, S, r, P.tc, team);
-    if (fuse_g) add_tiles(tG_vel, jg, S, r, P.tc, true, team_extras(jg, {jvel}));
+    add_tiles(tG, jg, S, r, P.tc, team, 0, team_nt);
+    if (fuse_g) add_tiles(tG_vel, jg, S, r, P.tc, true, team_extras(jg, {jvel}), team_nt);
     jobs.push_back(g);
     // decode all particles at the new latent
     // (a pipelined decode reads the snapshot of z_n the step's first kernel takes)
@@ -542,12 +551,13 @@ nsf_status build_plan(Plan& P, hipStream_t stream) {
   P.nG -= P.nGvel;
   auto kinds = [](const std::vector<FieldTile>& t) {
     int k = 0;
-    for (const FieldTile& f : t) k |= f.nt == -2 ? kTableTeam : (f.nt != 0 ? kTableTangents : 0);
+    for (const FieldTile& f : t)
+      k |= f.nt == -2 ? kTableTeam : f.nt == -3 ? kTableTeam | kTableTeamOne : (f.nt != 0 ? kTableTangents : 0);
     return k ? k : kTableTangents;
   };
   // a persistent plan's graph outlives its tables: its kernels take every kind
-  P.kindsA = P.persistent ? kTableTangents | kTableTeam : kinds(tA);
-  P.kindsG = P.persistent ? kTableTangents | kTableTeam : kinds(tG);
+  P.kindsA = P.persistent ? kTableTangents | kTableTeam | kTableTeamOne : kinds(tA);
+  P.kindsG = P.persistent ? kTableTangents | kTableTeam | kTableTeamOne : kinds(tG);
   P.nP = (int)bP.size(); P.nGN = (int)bGN.size();
   P.nsims = (int)sims.size();
   P.nH = (int)tH.size();

@@ -700,7 +700,8 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
 }
 
 // ---- team groups: reverse-mode Jacobian over two tiles per workgroup (FP32, width 128) --
-// The W / 16 waves of a workgroup share kTeamTiles 16-point tiles: wave q owns output block
+// The W / 16 waves of a workgroup share NT 16-point tiles (two, FieldTile.nt = -2, or one,
+// nt = -3, for tables too short to fill the device with pairs): wave q owns output block
 // q (16 neurons) of every layer for all of them. A layer's product needs the whole previous
 // layer as the MFMA B operand, so each wave publishes its block through LDS (K-steps
 // 4q .. 4q + 3 of each tile's operand, lane-major, conflict-free) and reads back all of
@@ -722,7 +723,8 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
 // job, one signed byte each, 0 = none): the step's stress and affine fields, or the
 // velocity's deformation field at the next step's points. A pass then holds one group per
 // CU of equal length instead of Jacobian groups beside longer primal groups.
-constexpr int kTeamTiles = 2;
+// Tiles of a team group from its FieldTile.nt (-2: two, -3: one).
+__host__ __device__ constexpr int team_tiles(int nt) { return nt == -2 ? 2 : 1; }
 constexpr int kTeamW6 = 3;   // output rows per thread (9 rows of W floats over W / 16 waves)
 
 template <int W>
@@ -1018,12 +1020,12 @@ __device__ __forceinline__ int team_extra(const FieldTile& tl, int e) {
 // the previous group, or at the kernel's start). `claim` claims the following group (every
 // thread calls it at the same point) and returns its index; a following team group's
 // first layer is then copied by the last stage, a primal group's after the last barrier.
-template <int W, int WPG, class ClaimFn>
+template <int W, int WPG, int NT, class ClaimFn>
 __device__ __forceinline__ void run_team(const FieldJob* __restrict__ jobs, const FieldTile& tl, ClaimFn&& claim,
                                          const FieldTile* __restrict__ groups, int total, char* lds, int wave,
                                          int lane) {
   static_assert(W / 16 == WPG, "one output block per wave");
-  constexpr int NT = kTeamTiles, LB = HiddenLayer<W, false>::kBytes;
+  constexpr int LB = HiddenLayer<W, false>::kBytes;
   static_assert(NT * 3 * (W / 4) * 64 * 4 <= LB && NT * WPG * 2 * 4 * 64 * 4 <= LB &&
                     (2 * NT * (W / 4) * 64 + 9 * W) * 4 <= LB &&
                     kTeamW6 * 64 * WPG >= 9 * W && 64 * WPG == 4 * W && WPG * team_block_bytes<W>() == LB,
@@ -1041,7 +1043,7 @@ __device__ __forceinline__ void run_team(const FieldJob* __restrict__ jobs, cons
   team_forward<W, NT, true>(jb, tp, TeamNext{&jb.w, 3, true}, X, lds, q, lane, D, h5, dphi5, w6);
   team_output<W, WPG, NT>(jb, tl.p0, h5, w6, X, q, lane);
   const int gn = claim();
-  const bool next_team = gn < total && groups[gn].nt == -2;
+  const bool next_team = gn < total && groups[gn].nt <= -2;
   const TeamNext next_first{next_team ? &jobs[groups[gn].job].w : nullptr, 0, false};
   team_reverse<W, WPG, NT>(jb, tl.p0, nx > 0 ? TeamNext{&jobs[tl.job + team_extra(tl, 0)].w, 0, false} : next_first,
                            X, lds, q, lane, D, dphi5);
@@ -1116,9 +1118,9 @@ __global__ __launch_bounds__(64 * WPG) void fields_table_kernel(const FieldJob* 
       g = gn;
       continue;
     }
-    if constexpr (TC > 0 && !BF && W / 16 == WPG && (KINDS & kTableTeam)) {   // team groups (nt == -2)
-      if (tl.nt == -2) {
-        run_team<W, WPG>(jobs, tl, claim_next, groups, total, lds, wave, lane);
+    if constexpr (TC > 0 && !BF && W / 16 == WPG && (KINDS & kTableTeam)) {   // team groups (nt -2, -3)
+      if (tl.nt <= -2) {
+        run_team<W, WPG, (KINDS & kTableTeamOne) ? 1 : 2>(jobs, tl, claim_next, groups, total, lds, wave, lane);
         if (gn >= total) break;
         g = gn;
         continue;
@@ -1330,7 +1332,7 @@ int fields_max_tangents(int width, bool bf16) {
 
 int fields_group_points(int tc) { return kTile16 * (tc > 0 ? Wpg<1>::value : Wpg<0>::value); }
 
-int fields_team_points() { return kTile16 * kTeamTiles; }
+int fields_team_points(int nt) { return kTile16 * team_tiles(nt); }
 
 bool fields_team_jacobian(int width, bool bf16) { return !bf16 && width / 16 == Wpg<1>::value; }
 
@@ -1346,9 +1348,14 @@ hipError_t launch_fields_table(int width, bool bf16, int tc, int kinds, const Fi
   }
   if (width == 128) {
     if (!bf16 && full && (kinds & kTableTeam)) {
-      if (kinds & kTableTangents)
-        return launch_table<128, kTcF32W128, false, kTableTangents | kTableTeam>(jobs, groups, n_groups, claim, grid, s);
-      return launch_table<128, kTcF32W128, false, kTableTeam>(jobs, groups, n_groups, claim, grid, s);
+#define NSF_TEAM(K) launch_table<128, kTcF32W128, false, K>(jobs, groups, n_groups, claim, grid, s)
+      switch (kinds & (kTableTangents | kTableTeamOne)) {
+        case 0: return NSF_TEAM(kTableTeam);
+        case kTableTangents: return NSF_TEAM(kTableTeam | kTableTangents);
+        case kTableTeamOne: return NSF_TEAM(kTableTeam | kTableTeamOne);
+        default: return NSF_TEAM(kTableTeam | kTableTeamOne | kTableTangents);
+      }
+#undef NSF_TEAM
     }
     if (!bf16) return full ? NSF_TABLE(128, kTcF32W128, false) : NSF_TABLE(128, 0, false);
     return full ? NSF_TABLE(128, kTcBf16W128, true) : NSF_TABLE(128, 0, true);

@@ -152,8 +152,9 @@ struct BlockWork {
 
 // ---- launchers (defined in the .hip files) ----
 // Group kinds a table holds besides primal groups (launch_fields_table's `kinds`, for
-// tc > 0): tangent or one-wave reverse groups (nt > 0, nt == -1), team groups (nt == -2).
-enum : int { kTableTangents = 1, kTableTeam = 2 };
+// tc > 0): tangent or one-wave reverse groups (nt > 0, nt == -1), team groups (nt -2, -3;
+// kTableTeamOne: the team groups take one tile, nt = -3; a table holds one kind of them).
+enum : int { kTableTangents = 1, kTableTeam = 2, kTableTeamOne = 4 };
 hipError_t launch_fields_table(int width, bool bf16, int tc, int kinds, const FieldJob* jobs,
                                const FieldTile* groups, const int32_t* n_groups, int32_t* claim,
                                int grid, hipStream_t s);
@@ -166,11 +167,12 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
 int fields_max_tangents(int width, bool bf16);
 int fields_group_points(int tc);  // points one work group (table entry) spans
 // Jacobians with more latent columns than forward mode carries take one workgroup per
-// fields_team_points() points (FieldTile.nt = -2) in this configuration; such a group also
-// evaluates up to three more jobs over the same points, forward only (FieldTile.t0: their
-// job offsets from FieldTile.job, one signed byte each, 0 = none)
+// fields_team_points(nt) points (FieldTile.nt = -2: two 16-point tiles, -3: one) in this
+// configuration; such a group also evaluates up to three more jobs over the same points,
+// forward only (FieldTile.t0: their job offsets from FieldTile.job, one signed byte each,
+// 0 = none)
 bool fields_team_jacobian(int width, bool bf16);
-int fields_team_points();
+int fields_team_points(int nt);
 
 // MPM transfers: bin (per integration particle; also zeroes the step's claim counters and,
 // for pipelined decodes, snapshots z_n), then allocate and place (per sim), sort and write
