@@ -238,13 +238,26 @@ __global__ __launch_bounds__(kGnThreads) void gn_partial_kernel(const SimDev* __
     if (iter >= S.gn_iters) continue;
     const int r = S.r, ns = S.n_samp, p0 = wk.p0;
     const int cnt = min(kGnChunk, ns - p0);
-    gn_stage_jacobian(S, S.J2, p0, cnt, sh);
     const int p = p0 + tid;
+    // the residual's values are loaded first, so their latency passes under the
+    // Jacobian's (twelve loads per thread: one batch up to r = 8)
+    float vn[3] = {0.f, 0.f, 0.f}, ug[3] = {0.f, 0.f, 0.f}, un[3] = {0.f, 0.f, 0.f};
+    if (tid < cnt) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        vn[c] = S.vnew[c * ns + p];
+        if (!S.tangent_forms) {
+          ug[c] = S.u_gn[c * ns + p];
+          un[c] = S.u_n[c * S.n_int + p];
+        }
+      }
+    }
+    gn_stage_jacobian<kGnThreads, 12>(S, S.J2, p0, cnt, sh);
 #pragma unroll
     for (int c = 0; c < 3 && tid < kGnChunk; ++c) {
       double rv = 0.0;
       if (tid < cnt) {
-        rv = -S.dt_d * (double)S.vnew[c * ns + p];
+        rv = -S.dt_d * (double)vn[c];
         if (S.tangent_forms) {
           // u(z^(k)) - u(z_n) by the trapezoid rule along z^(k) - z_n from the two
           // Jacobians (error O(|dz|^3)), avoiding the difference of two BF16 values
@@ -257,7 +270,7 @@ __global__ __launch_bounds__(kGnThreads) void gn_partial_kernel(const SimDev* __
           }
           rv += du;
         } else {
-          rv += (double)S.u_gn[c * ns + p] - (double)S.u_n[c * S.n_int + p];
+          rv += (double)ug[c] - (double)un[c];
         }
       }
       sh.res(c, tid) = rv;

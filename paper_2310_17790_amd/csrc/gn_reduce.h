@@ -50,11 +50,10 @@ __device__ __forceinline__ void gn_decode_entry(int e, int r, int& j, int& k, bo
 }
 
 // Stage the chunk's Jacobian rows (zero beyond the last sample point). Loads are issued
-// in batches of 8 per thread before any is stored, so their latencies overlap.
-template <int NT>
+// in batches of U per thread before any is stored, so their latencies overlap.
+template <int NT, int U = 8>
 __device__ __forceinline__ void gn_stage_jacobian(const SimDev& S, const float* J, int p0, int cnt,
                                                   const GnChunkLds<NT>& sh) {
-  constexpr int U = 8;
   const int r = S.r, ns = S.n_samp;
   const int total = 3 * r * kGnChunk;
   for (int e0 = threadIdx.x; e0 < total; e0 += NT * U) {

@@ -44,9 +44,11 @@ def _with_velocity(w, eps=2e-3, seed=99):
 # (r, width, particles, grid): the ragged and tiny cases, the largest latent (r = 32, split
 # over 16 waves per point tile) on the largest grid (256^3: bins of 8^3 cells, 32^3 bins),
 # the smallest well-posed sample sets (|S| = r / 3: one particle for r = 3, two for r = 6).
+# (6, 128, 8200, 32): enough samples for FP32 team groups of two tiles (257 pairs), the
+# last pair with 8 points in its first tile and none in its second
 @pytest.mark.parametrize("r,width,n,grid", [(6, 64, 1024, 32), (6, 128, 1000, 32), (24, 128, 515, 32),
                                             (1, 64, 77, 32), (3, 64, 96, 32), (32, 128, 700, 256),
-                                            (3, 64, 1, 32), (6, 64, 2, 32)])
+                                            (3, 64, 1, 32), (6, 64, 2, 32), (6, 128, 8200, 32)])
 def test_stage_parity_one_step(r, width, n, grid):
     w = _with_velocity(synth.small_cube(seed=3, r=r, width=width, n=n, bias_scale=0.1))
     w.grid_n, w.dx = grid, 1.0 / grid
