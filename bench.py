@@ -57,7 +57,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "mixed": 2500.0}   # dense MFMA pe
 # for a plain 256 MiB device copy (bench.py --copy-probe: FETCH_SIZE reads half the copied
 # bytes, WRITE_SIZE all of them). Valid only for the kernel source they were taken on
 # (SHA-256 of csrc/fields.hip); null otherwise.
-DECODE_COUNTERS = {"fields_hip_sha256": "0218306992d88b7929b34d8ca938d1082ad85a43fcff02b8aaffe46051906c12",
+DECODE_COUNTERS = {"fields_hip_sha256": "92a87514f97c747d120d4e1947c2dd2c5c7d0ff2e593f8ed0d9c25a59c583706",
                    "fetch_kib": 2357.4, "write_kib": 2343.75, "fetch_scale": 2.0, "write_scale": 1.0}
 
 

@@ -699,7 +699,7 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
   }
 }
 
-// ---- team groups: reverse-mode Jacobian over two tiles per workgroup (FP32, width 128) --
+// ---- team groups: reverse-mode Jacobian over one or two tiles per workgroup (FP32, W 128)
 // The W / 16 waves of a workgroup share NT 16-point tiles (two, FieldTile.nt = -2, or one,
 // nt = -3, for tables too short to fill the device with pairs): wave q owns output block
 // q (16 neurons) of every layer for all of them. A layer's product needs the whole previous
@@ -723,6 +723,7 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
 // job, one signed byte each, 0 = none): the step's stress and affine fields, or the
 // velocity's deformation field at the next step's points. A pass then holds one group per
 // CU of equal length instead of Jacobian groups beside longer primal groups.
+
 // Tiles of a team group from its FieldTile.nt (-2: two, -3: one).
 __host__ __device__ constexpr int team_tiles(int nt) { return nt == -2 ? 2 : 1; }
 constexpr int kTeamW6 = 3;   // output rows per thread (9 rows of W floats over W / 16 waves)
