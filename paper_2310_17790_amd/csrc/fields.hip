@@ -51,11 +51,13 @@ __device__ __forceinline__ f32x4 mfma16_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
 // itself gives e = exp(a), with no multiply (for large a' it may overflow to +inf, which
 // the selects discard):
 //   exact: h' = a' > 0 ? a' : (e - 1) / ln 2,  dh'/da' = a' > 0 ? 1 : e.
-//   fast (values about to be rounded to BF16): since (e - 1) / ln 2 >= a' everywhere and
-//     <= 0 for a' <= 0, h' is the median of ((e - 1) / ln 2, a', 0), and dh'/da' =
-//     min(e, 1): one op fewer. For 0 < a' < ~3e-4 the FP32 rounding of e can put
-//     (e - 1) / ln 2 below a', and the median then returns it, off by at most 1.7e-7 -
-//     far below BF16 resolution, so only the BF16 hidden layers use it.
+//   fast: since (e - 1) / ln 2 >= a' everywhere and <= 0 for a' <= 0, h' is the median of
+//     ((e - 1) / ln 2, a', 0), and dh'/da' = min(e, 1) (the same values): one op fewer.
+//     For 0 < a' < ~3e-4 the FP32 rounding of e can put (e - 1) / ln 2 below a', and the
+//     median then returns it, off by at most 1.7e-7 absolute - below the FP32 rounding of
+//     a width-128 layer's sum of products, so every layer uses it (the decode's ELU work
+//     is a sixth of its SIMD cycles, and this took it from 0.759 to 0.768 of the peak).
+//     A non-finite latent is still flagged: the solve checks the latent itself.
 constexpr float kInvLn2 = 1.44269504088896340736f;
 template <bool FAST>
 __device__ __forceinline__ void elu_pair(float a, float& y, float& dy) {
@@ -78,7 +80,7 @@ __device__ __forceinline__ void activate16(const f32x4 (&acc)[T][W / 16], float 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       float y, dy;
-      elu_pair<false>(acc[0][mb][v], y, dy);
+      elu_pair<true>(acc[0][mb][v], y, dy);
       H[0][4 * mb + v] = y;
 #pragma unroll
       for (int t = 1; t < T; ++t)
@@ -554,7 +556,7 @@ __device__ __forceinline__ void activate_keep(const f32x4 (&acc)[1][W / 16], flo
 #pragma unroll
     for (int mb = 0; mb < W / 16; ++mb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) elu_pair<false>(acc[0][mb][v], H[0][4 * mb + v], D[4 * mb + v]);
+      for (int v = 0; v < 4; ++v) elu_pair<true>(acc[0][mb][v], H[0][4 * mb + v], D[4 * mb + v]);
   }
 }
 
@@ -635,7 +637,7 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       float dy;
-      elu_pair<false>(acc[0][mb][v], H[0][4 * mb + v], dy);
+      elu_pair<true>(acc[0][mb][v], H[0][4 * mb + v], dy);
     }
   if (c == 0) {
 #pragma unroll 1
@@ -653,7 +655,7 @@ __device__ __forceinline__ void run_rev16(const FieldJob& jb, int p0, int c, Nex
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         float y, dy;
-        elu_pair<false>(acc[0][mb][v], y, dy);
+        elu_pair<true>(acc[0][mb][v], y, dy);
         acc[0][mb][v] = w4[v] * dy;
         ones[4 * mb + v] = 1.f;
       }
@@ -804,7 +806,7 @@ __device__ __forceinline__ void team_forward(const FieldJob& jb, const TilePoint
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       float dy;
-      elu_pair<false>(a[t][v], h[t][v], dy);
+      elu_pair<true>(a[t][v], h[t][v], dy);
       if constexpr (KEEP) D[t][0][v] = dy;
     }
   }
@@ -855,7 +857,7 @@ __device__ __forceinline__ void team_forward(const FieldJob& jb, const TilePoint
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float dy;
-          elu_pair<false>(a[t][v], h[t][v], dy);
+          elu_pair<true>(a[t][v], h[t][v], dy);
           if constexpr (KEEP) D[t][k + 1][v] = dy;
         }
     }
@@ -863,7 +865,7 @@ __device__ __forceinline__ void team_forward(const FieldJob& jb, const TilePoint
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) elu_pair<false>(a[t][v], h5[t][v], dphi5[t][v]);
+    for (int v = 0; v < 4; ++v) elu_pair<true>(a[t][v], h5[t][v], dphi5[t][v]);
 }
 
 // Output layer of a team job. The blocks of h5 are published like a layer's operand, with
