@@ -1053,9 +1053,14 @@ __device__ __forceinline__ void run_team(const FieldJob* __restrict__ jobs, cons
 #pragma unroll 1
   for (int e = 0; e < nx; ++e) {
     const FieldJob& xb = jobs[tl.job + team_extra(tl, e)];
+    // the same points as the Jacobian job's (the inference's h and l): its tile points
+    // again, without the dependent loads of the point list and the positions
+    const bool same_points = xb.idx == jb.idx && xb.step == jb.step && xb.step_off == jb.step_off &&
+                             xb.plan_steps == jb.plan_steps && xb.plan_ld == jb.plan_ld && xb.p_off == jb.p_off &&
+                             xb.X == jb.X && xb.ldx == jb.ldx && xb.n == jb.n;
     TilePoint xp[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) xp[t] = tile_point(xb, tl.p0 + 16 * t, lane);
+    for (int t = 0; t < NT; ++t) xp[t] = same_points ? tp[t] : tile_point(xb, tl.p0 + 16 * t, lane);
     const TeamNext xn = e + 1 < nx ? TeamNext{&jobs[tl.job + team_extra(tl, e + 1)].w, 0, false} : next_first;
     team_forward<W, NT, false>(xb, xp, xn, X, lds, q, lane, D, h5, dphi5, w6);
     team_output<W, WPG, NT>(xb, tl.p0, h5, w6, X, q, lane);
