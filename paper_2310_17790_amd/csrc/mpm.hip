@@ -782,12 +782,16 @@ typedef const __attribute__((address_space(1))) int* GlobalI;
 // constant-address-space view: uniform loads through it are scalar loads
 typedef const __attribute__((address_space(4))) float* ConstRec;
 constexpr int kGsWaves = 4, kGsThreads = 64 * kGsWaves;
-constexpr int kGsBatch = 2;   // records per batch of scalar loads (3: no faster, one wave fewer per SIMD)
+// A kept record's first 22 floats as six 4-float vectors (the last two floats past the
+// record's fields are padding); LDS rows of kGsRow floats.
+constexpr int kRecVec = 6, kGsRow = 4 * kRecVec;
 
 __global__ __launch_bounds__(kGsThreads) void gather_lanes_kernel(const SimDev* __restrict__ sims,
                                                                   const int32_t* __restrict__ n_sims) {
   __shared__ int s_pre[kMaxBatchSims + 1];
   __shared__ int wave_sums[kGsWaves];
+  // each wave's kept records of a chunk, one row each (22 floats, rows 16-byte aligned)
+  __shared__ __attribute__((aligned(16))) float s_rec[kGsWaves][64][kGsRow];
   const int nsims = *n_sims;
   const int total = sims_prefix<kGsThreads>(sims, nsims, s_pre, wave_sums,
                                             [](const SimDev& S) { return S.bin_edge == 4 ? S.n_active[0] : 0; });
@@ -842,7 +846,6 @@ __global__ __launch_bounds__(kGsThreads) void gather_lanes_kernel(const SimDev* 
     }
     const int total_rec = __builtin_amdgcn_readlane(incl, 7);
     const GlobalF recs = (GlobalF)S.rec;
-    const ConstRec crec = (ConstRec)S.rec;
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
     for (int c0 = 0; c0 < total_rec; c0 += 64) {
       // lane j tests record c0 + j: does its stencil reach the block?
@@ -855,11 +858,8 @@ __global__ __launch_bounds__(kGsThreads) void gather_lanes_kernel(const SimDev* 
       const int pb = __float_as_int(recs[(int64_t)slot * kRec + 21]);
       const bool keep = c0 + lane < total_rec && (pb >> 20) + 2 >= ox && ((pb >> 10) & 1023) + 2 >= oy &&
                         (pb & 1023) + 2 >= oz;
-      // the kept records in lane order, kGsBatch at a time, read through scalar loads (their
-      // loads in flight together; nothing in this kernel writes the records)
-      uint64_t ball = __ballot(keep);
-      // contribution of one record to the lane's node, or zero (branch-free, so that all
-      // the batch's loads are issued before the first use)
+      const uint64_t ball = __ballot(keep);
+      // contribution of one record to the lane's node, or zero (branch-free)
       auto add = [&](const float (&rr)[22], bool use) {
         const int pbj = __float_as_int(rr[21]);
         const int di = lx - ((pbj >> 20) - ox), dj = ly - (((pbj >> 10) & 1023) - oy), dk = lz - ((pbj & 1023) - oz);
@@ -874,25 +874,30 @@ __global__ __launch_bounds__(kGsThreads) void gather_lanes_kernel(const SimDev* 
         acc2 += w * (rr[1] + rr[6] * a + rr[7] * b + rr[8] * c);
         acc3 += w * (rr[2] + rr[9] * a + rr[10] * b + rr[11] * c);
       };
-      while (ball) {
-        int sl[kGsBatch];
-        bool use[kGsBatch];
+      // the kept records, in lane order, into the wave's rows of LDS: each kept lane loads
+      // its own record (all of them in flight together), then every lane reads them back
+      // one by one (the same address for all lanes) and adds its node's contribution
+      float* rows = &s_rec[wave][0][0];
+      if (keep) {
+        const int k = __builtin_amdgcn_mbcnt_hi((uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0));
+        const auto* src = (const __attribute__((address_space(1))) f32x4*)(S.rec + (int64_t)slot * kRec);
+        f32x4 q[kRecVec];
 #pragma unroll
-        for (int t = 0; t < kGsBatch; ++t) {
-          use[t] = ball != 0;
-          sl[t] = use[t] ? __builtin_amdgcn_readlane(slot, __builtin_ctzll(ball)) : sl[0];
-          if (use[t]) ball &= ball - 1;
-        }
-        float rr[kGsBatch][22];
+        for (int i = 0; i < kRecVec; ++i) q[i] = src[i];
+        f32x4* dst = reinterpret_cast<f32x4*>(rows + k * kGsRow);
 #pragma unroll
-        for (int t = 0; t < kGsBatch; ++t) {
-          const ConstRec q = crec + (int64_t)sl[t] * kRec;
-#pragma unroll
-          for (int i = 0; i < 22; ++i) rr[t][i] = q[i];
-        }
-#pragma unroll
-        for (int t = 0; t < kGsBatch; ++t) add(rr[t], use[t]);
+        for (int i = 0; i < kRecVec; ++i) dst[i] = q[i];
       }
+      wave_lds_sync();
+      const int n_kept = __popcll(ball);
+      for (int k = 0; k < n_kept; ++k) {
+        const f32x4* row = reinterpret_cast<const f32x4*>(rows + k * kGsRow);
+        float rr[22];
+#pragma unroll
+        for (int i = 0; i < 22; ++i) rr[i] = row[i >> 2][i & 3];
+        add(rr, true);
+      }
+      wave_lds_sync();   // every lane has read the rows: the next chunk may rewrite them
     }
     const int ni = ox + lx, nj = oy + ly, nk = oz + lz;
     if (ni < n && nj < n && nk < n) {
