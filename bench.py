@@ -66,9 +66,9 @@ DECODE_COUNTERS = {"fields_hip_sha256": "8cb9aec1c76e1a4f77a9c2501bdf48eebb594ce
 # per dispatch, summed over the stage's kernels, medians over the stages), scaled like the
 # decode's. Valid only for the kernel source they were taken on (SHA-256 of
 # csrc/mpm.hip).
-MPM_COUNTERS = {"mpm_hip_sha256": "7a72354e75d27841cc18a6837739137f38aef29f386ef07dff0114ca380706c1",
-                "single": {"fetch_kib": 9352.3, "write_kib": 2814.0},
-                "served": {"fetch_kib": 788347.3, "write_kib": 276947.9},
+MPM_COUNTERS = {"mpm_hip_sha256": "1dde338c377615c2303d2617901cd010e729b66099f8d273f6bf686ff8c2d137",
+                "single": {"fetch_kib": 9345.4, "write_kib": 2814.0},
+                "served": {"fetch_kib": 742188.9, "write_kib": 276559.4},
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
