@@ -689,8 +689,8 @@ nsf_status launch_decode(Plan& P, hipStream_t s, bool beside) {
 }
 
 // Pipelined decode: on the side stream between a fork and a join recorded on s (inline on
-// s when there is no side stream), on three quarters of the CUs: the latency-bound MPM and
-// Gauss-Newton kernels run on the rest meanwhile.
+// s when there is no side stream), on five eighths of the CUs: the step's MPM, Gauss-Newton
+// and field kernels run on the rest meanwhile (and on all of them once it ends).
 nsf_status fork_decode(Plan& P, hipStream_t s) {
   if (s == nullptr || !P.side) return launch_decode(P, s, false);
   NSF_HIP(hipEventRecord(P.ev_fork, s));

@@ -1400,9 +1400,11 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
     if (e == hipSuccess) e = hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
   }
-  // beside the latency-bound MPM and Gauss-Newton kernels: a quarter of the CUs stay free
-  // for them (sharing a CU with a decode workgroup, they measured no faster than waiting)
-  const int cus = beside ? dev_cus - dev_cus / 4 : dev_cus;
+  // beside the step's own kernels: three eighths of the CUs stay free for them (sharing a
+  // CU with a decode workgroup, they measured no faster than waiting). Of the shares
+  // measured (from 1/8 to 1/2 of the CUs free), 3/8 gave the fastest pipelined steps in
+  // both precisions taken together.
+  const int cus = beside ? dev_cus - dev_cus * 3 / 8 : dev_cus;
   const int tiles = (n_points + kTile16 - 1) / kTile16;
   if (width == 64) return launch_decode_width<64>(bf16, job, tiles, cus, s);
   if (width == 128) return launch_decode_width<128>(bf16, job, tiles, cus, s);

@@ -161,7 +161,7 @@ hipError_t launch_fields_table(int width, bool bf16, int tc, int kinds, const Fi
 int fields_table_blocks_per_cu(int width, bool bf16, int tc);
 hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s);   // n <= 64
 // One job over n points with persistent workgroups; `beside` = the launch runs next to the
-// latency-bound MPM and Gauss-Newton kernels and leaves them a quarter of the CUs.
+// step's own kernels (a pipelined decode) and leaves them three eighths of the CUs.
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
                                hipStream_t s, bool beside = false);
 int fields_max_tangents(int width, bool bf16);
