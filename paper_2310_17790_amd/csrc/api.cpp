@@ -677,11 +677,16 @@ nsf_status enqueue_inference(Plan& P, hipStream_t s) {
   return launch_hl(P, s);
 }
 
-// Decode of all particles on stream s: the dense kernel for one sim, else the primal
-// table kernel over every sim's decode groups.
+// Decode of all particles on stream s: the dense kernel for one sim, else over every sim's
+// decode groups: in BF16 with each workgroup's weight sets resident in LDS (one workgroup
+// per CU; beside the step, on the CUs a pipelined decode takes), in FP32 the primal table
+// kernel, which streams the layers (four FP32 layers do not fit in LDS).
 nsf_status launch_decode(Plan& P, hipStream_t s, bool beside) {
   if (P.nsims == 1 && !P.persistent)
     NSF_HIP(launch_fields_dense(P.width, P.bf16_hl, P.decode_job, P.decode_job.n, s, beside));
+  else if (P.bf16_hl)
+    NSF_HIP(launch_fields_decode_table(P.width, P.d_jobs, P.d_tD, P.d_counts + 7,
+                                       beside ? device_cus() - device_cus() * 3 / 8 : device_cus(), s));
   else
     NSF_HIP(launch_fields_table(P.width, P.bf16_hl, 0, kTableTangents, P.d_jobs, P.d_tD, P.d_counts + 7,
                                 P.d_counts + kClaimD, P.gF0, s));

@@ -1251,6 +1251,43 @@ constexpr int kTcF32W64 = 3, kTcF32W128 = 2, kTcBf16W64 = 4, kTcBf16W128 = 2;
 // primal. A group spans WPG tiles of 16 points.
 template <int TC> struct Wpg { static constexpr int value = TC > 0 ? 8 : 16; };
 
+// Decode of several jobs (a batch's sims, each with its own weight set) in BF16 with the
+// weights resident: each workgroup takes a contiguous range of the table's primal groups
+// (one tile per wave), loads a job's four hidden layers and small parameters into LDS when
+// its range reaches that job, and runs the groups' tiles as the single-job decode does (the
+// same operations, so the same bits). A range spans one or a few jobs, so a workgroup loads
+// a weight set once or twice per launch instead of streaming the layers for every group.
+template <int W, int WPG>
+__global__ __launch_bounds__(64 * WPG) void fields_decode_table_res_kernel(const FieldJob* __restrict__ jobs,
+                                                                           const FieldTile* __restrict__ groups,
+                                                                           const int32_t* __restrict__ n_groups) {
+  static_assert(WPG == Wpg<0>::value, "a primal group holds one tile per wave");
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int total = *n_groups;
+  const int g0 = (int)((int64_t)total * blockIdx.x / gridDim.x);
+  const int g1 = (int)((int64_t)total * (blockIdx.x + 1) / gridDim.x);
+  float* prm = reinterpret_cast<float*>(lds + 4 * HiddenLayer<W, true>::kBytes);
+  auto none = []() -> const FieldPack* { return nullptr; };
+  int cur = -1;
+#pragma unroll 1
+  for (int gi = g0; gi < g1; ++gi) {
+    const int j = __builtin_amdgcn_readfirstlane(groups[gi].job);
+    const int p0 = groups[gi].p0 + kTile16 * wave;
+    if (j != cur) {
+      if (cur >= 0) __syncthreads();   // every wave is done with the resident weight set
+      dma_all_layers<W, true, WPG>(jobs[j].w, lds, wave, lane);
+      copy_params<W, WPG>(jobs[j], prm);
+      wait_dma_and_sync();
+      cur = j;
+    }
+    // (as in the single-job decode: the weight reads stay inside the tile)
+    __asm__ volatile("" ::: "memory");
+    if (p0 < jobs[cur].n) run_group16<W, 0, true, WPG, true, true>(jobs[cur], p0, 0, none, lds, wave, lane);
+  }
+}
+
 template <int W, int TC, bool BF, int KINDS = kTableTangents>
 hipError_t launch_table(const FieldJob* jobs, const FieldTile* groups, const int32_t* n_groups,
                         int32_t* claim, int grid, hipStream_t s) {
@@ -1408,6 +1445,30 @@ hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_
   const int tiles = (n_points + kTile16 - 1) / kTile16;
   if (width == 64) return launch_decode_width<64>(bf16, job, tiles, cus, s);
   if (width == 128) return launch_decode_width<128>(bf16, job, tiles, cus, s);
+  return hipErrorInvalidValue;
+}
+
+template <int W>
+hipError_t launch_decode_table_res(const FieldJob* jobs, const FieldTile* groups, const int32_t* n_groups, int grid,
+                                   hipStream_t s) {
+  constexpr int lds = 4 * HiddenLayer<W, true>::kBytes + ParamsLds<W>::kFloats * 4;
+  static_assert(lds <= 160 * 1024, "four BF16 layers and the parameters must fit in LDS");
+  auto k = fields_decode_table_res_kernel<W, kDenseResWpg>;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kDenseResWpg), lds, s, jobs, groups, n_groups);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields_decode_table(int width, const FieldJob* jobs, const FieldTile* groups,
+                                      const int32_t* n_groups, int cus, hipStream_t s) {
+  if (cus <= 0) return hipSuccess;
+  if (width == 64) return launch_decode_table_res<64>(jobs, groups, n_groups, cus, s);
+  if (width == 128) return launch_decode_table_res<128>(jobs, groups, n_groups, cus, s);
   return hipErrorInvalidValue;
 }
 

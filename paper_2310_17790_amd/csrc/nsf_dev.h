@@ -164,6 +164,12 @@ hipError_t launch_reset_counters(int32_t* c, int n, hipStream_t s);   // n <= 64
 // step's own kernels (a pipelined decode) and leaves them three eighths of the CUs.
 hipError_t launch_fields_dense(int width, bool bf16, const FieldJob& job, int n_points,
                                hipStream_t s, bool beside = false);
+// BF16 decode over a table of primal groups (one tile per wave of a 16-wave workgroup) whose
+// jobs each have their own weight set, one workgroup per CU over `cus` CUs, weights resident
+// in LDS: every job must take the single-job decode's LDS-parameter form (no per-point
+// latents, no tangent direction, no saved pre-activations, d <= 9).
+hipError_t launch_fields_decode_table(int width, const FieldJob* jobs, const FieldTile* groups,
+                                      const int32_t* n_groups, int cus, hipStream_t s);
 int fields_max_tangents(int width, bool bf16);
 int fields_group_points(int tc);  // points one work group (table entry) spans
 // Jacobians with more latent columns than forward mode carries take one workgroup per
