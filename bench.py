@@ -57,7 +57,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "mixed": 2500.0}   # dense MFMA pe
 # for a plain 256 MiB device copy (bench.py --copy-probe: FETCH_SIZE reads half the copied
 # bytes, WRITE_SIZE all of them). Valid only for the kernel source they were taken on
 # (SHA-256 of csrc/fields.hip); null otherwise.
-DECODE_COUNTERS = {"fields_hip_sha256": "8176429b14136fc884eef25cab6420d0be33f6d4b1fc01264b6c19ae0971ad36",
+DECODE_COUNTERS = {"fields_hip_sha256": "a868a952876f8a27870a0cb2d7936618da42f44d21ccf091c3a62b9d9295939a",
                    "fetch_kib": 2353.4, "write_kib": 2343.75, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
