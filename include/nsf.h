@@ -311,6 +311,22 @@ nsf_status nsf_rows_expand(const float *table, const int64_t *offsets, int32_t s
 nsf_status nsf_rows_segment_sum(const float *rows, const int64_t *offsets, int32_t segments,
                                 int32_t width, float *out, void *stream);
 
+/* The fitting objective of one minibatch (Sec. 4.5 fits each field by least squares to the
+ * snapshots' values) and its gradient, in one pass. With e = out[c n + i] - Y[c ldy + q_i]
+ * and q_i = rows[i] P + cols[i] (pair i's snapshot and particle):
+ *   loss[0] = (sum over c < d, i < n of e^2) / (d n),   grad[c n + i] = e * (2 / (d n)),
+ * the factor 2 / (d n) rounded to FP32 once. out: device, d x n floats (output-major, as
+ * nsf_mlp_forward writes them); Y: device, d rows of ldy floats, every q_i < ldy; rows,
+ * cols: device, n int64 each; loss: device, 1 float; grad: device, d x n floats (may be
+ * out itself); workspace: device, NSF_SQERR_WORKSPACE_BYTES bytes, owned by the caller.
+ * The squares are summed in FP64 in a fixed order, so the loss is the same bits on every
+ * run. NSF_EINVAL for NULL pointers, d < 1, n < 1, P < 1 or ldy < 1; NSF_EHIP for a
+ * failed launch. */
+#define NSF_SQERR_WORKSPACE_BYTES 4096
+nsf_status nsf_squared_error(const float *out, int32_t d, int64_t n, const float *Y, int64_t ldy,
+                             const int64_t *rows, const int64_t *cols, int64_t P, float *loss,
+                             float *grad, void *workspace, void *stream);
+
 /* nsf_mlp_forward without a workspace argument, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc). It allocates nothing: the packed weights go to a library-owned device array

@@ -30,8 +30,9 @@ EXPORTED = ["nsf_sim_bytes", "nsf_create_sim", "nsf_step", "nsf_step_batch", "ns
             "nsf_status_flags", "nsf_sim_buffer",
             "nsf_destroy_sim", "nsf_last_error", "nsf_device_count", "nsf_mlp_param_count",
             "nsf_mlp_saved_floats", "nsf_mlp_workspace_bytes", "nsf_mlp_forward",
-            "nsf_mlp_backward", "nsf_mlp_forward_noalloc", "nsf_adam_step", "nsf_rows_expand", "nsf_rows_segment_sum", "nsf_fo_bytes", "nsf_fo_create", "nsf_fo_step", "nsf_fo_buffer",
+            "nsf_mlp_backward", "nsf_mlp_forward_noalloc", "nsf_adam_step", "nsf_rows_expand", "nsf_rows_segment_sum", "nsf_squared_error", "nsf_fo_bytes", "nsf_fo_create", "nsf_fo_step", "nsf_fo_buffer",
             "nsf_fo_flags", "nsf_fo_destroy"]
+NSF_SQERR_WORKSPACE_BYTES = 4096   # nsf_squared_error's workspace
 NSF_FO_U, NSF_FO_V, NSF_FO_C, NSF_FO_TAU, NSF_FO_F = range(5)
 NSF_FO_VON_MISES, NSF_FO_DRUCKER_PRAGER, NSF_FO_HERSCHEL_BULKLEY = range(3)
 
@@ -126,10 +127,11 @@ def lib() -> C.CDLL:
         L.nsf_adam_step.argtypes = [vp, vp, vp, vp, i64, C.c_double, C.c_double, C.c_double, C.c_double, i64, vp]
         L.nsf_rows_expand.argtypes = [vp, vp, i32, i32, vp, vp]
         L.nsf_rows_segment_sum.argtypes = [vp, vp, i32, i32, vp, vp]
+        L.nsf_squared_error.argtypes = [vp, i32, i64, vp, i64, vp, vp, i64, vp, vp, vp, vp]
         for name in ("nsf_create_sim", "nsf_step", "nsf_step_batch", "nsf_mpm_stage", "nsf_refresh", "nsf_decode", "nsf_get_latent",
                      "nsf_set_latent", "nsf_status_flags", "nsf_sim_buffer", "nsf_destroy_sim",
                      "nsf_mlp_forward", "nsf_mlp_backward", "nsf_mlp_forward_noalloc", "nsf_adam_step",
-                     "nsf_rows_expand", "nsf_rows_segment_sum"):
+                     "nsf_rows_expand", "nsf_rows_segment_sum", "nsf_squared_error"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib

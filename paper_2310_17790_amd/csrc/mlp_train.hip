@@ -919,6 +919,42 @@ nsf_status scratch_address(char** out) {
   return NSF_OK;
 }
 
+// The fitting objective: blocks of kSqErrThreads threads take pairs in a grid-stride loop,
+// write the gradient and sum the squares in FP64 (per thread in pair order, then over the
+// block in a fixed tree); one thread then adds the block sums in block order.
+constexpr int kSqErrThreads = 256, kSqErrBlocks = NSF_SQERR_WORKSPACE_BYTES / sizeof(double);
+
+__global__ __launch_bounds__(kSqErrThreads) void sq_err_kernel(const float* __restrict__ out, int d, int64_t n,
+                                                               const float* __restrict__ Y, int64_t ldy,
+                                                               const int64_t* __restrict__ rows,
+                                                               const int64_t* __restrict__ cols, int64_t P,
+                                                               float scale, float* grad, double* part) {
+  __shared__ double red[kSqErrThreads];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kSqErrThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSqErrThreads) {
+    const int64_t q = rows[i] * P + cols[i];
+    for (int c = 0; c < d; ++c) {
+      const float e = out[c * n + i] - Y[c * ldy + q];
+      acc += (double)e * (double)e;
+      grad[c * n + i] = e * scale;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kSqErrThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sq_err_total_kernel(const double* __restrict__ part, int blocks, double inv_count, float* loss) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < blocks; ++b) s += part[b];
+  loss[0] = (float)(s * inv_count);
+}
+
 }  // namespace
 }  // namespace nsf
 
@@ -980,6 +1016,22 @@ nsf_status nsf_rows_segment_sum(const float* rows, const int64_t* offsets, int32
   if (segments == 0) return NSF_OK;
   hipLaunchKernelGGL(rows_segment_sum_kernel, dim3(segments), dim3(256), 0, static_cast<hipStream_t>(stream), rows,
                      offsets, width, out);
+  return hipGetLastError() == hipSuccess ? NSF_OK : NSF_EHIP;
+}
+
+nsf_status nsf_squared_error(const float* out, int32_t d, int64_t n, const float* Y, int64_t ldy,
+                             const int64_t* rows, const int64_t* cols, int64_t P, float* loss, float* grad,
+                             void* workspace, void* stream) {
+  if (!out || !Y || !rows || !cols || !loss || !grad || !workspace || d < 1 || n < 1 || P < 1 || ldy < 1)
+    return NSF_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int blocks = (int)std::min<int64_t>(kSqErrBlocks, (n + kSqErrThreads - 1) / kSqErrThreads);
+  const double count = (double)d * (double)n;
+  double* part = static_cast<double*>(workspace);
+  hipLaunchKernelGGL(sq_err_kernel, dim3(blocks), dim3(kSqErrThreads), 0, s, out, (int)d, n, Y, ldy, rows, cols, P,
+                     (float)(2.0 / count), grad, part);
+  if (hipGetLastError() != hipSuccess) return NSF_EHIP;
+  hipLaunchKernelGGL(sq_err_total_kernel, dim3(1), dim3(64), 0, s, part, blocks, 1.0 / count, loss);
   return hipGetLastError() == hipSuccess ? NSF_OK : NSF_EHIP;
 }
 

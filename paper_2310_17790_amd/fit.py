@@ -20,7 +20,7 @@ import torch
 
 from . import _abi as A
 from .fullorder import FullOrderSim
-from .train import Adam, FieldFn, RowsExpand, SquaredError
+from .train import Adam, FieldFn, PairSquaredError, RowsExpand
 
 OUT_DIM = {"g": 3, "h": 6, "l": 9}
 # learning rates of the supplementary "Training Details", one per equal share of the run
@@ -135,8 +135,8 @@ class Fitter:
         zr = RowsExpand.apply(z, self.offsets, self.batch)
         Xp = torch.index_select(self.XT, 1, p).t()   # (n, 3) view of the SoA rows FieldFn takes
         out = FieldFn.apply(Xp, zr, self.w[f], self.width, OUT_DIM[f], self.precision)
-        y = torch.index_select(self.Y[f], 1, t * self.P + p)   # (d, n)
-        return SquaredError.apply(out.t(), y)
+        # targets at columns t P + p of the structure-of-arrays table, gathered in the loss
+        return PairSquaredError.apply(out, self.Y[f], t, p, self.P)
 
     def fit(self, f: str, iters: int) -> List[float]:
         """Adam over `iters` minibatches with the staged learning rates. g also trains the

@@ -230,3 +230,32 @@ def test_rows_expand_and_segment_sum():
     zt.grad = None
     RowsExpand.apply(zt, off, n).backward(torch.tensor(g, device="cuda"))
     np.testing.assert_array_equal(zt.grad.cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("d, n, P, T", [(3, 1000, 700, 5), (9, 300_000, 5_000, 80)])
+def test_pair_squared_error_matches_its_definition(d, n, P, T):
+    """nsf_squared_error (through PairSquaredError) against the fitting objective written out
+    in NumPy: e = out[c][i] - Y[c][rows[i] P + cols[i]], the gradient e * (2 / (d n)) bit for
+    bit in FP32, the loss (the mean of e^2) to FP32 rounding; the same bits on a second call
+    and through autograd. n = 1,000 leaves a ragged last block; 300,000 pairs make the
+    kernel's blocks loop over the pairs."""
+    from paper_2310_17790_amd.train import PairSquaredError
+    print(f"\n[case] pair squared error d={d} n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    out = rng.normal(size=(d, n)).astype(np.float32)
+    Y = rng.normal(size=(d, T * P)).astype(np.float32)
+    rows = np.sort(rng.integers(0, T, size=n)).astype(np.int64)
+    cols = rng.integers(0, P, size=n).astype(np.int64)
+    e = out - Y[:, rows * P + cols]
+    want_grad = e * np.float32(2.0 / (d * n))
+    want_loss = float((e.astype(np.float64) ** 2).sum() / (d * n))
+    out_t = torch.from_numpy(out).cuda().t().requires_grad_(True)   # the (n, d) view FieldFn returns
+    Yt, rt, ct = (torch.from_numpy(a).cuda() for a in (Y, rows, cols))
+    loss = PairSquaredError.apply(out_t, Yt, rt, ct, P)
+    loss.backward()
+    again = PairSquaredError.apply(out_t.detach(), Yt, rt, ct, P)
+    torch.cuda.synchronize()
+    got_grad = out_t.grad.t().cpu().numpy()
+    np.testing.assert_array_equal(got_grad, want_grad)
+    assert abs(float(loss) - want_loss) <= 1e-6 * want_loss
+    assert float(again) == float(loss)
