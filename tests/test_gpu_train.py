@@ -257,5 +257,5 @@ def test_pair_squared_error_matches_its_definition(d, n, P, T):
     torch.cuda.synchronize()
     got_grad = out_t.grad.t().cpu().numpy()
     np.testing.assert_array_equal(got_grad, want_grad)
-    assert abs(float(loss) - want_loss) <= 1e-6 * want_loss
-    assert float(again) == float(loss)
+    assert abs(float(loss.detach()) - want_loss) <= 1e-6 * want_loss
+    assert float(again) == float(loss.detach())
